@@ -712,6 +712,10 @@ static void score(orc_state *st, orc_round_stats *rs) {
         }
       }
     }
+    /* READING: the score is an int32; a count outside that range (degrees
+     * above ~46k) saturates. */
+    if (p > INT32_MAX) p = INT32_MAX;
+    if (p < INT32_MIN) p = INT32_MIN;
     st->P[u] = (int32_t)p;
   }
 }
