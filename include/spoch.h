@@ -1,0 +1,184 @@
+/*
+ * spoch.h -- C ABI of the MI355X (gfx950) contraction-hierarchy library.
+ *
+ * The library builds a contraction hierarchy (CH) of a directed graph with
+ * non-negative integer arc weights by round-synchronous contraction, the
+ * method of Wan et al., "Parallel Contraction Hierarchies Can Be Efficient
+ * and Scalable" (ICS 2025), and answers batches of s-t distance queries on
+ * it.  Every step runs as HIP kernels on the GPU; there is no CPU fallback.
+ *
+ * Problem statement followed (Sec. "Preliminaries" and "Contraction
+ * Hierarchies"): input G = (V, E, w) with w: E -> non-negative weights; the
+ * CH G_CH = (V, E_CH) preserves all pairwise distances; a query from s to t
+ * is answered by a bidirectional search over upward arcs (Sec. "Query on
+ * Contraction Hierarchies").
+ *
+ * Conventions for every entry point
+ *   - Return value: CH_OK (0) or a negative CH_E_* code.  On error no
+ *     out-parameter is written and ch_last_error() describes the failure
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Vertex ids are uint32 in [0, n); n <= 0xFFFFFFFE.
+ *   - Arc weights are uint32 in [0, 0xFFFFFFFE]; 0xFFFFFFFF is reserved.
+ *     Every witness-search bound and shortcut weight must fit in
+ *     [0, 0xFFFFFFFE], else CH_E_OVERFLOW.  Query distances are uint64.
+ *   - "Host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device allocations on the current device.  Flags say which.
+ *   - The caller owns every array it passes; the library reads inputs during
+ *     the call only and never retains a caller pointer.
+ *   - The library owns a ch_t from ch_build until ch_free.
+ *   - Calls on different ch_t objects may run concurrently on different
+ *     streams; calls on the same ch_t must not overlap.
+ */
+#ifndef SPOCH_H
+#define SPOCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define CH_OK 0
+#define CH_E_INVALID -1  /* bad argument: NULL, id >= n, weight 0xFFFFFFFF, labels not distinct */
+#define CH_E_OOM -2      /* device or host allocation failed */
+#define CH_E_OVERFLOW -3 /* a search bound or shortcut weight exceeds 0xFFFFFFFE */
+#define CH_E_DEVICE -4   /* HIP runtime error (message in ch_last_error) */
+#define CH_E_LIMIT -5    /* max_rounds reached with vertices still uncontracted */
+#define CH_E_UNSUPPORTED -6 /* option not implemented by this build */
+
+/* ---- witness-path-search modes ---- */
+/* The paper bounds each search by a settled-vertex budget whose value it
+ * does not give (Sec. "Step 1: Local Search with Memoization").  This
+ * library searches from source s up to radius D_s = the largest two-arc
+ * length w(s,u) + w(u,v) over its targets, which yields exact distances
+ * for every target. */
+#define CH_WPS_EXACT 0
+
+/* ---- flags ---- */
+#define CH_F_INPUT_ON_DEVICE 0x1u /* ch_graph_t arrays are device pointers */
+#define CH_F_STATS 0x2u           /* collect per-round counters and timings */
+#define CH_F_NO_QUERY_INDEX 0x4u  /* skip the rank-space CSR (ch_query_batch then fails) */
+
+#define CH_Q_ON_DEVICE 0x1u       /* s, t, dist of ch_query_batch are device pointers */
+
+/* Input graph in CSR form, arcs grouped by tail vertex.
+ *   offsets[n+1]: offsets[0] = 0, non-decreasing, offsets[n] = m
+ *   dst[m]:       head of each arc, < n
+ *   w[m]:         weight of each arc, <= 0xFFFFFFFE
+ *   labels[n]:    optional distinct tie-break labels (NULL: derived from
+ *                 the vertex id and params.seed by the MurmurHash3 32-bit
+ *                 finaliser, fmix32(v ^ lo32(seed) ^ hi32(seed))).
+ * Self-loops are dropped and parallel arcs keep the smallest weight. */
+typedef struct {
+  uint32_t n;
+  uint64_t m;
+  const uint64_t *offsets;
+  const uint32_t *dst;
+  const uint32_t *w;
+  const uint32_t *labels;
+} ch_graph_t;
+
+typedef struct {
+  uint32_t wps_mode;   /* CH_WPS_EXACT                                          */
+  uint32_t max_rounds; /* 0: no limit; else CH_E_LIMIT after that many rounds    */
+  uint64_t seed;       /* seed of the default labels                            */
+  uint32_t flags;      /* CH_F_*                                                */
+  uint32_t group;      /* lanes per item in the round kernels: 0 = automatic,   */
+                       /* else 4, 8, 16, 32 or 64 (changes speed, never results) */
+  void *stream;        /* hipStream_t to run on (borrowed); NULL = the library's */
+} ch_params_t;
+
+typedef struct ch_s ch_t;
+
+/* Per-round counters (CH_F_STATS). */
+typedef struct {
+  uint32_t alive_before;    /* |V_O| at the start of the round                */
+  uint32_t n_sources;       /* |V_W|, witness-search sources                  */
+  uint32_t n_affected;      /* |V_A|, vertices rescored                        */
+  uint32_t n_selected;      /* |V_F|, vertices contracted                      */
+  uint64_t n_targets;       /* sum over sources of the target-set size         */
+  uint64_t n_pruned;        /* arcs deleted by the pruning rule                */
+  uint64_t n_shortcuts;     /* distinct (v1, v2) shortcut pairs                */
+  uint64_t overlay_arcs;    /* arcs in the overlay after the round             */
+  /* the next four count the fast-path witness-search kernel only */
+  uint64_t rows_expanded;   /* adjacency rows read by the witness searches     */
+  uint64_t arcs_scanned;    /* arcs read by the witness searches               */
+  uint64_t memo_probes;     /* memo slots read by the local search             */
+  uint64_t memo_inserts;    /* memo entries written                            */
+  uint32_t n_ls_fallback;   /* sources whose search outgrew the fast-path table */
+  float ms_local_search;    /* device time of the fast-path witness-search kernel */
+  float ms_total;           /* device time of the whole round (host gaps included) */
+} ch_round_stats_t;
+
+/* Whole-build summary. */
+typedef struct {
+  uint32_t n;
+  uint32_t rounds;
+  uint64_t m_input;         /* arcs after dropping self-loops and duplicates  */
+  uint64_t up_arcs;         /* arcs of the upward graph                       */
+  uint64_t down_arcs;       /* arcs of the downward graph                     */
+  uint64_t shortcuts;       /* sum over rounds of n_shortcuts                 */
+  uint64_t memo_entries;
+  double ms_build;          /* device time of the build, upload excluded      */
+} ch_summary_t;
+
+/* Build the CH of `g`.  Sec. "Our Parallel CH Construction Algorithm",
+ * Alg. 2: rounds of LocalSearch (Alg. 3), Score (Alg. 4), Select (Alg. 5)
+ * and Contract (Alg. 6) until the overlay is empty, then Postprocessing
+ * (rank by level, then score, then label).
+ *   g:   input graph; host arrays, or device arrays with CH_F_INPUT_ON_DEVICE
+ *   p:   parameters (NULL = defaults: exact mode, no round limit, seed 0)
+ *   out: receives the new ch_t (library-owned; release with ch_free)
+ * Runs on p->stream and returns after the build has finished on the GPU.
+ * Errors: CH_E_INVALID (bad graph or parameters), CH_E_OVERFLOW, CH_E_OOM,
+ * CH_E_DEVICE, CH_E_LIMIT, CH_E_UNSUPPORTED. */
+int ch_build(const ch_graph_t *g, const ch_params_t *p, ch_t **out);
+
+/* Distances of q s-t pairs on the CH (Sec. "Query on Contraction
+ * Hierarchies"): dist[i] = min over v of d_up(s_i, v) + d_down(v, t_i),
+ * which equals the shortest s_i -> t_i distance in the input graph;
+ * 0 when s_i == t_i, UINT64_MAX when t_i is unreachable.
+ *   s, t: q vertex ids each; dist: q entries written by the call (caller-
+ *   owned).  All three on the host, or on the device with CH_Q_ON_DEVICE.
+ *   stream: hipStream_t (NULL = the CH's stream).
+ * Returns after the distances are written.
+ * Errors: CH_E_INVALID (NULL, id >= n, no query index), CH_E_OOM,
+ * CH_E_DEVICE. */
+int ch_query_batch(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
+                   uint64_t *dist, uint32_t flags, void *stream);
+
+/* Copy the finished CH to host arrays, in original vertex ids.  Any pointer
+ * may be NULL to skip that array.
+ *   level[n]: round in which the vertex was contracted (0-based)
+ *   score[n]: its score when it was selected
+ *   rank[n]:  position in the order (level, score, label)
+ *   up_*[up_arcs]:     upward arcs (tail -> head, weight, middle vertex or
+ *                      UINT32_MAX for an input arc), sorted by (rank of
+ *                      tail, rank of head)
+ *   down_*[down_arcs]: downward arcs (tail -> head) with rank(tail) >
+ *                      rank(head), sorted by (rank of head, rank of tail)
+ * Sizes are those of ch_get_summary. */
+int ch_export(const ch_t *ch, uint32_t *level, int32_t *score, uint32_t *rank,
+              uint32_t *up_tail, uint32_t *up_head, uint32_t *up_w, uint32_t *up_mid,
+              uint32_t *down_tail, uint32_t *down_head, uint32_t *down_w,
+              uint32_t *down_mid);
+
+int ch_get_summary(const ch_t *ch, ch_summary_t *out);
+
+/* Copy min(cap, rounds) per-round records (filled only with CH_F_STATS). */
+int ch_get_round_stats(const ch_t *ch, ch_round_stats_t *out, uint32_t cap);
+
+/* Release a CH (NULL is ignored). */
+void ch_free(ch_t *ch);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ch_last_error(void);
+
+/* Library version string. */
+const char *ch_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPOCH_H */

@@ -1,0 +1,205 @@
+"""ctypes binding of the C ABI in ``include/spoch.h``.
+
+Argument marshalling only: every step of the construction and of the
+queries runs in the HIP kernels of ``libspoch.so``.  Inputs may be numpy
+arrays (host) or torch CUDA tensors (device; passed by pointer with the
+device flag).  The library must be built (``paper_2412_18008_amd.build``);
+loading fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspoch.so")
+
+CH_OK = 0
+CH_E_INVALID = -1
+CH_E_OOM = -2
+CH_E_OVERFLOW = -3
+CH_E_DEVICE = -4
+CH_E_LIMIT = -5
+CH_E_UNSUPPORTED = -6
+
+CH_WPS_EXACT = 0
+CH_F_INPUT_ON_DEVICE = 0x1
+CH_F_STATS = 0x2
+CH_F_NO_QUERY_INDEX = 0x4
+CH_Q_ON_DEVICE = 0x1
+
+EXPORTED = ("ch_build", "ch_query_batch", "ch_export", "ch_get_summary",
+            "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version")
+
+
+class ChError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Graph(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("offsets", C.c_void_p),
+                ("dst", C.c_void_p), ("w", C.c_void_p), ("labels", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("wps_mode", C.c_uint32), ("max_rounds", C.c_uint32), ("seed", C.c_uint64),
+                ("flags", C.c_uint32), ("group", C.c_uint32), ("stream", C.c_void_p)]
+
+
+class RoundStats(C.Structure):
+    _fields_ = [
+        ("alive_before", C.c_uint32), ("n_sources", C.c_uint32), ("n_affected", C.c_uint32),
+        ("n_selected", C.c_uint32), ("n_targets", C.c_uint64), ("n_pruned", C.c_uint64),
+        ("n_shortcuts", C.c_uint64), ("overlay_arcs", C.c_uint64),
+        ("rows_expanded", C.c_uint64), ("arcs_scanned", C.c_uint64),
+        ("memo_probes", C.c_uint64), ("memo_inserts", C.c_uint64),
+        ("n_ls_fallback", C.c_uint32), ("ms_local_search", C.c_float),
+        ("ms_total", C.c_float),
+    ]
+
+
+class Summary(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("rounds", C.c_uint32), ("m_input", C.c_uint64),
+                ("up_arcs", C.c_uint64), ("down_arcs", C.c_uint64), ("shortcuts", C.c_uint64),
+                ("memo_entries", C.c_uint64), ("ms_build", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libspoch.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run python -m paper_2412_18008_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
+        L.ch_build.argtypes = [C.POINTER(Graph), C.POINTER(Params), C.POINTER(vp)]
+        L.ch_build.restype = i32
+        L.ch_query_batch.argtypes = [vp, vp, vp, u64, vp, u32, vp]
+        L.ch_query_batch.restype = i32
+        L.ch_export.argtypes = [vp] + [vp] * 11
+        L.ch_export.restype = i32
+        L.ch_get_summary.argtypes = [vp, C.POINTER(Summary)]
+        L.ch_get_summary.restype = i32
+        L.ch_get_round_stats.argtypes = [vp, vp, u32]
+        L.ch_get_round_stats.restype = i32
+        L.ch_free.argtypes = [vp]
+        L.ch_free.restype = None
+        L.ch_last_error.argtypes = []
+        L.ch_last_error.restype = C.c_char_p
+        L.ch_version.argtypes = []
+        L.ch_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != CH_OK:
+        msg = lib().ch_last_error().decode()
+        raise ChError(rc, f"{what}: {msg}")
+
+
+def _is_torch_cuda(a):
+    return hasattr(a, "is_cuda") and a.is_cuda
+
+
+def _ptr(a, dtype):
+    """Pointer of a numpy array (converted to dtype) or of a CUDA tensor."""
+    if a is None:
+        return None, None
+    if _is_torch_cuda(a):
+        return a.data_ptr(), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return arr.ctypes.data, arr
+
+
+class CH:
+    """A contraction hierarchy built on the GPU (owns a ch_t)."""
+
+    def __init__(self, handle):
+        self.h = handle
+        s = Summary()
+        _check(lib().ch_get_summary(self.h, C.byref(s)), "ch_get_summary")
+        self.summary = {f: getattr(s, f) for f, _ in Summary._fields_}
+        self.n = self.summary["n"]
+
+    def __del__(self):
+        self.free()
+
+    def free(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ch_free(self.h)
+            self.h = None
+
+    def query(self, s, t, stream=None):
+        """dist[i] = shortest s[i] -> t[i] distance (uint64, max = unreachable).
+        numpy inputs give a numpy result; torch CUDA inputs give a torch CUDA
+        int64 tensor (holding the uint64 bit patterns)."""
+        if _is_torch_cuda(s):
+            import torch
+
+            q = s.numel()
+            dist = torch.empty(q, dtype=torch.int64, device=s.device)
+            st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+            _check(lib().ch_query_batch(self.h, s.data_ptr(), t.data_ptr(), q, dist.data_ptr(),
+                                        CH_Q_ON_DEVICE, st), "ch_query_batch")
+            return dist
+        s = np.ascontiguousarray(s, np.uint32)
+        t = np.ascontiguousarray(t, np.uint32)
+        dist = np.empty(len(s), np.uint64)
+        _check(lib().ch_query_batch(self.h, s.ctypes.data, t.ctypes.data, len(s),
+                                    dist.ctypes.data, 0, stream), "ch_query_batch")
+        return dist
+
+    def export(self):
+        n, nu, nd = self.n, self.summary["up_arcs"], self.summary["down_arcs"]
+        out = dict(level=np.empty(n, np.uint32), score=np.empty(n, np.int32),
+                   rank=np.empty(n, np.uint32))
+        for k in ("up_tail", "up_head", "up_w", "up_mid"):
+            out[k] = np.empty(nu, np.uint32)
+        for k in ("down_tail", "down_head", "down_w", "down_mid"):
+            out[k] = np.empty(nd, np.uint32)
+        order = ("level", "score", "rank", "up_tail", "up_head", "up_w", "up_mid",
+                 "down_tail", "down_head", "down_w", "down_mid")
+        _check(lib().ch_export(self.h, *[out[k].ctypes.data for k in order]), "ch_export")
+        return out
+
+    def round_stats(self):
+        k = self.summary["rounds"]
+        arr = (RoundStats * max(k, 1))()
+        _check(lib().ch_get_round_stats(self.h, C.cast(arr, C.c_void_p), k),
+               "ch_get_round_stats")
+        return [{f: getattr(arr[i], f) for f, _ in RoundStats._fields_} for i in range(k)]
+
+
+def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
+          query_index=True, stream=None):
+    """ch_build on a CSR graph; numpy arrays or torch CUDA tensors."""
+    dev = _is_torch_cuda(off)
+    po, ko = _ptr(off, np.uint64)
+    pd, kd = _ptr(dst, np.uint32)
+    pw, kw = _ptr(w, np.uint32)
+    pl, kl = _ptr(labels, np.uint32)
+    n = (off.numel() if dev else len(ko)) - 1
+    m = dst.numel() if dev else len(kd)
+    g = Graph(n, m, po, pd, pw, pl)
+    flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (CH_F_STATS if stats else 0) | (
+        0 if query_index else CH_F_NO_QUERY_INDEX)
+    if stream is None and dev:
+        import torch
+
+        stream = torch.cuda.current_stream().cuda_stream
+    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream)
+    h = C.c_void_p()
+    _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
+    return CH(h)
+
+
+def version():
+    return lib().ch_version().decode()

@@ -1,0 +1,759 @@
+// builder.hip -- host driver of the round-synchronous CH construction
+// (Alg. 2 of Wan et al.): ingest, then rounds of LocalSearch, Score, Select
+// and Contract on a compacted overlay until no vertex is left, then the
+// postprocessing in post.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "builder.hpp"
+#include "round_kernels.hpp"
+
+namespace sp {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+const char *last_error_msg() { return g_last_error.c_str(); }
+void clear_error() { g_last_error.clear(); }
+
+int hip_error(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+    return set_error(CH_E_OOM, std::string(what) + ": " + hipGetErrorString(e));
+  return set_error(CH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_error(e_, #expr);  \
+  } while (0)
+#define TRY(expr)               \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != CH_OK) return r_; \
+  } while (0)
+
+static int bits_for(uint32_t n) {  // bits to hold values 0..n-1 (at least 1)
+  int b = 1;
+  while (b < 32 && (1ull << b) < (uint64_t)n) b++;
+  return b;
+}
+
+static uint64_t next_pow2(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Device-side counters read back by the host (one struct, one copy).
+struct DevCtr {
+  LsCounters ls;
+  unsigned long long bound, pruned, kept;
+  uint32_t err, bad;
+  uint32_t c32[8];  // scan totals and list counts
+};
+enum { C_NF = 0, C_UP, C_DN, C_PAIR, C_HEADS, C_NNEW, C_MF, C_MR };
+
+struct OvBuf {
+  DBuf foff, farc, fmid, roff, rarc, rmid, gid, P;
+  uint32_t n = 0, m = 0;
+  void release() {
+    foff.release(); farc.release(); fmid.release(); roff.release(); rarc.release();
+    rmid.release(); gid.release(); P.release();
+  }
+};
+
+struct Builder {
+  ch_s *ch = nullptr;
+  hipStream_t st = nullptr;
+  ch_params_t prm{};
+  uint32_t n = 0;
+  int cus = 256;
+
+  OvBuf ov[2];
+  int cur = 0;
+  DBuf aflag, aflag_next, wflag, F, S, newA, key, paircnt, newid, cnt, vw, va, vf;
+  DBuf memo, alive_g;
+  uint64_t mcap = 0, mcount = 0;
+  DBuf cup, cdn, cpair;
+  DBuf ekey, ekey_alt, eidx, eidx_alt, ew, elab, emid, ehead, eheads, ukey, uw, umid, rkey,
+      rkey_alt, ridx, ridx_alt;
+  DBuf ovf1, ovf2, gtabs;
+  DBuf dctr, tmp;
+  DevCtr *hctr = nullptr;  // pinned
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  uint64_t up_cap = 0, dn_cap = 0;
+
+  ~Builder() {
+    OvBuf *o = ov;
+    o[0].release();
+    o[1].release();
+    DBuf *all[] = {&aflag, &aflag_next, &wflag, &F, &S, &newA, &key, &paircnt, &newid, &cnt,
+                   &vw, &va, &vf, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
+                   &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
+                   &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp};
+    for (DBuf *b : all) b->release();
+    if (hctr) (void)hipHostFree(hctr);
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+
+  DevCtr *dc() { return dctr.as<DevCtr>(); }
+
+  unsigned grid(uint64_t items, unsigned block = 256) const {
+    uint64_t g = (items + block - 1) / block;
+    uint64_t cap = (uint64_t)cus * 16;
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+  }
+  template <int G>
+  unsigned ggrid(uint64_t items) const {  // group kernels, 256-thread blocks
+    return grid(items * G);
+  }
+
+  int readback() {
+    HIP_TRY(hipMemcpyAsync(hctr, dctr.p, sizeof(DevCtr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return CH_OK;
+  }
+
+  int check_err() {
+    if (hctr->err & kErrOverflow)
+      return set_error(CH_E_OVERFLOW,
+                       "a witness-search radius or shortcut weight exceeds 0xFFFFFFFE");
+    if (hctr->err & kErrCapacity) return set_error(CH_E_DEVICE, "internal capacity check failed");
+    return CH_OK;
+  }
+
+  // ---------------------------------------------------------------- ingest
+  int ingest(const ch_graph_t *g) {
+    const bool on_dev = prm.flags & CH_F_INPUT_ON_DEVICE;
+    const uint64_t m = g->m;
+    if (m >= 0xFFFFFFFFull)
+      return set_error(CH_E_UNSUPPORTED, "graphs with 2^32 - 1 or more arcs are not supported");
+    const uint32_t m32 = (uint32_t)m;
+    const int kb = bits_for(n);
+    DBuf d_off, d_dst, d_w;
+    const uint64_t *off = g->offsets;
+    const uint32_t *dst = g->dst, *w = g->w;
+    if (!on_dev) {
+      HIP_TRY(d_off.ensure((n + 1) * sizeof(uint64_t)));
+      HIP_TRY(d_dst.ensure(std::max<uint64_t>(m, 1) * 4));
+      HIP_TRY(d_w.ensure(std::max<uint64_t>(m, 1) * 4));
+      HIP_TRY(hipMemcpyAsync(d_off.p, g->offsets, (n + 1) * sizeof(uint64_t),
+                             hipMemcpyHostToDevice, st));
+      if (m) {
+        HIP_TRY(hipMemcpyAsync(d_dst.p, g->dst, m * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_w.p, g->w, m * 4, hipMemcpyHostToDevice, st));
+      }
+      off = d_off.as<uint64_t>();
+      dst = d_dst.as<uint32_t>();
+      w = d_w.as<uint32_t>();
+    }
+    HIP_TRY(ekey.ensure(std::max<uint64_t>(m, 1) * 8));
+    HIP_TRY(ekey_alt.ensure(std::max<uint64_t>(m, 1) * 8));
+    HIP_TRY(ew.ensure(std::max<uint64_t>(m, 1) * 4));
+    HIP_TRY(elab.ensure(std::max<uint64_t>(m, 1) * 4));
+    HIP_TRY(ehead.ensure(std::max<uint64_t>(m, 1)));
+    HIP_TRY(eheads.ensure(std::max<uint64_t>(m, 1) * 4));
+    HIP_TRY(ukey.ensure(std::max<uint64_t>(m, 1) * 8));
+    HIP_TRY(uw.ensure(std::max<uint64_t>(m, 1) * 4));
+    HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
+    // first offset and last offset checks happen on the host copy
+    uint64_t first = 0, last = 0;
+    if (on_dev) {
+      HIP_TRY(hipMemcpyAsync(&first, off, 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(&last, off + n, 8, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+    } else {
+      first = g->offsets[0];
+      last = g->offsets[n];
+    }
+    if (first != 0 || last != m)
+      return set_error(CH_E_INVALID, "offsets[0] must be 0 and offsets[n] must equal m");
+    if (m) {
+      k_ingest_keys<<<grid(n), 256, 0, st>>>(n, m, kb, off, dst, w, ekey.as<uint64_t>(),
+                                             ew.as<uint32_t>(), &dc()->bad);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(radix_sort_u64(ekey.as<uint64_t>(), ew.as<uint32_t>(), ekey_alt.as<uint64_t>(),
+                             elab.as<uint32_t>(), m32, 2 * kb, tmp, st));
+      k_run_heads<<<grid(m), 256, 0, st>>>(ekey.as<uint64_t>(), m32, ehead.as<uint8_t>());
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(select_flags(ehead.as<uint8_t>(), m32, eheads.as<uint32_t>(), &dc()->c32[C_HEADS],
+                           tmp, st));
+      k_run_min<<<grid(m), 256, 0, st>>>(ekey.as<uint64_t>(), ew.as<uint32_t>(), m32,
+                                         eheads.as<uint32_t>(), &dc()->c32[C_HEADS],
+                                         ukey.as<uint64_t>(), uw.as<uint32_t>());
+      HIP_TRY(hipGetLastError());
+    }
+    TRY(readback());
+    if (hctr->bad & 1) return set_error(CH_E_INVALID, "offsets are not non-decreasing");
+    if (hctr->bad & 2)
+      return set_error(CH_E_INVALID, "an arc has head >= n or weight 0xFFFFFFFF");
+    const uint32_t mu = m ? hctr->c32[C_HEADS] : 0;
+    if (!m) HIP_TRY(hipMemsetAsync(&dc()->c32[C_HEADS], 0, 4, st));
+    ch->m_input = mu;
+    OvBuf &O = ov[cur];
+    O.n = n;
+    O.m = mu;
+    HIP_TRY(O.foff.ensure((n + 1) * 4));
+    HIP_TRY(O.roff.ensure((n + 1) * 4));
+    HIP_TRY(O.farc.ensure(std::max<uint64_t>(mu, 1) * 8));
+    HIP_TRY(O.rarc.ensure(std::max<uint64_t>(mu, 1) * 8));
+    HIP_TRY(O.fmid.ensure(std::max<uint64_t>(mu, 1) * 4));
+    HIP_TRY(O.rmid.ensure(std::max<uint64_t>(mu, 1) * 4));
+    HIP_TRY(O.gid.ensure(std::max<uint64_t>(n, 1) * 4));
+    HIP_TRY(O.P.ensure(std::max<uint64_t>(n, 1) * 4));
+    k_csr_from_sorted<<<grid(std::max<uint64_t>(n + 1, mu)), 256, 0, st>>>(
+        ukey.as<uint64_t>(), uw.as<uint32_t>(), &dc()->c32[C_HEADS], n, kb, O.foff.as<uint32_t>(),
+        O.farc.as<uint2>(), O.fmid.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    if (mu) {
+      k_swap_key<<<grid(mu), 256, 0, st>>>(ukey.as<uint64_t>(), &dc()->c32[C_HEADS], kb,
+                                           ekey.as<uint64_t>());
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(ew.p, uw.p, (size_t)mu * 4, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(radix_sort_u64(ekey.as<uint64_t>(), ew.as<uint32_t>(), ekey_alt.as<uint64_t>(),
+                             elab.as<uint32_t>(), mu, 2 * kb, tmp, st));
+    }
+    k_csr_from_sorted<<<grid(std::max<uint64_t>(n + 1, mu)), 256, 0, st>>>(
+        ekey.as<uint64_t>(), ew.as<uint32_t>(), &dc()->c32[C_HEADS], n, kb, O.roff.as<uint32_t>(),
+        O.rarc.as<uint2>(), O.rmid.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(iota_u32(O.gid.as<uint32_t>(), n, st));
+    HIP_TRY(hipMemsetAsync(O.P.p, 0, (size_t)n * 4, st));
+
+    // labels
+    HIP_TRY(ch->label.ensure(std::max<uint64_t>(n, 1) * 4));
+    if (g->labels) {
+      HIP_TRY(hipMemcpyAsync(ch->label.p, g->labels, (size_t)n * 4,
+                             on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+      HIP_TRY(ekey.ensure(std::max<uint64_t>(n, 1) * 8));
+      HIP_TRY(ekey_alt.ensure(std::max<uint64_t>(n, 1) * 8));
+      HIP_TRY(ew.ensure(std::max<uint64_t>(n, 1) * 4));
+      HIP_TRY(elab.ensure(std::max<uint64_t>(n, 1) * 4));
+      k_labels_to_keys<<<grid(n), 256, 0, st>>>(n, ch->label.as<uint32_t>(), ekey.as<uint64_t>());
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(iota_u32(ew.as<uint32_t>(), n, st));
+      HIP_TRY(radix_sort_u64(ekey.as<uint64_t>(), ew.as<uint32_t>(), ekey_alt.as<uint64_t>(),
+                             elab.as<uint32_t>(), n, 32, tmp, st));
+      k_adjacent_equal<<<grid(n), 256, 0, st>>>(n, ekey.as<uint64_t>(), &dc()->bad);
+      HIP_TRY(hipGetLastError());
+      TRY(readback());
+      if (hctr->bad & 4) return set_error(CH_E_INVALID, "labels are not distinct");
+    } else {
+      const uint32_t mix = (uint32_t)prm.seed ^ (uint32_t)(prm.seed >> 32);
+      k_default_labels<<<grid(n), 256, 0, st>>>(n, mix, ch->label.as<uint32_t>());
+      HIP_TRY(hipGetLastError());
+    }
+    return CH_OK;
+  }
+
+  // ------------------------------------------------------------- helpers
+  Overlay view(OvBuf &O) {
+    Overlay v;
+    v.n = O.n;
+    v.m = O.m;
+    v.foff = O.foff.as<uint32_t>();
+    v.farc = O.farc.as<uint2>();
+    v.fmid = O.fmid.as<uint32_t>();
+    v.roff = O.roff.as<uint32_t>();
+    v.rarc = O.rarc.as<uint2>();
+    v.rmid = O.rmid.as<uint32_t>();
+    v.gid = O.gid.as<uint32_t>();
+    return v;
+  }
+
+  int grow_copy(DBuf &b, size_t used_bytes, size_t need_bytes) {
+    if (need_bytes <= b.cap) return CH_OK;
+    DBuf nb;
+    HIP_TRY(nb.ensure(std::max(need_bytes, b.cap * 2)));
+    if (used_bytes) HIP_TRY(hipMemcpyAsync(nb.p, b.p, used_bytes, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    b.release();
+    b = nb;
+    return CH_OK;
+  }
+
+  int ensure_memo(uint64_t extra) {
+    const uint64_t need = mcount + extra;
+    if (need * 2 <= mcap) return CH_OK;
+    uint64_t ncap = next_pow2(std::max<uint64_t>(need * 3, 1024));
+    DBuf nm;
+    HIP_TRY(nm.ensure(ncap * sizeof(MemoSlot)));
+    HIP_TRY(fill_u64(nm.as<uint64_t>(), SP_EMPTY64, ncap * 2, st));
+    uint64_t kept = 0;
+    if (mcap) {
+      HIP_TRY(hipMemsetAsync(&dc()->kept, 0, 8, st));
+      k_memo_rehash<<<grid(mcap), 256, 0, st>>>(memo.as<MemoSlot>(), mcap, alive_g.as<uint8_t>(),
+                                                 nm.as<MemoSlot>(), ncap - 1, &dc()->kept);
+      HIP_TRY(hipGetLastError());
+      TRY(readback());
+      kept = hctr->kept;
+    }
+    memo.release();
+    memo = nm;
+    mcap = ncap;
+    mcount = kept;
+    return CH_OK;
+  }
+
+  template <int G>
+  void launch_score(const Overlay &v, uint32_t na) {
+    k_score<G><<<ggrid<G>(na), 256, 0, st>>>(v, va.as<uint32_t>(), na, memo.as<MemoSlot>(),
+                                              mcap - 1, ov[cur].P.as<int32_t>(),
+                                              paircnt.as<uint32_t>());
+  }
+  template <int G>
+  void launch_select(const Overlay &v) {
+    k_select<G><<<ggrid<G>(v.n), 256, 0, st>>>(v, key.as<uint64_t>(), F.as<uint8_t>());
+  }
+  template <int G>
+  void launch_ccount(const Overlay &v, uint32_t nf) {
+    k_contract_count<G><<<ggrid<G>(nf), 256, 0, st>>>(
+        v, vf.as<uint32_t>(), nf, aflag.as<uint8_t>(), paircnt.as<uint32_t>(),
+        memo.as<MemoSlot>(), mcap - 1, cup.as<uint32_t>(), cdn.as<uint32_t>(),
+        cpair.as<uint32_t>());
+  }
+  template <int G>
+  void launch_contract(const Overlay &v, uint32_t nf, uint32_t round, int kb) {
+    ArcOut up{ch->up_t.as<uint32_t>(), ch->up_h.as<uint32_t>(), ch->up_w.as<uint32_t>(),
+              ch->up_m.as<uint32_t>()};
+    ArcOut dn{ch->dn_t.as<uint32_t>(), ch->dn_h.as<uint32_t>(), ch->dn_w.as<uint32_t>(),
+              ch->dn_m.as<uint32_t>()};
+    k_contract<G><<<ggrid<G>(nf), 256, 0, st>>>(
+        v, vf.as<uint32_t>(), nf, ov[cur].P.as<int32_t>(), ch->label.as<uint32_t>(),
+        memo.as<MemoSlot>(), mcap - 1, round, ch->level.as<uint32_t>(), ch->score.as<int32_t>(),
+        alive_g.as<uint8_t>(), cup.as<uint32_t>() + nf, cdn.as<uint32_t>() + nf,
+        cpair.as<uint32_t>() + nf, up, dn, ch->nup, ch->ndown, cpair.as<uint32_t>(), kb,
+        ekey.as<uint64_t>(), ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(),
+        S.as<uint8_t>(), newA.as<uint8_t>(), &dc()->err);
+  }
+
+  static int pick_group(double work) {
+    if (work <= 4) return 4;
+    if (work <= 8) return 8;
+    if (work <= 16) return 16;
+    if (work <= 32) return 32;
+    return 64;
+  }
+
+  template <typename F4, typename F8, typename F16, typename F32, typename F64>
+  static void dispatch(int G, F4 f4, F8 f8, F16 f16, F32 f32, F64 f64) {
+    switch (G) {
+      case 4: f4(); break;
+      case 8: f8(); break;
+      case 16: f16(); break;
+      case 32: f32(); break;
+      default: f64(); break;
+    }
+  }
+
+  // ------------------------------------------------------------- rounds
+  int run(const ch_graph_t *g) {
+    HIP_TRY(dctr.ensure(sizeof(DevCtr)));
+    HIP_TRY(hipHostMalloc((void **)&hctr, sizeof(DevCtr), hipHostMallocDefault));
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    const bool stats = prm.flags & CH_F_STATS;
+
+    TRY(ingest(g));
+
+    HIP_TRY(ch->level.ensure(std::max<uint64_t>(n, 1) * 4));
+    HIP_TRY(ch->score.ensure(std::max<uint64_t>(n, 1) * 4));
+    HIP_TRY(alive_g.ensure(std::max<uint64_t>(n, 1)));
+    HIP_TRY(fill_u32(ch->level.as<uint32_t>(), SP_INF32, n, st));
+    HIP_TRY(hipMemsetAsync(ch->score.p, 0, (size_t)n * 4, st));
+    HIP_TRY(fill_u8(alive_g.as<uint8_t>(), 1, n, st));
+    const size_t nn = std::max<uint64_t>(n, 1);
+    HIP_TRY(aflag.ensure(nn));
+    HIP_TRY(aflag_next.ensure(nn));
+    HIP_TRY(wflag.ensure(nn));
+    HIP_TRY(F.ensure(nn));
+    HIP_TRY(S.ensure(nn));
+    HIP_TRY(newA.ensure(nn));
+    HIP_TRY(key.ensure(nn * 8));
+    HIP_TRY(paircnt.ensure(nn * 4));
+    HIP_TRY(newid.ensure(nn * 4));
+    HIP_TRY(cnt.ensure(nn * 4));
+    HIP_TRY(vw.ensure(nn * 4));
+    HIP_TRY(va.ensure(nn * 4));
+    HIP_TRY(vf.ensure(nn * 4));
+    HIP_TRY(ovf1.ensure(nn * 4));
+    HIP_TRY(ovf2.ensure(nn * 4));
+    HIP_TRY(fill_u8(aflag.as<uint8_t>(), 1, n, st));
+    HIP_TRY(iota_u32(vw.as<uint32_t>(), n, st));
+    HIP_TRY(iota_u32(va.as<uint32_t>(), n, st));
+    uint32_t nw = n, na = n;
+    // CH arc buffers: start at the input size
+    up_cap = dn_cap = std::max<uint64_t>(ch->m_input, 16);
+    DBuf *ub[] = {&ch->up_t, &ch->up_h, &ch->up_w, &ch->up_m, &ch->dn_t, &ch->dn_h, &ch->dn_w,
+                  &ch->dn_m};
+    for (DBuf *b : ub) HIP_TRY(b->ensure(up_cap * 4));
+    ch->nup = ch->ndown = 0;
+    TRY(ensure_memo(std::max<uint64_t>(ch->m_input, 1) * 4));
+
+    uint32_t round = 0;
+    while (ov[cur].n > 0) {
+      if (prm.max_rounds && round >= prm.max_rounds)
+        return set_error(CH_E_LIMIT, "max_rounds reached before every vertex was contracted");
+      OvBuf &O = ov[cur];
+      Overlay v = view(O);
+      ch_round_stats_t rs{};
+      rs.alive_before = O.n;
+      rs.n_sources = nw;
+      rs.n_affected = na;
+      if (stats) HIP_TRY(hipEventRecord(ev[1], st));
+      const double avgdeg = O.n ? (double)O.m / O.n : 0.0;
+
+      // ---- Step 1: LocalSearch (Alg. 3) --------------------------------
+      HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
+      if (nw) {
+        k_ls_bound<<<grid(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(),
+                                             &dc()->bound);
+        HIP_TRY(hipGetLastError());
+        TRY(readback());
+        TRY(ensure_memo(hctr->bound));
+        if (stats) HIP_TRY(hipEventRecord(ev[2], st));
+        k_local_search<16, 128><<<(unsigned)cus * 16, kLsBlock, 0, st>>>(
+            v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap - 1,
+            &dc()->ls, ovf1.as<uint32_t>(), &dc()->err);
+        HIP_TRY(hipGetLastError());
+        if (stats) HIP_TRY(hipEventRecord(ev[3], st));
+        TRY(readback());
+        // counters of the LDS fast-path kernel alone (the measured kernel)
+        rs.rows_expanded = hctr->ls.rows;
+        rs.arcs_scanned = hctr->ls.arcs;
+        rs.memo_probes = hctr->ls.probes;
+        rs.memo_inserts = hctr->ls.inserts;
+        uint32_t novf = hctr->ls.ovf_count;
+        if (novf) {
+          HIP_TRY(hipMemsetAsync(&dc()->ls.work, 0, 8, st));
+          k_local_search<64, 2048><<<(unsigned)cus * 4, kLsBlock, 0, st>>>(
+              v, ovf1.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap - 1,
+              &dc()->ls, ovf2.as<uint32_t>(), &dc()->err);
+          HIP_TRY(hipGetLastError());
+          TRY(readback());
+          const uint32_t novf2 = hctr->ls.ovf_count;
+          if (novf2) {
+            const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
+            const size_t per = ((size_t)cap * 6 + 4) * 4;
+            size_t ntab = std::max<size_t>(1, std::min<size_t>(
+                                                  {(size_t)novf2, (size_t)cus * 2,
+                                                   (size_t)(4ull << 30) / per}));
+            HIP_TRY(gtabs.ensure(ntab * per));
+            // key, dist = all ones; flag, order, fronts, counters = 0
+            for (size_t t = 0; t < ntab; t++) {
+              uint32_t *b = gtabs.as<uint32_t>() + t * (per / 4);
+              HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));
+              HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, ((size_t)cap * 4 + 4) * 4, st));
+            }
+            k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
+                v, ovf2.as<uint32_t>(), novf2, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
+                mcap - 1, &dc()->ls, gtabs.as<uint32_t>(), cap, &dc()->err);
+            HIP_TRY(hipGetLastError());
+          }
+        }
+        TRY(readback());
+        TRY(check_err());
+        mcount += hctr->ls.inserts;
+        rs.n_targets = hctr->ls.targets;
+        rs.n_ls_fallback = novf;
+
+        // pruning at the end of Alg. 3
+        k_prune<<<grid(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, memo.as<MemoSlot>(), mcap - 1,
+                                          &dc()->pruned, &dc()->err);
+        HIP_TRY(hipGetLastError());
+      }
+
+      // ---- Step 2: Score (Alg. 4) --------------------------------------
+      const int Gs = prm.group ? (int)prm.group : pick_group(avgdeg * avgdeg / 4.0);
+      if (na) {
+        dispatch(Gs, [&] { launch_score<4>(v, na); }, [&] { launch_score<8>(v, na); },
+                 [&] { launch_score<16>(v, na); }, [&] { launch_score<32>(v, na); },
+                 [&] { launch_score<64>(v, na); });
+        HIP_TRY(hipGetLastError());
+      }
+
+      // ---- Step 3: Select (Alg. 5) -------------------------------------
+      k_keys<<<grid(O.n), 256, 0, st>>>(O.n, O.P.as<int32_t>(), O.gid.as<uint32_t>(),
+                                        ch->label.as<uint32_t>(), key.as<uint64_t>());
+      HIP_TRY(hipGetLastError());
+      const int Gsel = prm.group ? (int)prm.group : pick_group(avgdeg);
+      dispatch(Gsel, [&] { launch_select<4>(v); }, [&] { launch_select<8>(v); },
+               [&] { launch_select<16>(v); }, [&] { launch_select<32>(v); },
+               [&] { launch_select<64>(v); });
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(select_flags(F.as<uint8_t>(), O.n, vf.as<uint32_t>(), &dc()->c32[C_NF], tmp, st));
+      TRY(readback());
+      TRY(check_err());
+      const uint32_t nf = hctr->c32[C_NF];
+      rs.n_selected = nf;
+      rs.n_pruned = hctr->pruned;
+      if (nf == 0) return set_error(CH_E_DEVICE, "no vertex selected in a round (internal error)");
+
+      // ---- Step 4: Contract (Alg. 6) -----------------------------------
+      HIP_TRY(cup.ensure(((size_t)nf * 2 + 1) * 4));
+      HIP_TRY(cdn.ensure(((size_t)nf * 2 + 1) * 4));
+      HIP_TRY(cpair.ensure(((size_t)nf * 2 + 1) * 4));
+      dispatch(Gs, [&] { launch_ccount<4>(v, nf); }, [&] { launch_ccount<8>(v, nf); },
+               [&] { launch_ccount<16>(v, nf); }, [&] { launch_ccount<32>(v, nf); },
+               [&] { launch_ccount<64>(v, nf); });
+      HIP_TRY(hipGetLastError());
+      // exclusive scans into the second halves (counts stay in the first)
+      HIP_TRY(scan_u32(cup.as<uint32_t>(), cup.as<uint32_t>() + nf, nf, &dc()->c32[C_UP], tmp, st));
+      HIP_TRY(scan_u32(cdn.as<uint32_t>(), cdn.as<uint32_t>() + nf, nf, &dc()->c32[C_DN], tmp, st));
+      HIP_TRY(scan_u32(cpair.as<uint32_t>(), cpair.as<uint32_t>() + nf, nf, &dc()->c32[C_PAIR],
+                       tmp, st));
+      TRY(readback());
+      const uint32_t tup = hctr->c32[C_UP], tdn = hctr->c32[C_DN], ne = hctr->c32[C_PAIR];
+      if (ch->nup + tup > up_cap) {
+        uint64_t nc = std::max<uint64_t>((ch->nup + tup) * 3 / 2, up_cap * 2);
+        for (int i = 0; i < 4; i++) TRY(grow_copy(*ub[i], ch->nup * 4, nc * 4));
+        up_cap = nc;
+      }
+      if (ch->ndown + tdn > dn_cap) {
+        uint64_t nc = std::max<uint64_t>((ch->ndown + tdn) * 3 / 2, dn_cap * 2);
+        for (int i = 4; i < 8; i++) TRY(grow_copy(*ub[i], ch->ndown * 4, nc * 4));
+        dn_cap = nc;
+      }
+      const size_t ne1 = std::max<uint32_t>(ne, 1);
+      HIP_TRY(ekey.ensure(ne1 * 8));
+      HIP_TRY(ekey_alt.ensure(ne1 * 8));
+      HIP_TRY(eidx.ensure(ne1 * 4));
+      HIP_TRY(eidx_alt.ensure(ne1 * 4));
+      HIP_TRY(ew.ensure(ne1 * 4));
+      HIP_TRY(elab.ensure(ne1 * 4));
+      HIP_TRY(emid.ensure(ne1 * 4));
+      HIP_TRY(ehead.ensure(ne1));
+      HIP_TRY(eheads.ensure(ne1 * 4));
+      HIP_TRY(ukey.ensure(ne1 * 8));
+      HIP_TRY(uw.ensure(ne1 * 4));
+      HIP_TRY(umid.ensure(ne1 * 4));
+      HIP_TRY(rkey.ensure(ne1 * 8));
+      HIP_TRY(rkey_alt.ensure(ne1 * 8));
+      HIP_TRY(ridx.ensure(ne1 * 4));
+      HIP_TRY(ridx_alt.ensure(ne1 * 4));
+      HIP_TRY(hipMemsetAsync(S.p, 0, O.n, st));
+      HIP_TRY(hipMemsetAsync(newA.p, 0, O.n, st));
+      const int kb = bits_for(O.n);
+      dispatch(Gs, [&] { launch_contract<4>(v, nf, round, kb); },
+               [&] { launch_contract<8>(v, nf, round, kb); },
+               [&] { launch_contract<16>(v, nf, round, kb); },
+               [&] { launch_contract<32>(v, nf, round, kb); },
+               [&] { launch_contract<64>(v, nf, round, kb); });
+      HIP_TRY(hipGetLastError());
+      ch->nup += tup;
+      ch->ndown += tdn;
+
+      // shortcut set E+: sort candidates by (v1, v2), keep the minimum
+      uint32_t U = 0;
+      if (ne) {
+        HIP_TRY(iota_u32(eidx.as<uint32_t>(), ne, st));
+        HIP_TRY(radix_sort_u64(ekey.as<uint64_t>(), eidx.as<uint32_t>(), ekey_alt.as<uint64_t>(),
+                               eidx_alt.as<uint32_t>(), ne, 2 * kb, tmp, st));
+        k_run_heads<<<grid(ne), 256, 0, st>>>(ekey.as<uint64_t>(), ne, ehead.as<uint8_t>());
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(select_flags(ehead.as<uint8_t>(), ne, eheads.as<uint32_t>(), &dc()->c32[C_HEADS],
+                             tmp, st));
+        k_eplus_reduce<<<grid(ne), 256, 0, st>>>(
+            ekey.as<uint64_t>(), eidx.as<uint32_t>(), ne, eheads.as<uint32_t>(),
+            &dc()->c32[C_HEADS], ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(),
+            ukey.as<uint64_t>(), uw.as<uint32_t>(), umid.as<uint32_t>());
+        HIP_TRY(hipGetLastError());
+        TRY(readback());
+        TRY(check_err());
+        U = hctr->c32[C_HEADS];
+        k_swap_key<<<grid(U), 256, 0, st>>>(ukey.as<uint64_t>(), &dc()->c32[C_HEADS], kb,
+                                            rkey.as<uint64_t>());
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(iota_u32(ridx.as<uint32_t>(), U, st));
+        HIP_TRY(radix_sort_u64(rkey.as<uint64_t>(), ridx.as<uint32_t>(), rkey_alt.as<uint64_t>(),
+                               ridx_alt.as<uint32_t>(), U, 2 * kb, tmp, st));
+      } else {
+        TRY(readback());
+        TRY(check_err());
+      }
+      rs.n_shortcuts = U;
+
+      // ---- overlay rebuild: drop V_F, merge E+ ---------------------------
+      k_keep<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), cnt.as<uint32_t>());
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(scan_u32(cnt.as<uint32_t>(), newid.as<uint32_t>(), O.n, &dc()->c32[C_NNEW], tmp, st));
+      TRY(readback());
+      const uint32_t n2 = hctr->c32[C_NNEW];
+      OvBuf &N = ov[cur ^ 1];
+      N.n = n2;
+      HIP_TRY(N.foff.ensure(((size_t)n2 + 1) * 4));
+      HIP_TRY(N.roff.ensure(((size_t)n2 + 1) * 4));
+      HIP_TRY(N.gid.ensure(std::max<size_t>(n2, 1) * 4));
+      HIP_TRY(N.P.ensure(std::max<size_t>(n2, 1) * 4));
+      k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
+          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
+          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, U,
+          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, nullptr);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.foff.as<uint32_t>(), n2, N.foff.as<uint32_t>() + n2,
+                       tmp, st));
+      k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
+          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
+          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), U,
+          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, nullptr);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.roff.as<uint32_t>(), n2, N.roff.as<uint32_t>() + n2,
+                       tmp, st));
+      HIP_TRY(hipMemcpyAsync(&dc()->c32[C_MF], N.foff.as<uint32_t>() + n2, 4,
+                             hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemcpyAsync(&dc()->c32[C_MR], N.roff.as<uint32_t>() + n2, 4,
+                             hipMemcpyDeviceToDevice, st));
+      TRY(readback());
+      const uint32_t m2 = hctr->c32[C_MF];
+      if (hctr->c32[C_MR] != m2)
+        return set_error(CH_E_DEVICE, "forward and reverse overlay disagree (internal error)");
+      N.m = m2;
+      HIP_TRY(N.farc.ensure(std::max<size_t>(m2, 1) * 8));
+      HIP_TRY(N.rarc.ensure(std::max<size_t>(m2, 1) * 8));
+      HIP_TRY(N.fmid.ensure(std::max<size_t>(m2, 1) * 4));
+      HIP_TRY(N.rmid.ensure(std::max<size_t>(m2, 1) * 4));
+      k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
+          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
+          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, U,
+          uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.foff.as<uint32_t>(),
+          N.farc.as<uint2>(), N.fmid.as<uint32_t>());
+      HIP_TRY(hipGetLastError());
+      k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
+          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
+          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), U,
+          uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
+          N.rarc.as<uint2>(), N.rmid.as<uint32_t>());
+      HIP_TRY(hipGetLastError());
+      // carry state; V_W' = V_S + N_in(V_S); V_A' = N(V_F)
+      HIP_TRY(hipMemsetAsync(wflag.p, 0, std::max<uint32_t>(n2, 1), st));
+      k_carry<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), newid.as<uint32_t>(),
+                                         O.gid.as<uint32_t>(), O.P.as<int32_t>(), S.as<uint8_t>(),
+                                         newA.as<uint8_t>(), N.gid.as<uint32_t>(),
+                                         N.P.as<int32_t>(), wflag.as<uint8_t>(),
+                                         aflag_next.as<uint8_t>());
+      HIP_TRY(hipGetLastError());
+      k_mark_in_neighbours<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), S.as<uint8_t>(),
+                                                      newid.as<uint32_t>(), N.roff.as<uint32_t>(),
+                                                      N.rarc.as<uint2>(), wflag.as<uint8_t>());
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(select_flags(wflag.as<uint8_t>(), n2, vw.as<uint32_t>(), &dc()->c32[C_UP], tmp, st));
+      HIP_TRY(select_flags(aflag_next.as<uint8_t>(), n2, va.as<uint32_t>(), &dc()->c32[C_DN],
+                           tmp, st));
+      TRY(readback());
+      nw = hctr->c32[C_UP];
+      na = hctr->c32[C_DN];
+      std::swap(aflag, aflag_next);
+      cur ^= 1;
+      rs.overlay_arcs = m2;
+      if (stats) {
+        HIP_TRY(hipEventRecord(ev[4], st));
+        HIP_TRY(hipEventSynchronize(ev[4]));
+        float ls = 0.f, tot = 0.f;
+        if (rs.n_sources) HIP_TRY(hipEventElapsedTime(&ls, ev[2], ev[3]));
+        HIP_TRY(hipEventElapsedTime(&tot, ev[1], ev[4]));
+        rs.ms_local_search = ls;
+        rs.ms_total = tot;
+      }
+      ch->stats.push_back(rs);
+      round++;
+    }
+    ch->rounds = round;
+    return CH_OK;
+  }
+};
+
+int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out) {
+  clear_error();
+  if (!g || !out) return set_error(CH_E_INVALID, "graph and out must not be NULL");
+  ch_params_t prm{};
+  if (p) prm = *p;
+  if (prm.wps_mode != CH_WPS_EXACT) return set_error(CH_E_UNSUPPORTED, "unknown wps_mode");
+  if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&
+      prm.group != 64)
+    return set_error(CH_E_INVALID, "group must be 0, 4, 8, 16, 32 or 64");
+  if (g->n == 0xFFFFFFFFu) return set_error(CH_E_INVALID, "n must be at most 0xFFFFFFFE");
+  if (!g->offsets || (g->m && (!g->dst || !g->w)))
+    return set_error(CH_E_INVALID, "offsets, dst and w must not be NULL");
+  ch_s *ch = new (std::nothrow) ch_s();
+  if (!ch) return set_error(CH_E_OOM, "out of host memory");
+  ch->n = g->n;
+  hipError_t e = hipGetDevice(&ch->device);
+  if (e != hipSuccess) {
+    delete ch;
+    return hip_error(e, "hipGetDevice");
+  }
+  if (prm.stream) {
+    ch->stream = (hipStream_t)prm.stream;
+  } else {
+    e = hipStreamCreateWithFlags(&ch->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete ch;
+      return hip_error(e, "hipStreamCreate");
+    }
+    ch->own_stream = true;
+  }
+  int rc;
+  {
+    Builder b;
+    b.ch = ch;
+    b.st = ch->stream;
+    b.prm = prm;
+    b.n = g->n;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device) ==
+            hipSuccess &&
+        cus > 0)
+      b.cus = cus;
+    hipEvent_t t0, t1;
+    (void)hipEventCreate(&t0);
+    (void)hipEventCreate(&t1);
+    (void)hipEventRecord(t0, b.st);
+    rc = b.run(g);
+    if (rc == CH_OK) rc = postprocess(ch, !(prm.flags & CH_F_NO_QUERY_INDEX));
+    (void)hipEventRecord(t1, b.st);
+    if (rc == CH_OK) {
+      hipError_t se = hipEventSynchronize(t1);
+      if (se != hipSuccess) rc = hip_error(se, "build");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, t0, t1);
+      ch->summary.ms_build = ms;
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    if (rc == CH_OK) ch->summary.memo_entries = b.mcount;
+  }
+  if (rc != CH_OK) {
+    (void)hipStreamSynchronize(ch->stream);
+    delete ch;
+    return rc;
+  }
+  ch->summary.n = ch->n;
+  ch->summary.rounds = ch->rounds;
+  ch->summary.m_input = ch->m_input;
+  ch->summary.up_arcs = ch->nup;
+  ch->summary.down_arcs = ch->ndown;
+  uint64_t sc = 0;
+  for (auto &r : ch->stats) sc += r.n_shortcuts;
+  ch->summary.shortcuts = sc;
+  *out = ch;
+  return CH_OK;
+}
+
+}  // namespace sp
+
+ch_s::~ch_s() {
+  sp::DBuf *all[] = {&level, &score, &label, &rank, &up_t, &up_h, &up_w, &up_m, &dn_t, &dn_h,
+                     &dn_w, &dn_m, &q_upoff, &q_uparc, &q_dnoff, &q_dnarc, &q_s, &q_t, &q_d,
+                     &q_ovf, &q_tab, &q_ctr};
+  for (sp::DBuf *b : all) b->release();
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}

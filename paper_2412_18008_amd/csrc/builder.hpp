@@ -1,0 +1,56 @@
+// builder.hpp -- internal definitions shared by the builder, the query code
+// and the C ABI.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/spoch.h"
+#include "prim.hpp"
+
+// The finished contraction hierarchy (library-owned, device-resident).
+struct ch_s {
+  uint32_t n = 0;
+  uint64_t m_input = 0;
+  uint32_t rounds = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+
+  // per vertex, original ids
+  sp::DBuf level, score, label, rank;
+
+  // CH arcs in original ids, sorted as documented by ch_export
+  uint64_t nup = 0, ndown = 0;
+  sp::DBuf up_t, up_h, up_w, up_m;
+  sp::DBuf dn_t, dn_h, dn_w, dn_m;
+
+  // query index in rank space: upward arcs stored at their tail, downward
+  // arcs stored at their head (walked head -> tail by the backward search)
+  bool has_index = false;
+  sp::DBuf q_upoff, q_uparc, q_dnoff, q_dnarc;  // offsets uint32[n+1], arcs uint2{other, w}
+
+  // query scratch
+  sp::DBuf q_s, q_t, q_d, q_ovf, q_tab, q_ctr;
+
+  std::vector<ch_round_stats_t> stats;
+  ch_summary_t summary{};
+
+  ~ch_s();
+};
+
+namespace sp {
+
+// Records the message and returns code (thread-local last error).
+int set_error(int code, const std::string &msg);
+int hip_error(hipError_t e, const char *what);
+
+// Build entry (builder.hip).
+int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out);
+// Postprocess: rank, sorted arc lists, query index (post.hip).
+int postprocess(ch_s *ch, bool make_index);
+// Query batch (post.hip).
+int query_batch(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
+                uint64_t *dist, uint32_t flags, hipStream_t st);
+
+}  // namespace sp

@@ -1,0 +1,192 @@
+// common.hpp -- device helpers shared by the gfx950 kernels of the CH library.
+//
+// Wave size is 64.  Many kernels split a wave into "groups" of G lanes
+// (G in {4, 8, 16, 32, 64}); each group works on one item (a vertex, a
+// search source, a query) and its lanes cooperate through shuffles that stay
+// inside the group.  Group lanes are converged whenever a group collective
+// is called.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SP_INF32 0xFFFFFFFFu
+#define SP_MAXW 0xFFFFFFFEu
+#define SP_NOMID 0xFFFFFFFFu
+#define SP_EMPTY32 0xFFFFFFFFu
+#define SP_EMPTY64 0xFFFFFFFFFFFFFFFFull
+#define SP_INF64 0xFFFFFFFFFFFFFFFFull
+
+namespace sp {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Orders LDS accesses between lanes of one wave (the wave executes in
+// lockstep, but the compiler must not move LDS operations across this point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int G>
+__device__ __forceinline__ int glane() { return lane_id() & (G - 1); }
+
+template <int G>
+__device__ __forceinline__ uint64_t group_mask_bits() {
+  return G == 64 ? ~0ull : (((1ull << G) - 1ull) << (lane_id() & ~(G - 1)));
+}
+
+// Ballot restricted to this lane's group, shifted down to bit 0.
+template <int G>
+__device__ __forceinline__ uint64_t gballot(bool p) {
+  uint64_t b = __ballot(p);
+  if (G == 64) return b;
+  return (b >> (lane_id() & ~(G - 1))) & ((1ull << G) - 1ull);
+}
+
+template <int G>
+__device__ __forceinline__ bool gany(bool p) { return gballot<G>(p) != 0; }
+
+template <int G, typename T>
+__device__ __forceinline__ T gshfl(T v, int src) { return __shfl(v, src, G); }
+
+template <int G>
+__device__ __forceinline__ uint32_t gsum(uint32_t v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t gsum64(uint64_t v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, G);
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t gmax(uint32_t v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, G));
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t gmin64(uint64_t v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    uint64_t x = __shfl_xor(v, o, G);
+    v = x < v ? x : v;
+  }
+  return v;
+}
+
+// Inclusive prefix sum over the group.
+template <int G>
+__device__ __forceinline__ uint32_t gscan_incl(uint32_t v) {
+  const int l = glane<G>();
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    uint32_t x = __shfl_up(v, o, G);
+    if (l >= o) v += x;
+  }
+  return v;
+}
+
+// Lowest group lane whose inclusive prefix exceeds idx (binary search over
+// the group's prefix values; every group lane must call it).
+template <int G>
+__device__ __forceinline__ int gfind(uint32_t incl, uint32_t idx) {
+  int lo = 0;
+#pragma unroll
+  for (int step = G / 2; step > 0; step >>= 1) {
+    int probe = lo + step - 1;
+    uint32_t pv = __shfl(incl, probe, G);
+    if (pv <= idx) lo += step;
+  }
+  return lo;
+}
+
+// Published integer hashes (own implementations):
+//  - fmix32: the 32-bit finaliser of Appleby's MurmurHash3 (a bijection);
+//  - lowbias32: Wellons' "hash-prospector" 32-bit mixer.
+__host__ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+__host__ __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// Memo: open addressing over 16-byte slots {key = (s << 32) | v, value}.
+// The probe sequence of a pair starts inside a 16-slot bucket chosen by the
+// source s, so the ~10-30 entries of one source share one or two 128-byte
+// lines, and continues linearly (wrapping) through the table.
+// ---------------------------------------------------------------------------
+struct MemoSlot {
+  uint64_t key;
+  uint32_t val;
+  uint32_t pad;
+};
+
+__device__ __forceinline__ uint64_t memo_start(uint32_t s, uint32_t v, uint64_t mask) {
+  uint64_t b = ((uint64_t)lowbias32(s) << 4) | (lowbias32(v ^ 0x9e3779b9u) & 15u);
+  return b & mask;
+}
+
+// Returns the stored value or SP_INF32 when the pair is absent.
+__device__ __forceinline__ uint32_t memo_get(const MemoSlot *__restrict__ t, uint64_t mask,
+                                             uint32_t s, uint32_t v, uint32_t *probes) {
+  const uint64_t k = ((uint64_t)s << 32) | v;
+  uint64_t i = memo_start(s, v, mask);
+  for (;;) {
+    (*probes)++;
+    const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(&t[i]);
+    if (e.x == k) return (uint32_t)e.y;
+    if (e.x == SP_EMPTY64) return SP_INF32;
+    i = (i + 1) & mask;
+  }
+}
+
+// Insert (s, v) -> val if the pair is absent (first writer wins).
+__device__ __forceinline__ void memo_put(MemoSlot *__restrict__ t, uint64_t mask, uint32_t s,
+                                         uint32_t v, uint32_t val) {
+  const uint64_t k = ((uint64_t)s << 32) | v;
+  uint64_t i = memo_start(s, v, mask);
+  for (;;) {
+    uint64_t cur = __hip_atomic_load(&t[i].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cur == k) return;
+    if (cur == SP_EMPTY64) {
+      uint64_t prev = atomicCAS((unsigned long long *)&t[i].key, (unsigned long long)SP_EMPTY64,
+                                (unsigned long long)k);
+      if (prev == SP_EMPTY64) {
+        t[i].val = val;
+        return;
+      }
+      if (prev == k) return;
+    }
+    i = (i + 1) & mask;
+  }
+}
+
+// Device-side error flags (bit set by any kernel, read by the host).
+enum : uint32_t {
+  kErrOverflow = 1u,  // search bound or shortcut weight above 0xFFFFFFFE
+  kErrCapacity = 2u,  // an internal buffer bound was exceeded (a bug)
+};
+
+}  // namespace sp

@@ -1,0 +1,572 @@
+// post.hip -- Postprocessing (re-index by level, then score) and the batched
+// s-t query on the finished contraction hierarchy, for gfx950.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+#include "builder.hpp"
+#include "common.hpp"
+
+namespace sp {
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_error(e_, #expr);  \
+  } while (0)
+
+static int bits_for(uint32_t n) {
+  int b = 1;
+  while (b < 32 && (1ull << b) < (uint64_t)n) b++;
+  return b;
+}
+
+// ===========================================================================
+// postprocess kernels
+// ===========================================================================
+__global__ void k_label_keys(uint32_t n, const uint32_t *__restrict__ label,
+                             uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    key[v] = label[v];
+    val[v] = v;
+  }
+}
+
+// (level, score) key of the vertex at each position of the label order.
+__global__ void k_level_keys(uint32_t n, const uint32_t *__restrict__ order,
+                             const uint32_t *__restrict__ level, const int32_t *__restrict__ score,
+                             uint64_t *__restrict__ key) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint32_t v = order[i];
+    key[i] = ((uint64_t)level[v] << 32) | ((uint32_t)score[v] ^ 0x80000000u);
+  }
+}
+
+__global__ void k_rank_from_order(uint32_t n, const uint32_t *__restrict__ order,
+                                  uint32_t *__restrict__ rank) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) rank[order[i]] = i;
+}
+
+// key = (rank[a] << kb) | rank[b] for arc list (a[i], b[i]).
+__global__ void k_arc_rank_keys(uint64_t m, const uint32_t *__restrict__ a,
+                                const uint32_t *__restrict__ b, const uint32_t *__restrict__ rank,
+                                int kb, uint64_t *__restrict__ key, uint32_t *__restrict__ val) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    key[i] = ((uint64_t)rank[a[i]] << kb) | rank[b[i]];
+    val[i] = (uint32_t)i;
+  }
+}
+
+__global__ void k_gather4(uint64_t m, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ s0,
+                          const uint32_t *__restrict__ s1, const uint32_t *__restrict__ s2,
+                          const uint32_t *__restrict__ s3, uint32_t *__restrict__ d0,
+                          uint32_t *__restrict__ d1, uint32_t *__restrict__ d2,
+                          uint32_t *__restrict__ d3) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint32_t p = perm[i];
+    d0[i] = s0[p];
+    d1[i] = s1[p];
+    d2[i] = s2[p];
+    d3[i] = s3[p];
+  }
+}
+
+// Query index from arcs sorted by key = (row rank << kb) | other rank.
+__global__ void k_index(uint32_t n, uint64_t m, int kb, const uint64_t *__restrict__ key,
+                        const uint32_t *__restrict__ w, uint32_t *__restrict__ off,
+                        uint2 *__restrict__ arc) {
+  const uint64_t lowmask = (1ull << kb) - 1ull;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+    const uint64_t target = (uint64_t)i << kb;
+    uint64_t lo = 0, hi = m;
+    while (lo < hi) {
+      const uint64_t md = (lo + hi) >> 1;
+      if (key[md] < target) lo = md + 1;
+      else hi = md;
+    }
+    off[i] = (uint32_t)lo;
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    arc[i] = make_uint2((uint32_t)(key[i] & lowmask), w[i]);
+}
+
+static unsigned gridn(uint64_t items) {
+  uint64_t g = (items + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+// Sorts one arc set (t, h, w, mid) by (rank[row side], rank[other side]) and
+// builds its query index.  up = true: row = tail; up = false: row = head.
+static int sort_arcs(ch_s *ch, bool up, DBuf &k1, DBuf &k2, DBuf &v1, DBuf &v2, DBuf &tmp,
+                     bool make_index) {
+  hipStream_t st = ch->stream;
+  const uint64_t m = up ? ch->nup : ch->ndown;
+  DBuf &t = up ? ch->up_t : ch->dn_t;
+  DBuf &h = up ? ch->up_h : ch->dn_h;
+  DBuf &w = up ? ch->up_w : ch->dn_w;
+  DBuf &mid = up ? ch->up_m : ch->dn_m;
+  const int kb = bits_for(ch->n);
+  if (m >= 0xFFFFFFFFull) return set_error(CH_E_UNSUPPORTED, "too many CH arcs");
+  const size_t m1 = std::max<uint64_t>(m, 1);
+  HIP_TRY(k1.ensure(m1 * 8));
+  HIP_TRY(k2.ensure(m1 * 8));
+  HIP_TRY(v1.ensure(m1 * 4));
+  HIP_TRY(v2.ensure(m1 * 4));
+  if (m) {
+    k_arc_rank_keys<<<gridn(m), 256, 0, st>>>(m, up ? t.as<uint32_t>() : h.as<uint32_t>(),
+                                              up ? h.as<uint32_t>() : t.as<uint32_t>(),
+                                              ch->rank.as<uint32_t>(), kb, k1.as<uint64_t>(),
+                                              v1.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(radix_sort_u64(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(),
+                           v2.as<uint32_t>(), (uint32_t)m, 2 * kb, tmp, st));
+  }
+  DBuf nt, nh, nw, nm;
+  HIP_TRY(nt.ensure(m1 * 4));
+  HIP_TRY(nh.ensure(m1 * 4));
+  HIP_TRY(nw.ensure(m1 * 4));
+  HIP_TRY(nm.ensure(m1 * 4));
+  if (m) {
+    k_gather4<<<gridn(m), 256, 0, st>>>(m, v1.as<uint32_t>(), t.as<uint32_t>(), h.as<uint32_t>(),
+                                        w.as<uint32_t>(), mid.as<uint32_t>(), nt.as<uint32_t>(),
+                                        nh.as<uint32_t>(), nw.as<uint32_t>(), nm.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  t.release();
+  h.release();
+  w.release();
+  mid.release();
+  t = nt;
+  h = nh;
+  w = nw;
+  mid = nm;
+  if (make_index) {
+    DBuf &off = up ? ch->q_upoff : ch->q_dnoff;
+    DBuf &arc = up ? ch->q_uparc : ch->q_dnarc;
+    HIP_TRY(off.ensure(((size_t)ch->n + 1) * 4));
+    HIP_TRY(arc.ensure(m1 * 8));
+    k_index<<<gridn(std::max<uint64_t>(m, (uint64_t)ch->n + 1)), 256, 0, st>>>(
+        ch->n, m, kb, k1.as<uint64_t>(), w.as<uint32_t>(), off.as<uint32_t>(), arc.as<uint2>());
+    HIP_TRY(hipGetLastError());
+  }
+  return CH_OK;
+}
+
+// Postprocessing: vertices are ordered by level, then by score at
+// contraction (low to high), then by label; the CH arcs are re-keyed to the
+// new ranks and sorted.
+int postprocess(ch_s *ch, bool make_index) {
+  hipStream_t st = ch->stream;
+  const uint32_t n = ch->n;
+  const size_t n1 = std::max<uint32_t>(n, 1);
+  DBuf k1, k2, v1, v2, tmp;
+  int rc = CH_OK;
+  do {
+    hipError_t e;
+    if ((e = k1.ensure(n1 * 8)) != hipSuccess || (e = k2.ensure(n1 * 8)) != hipSuccess ||
+        (e = v1.ensure(n1 * 4)) != hipSuccess ||
+        (e = v2.ensure(n1 * 4)) != hipSuccess || (e = ch->rank.ensure(n1 * 4)) != hipSuccess) {
+      rc = hip_error(e, "postprocess alloc");
+      break;
+    }
+    if (n) {
+      k_label_keys<<<gridn(n), 256, 0, st>>>(n, ch->label.as<uint32_t>(), k1.as<uint64_t>(),
+                                             v1.as<uint32_t>());
+      if ((e = radix_sort_u64(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(),
+                              v2.as<uint32_t>(), n, 32, tmp, st)) != hipSuccess) {
+        rc = hip_error(e, "rank sort");
+        break;
+      }
+      k_level_keys<<<gridn(n), 256, 0, st>>>(n, v1.as<uint32_t>(), ch->level.as<uint32_t>(),
+                                             ch->score.as<int32_t>(), k1.as<uint64_t>());
+      const int lb = bits_for(ch->rounds + 1);
+      if ((e = radix_sort_u64(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(),
+                              v2.as<uint32_t>(), n, 32 + lb, tmp, st)) != hipSuccess) {
+        rc = hip_error(e, "rank sort");
+        break;
+      }
+      k_rank_from_order<<<gridn(n), 256, 0, st>>>(n, v1.as<uint32_t>(), ch->rank.as<uint32_t>());
+      if ((e = hipGetLastError()) != hipSuccess) {
+        rc = hip_error(e, "rank");
+        break;
+      }
+    }
+    if ((rc = sort_arcs(ch, true, k1, k2, v1, v2, tmp, make_index)) != CH_OK) break;
+    if ((rc = sort_arcs(ch, false, k1, k2, v1, v2, tmp, make_index)) != CH_OK) break;
+    ch->has_index = make_index;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) rc = hip_error(e, "postprocess");
+  } while (0);
+  k1.release();
+  k2.release();
+  v1.release();
+  v2.release();
+  tmp.release();
+  return rc;
+}
+
+// ===========================================================================
+// query: one wave per query; upward closures of s (upward arcs) and of t
+// (downward arcs, walked backwards) in two vertex -> distance tables, then
+// the minimum of d_s(v) + d_t(v) over common vertices.  Label-correcting
+// relaxation gives exact closure distances in any order, and because every
+// tentative value is the length of a real path, the minimum is exact.
+// ===========================================================================
+enum : uint32_t { kQFront = 1u };
+
+template <typename IdxT, bool GL>
+struct QTab {
+  uint32_t *key;
+  unsigned long long *dist;
+  uint32_t *flag;
+  IdxT *order, *fr0, *fr1;
+  uint32_t *ctr;  // used, |fr0|, |fr1|, overflow
+  uint32_t cap, shift, limit;
+
+  __device__ __forceinline__ uint32_t ld(const uint32_t *p) const {
+    if constexpr (GL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  }
+  __device__ __forceinline__ void st(uint32_t *p, uint32_t v) const {
+    if constexpr (GL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+  }
+  __device__ __forceinline__ unsigned long long ld64(const unsigned long long *p) const {
+    if constexpr (GL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  }
+  __device__ __forceinline__ void st64(unsigned long long *p, unsigned long long v) const {
+    if constexpr (GL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+  }
+  __device__ __forceinline__ IdxT ldi(const IdxT *p) const {
+    if constexpr (GL) return (IdxT)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  }
+  __device__ __forceinline__ void sti(IdxT *p, IdxT v) const {
+    if constexpr (GL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+  }
+  __device__ __forceinline__ void sync() const {
+    if constexpr (GL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    wave_sync();
+  }
+  __device__ __forceinline__ int insert(uint32_t v) const {
+    uint32_t h = (v * 0x9E3779B1u) >> shift;
+    for (uint32_t probes = 0; probes < cap; probes++) {
+      uint32_t k = ld(&key[h]);
+      if (k == v) return (int)h;
+      if (k == SP_EMPTY32) {
+        uint32_t prev = atomicCAS(&key[h], SP_EMPTY32, v);
+        if (prev == SP_EMPTY32) {
+          uint32_t idx = atomicAdd(&ctr[0], 1u);
+          if (idx < limit) sti(&order[idx], (IdxT)h);
+          else atomicOr(&ctr[3], 1u);
+          return (int)h;
+        }
+        if (prev == v) return (int)h;
+      }
+      h = (h + 1) & (cap - 1);
+    }
+    atomicOr(&ctr[3], 1u);
+    return -1;
+  }
+  __device__ __forceinline__ int find(uint32_t v) const {
+    uint32_t h = (v * 0x9E3779B1u) >> shift;
+    for (uint32_t probes = 0; probes < cap; probes++) {
+      uint32_t k = ld(&key[h]);
+      if (k == v) return (int)h;
+      if (k == SP_EMPTY32) return -1;
+      h = (h + 1) & (cap - 1);
+    }
+    return -1;
+  }
+};
+
+template <typename IdxT, bool GL>
+__device__ void qtab_reset(const QTab<IdxT, GL> &T) {
+  const int l = lane_id();
+  T.sync();
+  uint32_t used = T.ld(&T.ctr[0]);
+  if (used > T.limit) used = T.limit;
+  for (uint32_t i = l; i < used; i += kWave) {
+    IdxT s = T.ldi(&T.order[i]);
+    T.st(&T.key[s], SP_EMPTY32);
+    T.st64(&T.dist[s], SP_INF64);
+    T.st(&T.flag[s], 0u);
+  }
+  T.sync();
+  if (used >= T.limit) {
+    for (uint32_t i = l; i < T.cap; i += kWave) {
+      T.st(&T.key[i], SP_EMPTY32);
+      T.st64(&T.dist[i], SP_INF64);
+      T.st(&T.flag[i], 0u);
+    }
+  }
+  if (l < 4) T.st(&T.ctr[l], 0u);
+  T.sync();
+}
+
+// Upward closure from `src` over (off, arc).  Returns false on overflow.
+template <typename IdxT, bool GL>
+__device__ bool closure(const QTab<IdxT, GL> &T, const uint32_t *__restrict__ off,
+                        const uint2 *__restrict__ arc, uint32_t src) {
+  const int l = lane_id();
+  T.sync();
+  if (l == 0) {
+    const int s = T.insert(src);
+    if (s >= 0) {
+      T.st64(&T.dist[s], 0ull);
+      T.st(&T.flag[s], kQFront);
+      T.sti(&T.fr0[0], (IdxT)s);
+      T.st(&T.ctr[1], 1u);
+    }
+  }
+  T.sync();
+  int cur = 0;
+  while (!T.ld(&T.ctr[3])) {
+    IdxT *fc = cur ? T.fr1 : T.fr0;
+    IdxT *fn = cur ? T.fr0 : T.fr1;
+    uint32_t *nc = &T.ctr[cur ? 2 : 1];
+    uint32_t *nn = &T.ctr[cur ? 1 : 2];
+    const uint32_t ncur = T.ld(nc);
+    if (ncur == 0) break;
+    T.sync();
+    if (l == 0) T.st(nn, 0u);
+    T.sync();
+    for (uint32_t fb = 0; fb < ncur; fb += kWave) {
+      const uint32_t i = fb + l;
+      uint32_t rs = 0, rl = 0;
+      unsigned long long dx = 0;
+      if (i < ncur) {
+        const IdxT x = T.ldi(&fc[i]);
+        atomicAnd(&T.flag[x], ~kQFront);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        dx = T.ld64(&T.dist[x]);
+        const uint32_t vx = T.ld(&T.key[x]);
+        rs = off[vx];
+        rl = off[vx + 1] - rs;
+      }
+      const uint32_t incl = gscan_incl<kWave>(rl);
+      const uint32_t total = __shfl(incl, kWave - 1, kWave);
+      for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+        const uint32_t idx = i0 + l;
+        const int srcl = gfind<kWave>(incl, idx);
+        const uint32_t srs = __shfl(rs, srcl, kWave), sinc = __shfl(incl, srcl, kWave);
+        const uint32_t srl = __shfl(rl, srcl, kWave);
+        const unsigned long long sdx = __shfl(dx, srcl, kWave);
+        if (idx < total) {
+          const uint2 b = arc[srs + (idx - (sinc - srl))];
+          const unsigned long long nd = sdx + b.y;
+          const int y = T.insert(b.x);
+          if (y >= 0) {
+            const unsigned long long old = atomicMin(&T.dist[y], nd);
+            if (nd < old) {
+              const uint32_t f = atomicOr(&T.flag[y], kQFront);
+              if (!(f & kQFront)) {
+                const uint32_t p = atomicAdd(nn, 1u);
+                if (p < T.cap) T.sti(&fn[p], (IdxT)y);
+              }
+            }
+          }
+        }
+        T.sync();
+        if (T.ld(&T.ctr[3])) break;
+      }
+      if (T.ld(&T.ctr[3])) break;
+    }
+    T.sync();
+    cur ^= 1;
+  }
+  T.sync();
+  return !T.ld(&T.ctr[3]);
+}
+
+template <typename IdxT, bool GL>
+__device__ unsigned long long meet(const QTab<IdxT, GL> &Fw, const QTab<IdxT, GL> &Bw) {
+  const int l = lane_id();
+  unsigned long long best = SP_INF64;
+  const uint32_t used = Fw.ld(&Fw.ctr[0]);
+  for (uint32_t i = l; i < used; i += kWave) {
+    const IdxT s = Fw.ldi(&Fw.order[i]);
+    const int b = Bw.find(Fw.ld(&Fw.key[s]));
+    if (b >= 0) {
+      const unsigned long long c = Fw.ld64(&Fw.dist[s]) + Bw.ld64(&Bw.dist[b]);
+      best = c < best ? c : best;
+    }
+  }
+  return gmin64<kWave>(best);
+}
+
+constexpr int kQCap = 1024;
+
+__global__ void __launch_bounds__(64) k_query(
+    uint64_t q, const uint32_t *__restrict__ qs, const uint32_t *__restrict__ qt,
+    const uint32_t *__restrict__ rank, const uint32_t *__restrict__ upoff,
+    const uint2 *__restrict__ uparc, const uint32_t *__restrict__ dnoff,
+    const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
+    uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count) {
+  __shared__ uint32_t s_key[2][kQCap];
+  __shared__ unsigned long long s_dist[2][kQCap];
+  __shared__ uint32_t s_flag[2][kQCap];
+  __shared__ uint16_t s_order[2][kQCap];
+  __shared__ uint16_t s_fr[2][2][kQCap];
+  __shared__ uint32_t s_ctr[2][4];
+  const int l = lane_id();
+  for (int d = 0; d < 2; d++) {
+    for (int i = l; i < kQCap; i += kWave) {
+      s_key[d][i] = SP_EMPTY32;
+      s_dist[d][i] = SP_INF64;
+      s_flag[d][i] = 0;
+    }
+    if (l < 4) s_ctr[d][l] = 0;
+  }
+  wave_sync();
+  QTab<uint16_t, false> T[2];
+  for (int d = 0; d < 2; d++) {
+    T[d].key = s_key[d];
+    T[d].dist = s_dist[d];
+    T[d].flag = s_flag[d];
+    T[d].order = s_order[d];
+    T[d].fr0 = s_fr[d][0];
+    T[d].fr1 = s_fr[d][1];
+    T[d].ctr = s_ctr[d];
+    T[d].cap = kQCap;
+    T[d].shift = 32 - __builtin_ctz(kQCap);
+    T[d].limit = (kQCap * 3) / 4;
+  }
+  for (uint64_t k = blockIdx.x; k < q; k += gridDim.x) {
+    const uint32_t rs = rank[qs[k]], rt = rank[qt[k]];
+    bool ok = closure(T[0], upoff, uparc, rs);
+    if (ok) ok = closure(T[1], dnoff, dnarc, rt);
+    if (ok) {
+      const unsigned long long mu = meet(T[0], T[1]);
+      if (l == 0) dist[k] = mu;
+    } else if (l == 0) {
+      const uint32_t p = atomicAdd(ovf_count, 1u);
+      ovf_list[p] = (uint32_t)k;
+    }
+    qtab_reset(T[0]);
+    qtab_reset(T[1]);
+  }
+}
+
+// Fallback for queries whose closures outgrow LDS: tables in global memory
+// with cap >= 2n slots each (never overflow).
+__global__ void __launch_bounds__(64) k_query_global(
+    uint32_t nlist, const uint32_t *__restrict__ list, const uint32_t *__restrict__ qs,
+    const uint32_t *__restrict__ qt, const uint32_t *__restrict__ rank,
+    const uint32_t *__restrict__ upoff, const uint2 *__restrict__ uparc,
+    const uint32_t *__restrict__ dnoff, const uint2 *__restrict__ dnarc,
+    unsigned long long *__restrict__ dist, uint32_t *__restrict__ tabs, uint32_t cap) {
+  // per direction: key[cap], dist[cap] (2 words each), flag[cap], order, fr0,
+  // fr1 [cap] and 4 counters = 8 cap + 4 words
+  const size_t per = (size_t)cap * 8 + 4;
+  uint32_t *base = tabs + (size_t)blockIdx.x * 2 * per;
+  QTab<uint32_t, true> T[2];
+  for (int d = 0; d < 2; d++) {
+    uint32_t *b = base + d * per;
+    T[d].key = b;
+    T[d].dist = reinterpret_cast<unsigned long long *>(b + cap);
+    T[d].flag = b + 3 * (size_t)cap;
+    T[d].order = b + 4 * (size_t)cap;
+    T[d].fr0 = b + 5 * (size_t)cap;
+    T[d].fr1 = b + 6 * (size_t)cap;
+    T[d].ctr = b + 8 * (size_t)cap;
+    T[d].cap = cap;
+    T[d].shift = 32 - __builtin_ctz(cap);
+    T[d].limit = cap;
+  }
+  for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
+    const uint32_t k = list[i];
+    const uint32_t rs = rank[qs[k]], rt = rank[qt[k]];
+    closure(T[0], upoff, uparc, rs);
+    closure(T[1], dnoff, dnarc, rt);
+    const unsigned long long mu = meet(T[0], T[1]);
+    if (lane_id() == 0) dist[k] = mu;
+    qtab_reset(T[0]);
+    qtab_reset(T[1]);
+  }
+}
+
+__global__ void k_check_ids(uint64_t q, const uint32_t *__restrict__ s, const uint32_t *__restrict__ t,
+                            uint32_t n, uint32_t *__restrict__ bad) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride)
+    if (s[i] >= n || t[i] >= n) atomicOr(bad, 1u);
+}
+
+int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t q, uint64_t *dist,
+                uint32_t flags, hipStream_t st) {
+  ch_s *ch = const_cast<ch_s *>(chc);
+  if (!ch->has_index) return set_error(CH_E_INVALID, "the CH was built without a query index");
+  if (q == 0) return CH_OK;
+  if (!st) st = ch->stream;
+  const bool on_dev = flags & CH_Q_ON_DEVICE;
+  const uint32_t *ds = s, *dt = t;
+  unsigned long long *dd = reinterpret_cast<unsigned long long *>(dist);
+  HIP_TRY(ch->q_ctr.ensure(64));
+  if (!on_dev) {
+    HIP_TRY(ch->q_s.ensure(q * 4));
+    HIP_TRY(ch->q_t.ensure(q * 4));
+    HIP_TRY(ch->q_d.ensure(q * 8));
+    HIP_TRY(hipMemcpyAsync(ch->q_s.p, s, q * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ch->q_t.p, t, q * 4, hipMemcpyHostToDevice, st));
+    ds = ch->q_s.as<uint32_t>();
+    dt = ch->q_t.as<uint32_t>();
+    dd = ch->q_d.as<unsigned long long>();
+  }
+  HIP_TRY(ch->q_ovf.ensure(q * 4));
+  uint32_t *ctr = ch->q_ctr.as<uint32_t>();
+  HIP_TRY(hipMemsetAsync(ctr, 0, 64, st));
+  k_check_ids<<<gridn(q), 256, 0, st>>>(q, ds, dt, ch->n, ctr + 1);
+  HIP_TRY(hipGetLastError());
+  uint32_t hc[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hc[1]) return set_error(CH_E_INVALID, "a query vertex id is >= n");
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device);
+  const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 8);
+  k_query<<<(unsigned)g, 64, 0, st>>>(q, ds, dt, ch->rank.as<uint32_t>(),
+                                      ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(),
+                                      ch->q_dnoff.as<uint32_t>(), ch->q_dnarc.as<uint2>(), dd,
+                                      ch->q_ovf.as<uint32_t>(), ctr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hc[0]) {
+    uint64_t c = 1;
+    while (c < 2ull * ch->n + 2) c <<= 1;
+    const uint32_t cap = (uint32_t)std::min<uint64_t>(c, 1ull << 31);
+    const size_t per = ((size_t)cap * 8 + 4) * 4 * 2;
+    const size_t ntab = std::max<size_t>(
+        1, std::min<size_t>({(size_t)hc[0], (size_t)cus * 2, (size_t)(4ull << 30) / per}));
+    HIP_TRY(ch->q_tab.ensure(ntab * per));
+    // keys and dists all ones; flag, order, fronts, counters zero
+    for (size_t k = 0; k < 2 * ntab; k++) {
+      uint32_t *b = ch->q_tab.as<uint32_t>() + k * ((size_t)cap * 8 + 4);
+      HIP_TRY(fill_u32(b, SP_EMPTY32, 3ull * cap, st));
+      HIP_TRY(hipMemsetAsync(b + 3ull * cap, 0, ((size_t)cap * 5 + 4) * 4, st));
+    }
+    k_query_global<<<(unsigned)ntab, 64, 0, st>>>(
+        hc[0], ch->q_ovf.as<uint32_t>(), ds, dt, ch->rank.as<uint32_t>(),
+        ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(), ch->q_dnoff.as<uint32_t>(),
+        ch->q_dnarc.as<uint2>(), dd, ch->q_tab.as<uint32_t>(), cap);
+    HIP_TRY(hipGetLastError());
+  }
+  if (!on_dev) HIP_TRY(hipMemcpyAsync(dist, dd, q * 8, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return CH_OK;
+}
+
+}  // namespace sp

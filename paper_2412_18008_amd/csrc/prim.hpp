@@ -1,0 +1,45 @@
+// prim.hpp -- device-wide primitives (scan, compaction, radix sort) used by
+// the CH builder.  All run on a caller-given stream; scratch memory comes
+// from a caller-owned Workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace sp {
+
+// Growable device buffer (hipMalloc'ed; grows by 1.5x, never shrinks).
+struct DBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes);
+  void release();
+  template <typename T>
+  T *as() const { return reinterpret_cast<T *>(p); }
+};
+
+// Exclusive scan of n uint32 values; out may alias in.  *total_dev (device
+// pointer, may be null) receives the sum.
+hipError_t scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *total_dev,
+                    DBuf &tmp, hipStream_t st);
+// Same for uint64 values.
+hipError_t scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *total_dev,
+                    DBuf &tmp, hipStream_t st);
+
+// out[k] = i for the k-th i (ascending) with flags[i] != 0; *count_dev = k.
+hipError_t select_flags(const uint8_t *flags, uint32_t n, uint32_t *out, uint32_t *count_dev,
+                        DBuf &tmp, hipStream_t st);
+
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
+// Results end in keys/vals (the alt buffers are scratch of the same size).
+hipError_t radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
+                          uint32_t *vals_alt, uint32_t n, int bits, DBuf &tmp, hipStream_t st);
+
+// Fill helpers.
+hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);
+hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t st);
+hipError_t fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t st);
+hipError_t iota_u32(uint32_t *p, uint32_t n, hipStream_t st);
+
+}  // namespace sp

@@ -1,0 +1,692 @@
+// round_kernels.hpp -- kernels of one contraction round and of the input
+// ingest, for gfx950.  The host driver is builder.hip.
+//
+// Vertex ids inside a round are local ids 0..n_o-1 of the current overlay;
+// `gid` maps them to original ids.  Overlay rows are sorted by neighbour id.
+#pragma once
+
+#include "common.hpp"
+#include "search.hpp"
+
+namespace sp {
+
+// ===========================================================================
+// ingest
+// ===========================================================================
+
+// key = (tail << kb) | head for every input arc; self-loops get the
+// sentinel SP_EMPTY64 (sorted last, dropped).  Also validates the input.
+__global__ void k_ingest_keys(uint32_t n, uint64_t m, int kb, const uint64_t *__restrict__ off,
+                              const uint32_t *__restrict__ dst, const uint32_t *__restrict__ w,
+                              uint64_t *__restrict__ key, uint32_t *__restrict__ val,
+                              uint32_t *__restrict__ bad) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    const uint64_t a = off[u], b = off[u + 1];
+    if (a > b || b > m) {
+      atomicOr(bad, 1u);
+      continue;
+    }
+    for (uint64_t e = a; e < b; e++) {
+      const uint32_t v = dst[e], ww = w[e];
+      if (v >= n || ww == SP_INF32) atomicOr(bad, 2u);
+      key[e] = (v == u || v >= n) ? SP_EMPTY64 : (((uint64_t)u << kb) | v);
+      val[e] = ww;
+    }
+  }
+}
+
+// Marks the first element of each run of equal (non-sentinel) keys.
+__global__ void k_run_heads(const uint64_t *__restrict__ key, uint32_t m, uint8_t *__restrict__ head) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    head[i] = key[i] != SP_EMPTY64 && (i == 0 || key[i] != key[i - 1]);
+}
+
+// For each run head: the run's minimum weight.  Output arc k = (key, w).
+__global__ void k_run_min(const uint64_t *__restrict__ key, const uint32_t *__restrict__ w,
+                          uint32_t m, const uint32_t *__restrict__ heads, const uint32_t *nheads,
+                          uint64_t *__restrict__ okey, uint32_t *__restrict__ ow) {
+  const uint32_t nh = *nheads;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nh; k += stride) {
+    uint32_t i = heads[k];
+    const uint64_t kk = key[i];
+    uint32_t best = w[i];
+    for (uint32_t j = i + 1; j < m && key[j] == kk; j++) best = min(best, w[j]);
+    okey[k] = kk;
+    ow[k] = best;
+  }
+}
+
+// CSR from arcs sorted by key = (row << kb) | col: off[r] = first arc of row r.
+__global__ void k_csr_from_sorted(const uint64_t *__restrict__ key, const uint32_t *__restrict__ w,
+                                  const uint32_t *mcount, uint32_t n, int kb,
+                                  uint32_t *__restrict__ off, uint2 *__restrict__ arc,
+                                  uint32_t *__restrict__ mid) {
+  const uint32_t m = *mcount;
+  const uint64_t lowmask = (1ull << kb) - 1ull;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += stride) {
+    const uint64_t target = (uint64_t)i << kb;
+    uint32_t lo = 0, hi = m;
+    while (lo < hi) {
+      const uint32_t md = (lo + hi) >> 1;
+      if (key[md] < target) lo = md + 1;
+      else hi = md;
+    }
+    off[i] = lo;
+  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    arc[i] = make_uint2((uint32_t)(key[i] & lowmask), w[i]);
+    mid[i] = SP_NOMID;
+  }
+}
+
+// (a << kb) | b  ->  (b << kb) | a
+__global__ void k_swap_key(const uint64_t *__restrict__ in, const uint32_t *mcount, int kb,
+                           uint64_t *__restrict__ out) {
+  const uint32_t m = *mcount;
+  const uint64_t lowmask = (1ull << kb) - 1ull;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint64_t k = in[i];
+    out[i] = ((k & lowmask) << kb) | (k >> kb);
+  }
+}
+
+__global__ void k_default_labels(uint32_t n, uint32_t mixseed, uint32_t *__restrict__ lab) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    lab[v] = fmix32(v ^ mixseed);
+}
+
+__global__ void k_labels_to_keys(uint32_t n, const uint32_t *__restrict__ lab,
+                                 uint64_t *__restrict__ key) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) key[v] = lab[v];
+}
+
+__global__ void k_adjacent_equal(uint32_t n, const uint64_t *__restrict__ key,
+                                 uint32_t *__restrict__ bad) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x + 1; i < n; i += stride)
+    if (key[i] == key[i - 1]) atomicOr(bad, 4u);
+}
+
+// ===========================================================================
+// LocalSearch
+// ===========================================================================
+
+// Upper bound on this round's memo inserts: sum over s in V_W and affected
+// out-neighbours u of s of outdeg(u).
+__global__ void k_ls_bound(Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw,
+                           const uint8_t *__restrict__ aflag, unsigned long long *__restrict__ out) {
+  uint64_t acc = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) {
+    const uint32_t s = vw[i];
+    for (uint32_t e = ov.foff[s]; e < ov.foff[s + 1]; e++) {
+      const uint32_t u = ov.farc[e].x;
+      if (aflag[u]) acc += ov.foff[u + 1] - ov.foff[u];
+    }
+  }
+  acc = gsum64<kWave>(acc);
+  if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+}
+
+// Counters of the local search (device, accumulated per launch).
+struct LsCounters {
+  unsigned long long rows, arcs, probes, inserts, targets, searched;
+  uint32_t work;      // next source index (persistent scheduling)
+  uint32_t ovf_count; // sources deferred to the global-memory fallback
+};
+
+template <int G>
+__device__ __forceinline__ void flush_stats(const SearchStats &ss, LsCounters *c) {
+  uint64_t r = gsum64<kWave>(ss.rows), a = gsum64<kWave>(ss.arcs);
+  uint64_t p = gsum64<kWave>(ss.probes), in = gsum64<kWave>(ss.inserts);
+  uint64_t t = gsum64<kWave>(ss.targets), sr = gsum64<kWave>(ss.searched);
+  if (lane_id() == 0) {
+    atomicAdd(&c->rows, (unsigned long long)r);
+    atomicAdd(&c->arcs, (unsigned long long)a);
+    atomicAdd(&c->probes, (unsigned long long)p);
+    atomicAdd(&c->inserts, (unsigned long long)in);
+    atomicAdd(&c->targets, (unsigned long long)t);
+    atomicAdd(&c->searched, (unsigned long long)sr);
+  }
+}
+
+constexpr int kLsBlock = 64;  // one wave per workgroup
+constexpr uint32_t kLsChunk = 4;  // sources taken per scheduling step
+
+// LDS fast path: groups of G lanes, CAP-slot table per group.  Persistent:
+// every group takes kLsChunk sources at a time from a global counter.
+template <int G, int CAP>
+__global__ void __launch_bounds__(kLsBlock) k_local_search(
+    Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
+    MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
+    uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ err) {
+  constexpr int NG = kLsBlock / G;
+  __shared__ uint32_t s_key[NG][CAP];
+  __shared__ uint32_t s_dist[NG][CAP];
+  __shared__ uint32_t s_flag[NG][CAP];
+  __shared__ uint16_t s_order[NG][CAP];
+  __shared__ uint16_t s_fr[NG][2][CAP];
+  __shared__ uint32_t s_ctr[NG][4];
+  const int g = threadIdx.x / G, gl = glane<G>();
+  for (int i = gl; i < CAP; i += G) {
+    s_key[g][i] = SP_EMPTY32;
+    s_dist[g][i] = SP_INF32;
+    s_flag[g][i] = 0;
+  }
+  if (gl < 4) s_ctr[g][gl] = 0;
+  wave_sync();
+  Tab<uint16_t, false> T;
+  T.key = s_key[g];
+  T.dist = s_dist[g];
+  T.flag = s_flag[g];
+  T.order = s_order[g];
+  T.fr0 = s_fr[g][0];
+  T.fr1 = s_fr[g][1];
+  T.ctr = s_ctr[g];
+  T.cap = CAP;
+  T.shift = 32 - __builtin_ctz(CAP);
+  T.limit = (CAP * 3) / 4;
+  SearchStats ss;
+  for (;;) {
+    uint32_t base = 0;
+    if (gl == 0) base = atomicAdd(&cnt->work, kLsChunk);
+    base = gshfl<G>(base, 0);
+    if (base >= nw) break;
+    const uint32_t end = min(base + kLsChunk, nw);
+    for (uint32_t i = base; i < end; i++) {
+      const uint32_t s = vw[i];
+      if (!search_source<G>(ov, aflag, memo, mmask, T, s, ss, err)) {
+        if (gl == 0) {
+          const uint32_t k = atomicAdd(&cnt->ovf_count, 1u);
+          ovf_list[k] = s;
+        }
+      }
+    }
+  }
+  flush_stats<G>(ss, cnt);
+}
+
+// Global-memory fallback: one wave per source, table of `cap` slots per
+// wave at tabs + wave * stride_words (key, dist, flag, order, fr0, fr1 as
+// consecutive uint32 arrays of `cap`, then 4 counters).
+__global__ void __launch_bounds__(64) k_local_search_global(
+    Overlay ov, const uint32_t *__restrict__ list, uint32_t nlist,
+    const uint8_t *__restrict__ aflag, MemoSlot *__restrict__ memo, uint64_t mmask,
+    LsCounters *__restrict__ cnt, uint32_t *__restrict__ tabs, uint32_t cap,
+    uint32_t *__restrict__ err) {
+  uint32_t *base = tabs + (size_t)blockIdx.x * ((size_t)cap * 6 + 4);
+  Tab<uint32_t, true> T;
+  T.key = base;
+  T.dist = base + cap;
+  T.flag = base + 2 * (size_t)cap;
+  T.order = base + 3 * (size_t)cap;
+  T.fr0 = base + 4 * (size_t)cap;
+  T.fr1 = base + 5 * (size_t)cap;
+  T.ctr = base + 6 * (size_t)cap;
+  T.cap = cap;
+  T.shift = 32 - __builtin_ctz(cap);
+  T.limit = cap;  // cap >= 2 n_o: never overflows
+  SearchStats ss;
+  for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
+    if (!search_source<64>(ov, aflag, memo, mmask, T, list[i], ss, err)) {
+      if (lane_id() == 0) atomicOr(err, kErrCapacity);
+    }
+  }
+  flush_stats<64>(ss, cnt);
+}
+
+// Pruning (end of Alg. 3): an out-arc (s, v) of a source s whose weight
+// exceeds the memoized dist(s, v) is deleted (weight set to SP_INF32 in both
+// the forward row of s and the reverse row of v).
+__global__ void k_prune(Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw,
+                        const MemoSlot *__restrict__ memo, uint64_t mmask,
+                        unsigned long long *__restrict__ npruned, uint32_t *__restrict__ err) {
+  uint32_t probes = 0;
+  uint64_t c = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) {
+    const uint32_t s = vw[i];
+    const uint32_t gs = ov.gid[s];
+    for (uint32_t e = ov.foff[s]; e < ov.foff[s + 1]; e++) {
+      const uint2 a = ov.farc[e];
+      const uint32_t d = memo_get(memo, mmask, gs, ov.gid[a.x], &probes);
+      if (d != SP_INF32 && a.y > d) {
+        ov.farc[e].y = SP_INF32;
+        const uint32_t end = ov.roff[a.x + 1];
+        uint32_t lo = ov.roff[a.x], hi = end;
+        while (lo < hi) {
+          const uint32_t md = (lo + hi) >> 1;
+          if (ov.rarc[md].x < s) lo = md + 1;
+          else hi = md;
+        }
+        if (lo < end && ov.rarc[lo].x == s) ov.rarc[lo].y = SP_INF32;
+        else atomicOr(err, kErrCapacity);  // reverse twin missing: internal error
+        c++;
+      }
+    }
+  }
+  c = gsum64<kWave>(c);
+  if (lane_id() == 0 && c) atomicAdd(npruned, (unsigned long long)c);
+}
+
+// ===========================================================================
+// Score (Alg. 4) -- group of G lanes per affected vertex
+// ===========================================================================
+// Number of pairs (v1, v2) in N_in(u) x N_out(u), v1 != v2, both arcs live,
+// whose path through u is no longer than the memoized distance or whose
+// distance is not memoized.  Every group lane must call it.
+template <int G>
+__device__ __forceinline__ uint32_t count_pairs(const Overlay &ov, const MemoSlot *memo,
+                                                uint64_t mmask, uint32_t u, uint32_t *probes) {
+  const int gl = glane<G>();
+  const uint32_t i0 = ov.roff[u], din = ov.roff[u + 1] - i0;
+  const uint32_t o0 = ov.foff[u], dout = ov.foff[u + 1] - o0;
+  uint32_t cnt = 0;
+  const uint64_t np = (uint64_t)din * dout;
+  for (uint64_t p = gl; p < np; p += G) {
+    const uint32_t i = (uint32_t)(p / dout), j = (uint32_t)(p - (uint64_t)i * dout);
+    const uint2 a = ov.rarc[i0 + i], b = ov.farc[o0 + j];
+    if (a.y == SP_INF32 || b.y == SP_INF32 || a.x == b.x) continue;
+    const uint64_t via = (uint64_t)a.y + b.y;
+    const uint32_t d = memo_get(memo, mmask, ov.gid[a.x], ov.gid[b.x], probes);
+    if (d == SP_INF32 || via <= d) cnt++;
+  }
+  return gsum<G>(cnt);
+}
+
+// |N_in(u) union N_out(u)| over live arcs.  Every group lane must call it.
+template <int G>
+__device__ __forceinline__ uint32_t count_neighbours(const Overlay &ov, uint32_t u) {
+  const int gl = glane<G>();
+  const uint32_t i0 = ov.roff[u], i1 = ov.roff[u + 1];
+  const uint32_t o0 = ov.foff[u], o1 = ov.foff[u + 1];
+  uint32_t c = 0;
+  for (uint32_t e = o0 + gl; e < o1; e += G) c += ov.farc[e].y != SP_INF32;
+  for (uint32_t e = i0 + gl; e < i1; e += G) {
+    const uint2 a = ov.rarc[e];
+    if (a.y == SP_INF32) continue;
+    uint32_t lo = o0, hi = o1;
+    while (lo < hi) {
+      const uint32_t md = (lo + hi) >> 1;
+      if (ov.farc[md].x < a.x) lo = md + 1;
+      else hi = md;
+    }
+    const bool both = lo < o1 && ov.farc[lo].x == a.x && ov.farc[lo].y != SP_INF32;
+    c += both ? 0u : 1u;
+  }
+  return gsum<G>(c);
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_score(Overlay ov, const uint32_t *__restrict__ va,
+                                               uint32_t na, const MemoSlot *__restrict__ memo,
+                                               uint64_t mmask, int32_t *__restrict__ P,
+                                               uint32_t *__restrict__ paircnt) {
+  const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+  const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+  uint32_t probes = 0;
+  for (uint32_t k = g0; k < na; k += ngroups) {
+    const uint32_t u = va[k];
+    const uint32_t pairs = count_pairs<G>(ov, memo, mmask, u, &probes);
+    const uint32_t nb = count_neighbours<G>(ov, u);
+    if (glane<G>() == 0) {
+      int64_t p = (int64_t)pairs - (int64_t)nb;
+      p = p > INT32_MAX ? INT32_MAX : (p < INT32_MIN ? INT32_MIN : p);
+      P[u] = (int32_t)p;
+      paircnt[u] = pairs;
+    }
+  }
+}
+
+// ===========================================================================
+// Select (Alg. 5)
+// ===========================================================================
+__global__ void k_keys(uint32_t n, const int32_t *__restrict__ P, const uint32_t *__restrict__ gid,
+                       const uint32_t *__restrict__ label, uint64_t *__restrict__ key) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+    key[u] = ((uint64_t)((uint32_t)P[u] ^ 0x80000000u) << 32) | label[gid[u]];
+}
+
+// u is selected iff key(u) < key(v) for every live neighbour v (keys are
+// distinct because labels are).
+template <int G>
+__global__ void __launch_bounds__(256) k_select(Overlay ov, const uint64_t *__restrict__ key,
+                                                uint8_t *__restrict__ F) {
+  const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+  const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+  const int gl = glane<G>();
+  for (uint32_t u = g0; u < ov.n; u += ngroups) {
+    const uint64_t ku = key[u];
+    bool beaten = false;
+    for (uint32_t e = ov.foff[u] + gl; e < ov.foff[u + 1]; e += G) {
+      const uint2 b = ov.farc[e];
+      beaten |= b.y != SP_INF32 && key[b.x] < ku;
+    }
+    for (uint32_t e = ov.roff[u] + gl; e < ov.roff[u + 1]; e += G) {
+      const uint2 a = ov.rarc[e];
+      beaten |= a.y != SP_INF32 && key[a.x] < ku;
+    }
+    beaten = gany<G>(beaten);
+    if (gl == 0) F[u] = beaten ? 0 : 1;
+  }
+}
+
+// ===========================================================================
+// Contract (Alg. 6)
+// ===========================================================================
+// Per selected vertex: live out-arcs, live in-arcs, shortcut pairs (the
+// pair count of the score when the vertex was rescored this round).
+template <int G>
+__global__ void __launch_bounds__(256) k_contract_count(
+    Overlay ov, const uint32_t *__restrict__ vf, uint32_t nf, const uint8_t *__restrict__ aflag,
+    const uint32_t *__restrict__ paircnt, const MemoSlot *__restrict__ memo, uint64_t mmask,
+    uint32_t *__restrict__ cup, uint32_t *__restrict__ cdn, uint32_t *__restrict__ cpair) {
+  const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+  const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+  const int gl = glane<G>();
+  uint32_t probes = 0;
+  for (uint32_t k = g0; k < nf; k += ngroups) {
+    const uint32_t u = vf[k];
+    uint32_t co = 0, ci = 0;
+    for (uint32_t e = ov.foff[u] + gl; e < ov.foff[u + 1]; e += G) co += ov.farc[e].y != SP_INF32;
+    for (uint32_t e = ov.roff[u] + gl; e < ov.roff[u + 1]; e += G) ci += ov.rarc[e].y != SP_INF32;
+    co = gsum<G>(co);
+    ci = gsum<G>(ci);
+    uint32_t pc;
+    if (aflag[u]) pc = paircnt[u];
+    else pc = count_pairs<G>(ov, memo, mmask, u, &probes);
+    if (gl == 0) {
+      cup[k] = co;
+      cdn[k] = ci;
+      cpair[k] = pc;
+    }
+  }
+}
+
+struct ArcOut {
+  uint32_t *t, *h, *w, *m;
+};
+
+// Moves the live arcs of each selected vertex into the CH (out-arcs to the
+// upward set, in-arcs to the downward set) at scanned positions, emits the
+// shortcut candidates (v1, v2, w1 + w2, label(u), u) and marks V_S and the
+// next round's affected set.
+template <int G>
+__global__ void __launch_bounds__(256) k_contract(
+    Overlay ov, const uint32_t *__restrict__ vf, uint32_t nf, const int32_t *__restrict__ P,
+    const uint32_t *__restrict__ label, const MemoSlot *__restrict__ memo, uint64_t mmask,
+    uint32_t round, uint32_t *__restrict__ level, int32_t *__restrict__ score,
+    uint8_t *__restrict__ alive_g, const uint32_t *__restrict__ pup,
+    const uint32_t *__restrict__ pdn, const uint32_t *__restrict__ ppair, ArcOut up, ArcOut dn,
+    uint64_t up_base, uint64_t dn_base, const uint32_t *__restrict__ cpair, int kb,
+    uint64_t *__restrict__ ekey, uint32_t *__restrict__ ew,
+    uint32_t *__restrict__ elab, uint32_t *__restrict__ emid, uint8_t *__restrict__ S,
+    uint8_t *__restrict__ newA, uint32_t *__restrict__ err) {
+  const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+  const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+  const int gl = glane<G>();
+  const uint64_t below = (gl == 0) ? 0ull : ((1ull << gl) - 1ull);
+  uint32_t probes = 0;
+  for (uint32_t k = g0; k < nf; k += ngroups) {
+    const uint32_t u = vf[k];
+    const uint32_t gu = ov.gid[u];
+    const uint32_t lab = label[gu];
+    if (gl == 0) {
+      level[gu] = round;
+      score[gu] = P[u];
+      alive_g[gu] = 0;
+    }
+    // out-arcs -> upward set
+    uint64_t pos = up_base + pup[k];
+    const uint32_t o0 = ov.foff[u], o1 = ov.foff[u + 1];
+    for (uint32_t b0 = o0; b0 < o1; b0 += G) {
+      const uint32_t e = b0 + gl;
+      uint2 b = make_uint2(0, SP_INF32);
+      if (e < o1) b = ov.farc[e];
+      const bool live = e < o1 && b.y != SP_INF32;
+      const uint64_t msk = gballot<G>(live);
+      if (live) {
+        const uint64_t at = pos + __popcll(msk & below);
+        up.t[at] = gu;
+        up.h[at] = ov.gid[b.x];
+        up.w[at] = b.y;
+        up.m[at] = ov.fmid[e];
+        newA[b.x] = 1;
+      }
+      pos += __popcll(msk);
+    }
+    // in-arcs -> downward set
+    pos = dn_base + pdn[k];
+    const uint32_t i0 = ov.roff[u], i1 = ov.roff[u + 1];
+    for (uint32_t b0 = i0; b0 < i1; b0 += G) {
+      const uint32_t e = b0 + gl;
+      uint2 a = make_uint2(0, SP_INF32);
+      if (e < i1) a = ov.rarc[e];
+      const bool live = e < i1 && a.y != SP_INF32;
+      const uint64_t msk = gballot<G>(live);
+      if (live) {
+        const uint64_t at = pos + __popcll(msk & below);
+        dn.t[at] = ov.gid[a.x];
+        dn.h[at] = gu;
+        dn.w[at] = a.y;
+        dn.m[at] = ov.rmid[e];
+        newA[a.x] = 1;
+      }
+      pos += __popcll(msk);
+    }
+    // shortcut candidates, in pair order
+    pos = ppair[k];
+    const uint64_t pend = pos + cpair[k];
+    const uint32_t din = i1 - i0, dout = o1 - o0;
+    const uint64_t np = (uint64_t)din * dout;
+    for (uint64_t p0 = 0; p0 < np; p0 += G) {
+      const uint64_t p = p0 + gl;
+      bool emit = false;
+      uint2 a = make_uint2(0, 0), b = make_uint2(0, 0);
+      uint64_t via = 0;
+      if (p < np) {
+        const uint32_t i = (uint32_t)(p / dout), j = (uint32_t)(p - (uint64_t)i * dout);
+        a = ov.rarc[i0 + i];
+        b = ov.farc[o0 + j];
+        if (a.y != SP_INF32 && b.y != SP_INF32 && a.x != b.x) {
+          via = (uint64_t)a.y + b.y;
+          const uint32_t d = memo_get(memo, mmask, ov.gid[a.x], ov.gid[b.x], &probes);
+          emit = d == SP_INF32 || via <= d;
+        }
+      }
+      const uint64_t msk = gballot<G>(emit);
+      if (emit) {
+        if (via > SP_MAXW) atomicOr(err, kErrOverflow);
+        const uint64_t at = pos + __popcll(msk & below);
+        if (at >= pend) {
+          atomicOr(err, kErrCapacity);
+          continue;
+        }
+        ekey[at] = ((uint64_t)a.x << kb) | b.x;
+        ew[at] = (uint32_t)via;
+        elab[at] = lab;
+        emid[at] = gu;
+        S[a.x] = 1;
+      }
+      pos += __popcll(msk);
+    }
+  }
+}
+
+// After sorting the candidates by (v1, v2): one record per distinct pair
+// with the smallest (weight, label of the middle vertex).
+__global__ void k_eplus_reduce(const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
+                               uint32_t ne, const uint32_t *__restrict__ heads,
+                               const uint32_t *nheads, const uint32_t *__restrict__ ew,
+                               const uint32_t *__restrict__ elab, const uint32_t *__restrict__ emid,
+                               uint64_t *__restrict__ ukey, uint32_t *__restrict__ uw,
+                               uint32_t *__restrict__ umid) {
+  const uint32_t nh = *nheads;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nh; k += stride) {
+    const uint32_t i = heads[k];
+    const uint64_t kk = key[i];
+    uint32_t bi = idx[i];
+    uint32_t bw = ew[bi], bl = elab[bi];
+    for (uint32_t j = i + 1; j < ne && key[j] == kk; j++) {
+      const uint32_t c = idx[j];
+      if (ew[c] < bw || (ew[c] == bw && elab[c] < bl)) {
+        bi = c;
+        bw = ew[c];
+        bl = elab[c];
+      }
+    }
+    ukey[k] = kk;
+    uw[k] = bw;
+    umid[k] = emid[bi];
+  }
+}
+
+// ===========================================================================
+// overlay rebuild
+// ===========================================================================
+__global__ void k_keep(uint32_t n, const uint8_t *__restrict__ F, uint32_t *__restrict__ keep) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) keep[u] = !F[u];
+}
+
+// Row of vertex u in direction dir merged with its shortcut row.  Old row:
+// live arcs to kept vertices.  Shortcut row: records with first key half u
+// (sorted by the second half).  On a common neighbour the shortcut wins only
+// if strictly lighter.  Mode 0 counts, mode 1 writes.
+template <int MODE>
+__global__ void k_merge_rows(uint32_t n, int kb, const uint8_t *__restrict__ F,
+                             const uint32_t *__restrict__ newid, const uint32_t *__restrict__ off,
+                             const uint2 *__restrict__ arc, const uint32_t *__restrict__ mid,
+                             const uint64_t *__restrict__ ekey, const uint32_t *__restrict__ eidx,
+                             uint32_t ne, const uint32_t *__restrict__ uw,
+                             const uint32_t *__restrict__ umid, uint32_t *__restrict__ cnt,
+                             const uint32_t *__restrict__ noff, uint2 *__restrict__ narc,
+                             uint32_t *__restrict__ nmid) {
+  const uint64_t lowmask = (1ull << kb) - 1ull;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    if (F[u]) continue;
+    // shortcut row: keys in [u << kb, (u + 1) << kb)
+    const uint64_t lo_key = (uint64_t)u << kb, hi_key = lo_key | lowmask;
+    uint32_t lo = 0, hi = ne;
+    while (lo < hi) {
+      const uint32_t md = (lo + hi) >> 1;
+      if (ekey[md] < lo_key) lo = md + 1;
+      else hi = md;
+    }
+    uint32_t b = lo, b1;
+    {
+      uint32_t l2 = lo, h2 = ne;
+      while (l2 < h2) {
+        const uint32_t md = (l2 + h2) >> 1;
+        if (ekey[md] <= hi_key) l2 = md + 1;
+        else h2 = md;
+      }
+      b1 = l2;
+    }
+    uint32_t a = off[u];
+    const uint32_t a1 = off[u + 1];
+    uint32_t c = 0;
+    uint32_t outp = MODE ? noff[newid[u]] : 0;
+    for (;;) {
+      while (a < a1 && (arc[a].y == SP_INF32 || F[arc[a].x])) a++;  // dead old arcs
+      const bool ha = a < a1, hb = b < b1;
+      if (!ha && !hb) break;
+      const uint32_t va = ha ? arc[a].x : 0xFFFFFFFFu;
+      const uint32_t vb = hb ? (uint32_t)(ekey[b] & lowmask) : 0xFFFFFFFFu;
+      uint32_t v, ww, mm;
+      if (ha && (!hb || va < vb)) {
+        v = va;
+        ww = arc[a].y;
+        mm = mid[a];
+        a++;
+      } else if (!ha || vb < va) {
+        const uint32_t r = eidx ? eidx[b] : b;
+        v = vb;
+        ww = uw[r];
+        mm = umid[r];
+        b++;
+      } else {  // same neighbour: the shortcut replaces the arc only if lighter
+        const uint32_t r = eidx ? eidx[b] : b;
+        if (uw[r] < arc[a].y) {
+          ww = uw[r];
+          mm = umid[r];
+        } else {
+          ww = arc[a].y;
+          mm = mid[a];
+        }
+        v = va;
+        a++;
+        b++;
+      }
+      if (MODE) {
+        narc[outp] = make_uint2(newid[v], ww);
+        nmid[outp] = mm;
+        outp++;
+      }
+      c++;
+    }
+    if (!MODE) cnt[newid[u]] = c;
+  }
+}
+
+// Carries per-vertex state to the new local ids and marks V_S in W'.
+__global__ void k_carry(uint32_t n, const uint8_t *__restrict__ F, const uint32_t *__restrict__ newid,
+                        const uint32_t *__restrict__ gid, const int32_t *__restrict__ P,
+                        const uint8_t *__restrict__ S, const uint8_t *__restrict__ newA,
+                        uint32_t *__restrict__ ngid, int32_t *__restrict__ nP,
+                        uint8_t *__restrict__ nW, uint8_t *__restrict__ nA) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    if (F[u]) continue;
+    const uint32_t nu = newid[u];
+    ngid[nu] = gid[u];
+    nP[nu] = P[u];
+    nA[nu] = newA[u];
+    if (S[u]) nW[nu] = 1;
+  }
+}
+
+// V_W' = V_S union N_in(V_S) on the combined overlay.
+__global__ void k_mark_in_neighbours(uint32_t n, const uint8_t *__restrict__ F,
+                                     const uint8_t *__restrict__ S,
+                                     const uint32_t *__restrict__ newid,
+                                     const uint32_t *__restrict__ nroff,
+                                     const uint2 *__restrict__ nrarc, uint8_t *__restrict__ nW) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+    if (F[u] || !S[u]) continue;
+    const uint32_t nu = newid[u];
+    for (uint32_t e = nroff[nu]; e < nroff[nu + 1]; e++) nW[nrarc[e].x] = 1;
+  }
+}
+
+// Memo rehash into a larger table, dropping entries with a contracted
+// endpoint (they are never looked up again).
+__global__ void k_memo_rehash(const MemoSlot *__restrict__ old, uint64_t ocap,
+                              const uint8_t *__restrict__ alive_g, MemoSlot *__restrict__ nt,
+                              uint64_t nmask, unsigned long long *__restrict__ kept) {
+  uint64_t c = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ocap; i += stride) {
+    const uint64_t k = old[i].key;
+    if (k == SP_EMPTY64) continue;
+    const uint32_t s = (uint32_t)(k >> 32), v = (uint32_t)k;
+    if (!alive_g[s] || !alive_g[v]) continue;
+    memo_put(nt, nmask, s, v, old[i].val);
+    c++;
+  }
+  c = gsum64<kWave>(c);
+  if (lane_id() == 0 && c) atomicAdd(kept, (unsigned long long)c);
+}
+
+}  // namespace sp

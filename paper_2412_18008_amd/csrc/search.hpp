@@ -1,0 +1,297 @@
+// search.hpp -- the witness-path search of one source by one group of G
+// lanes (Alg. 3, "Step 1: Local Search with Memoization").
+//
+// For a source s in V_W the group
+//   1. gathers the target set V_n: every out-neighbour v != s of every
+//      affected out-neighbour u of s (u in V_A) whose pair (s, v) is not in
+//      the memo, and the radius D_s = the largest w(s,u) + w(u,v) over the
+//      gathered pairs;
+//   2. computes the exact overlay distance from s to every vertex within
+//      radius D_s by label-correcting relaxation (frontier lists and a
+//      vertex -> distance hash in a per-group table);
+//   3. writes dist(s, v) into the memo for every target.
+// Every target's distance is at most its own two-arc length, so radius D_s
+// returns exact values, and those values do not depend on the relaxation
+// order.  The table lives in LDS (fast path) or in global memory (the
+// fallback for searches that outgrow LDS); `GL` selects the accessors.
+#pragma once
+
+#include "common.hpp"
+
+namespace sp {
+
+struct Overlay {
+  uint32_t n;
+  uint32_t m;
+  const uint32_t *foff;  // n+1
+  uint2 *farc;           // m: {head, weight}; weight SP_INF32 marks a pruned arc
+  uint32_t *fmid;        // m: middle vertex (original id) or SP_NOMID
+  const uint32_t *roff;  // n+1
+  uint2 *rarc;           // m: {tail, weight}
+  uint32_t *rmid;        // m
+  const uint32_t *gid;   // n: original id of each local vertex
+};
+
+enum : uint32_t { kFlagTarget = 1u, kFlagFront = 2u };
+enum : int { kCtrUsed = 0, kCtrF0 = 1, kCtrF1 = 2, kCtrOvf = 3 };
+
+template <typename IdxT, bool GL>
+struct Tab {
+  uint32_t *key;   // vertex (local id) or SP_EMPTY32
+  uint32_t *dist;  // tentative distance; during target collection 0xFFFFFFFF - max via
+  uint32_t *flag;  // kFlag*
+  IdxT *order;     // slots in insertion order
+  IdxT *fr0, *fr1; // frontier slot lists
+  uint32_t *ctr;   // used, |fr0|, |fr1|, overflow
+  uint32_t cap;    // power of two
+  uint32_t shift;  // 32 - log2(cap)
+  uint32_t limit;  // overflow when more slots than this are used
+
+  __device__ __forceinline__ uint32_t ld(const uint32_t *p) const {
+    if constexpr (GL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  }
+  __device__ __forceinline__ void st(uint32_t *p, uint32_t v) const {
+    if constexpr (GL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+  }
+  __device__ __forceinline__ IdxT ldi(const IdxT *p) const {
+    if constexpr (GL) return (IdxT)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  }
+  __device__ __forceinline__ void sti(IdxT *p, IdxT v) const {
+    if constexpr (GL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+  }
+  __device__ __forceinline__ void sync() const {
+    if constexpr (GL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+    wave_sync();
+  }
+
+  // Find or insert vertex v; returns its slot or -1 when the table is full.
+  __device__ __forceinline__ int insert(uint32_t v) const {
+    uint32_t h = (v * 0x9E3779B1u) >> shift;
+    for (uint32_t probes = 0; probes < cap; probes++) {
+      uint32_t k = ld(&key[h]);
+      if (k == v) return (int)h;
+      if (k == SP_EMPTY32) {
+        uint32_t prev = atomicCAS(&key[h], SP_EMPTY32, v);
+        if (prev == SP_EMPTY32) {
+          uint32_t idx = atomicAdd(&ctr[kCtrUsed], 1u);
+          if (idx < limit) sti(&order[idx], (IdxT)h);
+          else atomicOr(&ctr[kCtrOvf], 1u);
+          return (int)h;
+        }
+        if (prev == v) return (int)h;
+      }
+      h = (h + 1) & (cap - 1);
+    }
+    atomicOr(&ctr[kCtrOvf], 1u);
+    return -1;
+  }
+};
+
+struct SearchStats {
+  uint32_t rows = 0, arcs = 0, probes = 0, inserts = 0, targets = 0, searched = 0;
+};
+
+// Clears the slots listed in `order` (and the counters) after a search.
+template <int G, typename IdxT, bool GL>
+__device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
+  const int gl = glane<G>();
+  T.sync();
+  uint32_t used = T.ld(&T.ctr[kCtrUsed]);
+  if (used > T.limit) used = T.limit;
+  for (uint32_t i = gl; i < used; i += G) {
+    IdxT s = T.ldi(&T.order[i]);
+    T.st(&T.key[s], SP_EMPTY32);
+    T.st(&T.dist[s], SP_INF32);
+    T.st(&T.flag[s], 0u);
+  }
+  T.sync();
+  if (used >= T.limit) {  // an overflowing insert may have left unlisted keys
+    for (uint32_t i = gl; i < T.cap; i += G) {
+      T.st(&T.key[i], SP_EMPTY32);
+      T.st(&T.dist[i], SP_INF32);
+      T.st(&T.flag[i], 0u);
+    }
+  }
+  if (gl < 4) T.st(&T.ctr[gl], 0u);
+  T.sync();
+}
+
+// One source.  Returns false when the table overflowed (nothing written).
+template <int G, typename IdxT, bool GL>
+__device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ aflag,
+                              MemoSlot *__restrict__ memo, uint64_t mmask,
+                              const Tab<IdxT, GL> &T, uint32_t s, SearchStats &ss,
+                              uint32_t *__restrict__ err) {
+  const int gl = glane<G>();
+  const uint32_t gs = ov.gid[s];
+
+  // ---- 1. targets and radius ------------------------------------------
+  const uint32_t a0 = ov.foff[s], a1 = ov.foff[s + 1];
+  for (uint32_t base = a0; base < a1; base += G) {
+    const uint32_t e = base + gl;
+    uint32_t rs = 0, rl = 0, wsu = 0;
+    if (e < a1) {
+      const uint2 a = ov.farc[e];
+      if (aflag[a.x]) {
+        rs = ov.foff[a.x];
+        rl = ov.foff[a.x + 1] - rs;
+        wsu = a.y;
+        ss.rows++;
+      }
+    }
+    const uint32_t incl = gscan_incl<G>(rl);
+    const uint32_t total = gshfl<G>(incl, G - 1);
+    for (uint32_t i0 = 0; i0 < total; i0 += G) {
+      const uint32_t idx = i0 + gl;
+      const int src = gfind<G>(incl, idx);
+      const uint32_t srs = gshfl<G>(rs, src), sinc = gshfl<G>(incl, src);
+      const uint32_t srl = gshfl<G>(rl, src), sw = gshfl<G>(wsu, src);
+      if (idx < total) {
+        const uint2 b = ov.farc[srs + (idx - (sinc - srl))];
+        ss.arcs++;
+        if (b.x != s) {
+          const uint64_t via = (uint64_t)sw + b.y;
+          const uint32_t viac = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
+          const int slot = T.insert(b.x);
+          if (slot >= 0) atomicMin(&T.dist[slot], 0xFFFFFFFFu - viac);
+        }
+      }
+      T.sync();
+      if (T.ld(&T.ctr[kCtrOvf])) break;
+    }
+    if (T.ld(&T.ctr[kCtrOvf])) break;
+  }
+  T.sync();
+  if (T.ld(&T.ctr[kCtrOvf])) {
+    tab_reset<G>(T);
+    return false;
+  }
+  uint32_t D = 0, nt = 0;
+  {
+    const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
+    for (uint32_t i = gl; i < used; i += G) {
+      const IdxT slot = T.ldi(&T.order[i]);
+      const uint32_t v = T.ld(&T.key[slot]);
+      const uint32_t got = memo_get(memo, mmask, gs, ov.gid[v], &ss.probes);
+      if (got == SP_INF32) {
+        T.st(&T.flag[slot], kFlagTarget);
+        D = max(D, 0xFFFFFFFFu - T.ld(&T.dist[slot]));
+        nt++;
+      }
+      T.st(&T.dist[slot], SP_INF32);
+    }
+  }
+  D = gmax<G>(D);
+  nt = gsum<G>(nt);
+  if (nt == 0) {
+    tab_reset<G>(T);
+    return true;
+  }
+  if (D > SP_MAXW) {
+    if (gl == 0) atomicOr(err, kErrOverflow);
+    tab_reset<G>(T);
+    return true;
+  }
+  ss.targets += (gl == 0) ? nt : 0;
+  ss.searched += (gl == 0) ? 1 : 0;
+
+  // ---- 2. bounded label-correcting search from s ----------------------
+  T.sync();
+  if (gl == 0) {
+    const int slot = T.insert(s);
+    if (slot >= 0) {
+      T.st(&T.dist[slot], 0u);
+      T.st(&T.flag[slot], kFlagFront);
+      T.sti(&T.fr0[0], (IdxT)slot);
+      T.st(&T.ctr[kCtrF0], 1u);
+    }
+  }
+  T.sync();
+  int cur = 0;
+  while (!T.ld(&T.ctr[kCtrOvf])) {
+    IdxT *fc = cur ? T.fr1 : T.fr0;
+    IdxT *fn = cur ? T.fr0 : T.fr1;
+    uint32_t *nc = &T.ctr[cur ? kCtrF1 : kCtrF0];
+    uint32_t *nn = &T.ctr[cur ? kCtrF0 : kCtrF1];
+    const uint32_t ncur = T.ld(nc);
+    if (ncur == 0) break;
+    T.sync();
+    if (gl == 0) T.st(nn, 0u);
+    T.sync();
+    for (uint32_t fb = 0; fb < ncur; fb += G) {
+      const uint32_t i = fb + gl;
+      uint32_t rs = 0, rl = 0, dx = 0;
+      if (i < ncur) {
+        const IdxT x = T.ldi(&fc[i]);
+        atomicAnd(&T.flag[x], ~kFlagFront);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        dx = T.ld(&T.dist[x]);
+        const uint32_t vx = T.ld(&T.key[x]);
+        rs = ov.foff[vx];
+        rl = ov.foff[vx + 1] - rs;
+        ss.rows++;
+      }
+      const uint32_t incl = gscan_incl<G>(rl);
+      const uint32_t total = gshfl<G>(incl, G - 1);
+      for (uint32_t i0 = 0; i0 < total; i0 += G) {
+        const uint32_t idx = i0 + gl;
+        const int src = gfind<G>(incl, idx);
+        const uint32_t srs = gshfl<G>(rs, src), sinc = gshfl<G>(incl, src);
+        const uint32_t srl = gshfl<G>(rl, src), sdx = gshfl<G>(dx, src);
+        if (idx < total) {
+          const uint2 b = ov.farc[srs + (idx - (sinc - srl))];
+          ss.arcs++;
+          const uint64_t nd = (uint64_t)sdx + b.y;
+          if (nd <= D) {
+            const int y = T.insert(b.x);
+            if (y >= 0) {
+              const uint32_t old = atomicMin(&T.dist[y], (uint32_t)nd);
+              if ((uint32_t)nd < old) {
+                const uint32_t f = atomicOr(&T.flag[y], kFlagFront);
+                if (!(f & kFlagFront)) {
+                  const uint32_t p = atomicAdd(nn, 1u);
+                  if (p < T.cap) T.sti(&fn[p], (IdxT)y);
+                }
+              }
+            }
+          }
+        }
+        T.sync();
+        if (T.ld(&T.ctr[kCtrOvf])) break;
+      }
+      if (T.ld(&T.ctr[kCtrOvf])) break;
+    }
+    T.sync();
+    cur ^= 1;
+  }
+  T.sync();
+  if (T.ld(&T.ctr[kCtrOvf])) {
+    tab_reset<G>(T);
+    return false;
+  }
+
+  // ---- 3. memoize the targets' distances ------------------------------
+  {
+    const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
+    for (uint32_t i = gl; i < used; i += G) {
+      const IdxT slot = T.ldi(&T.order[i]);
+      if (T.ld(&T.flag[slot]) & kFlagTarget) {
+        const uint32_t d = T.ld(&T.dist[slot]);
+        if (d <= D) {
+          memo_put(memo, mmask, gs, ov.gid[T.ld(&T.key[slot])], d);
+          ss.inserts++;
+        } else {
+          atomicOr(err, kErrCapacity);  // cannot happen: every target is within D
+        }
+      }
+    }
+  }
+  tab_reset<G>(T);
+  return true;
+}
+
+}  // namespace sp

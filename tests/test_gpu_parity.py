@@ -1,0 +1,179 @@
+"""GPU parity: the HIP library, called through its C ABI, must reproduce the
+oracle bit for bit -- level, score at contraction, rank, every upward and
+downward CH arc with weight and middle vertex, and the per-round counts --
+and its query distances must equal Dijkstra's.  Integer work, so the bar is
+exact equality everywhere."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_18008_amd import synth
+from parity_util import (assert_export_order, assert_same_ch, gpu_export, gpu_round_counts,
+                         oracle_export, oracle_round_counts, reference_distances)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_18008_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def _case(name, off, dst, w, labels, gpu, group=0, seed=0):
+    print(f"[parity] {name} n={len(off) - 1} m={len(dst)} group={group}", flush=True)
+    o = oracle.OracleCH(off, dst, w, labels=labels, seed=seed).run()
+    ch = gpu.build(off, dst, w, labels=labels, seed=seed, stats=True, group=group)
+    a, b = oracle_export(o), gpu_export(ch)
+    assert_same_ch(a, b, name)
+    assert_export_order(b)
+    assert ch.summary["rounds"] == o.rounds
+    assert gpu_round_counts(ch) == oracle_round_counts(o), name
+    return o, ch
+
+
+def small_cases():
+    cases = []
+    for s in range(8):
+        cases.append((f"digraph{s}", *synth.random_digraph(40, 160, seed=s, wmax=9,
+                                                            zero_frac=0.15, loops=True)))
+    for s in range(4):
+        cases.append((f"road{s}", *synth.random_geometric_small(300, seed=s)))
+    cases.append(("grid7x9", *synth.grid(7, 9, seed=3)))
+    cases.append(("unitgrid6", *synth.grid(6, 6, seed=0, wmin=1, wmax=1)))
+    cases.append(("chain", *synth.chain(257, seed=1, directed=True)))
+    cases.append(("bichain", *synth.chain(300, seed=2, directed=False)))
+    cases.append(("star", *synth.star(70, seed=3)))
+    cases.append(("sparse", *synth.random_digraph(200, 60, seed=9, wmax=5)))
+    cases.append(("dense", *synth.random_digraph(60, 1500, seed=4, wmax=3)))
+    return cases
+
+
+def test_small_graphs_bit_exact(gpu):
+    for name, off, dst, w in small_cases():
+        n = len(off) - 1
+        _case(name, off, dst, w, synth.labels(n, 17), gpu)
+
+
+def test_grid64_bit_exact_and_queries(gpu):
+    off, dst, w = synth.config_grid64(seed=0)
+    n = len(off) - 1
+    lab = synth.labels(n, 1)
+    o, ch = _case("grid64", off, dst, w, lab, gpu)
+    s, t = synth.queries(n, 1000, seed=1)
+    d = ch.query(s, t)
+    ref = reference_distances(off, dst, w, s, t)
+    assert np.array_equal(d, ref)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(d, od)
+
+
+def test_group_split_invariance(gpu):
+    off, dst, w = synth.grid(20, 25, seed=5)
+    n = len(off) - 1
+    lab = synth.labels(n, 2)
+    ref = gpu_export(gpu.build(off, dst, w, labels=lab))
+    for g in (4, 8, 16, 32, 64):
+        assert_same_ch(ref, gpu_export(gpu.build(off, dst, w, labels=lab, group=g)), f"G={g}")
+
+
+def test_default_labels_match_oracle(gpu):
+    off, dst, w = synth.random_geometric_small(500, seed=7)
+    for seed in (0, 12345, 0xDEADBEEF12345678):
+        _case(f"default-labels seed={seed}", off, dst, w, None, gpu, seed=seed)
+
+
+def test_device_input_and_device_queries(gpu):
+    import torch
+
+    off, dst, w = synth.road_like(5000, seed=3)
+    n = len(off) - 1
+    lab = synth.labels(n, 4)
+    dev = torch.device("cuda:0")
+    t_off = torch.from_numpy(off.astype(np.int64)).to(dev)
+    t_dst = torch.from_numpy(dst.astype(np.int32)).to(dev)
+    t_w = torch.from_numpy(w.astype(np.int32)).to(dev)
+    t_lab = torch.from_numpy(lab.astype(np.int32)).to(dev)
+    ch = gpu.build(t_off, t_dst, t_w, labels=t_lab)
+    o = oracle.OracleCH(off, dst, w, labels=lab).run()
+    assert_same_ch(oracle_export(o), gpu_export(ch), "device-input")
+    s, t = synth.queries(n, 2000, seed=5)
+    ds = ch.query(torch.from_numpy(s.astype(np.int32)).to(dev),
+                  torch.from_numpy(t.astype(np.int32)).to(dev))
+    torch.cuda.synchronize()
+    got = ds.cpu().numpy().view(np.uint64)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(got, od)
+
+
+def test_queries_unreachable_and_self(gpu):
+    off, dst, w = synth.random_digraph(300, 250, seed=11, wmax=7)
+    n = len(off) - 1
+    ch = gpu.build(off, dst, w, labels=synth.labels(n, 3))
+    s = np.repeat(np.arange(0, n, 7, dtype=np.uint32), 5)
+    t = np.tile(np.arange(0, 5 * 7, 7, dtype=np.uint32), len(s) // 5)
+    s = np.concatenate([s, np.arange(20, dtype=np.uint32)])
+    t = np.concatenate([t, np.arange(20, dtype=np.uint32)])
+    d = ch.query(s, t)
+    assert np.array_equal(d, reference_distances(off, dst, w, s, t))
+    assert np.all(d[-20:] == 0)
+    assert np.any(d == np.uint64(0xFFFFFFFFFFFFFFFF))
+
+
+def test_empty_and_isolated(gpu):
+    ch = gpu.build(np.zeros(1, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert ch.summary["rounds"] == 0
+    off = np.zeros(9, np.uint64)
+    ch = gpu.build(off, np.zeros(0, np.uint32), np.zeros(0, np.uint32),
+                   labels=synth.labels(8, 0))
+    assert ch.summary["rounds"] == 1
+    d = ch.query(np.array([0, 3], np.uint32), np.array([0, 5], np.uint32))
+    assert d[0] == 0 and d[1] == np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def test_errors(gpu):
+    off, dst, w = synth.to_csr(3, [0, 1], [1, 2], [1, 2])
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(off, np.array([1, 3], np.uint32), w)
+    assert e.value.code == gpu.CH_E_INVALID
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(off, dst, np.array([1, 0xFFFFFFFF], np.uint32))
+    assert e.value.code == gpu.CH_E_INVALID
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(off, dst, w, labels=np.array([1, 1, 2], np.uint32))
+    assert e.value.code == gpu.CH_E_INVALID
+    bad_off = np.array([0, 2, 1, 2], np.uint64)
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(bad_off, dst, w)
+    assert e.value.code == gpu.CH_E_INVALID
+    off2, dst2, w2 = synth.to_csr(3, [0, 1], [1, 2], [0xFFFFFFFE, 1])
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(off2, dst2, w2, labels=np.array([5, 0, 9], np.uint32))
+    assert e.value.code == gpu.CH_E_OVERFLOW
+    off3, dst3, w3 = synth.chain(50, seed=1, directed=False)
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(off3, dst3, w3, max_rounds=2)
+    assert e.value.code == gpu.CH_E_LIMIT
+    ch = gpu.build(off, dst, w)
+    with pytest.raises(gpu.ChError) as e:
+        ch.query(np.array([0], np.uint32), np.array([3], np.uint32))
+    assert e.value.code == gpu.CH_E_INVALID
+
+
+def test_road_100k_bit_exact(gpu):
+    off, dst, w = synth.road_like(100_000, seed=0)
+    n = len(off) - 1
+    lab = synth.labels(n, 7)
+    o, ch = _case("road100k", off, dst, w, lab, gpu)
+    s, t = synth.queries(n, 20_000, seed=3)
+    d = ch.query(s, t)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(d, od)
+    ref = reference_distances(off, dst, w, s[:20], t[:20])
+    assert np.array_equal(d[:20], ref)
