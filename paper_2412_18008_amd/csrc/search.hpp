@@ -196,8 +196,6 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     tab_reset<G>(T);
     return true;
   }
-  ss.targets += (gl == 0) ? nt : 0;
-  ss.searched += (gl == 0) ? 1 : 0;
 
   // ---- 2. bounded label-correcting search from s ----------------------
   T.sync();
@@ -275,6 +273,8 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
   }
 
   // ---- 3. memoize the targets' distances ------------------------------
+  ss.targets += (gl == 0) ? nt : 0;  // counted once, by the attempt that completes
+  ss.searched += (gl == 0) ? 1 : 0;
   {
     const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
     for (uint32_t i = gl; i < used; i += G) {
