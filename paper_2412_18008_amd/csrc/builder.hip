@@ -293,7 +293,8 @@ struct Builder {
     if (mcap) {
       HIP_TRY(hipMemsetAsync(&dc()->kept, 0, 8, st));
       k_memo_rehash<<<grid(mcap), 256, 0, st>>>(memo.as<MemoSlot>(), mcap, alive_g.as<uint8_t>(),
-                                                 nm.as<MemoSlot>(), ncap - 1, &dc()->kept);
+                                                 nm.as<MemoSlot>(), ncap / kMemoBucket - 1,
+                                                 &dc()->kept);
       HIP_TRY(hipGetLastError());
       TRY(readback());
       kept = hctr->kept;
@@ -305,11 +306,23 @@ struct Builder {
     return CH_OK;
   }
 
+  template <int G, int CAP>
+  void launch_ls(const Overlay &v, const uint32_t *list, uint32_t nl, uint32_t *ovf_out,
+                 int blocks_per_cu) {
+    k_local_search<G, CAP><<<(unsigned)cus * blocks_per_cu, kLsBlock, 0, st>>>(
+        v, list, nl, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1, &dc()->ls,
+        ovf_out, &dc()->err);
+  }
   template <int G>
   void launch_score(const Overlay &v, uint32_t na) {
     k_score<G><<<ggrid<G>(na), 256, 0, st>>>(v, va.as<uint32_t>(), na, memo.as<MemoSlot>(),
-                                              mcap - 1, ov[cur].P.as<int32_t>(),
+                                              mcap / kMemoBucket - 1, ov[cur].P.as<int32_t>(),
                                               paircnt.as<uint32_t>());
+  }
+  template <int G>
+  void launch_prune(const Overlay &v, uint32_t nw) {
+    k_prune<G><<<ggrid<G>(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, memo.as<MemoSlot>(),
+                                              mcap / kMemoBucket - 1, &dc()->pruned, &dc()->err);
   }
   template <int G>
   void launch_select(const Overlay &v) {
@@ -319,7 +332,7 @@ struct Builder {
   void launch_ccount(const Overlay &v, uint32_t nf) {
     k_contract_count<G><<<ggrid<G>(nf), 256, 0, st>>>(
         v, vf.as<uint32_t>(), nf, aflag.as<uint8_t>(), paircnt.as<uint32_t>(),
-        memo.as<MemoSlot>(), mcap - 1, cup.as<uint32_t>(), cdn.as<uint32_t>(),
+        memo.as<MemoSlot>(), mcap / kMemoBucket - 1, cup.as<uint32_t>(), cdn.as<uint32_t>(),
         cpair.as<uint32_t>());
   }
   template <int G>
@@ -330,7 +343,7 @@ struct Builder {
               ch->dn_m.as<uint32_t>()};
     k_contract<G><<<ggrid<G>(nf), 256, 0, st>>>(
         v, vf.as<uint32_t>(), nf, ov[cur].P.as<int32_t>(), ch->label.as<uint32_t>(),
-        memo.as<MemoSlot>(), mcap - 1, round, ch->level.as<uint32_t>(), ch->score.as<int32_t>(),
+        memo.as<MemoSlot>(), mcap / kMemoBucket - 1, round, ch->level.as<uint32_t>(), ch->score.as<int32_t>(),
         alive_g.as<uint8_t>(), cup.as<uint32_t>() + nf, cdn.as<uint32_t>() + nf,
         cpair.as<uint32_t>() + nf, up, dn, ch->nup, ch->ndown, cpair.as<uint32_t>(), kb,
         ekey.as<uint64_t>(), ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(),
@@ -420,55 +433,59 @@ struct Builder {
         HIP_TRY(hipGetLastError());
         TRY(readback());
         TRY(ensure_memo(hctr->bound));
+        // tier 1: LDS tables sized for the overlay's degree; overflowing
+        // sources go to a larger LDS tier, then to global-memory tables
+        const bool small = avgdeg <= 5.0;
         if (stats) HIP_TRY(hipEventRecord(ev[2], st));
-        k_local_search<16, 128><<<(unsigned)cus * 16, kLsBlock, 0, st>>>(
-            v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap - 1,
-            &dc()->ls, ovf1.as<uint32_t>(), &dc()->err);
+        if (small) launch_ls<16, 128>(v, vw.as<uint32_t>(), nw, ovf1.as<uint32_t>(), 16);
+        else launch_ls<64, 2048>(v, vw.as<uint32_t>(), nw, ovf1.as<uint32_t>(), 4);
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
         TRY(readback());
-        // counters of the LDS fast-path kernel alone (the measured kernel)
+        // counters of the first-tier kernel alone (the measured kernel)
         rs.rows_expanded = hctr->ls.rows;
         rs.arcs_scanned = hctr->ls.arcs;
         rs.memo_probes = hctr->ls.probes;
         rs.memo_inserts = hctr->ls.inserts;
         uint32_t novf = hctr->ls.ovf_count;
-        if (novf) {
+        const uint32_t *olist = ovf1.as<uint32_t>();
+        if (novf && small) {
           HIP_TRY(hipMemsetAsync(&dc()->ls.work, 0, 8, st));
-          k_local_search<64, 2048><<<(unsigned)cus * 4, kLsBlock, 0, st>>>(
-              v, ovf1.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap - 1,
-              &dc()->ls, ovf2.as<uint32_t>(), &dc()->err);
+          launch_ls<64, 2048>(v, ovf1.as<uint32_t>(), novf, ovf2.as<uint32_t>(), 4);
           HIP_TRY(hipGetLastError());
           TRY(readback());
-          const uint32_t novf2 = hctr->ls.ovf_count;
-          if (novf2) {
-            const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
-            const size_t per = ((size_t)cap * 6 + 4) * 4;
-            size_t ntab = std::max<size_t>(1, std::min<size_t>(
-                                                  {(size_t)novf2, (size_t)cus * 2,
-                                                   (size_t)(4ull << 30) / per}));
-            HIP_TRY(gtabs.ensure(ntab * per));
-            // key, dist = all ones; flag, order, fronts, counters = 0
-            for (size_t t = 0; t < ntab; t++) {
-              uint32_t *b = gtabs.as<uint32_t>() + t * (per / 4);
-              HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));
-              HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, ((size_t)cap * 4 + 4) * 4, st));
-            }
-            k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
-                v, ovf2.as<uint32_t>(), novf2, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
-                mcap - 1, &dc()->ls, gtabs.as<uint32_t>(), cap, &dc()->err);
-            HIP_TRY(hipGetLastError());
+          rs.n_ls_fallback += novf;
+          novf = hctr->ls.ovf_count;
+          olist = ovf2.as<uint32_t>();
+        }
+        if (novf) {
+          rs.n_ls_fallback += novf;
+          const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
+          const size_t per = ((size_t)cap * 6 + 4) * 4;
+          size_t ntab = std::max<size_t>(1, std::min<size_t>({(size_t)novf, (size_t)cus * 2,
+                                                              (size_t)(4ull << 30) / per}));
+          HIP_TRY(gtabs.ensure(ntab * per));
+          // key, dist = all ones; flag, order, fronts, counters = 0
+          for (size_t t = 0; t < ntab; t++) {
+            uint32_t *b = gtabs.as<uint32_t>() + t * (per / 4);
+            HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));
+            HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, ((size_t)cap * 4 + 4) * 4, st));
           }
+          k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
+              v, olist, novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1,
+              &dc()->ls, gtabs.as<uint32_t>(), cap, &dc()->err);
+          HIP_TRY(hipGetLastError());
         }
         TRY(readback());
         TRY(check_err());
         mcount += hctr->ls.inserts;
         rs.n_targets = hctr->ls.targets;
-        rs.n_ls_fallback = novf;
 
         // pruning at the end of Alg. 3
-        k_prune<<<grid(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, memo.as<MemoSlot>(), mcap - 1,
-                                          &dc()->pruned, &dc()->err);
+        const int Gp = prm.group ? (int)prm.group : pick_group(avgdeg);
+        dispatch(Gp, [&] { launch_prune<4>(v, nw); }, [&] { launch_prune<8>(v, nw); },
+                 [&] { launch_prune<16>(v, nw); }, [&] { launch_prune<32>(v, nw); },
+                 [&] { launch_prune<64>(v, nw); });
         HIP_TRY(hipGetLastError());
       }
 

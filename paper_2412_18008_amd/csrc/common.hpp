@@ -132,10 +132,12 @@ __host__ __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
 }
 
 // ---------------------------------------------------------------------------
-// Memo: open addressing over 16-byte slots {key = (s << 32) | v, value}.
-// The probe sequence of a pair starts inside a 16-slot bucket chosen by the
-// source s, so the ~10-30 entries of one source share one or two 128-byte
-// lines, and continues linearly (wrapping) through the table.
+// Memo: open addressing over 16-byte slots {key = (s << 32) | v, value},
+// grouped in buckets of 16 slots (256 bytes).  The probe sequence of a pair
+// visits bucket 0 = the bucket of its source s, then buckets chosen by the
+// pair; inside a bucket it starts at a pair-dependent slot and wraps.  So
+// the entries of one source share one bucket until it fills, and no probe
+// sequence walks a long cluster.  `bmask` = number of buckets - 1.
 // ---------------------------------------------------------------------------
 struct MemoSlot {
   uint64_t key;
@@ -143,43 +145,57 @@ struct MemoSlot {
   uint32_t pad;
 };
 
-__device__ __forceinline__ uint64_t memo_start(uint32_t s, uint32_t v, uint64_t mask) {
-  uint64_t b = ((uint64_t)lowbias32(s) << 4) | (lowbias32(v ^ 0x9e3779b9u) & 15u);
-  return b & mask;
+constexpr uint32_t kMemoBucket = 16;
+
+// splitmix64 finaliser (Steele, Lea and Flood).
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t memo_bucket(uint64_t k, uint32_t s, uint32_t i, uint64_t bmask) {
+  return (i == 0 ? mix64(s) : mix64(k ^ (0x9E3779B97F4A7C15ull * i))) & bmask;
 }
 
 // Returns the stored value or SP_INF32 when the pair is absent.
-__device__ __forceinline__ uint32_t memo_get(const MemoSlot *__restrict__ t, uint64_t mask,
+__device__ __forceinline__ uint32_t memo_get(const MemoSlot *__restrict__ t, uint64_t bmask,
                                              uint32_t s, uint32_t v, uint32_t *probes) {
   const uint64_t k = ((uint64_t)s << 32) | v;
-  uint64_t i = memo_start(s, v, mask);
-  for (;;) {
-    (*probes)++;
-    const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(&t[i]);
-    if (e.x == k) return (uint32_t)e.y;
-    if (e.x == SP_EMPTY64) return SP_INF32;
-    i = (i + 1) & mask;
+  const uint32_t o = lowbias32(v ^ 0x9e3779b9u) & (kMemoBucket - 1);
+  for (uint32_t i = 0;; i++) {
+    const MemoSlot *b = t + memo_bucket(k, s, i, bmask) * kMemoBucket;
+    for (uint32_t j = 0; j < kMemoBucket; j++) {
+      (*probes)++;
+      const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(&b[(o + j) & (kMemoBucket - 1)]);
+      if (e.x == k) return (uint32_t)e.y;
+      if (e.x == SP_EMPTY64) return SP_INF32;
+    }
   }
 }
 
-// Insert (s, v) -> val if the pair is absent (first writer wins).
-__device__ __forceinline__ void memo_put(MemoSlot *__restrict__ t, uint64_t mask, uint32_t s,
+// Insert (s, v) -> val if the pair is absent (first writer wins).  The
+// table is kept at most half full, so an empty slot is always reached.
+__device__ __forceinline__ void memo_put(MemoSlot *__restrict__ t, uint64_t bmask, uint32_t s,
                                          uint32_t v, uint32_t val) {
   const uint64_t k = ((uint64_t)s << 32) | v;
-  uint64_t i = memo_start(s, v, mask);
-  for (;;) {
-    uint64_t cur = __hip_atomic_load(&t[i].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (cur == k) return;
-    if (cur == SP_EMPTY64) {
-      uint64_t prev = atomicCAS((unsigned long long *)&t[i].key, (unsigned long long)SP_EMPTY64,
-                                (unsigned long long)k);
-      if (prev == SP_EMPTY64) {
-        t[i].val = val;
-        return;
+  const uint32_t o = lowbias32(v ^ 0x9e3779b9u) & (kMemoBucket - 1);
+  for (uint32_t i = 0;; i++) {
+    MemoSlot *b = t + memo_bucket(k, s, i, bmask) * kMemoBucket;
+    for (uint32_t j = 0; j < kMemoBucket; j++) {
+      MemoSlot *slot = &b[(o + j) & (kMemoBucket - 1)];
+      uint64_t cur = __hip_atomic_load(&slot->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (cur == k) return;
+      if (cur == SP_EMPTY64) {
+        uint64_t prev = atomicCAS((unsigned long long *)&slot->key,
+                                  (unsigned long long)SP_EMPTY64, (unsigned long long)k);
+        if (prev == SP_EMPTY64) {
+          slot->val = val;
+          return;
+        }
+        if (prev == k) return;
       }
-      if (prev == k) return;
     }
-    i = (i + 1) & mask;
   }
 }
 

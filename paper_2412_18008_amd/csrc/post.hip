@@ -223,10 +223,13 @@ int postprocess(ch_s *ch, bool make_index) {
 // ===========================================================================
 enum : uint32_t { kQFront = 1u };
 
-template <typename IdxT, bool GL>
+// Vertex -> distance table of one search direction.  DistT is uint32_t in
+// LDS (a sum above 0xFFFFFFFE marks the query for the 64-bit path) or
+// unsigned long long in the global-memory fallback.
+template <typename IdxT, typename DistT, bool GL>
 struct QTab {
   uint32_t *key;
-  unsigned long long *dist;
+  DistT *dist;
   uint32_t *flag;
   IdxT *order, *fr0, *fr1;
   uint32_t *ctr;  // used, |fr0|, |fr1|, overflow
@@ -240,11 +243,11 @@ struct QTab {
     if constexpr (GL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
   }
-  __device__ __forceinline__ unsigned long long ld64(const unsigned long long *p) const {
+  __device__ __forceinline__ DistT ldd(const DistT *p) const {
     if constexpr (GL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else return *p;
   }
-  __device__ __forceinline__ void st64(unsigned long long *p, unsigned long long v) const {
+  __device__ __forceinline__ void std_(DistT *p, DistT v) const {
     if constexpr (GL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
   }
@@ -292,8 +295,8 @@ struct QTab {
   }
 };
 
-template <typename IdxT, bool GL>
-__device__ void qtab_reset(const QTab<IdxT, GL> &T) {
+template <typename IdxT, typename DistT, bool GL>
+__device__ void qtab_reset(const QTab<IdxT, DistT, GL> &T) {
   const int l = lane_id();
   T.sync();
   uint32_t used = T.ld(&T.ctr[0]);
@@ -301,14 +304,14 @@ __device__ void qtab_reset(const QTab<IdxT, GL> &T) {
   for (uint32_t i = l; i < used; i += kWave) {
     IdxT s = T.ldi(&T.order[i]);
     T.st(&T.key[s], SP_EMPTY32);
-    T.st64(&T.dist[s], SP_INF64);
+    T.std_(&T.dist[s], (DistT)~(DistT)0);
     T.st(&T.flag[s], 0u);
   }
   T.sync();
   if (used >= T.limit) {
     for (uint32_t i = l; i < T.cap; i += kWave) {
       T.st(&T.key[i], SP_EMPTY32);
-      T.st64(&T.dist[i], SP_INF64);
+      T.std_(&T.dist[i], (DistT)~(DistT)0);
       T.st(&T.flag[i], 0u);
     }
   }
@@ -316,16 +319,18 @@ __device__ void qtab_reset(const QTab<IdxT, GL> &T) {
   T.sync();
 }
 
-// Upward closure from `src` over (off, arc).  Returns false on overflow.
-template <typename IdxT, bool GL>
-__device__ bool closure(const QTab<IdxT, GL> &T, const uint32_t *__restrict__ off,
+// Upward closure from `src` over (off, arc).  Returns false on overflow of
+// the table or of the distance type.
+template <typename IdxT, typename DistT, bool GL>
+__device__ bool closure(const QTab<IdxT, DistT, GL> &T, const uint32_t *__restrict__ off,
                         const uint2 *__restrict__ arc, uint32_t src) {
   const int l = lane_id();
+  constexpr unsigned long long kMax = sizeof(DistT) == 4 ? 0xFFFFFFFEull : 0xFFFFFFFFFFFFFFFEull;
   T.sync();
   if (l == 0) {
     const int s = T.insert(src);
     if (s >= 0) {
-      T.st64(&T.dist[s], 0ull);
+      T.std_(&T.dist[s], (DistT)0);
       T.st(&T.flag[s], kQFront);
       T.sti(&T.fr0[0], (IdxT)s);
       T.st(&T.ctr[1], 1u);
@@ -351,7 +356,7 @@ __device__ bool closure(const QTab<IdxT, GL> &T, const uint32_t *__restrict__ of
         const IdxT x = T.ldi(&fc[i]);
         atomicAnd(&T.flag[x], ~kQFront);
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        dx = T.ld64(&T.dist[x]);
+        dx = T.ldd(&T.dist[x]);
         const uint32_t vx = T.ld(&T.key[x]);
         rs = off[vx];
         rl = off[vx + 1] - rs;
@@ -367,14 +372,18 @@ __device__ bool closure(const QTab<IdxT, GL> &T, const uint32_t *__restrict__ of
         if (idx < total) {
           const uint2 b = arc[srs + (idx - (sinc - srl))];
           const unsigned long long nd = sdx + b.y;
-          const int y = T.insert(b.x);
-          if (y >= 0) {
-            const unsigned long long old = atomicMin(&T.dist[y], nd);
-            if (nd < old) {
-              const uint32_t f = atomicOr(&T.flag[y], kQFront);
-              if (!(f & kQFront)) {
-                const uint32_t p = atomicAdd(nn, 1u);
-                if (p < T.cap) T.sti(&fn[p], (IdxT)y);
+          if (nd > kMax) {
+            atomicOr(&T.ctr[3], 1u);
+          } else {
+            const int y = T.insert(b.x);
+            if (y >= 0) {
+              const DistT old = atomicMin(&T.dist[y], (DistT)nd);
+              if ((DistT)nd < old) {
+                const uint32_t f = atomicOr(&T.flag[y], kQFront);
+                if (!(f & kQFront)) {
+                  const uint32_t p = atomicAdd(nn, 1u);
+                  if (p < T.cap) T.sti(&fn[p], (IdxT)y);
+                }
               }
             }
           }
@@ -391,8 +400,8 @@ __device__ bool closure(const QTab<IdxT, GL> &T, const uint32_t *__restrict__ of
   return !T.ld(&T.ctr[3]);
 }
 
-template <typename IdxT, bool GL>
-__device__ unsigned long long meet(const QTab<IdxT, GL> &Fw, const QTab<IdxT, GL> &Bw) {
+template <typename IdxT, typename DistT, bool GL>
+__device__ unsigned long long meet(const QTab<IdxT, DistT, GL> &Fw, const QTab<IdxT, DistT, GL> &Bw) {
   const int l = lane_id();
   unsigned long long best = SP_INF64;
   const uint32_t used = Fw.ld(&Fw.ctr[0]);
@@ -400,14 +409,15 @@ __device__ unsigned long long meet(const QTab<IdxT, GL> &Fw, const QTab<IdxT, GL
     const IdxT s = Fw.ldi(&Fw.order[i]);
     const int b = Bw.find(Fw.ld(&Fw.key[s]));
     if (b >= 0) {
-      const unsigned long long c = Fw.ld64(&Fw.dist[s]) + Bw.ld64(&Bw.dist[b]);
+      const unsigned long long c =
+          (unsigned long long)Fw.ldd(&Fw.dist[s]) + (unsigned long long)Bw.ldd(&Bw.dist[b]);
       best = c < best ? c : best;
     }
   }
   return gmin64<kWave>(best);
 }
 
-constexpr int kQCap = 1024;
+constexpr int kQCap = 2048;
 
 __global__ void __launch_bounds__(64) k_query(
     uint64_t q, const uint32_t *__restrict__ qs, const uint32_t *__restrict__ qt,
@@ -416,7 +426,7 @@ __global__ void __launch_bounds__(64) k_query(
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
     uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count) {
   __shared__ uint32_t s_key[2][kQCap];
-  __shared__ unsigned long long s_dist[2][kQCap];
+  __shared__ uint32_t s_dist[2][kQCap];
   __shared__ uint32_t s_flag[2][kQCap];
   __shared__ uint16_t s_order[2][kQCap];
   __shared__ uint16_t s_fr[2][2][kQCap];
@@ -425,13 +435,13 @@ __global__ void __launch_bounds__(64) k_query(
   for (int d = 0; d < 2; d++) {
     for (int i = l; i < kQCap; i += kWave) {
       s_key[d][i] = SP_EMPTY32;
-      s_dist[d][i] = SP_INF64;
+      s_dist[d][i] = SP_INF32;
       s_flag[d][i] = 0;
     }
     if (l < 4) s_ctr[d][l] = 0;
   }
   wave_sync();
-  QTab<uint16_t, false> T[2];
+  QTab<uint16_t, uint32_t, false> T[2];
   for (int d = 0; d < 2; d++) {
     T[d].key = s_key[d];
     T[d].dist = s_dist[d];
@@ -442,7 +452,7 @@ __global__ void __launch_bounds__(64) k_query(
     T[d].ctr = s_ctr[d];
     T[d].cap = kQCap;
     T[d].shift = 32 - __builtin_ctz(kQCap);
-    T[d].limit = (kQCap * 3) / 4;
+    T[d].limit = (kQCap * 7) / 8;
   }
   for (uint64_t k = blockIdx.x; k < q; k += gridDim.x) {
     const uint32_t rs = rank[qs[k]], rt = rank[qt[k]];
@@ -460,8 +470,9 @@ __global__ void __launch_bounds__(64) k_query(
   }
 }
 
-// Fallback for queries whose closures outgrow LDS: tables in global memory
-// with cap >= 2n slots each (never overflow).
+// Fallback for queries whose closures outgrow LDS or 32-bit distances:
+// tables in global memory with cap >= 2n slots each (never overflow) and
+// 64-bit distances.
 __global__ void __launch_bounds__(64) k_query_global(
     uint32_t nlist, const uint32_t *__restrict__ list, const uint32_t *__restrict__ qs,
     const uint32_t *__restrict__ qt, const uint32_t *__restrict__ rank,
@@ -472,7 +483,7 @@ __global__ void __launch_bounds__(64) k_query_global(
   // fr1 [cap] and 4 counters = 8 cap + 4 words
   const size_t per = (size_t)cap * 8 + 4;
   uint32_t *base = tabs + (size_t)blockIdx.x * 2 * per;
-  QTab<uint32_t, true> T[2];
+  QTab<uint32_t, unsigned long long, true> T[2];
   for (int d = 0; d < 2; d++) {
     uint32_t *b = base + d * per;
     T[d].key = b;

@@ -244,19 +244,26 @@ __global__ void __launch_bounds__(64) k_local_search_global(
 
 // Pruning (end of Alg. 3): an out-arc (s, v) of a source s whose weight
 // exceeds the memoized dist(s, v) is deleted (weight set to SP_INF32 in both
-// the forward row of s and the reverse row of v).
-__global__ void k_prune(Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw,
-                        const MemoSlot *__restrict__ memo, uint64_t mmask,
-                        unsigned long long *__restrict__ npruned, uint32_t *__restrict__ err) {
+// the forward row of s and the reverse row of v).  A group of G lanes per
+// source, lanes over its out-arcs.
+template <int G>
+__global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__restrict__ vw,
+                                               uint32_t nw, const MemoSlot *__restrict__ memo,
+                                               uint64_t bmask,
+                                               unsigned long long *__restrict__ npruned,
+                                               uint32_t *__restrict__ err) {
+  const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+  const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+  const int gl = glane<G>();
   uint32_t probes = 0;
   uint64_t c = 0;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) {
-    const uint32_t s = vw[i];
+  for (uint32_t k = g0; k < nw; k += ngroups) {
+    const uint32_t s = vw[k];
     const uint32_t gs = ov.gid[s];
-    for (uint32_t e = ov.foff[s]; e < ov.foff[s + 1]; e++) {
+    const uint32_t e1 = ov.foff[s + 1];
+    for (uint32_t e = ov.foff[s] + gl; e < e1; e += G) {
       const uint2 a = ov.farc[e];
-      const uint32_t d = memo_get(memo, mmask, gs, ov.gid[a.x], &probes);
+      const uint32_t d = memo_get(memo, bmask, gs, ov.gid[a.x], &probes);
       if (d != SP_INF32 && a.y > d) {
         ov.farc[e].y = SP_INF32;
         const uint32_t end = ov.roff[a.x + 1];
