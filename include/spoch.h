@@ -101,13 +101,15 @@ typedef struct {
   uint64_t n_pruned;        /* arcs deleted by the pruning rule                */
   uint64_t n_shortcuts;     /* distinct (v1, v2) shortcut pairs                */
   uint64_t overlay_arcs;    /* arcs in the overlay after the round             */
-  /* the next four count the fast-path witness-search kernel only */
+  /* the next four count the first-tier witness-search kernel only */
   uint64_t rows_expanded;   /* adjacency rows read by the witness searches     */
   uint64_t arcs_scanned;    /* arcs read by the witness searches               */
   uint64_t memo_probes;     /* memo slots read by the local search             */
   uint64_t memo_inserts;    /* memo entries written                            */
-  uint32_t n_ls_fallback;   /* sources whose search outgrew the fast-path table */
-  float ms_local_search;    /* device time of the fast-path witness-search kernel */
+  uint32_t n_ls_fallback;   /* sources whose search outgrew the first-tier table */
+  uint32_t ls_tier1;        /* first-tier search kernel: 0 = 16 lanes x 128 slots, */
+                            /* 1 = 64 lanes x 2048 slots                           */
+  float ms_local_search;    /* device time of the first-tier witness-search kernel */
   float ms_total;           /* device time of the whole round (host gaps included) */
 } ch_round_stats_t;
 

@@ -57,7 +57,7 @@ class RoundStats(C.Structure):
         ("n_shortcuts", C.c_uint64), ("overlay_arcs", C.c_uint64),
         ("rows_expanded", C.c_uint64), ("arcs_scanned", C.c_uint64),
         ("memo_probes", C.c_uint64), ("memo_inserts", C.c_uint64),
-        ("n_ls_fallback", C.c_uint32), ("ms_local_search", C.c_float),
+        ("n_ls_fallback", C.c_uint32), ("ls_tier1", C.c_uint32), ("ms_local_search", C.c_float),
         ("ms_total", C.c_float),
     ]
 

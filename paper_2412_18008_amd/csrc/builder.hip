@@ -53,8 +53,9 @@ static uint64_t next_pow2(uint64_t x) {
 
 // Device-side counters read back by the host (one struct, one copy).
 struct DevCtr {
-  LsCounters ls;
+  LsCounters ls, ls2;  // first search tier; later tiers
   unsigned long long bound, pruned, kept;
+  uint32_t work1, work2, novf1, novf2;  // persistent scheduling and overflow counts
   uint32_t err, bad;
   uint32_t c32[8];  // scan totals and list counts
 };
@@ -306,12 +307,19 @@ struct Builder {
     return CH_OK;
   }
 
+  // Persistent launch: blocks_per_cu one-wave blocks per CU; a group takes
+  // 4 sources per scheduling step while sources are plentiful, else 1.
   template <int G, int CAP>
-  void launch_ls(const Overlay &v, const uint32_t *list, uint32_t nl, uint32_t *ovf_out,
-                 int blocks_per_cu) {
+  void launch_ls(const Overlay &v, const uint32_t *list, uint32_t nl, const uint32_t *nl_dev,
+                 int tier, int blocks_per_cu) {
+    const uint32_t groups = (uint32_t)cus * blocks_per_cu * (kLsBlock / G);
+    const uint32_t chunk = (!nl_dev && nl >= 16u * groups) ? 4u : 1u;
+    DevCtr *d = dc();
     k_local_search<G, CAP><<<(unsigned)cus * blocks_per_cu, kLsBlock, 0, st>>>(
-        v, list, nl, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1, &dc()->ls,
-        ovf_out, &dc()->err);
+        v, list, nl, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1,
+        tier == 1 ? &d->ls : &d->ls2, nl_dev, tier == 1 ? &d->work1 : &d->work2,
+        tier == 1 ? ovf1.as<uint32_t>() : ovf2.as<uint32_t>(), tier == 1 ? &d->novf1 : &d->novf2,
+        chunk, &d->err);
   }
   template <int G>
   void launch_score(const Overlay &v, uint32_t na) {
@@ -412,6 +420,15 @@ struct Builder {
     ch->nup = ch->ndown = 0;
     TRY(ensure_memo(std::max<uint64_t>(ch->m_input, 1) * 4));
 
+    uint64_t next_bound = 0;
+    if (n) {
+      HIP_TRY(hipMemsetAsync(&dc()->bound, 0, 8, st));
+      k_ls_bound_flags<<<grid(n), 256, 0, st>>>(view(ov[cur]), aflag.as<uint8_t>(),
+                                                 aflag.as<uint8_t>(), &dc()->bound);
+      HIP_TRY(hipGetLastError());
+      TRY(readback());
+      next_bound = hctr->bound;
+    }
     uint32_t round = 0;
     while (ov[cur].n > 0) {
       if (prm.max_rounds && round >= prm.max_rounds)
@@ -426,40 +443,33 @@ struct Builder {
       const double avgdeg = O.n ? (double)O.m / O.n : 0.0;
 
       // ---- Step 1: LocalSearch (Alg. 3) --------------------------------
+      // memo capacity for this round's inserts (bound computed with the
+      // previous round's final readback)
+      TRY(ensure_memo(next_bound));
       HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
       if (nw) {
-        k_ls_bound<<<grid(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(),
-                                             &dc()->bound);
-        HIP_TRY(hipGetLastError());
-        TRY(readback());
-        TRY(ensure_memo(hctr->bound));
-        // tier 1: LDS tables sized for the overlay's degree; overflowing
-        // sources go to a larger LDS tier, then to global-memory tables
+        // tier 1: LDS tables sized for the overlay's degree (16 lanes x 128
+        // slots on sparse overlays, 64 lanes x 2048 slots on dense ones);
+        // sources whose search outgrows them go to a 4096-slot LDS tier
+        // (launched with its count on the device, so no host round trip),
+        // then to tables in global memory
         const bool small = avgdeg <= 5.0;
+        rs.ls_tier1 = small ? 0 : 1;
         if (stats) HIP_TRY(hipEventRecord(ev[2], st));
-        if (small) launch_ls<16, 128>(v, vw.as<uint32_t>(), nw, ovf1.as<uint32_t>(), 16);
-        else launch_ls<64, 2048>(v, vw.as<uint32_t>(), nw, ovf1.as<uint32_t>(), 4);
+        if (small) launch_ls<16, 128>(v, vw.as<uint32_t>(), nw, nullptr, 1, 16);
+        else launch_ls<64, 2048>(v, vw.as<uint32_t>(), nw, nullptr, 1, 4);
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
+        launch_ls<64, 4096>(v, ovf1.as<uint32_t>(), 0, &dc()->novf1, 2, 2);
+        HIP_TRY(hipGetLastError());
         TRY(readback());
-        // counters of the first-tier kernel alone (the measured kernel)
         rs.rows_expanded = hctr->ls.rows;
         rs.arcs_scanned = hctr->ls.arcs;
         rs.memo_probes = hctr->ls.probes;
         rs.memo_inserts = hctr->ls.inserts;
-        uint32_t novf = hctr->ls.ovf_count;
-        const uint32_t *olist = ovf1.as<uint32_t>();
-        if (novf && small) {
-          HIP_TRY(hipMemsetAsync(&dc()->ls.work, 0, 8, st));
-          launch_ls<64, 2048>(v, ovf1.as<uint32_t>(), novf, ovf2.as<uint32_t>(), 4);
-          HIP_TRY(hipGetLastError());
-          TRY(readback());
-          rs.n_ls_fallback += novf;
-          novf = hctr->ls.ovf_count;
-          olist = ovf2.as<uint32_t>();
-        }
+        rs.n_ls_fallback = hctr->novf1;
+        const uint32_t novf = hctr->novf2;
         if (novf) {
-          rs.n_ls_fallback += novf;
           const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
           const size_t per = ((size_t)cap * 6 + 4) * 4;
           size_t ntab = std::max<size_t>(1, std::min<size_t>({(size_t)novf, (size_t)cus * 2,
@@ -472,14 +482,14 @@ struct Builder {
             HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, ((size_t)cap * 4 + 4) * 4, st));
           }
           k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
-              v, olist, novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1,
-              &dc()->ls, gtabs.as<uint32_t>(), cap, &dc()->err);
+              v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
+              mcap / kMemoBucket - 1, &dc()->ls2, gtabs.as<uint32_t>(), cap, &dc()->err);
           HIP_TRY(hipGetLastError());
         }
         TRY(readback());
         TRY(check_err());
-        mcount += hctr->ls.inserts;
-        rs.n_targets = hctr->ls.targets;
+        mcount += hctr->ls.inserts + hctr->ls2.inserts;
+        rs.n_targets = hctr->ls.targets + hctr->ls2.targets;
 
         // pruning at the end of Alg. 3
         const int Gp = prm.group ? (int)prm.group : pick_group(avgdeg);
@@ -665,9 +675,16 @@ struct Builder {
       HIP_TRY(select_flags(wflag.as<uint8_t>(), n2, vw.as<uint32_t>(), &dc()->c32[C_UP], tmp, st));
       HIP_TRY(select_flags(aflag_next.as<uint8_t>(), n2, va.as<uint32_t>(), &dc()->c32[C_DN],
                            tmp, st));
+      // upper bound on the next round's memo inserts: over every source s
+      // and affected out-neighbour u, the out-degree of u
+      HIP_TRY(hipMemsetAsync(&dc()->bound, 0, 8, st));
+      k_ls_bound_flags<<<grid(n2), 256, 0, st>>>(view(N), wflag.as<uint8_t>(),
+                                                  aflag_next.as<uint8_t>(), &dc()->bound);
+      HIP_TRY(hipGetLastError());
       TRY(readback());
       nw = hctr->c32[C_UP];
       na = hctr->c32[C_DN];
+      next_bound = hctr->bound;
       std::swap(aflag, aflag_next);
       cur ^= 1;
       rs.overlay_arcs = m2;

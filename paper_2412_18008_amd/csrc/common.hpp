@@ -158,18 +158,26 @@ __device__ __forceinline__ uint64_t memo_bucket(uint64_t k, uint32_t s, uint32_t
   return (i == 0 ? mix64(s) : mix64(k ^ (0x9E3779B97F4A7C15ull * i))) & bmask;
 }
 
-// Returns the stored value or SP_INF32 when the pair is absent.
+// Returns the stored value or SP_INF32 when the pair is absent.  Slots are
+// read four at a time (independent loads inside one bucket), then checked
+// in probe order.
 __device__ __forceinline__ uint32_t memo_get(const MemoSlot *__restrict__ t, uint64_t bmask,
                                              uint32_t s, uint32_t v, uint32_t *probes) {
   const uint64_t k = ((uint64_t)s << 32) | v;
   const uint32_t o = lowbias32(v ^ 0x9e3779b9u) & (kMemoBucket - 1);
   for (uint32_t i = 0;; i++) {
     const MemoSlot *b = t + memo_bucket(k, s, i, bmask) * kMemoBucket;
-    for (uint32_t j = 0; j < kMemoBucket; j++) {
-      (*probes)++;
-      const ulonglong2 e = *reinterpret_cast<const ulonglong2 *>(&b[(o + j) & (kMemoBucket - 1)]);
-      if (e.x == k) return (uint32_t)e.y;
-      if (e.x == SP_EMPTY64) return SP_INF32;
+    for (uint32_t j = 0; j < kMemoBucket; j += 4) {
+      ulonglong2 e[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++)
+        e[q] = *reinterpret_cast<const ulonglong2 *>(&b[(o + j + q) & (kMemoBucket - 1)]);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        (*probes)++;
+        if (e[q].x == k) return (uint32_t)e[q].y;
+        if (e[q].x == SP_EMPTY64) return SP_INF32;
+      }
     }
   }
 }

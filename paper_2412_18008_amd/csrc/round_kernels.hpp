@@ -135,11 +135,26 @@ __global__ void k_ls_bound(Overlay ov, const uint32_t *__restrict__ vw, uint32_t
   if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
 }
 
+// Same bound with the sources given as a flag array (thread per vertex).
+__global__ void k_ls_bound_flags(Overlay ov, const uint8_t *__restrict__ wflag,
+                                 const uint8_t *__restrict__ aflag,
+                                 unsigned long long *__restrict__ out) {
+  uint64_t acc = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < ov.n; s += stride) {
+    if (!wflag[s]) continue;
+    for (uint32_t e = ov.foff[s]; e < ov.foff[s + 1]; e++) {
+      const uint32_t u = ov.farc[e].x;
+      if (aflag[u]) acc += ov.foff[u + 1] - ov.foff[u];
+    }
+  }
+  acc = gsum64<kWave>(acc);
+  if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
+}
+
 // Counters of the local search (device, accumulated per launch).
 struct LsCounters {
   unsigned long long rows, arcs, probes, inserts, targets, searched;
-  uint32_t work;      // next source index (persistent scheduling)
-  uint32_t ovf_count; // sources deferred to the global-memory fallback
 };
 
 template <int G>
@@ -158,16 +173,19 @@ __device__ __forceinline__ void flush_stats(const SearchStats &ss, LsCounters *c
 }
 
 constexpr int kLsBlock = 64;  // one wave per workgroup
-constexpr uint32_t kLsChunk = 4;  // sources taken per scheduling step
 
 // LDS fast path: groups of G lanes, CAP-slot table per group.  Persistent:
-// every group takes kLsChunk sources at a time from a global counter.
+// every group takes `chunk` sources at a time from a global counter.
 template <int G, int CAP>
 __global__ void __launch_bounds__(kLsBlock) k_local_search(
     Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
     MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
-    uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ err) {
+    const uint32_t *__restrict__ nw_dev, uint32_t *__restrict__ work,
+    uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count, uint32_t chunk,
+    uint32_t *__restrict__ err) {
   constexpr int NG = kLsBlock / G;
+  if (nw_dev) nw = *nw_dev;  // source count produced by an earlier kernel
+  if (nw == 0) return;
   __shared__ uint32_t s_key[NG][CAP];
   __shared__ uint32_t s_dist[NG][CAP];
   __shared__ uint32_t s_flag[NG][CAP];
@@ -196,15 +214,15 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
   SearchStats ss;
   for (;;) {
     uint32_t base = 0;
-    if (gl == 0) base = atomicAdd(&cnt->work, kLsChunk);
+    if (gl == 0) base = atomicAdd(work, chunk);
     base = gshfl<G>(base, 0);
     if (base >= nw) break;
-    const uint32_t end = min(base + kLsChunk, nw);
+    const uint32_t end = min(base + chunk, nw);
     for (uint32_t i = base; i < end; i++) {
       const uint32_t s = vw[i];
       if (!search_source<G>(ov, aflag, memo, mmask, T, s, ss, err)) {
         if (gl == 0) {
-          const uint32_t k = atomicAdd(&cnt->ovf_count, 1u);
+          const uint32_t k = atomicAdd(ovf_count, 1u);
           ovf_list[k] = s;
         }
       }
