@@ -137,6 +137,23 @@ typedef struct {
  * CH_E_DEVICE, CH_E_LIMIT, CH_E_UNSUPPORTED. */
 int ch_build(const ch_graph_t *g, const ch_params_t *p, ch_t **out);
 
+/* Build the CHs of k independent graphs in one pass of the round loop (the
+ * graphs become one disjoint union; every rule is local to a graph and
+ * every tie uses that graph's own labels).  outs[i] is exactly the CH that
+ * ch_build gives gs[i] alone; its summary has that graph's rounds, arcs and
+ * shortcuts (memo_entries 0, ms_build of the whole batch); per-round stats
+ * are not kept.
+ *   gs:   k graphs (host arrays, or device arrays with CH_F_INPUT_ON_DEVICE);
+ *         either every graph has labels or none has (then each graph gets
+ *         the default labels of its local ids); labels need only be
+ *         distinct within a graph
+ *   p:    parameters as for ch_build (NULL = defaults)
+ *   outs: k entries receive library-owned CHs (each released with ch_free);
+ *         they run on p->stream (NULL: the default stream)
+ * Errors: as ch_build; also CH_E_UNSUPPORTED when the union has more than
+ * 0xFFFFFFFE vertices or 2^32 - 1 arcs.  On error no CH is returned. */
+int ch_build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **outs);
+
 /* Distances of q s-t pairs on the CH (Sec. "Query on Contraction
  * Hierarchies"): dist[i] = min over v of d_up(s_i, v) + d_down(v, t_i),
  * which equals the shortest s_i -> t_i distance in the input graph;

@@ -30,7 +30,7 @@ CH_F_STATS = 0x2
 CH_F_NO_QUERY_INDEX = 0x4
 CH_Q_ON_DEVICE = 0x1
 
-EXPORTED = ("ch_build", "ch_query_batch", "ch_export", "ch_get_summary",
+EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
             "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version")
 
 
@@ -81,6 +81,8 @@ def lib():
         vp, u32, u64, i32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int
         L.ch_build.argtypes = [C.POINTER(Graph), C.POINTER(Params), C.POINTER(vp)]
         L.ch_build.restype = i32
+        L.ch_build_batch.argtypes = [C.POINTER(Graph), u32, C.POINTER(Params), C.POINTER(vp)]
+        L.ch_build_batch.restype = i32
         L.ch_query_batch.argtypes = [vp, vp, vp, u64, vp, u32, vp]
         L.ch_query_batch.restype = i32
         L.ch_export.argtypes = [vp] + [vp] * 11
@@ -199,6 +201,30 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
+
+
+def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=True,
+                stream=None):
+    """ch_build_batch on a list of (off, dst, w) CSR graphs (numpy arrays or
+    torch CUDA tensors); returns one CH per graph."""
+    k = len(graphs)
+    keep = []
+    arr = (Graph * max(k, 1))()
+    dev = k > 0 and _is_torch_cuda(graphs[0][0])
+    for i, (off, dst, w) in enumerate(graphs):
+        po, ko = _ptr(off, np.uint64)
+        pd, kd = _ptr(dst, np.uint32)
+        pw, kw = _ptr(w, np.uint32)
+        pl, kl = _ptr(None if labels is None else labels[i], np.uint32)
+        keep += [ko, kd, kw, kl]
+        n = (off.numel() if dev else len(ko)) - 1
+        m = dst.numel() if dev else len(kd)
+        arr[i] = Graph(n, m, po, pd, pw, pl)
+    flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX)
+    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream)
+    outs = (C.c_void_p * max(k, 1))()
+    _check(lib().ch_build_batch(arr, k, C.byref(p), outs), "ch_build_batch")
+    return [CH(C.c_void_p(outs[i])) for i in range(k)]
 
 
 def version():

@@ -90,6 +90,15 @@ struct Builder {
   DevCtr *hctr = nullptr;  // pinned
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   uint64_t up_cap = 0, dn_cap = 0;
+  // disjoint-union batch: graph of each original vertex, per-graph
+  // shortcut counters (device), vertex bases (device, k+1)
+  struct Batch {
+    uint32_t k = 0;
+    const uint32_t *gof = nullptr;
+    unsigned long long *shortcuts = nullptr;  // per graph
+    unsigned long long *m_in = nullptr;       // per graph, arcs after ingest
+  };
+  const Batch *batch = nullptr;
 
   ~Builder() {
     OvBuf *o = ov;
@@ -231,7 +240,8 @@ struct Builder {
     HIP_TRY(iota_u32(O.gid.as<uint32_t>(), n, st));
     HIP_TRY(hipMemsetAsync(O.P.p, 0, (size_t)n * 4, st));
 
-    // labels
+    // labels (a batch build prepares and validates them per graph)
+    if (batch) return CH_OK;
     HIP_TRY(ch->label.ensure(std::max<uint64_t>(n, 1) * 4));
     if (g->labels) {
       HIP_TRY(hipMemcpyAsync(ch->label.p, g->labels, (size_t)n * 4,
@@ -286,7 +296,7 @@ struct Builder {
   int ensure_memo(uint64_t extra) {
     const uint64_t need = mcount + extra;
     if (need * 2 <= mcap) return CH_OK;
-    uint64_t ncap = next_pow2(std::max<uint64_t>(need * 3, 1024));
+    uint64_t ncap = next_pow2(std::max<uint64_t>(need * 2, 1024));
     DBuf nm;
     HIP_TRY(nm.ensure(ncap * sizeof(MemoSlot)));
     HIP_TRY(fill_u64(nm.as<uint64_t>(), SP_EMPTY64, ncap * 2, st));
@@ -385,6 +395,11 @@ struct Builder {
     const bool stats = prm.flags & CH_F_STATS;
 
     TRY(ingest(g));
+    if (batch && n) {
+      k_rowlen_by_graph<<<grid(n), 256, 0, st>>>(n, ov[cur].foff.as<uint32_t>(), batch->gof,
+                                                 batch->m_in);
+      HIP_TRY(hipGetLastError());
+    }
 
     HIP_TRY(ch->level.ensure(std::max<uint64_t>(n, 1) * 4));
     HIP_TRY(ch->score.ensure(std::max<uint64_t>(n, 1) * 4));
@@ -418,7 +433,6 @@ struct Builder {
                   &ch->dn_m};
     for (DBuf *b : ub) HIP_TRY(b->ensure(up_cap * 4));
     ch->nup = ch->ndown = 0;
-    TRY(ensure_memo(std::max<uint64_t>(ch->m_input, 1) * 4));
 
     uint64_t next_bound = 0;
     if (n) {
@@ -597,6 +611,12 @@ struct Builder {
         TRY(readback());
         TRY(check_err());
         U = hctr->c32[C_HEADS];
+        if (batch && U) {
+          k_count_by_graph<<<grid(U), 256, 0, st>>>(ukey.as<uint64_t>(), U, kb,
+                                                    O.gid.as<uint32_t>(), batch->gof,
+                                                    batch->shortcuts);
+          HIP_TRY(hipGetLastError());
+        }
         k_swap_key<<<grid(U), 256, 0, st>>>(ukey.as<uint64_t>(), &dc()->c32[C_HEADS], kb,
                                             rkey.as<uint64_t>());
         HIP_TRY(hipGetLastError());
@@ -705,28 +725,26 @@ struct Builder {
   }
 };
 
-int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out) {
-  clear_error();
-  if (!g || !out) return set_error(CH_E_INVALID, "graph and out must not be NULL");
-  ch_params_t prm{};
+static int check_params(const ch_params_t *p, ch_params_t &prm) {
+  prm = ch_params_t{};
   if (p) prm = *p;
   if (prm.wps_mode != CH_WPS_EXACT) return set_error(CH_E_UNSUPPORTED, "unknown wps_mode");
   if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&
       prm.group != 64)
     return set_error(CH_E_INVALID, "group must be 0, 4, 8, 16, 32 or 64");
-  if (g->n == 0xFFFFFFFFu) return set_error(CH_E_INVALID, "n must be at most 0xFFFFFFFE");
-  if (!g->offsets || (g->m && (!g->dst || !g->w)))
-    return set_error(CH_E_INVALID, "offsets, dst and w must not be NULL");
+  return CH_OK;
+}
+
+static int new_ch(hipStream_t stream, bool create_stream, ch_s **out) {
   ch_s *ch = new (std::nothrow) ch_s();
   if (!ch) return set_error(CH_E_OOM, "out of host memory");
-  ch->n = g->n;
   hipError_t e = hipGetDevice(&ch->device);
   if (e != hipSuccess) {
     delete ch;
     return hip_error(e, "hipGetDevice");
   }
-  if (prm.stream) {
-    ch->stream = (hipStream_t)prm.stream;
+  if (stream || !create_stream) {
+    ch->stream = stream;
   } else {
     e = hipStreamCreateWithFlags(&ch->stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -735,41 +753,49 @@ int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out) {
     }
     ch->own_stream = true;
   }
+  *out = ch;
+  return CH_OK;
+}
+
+// Rounds + postprocessing of `g` into ch (timed with events on ch's stream).
+static int run_build(ch_s *ch, const ch_graph_t *g, const ch_params_t &prm,
+                     const Builder::Batch *batch) {
   int rc;
-  {
-    Builder b;
-    b.ch = ch;
-    b.st = ch->stream;
-    b.prm = prm;
-    b.n = g->n;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device) ==
-            hipSuccess &&
-        cus > 0)
-      b.cus = cus;
-    hipEvent_t t0, t1;
-    (void)hipEventCreate(&t0);
-    (void)hipEventCreate(&t1);
-    (void)hipEventRecord(t0, b.st);
-    rc = b.run(g);
-    if (rc == CH_OK) rc = postprocess(ch, !(prm.flags & CH_F_NO_QUERY_INDEX));
-    (void)hipEventRecord(t1, b.st);
-    if (rc == CH_OK) {
-      hipError_t se = hipEventSynchronize(t1);
-      if (se != hipSuccess) rc = hip_error(se, "build");
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, t0, t1);
-      ch->summary.ms_build = ms;
-    }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    if (rc == CH_OK) ch->summary.memo_entries = b.mcount;
+  Builder b;
+  b.ch = ch;
+  b.st = ch->stream;
+  b.prm = prm;
+  b.n = g->n;
+  b.batch = batch;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device) ==
+          hipSuccess &&
+      cus > 0)
+    b.cus = cus;
+  hipEvent_t t0, t1;
+  (void)hipEventCreate(&t0);
+  (void)hipEventCreate(&t1);
+  (void)hipEventRecord(t0, b.st);
+  rc = b.run(g);
+  if (rc == CH_OK)
+    rc = postprocess(ch, !batch && !(prm.flags & CH_F_NO_QUERY_INDEX), batch ? batch->gof : nullptr,
+                     batch ? batch->k : 0);
+  (void)hipEventRecord(t1, b.st);
+  if (rc == CH_OK) {
+    hipError_t se = hipEventSynchronize(t1);
+    if (se != hipSuccess) rc = hip_error(se, "build");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    ch->summary.ms_build = ms;
   }
-  if (rc != CH_OK) {
-    (void)hipStreamSynchronize(ch->stream);
-    delete ch;
-    return rc;
-  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (rc == CH_OK) ch->summary.memo_entries = b.mcount;
+  if (rc != CH_OK) (void)hipStreamSynchronize(ch->stream);
+  return rc;
+}
+
+static void fill_summary(ch_s *ch) {
   ch->summary.n = ch->n;
   ch->summary.rounds = ch->rounds;
   ch->summary.m_input = ch->m_input;
@@ -778,7 +804,275 @@ int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out) {
   uint64_t sc = 0;
   for (auto &r : ch->stats) sc += r.n_shortcuts;
   ch->summary.shortcuts = sc;
+}
+
+int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out) {
+  clear_error();
+  if (!g || !out) return set_error(CH_E_INVALID, "graph and out must not be NULL");
+  ch_params_t prm;
+  TRY(check_params(p, prm));
+  if (g->n == 0xFFFFFFFFu) return set_error(CH_E_INVALID, "n must be at most 0xFFFFFFFE");
+  if (!g->offsets || (g->m && (!g->dst || !g->w)))
+    return set_error(CH_E_INVALID, "offsets, dst and w must not be NULL");
+  ch_s *ch = nullptr;
+  TRY(new_ch((hipStream_t)prm.stream, true, &ch));
+  ch->n = g->n;
+  int rc = run_build(ch, g, prm, nullptr);
+  if (rc != CH_OK) {
+    delete ch;
+    return rc;
+  }
+  fill_summary(ch);
   *out = ch;
+  return CH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched construction: the k graphs become one disjoint union (ids shifted
+// by each graph's vertex base, labels kept per graph), the rounds run once,
+// and the result is split.  Every rule of a round is local to a vertex's own
+// graph and every tie is broken by the graph's own labels, so each graph's
+// CH equals the one ch_build gives it alone.
+// ---------------------------------------------------------------------------
+int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **outs) {
+  clear_error();
+  if (!gs || !outs || k == 0) return set_error(CH_E_INVALID, "graphs and outs must not be NULL");
+  ch_params_t prm;
+  TRY(check_params(p, prm));
+  const bool on_dev = prm.flags & CH_F_INPUT_ON_DEVICE;
+  std::vector<uint32_t> vb(k + 1, 0);
+  std::vector<uint64_t> ab(k + 1, 0);
+  bool any_labels = false, all_labels = true;
+  for (uint32_t g = 0; g < k; g++) {
+    const ch_graph_t &G = gs[g];
+    if (!G.offsets || (G.m && (!G.dst || !G.w)))
+      return set_error(CH_E_INVALID, "offsets, dst and w must not be NULL");
+    if ((uint64_t)vb[g] + G.n > 0xFFFFFFFEull)
+      return set_error(CH_E_UNSUPPORTED, "the batch has more than 0xFFFFFFFE vertices");
+    vb[g + 1] = vb[g] + G.n;
+    ab[g + 1] = ab[g] + G.m;
+    any_labels |= G.labels != nullptr;
+    all_labels &= G.labels != nullptr || G.n == 0;
+  }
+  if (any_labels && !all_labels)
+    return set_error(CH_E_INVALID, "either every graph of a batch has labels or none has");
+  const uint32_t n = vb[k];
+  const uint64_t m = ab[k];
+  if (m >= 0xFFFFFFFFull)
+    return set_error(CH_E_UNSUPPORTED, "the batch has 2^32 - 1 or more arcs");
+  const size_t n1 = std::max<uint32_t>(n, 1), m1 = std::max<uint64_t>(m, 1);
+
+  ch_s *U = nullptr;
+  TRY(new_ch((hipStream_t)prm.stream, true, &U));
+  U->n = n;
+  hipStream_t st = U->stream;
+  DBuf d_vb, d_ab, stage, off, dst, w, gof, sc, min, mx, dbad;
+  auto cleanup = [&]() {
+    DBuf *all[] = {&d_vb, &d_ab, &stage, &off, &dst, &w, &gof, &sc, &min, &mx, &dbad};
+    for (DBuf *b : all) b->release();
+  };
+  auto fail = [&](int rc) {
+    (void)hipStreamSynchronize(st);
+    cleanup();
+    delete U;
+    return rc;
+  };
+#define BTRY(expr)                                              \
+  do {                                                          \
+    hipError_t e_ = (expr);                                     \
+    if (e_ != hipSuccess) return fail(hip_error(e_, #expr));    \
+  } while (0)
+  const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  BTRY(d_vb.ensure((k + 1) * 4));
+  BTRY(d_ab.ensure((k + 1) * 8));
+  BTRY(stage.ensure(((size_t)n + k) * 8));
+  BTRY(off.ensure((n1 + 1) * 8));
+  BTRY(dst.ensure(m1 * 4));
+  BTRY(w.ensure(m1 * 4));
+  BTRY(gof.ensure(n1 * 4));
+  BTRY(sc.ensure(k * 8));
+  BTRY(min.ensure(k * 8));
+  BTRY(mx.ensure(k * 4));
+  BTRY(dbad.ensure(4));
+  BTRY(U->label.ensure(n1 * 4));
+  BTRY(hipMemcpyAsync(d_vb.p, vb.data(), (k + 1) * 4, hipMemcpyHostToDevice, st));
+  BTRY(hipMemcpyAsync(d_ab.p, ab.data(), (k + 1) * 8, hipMemcpyHostToDevice, st));
+  BTRY(hipMemsetAsync(sc.p, 0, k * 8, st));
+  BTRY(hipMemsetAsync(min.p, 0, k * 8, st));
+  BTRY(hipMemsetAsync(mx.p, 0, k * 4, st));
+  BTRY(hipMemsetAsync(dbad.p, 0, 4, st));
+  for (uint32_t g = 0; g < k; g++) {
+    const ch_graph_t &G = gs[g];
+    BTRY(hipMemcpyAsync(stage.as<uint64_t>() + vb[g] + g, G.offsets, ((size_t)G.n + 1) * 8, kind,
+                        st));
+    if (G.m) {
+      BTRY(hipMemcpyAsync(dst.as<uint32_t>() + ab[g], G.dst, G.m * 4, kind, st));
+      BTRY(hipMemcpyAsync(w.as<uint32_t>() + ab[g], G.w, G.m * 4, kind, st));
+    }
+    if (G.labels && G.n)
+      BTRY(hipMemcpyAsync(U->label.as<uint32_t>() + vb[g], G.labels, (size_t)G.n * 4, kind, st));
+  }
+  const unsigned gr = 1024;
+  if (n) {
+    k_batch_offsets<<<gr, 256, 0, st>>>(n, k, d_vb.as<uint32_t>(), d_ab.as<uint64_t>(),
+                                        stage.as<uint64_t>(), off.as<uint64_t>(),
+                                        gof.as<uint32_t>(), dbad.as<uint32_t>());
+    BTRY(hipGetLastError());
+  }
+  BTRY(hipMemcpyAsync(off.as<uint64_t>() + n, &ab[k], 8, hipMemcpyHostToDevice, st));
+  if (m) {
+    k_batch_arcs<<<gr, 256, 0, st>>>(m, k, d_vb.as<uint32_t>(), d_ab.as<uint64_t>(),
+                                     dst.as<uint32_t>(), dbad.as<uint32_t>());
+    BTRY(hipGetLastError());
+  }
+  if (!any_labels && n) {
+    const uint32_t mix = (uint32_t)prm.seed ^ (uint32_t)(prm.seed >> 32);
+    k_batch_default_labels<<<gr, 256, 0, st>>>(n, k, d_vb.as<uint32_t>(), mix,
+                                               U->label.as<uint32_t>());
+    BTRY(hipGetLastError());
+  }
+  if (any_labels && n > 1) {  // distinct within each graph
+    DBuf k1, k2, v1, v2, tmp;
+    BTRY(k1.ensure(n1 * 8));
+    BTRY(k2.ensure(n1 * 8));
+    BTRY(v1.ensure(n1 * 4));
+    BTRY(v2.ensure(n1 * 4));
+    k_graph_label_keys<<<gr, 256, 0, st>>>(n, gof.as<uint32_t>(), U->label.as<uint32_t>(),
+                                           k1.as<uint64_t>());
+    BTRY(iota_u32(v1.as<uint32_t>(), n, st));
+    int kbits = 1;
+    while (kbits < 32 && (1u << kbits) < k) kbits++;
+    BTRY(radix_sort_u64(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(),
+                        v2.as<uint32_t>(), n, 32 + kbits, tmp, st));
+    k_adjacent_equal<<<gr, 256, 0, st>>>(n, k1.as<uint64_t>(), dbad.as<uint32_t>());
+    BTRY(hipGetLastError());
+    BTRY(hipStreamSynchronize(st));
+    DBuf *bb[] = {&k1, &k2, &v1, &v2, &tmp};
+    for (DBuf *b : bb) b->release();
+  }
+  uint32_t bad = 0;
+  BTRY(hipMemcpyAsync(&bad, dbad.p, 4, hipMemcpyDeviceToHost, st));
+  BTRY(hipStreamSynchronize(st));
+  if (bad & 8) return fail(set_error(CH_E_INVALID, "a graph's offsets[0] is not 0 or offsets[n] is not m"));
+  if (bad & 1) return fail(set_error(CH_E_INVALID, "a graph's offsets exceed its arc count"));
+  if (bad & 2) return fail(set_error(CH_E_INVALID, "an arc has head >= n or weight 0xFFFFFFFF"));
+  if (bad & 4) return fail(set_error(CH_E_INVALID, "labels are not distinct within a graph"));
+
+  ch_graph_t ug{n, m, off.as<uint64_t>(), dst.as<uint32_t>(), w.as<uint32_t>(), U->label.as<uint32_t>()};
+  ch_params_t uprm = prm;
+  uprm.flags |= CH_F_INPUT_ON_DEVICE;
+  Builder::Batch binfo;
+  binfo.k = k;
+  binfo.gof = gof.as<uint32_t>();
+  binfo.shortcuts = sc.as<unsigned long long>();
+  binfo.m_in = min.as<unsigned long long>();
+  int rc = run_build(U, &ug, uprm, &binfo);
+  if (rc != CH_OK) return fail(rc);
+
+  // split: arcs per graph (sorted by graph, then rank), rounds per graph
+  std::vector<unsigned long long> up_cnt(k, 0), dn_cnt(k, 0), h_sc(k), h_min(k);
+  std::vector<uint32_t> h_mx(k);
+  {
+    DBuf cu, cd;
+    BTRY(cu.ensure(k * 8));
+    BTRY(cd.ensure(k * 8));
+    BTRY(hipMemsetAsync(cu.p, 0, k * 8, st));
+    BTRY(hipMemsetAsync(cd.p, 0, k * 8, st));
+    if (U->nup)
+      k_arcs_by_graph<<<gr, 256, 0, st>>>(U->nup, U->up_t.as<uint32_t>(), gof.as<uint32_t>(),
+                                          cu.as<unsigned long long>());
+    if (U->ndown)
+      k_arcs_by_graph<<<gr, 256, 0, st>>>(U->ndown, U->dn_h.as<uint32_t>(), gof.as<uint32_t>(),
+                                          cd.as<unsigned long long>());
+    if (n)
+      k_level_max_by_graph<<<gr, 256, 0, st>>>(n, U->level.as<uint32_t>(), gof.as<uint32_t>(),
+                                               mx.as<uint32_t>());
+    BTRY(hipGetLastError());
+    BTRY(hipMemcpyAsync(up_cnt.data(), cu.p, k * 8, hipMemcpyDeviceToHost, st));
+    BTRY(hipMemcpyAsync(dn_cnt.data(), cd.p, k * 8, hipMemcpyDeviceToHost, st));
+    BTRY(hipMemcpyAsync(h_sc.data(), sc.p, k * 8, hipMemcpyDeviceToHost, st));
+    BTRY(hipMemcpyAsync(h_min.data(), min.p, k * 8, hipMemcpyDeviceToHost, st));
+    BTRY(hipMemcpyAsync(h_mx.data(), mx.p, k * 4, hipMemcpyDeviceToHost, st));
+    BTRY(hipStreamSynchronize(st));
+    cu.release();
+    cd.release();
+  }
+  std::vector<ch_s *> made;
+  auto fail_split = [&](int rc2) {
+    for (ch_s *c : made) delete c;
+    return fail(rc2);
+  };
+  uint64_t ubase = 0, dbase = 0;
+  for (uint32_t g = 0; g < k; g++) {
+    ch_s *c = nullptr;
+    int r2 = new_ch((hipStream_t)prm.stream, false, &c);
+    if (r2 != CH_OK) return fail_split(r2);
+    made.push_back(c);
+    const uint32_t ng = vb[g + 1] - vb[g];
+    c->n = ng;
+    c->nup = up_cnt[g];
+    c->ndown = dn_cnt[g];
+    c->rounds = h_mx[g];
+    c->m_input = h_min[g];
+    const size_t ng1 = std::max<uint32_t>(ng, 1);
+    hipStream_t cs = c->stream;
+    hipError_t e2;
+#define STRY(expr)                                   \
+  do {                                               \
+    if ((e2 = (expr)) != hipSuccess) return fail_split(hip_error(e2, #expr)); \
+  } while (0)
+    STRY(c->level.ensure(ng1 * 4));
+    STRY(c->score.ensure(ng1 * 4));
+    STRY(c->label.ensure(ng1 * 4));
+    STRY(c->rank.ensure(ng1 * 4));
+    STRY(hipStreamSynchronize(st));
+    if (ng) {
+      STRY(hipMemcpyAsync(c->level.p, U->level.as<uint32_t>() + vb[g], ng * 4,
+                          hipMemcpyDeviceToDevice, cs));
+      STRY(hipMemcpyAsync(c->score.p, U->score.as<int32_t>() + vb[g], ng * 4,
+                          hipMemcpyDeviceToDevice, cs));
+      STRY(hipMemcpyAsync(c->label.p, U->label.as<uint32_t>() + vb[g], ng * 4,
+                          hipMemcpyDeviceToDevice, cs));
+      k_sub_base<<<gr, 256, 0, cs>>>(ng, U->rank.as<uint32_t>() + vb[g], vb[g], false,
+                                     c->rank.as<uint32_t>());
+      STRY(hipGetLastError());
+    }
+    DBuf *cu_[] = {&c->up_t, &c->up_h, &c->up_w, &c->up_m};
+    DBuf *uu_[] = {&U->up_t, &U->up_h, &U->up_w, &U->up_m};
+    DBuf *cd_[] = {&c->dn_t, &c->dn_h, &c->dn_w, &c->dn_m};
+    DBuf *ud_[] = {&U->dn_t, &U->dn_h, &U->dn_w, &U->dn_m};
+    for (int q = 0; q < 4; q++) {
+      STRY(cu_[q]->ensure(std::max<uint64_t>(c->nup, 1) * 4));
+      STRY(cd_[q]->ensure(std::max<uint64_t>(c->ndown, 1) * 4));
+      if (c->nup)
+        k_sub_base<<<gr, 256, 0, cs>>>(c->nup, uu_[q]->as<uint32_t>() + ubase,
+                                       q == 2 ? 0u : vb[g], q == 3, cu_[q]->as<uint32_t>());
+      if (c->ndown)
+        k_sub_base<<<gr, 256, 0, cs>>>(c->ndown, ud_[q]->as<uint32_t>() + dbase,
+                                       q == 2 ? 0u : vb[g], q == 3, cd_[q]->as<uint32_t>());
+      STRY(hipGetLastError());
+    }
+    ubase += c->nup;
+    dbase += c->ndown;
+    if (!(prm.flags & CH_F_NO_QUERY_INDEX)) {
+      r2 = build_index(c);
+      if (r2 != CH_OK) return fail_split(r2);
+    }
+    STRY(hipStreamSynchronize(cs));
+#undef STRY
+    c->summary.n = ng;
+    c->summary.rounds = c->rounds;
+    c->summary.m_input = c->m_input;
+    c->summary.up_arcs = c->nup;
+    c->summary.down_arcs = c->ndown;
+    c->summary.shortcuts = h_sc[g];
+    c->summary.memo_entries = 0;
+    c->summary.ms_build = U->summary.ms_build;
+  }
+#undef BTRY
+  for (uint32_t g = 0; g < k; g++) outs[g] = made[g];
+  cleanup();
+  delete U;
   return CH_OK;
 }
 

@@ -47,8 +47,13 @@ int hip_error(hipError_t e, const char *what);
 
 // Build entry (builder.hip).
 int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out);
-// Postprocess: rank, sorted arc lists, query index (post.hip).
-int postprocess(ch_s *ch, bool make_index);
+// Postprocess: rank, sorted arc lists, query index (post.hip).  With gof
+// (graph of each vertex, kgraphs graphs) the graph id is the major rank key.
+int postprocess(ch_s *ch, bool make_index, const uint32_t *gof = nullptr, uint32_t kgraphs = 0);
+// Query index of a CH whose arc lists are already sorted by rank (post.hip).
+int build_index(ch_s *ch);
+// Batched build of k graphs as one disjoint union (builder.hip).
+int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **outs);
 // Query batch (post.hip).
 int query_batch(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                 uint64_t *dist, uint32_t flags, hipStream_t st);

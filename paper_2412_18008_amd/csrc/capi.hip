@@ -19,6 +19,10 @@ int ch_build(const ch_graph_t *g, const ch_params_t *p, ch_t **out) {
   return sp::build_ch(g, p, out);
 }
 
+int ch_build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **outs) {
+  return sp::build_batch(gs, k, p, outs);
+}
+
 int ch_query_batch(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                    uint64_t *dist, uint32_t flags, void *stream) {
   sp::clear_error();

@@ -45,6 +45,12 @@ __global__ void k_level_keys(uint32_t n, const uint32_t *__restrict__ order,
   }
 }
 
+__global__ void k_graph_keys(uint32_t n, const uint32_t *__restrict__ order,
+                             const uint32_t *__restrict__ gof, uint64_t *__restrict__ key) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) key[i] = gof[order[i]];
+}
+
 __global__ void k_rank_from_order(uint32_t n, const uint32_t *__restrict__ order,
                                   uint32_t *__restrict__ rank) {
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -97,7 +103,8 @@ __global__ void k_index(uint32_t n, uint64_t m, int kb, const uint64_t *__restri
     arc[i] = make_uint2((uint32_t)(key[i] & lowmask), w[i]);
 }
 
-static unsigned gridn(uint64_t items) {
+unsigned gridn(uint64_t items);
+unsigned gridn(uint64_t items) {
   uint64_t g = (items + 255) / 256;
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
@@ -162,10 +169,44 @@ static int sort_arcs(ch_s *ch, bool up, DBuf &k1, DBuf &k2, DBuf &v1, DBuf &v2, 
   return CH_OK;
 }
 
+// Query index of a CH whose arc lists are already sorted by rank.
+int build_index(ch_s *ch) {
+  hipStream_t st = ch->stream;
+  const int kb = bits_for(ch->n);
+  DBuf k1, v1;
+  for (int dir = 0; dir < 2; dir++) {
+    const bool up = dir == 0;
+    const uint64_t m = up ? ch->nup : ch->ndown;
+    const size_t m1 = std::max<uint64_t>(m, 1);
+    DBuf &off = up ? ch->q_upoff : ch->q_dnoff;
+    DBuf &arc = up ? ch->q_uparc : ch->q_dnarc;
+    HIP_TRY(k1.ensure(m1 * 8));
+    HIP_TRY(v1.ensure(m1 * 4));
+    HIP_TRY(off.ensure(((size_t)ch->n + 1) * 4));
+    HIP_TRY(arc.ensure(m1 * 8));
+    if (m) {
+      k_arc_rank_keys<<<gridn(m), 256, 0, st>>>(
+          m, up ? ch->up_t.as<uint32_t>() : ch->dn_h.as<uint32_t>(),
+          up ? ch->up_h.as<uint32_t>() : ch->dn_t.as<uint32_t>(), ch->rank.as<uint32_t>(), kb,
+          k1.as<uint64_t>(), v1.as<uint32_t>());
+      HIP_TRY(hipGetLastError());
+    }
+    k_index<<<gridn(std::max<uint64_t>(m, (uint64_t)ch->n + 1)), 256, 0, st>>>(
+        ch->n, m, kb, k1.as<uint64_t>(), up ? ch->up_w.as<uint32_t>() : ch->dn_w.as<uint32_t>(),
+        off.as<uint32_t>(), arc.as<uint2>());
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  k1.release();
+  v1.release();
+  ch->has_index = true;
+  return CH_OK;
+}
+
 // Postprocessing: vertices are ordered by level, then by score at
 // contraction (low to high), then by label; the CH arcs are re-keyed to the
 // new ranks and sorted.
-int postprocess(ch_s *ch, bool make_index) {
+int postprocess(ch_s *ch, bool make_index, const uint32_t *gof, uint32_t kgraphs) {
   hipStream_t st = ch->stream;
   const uint32_t n = ch->n;
   const size_t n1 = std::max<uint32_t>(n, 1);
@@ -194,6 +235,14 @@ int postprocess(ch_s *ch, bool make_index) {
                               v2.as<uint32_t>(), n, 32 + lb, tmp, st)) != hipSuccess) {
         rc = hip_error(e, "rank sort");
         break;
+      }
+      if (gof && kgraphs > 1) {  // disjoint-union batch: graph id is the major key
+        k_graph_keys<<<gridn(n), 256, 0, st>>>(n, v1.as<uint32_t>(), gof, k1.as<uint64_t>());
+        if ((e = radix_sort_u64(k1.as<uint64_t>(), v1.as<uint32_t>(), k2.as<uint64_t>(),
+                                v2.as<uint32_t>(), n, bits_for(kgraphs), tmp, st)) != hipSuccess) {
+          rc = hip_error(e, "rank sort");
+          break;
+        }
       }
       k_rank_from_order<<<gridn(n), 256, 0, st>>>(n, v1.as<uint32_t>(), ch->rank.as<uint32_t>());
       if ((e = hipGetLastError()) != hipSuccess) {

@@ -575,6 +575,134 @@ __global__ void k_eplus_reduce(const uint64_t *__restrict__ key, const uint32_t 
   }
 }
 
+// ---------------------------------------------------------------------------
+// disjoint-union batch preparation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t graph_of(const uint32_t *vbase, uint32_t k, uint32_t v) {
+  uint32_t lo = 0, hi = k;  // last g with vbase[g] <= v
+  while (hi - lo > 1) {
+    const uint32_t md = (lo + hi) >> 1;
+    if (vbase[md] <= v) lo = md;
+    else hi = md;
+  }
+  return lo;
+}
+
+// Union offsets from the graphs' own offsets (staged: graph g's n_g + 1
+// values start at vbase[g] + g).  Also records the graph of each vertex and
+// validates each graph's first and last offset.
+__global__ void k_batch_offsets(uint32_t n, uint32_t k, const uint32_t *__restrict__ vbase,
+                                const uint64_t *__restrict__ abase,
+                                const uint64_t *__restrict__ stage, uint64_t *__restrict__ off,
+                                uint32_t *__restrict__ gof, uint32_t *__restrict__ bad) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint32_t g = graph_of(vbase, k, v);
+    const uint32_t i = v - vbase[g];
+    const uint64_t local = stage[(uint64_t)vbase[g] + g + i];
+    const uint64_t mg = abase[g + 1] - abase[g];
+    if (local > mg) {
+      atomicOr(bad, 1u);
+      off[v] = abase[g];
+    } else {
+      off[v] = abase[g] + local;
+    }
+    gof[v] = g;
+    if (i == 0) {
+      const uint32_t ng = vbase[g + 1] - vbase[g];
+      if (local != 0 || stage[(uint64_t)vbase[g] + g + ng] != mg) atomicOr(bad, 8u);
+    }
+  }
+}
+
+// Shift arc heads into union ids; a head >= n_g is an error.
+__global__ void k_batch_arcs(uint64_t m, uint32_t k, const uint32_t *__restrict__ vbase,
+                             const uint64_t *__restrict__ abase, uint32_t *__restrict__ dst,
+                             uint32_t *__restrict__ bad) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+    uint32_t lo = 0, hi = k;  // last g with abase[g] <= e and a non-empty arc range
+    while (hi - lo > 1) {
+      const uint32_t md = (lo + hi) >> 1;
+      if (abase[md] <= e) lo = md;
+      else hi = md;
+    }
+    const uint32_t g = lo;
+    const uint32_t ng = vbase[g + 1] - vbase[g];
+    const uint32_t h = dst[e];
+    if (h >= ng) {
+      atomicOr(bad, 2u);
+      dst[e] = vbase[g];
+    } else {
+      dst[e] = vbase[g] + h;
+    }
+  }
+}
+
+// Default labels per graph: fmix32(local id ^ mix).
+__global__ void k_batch_default_labels(uint32_t n, uint32_t k, const uint32_t *__restrict__ vbase,
+                                       uint32_t mix, uint32_t *__restrict__ lab) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    lab[v] = fmix32((v - vbase[graph_of(vbase, k, v)]) ^ mix);
+}
+
+// key = (graph << 32) | label, for the per-graph distinctness check.
+__global__ void k_graph_label_keys(uint32_t n, const uint32_t *__restrict__ gof,
+                                   const uint32_t *__restrict__ lab, uint64_t *__restrict__ key) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    key[v] = ((uint64_t)gof[v] << 32) | lab[v];
+}
+
+// Row lengths of the (union) forward CSR summed per graph.
+__global__ void k_rowlen_by_graph(uint32_t n, const uint32_t *__restrict__ foff,
+                                  const uint32_t *__restrict__ gof,
+                                  unsigned long long *__restrict__ cnt) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint32_t len = foff[v + 1] - foff[v];
+    if (len) atomicAdd(&cnt[gof[v]], (unsigned long long)len);
+  }
+}
+
+// Arcs per graph (of the vertex `a[i]`), for splitting sorted arc lists.
+__global__ void k_arcs_by_graph(uint64_t m, const uint32_t *__restrict__ a,
+                                const uint32_t *__restrict__ gof,
+                                unsigned long long *__restrict__ cnt) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+    atomicAdd(&cnt[gof[a[i]]], 1ull);
+}
+
+// Largest level per graph.
+__global__ void k_level_max_by_graph(uint32_t n, const uint32_t *__restrict__ level,
+                                     const uint32_t *__restrict__ gof, uint32_t *__restrict__ mx) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    atomicMax(&mx[gof[v]], level[v] + 1);
+}
+
+// out[i] = in[i] - base (ids of one graph back to its local ids); SP_NOMID
+// is kept when keep_nomid.
+__global__ void k_sub_base(uint64_t m, const uint32_t *__restrict__ in, uint32_t base,
+                           bool keep_nomid, uint32_t *__restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint32_t x = in[i];
+    out[i] = (keep_nomid && x == SP_NOMID) ? x : x - base;
+  }
+}
+
+// Batch bookkeeping: one count per distinct shortcut pair, by graph of v1.
+__global__ void k_count_by_graph(const uint64_t *__restrict__ ukey, uint32_t U, int kb,
+                                 const uint32_t *__restrict__ gid, const uint32_t *__restrict__ gof,
+                                 unsigned long long *__restrict__ cnt) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < U; i += stride)
+    atomicAdd(&cnt[gof[gid[(uint32_t)(ukey[i] >> kb)]]], 1ull);
+}
+
 // ===========================================================================
 // overlay rebuild
 // ===========================================================================

@@ -177,3 +177,35 @@ def test_road_100k_bit_exact(gpu):
     assert np.array_equal(d, od)
     ref = reference_distances(off, dst, w, s[:20], t[:20])
     assert np.array_equal(d[:20], ref)
+
+
+def test_batch_equals_single_builds(gpu):
+    graphs = [synth.random_geometric_small(800, seed=1), synth.grid(9, 11, seed=2),
+              synth.random_digraph(60, 240, seed=3, wmax=9, zero_frac=0.1, loops=True),
+              (np.zeros(1, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32)),
+              synth.chain(150, seed=4, directed=False), synth.star(40, seed=5),
+              synth.road_like(3000, seed=6)]
+    labels = [synth.labels(len(g[0]) - 1, 100 + i) for i, g in enumerate(graphs)]
+    print("[parity] batch of", len(graphs), flush=True)
+    outs = gpu.build_batch(graphs, labels=labels)
+    for i, (g, lab, ch) in enumerate(zip(graphs, labels, outs)):
+        single = gpu.build(*g, labels=lab)
+        a, b = gpu_export(single), gpu_export(ch)
+        assert_same_ch(a, b, f"batch[{i}]")
+        for key in ("rounds", "up_arcs", "down_arcs", "shortcuts", "m_input"):
+            assert ch.summary[key] == single.summary[key], (i, key)
+        n = len(g[0]) - 1
+        if n:
+            s, t = synth.queries(n, 300, seed=i)
+            assert np.array_equal(ch.query(s, t), single.query(s, t))
+    # default labels: each graph labelled by its local ids
+    outs = gpu.build_batch(graphs[:3], seed=77)
+    for i, g in enumerate(graphs[:3]):
+        assert_same_ch(gpu_export(gpu.build(*g, seed=77)), gpu_export(outs[i]), f"default[{i}]")
+    # labels need only be distinct within a graph
+    same = [synth.labels(len(graphs[1][0]) - 1, 5)] * 2
+    outs = gpu.build_batch([graphs[1], graphs[1]], labels=same)
+    assert_same_ch(gpu_export(outs[0]), gpu_export(outs[1]), "twins")
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build_batch([graphs[1], graphs[2]], labels=[labels[1], np.zeros(60, np.uint32)])
+    assert e.value.code == gpu.CH_E_INVALID
