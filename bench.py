@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TIER1_KERNELS = ("k_local_search<16, 128>", "k_local_search<64, 2048>")
+
 
 WORKLOADS = {
     "road1m": dict(
@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="road1m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--untuned", action="store_true",
+                    help="ignore the autotuner cache (default knobs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the build is a single-GPU path "
@@ -115,9 +117,14 @@ def main():
     t_t = torch.from_numpy(qt.astype(np.int32)).to(dev)
     torch.cuda.synchronize()
 
+    from paper_2412_18008_amd import autotune
+
+    knobs = {} if args.untuned else autotune.params_for(n, m)
+    print(f"[bench] knobs {knobs or 'default'}", file=sys.stderr, flush=True)
+
     def step():
         tb = time.perf_counter()
-        ch = binding.build(t_off, t_dst, t_w, seed=0, stats=True)
+        ch = binding.build(t_off, t_dst, t_w, seed=0, stats=True, **knobs)
         tq = time.perf_counter()
         d = ch.query(t_s, t_t)
         te = time.perf_counter()
@@ -151,12 +158,12 @@ def main():
         for x in r["rounds"]:
             if x["n_sources"] == 0:
                 continue
-            k = TIER1_KERNELS[x["ls_tier1"]]
+            k = binding.LS_KERNELS[x["ls_tier1"]]
             a = per.setdefault(k, [0, 0.0, 0])
             a[0] += 1
             a[1] += x["ms_local_search"]
             a[2] += ls_bytes(x)
-    dom = max(per, key=lambda k: per[k][1]) if per else TIER1_KERNELS[0]
+    dom = max(per, key=lambda k: per[k][1]) if per else binding.LS_KERNELS[1]
     ls_launches, ls_ms, ls_b = per.get(dom, [0, 0.0, 0])
     achieved = (ls_b / 1e9) / (ls_ms / 1e3) if ls_ms > 0 else 0.0
 
@@ -175,7 +182,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload]["desc"], "n": n, "m": m,
                    "queries": int(len(qs)), "priority": "plain (edge difference)",
-                   "wps": "exact, radius D_s"},
+                   "wps": "exact, radius D_s", "knobs": knobs or "default"},
         "build_time_s": build_s,
         "query_batch_ms": query_s * 1e3,
         "queries_per_s": len(qs) / query_s,

@@ -87,7 +87,21 @@ typedef struct {
   uint32_t group;      /* lanes per item in the round kernels: 0 = automatic,   */
                        /* else 4, 8, 16, 32 or 64 (changes speed, never results) */
   void *stream;        /* hipStream_t to run on (borrowed); NULL = the library's */
+  /* First-tier witness-search kernel (lanes x LDS table slots) for rounds
+   * whose overlay has average out-degree <= dense_deg10 / 10 ("sparse") and
+   * for the others ("dense"): CH_LS_AUTO or one of CH_LS_16x128 ...
+   * CH_LS_64x2048.  dense_deg10 = 0 means 50.  These change speed only. */
+  uint32_t ls_sparse;
+  uint32_t ls_dense;
+  uint32_t dense_deg10;
+  uint32_t reserved;   /* must be 0 */
 } ch_params_t;
+
+#define CH_LS_AUTO 0u
+#define CH_LS_16x128 1u
+#define CH_LS_32x512 2u
+#define CH_LS_64x512 3u
+#define CH_LS_64x2048 4u
 
 typedef struct ch_s ch_t;
 
@@ -107,8 +121,7 @@ typedef struct {
   uint64_t memo_probes;     /* memo slots read by the local search             */
   uint64_t memo_inserts;    /* memo entries written                            */
   uint32_t n_ls_fallback;   /* sources whose search outgrew the first-tier table */
-  uint32_t ls_tier1;        /* first-tier search kernel: 0 = 16 lanes x 128 slots, */
-                            /* 1 = 64 lanes x 2048 slots                           */
+  uint32_t ls_tier1;        /* first-tier search kernel used (CH_LS_16x128 ...)   */
   float ms_local_search;    /* device time of the first-tier witness-search kernel */
   float ms_total;           /* device time of the whole round (host gaps included) */
 } ch_round_stats_t;

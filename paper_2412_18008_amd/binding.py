@@ -47,7 +47,14 @@ class Graph(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("wps_mode", C.c_uint32), ("max_rounds", C.c_uint32), ("seed", C.c_uint64),
-                ("flags", C.c_uint32), ("group", C.c_uint32), ("stream", C.c_void_p)]
+                ("flags", C.c_uint32), ("group", C.c_uint32), ("stream", C.c_void_p),
+                ("ls_sparse", C.c_uint32), ("ls_dense", C.c_uint32),
+                ("dense_deg10", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+CH_LS_AUTO, CH_LS_16x128, CH_LS_32x512, CH_LS_64x512, CH_LS_64x2048 = 0, 1, 2, 3, 4
+LS_KERNELS = {1: "k_local_search<16, 128>", 2: "k_local_search<32, 512>",
+              3: "k_local_search<64, 512>", 4: "k_local_search<64, 2048>"}
 
 
 class RoundStats(C.Structure):
@@ -181,7 +188,7 @@ class CH:
 
 
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
-          query_index=True, stream=None):
+          query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
@@ -197,7 +204,8 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
         import torch
 
         stream = torch.cuda.current_stream().cuda_stream
-    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream)
+    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream, ls_sparse, ls_dense,
+               dense_deg10, 0)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
@@ -221,7 +229,7 @@ def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=
         m = dst.numel() if dev else len(kd)
         arr[i] = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX)
-    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream)
+    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream, 0, 0, 0, 0)
     outs = (C.c_void_p * max(k, 1))()
     _check(lib().ch_build_batch(arr, k, C.byref(p), outs), "ch_build_batch")
     return [CH(C.c_void_p(outs[i])) for i in range(k)]

@@ -467,11 +467,18 @@ struct Builder {
         // sources whose search outgrows them go to a 4096-slot LDS tier
         // (launched with its count on the device, so no host round trip),
         // then to tables in global memory
-        const bool small = avgdeg <= 5.0;
-        rs.ls_tier1 = small ? 0 : 1;
+        const double thr = prm.dense_deg10 ? prm.dense_deg10 / 10.0 : 5.0;
+        const bool sparse = avgdeg <= thr;
+        uint32_t kind = sparse ? prm.ls_sparse : prm.ls_dense;
+        if (kind == CH_LS_AUTO) kind = sparse ? CH_LS_16x128 : CH_LS_64x2048;
+        rs.ls_tier1 = kind;
         if (stats) HIP_TRY(hipEventRecord(ev[2], st));
-        if (small) launch_ls<16, 128>(v, vw.as<uint32_t>(), nw, nullptr, 1, 16);
-        else launch_ls<64, 2048>(v, vw.as<uint32_t>(), nw, nullptr, 1, 4);
+        switch (kind) {
+          case CH_LS_16x128: launch_ls<16, 128>(v, vw.as<uint32_t>(), nw, nullptr, 1, 16); break;
+          case CH_LS_32x512: launch_ls<32, 512>(v, vw.as<uint32_t>(), nw, nullptr, 1, 8); break;
+          case CH_LS_64x512: launch_ls<64, 512>(v, vw.as<uint32_t>(), nw, nullptr, 1, 16); break;
+          default: launch_ls<64, 2048>(v, vw.as<uint32_t>(), nw, nullptr, 1, 4); break;
+        }
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
         launch_ls<64, 4096>(v, ovf1.as<uint32_t>(), 0, &dc()->novf1, 2, 2);
@@ -732,6 +739,9 @@ static int check_params(const ch_params_t *p, ch_params_t &prm) {
   if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&
       prm.group != 64)
     return set_error(CH_E_INVALID, "group must be 0, 4, 8, 16, 32 or 64");
+  if (prm.ls_sparse > CH_LS_64x2048 || prm.ls_dense > CH_LS_64x2048)
+    return set_error(CH_E_INVALID, "unknown first-tier search kernel");
+  if (prm.reserved) return set_error(CH_E_INVALID, "reserved must be 0");
   return CH_OK;
 }
 

@@ -47,9 +47,15 @@ def test_null_and_invalid_arguments(binding):
     off = np.zeros(2, np.uint64)
     g = binding.Graph(1, 0, off.ctypes.data, None, None, None)
     assert L.ch_build(C.byref(g), None, None) == binding.CH_E_INVALID
-    p = binding.Params(0, 0, 0, 0, 3, None)  # group 3 is not allowed
+    p = binding.Params(0, 0, 0, 0, 3, None, 0, 0, 0, 0)  # group 3 is not allowed
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
-    p = binding.Params(7, 0, 0, 0, 0, None)  # unknown search mode
+    p = binding.Params(7, 0, 0, 0, 0, None, 0, 0, 0, 0)  # unknown search mode
+    assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_UNSUPPORTED
+    p = binding.Params(0, 0, 0, 0, 0, None, 9, 0, 0, 0)  # unknown search kernel
+    assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
+    p = binding.Params(0, 0, 0, 0, 0, None, 0, 0, 0, 1)  # reserved must be 0
+    assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
+    p = binding.Params(7, 0, 0, 0, 0, None, 0, 0, 0, 0)
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_UNSUPPORTED
     g = binding.Graph(0xFFFFFFFF, 0, off.ctypes.data, None, None, None)
     assert L.ch_build(C.byref(g), None, C.byref(h)) == binding.CH_E_INVALID

@@ -209,3 +209,28 @@ def test_batch_equals_single_builds(gpu):
     with pytest.raises(gpu.ChError) as e:
         gpu.build_batch([graphs[1], graphs[2]], labels=[labels[1], np.zeros(60, np.uint32)])
     assert e.value.code == gpu.CH_E_INVALID
+
+
+def test_search_kernel_knobs_invariance(gpu):
+    off, dst, w = synth.road_like(20_000, seed=8)
+    n = len(off) - 1
+    lab = synth.labels(n, 9)
+    ref = gpu_export(gpu.build(off, dst, w, labels=lab))
+    for a in (1, 2, 3, 4):
+        for b in (1, 2, 3, 4):
+            for t in (30, 50, 90):
+                got = gpu_export(gpu.build(off, dst, w, labels=lab, ls_sparse=a, ls_dense=b,
+                                           dense_deg10=t))
+                assert_same_ch(ref, got, f"ls_sparse={a} ls_dense={b} thr={t}")
+
+
+def test_autotuner_roundtrip(gpu, tmp_path, monkeypatch):
+    from paper_2412_18008_amd import autotune
+
+    monkeypatch.setenv("SPOCH_AUTOTUNE_CACHE", str(tmp_path / "tuned.json"))
+    off, dst, w = synth.road_like(30_000, seed=2)
+    best, table = autotune.tune(off, dst, w, reps=1)
+    assert len(table) == len(autotune.candidates())
+    n, m = len(off) - 1, len(dst)
+    autotune.save({autotune.size_class(n, m): dict(params=best["params"], ms=best["ms"])})
+    assert autotune.params_for(n, m) == best["params"]
