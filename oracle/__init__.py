@@ -49,9 +49,11 @@ def build(force: bool = False) -> str:
         os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH)
     ):
         tmp = LIB_PATH + ".tmp"
+        # -ffp-contract=off: the learned priority is evaluated without fused
+        # multiply-add, so its single-precision result is reproducible
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
-             "-o", tmp, SRC_PATH]
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-shared",
+             "-fPIC", "-o", tmp, SRC_PATH, "-lm"]
         )
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -59,7 +61,13 @@ def build(force: bool = False) -> str:
 
 class _Params(C.Structure):
     _fields_ = [("wps_mode", C.c_uint32), ("hop_limit", C.c_uint32),
-                ("settle_limit", C.c_uint32), ("max_rounds", C.c_uint32)]
+                ("settle_limit", C.c_uint32), ("max_rounds", C.c_uint32),
+                ("priority", C.c_uint32), ("record", C.c_uint32), ("mlp", C.c_void_p)]
+
+
+PRIO_PLAIN = 0
+PRIO_LEARNED = 1
+MLP_PARAMS = 4801
 
 
 class RoundStats(C.Structure):
@@ -117,6 +125,12 @@ def lib():
         L.orc_overlay_dijkstra.restype = i32
         L.orc_default_label.argtypes = [u32, u64]
         L.orc_default_label.restype = u32
+        L.orc_get_features.argtypes = [vp, vp]
+        L.orc_get_features.restype = i32
+        L.orc_mlp_priority.argtypes = [vp, vp, C.POINTER(C.c_float)]
+        L.orc_mlp_priority.restype = C.c_int32
+        L.orc_gelu.argtypes = [C.c_float]
+        L.orc_gelu.restype = C.c_float
         _lib = L
     return _lib
 
@@ -133,13 +147,17 @@ class OracleCH:
     or ``run()`` once; inspection methods copy state into numpy arrays."""
 
     def __init__(self, off, dst, w, labels=None, seed=0, wps_mode=WPS_EXACT,
-                 hop_limit=2, settle_limit=64, max_rounds=0):
+                 hop_limit=2, settle_limit=64, max_rounds=0, mlp=None, record=False):
         L = lib()
         off, dst, w = _csr(off, dst, w)
         n = len(off) - 1
         self._keep = (off, dst, w)
         lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.uint32)
-        p = _Params(wps_mode, hop_limit, settle_limit, max_rounds)
+        wts = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float32)
+        if wts is not None and wts.size != MLP_PARAMS:
+            raise ValueError("mlp must hold 4801 weights")
+        p = _Params(wps_mode, hop_limit, settle_limit, max_rounds,
+                    PRIO_LEARNED if wts is not None else PRIO_PLAIN, int(record), _p(wts))
         h = C.c_void_p()
         rc = L.orc_create(n, len(dst), _p(off), _p(dst), _p(w), _p(lab), seed,
                           C.byref(p), C.byref(h))
@@ -152,6 +170,13 @@ class OracleCH:
         if getattr(self, "h", None) and _lib is not None:
             _lib.orc_free(self.h)
             self.h = None
+
+    def features(self):
+        x = np.empty((self.n, 8), np.float32)
+        rc = lib().orc_get_features(self.h, _p(x))
+        if rc:
+            raise OracleError(rc, "orc_get_features")
+        return x
 
     def round(self) -> int:
         rc = lib().orc_round(self.h)
@@ -263,6 +288,19 @@ def dijkstra(off, dst, w, s):
     if rc:
         raise OracleError(rc, "orc_dijkstra")
     return d
+
+
+def mlp_priority(w, x):
+    """(priority, output y) of the learned priority for one feature vector."""
+    w = np.ascontiguousarray(w, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    y = C.c_float()
+    p = lib().orc_mlp_priority(_p(w), _p(x), C.byref(y))
+    return p, y.value
+
+
+def gelu(x):
+    return lib().orc_gelu(float(x))
 
 
 def default_label(v, seed):

@@ -26,6 +26,7 @@
  */
 #include "spoch_oracle.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -276,6 +277,14 @@ struct orc_state {
   orc_round_stats *stats;
   uint32_t nstats, capstats;
 
+  /* learned priority: per-vertex feature state */
+  float *mlp;        /* ORC_MLP_PARAMS weights, or NULL */
+  uint32_t *cn;      /* contracted neighbours so far */
+  uint32_t *depth;   /* hierarchy depth: max over contracted neighbours + 1 */
+  uint32_t *ws;      /* vertices reached by this vertex's latest witness search */
+  float *feat;       /* current features, 8 per vertex */
+  float *rec;        /* features at contraction (params.record) */
+
   int finished;
   uint32_t *rank;
   /* CH in rank space for queries */
@@ -348,6 +357,12 @@ void orc_free(orc_state *st) {
   free(st->qdf);
   free(st->qdb);
   free(st->qtouch);
+  free(st->mlp);
+  free(st->cn);
+  free(st->depth);
+  free(st->ws);
+  free(st->feat);
+  free(st->rec);
   free(st);
 }
 
@@ -364,6 +379,8 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
   if (p->wps_mode > ORC_WPS_SETTLED) return ORC_E_INVALID;
   if (p->wps_mode == ORC_WPS_HOP && p->hop_limit < 1) return ORC_E_INVALID;
   if (p->wps_mode == ORC_WPS_SETTLED && p->settle_limit < 1) return ORC_E_INVALID;
+  if (p->priority > ORC_PRIO_LEARNED || (p->priority == ORC_PRIO_LEARNED && !p->mlp))
+    return ORC_E_INVALID;
   if (n > 0 && (off[0] != 0 || off[n] != m)) return ORC_E_INVALID;
   for (uint32_t v = 0; v < n; v++)
     if (off[v] > off[v + 1]) return ORC_E_INVALID;
@@ -391,9 +408,20 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
   st->stamp2 = (uint32_t *)calloc(nn, sizeof(uint32_t));
   st->list1 = (uint32_t *)malloc(nn * sizeof(uint32_t));
   st->list2 = (uint32_t *)malloc(nn * sizeof(uint32_t));
+  st->cn = (uint32_t *)calloc(nn, sizeof(uint32_t));
+  st->depth = (uint32_t *)calloc(nn, sizeof(uint32_t));
+  st->ws = (uint32_t *)calloc(nn, sizeof(uint32_t));
+  st->feat = (float *)calloc(nn * 8, sizeof(float));
+  if (p->record) st->rec = (float *)calloc(nn * 8, sizeof(float));
+  if (p->priority == ORC_PRIO_LEARNED) {
+    st->mlp = (float *)malloc(ORC_MLP_PARAMS * sizeof(float));
+    if (st->mlp) memcpy(st->mlp, p->mlp, ORC_MLP_PARAMS * sizeof(float));
+  }
   if (!st->label || !st->out || !st->in || !st->alive || !st->P || !st->Pc ||
       !st->level || !st->VW || !st->VA || !st->dist || !st->dist2 ||
-      !st->touched || !st->stamp || !st->stamp2 || !st->list1 || !st->list2) {
+      !st->touched || !st->stamp || !st->stamp2 || !st->list1 || !st->list2 || !st->cn ||
+      !st->depth || !st->ws || !st->feat || (p->record && !st->rec) ||
+      (p->priority == ORC_PRIO_LEARNED && !st->mlp)) {
     orc_free(st);
     return ORC_E_OOM;
   }
@@ -637,6 +665,7 @@ static int local_search(orc_state *st, orc_round_stats *rs) {
       rc = wps_settled(st, s, D, st->p.settle_limit, nt, tst, &settled);
     }
     rs->n_settled += settled;
+    st->ws[s] = (uint32_t)(settled > 0xFFFFFFFFull ? 0xFFFFFFFFull : settled);
     for (uint32_t k = 0; k < nt && rc == ORC_OK; k++) {
       uint32_t v = targets[k];
       uint64_t d = (st->p.wps_mode == ORC_WPS_SETTLED) ? st->dist2[v] : st->dist[v];
@@ -689,6 +718,76 @@ static uint32_t neighbour_count(orc_state *st, uint32_t u) {
   return c;
 }
 
+/* ---- learned priority ------------------------------------------------
+ * READING (the learned priority is not in the paper): the priority is an MLP
+ * over eight features of the vertex, each squashed to [0, 1) (or (-1, 1))
+ * by x / (x + c):
+ *   0 edge difference (signed: x / (|x| + 8))   1 contracted neighbours
+ *   2 live in-degree   3 live out-degree          4 hierarchy depth
+ *   5 vertices reached by the vertex's latest witness search (c = 64)
+ *   6 |N(u)|           7 pairs that need a shortcut
+ * GELU uses tanh through its [7/6] Pade approximant (Lambert's continued
+ * fraction), set to +-1 for |t| >= 4.97.  Everything is single precision,
+ * evaluated left to right as written, with no fused multiply-add, so any
+ * IEEE implementation gives the same bits.  The priority is the output
+ * times 2^16, rounded to nearest even and saturated to int32. */
+static float tanh_pade(float t) {
+  if (t >= 4.97f) return 1.0f;
+  if (t <= -4.97f) return -1.0f;
+  float t2 = t * t;
+  float num = t * (135135.0f + t2 * (17325.0f + t2 * (378.0f + t2)));
+  float den = 135135.0f + t2 * (62370.0f + t2 * (3150.0f + t2 * 28.0f));
+  float r = num / den;
+  if (r > 1.0f) r = 1.0f;
+  if (r < -1.0f) r = -1.0f;
+  return r;
+}
+
+float orc_gelu(float x) {
+  float x3 = (x * x) * x;
+  float inner = x + 0.044715f * x3;
+  float t = 0.7978845608f * inner;
+  return (0.5f * x) * (1.0f + tanh_pade(t));
+}
+
+int32_t orc_mlp_priority(const float *w, const float *x, float *y_out) {
+  const float *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *W3 = w + 4736,
+              *b3 = w + 4800;
+  float a1[64], a2[64];
+  for (int j = 0; j < 64; j++) {
+    float h = b1[j];
+    for (int i = 0; i < 8; i++) h = h + W1[j * 8 + i] * x[i];
+    a1[j] = orc_gelu(h);
+  }
+  for (int j = 0; j < 64; j++) {
+    float h = b2[j];
+    for (int i = 0; i < 64; i++) h = h + W2[j * 64 + i] * a1[i];
+    a2[j] = orc_gelu(h);
+  }
+  float y = b3[0];
+  for (int i = 0; i < 64; i++) y = y + W3[i] * a2[i];
+  if (y_out) *y_out = y;
+  float z = y * 65536.0f;
+  if (!(z < 2147483648.0f)) return INT32_MAX; /* also NaN */
+  if (z < -2147483648.0f) return INT32_MIN;
+  return (int32_t)rintf(z);
+}
+
+static float squash(uint64_t x, float c) { return (float)x / ((float)x + c); }
+
+static void vertex_features(const orc_state *st, uint32_t u, int32_t ed, uint32_t din,
+                            uint32_t dout, uint32_t nb, uint32_t pairs, float *f) {
+  uint64_t mag = ed < 0 ? (uint64_t)(-(int64_t)ed) : (uint64_t)ed;
+  f[0] = (float)ed / ((float)mag + 8.0f);
+  f[1] = squash(st->cn[u], 8.0f);
+  f[2] = squash(din, 8.0f);
+  f[3] = squash(dout, 8.0f);
+  f[4] = squash(st->depth[u], 8.0f);
+  f[5] = squash(st->ws[u], 64.0f);
+  f[6] = squash(nb, 8.0f);
+  f[7] = squash(pairs, 8.0f);
+}
+
 /* Alg. 4: P[u] = -|N(u)| + number of pairs (v1, v2) in N_in(u) x N_out(u)
  * whose path through u is no longer than the memoized distance, or whose
  * distance is not memoized.  READING: pairs with v1 == v2 are skipped (a
@@ -697,7 +796,9 @@ static uint32_t neighbour_count(orc_state *st, uint32_t u) {
 static void score(orc_state *st, orc_round_stats *rs) {
   for (uint32_t i = 0; i < st->nVA; i++) {
     uint32_t u = st->VA[i];
-    int64_t p = -(int64_t)neighbour_count(st, u);
+    uint32_t nb = neighbour_count(st, u);
+    int64_t p = -(int64_t)nb;
+    uint32_t pairs = 0;
     adj_t *li = &st->in[u], *lo = &st->out[u];
     for (uint32_t a = 0; a < li->n; a++) {
       for (uint32_t b = 0; b < lo->n; b++) {
@@ -707,8 +808,10 @@ static void score(orc_state *st, orc_round_stats *rs) {
         if (!pm_get(&st->memo, v1, v2, &d)) {
           rs->n_absent++;
           p++;
+          pairs++;
         } else if (via <= d) {
           p++;
+          pairs++;
         }
       }
     }
@@ -716,7 +819,9 @@ static void score(orc_state *st, orc_round_stats *rs) {
      * above ~46k) saturates. */
     if (p > INT32_MAX) p = INT32_MAX;
     if (p < INT32_MIN) p = INT32_MIN;
-    st->P[u] = (int32_t)p;
+    float *f = &st->feat[(size_t)u * 8];
+    vertex_features(st, u, (int32_t)p, li->n, lo->n, nb, pairs, f);
+    st->P[u] = st->mlp ? orc_mlp_priority(st->mlp, f, NULL) : (int32_t)p;
   }
 }
 
@@ -771,6 +876,26 @@ static int contract(orc_state *st, const uint32_t *VF, uint32_t nF, orc_round_st
     adj_t *li = &st->in[u], *lo = &st->out[u];
     st->level[u] = r;
     st->Pc[u] = st->P[u];
+    if (st->rec) memcpy(&st->rec[(size_t)u * 8], &st->feat[(size_t)u * 8], 8 * sizeof(float));
+    /* feature state of the neighbours: one more contracted neighbour each,
+     * depth at least depth(u) + 1 */
+    {
+      uint32_t sv = next_stamp(st->stamp2, &st->stamp2v, st->n);
+      for (uint32_t b = 0; b < lo->n; b++) {
+        uint32_t v = lo->a[b].v;
+        if (st->stamp2[v] == sv) continue;
+        st->stamp2[v] = sv;
+        st->cn[v]++;
+        if (st->depth[v] < st->depth[u] + 1) st->depth[v] = st->depth[u] + 1;
+      }
+      for (uint32_t a = 0; a < li->n; a++) {
+        uint32_t v = li->a[a].v;
+        if (st->stamp2[v] == sv) continue;
+        st->stamp2[v] = sv;
+        st->cn[v]++;
+        if (st->depth[v] < st->depth[u] + 1) st->depth[v] = st->depth[u] + 1;
+      }
+    }
     /* incident arcs move to the CH: out-arcs to the upward set, in-arcs to
      * the downward set */
     for (uint32_t b = 0; b < lo->n && rc == ORC_OK; b++)
@@ -1258,6 +1383,12 @@ void orc_get_vertex_state(const orc_state *st, uint32_t *level, int32_t *pc,
 int orc_get_rank(const orc_state *st, uint32_t *rank) {
   if (!st->finished) return ORC_E_STATE;
   memcpy(rank, st->rank, (size_t)st->n * sizeof(uint32_t));
+  return ORC_OK;
+}
+
+int orc_get_features(const orc_state *st, float *x) {
+  if (!st->rec) return ORC_E_STATE;
+  memcpy(x, st->rec, (size_t)st->n * 8 * sizeof(float));
   return ORC_OK;
 }
 

@@ -39,11 +39,26 @@ enum {
   ORC_WPS_SETTLED = 2  /* Dijkstra stopped after settle_limit pops         */
 };
 
+/* Priority functions. */
+enum {
+  ORC_PRIO_PLAIN = 0,   /* edge difference (Alg. 4)                       */
+  ORC_PRIO_LEARNED = 1  /* MLP over per-vertex features (see below)       */
+};
+
+/* The learned priority is an MLP 8 -> 64 -> 64 -> 1 with GELU, evaluated in
+ * IEEE single precision in a fixed order without fused multiply-add.  Its
+ * 4801 weights are laid out as W1[64][8], b1[64], W2[64][64], b2[64],
+ * W3[64], b3. */
+#define ORC_MLP_PARAMS 4801
+
 typedef struct {
   uint32_t wps_mode;
   uint32_t hop_limit;    /* ORC_WPS_HOP: H >= 1                          */
   uint32_t settle_limit; /* ORC_WPS_SETTLED: theta >= 1                  */
   uint32_t max_rounds;   /* 0: no limit                                  */
+  uint32_t priority;     /* ORC_PRIO_PLAIN or ORC_PRIO_LEARNED            */
+  uint32_t record;       /* keep each vertex's features at contraction   */
+  const float *mlp;      /* ORC_MLP_PARAMS weights (learned priority)    */
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -91,6 +106,12 @@ void orc_get_labels(const orc_state *st, uint32_t *label);
  * contraction Pc[v], current score P[v], alive flag. */
 void orc_get_vertex_state(const orc_state *st, uint32_t *level, int32_t *pc,
                           int32_t *p, uint8_t *alive);
+/* Features (8 floats per vertex) each vertex had when it was contracted
+ * (needs params.record). */
+int orc_get_features(const orc_state *st, float *x);
+/* MLP helpers: the features -> priority map used by the learned priority. */
+int32_t orc_mlp_priority(const float *w, const float *x, float *y_out);
+float orc_gelu(float x);
 /* rank[v] after orc_finish. */
 int orc_get_rank(const orc_state *st, uint32_t *rank);
 
