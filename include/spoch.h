@@ -94,8 +94,37 @@ typedef struct {
   uint32_t ls_sparse;
   uint32_t ls_dense;
   uint32_t dense_deg10;
-  uint32_t reserved;   /* must be 0 */
+  uint32_t priority;   /* CH_PRIO_PLAIN (edge difference, Alg. 4) or CH_PRIO_LEARNED */
+  const float *mlp;    /* CH_PRIO_LEARNED: CH_MLP_PARAMS weights, host memory      */
 } ch_params_t;
+
+/* ---- learned priority ----
+ * An MLP 8 -> 64 -> 64 -> 1 with GELU maps eight features of a rescored
+ * vertex to its priority (replacing the edge difference; Select and the rest
+ * of the round are unchanged, so distances stay exact).  Features, each
+ * squashed as x / (x + c): 0 edge difference (signed, x / (|x| + 8)),
+ * 1 contracted neighbours, 2 live in-degree, 3 live out-degree, 4 hierarchy
+ * depth (max over contracted neighbours of their depth + 1), 5 vertices
+ * reached by the vertex's latest witness search (c = 64), 6 |N(u)|, 7 pairs
+ * needing a shortcut; c = 8 unless stated.  GELU(x) = x/2 (1 + T(0.7978845608
+ * (x + 0.044715 x^3))), T the [7/6] Pade approximant of tanh, +-1 for
+ * |t| >= 4.97.  Evaluated in single precision in a fixed order without fused
+ * multiply-add; priority = output x 2^16 rounded to nearest even, saturated
+ * to int32.  Weights: W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3. */
+#define CH_PRIO_PLAIN 0u
+#define CH_PRIO_LEARNED 1u
+#define CH_MLP_PARAMS 4801
+#define CH_F_RECORD_FEATURES 0x8u /* keep each vertex's features at contraction */
+
+#define CH_MLP_ON_DEVICE 0x1u     /* x, t, y, prio are device pointers */
+#define CH_MLP_BF16 0x2u          /* forward with bf16 weights and activations */
+
+typedef struct {
+  uint32_t batch;  /* samples per step (<= 2^20), drawn with replacement */
+  uint32_t steps;  /* Adam steps */
+  float lr, beta1, beta2, eps;
+  uint64_t seed;   /* sample-index generator seed */
+} ch_mlp_train_params_t;
 
 #define CH_LS_AUTO 0u
 #define CH_LS_16x128 1u
@@ -200,6 +229,34 @@ int ch_get_summary(const ch_t *ch, ch_summary_t *out);
 
 /* Copy min(cap, rounds) per-round records (filled only with CH_F_STATS). */
 int ch_get_round_stats(const ch_t *ch, ch_round_stats_t *out, uint32_t cap);
+
+/* Features (8 floats per vertex, original ids) each vertex had when it was
+ * contracted; needs CH_F_RECORD_FEATURES at build time.  x: n*8 host floats.
+ * Errors: CH_E_INVALID (NULL, or built without recording). */
+int ch_export_features(const ch_t *ch, float *x);
+
+/* The network on n feature vectors: y[i] (output, may be NULL) and prio[i]
+ * (the int32 priority, may be NULL).  x: n*8 floats; w: CH_MLP_PARAMS
+ * weights; host arrays, or device arrays with CH_MLP_ON_DEVICE.  With
+ * CH_MLP_BF16 weights, inputs and activations are rounded to bf16
+ * (accumulation stays fp32).  Errors: CH_E_INVALID, CH_E_OOM, CH_E_DEVICE. */
+int ch_mlp_forward(const float *x, uint64_t n, const float *w, float *y, int32_t *prio,
+                   uint32_t flags, void *stream);
+
+/* Gradient of the mean squared error (1/n) sum (f(x_i) - t_i)^2 over all n
+ * samples with respect to the weights: grad (CH_MLP_PARAMS host floats),
+ * loss (host float, may be NULL).  Sums run in sample order (deterministic).
+ * x (n*8), t (n): host, or device with CH_MLP_ON_DEVICE; w host. */
+int ch_mlp_grad(const float *x, const float *t, uint32_t n, const float *w, float *grad,
+                float *loss, uint32_t flags, void *stream);
+
+/* Adam on the mean squared error, minibatches drawn with replacement by a
+ * counter-based generator (splitmix64 of seed and sample counter).  w (host,
+ * CH_MLP_PARAMS) holds the initial weights and receives the trained ones;
+ * losses (host, p->steps floats, may be NULL) receives each step's batch
+ * loss.  Deterministic for given inputs. */
+int ch_mlp_train(const float *x, const float *t, uint64_t n, float *w,
+                 const ch_mlp_train_params_t *p, float *losses, uint32_t flags, void *stream);
 
 /* Release a CH (NULL is ignored). */
 void ch_free(ch_t *ch);

@@ -131,6 +131,8 @@ def lib():
         L.orc_mlp_priority.restype = C.c_int32
         L.orc_gelu.argtypes = [C.c_float]
         L.orc_gelu.restype = C.c_float
+        L.orc_load.argtypes = [u32, vp, u64, vp, vp, vp, u64, vp, vp, vp, C.POINTER(vp)]
+        L.orc_load.restype = i32
         _lib = L
     return _lib
 
@@ -277,6 +279,24 @@ class OracleCH:
         if rc:
             raise OracleError(rc, "orc_overlay_dijkstra")
         return d
+
+
+class LoadedCH(OracleCH):
+    """A finished CH given by its rank order and arc lists (queries only)."""
+
+    def __init__(self, rank, up_tail, up_head, up_w, down_tail, down_head, down_w):
+        L = lib()
+        arrs = [np.ascontiguousarray(a, np.uint32) for a in
+                (rank, up_tail, up_head, up_w, down_tail, down_head, down_w)]
+        self._keep = arrs
+        r, ut, uh, uw, dt, dh, dw = arrs
+        h = C.c_void_p()
+        rc = L.orc_load(len(r), _p(r), len(ut), _p(ut), _p(uh), _p(uw), len(dt), _p(dt), _p(dh),
+                        _p(dw), C.byref(h))
+        if rc != ORC_OK:
+            raise OracleError(rc, "orc_load")
+        self.h = h
+        self.n = len(r)
 
 
 def dijkstra(off, dst, w, s):

@@ -1149,6 +1149,61 @@ int orc_finish(orc_state *st) {
   return ORC_OK;
 }
 
+int orc_load(uint32_t n, const uint32_t *rank, uint64_t nup, const uint32_t *up_tail,
+             const uint32_t *up_head, const uint32_t *up_w, uint64_t ndown,
+             const uint32_t *dn_tail, const uint32_t *dn_head, const uint32_t *dn_w,
+             orc_state **out) {
+  if (!out || (n && !rank)) return ORC_E_INVALID;
+  orc_state *st = (orc_state *)calloc(1, sizeof(orc_state));
+  if (!st) return ORC_E_OOM;
+  st->n = n;
+  size_t nn = n ? n : 1;
+  st->rank = (uint32_t *)malloc(nn * sizeof(uint32_t));
+  st->upoff = (uint64_t *)calloc(nn + 1, sizeof(uint64_t));
+  st->dnoff = (uint64_t *)calloc(nn + 1, sizeof(uint64_t));
+  st->uphead = (uint32_t *)malloc((nup ? nup : 1) * sizeof(uint32_t));
+  st->upw = (uint32_t *)malloc((nup ? nup : 1) * sizeof(uint32_t));
+  st->dntail = (uint32_t *)malloc((ndown ? ndown : 1) * sizeof(uint32_t));
+  st->dnw = (uint32_t *)malloc((ndown ? ndown : 1) * sizeof(uint32_t));
+  st->qdf = (uint64_t *)malloc(nn * sizeof(uint64_t));
+  st->qdb = (uint64_t *)malloc(nn * sizeof(uint64_t));
+  st->qtouch = (uint32_t *)malloc(2 * nn * sizeof(uint32_t));
+  uint64_t *pu = (uint64_t *)malloc(nn * sizeof(uint64_t));
+  uint64_t *pd = (uint64_t *)malloc(nn * sizeof(uint64_t));
+  if (!st->rank || !st->upoff || !st->dnoff || !st->uphead || !st->upw || !st->dntail ||
+      !st->dnw || !st->qdf || !st->qdb || !st->qtouch || !pu || !pd) {
+    free(pu);
+    free(pd);
+    orc_free(st);
+    return ORC_E_OOM;
+  }
+  memcpy(st->rank, rank, (size_t)n * sizeof(uint32_t));
+  for (uint64_t i = 0; i < nup; i++) st->upoff[st->rank[up_tail[i]] + 1]++;
+  for (uint64_t i = 0; i < ndown; i++) st->dnoff[st->rank[dn_head[i]] + 1]++;
+  for (uint32_t v = 0; v < n; v++) {
+    st->upoff[v + 1] += st->upoff[v];
+    st->dnoff[v + 1] += st->dnoff[v];
+  }
+  memcpy(pu, st->upoff, nn * sizeof(uint64_t));
+  memcpy(pd, st->dnoff, nn * sizeof(uint64_t));
+  for (uint64_t i = 0; i < nup; i++) {
+    uint64_t at = pu[st->rank[up_tail[i]]]++;
+    st->uphead[at] = st->rank[up_head[i]];
+    st->upw[at] = up_w[i];
+  }
+  for (uint64_t i = 0; i < ndown; i++) {
+    uint64_t at = pd[st->rank[dn_head[i]]]++;
+    st->dntail[at] = st->rank[dn_tail[i]];
+    st->dnw[at] = dn_w[i];
+  }
+  free(pu);
+  free(pd);
+  for (uint32_t v = 0; v < n; v++) st->qdf[v] = st->qdb[v] = INF64;
+  st->finished = 1;
+  *out = st;
+  return ORC_OK;
+}
+
 int orc_run(orc_state *st) {
   int rc;
   while ((rc = orc_round(st)) == 1) {

@@ -144,6 +144,14 @@ uint64_t orc_query(orc_state *st, uint32_t s, uint32_t t, uint64_t *settled);
 int orc_query_batch(orc_state *st, uint64_t q, const uint32_t *s, const uint32_t *t,
                     uint64_t *dist, uint64_t *settled);
 
+/* A finished CH given by its rank order and arc lists (as exported), for
+ * queries only: upward arcs (tail -> head) with rank(tail) < rank(head),
+ * downward arcs (tail -> head) with rank(tail) > rank(head). */
+int orc_load(uint32_t n, const uint32_t *rank, uint64_t nup, const uint32_t *up_tail,
+             const uint32_t *up_head, const uint32_t *up_w, uint64_t ndown,
+             const uint32_t *dn_tail, const uint32_t *dn_head, const uint32_t *dn_w,
+             orc_state **out);
+
 /* Plain Dijkstra on a CSR graph: dist[v] for all v (UINT64_MAX unreachable). */
 int orc_dijkstra(uint32_t n, const uint64_t *off, const uint32_t *dst,
                  const uint32_t *w, uint32_t s, uint64_t *dist);

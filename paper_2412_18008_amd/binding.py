@@ -31,7 +31,8 @@ CH_F_NO_QUERY_INDEX = 0x4
 CH_Q_ON_DEVICE = 0x1
 
 EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
-            "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version")
+            "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version", "ch_export_features",
+            "ch_mlp_forward", "ch_mlp_grad", "ch_mlp_train")
 
 
 class ChError(RuntimeError):
@@ -49,7 +50,19 @@ class Params(C.Structure):
     _fields_ = [("wps_mode", C.c_uint32), ("max_rounds", C.c_uint32), ("seed", C.c_uint64),
                 ("flags", C.c_uint32), ("group", C.c_uint32), ("stream", C.c_void_p),
                 ("ls_sparse", C.c_uint32), ("ls_dense", C.c_uint32),
-                ("dense_deg10", C.c_uint32), ("reserved", C.c_uint32)]
+                ("dense_deg10", C.c_uint32), ("priority", C.c_uint32), ("mlp", C.c_void_p)]
+
+
+CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
+CH_MLP_PARAMS = 4801
+CH_F_RECORD_FEATURES = 0x8
+CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
+
+
+class MlpTrainParams(C.Structure):
+    _fields_ = [("batch", C.c_uint32), ("steps", C.c_uint32), ("lr", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("seed", C.c_uint64)]
 
 
 CH_LS_AUTO, CH_LS_16x128, CH_LS_32x512, CH_LS_64x512, CH_LS_64x2048 = 0, 1, 2, 3, 4
@@ -104,6 +117,14 @@ def lib():
         L.ch_last_error.restype = C.c_char_p
         L.ch_version.argtypes = []
         L.ch_version.restype = C.c_char_p
+        L.ch_export_features.argtypes = [vp, vp]
+        L.ch_export_features.restype = i32
+        L.ch_mlp_forward.argtypes = [vp, u64, vp, vp, vp, u32, vp]
+        L.ch_mlp_forward.restype = i32
+        L.ch_mlp_grad.argtypes = [vp, vp, u32, vp, vp, vp, u32, vp]
+        L.ch_mlp_grad.restype = i32
+        L.ch_mlp_train.argtypes = [vp, vp, u64, vp, C.POINTER(MlpTrainParams), vp, u32, vp]
+        L.ch_mlp_train.restype = i32
         _lib = L
     return _lib
 
@@ -179,6 +200,12 @@ class CH:
         _check(lib().ch_export(self.h, *[out[k].ctypes.data for k in order]), "ch_export")
         return out
 
+    def features(self):
+        """Features (n x 8 float32) each vertex had when it was contracted."""
+        x = np.empty((self.n, 8), np.float32)
+        _check(lib().ch_export_features(self.h, x.ctypes.data), "ch_export_features")
+        return x
+
     def round_stats(self):
         k = self.summary["rounds"]
         arr = (RoundStats * max(k, 1))()
@@ -188,7 +215,8 @@ class CH:
 
 
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
-          query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0):
+          query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
+          record=False):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
@@ -199,13 +227,17 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     m = dst.numel() if dev else len(kd)
     g = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (CH_F_STATS if stats else 0) | (
-        0 if query_index else CH_F_NO_QUERY_INDEX)
+        0 if query_index else CH_F_NO_QUERY_INDEX) | (CH_F_RECORD_FEATURES if record else 0)
     if stream is None and dev:
         import torch
 
         stream = torch.cuda.current_stream().cuda_stream
+    wts = None if mlp is None else np.ascontiguousarray(mlp, np.float32)
+    if wts is not None and wts.size != CH_MLP_PARAMS:
+        raise ValueError("mlp must hold 4801 weights")
     p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream, ls_sparse, ls_dense,
-               dense_deg10, 0)
+               dense_deg10, CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
+               None if wts is None else wts.ctypes.data)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
@@ -229,10 +261,46 @@ def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=
         m = dst.numel() if dev else len(kd)
         arr[i] = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX)
-    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream, 0, 0, 0, 0)
+    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream, 0, 0, 0, CH_PRIO_PLAIN,
+               None)
     outs = (C.c_void_p * max(k, 1))()
     _check(lib().ch_build_batch(arr, k, C.byref(p), outs), "ch_build_batch")
     return [CH(C.c_void_p(outs[i])) for i in range(k)]
+
+
+def mlp_forward(x, w, bf16=False):
+    """(y, priority) of the learned priority's network on n x 8 features."""
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, 8)
+    w = np.ascontiguousarray(w, np.float32)
+    y = np.empty(len(x), np.float32)
+    p = np.empty(len(x), np.int32)
+    _check(lib().ch_mlp_forward(x.ctypes.data, len(x), w.ctypes.data, y.ctypes.data,
+                                p.ctypes.data, CH_MLP_BF16 if bf16 else 0, None), "ch_mlp_forward")
+    return y, p
+
+
+def mlp_grad(x, t, w):
+    """(gradient, loss) of the mean squared error over all samples."""
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, 8)
+    t = np.ascontiguousarray(t, np.float32)
+    w = np.ascontiguousarray(w, np.float32)
+    g = np.empty(CH_MLP_PARAMS, np.float32)
+    loss = C.c_float()
+    _check(lib().ch_mlp_grad(x.ctypes.data, t.ctypes.data, len(x), w.ctypes.data, g.ctypes.data,
+                             C.byref(loss), 0, None), "ch_mlp_grad")
+    return g, loss.value
+
+
+def mlp_train(x, t, w, batch=1024, steps=500, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
+    """Adam on the GPU; returns (trained weights, per-step batch losses)."""
+    x = np.ascontiguousarray(x, np.float32).reshape(-1, 8)
+    t = np.ascontiguousarray(t, np.float32)
+    w = np.array(w, np.float32, copy=True)
+    losses = np.empty(steps, np.float32)
+    p = MlpTrainParams(batch, steps, lr, beta1, beta2, eps, seed)
+    _check(lib().ch_mlp_train(x.ctypes.data, t.ctypes.data, len(x), w.ctypes.data, C.byref(p),
+                              losses.ctypes.data, 0, None), "ch_mlp_train")
+    return w, losses
 
 
 def version():

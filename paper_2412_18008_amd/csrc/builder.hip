@@ -9,6 +9,7 @@
 #include <string>
 
 #include "builder.hpp"
+#include "mlp.hpp"
 #include "round_kernels.hpp"
 
 namespace sp {
@@ -82,6 +83,7 @@ struct Builder {
   DBuf aflag, aflag_next, wflag, F, S, newA, key, paircnt, newid, cnt, vw, va, vf;
   DBuf memo, alive_g;
   uint64_t mcap = 0, mcount = 0;
+  DBuf f_cn, f_depth, f_ws, f_feat, mlpw;  // learned-priority feature state
   DBuf cup, cdn, cpair;
   DBuf ekey, ekey_alt, eidx, eidx_alt, ew, elab, emid, ehead, eheads, ukey, uw, umid, rkey,
       rkey_alt, ridx, ridx_alt;
@@ -107,7 +109,8 @@ struct Builder {
     DBuf *all[] = {&aflag, &aflag_next, &wflag, &F, &S, &newA, &key, &paircnt, &newid, &cnt,
                    &vw, &va, &vf, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
-                   &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp};
+                   &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
+                   &f_cn, &f_depth, &f_ws, &f_feat, &mlpw};
     for (DBuf *b : all) b->release();
     if (hctr) (void)hipHostFree(hctr);
     for (auto &e : ev)
@@ -115,6 +118,16 @@ struct Builder {
   }
 
   DevCtr *dc() { return dctr.as<DevCtr>(); }
+
+  FeatState fstate() {
+    FeatState f;
+    f.cn = f_cn.as<uint32_t>();
+    f.depth = f_depth.as<uint32_t>();
+    f.ws = f_ws.as<uint32_t>();
+    f.feat = f_feat.as<float>();
+    f.rec = (prm.flags & CH_F_RECORD_FEATURES) ? ch->rec.as<float>() : nullptr;
+    return f;
+  }
 
   unsigned grid(uint64_t items, unsigned block = 256) const {
     uint64_t g = (items + block - 1) / block;
@@ -329,13 +342,13 @@ struct Builder {
         v, list, nl, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1,
         tier == 1 ? &d->ls : &d->ls2, nl_dev, tier == 1 ? &d->work1 : &d->work2,
         tier == 1 ? ovf1.as<uint32_t>() : ovf2.as<uint32_t>(), tier == 1 ? &d->novf1 : &d->novf2,
-        chunk, &d->err);
+        chunk, f_ws.as<uint32_t>(), &d->err);
   }
   template <int G>
   void launch_score(const Overlay &v, uint32_t na) {
     k_score<G><<<ggrid<G>(na), 256, 0, st>>>(v, va.as<uint32_t>(), na, memo.as<MemoSlot>(),
                                               mcap / kMemoBucket - 1, ov[cur].P.as<int32_t>(),
-                                              paircnt.as<uint32_t>());
+                                              paircnt.as<uint32_t>(), fstate());
   }
   template <int G>
   void launch_prune(const Overlay &v, uint32_t nw) {
@@ -365,7 +378,7 @@ struct Builder {
         alive_g.as<uint8_t>(), cup.as<uint32_t>() + nf, cdn.as<uint32_t>() + nf,
         cpair.as<uint32_t>() + nf, up, dn, ch->nup, ch->ndown, cpair.as<uint32_t>(), kb,
         ekey.as<uint64_t>(), ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(),
-        S.as<uint8_t>(), newA.as<uint8_t>(), &dc()->err);
+        S.as<uint8_t>(), newA.as<uint8_t>(), fstate(), &dc()->err);
   }
 
   static int pick_group(double work) {
@@ -407,6 +420,23 @@ struct Builder {
     HIP_TRY(fill_u32(ch->level.as<uint32_t>(), SP_INF32, n, st));
     HIP_TRY(hipMemsetAsync(ch->score.p, 0, (size_t)n * 4, st));
     HIP_TRY(fill_u8(alive_g.as<uint8_t>(), 1, n, st));
+    HIP_TRY(f_cn.ensure(std::max<uint64_t>(n, 1) * 4));
+    HIP_TRY(f_depth.ensure(std::max<uint64_t>(n, 1) * 4));
+    HIP_TRY(f_ws.ensure(std::max<uint64_t>(n, 1) * 4));
+    HIP_TRY(f_feat.ensure(std::max<uint64_t>(n, 1) * 32));
+    HIP_TRY(hipMemsetAsync(f_cn.p, 0, (size_t)n * 4, st));
+    HIP_TRY(hipMemsetAsync(f_depth.p, 0, (size_t)n * 4, st));
+    HIP_TRY(hipMemsetAsync(f_ws.p, 0, (size_t)n * 4, st));
+    HIP_TRY(hipMemsetAsync(f_feat.p, 0, (size_t)n * 32, st));
+    if (prm.flags & CH_F_RECORD_FEATURES) {
+      HIP_TRY(ch->rec.ensure(std::max<uint64_t>(n, 1) * 32));
+      HIP_TRY(hipMemsetAsync(ch->rec.p, 0, (size_t)n * 32, st));
+      ch->has_rec = true;
+    }
+    if (prm.priority == CH_PRIO_LEARNED) {
+      HIP_TRY(mlpw.ensure(kMlpParams * 4));
+      HIP_TRY(hipMemcpyAsync(mlpw.p, prm.mlp, kMlpParams * 4, hipMemcpyHostToDevice, st));
+    }
     const size_t nn = std::max<uint64_t>(n, 1);
     HIP_TRY(aflag.ensure(nn));
     HIP_TRY(aflag_next.ensure(nn));
@@ -504,7 +534,8 @@ struct Builder {
           }
           k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
               v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
-              mcap / kMemoBucket - 1, &dc()->ls2, gtabs.as<uint32_t>(), cap, &dc()->err);
+              mcap / kMemoBucket - 1, &dc()->ls2, gtabs.as<uint32_t>(), cap, f_ws.as<uint32_t>(),
+              &dc()->err);
           HIP_TRY(hipGetLastError());
         }
         TRY(readback());
@@ -527,6 +558,10 @@ struct Builder {
                  [&] { launch_score<16>(v, na); }, [&] { launch_score<32>(v, na); },
                  [&] { launch_score<64>(v, na); });
         HIP_TRY(hipGetLastError());
+        if (prm.priority == CH_PRIO_LEARNED)
+          HIP_TRY(launch_mlp_priority(va.as<uint32_t>(), na, O.gid.as<uint32_t>(),
+                                      f_feat.as<float>(), mlpw.as<float>(), O.P.as<int32_t>(),
+                                      cus, st));
       }
 
       // ---- Step 3: Select (Alg. 5) -------------------------------------
@@ -741,7 +776,9 @@ static int check_params(const ch_params_t *p, ch_params_t &prm) {
     return set_error(CH_E_INVALID, "group must be 0, 4, 8, 16, 32 or 64");
   if (prm.ls_sparse > CH_LS_64x2048 || prm.ls_dense > CH_LS_64x2048)
     return set_error(CH_E_INVALID, "unknown first-tier search kernel");
-  if (prm.reserved) return set_error(CH_E_INVALID, "reserved must be 0");
+  if (prm.priority > CH_PRIO_LEARNED) return set_error(CH_E_INVALID, "unknown priority");
+  if (prm.priority == CH_PRIO_LEARNED && !prm.mlp)
+    return set_error(CH_E_INVALID, "the learned priority needs mlp weights");
   return CH_OK;
 }
 
@@ -849,6 +886,8 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
   if (!gs || !outs || k == 0) return set_error(CH_E_INVALID, "graphs and outs must not be NULL");
   ch_params_t prm;
   TRY(check_params(p, prm));
+  if (prm.flags & CH_F_RECORD_FEATURES)
+    return set_error(CH_E_UNSUPPORTED, "feature recording is not available for batches");
   const bool on_dev = prm.flags & CH_F_INPUT_ON_DEVICE;
   std::vector<uint32_t> vb(k + 1, 0);
   std::vector<uint64_t> ab(k + 1, 0);
@@ -1091,7 +1130,7 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
 ch_s::~ch_s() {
   sp::DBuf *all[] = {&level, &score, &label, &rank, &up_t, &up_h, &up_w, &up_m, &dn_t, &dn_h,
                      &dn_w, &dn_m, &q_upoff, &q_uparc, &q_dnoff, &q_dnarc, &q_s, &q_t, &q_d,
-                     &q_ovf, &q_tab, &q_ctr};
+                     &q_ovf, &q_tab, &q_ctr, &rec};
   for (sp::DBuf *b : all) b->release();
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

@@ -33,6 +33,10 @@ struct ch_s {
   // query scratch
   sp::DBuf q_s, q_t, q_d, q_ovf, q_tab, q_ctr;
 
+  // features at contraction (CH_F_RECORD_FEATURES), 8 floats per vertex
+  bool has_rec = false;
+  sp::DBuf rec;
+
   std::vector<ch_round_stats_t> stats;
   ch_summary_t summary{};
 

@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "builder.hpp"
+#include "mlp.hpp"
 
 namespace sp {
 const char *last_error_msg();
@@ -73,6 +74,38 @@ int ch_get_round_stats(const ch_t *ch, ch_round_stats_t *out, uint32_t cap) {
   const uint32_t k = (uint32_t)std::min<size_t>(cap, ch->stats.size());
   if (k) memcpy(out, ch->stats.data(), (size_t)k * sizeof(ch_round_stats_t));
   return CH_OK;
+}
+
+int ch_export_features(const ch_t *ch, float *x) {
+  sp::clear_error();
+  if (!ch || !x) return set_error(CH_E_INVALID, "ch and x must not be NULL");
+  if (!ch->has_rec) return set_error(CH_E_INVALID, "the CH was built without CH_F_RECORD_FEATURES");
+  if (!ch->n) return CH_OK;
+  hipError_t e = hipMemcpyAsync(x, ch->rec.p, (size_t)ch->n * 32, hipMemcpyDeviceToHost, ch->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ch->stream);
+  if (e != hipSuccess) return sp::hip_error(e, "ch_export_features");
+  return CH_OK;
+}
+
+int ch_mlp_forward(const float *x, uint64_t n, const float *w, float *y, int32_t *prio,
+                   uint32_t flags, void *stream) {
+  sp::clear_error();
+  if ((n && !x) || !w) return set_error(CH_E_INVALID, "x and w must not be NULL");
+  return sp::mlp_forward(x, n, w, y, prio, flags, (hipStream_t)stream);
+}
+
+int ch_mlp_grad(const float *x, const float *t, uint32_t n, const float *w, float *grad,
+                float *loss, uint32_t flags, void *stream) {
+  sp::clear_error();
+  if (!x || !t || !w || !grad) return set_error(CH_E_INVALID, "x, t, w and grad must not be NULL");
+  return sp::mlp_grad(x, t, n, w, grad, loss, flags, (hipStream_t)stream);
+}
+
+int ch_mlp_train(const float *x, const float *t, uint64_t n, float *w,
+                 const ch_mlp_train_params_t *p, float *losses, uint32_t flags, void *stream) {
+  sp::clear_error();
+  if (!x || !t || !w || !p) return set_error(CH_E_INVALID, "x, t, w and p must not be NULL");
+  return sp::mlp_train(x, t, n, w, p, losses, flags, (hipStream_t)stream);
 }
 
 void ch_free(ch_t *ch) {

@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
     MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
     const uint32_t *__restrict__ nw_dev, uint32_t *__restrict__ work,
     uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count, uint32_t chunk,
-    uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
   constexpr int NG = kLsBlock / G;
   if (nw_dev) nw = *nw_dev;  // source count produced by an earlier kernel
   if (nw == 0) return;
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
     const uint32_t end = min(base + chunk, nw);
     for (uint32_t i = base; i < end; i++) {
       const uint32_t s = vw[i];
-      if (!search_source<G>(ov, aflag, memo, mmask, T, s, ss, err)) {
+      if (!search_source<G>(ov, aflag, memo, mmask, T, s, ss, ws, err)) {
         if (gl == 0) {
           const uint32_t k = atomicAdd(ovf_count, 1u);
           ovf_list[k] = s;
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(64) k_local_search_global(
     Overlay ov, const uint32_t *__restrict__ list, uint32_t nlist,
     const uint8_t *__restrict__ aflag, MemoSlot *__restrict__ memo, uint64_t mmask,
     LsCounters *__restrict__ cnt, uint32_t *__restrict__ tabs, uint32_t cap,
-    uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
   uint32_t *base = tabs + (size_t)blockIdx.x * ((size_t)cap * 6 + 4);
   Tab<uint32_t, true> T;
   T.key = base;
@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(64) k_local_search_global(
   T.limit = cap;  // cap >= 2 n_o: never overflows
   SearchStats ss;
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
-    if (!search_source<64>(ov, aflag, memo, mmask, T, list[i], ss, err)) {
+    if (!search_source<64>(ov, aflag, memo, mmask, T, list[i], ss, ws, err)) {
       if (lane_id() == 0) atomicOr(err, kErrCapacity);
     }
   }
@@ -326,17 +326,19 @@ __device__ __forceinline__ uint32_t count_pairs(const Overlay &ov, const MemoSlo
   return gsum<G>(cnt);
 }
 
-// |N_in(u) union N_out(u)| over live arcs.  Every group lane must call it.
+// Live out-degree, live in-degree and |N_in(u) union N_out(u)| over live
+// arcs.  Every group lane must call it.
 template <int G>
-__device__ __forceinline__ uint32_t count_neighbours(const Overlay &ov, uint32_t u) {
+__device__ __forceinline__ uint3 count_neighbours(const Overlay &ov, uint32_t u) {
   const int gl = glane<G>();
   const uint32_t i0 = ov.roff[u], i1 = ov.roff[u + 1];
   const uint32_t o0 = ov.foff[u], o1 = ov.foff[u + 1];
-  uint32_t c = 0;
-  for (uint32_t e = o0 + gl; e < o1; e += G) c += ov.farc[e].y != SP_INF32;
+  uint32_t cout = 0, cin = 0, only_in = 0;
+  for (uint32_t e = o0 + gl; e < o1; e += G) cout += ov.farc[e].y != SP_INF32;
   for (uint32_t e = i0 + gl; e < i1; e += G) {
     const uint2 a = ov.rarc[e];
     if (a.y == SP_INF32) continue;
+    cin++;
     uint32_t lo = o0, hi = o1;
     while (lo < hi) {
       const uint32_t md = (lo + hi) >> 1;
@@ -344,28 +346,58 @@ __device__ __forceinline__ uint32_t count_neighbours(const Overlay &ov, uint32_t
       else hi = md;
     }
     const bool both = lo < o1 && ov.farc[lo].x == a.x && ov.farc[lo].y != SP_INF32;
-    c += both ? 0u : 1u;
+    only_in += both ? 0u : 1u;
   }
-  return gsum<G>(c);
+  cout = gsum<G>(cout);
+  cin = gsum<G>(cin);
+  only_in = gsum<G>(only_in);
+  return make_uint3(cout, cin, cout + only_in);
 }
 
+// Per-vertex feature state of the learned priority (original ids).
+struct FeatState {
+  uint32_t *cn;     // contracted neighbours
+  uint32_t *depth;  // hierarchy depth
+  uint32_t *ws;     // vertices reached by the latest witness search
+  float *feat;      // current features, 8 per vertex
+  float *rec;       // features at contraction (or null)
+};
+
+// x / (x + c) in single precision (the learned priority's squash).
+__device__ __forceinline__ float squash(uint32_t x, float c) {
+  return __fdiv_rn((float)x, __fadd_rn((float)x, c));
+}
+
+// Edge difference (the plain priority) and the features of the learned one.
 template <int G>
 __global__ void __launch_bounds__(256) k_score(Overlay ov, const uint32_t *__restrict__ va,
                                                uint32_t na, const MemoSlot *__restrict__ memo,
                                                uint64_t mmask, int32_t *__restrict__ P,
-                                               uint32_t *__restrict__ paircnt) {
+                                               uint32_t *__restrict__ paircnt, FeatState fs) {
   const uint32_t ngroups = gridDim.x * (blockDim.x / G);
   const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
   uint32_t probes = 0;
   for (uint32_t k = g0; k < na; k += ngroups) {
     const uint32_t u = va[k];
     const uint32_t pairs = count_pairs<G>(ov, memo, mmask, u, &probes);
-    const uint32_t nb = count_neighbours<G>(ov, u);
+    const uint3 deg = count_neighbours<G>(ov, u);  // out, in, |N(u)|
     if (glane<G>() == 0) {
-      int64_t p = (int64_t)pairs - (int64_t)nb;
+      int64_t p = (int64_t)pairs - (int64_t)deg.z;
       p = p > INT32_MAX ? INT32_MAX : (p < INT32_MIN ? INT32_MIN : p);
-      P[u] = (int32_t)p;
+      const int32_t ed = (int32_t)p;
+      P[u] = ed;
       paircnt[u] = pairs;
+      const uint32_t g = ov.gid[u];
+      float *f = fs.feat + (size_t)g * 8;
+      const uint32_t mag = ed < 0 ? (uint32_t)(-(int64_t)ed) : (uint32_t)ed;
+      f[0] = __fdiv_rn((float)ed, __fadd_rn((float)mag, 8.0f));
+      f[1] = squash(fs.cn[g], 8.0f);
+      f[2] = squash(deg.y, 8.0f);
+      f[3] = squash(deg.x, 8.0f);
+      f[4] = squash(fs.depth[g], 8.0f);
+      f[5] = squash(fs.ws[g], 64.0f);
+      f[6] = squash(deg.z, 8.0f);
+      f[7] = squash(pairs, 8.0f);
     }
   }
 }
@@ -454,7 +486,7 @@ __global__ void __launch_bounds__(256) k_contract(
     uint64_t up_base, uint64_t dn_base, const uint32_t *__restrict__ cpair, int kb,
     uint64_t *__restrict__ ekey, uint32_t *__restrict__ ew,
     uint32_t *__restrict__ elab, uint32_t *__restrict__ emid, uint8_t *__restrict__ S,
-    uint8_t *__restrict__ newA, uint32_t *__restrict__ err) {
+    uint8_t *__restrict__ newA, FeatState fs, uint32_t *__restrict__ err) {
   const uint32_t ngroups = gridDim.x * (blockDim.x / G);
   const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
   const int gl = glane<G>();
@@ -469,6 +501,8 @@ __global__ void __launch_bounds__(256) k_contract(
       score[gu] = P[u];
       alive_g[gu] = 0;
     }
+    if (fs.rec && gl < 8) fs.rec[(size_t)gu * 8 + gl] = fs.feat[(size_t)gu * 8 + gl];
+    const uint32_t dnext = fs.depth[gu] + 1;
     // out-arcs -> upward set
     uint64_t pos = up_base + pup[k];
     const uint32_t o0 = ov.foff[u], o1 = ov.foff[u + 1];
@@ -485,6 +519,9 @@ __global__ void __launch_bounds__(256) k_contract(
         up.w[at] = b.y;
         up.m[at] = ov.fmid[e];
         newA[b.x] = 1;
+        const uint32_t gv = ov.gid[b.x];
+        atomicAdd(&fs.cn[gv], 1u);
+        atomicMax(&fs.depth[gv], dnext);
       }
       pos += __popcll(msk);
     }
@@ -504,6 +541,18 @@ __global__ void __launch_bounds__(256) k_contract(
         dn.w[at] = a.y;
         dn.m[at] = ov.rmid[e];
         newA[a.x] = 1;
+        // one more contracted neighbour, unless a.x is also a live
+        // out-neighbour (counted above)
+        uint32_t lo = o0, hi = o1;
+        while (lo < hi) {
+          const uint32_t md = (lo + hi) >> 1;
+          if (ov.farc[md].x < a.x) lo = md + 1;
+          else hi = md;
+        }
+        const bool both = lo < o1 && ov.farc[lo].x == a.x && ov.farc[lo].y != SP_INF32;
+        const uint32_t gv = ov.gid[a.x];
+        if (!both) atomicAdd(&fs.cn[gv], 1u);
+        atomicMax(&fs.depth[gv], dnext);
       }
       pos += __popcll(msk);
     }

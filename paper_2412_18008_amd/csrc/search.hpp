@@ -125,7 +125,7 @@ template <int G, typename IdxT, bool GL>
 __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ aflag,
                               MemoSlot *__restrict__ memo, uint64_t mmask,
                               const Tab<IdxT, GL> &T, uint32_t s, SearchStats &ss,
-                              uint32_t *__restrict__ err) {
+                              uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
   const int gl = glane<G>();
   const uint32_t gs = ov.gid[s];
 
@@ -277,8 +277,10 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
   ss.searched += (gl == 0) ? 1 : 0;
   {
     const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
+    uint32_t ball = 0;  // vertices within radius D of s (s included)
     for (uint32_t i = gl; i < used; i += G) {
       const IdxT slot = T.ldi(&T.order[i]);
+      ball += T.ld(&T.dist[slot]) <= D ? 1u : 0u;
       if (T.ld(&T.flag[slot]) & kFlagTarget) {
         const uint32_t d = T.ld(&T.dist[slot]);
         if (d <= D) {
@@ -289,6 +291,8 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
         }
       }
     }
+    ball = gsum<G>(ball);
+    if (ws && gl == 0) ws[gs] = ball;
   }
   tab_reset<G>(T);
   return true;

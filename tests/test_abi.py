@@ -47,15 +47,15 @@ def test_null_and_invalid_arguments(binding):
     off = np.zeros(2, np.uint64)
     g = binding.Graph(1, 0, off.ctypes.data, None, None, None)
     assert L.ch_build(C.byref(g), None, None) == binding.CH_E_INVALID
-    p = binding.Params(0, 0, 0, 0, 3, None, 0, 0, 0, 0)  # group 3 is not allowed
+    p = binding.Params(0, 0, 0, 0, 3, None, 0, 0, 0, 0, None)  # group 3 is not allowed
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
-    p = binding.Params(7, 0, 0, 0, 0, None, 0, 0, 0, 0)  # unknown search mode
+    p = binding.Params(7, 0, 0, 0, 0, None, 0, 0, 0, 0, None)  # unknown search mode
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_UNSUPPORTED
-    p = binding.Params(0, 0, 0, 0, 0, None, 9, 0, 0, 0)  # unknown search kernel
+    p = binding.Params(0, 0, 0, 0, 0, None, 9, 0, 0, 0, None)  # unknown search kernel
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
-    p = binding.Params(0, 0, 0, 0, 0, None, 0, 0, 0, 1)  # reserved must be 0
+    p = binding.Params(0, 0, 0, 0, 0, None, 0, 0, 0, 1, None)  # learned without weights
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
-    p = binding.Params(7, 0, 0, 0, 0, None, 0, 0, 0, 0)
+    p = binding.Params(7, 0, 0, 0, 0, None, 0, 0, 0, 0, None)
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_UNSUPPORTED
     g = binding.Graph(0xFFFFFFFF, 0, off.ctypes.data, None, None, None)
     assert L.ch_build(C.byref(g), None, C.byref(h)) == binding.CH_E_INVALID
@@ -70,7 +70,8 @@ def test_struct_layouts_match_header(binding, tmp_path):
     import subprocess
 
     structs = {"ch_graph_t": binding.Graph, "ch_params_t": binding.Params,
-               "ch_summary_t": binding.Summary, "ch_round_stats_t": binding.RoundStats}
+               "ch_summary_t": binding.Summary, "ch_round_stats_t": binding.RoundStats,
+               "ch_mlp_train_params_t": binding.MlpTrainParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "spoch.h"', 'int main(void){']
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

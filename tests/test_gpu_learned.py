@@ -1,0 +1,141 @@
+"""GPU parity of the learned priority.
+
+* the network's fp32 forward on the GPU gives the oracle's bits (priority
+  and output); the bf16 forward stays within bf16 rounding of the fp64
+  reference;
+* the GPU gradient (deterministic sums) matches the fp64 reference;
+* a learned build equals the oracle's learned build bit for bit (same
+  features, same priorities, same CH), and recorded features are identical;
+* training lowers the loss, and the trained network's CH answers every
+  sampled query exactly; its shortcut count and query cost are reported
+  beside the plain method's and an untrained network's."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as ref
+from paper_2412_18008_amd import synth
+from parity_util import assert_same_ch, gpu_export, gpu_round_counts, oracle_export, \
+    oracle_round_counts, reference_distances
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_18008_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def _features(rng, k):
+    x = rng.random((k, 8)).astype(np.float32)
+    x[:, 0] = rng.random(k).astype(np.float32) * 2 - 1
+    return x
+
+
+def test_forward_bits_match_oracle(gpu):
+    from paper_2412_18008_amd import learned
+
+    rng = np.random.default_rng(0)
+    for seed in (0, 1, 2):
+        w = learned.init_weights(seed)
+        w[4800] = np.float32(rng.standard_normal())
+        x = _features(rng, 3000)
+        y, p = gpu.mlp_forward(x, w)
+        for i in range(0, 3000, 7):
+            po, yo = oracle.mlp_priority(w, x[i])
+            assert p[i] == po and np.float32(yo).view(np.uint32) == y[i].view(np.uint32), i
+        yr, _ = ref.forward(w.astype(np.float64), x.astype(np.float64))
+        yb, _ = gpu.mlp_forward(x, w, bf16=True)
+        scale = np.max(np.abs(yr)) + 1e-6
+        assert np.max(np.abs(yb - yr)) <= 2e-2 * scale
+        assert np.max(np.abs(y - yr)) <= 1e-5 * scale
+
+
+def test_gradient_matches_reference(gpu):
+    from paper_2412_18008_amd import learned
+
+    rng = np.random.default_rng(1)
+    w = learned.init_weights(3) + np.float32(0.05) * rng.standard_normal(4801).astype(np.float32)
+    x = _features(rng, 777)
+    t = rng.random(777).astype(np.float32)
+    g, loss = gpu.mlp_grad(x, t, w)
+    gr = ref.grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    lr = ref.loss(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - lr) <= 1e-5 * max(1.0, lr)
+    assert np.linalg.norm(g - gr) <= 1e-5 * np.linalg.norm(gr) + 1e-7
+    assert np.max(np.abs(g - gr)) <= 1e-4 * np.max(np.abs(gr)) + 1e-7
+    g2, _ = gpu.mlp_grad(x, t, w)
+    assert np.array_equal(g, g2)  # deterministic
+
+
+def _learned_case(gpu, name, off, dst, w, lab, weights):
+    print(f"[learned] {name} n={len(off) - 1}", flush=True)
+    o = oracle.OracleCH(off, dst, w, labels=lab, mlp=weights).run()
+    ch = gpu.build(off, dst, w, labels=lab, mlp=weights, stats=True)
+    assert_same_ch(oracle_export(o), gpu_export(ch), name)
+    assert gpu_round_counts(ch) == oracle_round_counts(o), name
+    return o, ch
+
+
+def test_learned_build_bit_exact(gpu):
+    from paper_2412_18008_amd import learned
+
+    cases = [("road3k", *synth.road_like(3000, seed=1)), ("grid", *synth.grid(12, 15, seed=2)),
+             ("digraph", *synth.random_digraph(80, 320, seed=3, wmax=9, zero_frac=0.1)),
+             ("road20k", *synth.road_like(20_000, seed=4))]
+    for wseed in (0, 5):
+        weights = learned.init_weights(wseed)
+        for name, off, dst, w in cases:
+            n = len(off) - 1
+            _learned_case(gpu, f"{name}/w{wseed}", off, dst, w, synth.labels(n, 7), weights)
+
+
+def test_recorded_features_bit_exact(gpu):
+    off, dst, w = synth.road_like(10_000, seed=9)
+    n = len(off) - 1
+    lab = synth.labels(n, 3)
+    o = oracle.OracleCH(off, dst, w, labels=lab, record=True).run()
+    ch = gpu.build(off, dst, w, labels=lab, record=True)
+    assert np.array_equal(o.features().view(np.uint32), ch.features().view(np.uint32))
+
+
+def test_training_and_gain(gpu):
+    from paper_2412_18008_amd import learned
+
+    graphs = list(learned.training_graphs(6, nmin=4000, nmax=20000))
+    X, t = learned.record(graphs)
+    assert X.shape[1] == 8 and len(X) == len(t) == sum(len(g[0]) - 1 for g in graphs)
+    w_trained, losses = learned.train(X, t, steps=400, batch=2048, lr=3e-3)
+    head, tail = float(np.mean(losses[:20])), float(np.mean(losses[-20:]))
+    print(f"[learned] loss {head:.4f} -> {tail:.4f}", flush=True)
+    assert tail < 0.5 * head
+
+    off, dst, w = synth.road_like(30_000, seed=4242)
+    n = len(off) - 1
+    s, tq = synth.queries(n, 400, seed=5)
+    ref_d = reference_distances(off, dst, w, s[:40], tq[:40])
+    report = {}
+    for tag, weights in (("plain", None), ("untrained", learned.init_weights(77)),
+                         ("trained", w_trained)):
+        ch = gpu.build(off, dst, w, mlp=weights)
+        d = ch.query(s, tq)
+        assert np.array_equal(d[:40], ref_d), tag  # zero distance error
+        e = ch.export()
+        L = oracle.LoadedCH(e["rank"], e["up_tail"], e["up_head"], e["up_w"], e["down_tail"],
+                            e["down_head"], e["down_w"])
+        od, settled = L.query_batch(s, tq)
+        assert np.array_equal(od, d), tag
+        report[tag] = dict(shortcuts=ch.summary["shortcuts"],
+                           ch_arcs=ch.summary["up_arcs"] + ch.summary["down_arcs"],
+                           settled=float(settled.mean()))
+    print(f"[learned] gain report: {report}", flush=True)
+    # the trained network must order contraction far better than an untrained one
+    assert report["trained"]["shortcuts"] < report["untrained"]["shortcuts"]
+    assert report["trained"]["settled"] < report["untrained"]["settled"]

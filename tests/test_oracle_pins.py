@@ -374,3 +374,16 @@ def test_empty_and_isolated(oracle_lib):
     assert o.rounds == 1
     d, _ = o.query_batch(np.array([0, 1], np.uint32), np.array([0, 2], np.uint32))
     assert d[0] == 0 and d[1] == np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def test_loaded_ch_answers_like_built_ch(oracle_lib):
+    for name, (off, dst, w) in small_graphs()[:8] + [("road2k", synth.road_like(2000, seed=3))]:
+        n = len(off) - 1
+        o = oracle.OracleCH(off, dst, w, labels=synth.labels(n, 4)).run()
+        up, dn = o.up(), o.down()
+        L = oracle.LoadedCH(o.rank(), up["tail"], up["head"], up["w"], dn["tail"], dn["head"],
+                            dn["w"])
+        s, t = synth.queries(n, 500, seed=2)
+        a = o.query_batch(s, t)
+        b = L.query_batch(s, t)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), name
