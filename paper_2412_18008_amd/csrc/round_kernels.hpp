@@ -501,7 +501,8 @@ __global__ void __launch_bounds__(256) k_contract(
       score[gu] = P[u];
       alive_g[gu] = 0;
     }
-    if (fs.rec && gl < 8) fs.rec[(size_t)gu * 8 + gl] = fs.feat[(size_t)gu * 8 + gl];
+    if (fs.rec)
+      for (int i = gl; i < 8; i += G) fs.rec[(size_t)gu * 8 + i] = fs.feat[(size_t)gu * 8 + i];
     const uint32_t dnext = fs.depth[gu] + 1;
     // out-arcs -> upward set
     uint64_t pos = up_base + pup[k];
