@@ -79,6 +79,64 @@ def cpu_baseline(g, budget_note):
             "build_s": el}
 
 
+MLP_FLOP_PER_ROW = 2 * (8 * 64 + 64 * 64 + 64)  # multiply-adds of the three layers
+
+
+def mlp_throughput(binding, w_host, dev, rows=1 << 20, reps=20):
+    """GFLOP/s of the learned priority's forward kernel (fp32 and bf16) on
+    `rows` device-resident feature vectors, timed with HIP events."""
+    import numpy as np
+    import torch
+
+    g = torch.Generator(device="cpu").manual_seed(7)
+    x = torch.rand(rows, 8, generator=g).to(dev)
+    w = torch.from_numpy(np.asarray(w_host, np.float32)).to(dev)
+    out = {}
+    for tag, bf16 in (("fp32", False), ("bf16", True)):
+        binding.mlp_forward(x, w, bf16=bf16)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            binding.mlp_forward(x, w, bf16=bf16)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[tag] = {"ms_per_launch": ms, "rows": rows,
+                    "gflop_s": rows * MLP_FLOP_PER_ROW / (ms / 1e3) / 1e9}
+    return out
+
+
+def plain_vs_learned(binding, args, t_off, t_dst, t_w, qs, qt, knobs, dev):
+    """Same graph and knobs, priority plain vs learned: build time, shortcuts,
+    CH arcs, mean vertices visited per query (the two upward search spaces,
+    counted by the query kernel) and the number of distances that differ."""
+    import numpy as np
+    import torch
+
+    wts = np.load(args.learned).astype(np.float32)
+    nq = min(len(qs), 20_000)
+    rep = {"weights": os.path.basename(args.learned), "queries": nq}
+    dist = {}
+    for tag, mlp in (("plain", None), ("learned", wts)):
+        print(f"[bench] {tag} build for the comparison", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch = binding.build(t_off, t_dst, t_w, seed=0, mlp=mlp, **knobs)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        d, vis = ch.query_stats(qs[:nq], qt[:nq])
+        dist[tag] = d
+        sm = ch.summary
+        rep[tag] = {"build_s": el, "rounds": sm["rounds"], "shortcuts": sm["shortcuts"],
+                    "ch_arcs": sm["up_arcs"] + sm["down_arcs"],
+                    "mean_visited_per_query": float(vis.mean())}
+        ch.free()
+    rep["distance_errors"] = int(np.count_nonzero(dist["plain"] != dist["learned"]))
+    rep["mlp_forward"] = mlp_throughput(binding, wts, dev)
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +146,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner cache (default knobs)")
+    ap.add_argument("--learned", default=os.path.join(ROOT, "paper_2412_18008_amd",
+                                                      "learned_weights.npy"),
+                    help="weights (.npy, 4801 float32) of the learned priority; the plain vs "
+                         "learned comparison runs after the timed steps when the file exists")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the build is a single-GPU path "
@@ -204,6 +266,9 @@ def main():
             "algorithmic_bytes_per_launch": ls_b / max(ls_launches, 1),
         },
     }
+    if os.path.exists(args.learned):
+        line["plain_vs_learned"] = plain_vs_learned(binding, args, t_off, t_dst, t_w, qs, qt,
+                                                    knobs, dev)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, f"the full {args.workload} build (same graph)")

@@ -209,6 +209,12 @@ int ch_build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t 
 int ch_query_batch(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                    uint64_t *dist, uint32_t flags, void *stream);
 
+/* As ch_query_batch, and visited[i] = the number of vertices in the two
+ * upward search spaces of the i-th query (the query's cost; q uint32 entries,
+ * host or device like dist). */
+int ch_query_batch_stats(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
+                         uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream);
+
 /* Copy the finished CH to host arrays, in original vertex ids.  Any pointer
  * may be NULL to skip that array.
  *   level[n]: round in which the vertex was contracted (0-based)

@@ -32,7 +32,7 @@ CH_Q_ON_DEVICE = 0x1
 
 EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
             "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version", "ch_export_features",
-            "ch_mlp_forward", "ch_mlp_grad", "ch_mlp_train")
+            "ch_mlp_forward", "ch_mlp_grad", "ch_mlp_train", "ch_query_batch_stats")
 
 
 class ChError(RuntimeError):
@@ -117,6 +117,8 @@ def lib():
         L.ch_last_error.restype = C.c_char_p
         L.ch_version.argtypes = []
         L.ch_version.restype = C.c_char_p
+        L.ch_query_batch_stats.argtypes = [vp, vp, vp, u64, vp, vp, u32, vp]
+        L.ch_query_batch_stats.restype = i32
         L.ch_export_features.argtypes = [vp, vp]
         L.ch_export_features.restype = i32
         L.ch_mlp_forward.argtypes = [vp, u64, vp, vp, vp, u32, vp]
@@ -186,6 +188,18 @@ class CH:
         _check(lib().ch_query_batch(self.h, s.ctypes.data, t.ctypes.data, len(s),
                                     dist.ctypes.data, 0, stream), "ch_query_batch")
         return dist
+
+    def query_stats(self, s, t):
+        """(dist, visited): distances and vertices in the two upward search
+        spaces of each query (numpy, host)."""
+        s = np.ascontiguousarray(s, np.uint32)
+        t = np.ascontiguousarray(t, np.uint32)
+        dist = np.empty(len(s), np.uint64)
+        vis = np.empty(len(s), np.uint32)
+        _check(lib().ch_query_batch_stats(self.h, s.ctypes.data, t.ctypes.data, len(s),
+                                          dist.ctypes.data, vis.ctypes.data, 0, None),
+               "ch_query_batch_stats")
+        return dist, vis
 
     def export(self):
         n, nu, nd = self.n, self.summary["up_arcs"], self.summary["down_arcs"]
@@ -268,8 +282,22 @@ def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=
     return [CH(C.c_void_p(outs[i])) for i in range(k)]
 
 
-def mlp_forward(x, w, bf16=False):
-    """(y, priority) of the learned priority's network on n x 8 features."""
+def mlp_forward(x, w, bf16=False, stream=None):
+    """(y, priority) of the learned priority's network on n x 8 features.
+    x and w as numpy (host) or as float32 CUDA tensors (device; the results
+    are then device tensors and the call is asynchronous on ``stream``)."""
+    if _is_torch_cuda(x):
+        import torch
+
+        n = x.numel() // 8
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        y = torch.empty(n, dtype=torch.float32, device=x.device)
+        p = torch.empty(n, dtype=torch.int32, device=x.device)
+        flags = CH_MLP_ON_DEVICE | (CH_MLP_BF16 if bf16 else 0)
+        _check(lib().ch_mlp_forward(x.data_ptr(), n, w.data_ptr(), y.data_ptr(), p.data_ptr(),
+                                    flags, stream), "ch_mlp_forward")
+        return y, p
     x = np.ascontiguousarray(x, np.float32).reshape(-1, 8)
     w = np.ascontiguousarray(w, np.float32)
     y = np.empty(len(x), np.float32)

@@ -31,7 +31,7 @@ struct ch_s {
   sp::DBuf q_upoff, q_uparc, q_dnoff, q_dnarc;  // offsets uint32[n+1], arcs uint2{other, w}
 
   // query scratch
-  sp::DBuf q_s, q_t, q_d, q_ovf, q_tab, q_ctr;
+  sp::DBuf q_s, q_t, q_d, q_v, q_ovf, q_tab, q_ctr;
 
   // features at contraction (CH_F_RECORD_FEATURES), 8 floats per vertex
   bool has_rec = false;
@@ -60,6 +60,6 @@ int build_index(ch_s *ch);
 int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **outs);
 // Query batch (post.hip).
 int query_batch(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
-                uint64_t *dist, uint32_t flags, hipStream_t st);
+                uint64_t *dist, uint32_t *visited, uint32_t flags, hipStream_t st);
 
 }  // namespace sp

@@ -473,7 +473,8 @@ __global__ void __launch_bounds__(64) k_query(
     const uint32_t *__restrict__ rank, const uint32_t *__restrict__ upoff,
     const uint2 *__restrict__ uparc, const uint32_t *__restrict__ dnoff,
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
-    uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count) {
+    uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
+    uint32_t *__restrict__ ovf_count) {
   __shared__ uint32_t s_key[2][kQCap];
   __shared__ uint32_t s_dist[2][kQCap];
   __shared__ uint32_t s_flag[2][kQCap];
@@ -509,7 +510,10 @@ __global__ void __launch_bounds__(64) k_query(
     if (ok) ok = closure(T[1], dnoff, dnarc, rt);
     if (ok) {
       const unsigned long long mu = meet(T[0], T[1]);
-      if (l == 0) dist[k] = mu;
+      if (l == 0) {
+        dist[k] = mu;
+        if (visited) visited[k] = T[0].ld(&T[0].ctr[0]) + T[1].ld(&T[1].ctr[0]);
+      }
     } else if (l == 0) {
       const uint32_t p = atomicAdd(ovf_count, 1u);
       ovf_list[p] = (uint32_t)k;
@@ -527,7 +531,8 @@ __global__ void __launch_bounds__(64) k_query_global(
     const uint32_t *__restrict__ qt, const uint32_t *__restrict__ rank,
     const uint32_t *__restrict__ upoff, const uint2 *__restrict__ uparc,
     const uint32_t *__restrict__ dnoff, const uint2 *__restrict__ dnarc,
-    unsigned long long *__restrict__ dist, uint32_t *__restrict__ tabs, uint32_t cap) {
+    unsigned long long *__restrict__ dist, uint32_t *__restrict__ visited,
+    uint32_t *__restrict__ tabs, uint32_t cap) {
   // per direction: key[cap], dist[cap] (2 words each), flag[cap], order, fr0,
   // fr1 [cap] and 4 counters = 8 cap + 4 words
   const size_t per = (size_t)cap * 8 + 4;
@@ -552,7 +557,10 @@ __global__ void __launch_bounds__(64) k_query_global(
     closure(T[0], upoff, uparc, rs);
     closure(T[1], dnoff, dnarc, rt);
     const unsigned long long mu = meet(T[0], T[1]);
-    if (lane_id() == 0) dist[k] = mu;
+    if (lane_id() == 0) {
+      dist[k] = mu;
+      if (visited) visited[k] = T[0].ld(&T[0].ctr[0]) + T[1].ld(&T[1].ctr[0]);
+    }
     qtab_reset(T[0]);
     qtab_reset(T[1]);
   }
@@ -566,7 +574,7 @@ __global__ void k_check_ids(uint64_t q, const uint32_t *__restrict__ s, const ui
 }
 
 int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t q, uint64_t *dist,
-                uint32_t flags, hipStream_t st) {
+                uint32_t *visited, uint32_t flags, hipStream_t st) {
   ch_s *ch = const_cast<ch_s *>(chc);
   if (!ch->has_index) return set_error(CH_E_INVALID, "the CH was built without a query index");
   if (q == 0) return CH_OK;
@@ -585,6 +593,11 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     dt = ch->q_t.as<uint32_t>();
     dd = ch->q_d.as<unsigned long long>();
   }
+  uint32_t *dv = visited;
+  if (visited && !on_dev) {
+    HIP_TRY(ch->q_v.ensure(q * 4));
+    dv = ch->q_v.as<uint32_t>();
+  }
   HIP_TRY(ch->q_ovf.ensure(q * 4));
   uint32_t *ctr = ch->q_ctr.as<uint32_t>();
   HIP_TRY(hipMemsetAsync(ctr, 0, 64, st));
@@ -600,7 +613,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   k_query<<<(unsigned)g, 64, 0, st>>>(q, ds, dt, ch->rank.as<uint32_t>(),
                                       ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(),
                                       ch->q_dnoff.as<uint32_t>(), ch->q_dnarc.as<uint2>(), dd,
-                                      ch->q_ovf.as<uint32_t>(), ctr);
+                                      dv, ch->q_ovf.as<uint32_t>(), ctr);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
@@ -621,10 +634,11 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     k_query_global<<<(unsigned)ntab, 64, 0, st>>>(
         hc[0], ch->q_ovf.as<uint32_t>(), ds, dt, ch->rank.as<uint32_t>(),
         ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(), ch->q_dnoff.as<uint32_t>(),
-        ch->q_dnarc.as<uint2>(), dd, ch->q_tab.as<uint32_t>(), cap);
+        ch->q_dnarc.as<uint2>(), dd, dv, ch->q_tab.as<uint32_t>(), cap);
     HIP_TRY(hipGetLastError());
   }
   if (!on_dev) HIP_TRY(hipMemcpyAsync(dist, dd, q * 8, hipMemcpyDeviceToHost, st));
+  if (visited && !on_dev) HIP_TRY(hipMemcpyAsync(visited, dv, q * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   return CH_OK;
 }

@@ -57,3 +57,38 @@ def train(X, t, steps=2000, batch=4096, lr=2e-3, seed=0, init_seed=0):
     """Trained weights and the per-step batch losses."""
     return binding.mlp_train(X, t, init_weights(init_seed), batch=batch, steps=steps, lr=lr,
                              seed=seed)
+
+
+def main():
+    import argparse
+    import json
+    import time
+
+    ap = argparse.ArgumentParser(description="train the learned priority on the GPU")
+    ap.add_argument("--graphs", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--out", required=True, help="output .npy file of 4801 float32 weights")
+    args = ap.parse_args()
+    t0 = time.time()
+    xs, ts = [], []
+    for i, g in enumerate(training_graphs(args.graphs)):
+        x, y = record([g])
+        xs.append(x)
+        ts.append(y)
+        if (i + 1) % 20 == 0:
+            print(f"[learned] recorded {i + 1}/{args.graphs} graphs", flush=True)
+    X, t = np.concatenate(xs), np.concatenate(ts)
+    t1 = time.time()
+    w, losses = train(X, t, steps=args.steps, batch=args.batch, lr=args.lr)
+    t2 = time.time()
+    np.save(args.out, w)
+    print(json.dumps(dict(samples=int(len(X)), graphs=args.graphs, record_s=t1 - t0,
+                          train_s=t2 - t1, loss_first=float(losses[:50].mean()),
+                          loss_last=float(losses[-50:].mean()), steps=args.steps,
+                          batch=args.batch, lr=args.lr)))
+
+
+if __name__ == "__main__":
+    main()

@@ -79,3 +79,20 @@ def reference_distances(off, dst, w, s, t):
             cache[a] = oracle.dijkstra(off, dst, w, a)
         out[i] = cache[a][b]
     return out
+
+
+def closure_sizes(o, s, t):
+    """|vertices reachable from s over upward arcs| + |vertices that reach t
+    over downward arcs|, from the oracle's finished CH (plain reachability)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import breadth_first_order
+
+    n = o.n
+    up, dn = o.up(), o.down()
+    U = csr_matrix((np.ones(len(up["tail"])), (up["tail"], up["head"])), shape=(n, n))
+    D = csr_matrix((np.ones(len(dn["tail"])), (dn["head"], dn["tail"])), shape=(n, n))
+    out = np.empty(len(s), np.int64)
+    for i, (a, b) in enumerate(zip(s, t)):
+        out[i] = (len(breadth_first_order(U, int(a), return_predecessors=False))
+                  + len(breadth_first_order(D, int(b), return_predecessors=False)))
+    return out

@@ -8,8 +8,9 @@ import pytest
 
 import oracle
 from paper_2412_18008_amd import synth
-from parity_util import (assert_export_order, assert_same_ch, gpu_export, gpu_round_counts,
-                         oracle_export, oracle_round_counts, reference_distances)
+from parity_util import (assert_export_order, assert_same_ch, closure_sizes, gpu_export,
+                         gpu_round_counts, oracle_export, oracle_round_counts,
+                         reference_distances)
 
 pytestmark = pytest.mark.gpu
 
@@ -72,6 +73,10 @@ def test_grid64_bit_exact_and_queries(gpu):
     assert np.array_equal(d, ref)
     od, _ = o.query_batch(s, t)
     assert np.array_equal(d, od)
+    # query cost: the sizes of the two upward search spaces
+    d2, vis = ch.query_stats(s[:300], t[:300])
+    assert np.array_equal(d2, d[:300])
+    assert np.array_equal(vis.astype(np.int64), closure_sizes(o, s[:300], t[:300]))
 
 
 def test_group_split_invariance(gpu):
