@@ -61,6 +61,9 @@ extern "C" {
 #define CH_F_NO_QUERY_INDEX 0x4u  /* skip the rank-space CSR (ch_query_batch then fails) */
 
 #define CH_Q_ON_DEVICE 0x1u       /* s, t, dist of ch_query_batch are device pointers */
+/* Waves that share one query (1, 2 or 4; 0 = the default, 4).  Results do
+ * not depend on it. */
+#define CH_Q_WAVES(nw) ((uint32_t)(nw) << 8)
 
 /* Input graph in CSR form, arcs grouped by tail vertex.
  *   offsets[n+1]: offsets[0] = 0, non-decreasing, offsets[n] = m

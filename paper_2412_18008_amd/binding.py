@@ -59,6 +59,13 @@ CH_F_RECORD_FEATURES = 0x8
 CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
 
 
+def CH_Q_WAVES(nw):
+    """Query flag: waves that share one query (1, 2, 4; 0 = default)."""
+    if nw not in (0, 1, 2, 4):
+        raise ValueError("waves must be 0, 1, 2 or 4")
+    return nw << 8
+
+
 class MlpTrainParams(C.Structure):
     _fields_ = [("batch", C.c_uint32), ("steps", C.c_uint32), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
@@ -169,10 +176,12 @@ class CH:
             _lib.ch_free(self.h)
             self.h = None
 
-    def query(self, s, t, stream=None):
+    def query(self, s, t, stream=None, waves=0):
         """dist[i] = shortest s[i] -> t[i] distance (uint64, max = unreachable).
         numpy inputs give a numpy result; torch CUDA inputs give a torch CUDA
-        int64 tensor (holding the uint64 bit patterns)."""
+        int64 tensor (holding the uint64 bit patterns).  waves: waves per
+        query in the kernel (1, 2, 4; 0 = default)."""
+        qf = CH_Q_WAVES(waves)
         if _is_torch_cuda(s):
             import torch
 
@@ -180,16 +189,16 @@ class CH:
             dist = torch.empty(q, dtype=torch.int64, device=s.device)
             st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
             _check(lib().ch_query_batch(self.h, s.data_ptr(), t.data_ptr(), q, dist.data_ptr(),
-                                        CH_Q_ON_DEVICE, st), "ch_query_batch")
+                                        CH_Q_ON_DEVICE | qf, st), "ch_query_batch")
             return dist
         s = np.ascontiguousarray(s, np.uint32)
         t = np.ascontiguousarray(t, np.uint32)
         dist = np.empty(len(s), np.uint64)
         _check(lib().ch_query_batch(self.h, s.ctypes.data, t.ctypes.data, len(s),
-                                    dist.ctypes.data, 0, stream), "ch_query_batch")
+                                    dist.ctypes.data, qf, stream), "ch_query_batch")
         return dist
 
-    def query_stats(self, s, t):
+    def query_stats(self, s, t, waves=0):
         """(dist, visited): distances and vertices in the two upward search
         spaces of each query (numpy, host)."""
         s = np.ascontiguousarray(s, np.uint32)
@@ -197,7 +206,8 @@ class CH:
         dist = np.empty(len(s), np.uint64)
         vis = np.empty(len(s), np.uint32)
         _check(lib().ch_query_batch_stats(self.h, s.ctypes.data, t.ctypes.data, len(s),
-                                          dist.ctypes.data, vis.ctypes.data, 0, None),
+                                          dist.ctypes.data, vis.ctypes.data,
+                                          CH_Q_WAVES(waves), None),
                "ch_query_batch_stats")
         return dist, vis
 

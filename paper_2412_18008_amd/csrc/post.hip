@@ -466,60 +466,263 @@ __device__ unsigned long long meet(const QTab<IdxT, DistT, GL> &Fw, const QTab<I
   return gmin64<kWave>(best);
 }
 
-constexpr int kQCap = 2048;
+// ---------------------------------------------------------------------------
+// Fast path: both upward closures of one query at once, in LDS.  Each
+// direction has an open-addressing table of kQCap slots (vertex, distance)
+// and one frontier bit per slot.  A level takes every flagged slot of both
+// directions (clearing the bits), expands them, and flags each slot whose
+// distance dropped; the closures are complete when no bit is set.  Arc loads
+// of a level are issued kQUnroll deep per lane before any of them is used.
+// A query goes to the global fallback when a table passes kQLimit entries or
+// a distance passes 32 bits.  NW waves share one query's tables.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kQCap = 2048;
+constexpr uint32_t kQShift = 21;  // 32 - log2(kQCap)
+constexpr uint32_t kQLimit = kQCap * 7 / 8;
+constexpr uint32_t kQWords = kQCap / 32;
+constexpr int kQUnroll = 8;
 
-__global__ void __launch_bounds__(64) k_query(
+struct QLds {
+  uint32_t key[2][kQCap];
+  uint32_t dist[2][kQCap];
+  uint32_t bits[2][kQWords];
+  uint16_t list[2 * kQLimit];  // flagged slots of one level: dir << 11 | slot
+  uint32_t used[2];
+  uint32_t ovf;
+  uint32_t wsum[4];
+  unsigned long long wmin[4];
+};
+
+template <int NW>
+__device__ __forceinline__ void qsync() {
+  if constexpr (NW == 1) wave_sync();
+  else __syncthreads();
+}
+
+// Slot of v in direction d (inserted if absent); *fresh = 1 when inserted
+// here; -1 when the table is full.
+__device__ __forceinline__ int qins(QLds &S, uint32_t d, uint32_t v, uint32_t *fresh) {
+  uint32_t h = (v * 0x9E3779B1u) >> kQShift;
+  for (uint32_t probes = 0; probes < kQCap; probes++) {
+    const uint32_t k = __hip_atomic_load(&S.key[d][h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == v) return (int)h;
+    if (k == SP_EMPTY32) {
+      const uint32_t prev = atomicCAS(&S.key[d][h], SP_EMPTY32, v);
+      if (prev == SP_EMPTY32) {
+        *fresh = 1;
+        return (int)h;
+      }
+      if (prev == v) return (int)h;
+    }
+    h = (h + 1) & (kQCap - 1);
+  }
+  return -1;
+}
+
+__device__ __forceinline__ int qfind(const QLds &S, uint32_t d, uint32_t v) {
+  uint32_t h = (v * 0x9E3779B1u) >> kQShift;
+  for (uint32_t probes = 0; probes < kQCap; probes++) {
+    const uint32_t k = S.key[d][h];
+    if (k == v) return (int)h;
+    if (k == SP_EMPTY32) return -1;
+    h = (h + 1) & (kQCap - 1);
+  }
+  return -1;
+}
+
+// Block-wide exclusive prefix of c over NW waves; *total = the block sum.
+template <int NW>
+__device__ __forceinline__ uint32_t qscan(QLds &S, uint32_t c, uint32_t *total) {
+  const uint32_t incl = gscan_incl<kWave>(c);
+  if constexpr (NW == 1) {
+    *total = __shfl(incl, kWave - 1, kWave);
+    return incl - c;
+  } else {
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) S.wsum[wv] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      const uint32_t x = S.wsum[i];
+      before += i < wv ? x : 0u;
+      all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - c;
+  }
+}
+
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) k_query(
     uint64_t q, const uint32_t *__restrict__ qs, const uint32_t *__restrict__ qt,
     const uint32_t *__restrict__ rank, const uint32_t *__restrict__ upoff,
     const uint2 *__restrict__ uparc, const uint32_t *__restrict__ dnoff,
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
     uint32_t *__restrict__ ovf_count) {
-  __shared__ uint32_t s_key[2][kQCap];
-  __shared__ uint32_t s_dist[2][kQCap];
-  __shared__ uint32_t s_flag[2][kQCap];
-  __shared__ uint16_t s_order[2][kQCap];
-  __shared__ uint16_t s_fr[2][2][kQCap];
-  __shared__ uint32_t s_ctr[2][4];
+  __shared__ QLds S;
+  constexpr uint32_t NT = 64 * NW;
+  const uint32_t tid = threadIdx.x;
   const int l = lane_id();
-  for (int d = 0; d < 2; d++) {
-    for (int i = l; i < kQCap; i += kWave) {
-      s_key[d][i] = SP_EMPTY32;
-      s_dist[d][i] = SP_INF32;
-      s_flag[d][i] = 0;
-    }
-    if (l < 4) s_ctr[d][l] = 0;
+  const uint32_t wv = tid / kWave;
+  for (uint32_t i = tid; i < kQCap; i += NT) {
+    S.key[0][i] = SP_EMPTY32;
+    S.key[1][i] = SP_EMPTY32;
+    S.dist[0][i] = SP_INF32;
+    S.dist[1][i] = SP_INF32;
   }
-  wave_sync();
-  QTab<uint16_t, uint32_t, false> T[2];
-  for (int d = 0; d < 2; d++) {
-    T[d].key = s_key[d];
-    T[d].dist = s_dist[d];
-    T[d].flag = s_flag[d];
-    T[d].order = s_order[d];
-    T[d].fr0 = s_fr[d][0];
-    T[d].fr1 = s_fr[d][1];
-    T[d].ctr = s_ctr[d];
-    T[d].cap = kQCap;
-    T[d].shift = 32 - __builtin_ctz(kQCap);
-    T[d].limit = (kQCap * 7) / 8;
-  }
+  for (uint32_t i = tid; i < 2 * kQWords; i += NT) S.bits[i / kQWords][i % kQWords] = 0;
+  if (tid < 2) S.used[tid] = 0;
+  if (tid == 0) S.ovf = 0;
+  qsync<NW>();
   for (uint64_t k = blockIdx.x; k < q; k += gridDim.x) {
-    const uint32_t rs = rank[qs[k]], rt = rank[qt[k]];
-    bool ok = closure(T[0], upoff, uparc, rs);
-    if (ok) ok = closure(T[1], dnoff, dnarc, rt);
-    if (ok) {
-      const unsigned long long mu = meet(T[0], T[1]);
-      if (l == 0) {
-        dist[k] = mu;
-        if (visited) visited[k] = T[0].ld(&T[0].ctr[0]) + T[1].ld(&T[1].ctr[0]);
-      }
-    } else if (l == 0) {
-      const uint32_t p = atomicAdd(ovf_count, 1u);
-      ovf_list[p] = (uint32_t)k;
+    if (tid < 2) {
+      const uint32_t v = rank[tid ? qt[k] : qs[k]];
+      uint32_t fresh = 0;
+      const int a = qins(S, tid, v, &fresh);  // an empty table has room
+      S.dist[tid][a] = 0;
+      S.bits[tid][a >> 5] = 1u << (a & 31);
+      S.used[tid] = 1;
     }
-    qtab_reset(T[0]);
-    qtab_reset(T[1]);
+    qsync<NW>();
+    for (;;) {
+      // take the flags of both directions: words tid, tid + NT, ...
+      uint32_t wa = 0, wb = 0;
+      const uint32_t ia = tid, ib = tid + NT;
+      if (ia < 2 * kQWords) {
+        wa = S.bits[ia / kQWords][ia % kQWords];
+        S.bits[ia / kQWords][ia % kQWords] = 0;
+      }
+      if (NT < 2 * kQWords && ib < 2 * kQWords) {
+        wb = S.bits[ib / kQWords][ib % kQWords];
+        S.bits[ib / kQWords][ib % kQWords] = 0;
+      }
+      const uint32_t c = __popc(wa) + __popc(wb);
+      uint32_t F;
+      uint32_t p = qscan<NW>(S, c, &F);
+      if (F == 0) break;
+      while (wa) {
+        const uint32_t b = __builtin_ctz(wa);
+        wa &= wa - 1;
+        const uint32_t slot = (ia % kQWords) * 32 + b;
+        if (p < 2 * kQLimit) S.list[p] = (uint16_t)(((ia / kQWords) << 11) | slot);
+        p++;
+      }
+      while (wb) {
+        const uint32_t b = __builtin_ctz(wb);
+        wb &= wb - 1;
+        const uint32_t slot = (ib % kQWords) * 32 + b;
+        if (p < 2 * kQLimit) S.list[p] = (uint16_t)(((ib / kQWords) << 11) | slot);
+        p++;
+      }
+      if (F > 2 * kQLimit) F = 2 * kQLimit;  // only after an overflow (then discarded)
+      qsync<NW>();
+      uint32_t fresh0 = 0, fresh1 = 0;
+      for (uint32_t cb = wv * kWave; cb < F; cb += NT) {
+        const uint32_t i = cb + l;
+        uint32_t rs = 0, rl = 0, dx = 0, dr = 0;
+        if (i < F) {
+          const uint32_t e = S.list[i];
+          dr = e >> 11;
+          const uint32_t slot = e & (kQCap - 1);
+          const uint32_t vx = S.key[dr][slot];
+          dx = __hip_atomic_load(&S.dist[dr][slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const uint32_t *o = dr ? dnoff : upoff;
+          rs = o[vx];
+          rl = o[vx + 1] - rs;
+        }
+        const uint32_t incl = gscan_incl<kWave>(rl);
+        const uint32_t T = __shfl(incl, kWave - 1, kWave);
+        for (uint32_t i0 = 0; i0 < T; i0 += kWave * kQUnroll) {
+          uint2 a[kQUnroll];
+          uint32_t sd[kQUnroll], sdr[kQUnroll];
+#pragma unroll
+          for (int u = 0; u < kQUnroll; u++) {
+            const uint32_t idx = i0 + u * kWave + l;
+            a[u] = make_uint2(SP_EMPTY32, 0u);
+            sd[u] = 0;
+            sdr[u] = 0;
+            if (i0 + u * kWave < T) {  // uniform across the wave
+              const int src = gfind<kWave>(incl, idx);
+              const uint32_t srs = __shfl(rs, src, kWave), sinc = __shfl(incl, src, kWave);
+              const uint32_t srl = __shfl(rl, src, kWave);
+              sd[u] = __shfl(dx, src, kWave);
+              sdr[u] = __shfl(dr, src, kWave);
+              if (idx < T) a[u] = (sdr[u] ? dnarc : uparc)[srs + (idx - (sinc - srl))];
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kQUnroll; u++) {
+            if (a[u].x == SP_EMPTY32) continue;
+            const unsigned long long nd = (unsigned long long)sd[u] + a[u].y;
+            if (nd > 0xFFFFFFFEull) {
+              atomicOr(&S.ovf, 1u);
+              continue;
+            }
+            uint32_t fr = 0;
+            const int y = qins(S, sdr[u], a[u].x, &fr);
+            if (y < 0) {
+              atomicOr(&S.ovf, 1u);
+              continue;
+            }
+            if (sdr[u]) fresh1 += fr;
+            else fresh0 += fr;
+            const uint32_t old = atomicMin(&S.dist[sdr[u]][y], (uint32_t)nd);
+            if ((uint32_t)nd < old) atomicOr(&S.bits[sdr[u]][y >> 5], 1u << (y & 31));
+          }
+        }
+      }
+      fresh0 = gsum<kWave>(fresh0);
+      fresh1 = gsum<kWave>(fresh1);
+      if (l == 0) {
+        const uint32_t u0 = atomicAdd(&S.used[0], fresh0) + fresh0;
+        const uint32_t u1 = atomicAdd(&S.used[1], fresh1) + fresh1;
+        if (u0 > kQLimit || u1 > kQLimit) atomicOr(&S.ovf, 1u);
+      }
+      qsync<NW>();
+      if (S.ovf) break;
+    }
+    qsync<NW>();
+    const bool ok = S.ovf == 0;
+    if (ok) {
+      unsigned long long best = SP_INF64;
+      for (uint32_t i = tid; i < kQCap; i += NT) {
+        const uint32_t v = S.key[0][i];
+        if (v == SP_EMPTY32) continue;
+        const int b = qfind(S, 1, v);
+        if (b >= 0) {
+          const unsigned long long c2 =
+              (unsigned long long)S.dist[0][i] + (unsigned long long)S.dist[1][b];
+          best = c2 < best ? c2 : best;
+        }
+      }
+      best = gmin64<kWave>(best);
+      if constexpr (NW > 1) {
+        if (l == 0) S.wmin[wv] = best;
+        __syncthreads();
+        for (int i = 0; i < NW; i++) best = S.wmin[i] < best ? S.wmin[i] : best;
+      }
+      if (tid == 0) {
+        dist[k] = best;
+        if (visited) visited[k] = S.used[0] + S.used[1];
+      }
+    } else if (tid == 0) {
+      const uint32_t p2 = atomicAdd(ovf_count, 1u);
+      ovf_list[p2] = (uint32_t)k;
+    }
+    qsync<NW>();
+    for (uint32_t i = tid; i < kQCap; i += NT) {
+      S.key[0][i] = SP_EMPTY32;
+      S.key[1][i] = SP_EMPTY32;
+      S.dist[0][i] = SP_INF32;
+      S.dist[1][i] = SP_INF32;
+    }
+    for (uint32_t i = tid; i < 2 * kQWords; i += NT) S.bits[i / kQWords][i % kQWords] = 0;
+    if (tid < 2) S.used[tid] = 0;
+    if (tid == 0) S.ovf = 0;
+    qsync<NW>();
   }
 }
 
@@ -609,11 +812,18 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   if (hc[1]) return set_error(CH_E_INVALID, "a query vertex id is >= n");
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device);
-  const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 8);
-  k_query<<<(unsigned)g, 64, 0, st>>>(q, ds, dt, ch->rank.as<uint32_t>(),
-                                      ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(),
-                                      ch->q_dnoff.as<uint32_t>(), ch->q_dnarc.as<uint2>(), dd,
-                                      dv, ch->q_ovf.as<uint32_t>(), ctr);
+  // four query tables fit in one CU's LDS
+  const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 4);
+  const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
+#define SP_QUERY_LAUNCH(NW)                                                                   \
+  k_query<NW><<<(unsigned)g, 64 * NW, 0, st>>>(                                              \
+      q, ds, dt, ch->rank.as<uint32_t>(), ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(), \
+      ch->q_dnoff.as<uint32_t>(), ch->q_dnarc.as<uint2>(), dd, dv, ch->q_ovf.as<uint32_t>(),   \
+      ctr)
+  if (nw == 1) SP_QUERY_LAUNCH(1);
+  else if (nw == 2) SP_QUERY_LAUNCH(2);
+  else SP_QUERY_LAUNCH(4);
+#undef SP_QUERY_LAUNCH
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));

@@ -74,9 +74,12 @@ def test_grid64_bit_exact_and_queries(gpu):
     od, _ = o.query_batch(s, t)
     assert np.array_equal(d, od)
     # query cost: the sizes of the two upward search spaces
-    d2, vis = ch.query_stats(s[:300], t[:300])
-    assert np.array_equal(d2, d[:300])
-    assert np.array_equal(vis.astype(np.int64), closure_sizes(o, s[:300], t[:300]))
+    cs = closure_sizes(o, s[:300], t[:300])
+    for nw in (1, 2, 4):
+        assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
+        d2, vis = ch.query_stats(s[:300], t[:300], waves=nw)
+        assert np.array_equal(d2, d[:300])
+        assert np.array_equal(vis.astype(np.int64), cs), nw
 
 
 def test_group_split_invariance(gpu):
@@ -182,6 +185,34 @@ def test_road_100k_bit_exact(gpu):
     assert np.array_equal(d, od)
     ref = reference_distances(off, dst, w, s[:20], t[:20])
     assert np.array_equal(d[:20], ref)
+
+
+def test_query_fallbacks(gpu):
+    # closures past the LDS tables (unit-weight grids have very large upward
+    # search spaces) and distances past 32 bits both take the global path
+    off, dst, w = synth.grid(100, 100, seed=1, wmin=1, wmax=1)
+    n = len(off) - 1
+    ch = gpu.build(off, dst, w, labels=synth.labels(n, 2))
+    s, t = synth.queries(n, 300, seed=4)
+    ref = reference_distances(off, dst, w, s, t)
+    for nw in (1, 2, 4):
+        d, vis = ch.query_stats(s, t, waves=nw)
+        assert np.array_equal(d, ref), nw
+        assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
+    # one direction holds more than 7/8 of a 2048-slot table
+    assert vis.max() > 2 * 1792
+    # a one-way path with increasing labels is contracted from its source
+    # end without shortcuts, so one upward search passes 2^32 on its own
+    k = 7
+    off, dst, w = synth.to_csr(k, np.arange(k - 1), np.arange(1, k),
+                               np.full(k - 1, 0x7FFFFFFF, np.int64))
+    ch = gpu.build(off, dst, w, labels=np.arange(k, dtype=np.uint32))
+    assert ch.summary["shortcuts"] == 0
+    s, t = (a.ravel().astype(np.uint32) for a in np.meshgrid(np.arange(k), np.arange(k)))
+    ref = reference_distances(off, dst, w, s, t)
+    assert ref.max(initial=0, where=ref != np.uint64(2**64 - 1)) == 6 * 0x7FFFFFFF
+    for nw in (1, 2, 4):
+        assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
 
 
 def test_batch_equals_single_builds(gpu):
