@@ -61,8 +61,8 @@ extern "C" {
 #define CH_F_NO_QUERY_INDEX 0x4u  /* skip the rank-space CSR (ch_query_batch then fails) */
 
 #define CH_Q_ON_DEVICE 0x1u       /* s, t, dist of ch_query_batch are device pointers */
-/* Waves that share one query (1, 2 or 4; 0 = the default, 4).  Results do
- * not depend on it. */
+/* Waves that share one query in the first (2048-slot) query tier (1, 2 or
+ * 4; 0 = the default, 4).  Results do not depend on it. */
 #define CH_Q_WAVES(nw) ((uint32_t)(nw) << 8)
 
 /* Input graph in CSR form, arcs grouped by tail vertex.
@@ -206,7 +206,9 @@ int ch_build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t 
  *   s, t: q vertex ids each; dist: q entries written by the call (caller-
  *   owned).  All three on the host, or on the device with CH_Q_ON_DEVICE.
  *   stream: hipStream_t (NULL = the CH's stream).
- * Returns after the distances are written.
+ * Returns after the distances are written.  The CH keeps query scratch and
+ * remembers which table size most of the last batch needed (a later batch
+ * starts there), so calls on one CH must not overlap.
  * Errors: CH_E_INVALID (NULL, id >= n, no query index), CH_E_OOM,
  * CH_E_DEVICE. */
 int ch_query_batch(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,

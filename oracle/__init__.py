@@ -121,6 +121,8 @@ def lib():
         L.orc_query_batch.restype = i32
         L.orc_dijkstra.argtypes = [u32, vp, vp, vp, u32, vp]
         L.orc_dijkstra.restype = i32
+        L.orc_dijkstra_settle.argtypes = [u32, vp, vp, vp, u32, u64, vp, vp]
+        L.orc_dijkstra_settle.restype = i32
         L.orc_overlay_dijkstra.argtypes = [vp, u32, vp]
         L.orc_overlay_dijkstra.restype = i32
         L.orc_default_label.argtypes = [u32, u64]
@@ -308,6 +310,20 @@ def dijkstra(off, dst, w, s):
     if rc:
         raise OracleError(rc, "orc_dijkstra")
     return d
+
+
+def dijkstra_settle(off, dst, w, s, max_settled):
+    """Dijkstra stopped after max_settled vertices: (dist, settled count);
+    dist is UINT64_MAX for every vertex not settled."""
+    off, dst, w = _csr(off, dst, w)
+    n = len(off) - 1
+    d = np.empty(n, np.uint64)
+    c = C.c_uint64()
+    rc = lib().orc_dijkstra_settle(n, _p(off), _p(dst), _p(w), int(s), int(max_settled), _p(d),
+                                   C.byref(c))
+    if rc:
+        raise OracleError(rc, "orc_dijkstra_settle")
+    return d, c.value
 
 
 def mlp_priority(w, x):

@@ -1383,6 +1383,45 @@ int orc_dijkstra(uint32_t n, const uint64_t *off, const uint32_t *dst,
   return ORC_OK;
 }
 
+int orc_dijkstra_settle(uint32_t n, const uint64_t *off, const uint32_t *dst,
+                        const uint32_t *w, uint32_t s, uint64_t max_settled, uint64_t *dist,
+                        uint64_t *n_settled) {
+  if (s >= n) return ORC_E_INVALID;
+  uint8_t *done = (uint8_t *)calloc(n ? n : 1, 1);
+  if (!done) return ORC_E_OOM;
+  for (uint32_t v = 0; v < n; v++) dist[v] = INF64;
+  heap_t h = {0};
+  uint64_t cnt = 0;
+  dist[s] = 0;
+  int rc = heap_push(&h, 0, s) ? ORC_E_OOM : ORC_OK;
+  while (rc == ORC_OK && h.n && cnt < max_settled) {
+    uint64_t d;
+    uint32_t x;
+    heap_pop(&h, &d, &x);
+    if (d != dist[x] || done[x]) continue;
+    done[x] = 1;
+    cnt++;
+    for (uint64_t e = off[x]; e < off[x + 1]; e++) {
+      uint64_t nd = d + w[e];
+      if (nd < dist[dst[e]]) {
+        dist[dst[e]] = nd;
+        if (heap_push(&h, nd, dst[e])) {
+          rc = ORC_E_OOM;
+          break;
+        }
+      }
+    }
+  }
+  /* tentative labels of unsettled vertices are not distances */
+  for (uint32_t v = 0; v < n; v++)
+    if (!done[v]) dist[v] = INF64;
+  free(h.k);
+  free(h.v);
+  free(done);
+  if (n_settled) *n_settled = cnt;
+  return rc;
+}
+
 int orc_overlay_dijkstra(const orc_state *st, uint32_t s, uint64_t *dist) {
   if (!st || s >= st->n) return ORC_E_INVALID;
   for (uint32_t v = 0; v < st->n; v++) dist[v] = INF64;

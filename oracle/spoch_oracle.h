@@ -156,6 +156,12 @@ int orc_load(uint32_t n, const uint32_t *rank, uint64_t nup, const uint32_t *up_
 int orc_dijkstra(uint32_t n, const uint64_t *off, const uint32_t *dst,
                  const uint32_t *w, uint32_t s, uint64_t *dist);
 
+/* Dijkstra that stops after settling max_settled vertices: dist[v] is the
+ * distance of every settled vertex and UINT64_MAX for all others. */
+int orc_dijkstra_settle(uint32_t n, const uint64_t *off, const uint32_t *dst,
+                        const uint32_t *w, uint32_t s, uint64_t max_settled, uint64_t *dist,
+                        uint64_t *n_settled);
+
 /* Single-source Dijkstra on the oracle's current overlay (alive vertices). */
 int orc_overlay_dijkstra(const orc_state *st, uint32_t s, uint64_t *dist);
 

@@ -31,7 +31,8 @@ struct ch_s {
   sp::DBuf q_upoff, q_uparc, q_dnoff, q_dnarc;  // offsets uint32[n+1], arcs uint2{other, w}
 
   // query scratch
-  sp::DBuf q_s, q_t, q_d, q_v, q_ovf, q_tab, q_ctr;
+  sp::DBuf q_s, q_t, q_d, q_v, q_ovf, q_ovf2, q_tab, q_gtab, q_ctr;
+  int q_first_tier = 1;  // query tier where the previous batch mostly ended
 
   // features at contraction (CH_F_RECORD_FEATURES), 8 floats per vertex
   bool has_rec = false;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <string>
 
 #include "builder.hpp"
@@ -467,44 +468,75 @@ __device__ unsigned long long meet(const QTab<IdxT, DistT, GL> &Fw, const QTab<I
 }
 
 // ---------------------------------------------------------------------------
-// Fast path: both upward closures of one query at once, in LDS.  Each
-// direction has an open-addressing table of kQCap slots (vertex, distance)
-// and one frontier bit per slot.  A level takes every flagged slot of both
+// Bitmap-frontier query: both upward closures of one query at once.  Each
+// direction has an open-addressing table of CAP slots (vertex, distance) and
+// one frontier bit per slot.  A level takes every flagged slot of both
 // directions (clearing the bits), expands them, and flags each slot whose
 // distance dropped; the closures are complete when no bit is set.  Arc loads
 // of a level are issued kQUnroll deep per lane before any of them is used.
-// A query goes to the global fallback when a table passes kQLimit entries or
-// a distance passes 32 bits.  NW waves share one query's tables.
+// A query moves to the next tier when a table passes 7/8 of CAP or a
+// distance passes 32 bits.  NW waves share one query's tables, which live in
+// LDS (GM = false: CAP 2048 fits four blocks in a CU, CAP 8192 one) or in
+// global memory (GM = true: one table set per block, reached through L2).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kQCap = 2048;
-constexpr uint32_t kQShift = 21;  // 32 - log2(kQCap)
-constexpr uint32_t kQLimit = kQCap * 7 / 8;
-constexpr uint32_t kQWords = kQCap / 32;
 constexpr int kQUnroll = 8;
 
+template <uint32_t CAP>
 struct QLds {
-  uint32_t key[2][kQCap];
-  uint32_t dist[2][kQCap];
-  uint32_t bits[2][kQWords];
-  uint16_t list[2 * kQLimit];  // flagged slots of one level: dir << 11 | slot
+  using Entry = typename std::conditional<(2 * CAP <= 65536), uint16_t, uint32_t>::type;
+  static constexpr uint32_t kLimit = CAP * 7 / 8;
+  static constexpr uint32_t kWords = CAP / 32;
+  static constexpr uint32_t kShift = 32 - __builtin_ctz(CAP);
+  uint32_t key[2][CAP];
+  uint32_t dist[2][CAP];
+  uint32_t bits[2][kWords];
+  Entry list[2 * kLimit];  // flagged slots of one level: dir * CAP + slot
   uint32_t used[2];
   uint32_t ovf;
-  uint32_t wsum[4];
-  unsigned long long wmin[4];
+  uint32_t wsum[16];
+  unsigned long long wmin[16];
 };
+static_assert(sizeof(QLds<2048>) * 4 <= 163840, "four 2048-slot query blocks per CU");
+static_assert(sizeof(QLds<8192>) <= 163840, "one 8192-slot query block per CU");
 
-template <int NW>
+// Table accessors: plain LDS accesses, or device-coherent ones for tables in
+// global memory (written by other waves' atomics, which bypass the CU's
+// vector L1).
+template <bool GM>
+__device__ __forceinline__ uint32_t qld(const uint32_t *p) {
+  if constexpr (GM) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <bool GM>
+__device__ __forceinline__ void qst(uint32_t *p, uint32_t v) {
+  if constexpr (GM) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+template <bool GM, typename E>
+__device__ __forceinline__ E qlde(const E *p) {
+  if constexpr (GM) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
+template <bool GM, typename E>
+__device__ __forceinline__ void qste(E *p, E v) {
+  if constexpr (GM) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else *p = v;
+}
+
+template <int NW, bool GM>
 __device__ __forceinline__ void qsync() {
+  if constexpr (GM) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
   if constexpr (NW == 1) wave_sync();
   else __syncthreads();
 }
 
 // Slot of v in direction d (inserted if absent); *fresh = 1 when inserted
 // here; -1 when the table is full.
-__device__ __forceinline__ int qins(QLds &S, uint32_t d, uint32_t v, uint32_t *fresh) {
-  uint32_t h = (v * 0x9E3779B1u) >> kQShift;
-  for (uint32_t probes = 0; probes < kQCap; probes++) {
-    const uint32_t k = __hip_atomic_load(&S.key[d][h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+template <bool GM, uint32_t CAP>
+__device__ __forceinline__ int qins(QLds<CAP> &S, uint32_t d, uint32_t v, uint32_t *fresh) {
+  uint32_t h = (v * 0x9E3779B1u) >> QLds<CAP>::kShift;
+  for (uint32_t probes = 0; probes < CAP; probes++) {
+    const uint32_t k = qld<GM>(&S.key[d][h]);
     if (k == v) return (int)h;
     if (k == SP_EMPTY32) {
       const uint32_t prev = atomicCAS(&S.key[d][h], SP_EMPTY32, v);
@@ -514,121 +546,136 @@ __device__ __forceinline__ int qins(QLds &S, uint32_t d, uint32_t v, uint32_t *f
       }
       if (prev == v) return (int)h;
     }
-    h = (h + 1) & (kQCap - 1);
+    h = (h + 1) & (CAP - 1);
   }
   return -1;
 }
 
-__device__ __forceinline__ int qfind(const QLds &S, uint32_t d, uint32_t v) {
-  uint32_t h = (v * 0x9E3779B1u) >> kQShift;
-  for (uint32_t probes = 0; probes < kQCap; probes++) {
-    const uint32_t k = S.key[d][h];
+template <bool GM, uint32_t CAP>
+__device__ __forceinline__ int qfind(const QLds<CAP> &S, uint32_t d, uint32_t v) {
+  uint32_t h = (v * 0x9E3779B1u) >> QLds<CAP>::kShift;
+  for (uint32_t probes = 0; probes < CAP; probes++) {
+    const uint32_t k = qld<GM>(&S.key[d][h]);
     if (k == v) return (int)h;
     if (k == SP_EMPTY32) return -1;
-    h = (h + 1) & (kQCap - 1);
+    h = (h + 1) & (CAP - 1);
   }
   return -1;
 }
 
 // Block-wide exclusive prefix of c over NW waves; *total = the block sum.
-template <int NW>
-__device__ __forceinline__ uint32_t qscan(QLds &S, uint32_t c, uint32_t *total) {
+template <int NW, bool GM, uint32_t CAP>
+__device__ __forceinline__ uint32_t qscan(QLds<CAP> &S, uint32_t c, uint32_t *total) {
   const uint32_t incl = gscan_incl<kWave>(c);
   if constexpr (NW == 1) {
     *total = __shfl(incl, kWave - 1, kWave);
     return incl - c;
   } else {
     const int wv = threadIdx.x / kWave;
-    if (lane_id() == kWave - 1) S.wsum[wv] = incl;
-    __syncthreads();
+    if (lane_id() == kWave - 1) qst<GM>(&S.wsum[wv], incl);
+    qsync<NW, GM>();
     uint32_t before = 0, all = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
-      const uint32_t x = S.wsum[i];
+      const uint32_t x = qld<GM>(&S.wsum[i]);
       before += i < wv ? x : 0u;
       all += x;
     }
-    __syncthreads();
+    qsync<NW, GM>();
     *total = all;
     return before + incl - c;
   }
 }
 
-template <int NW>
+template <bool GM, uint32_t CAP>
+__device__ __forceinline__ void qclear(QLds<CAP> &S, uint32_t tid, uint32_t nt) {
+  for (uint32_t i = tid; i < CAP; i += nt) {
+    qst<GM>(&S.key[0][i], SP_EMPTY32);
+    qst<GM>(&S.key[1][i], SP_EMPTY32);
+    qst<GM>(&S.dist[0][i], SP_INF32);
+    qst<GM>(&S.dist[1][i], SP_INF32);
+  }
+  for (uint32_t i = tid; i < 2 * QLds<CAP>::kWords; i += nt)
+    qst<GM>(&S.bits[i / QLds<CAP>::kWords][i % QLds<CAP>::kWords], 0u);
+  if (tid < 2) qst<GM>(&S.used[tid], 0u);
+  if (tid == 0) qst<GM>(&S.ovf, 0u);
+}
+
+// Queries: list ? list[i] for i < *nlist : i for i < q.  Queries that do
+// not fit go to ovf_list (count in *ovf_count).  GM: gtab holds one
+// QLds<CAP> per block.
+template <int NW, uint32_t CAP, bool GM>
 __global__ void __launch_bounds__(64 * NW) k_query(
-    uint64_t q, const uint32_t *__restrict__ qs, const uint32_t *__restrict__ qt,
+    uint64_t q, uint32_t n, const uint32_t *__restrict__ list,
+    const uint32_t *__restrict__ nlist, uint32_t *__restrict__ bad,
+    const uint32_t *__restrict__ qs, const uint32_t *__restrict__ qt,
     const uint32_t *__restrict__ rank, const uint32_t *__restrict__ upoff,
     const uint2 *__restrict__ uparc, const uint32_t *__restrict__ dnoff,
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
-    uint32_t *__restrict__ ovf_count) {
-  __shared__ QLds S;
+    uint32_t *__restrict__ ovf_count, QLds<CAP> *__restrict__ gtab) {
+  using L = QLds<CAP>;
+  using E = typename L::Entry;
+  constexpr bool kLds = !GM;
+  __shared__ typename std::conditional<kLds, L, char>::type sh;
+  L &S = *(GM ? gtab + blockIdx.x : reinterpret_cast<L *>(&sh));
   constexpr uint32_t NT = 64 * NW;
+  constexpr uint32_t kW2 = 2 * L::kWords;  // bitmap words of both directions
   const uint32_t tid = threadIdx.x;
   const int l = lane_id();
   const uint32_t wv = tid / kWave;
-  for (uint32_t i = tid; i < kQCap; i += NT) {
-    S.key[0][i] = SP_EMPTY32;
-    S.key[1][i] = SP_EMPTY32;
-    S.dist[0][i] = SP_INF32;
-    S.dist[1][i] = SP_INF32;
-  }
-  for (uint32_t i = tid; i < 2 * kQWords; i += NT) S.bits[i / kQWords][i % kQWords] = 0;
-  if (tid < 2) S.used[tid] = 0;
-  if (tid == 0) S.ovf = 0;
-  qsync<NW>();
-  for (uint64_t k = blockIdx.x; k < q; k += gridDim.x) {
+  const uint64_t nq = list ? (uint64_t)*nlist : q;
+  qclear<GM>(S, tid, NT);
+  qsync<NW, GM>();
+  for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+    const uint64_t k = list ? (uint64_t)list[qi] : qi;
+    if (qs[k] >= n || qt[k] >= n) {  // the same k in every thread
+      if (tid == 0) {
+        atomicOr(bad, 1u);
+        dist[k] = SP_INF64;
+      }
+      continue;
+    }
     if (tid < 2) {
       const uint32_t v = rank[tid ? qt[k] : qs[k]];
       uint32_t fresh = 0;
-      const int a = qins(S, tid, v, &fresh);  // an empty table has room
-      S.dist[tid][a] = 0;
-      S.bits[tid][a >> 5] = 1u << (a & 31);
-      S.used[tid] = 1;
+      const int a = qins<GM>(S, tid, v, &fresh);  // an empty table has room
+      qst<GM>(&S.dist[tid][a], 0u);
+      qst<GM>(&S.bits[tid][a >> 5], 1u << (a & 31));
+      qst<GM>(&S.used[tid], 1u);
     }
-    qsync<NW>();
+    qsync<NW, GM>();
     for (;;) {
       // take the flags of both directions: words tid, tid + NT, ...
-      uint32_t wa = 0, wb = 0;
-      const uint32_t ia = tid, ib = tid + NT;
-      if (ia < 2 * kQWords) {
-        wa = S.bits[ia / kQWords][ia % kQWords];
-        S.bits[ia / kQWords][ia % kQWords] = 0;
-      }
-      if (NT < 2 * kQWords && ib < 2 * kQWords) {
-        wb = S.bits[ib / kQWords][ib % kQWords];
-        S.bits[ib / kQWords][ib % kQWords] = 0;
-      }
-      const uint32_t c = __popc(wa) + __popc(wb);
+      uint32_t c = 0;
+      for (uint32_t wi = tid; wi < kW2; wi += NT)
+        c += __popc(qld<GM>(&S.bits[wi / L::kWords][wi % L::kWords]));
       uint32_t F;
-      uint32_t p = qscan<NW>(S, c, &F);
+      uint32_t p = qscan<NW, GM>(S, c, &F);
       if (F == 0) break;
-      while (wa) {
-        const uint32_t b = __builtin_ctz(wa);
-        wa &= wa - 1;
-        const uint32_t slot = (ia % kQWords) * 32 + b;
-        if (p < 2 * kQLimit) S.list[p] = (uint16_t)(((ia / kQWords) << 11) | slot);
-        p++;
+      for (uint32_t wi = tid; wi < kW2; wi += NT) {
+        const uint32_t d = wi / L::kWords, wd = wi % L::kWords;
+        uint32_t x = qld<GM>(&S.bits[d][wd]);
+        qst<GM>(&S.bits[d][wd], 0u);
+        while (x) {
+          const uint32_t b = __builtin_ctz(x);
+          x &= x - 1;
+          if (p < 2 * L::kLimit) qste<GM>(&S.list[p], (E)(d * CAP + wd * 32 + b));
+          p++;
+        }
       }
-      while (wb) {
-        const uint32_t b = __builtin_ctz(wb);
-        wb &= wb - 1;
-        const uint32_t slot = (ib % kQWords) * 32 + b;
-        if (p < 2 * kQLimit) S.list[p] = (uint16_t)(((ib / kQWords) << 11) | slot);
-        p++;
-      }
-      if (F > 2 * kQLimit) F = 2 * kQLimit;  // only after an overflow (then discarded)
-      qsync<NW>();
+      if (F > 2 * L::kLimit) F = 2 * L::kLimit;  // only after an overflow (then discarded)
+      qsync<NW, GM>();
       uint32_t fresh0 = 0, fresh1 = 0;
       for (uint32_t cb = wv * kWave; cb < F; cb += NT) {
         const uint32_t i = cb + l;
         uint32_t rs = 0, rl = 0, dx = 0, dr = 0;
         if (i < F) {
-          const uint32_t e = S.list[i];
-          dr = e >> 11;
-          const uint32_t slot = e & (kQCap - 1);
-          const uint32_t vx = S.key[dr][slot];
-          dx = __hip_atomic_load(&S.dist[dr][slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          const uint32_t e = qlde<GM>(&S.list[i]);
+          dr = e / CAP;
+          const uint32_t slot = e & (CAP - 1);
+          const uint32_t vx = qld<GM>(&S.key[dr][slot]);
+          dx = qld<GM>(&S.dist[dr][slot]);
           const uint32_t *o = dr ? dnoff : upoff;
           rs = o[vx];
           rl = o[vx + 1] - rs;
@@ -662,7 +709,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
               continue;
             }
             uint32_t fr = 0;
-            const int y = qins(S, sdr[u], a[u].x, &fr);
+            const int y = qins<GM>(S, sdr[u], a[u].x, &fr);
             if (y < 0) {
               atomicOr(&S.ovf, 1u);
               continue;
@@ -679,63 +726,65 @@ __global__ void __launch_bounds__(64 * NW) k_query(
       if (l == 0) {
         const uint32_t u0 = atomicAdd(&S.used[0], fresh0) + fresh0;
         const uint32_t u1 = atomicAdd(&S.used[1], fresh1) + fresh1;
-        if (u0 > kQLimit || u1 > kQLimit) atomicOr(&S.ovf, 1u);
+        if (u0 > L::kLimit || u1 > L::kLimit) atomicOr(&S.ovf, 1u);
       }
-      qsync<NW>();
-      if (S.ovf) break;
+      qsync<NW, GM>();
+      if (qld<GM>(&S.ovf)) break;
     }
-    qsync<NW>();
-    const bool ok = S.ovf == 0;
+    qsync<NW, GM>();
+    const bool ok = qld<GM>(&S.ovf) == 0;
     if (ok) {
       unsigned long long best = SP_INF64;
-      for (uint32_t i = tid; i < kQCap; i += NT) {
-        const uint32_t v = S.key[0][i];
+      for (uint32_t i = tid; i < CAP; i += NT) {
+        const uint32_t v = qld<GM>(&S.key[0][i]);
         if (v == SP_EMPTY32) continue;
-        const int b = qfind(S, 1, v);
+        const int b = qfind<GM>(S, 1, v);
         if (b >= 0) {
-          const unsigned long long c2 =
-              (unsigned long long)S.dist[0][i] + (unsigned long long)S.dist[1][b];
+          const unsigned long long c2 = (unsigned long long)qld<GM>(&S.dist[0][i]) +
+                                        (unsigned long long)qld<GM>(&S.dist[1][b]);
           best = c2 < best ? c2 : best;
         }
       }
       best = gmin64<kWave>(best);
       if constexpr (NW > 1) {
-        if (l == 0) S.wmin[wv] = best;
-        __syncthreads();
-        for (int i = 0; i < NW; i++) best = S.wmin[i] < best ? S.wmin[i] : best;
+        if (l == 0) {
+          qst<GM>(reinterpret_cast<uint32_t *>(&S.wmin[wv]), (uint32_t)best);
+          qst<GM>(reinterpret_cast<uint32_t *>(&S.wmin[wv]) + 1, (uint32_t)(best >> 32));
+        }
+        qsync<NW, GM>();
+        for (int i = 0; i < NW; i++) {
+          const uint32_t *wp = reinterpret_cast<const uint32_t *>(&S.wmin[i]);
+          const unsigned long long x =
+              (unsigned long long)qld<GM>(wp) | ((unsigned long long)qld<GM>(wp + 1) << 32);
+          best = x < best ? x : best;
+        }
       }
       if (tid == 0) {
         dist[k] = best;
-        if (visited) visited[k] = S.used[0] + S.used[1];
+        if (visited) visited[k] = qld<GM>(&S.used[0]) + qld<GM>(&S.used[1]);
       }
     } else if (tid == 0) {
       const uint32_t p2 = atomicAdd(ovf_count, 1u);
       ovf_list[p2] = (uint32_t)k;
     }
-    qsync<NW>();
-    for (uint32_t i = tid; i < kQCap; i += NT) {
-      S.key[0][i] = SP_EMPTY32;
-      S.key[1][i] = SP_EMPTY32;
-      S.dist[0][i] = SP_INF32;
-      S.dist[1][i] = SP_INF32;
-    }
-    for (uint32_t i = tid; i < 2 * kQWords; i += NT) S.bits[i / kQWords][i % kQWords] = 0;
-    if (tid < 2) S.used[tid] = 0;
-    if (tid == 0) S.ovf = 0;
-    qsync<NW>();
+    qsync<NW, GM>();
+    qclear<GM>(S, tid, NT);
+    qsync<NW, GM>();
   }
 }
 
-// Fallback for queries whose closures outgrow LDS or 32-bit distances:
-// tables in global memory with cap >= 2n slots each (never overflow) and
-// 64-bit distances.
+// Queries whose closures outgrow LDS or 32-bit distances: tables of cap
+// slots in global memory with 64-bit distances.  With limit < cap a query
+// whose table passes limit entries goes to ovf_list; with cap >= 2n slots
+// and limit = cap no query overflows.
 __global__ void __launch_bounds__(64) k_query_global(
     uint32_t nlist, const uint32_t *__restrict__ list, const uint32_t *__restrict__ qs,
     const uint32_t *__restrict__ qt, const uint32_t *__restrict__ rank,
     const uint32_t *__restrict__ upoff, const uint2 *__restrict__ uparc,
     const uint32_t *__restrict__ dnoff, const uint2 *__restrict__ dnarc,
     unsigned long long *__restrict__ dist, uint32_t *__restrict__ visited,
-    uint32_t *__restrict__ tabs, uint32_t cap) {
+    uint32_t *__restrict__ tabs, uint32_t cap, uint32_t limit, uint32_t *__restrict__ ovf_list,
+    uint32_t *__restrict__ ovf_count) {
   // per direction: key[cap], dist[cap] (2 words each), flag[cap], order, fr0,
   // fr1 [cap] and 4 counters = 8 cap + 4 words
   const size_t per = (size_t)cap * 8 + 4;
@@ -752,28 +801,26 @@ __global__ void __launch_bounds__(64) k_query_global(
     T[d].ctr = b + 8 * (size_t)cap;
     T[d].cap = cap;
     T[d].shift = 32 - __builtin_ctz(cap);
-    T[d].limit = cap;
+    T[d].limit = limit;
   }
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
     const uint32_t k = list[i];
     const uint32_t rs = rank[qs[k]], rt = rank[qt[k]];
-    closure(T[0], upoff, uparc, rs);
-    closure(T[1], dnoff, dnarc, rt);
-    const unsigned long long mu = meet(T[0], T[1]);
-    if (lane_id() == 0) {
-      dist[k] = mu;
-      if (visited) visited[k] = T[0].ld(&T[0].ctr[0]) + T[1].ld(&T[1].ctr[0]);
+    bool ok = closure(T[0], upoff, uparc, rs);
+    if (ok) ok = closure(T[1], dnoff, dnarc, rt);
+    if (ok) {
+      const unsigned long long mu = meet(T[0], T[1]);
+      if (lane_id() == 0) {
+        dist[k] = mu;
+        if (visited) visited[k] = T[0].ld(&T[0].ctr[0]) + T[1].ld(&T[1].ctr[0]);
+      }
+    } else if (lane_id() == 0) {
+      const uint32_t p = atomicAdd(ovf_count, 1u);
+      ovf_list[p] = k;
     }
     qtab_reset(T[0]);
     qtab_reset(T[1]);
   }
-}
-
-__global__ void k_check_ids(uint64_t q, const uint32_t *__restrict__ s, const uint32_t *__restrict__ t,
-                            uint32_t n, uint32_t *__restrict__ bad) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q; i += stride)
-    if (s[i] >= n || t[i] >= n) atomicOr(bad, 1u);
 }
 
 int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t q, uint64_t *dist,
@@ -802,51 +849,87 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     dv = ch->q_v.as<uint32_t>();
   }
   HIP_TRY(ch->q_ovf.ensure(q * 4));
+  // Tiers: 1 = 2048-slot LDS tables (four blocks per CU), 2 = 8192-slot LDS
+  // tables (one block of 16 waves per CU), 3 = 16384-slot tables in global
+  // memory, 4 = tables of at least 2n slots with 64-bit distances (never
+  // overflow).  Each tier takes the previous one's overflow list; the first
+  // tier is the one where most queries of the previous batch ended.
+  // counters: [0] tier-1 overflows, [1] bad ids, [2] tier-2 overflows,
+  // [3] tier-3 overflows
   uint32_t *ctr = ch->q_ctr.as<uint32_t>();
+  HIP_TRY(ch->q_ovf2.ensure(q * 4));
   HIP_TRY(hipMemsetAsync(ctr, 0, 64, st));
-  k_check_ids<<<gridn(q), 256, 0, st>>>(q, ds, dt, ch->n, ctr + 1);
-  HIP_TRY(hipGetLastError());
-  uint32_t hc[2] = {0, 0};
-  HIP_TRY(hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (hc[1]) return set_error(CH_E_INVALID, "a query vertex id is >= n");
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device);
-  // four query tables fit in one CU's LDS
-  const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 4);
-  const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
-#define SP_QUERY_LAUNCH(NW)                                                                   \
-  k_query<NW><<<(unsigned)g, 64 * NW, 0, st>>>(                                              \
-      q, ds, dt, ch->rank.as<uint32_t>(), ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(), \
-      ch->q_dnoff.as<uint32_t>(), ch->q_dnarc.as<uint2>(), dd, dv, ch->q_ovf.as<uint32_t>(),   \
-      ctr)
-  if (nw == 1) SP_QUERY_LAUNCH(1);
-  else if (nw == 2) SP_QUERY_LAUNCH(2);
-  else SP_QUERY_LAUNCH(4);
+  const uint32_t *rank = ch->rank.as<uint32_t>();
+  const uint32_t *upoff = ch->q_upoff.as<uint32_t>(), *dnoff = ch->q_dnoff.as<uint32_t>();
+  const uint2 *uparc = ch->q_uparc.as<uint2>(), *dnarc = ch->q_dnarc.as<uint2>();
+  uint32_t *ovf1 = ch->q_ovf.as<uint32_t>(), *ovf2 = ch->q_ovf2.as<uint32_t>();
+  const int first = ch->q_first_tier;
+  if (first <= 1) {
+    const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 4);
+    const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
+#define SP_QUERY_LAUNCH(NW)                                                                    \
+  k_query<NW, 2048, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
+      q, ch->n, nullptr, nullptr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,   \
+      ovf1, ctr, nullptr)
+    if (nw == 1) SP_QUERY_LAUNCH(1);
+    else if (nw == 2) SP_QUERY_LAUNCH(2);
+    else SP_QUERY_LAUNCH(4);
 #undef SP_QUERY_LAUNCH
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(hc, ctr, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipGetLastError());
+  }
+  if (first <= 2) {
+    k_query<16, 8192, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
+        q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
+        dnarc, dd, dv, ovf2, ctr + 2, nullptr);
+    HIP_TRY(hipGetLastError());
+  }
+  uint32_t hc[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(hc, ctr, 16, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (hc[0]) {
+  if (hc[1]) return set_error(CH_E_INVALID, "a query vertex id is >= n");
+  const uint64_t into2 = first <= 1 ? hc[0] : q;
+  uint64_t n3 = first <= 2 ? hc[2] : q;
+  uint32_t *list3 = first <= 2 ? ovf2 : nullptr;
+  uint32_t n4 = 0;
+  if (n3) {
+    using T3 = QLds<16384>;
+    const uint64_t nb = std::min<uint64_t>(n3, (uint64_t)cus * 4);
+    HIP_TRY(ch->q_tab.ensure(nb * sizeof(T3)));
+    // overflows into ctr[4]; the input count is tier 2's, on the device
+    k_query<8, 16384, true><<<(unsigned)nb, 512, 0, st>>>(
+        q, ch->n, list3, ctr + 2, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,
+        ovf1, ctr + 4, reinterpret_cast<T3 *>(ch->q_tab.p));
+    HIP_TRY(hipGetLastError());
+    uint32_t h2[4] = {0, 0, 0, 0};  // ctr[1..4]
+    HIP_TRY(hipMemcpyAsync(h2, ctr + 1, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h2[0]) return set_error(CH_E_INVALID, "a query vertex id is >= n");
+    n4 = h2[3];
+  }
+  if (n4) {
     uint64_t c = 1;
     while (c < 2ull * ch->n + 2) c <<= 1;
     const uint32_t cap = (uint32_t)std::min<uint64_t>(c, 1ull << 31);
     const size_t per = ((size_t)cap * 8 + 4) * 4 * 2;
     const size_t ntab = std::max<size_t>(
-        1, std::min<size_t>({(size_t)hc[0], (size_t)cus * 2, (size_t)(4ull << 30) / per}));
-    HIP_TRY(ch->q_tab.ensure(ntab * per));
+        1, std::min<size_t>({(size_t)n4, (size_t)cus * 2, (size_t)(4ull << 30) / per}));
+    HIP_TRY(ch->q_gtab.ensure(ntab * per));
     // keys and dists all ones; flag, order, fronts, counters zero
     for (size_t k = 0; k < 2 * ntab; k++) {
-      uint32_t *b = ch->q_tab.as<uint32_t>() + k * ((size_t)cap * 8 + 4);
+      uint32_t *b = ch->q_gtab.as<uint32_t>() + k * ((size_t)cap * 8 + 4);
       HIP_TRY(fill_u32(b, SP_EMPTY32, 3ull * cap, st));
       HIP_TRY(hipMemsetAsync(b + 3ull * cap, 0, ((size_t)cap * 5 + 4) * 4, st));
     }
-    k_query_global<<<(unsigned)ntab, 64, 0, st>>>(
-        hc[0], ch->q_ovf.as<uint32_t>(), ds, dt, ch->rank.as<uint32_t>(),
-        ch->q_upoff.as<uint32_t>(), ch->q_uparc.as<uint2>(), ch->q_dnoff.as<uint32_t>(),
-        ch->q_dnarc.as<uint2>(), dd, dv, ch->q_tab.as<uint32_t>(), cap);
+    k_query_global<<<(unsigned)ntab, 64, 0, st>>>(n4, ovf1, ds, dt, rank, upoff, uparc, dnoff,
+                                                 dnarc, dd, dv, ch->q_gtab.as<uint32_t>(), cap,
+                                                 cap, ovf2, ctr + 6);
     HIP_TRY(hipGetLastError());
   }
+  // where the next batch starts
+  if (first <= 1 && hc[0] * 2 > q) ch->q_first_tier = 2;
+  if (first <= 2 && into2 && (uint64_t)hc[2] * 2 > into2) ch->q_first_tier = 3;
   if (!on_dev) HIP_TRY(hipMemcpyAsync(dist, dd, q * 8, hipMemcpyDeviceToHost, st));
   if (visited && !on_dev) HIP_TRY(hipMemcpyAsync(visited, dv, q * 4, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));

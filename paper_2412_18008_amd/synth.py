@@ -12,6 +12,8 @@ experiments (its OpenStreetMap, DIMACS and k-NN data are not available):
 * ``clustered_road``  the same construction over Gaussian "city" clusters
                       with travel-time weights (length / speed class);
 * ``chain``           a path with weights 1..32 (the paper's chain family);
+* ``fan``             a path plus a hub with arcs to all of it (a vertex
+                      whose upward search space is the whole graph);
 * ``random_digraph``  small random digraphs with self-loops, parallel arcs
                       and zero weights, for input-hygiene tests.
 
@@ -62,6 +64,17 @@ def grid(rows, cols, seed=0, wmin=1, wmax=1000):
     dst = np.concatenate([p[1] for p in pairs])
     w = rng.integers(wmin, wmax + 1, size=len(src), dtype=np.int64)
     return to_csr(rows * cols, src, dst, w)
+
+
+def fan(k, w_hub=1000):
+    """A bidirectional unit-weight path 0..k-1 and a hub k with one-way arcs
+    of weight w_hub to every path vertex.  The hub has no in-arcs, so it is
+    contracted first and its upward search space holds the whole path."""
+    i = np.arange(k - 1)
+    src = np.concatenate([i, i + 1, np.full(k, k)])
+    dst = np.concatenate([i + 1, i, np.arange(k)])
+    w = np.concatenate([np.ones(2 * (k - 1), np.int64), np.full(k, w_hub, np.int64)])
+    return to_csr(k + 1, src, dst, w)
 
 
 def _knn_edges(pts, k):

@@ -1,8 +1,28 @@
 """Helpers shared by the GPU parity tests: canonical forms of a CH export so
 that the GPU library and the oracle can be compared element by element."""
+import os
+import time
+
 import numpy as np
 
 import oracle
+
+_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+_T0 = time.time()
+
+
+def progress(msg):
+    """A progress line on stdout and, for runs whose output pytest captures,
+    appended to gpurun_out/test_progress.log under the repository."""
+    line = f"[{time.time() - _T0:8.1f}s] {msg}"
+    print(line, flush=True)
+    d = os.path.join(_ROOT, "gpurun_out")
+    try:
+        os.makedirs(d, exist_ok=True)
+        with open(os.path.join(d, "test_progress.log"), "a") as f:
+            f.write(line + "\n")
+    except OSError:
+        pass
 
 
 def oracle_export(o):

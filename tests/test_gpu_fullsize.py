@@ -1,0 +1,173 @@
+"""GPU parity at the full workload sizes.
+
+road-like 1M (the benchmarked workload, in the benchmark's launch
+configuration: device-resident input, tuned search-kernel knobs, statistics
+on): the whole CH is compared with the oracle's, element by element, and
+sampled query distances with the oracle's queries and Dijkstra's.
+
+clustered road-like 24M: too large for the oracle's full build, so the test
+checks what holds at any size -- every vertex contracted once, rank a
+permutation consistent with level, arcs oriented and sorted by rank, every
+shortcut's weight equal to the two CH arcs through its middle vertex, every
+input-arc entry equal to the lightest parallel input arc -- and sampled query
+distances against Dijkstra's on the input graph.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_18008_amd import autotune, synth
+from parity_util import (assert_export_order, assert_same_ch, gpu_export, gpu_round_counts,
+                         oracle_export, oracle_round_counts, progress)
+
+pytestmark = pytest.mark.gpu
+
+NONE = np.uint32(0xFFFFFFFF)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_18008_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def _device_build(gpu, off, dst, w, **kw):
+    import torch
+
+    dev = torch.device("cuda:0")
+    t_off = torch.from_numpy(off.astype(np.int64)).to(dev)
+    t_dst = torch.from_numpy(dst.astype(np.int32)).to(dev)
+    t_w = torch.from_numpy(w.astype(np.int32)).to(dev)
+    ch = gpu.build(t_off, t_dst, t_w, **kw)
+    torch.cuda.synchronize()
+    return ch
+
+
+def _keys(t, h):
+    return (t.astype(np.uint64) << np.uint64(32)) | h.astype(np.uint64)
+
+
+def _lookup(keys_sorted, vals_sorted, q):
+    i = np.searchsorted(keys_sorted, q)
+    i = np.minimum(i, len(keys_sorted) - 1)
+    found = keys_sorted[i] == q
+    return found, vals_sorted[i]
+
+
+def check_ch_properties(e, off, dst, w, rounds, sample=None, seed=0):
+    """Checks that hold for any CH; with `sample`, the per-arc checks run on
+    that many randomly chosen arcs of each kind."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+
+    def pick(mask):
+        idx = np.flatnonzero(mask)
+        if sample is not None and len(idx) > sample:
+            idx = np.sort(rng.choice(idx, size=sample, replace=False))
+        return idx
+
+    n = len(off) - 1
+    level, rank = e["level"], e["rank"]
+    assert np.all(level < rounds)
+    assert np.array_equal(np.bincount(rank, minlength=n), np.ones(n, np.int64))
+    # rank is ordered by level first
+    by_rank = np.empty(n, np.uint32)
+    by_rank[rank] = level
+    assert np.all(np.diff(by_rank.astype(np.int64)) >= 0)
+    progress("rank and level checked")
+    # arcs in rank space; the export's order makes these keys strictly
+    # increasing (upward by (tail, head), downward by (head, tail))
+    ut, uh = rank[e["up_tail"]], rank[e["up_head"]]
+    dt, dh = rank[e["down_tail"]], rank[e["down_head"]]
+    assert np.all(ut < uh) and np.all(dh < dt)
+    uk, dk = _keys(ut, uh), _keys(dh, dt)
+    assert np.all(uk[1:] > uk[:-1]) and np.all(dk[1:] > dk[:-1])
+    uw, dw = e["up_w"].astype(np.uint64), e["down_w"].astype(np.uint64)
+    progress("arc order checked")
+    # shortcut (u, v, w, x): down arc u -> x and up arc x -> v whose weights
+    # sum to w; x ranks below both ends
+    for tail, head, wt, mid in ((ut, uh, uw, e["up_mid"]), (dt, dh, dw, e["down_mid"])):
+        sc = pick(mid != NONE)
+        x = rank[mid[sc]]
+        a, b = tail[sc], head[sc]
+        assert np.all(x < np.minimum(a, b))
+        f1, w1 = _lookup(dk, dw, _keys(x, a))
+        f2, w2 = _lookup(uk, uw, _keys(x, b))
+        assert f1.all() and f2.all()
+        assert np.array_equal(w1 + w2, wt[sc])
+    progress("shortcut weights checked")
+    # entries for input arcs carry the lightest parallel input arc
+    src = np.repeat(np.arange(n, dtype=np.uint32), np.diff(off).astype(np.int64))
+    keep = src != dst
+    ik = _keys(src[keep], dst[keep])
+    iw = w[keep].astype(np.uint64)
+    if not np.all(ik[1:] >= ik[:-1]):
+        o = np.argsort(ik, kind="stable")
+        ik, iw = ik[o], iw[o]
+    starts = np.flatnonzero(np.concatenate([[True], ik[1:] != ik[:-1]]))
+    ik, iw = ik[starts], np.minimum.reduceat(iw, starts)
+    for tail, head, wt, mid in ((e["up_tail"], e["up_head"], uw, e["up_mid"]),
+                                (e["down_tail"], e["down_head"], dw, e["down_mid"])):
+        org = pick(mid == NONE)
+        f, wmin = _lookup(ik, iw, _keys(tail[org], head[org]))
+        assert f.all()
+        assert np.array_equal(wmin, wt[org])
+    progress("input arcs checked")
+
+
+def test_road1m_bench_config_bit_exact(gpu):
+    off, dst, w = synth.config_road1m(seed=0)
+    n, m = len(off) - 1, len(dst)
+    knobs = autotune.params_for(n, m)
+    progress(f"road1m n={n} m={m} knobs={knobs}")
+    ch = _device_build(gpu, off, dst, w, seed=0, stats=True, **knobs)
+    progress("road1m built on the GPU")
+    o = oracle.OracleCH(off, dst, w, seed=0).run()
+    progress("road1m built by the oracle")
+    a, b = oracle_export(o), gpu_export(ch)
+    assert_same_ch(a, b, "road1m")
+    assert_export_order(b)
+    assert ch.summary["rounds"] == o.rounds
+    assert gpu_round_counts(ch) == oracle_round_counts(o)
+    check_ch_properties(ch.export(), off, dst, w, ch.summary["rounds"])
+    s, t = synth.queries(n, 100_000, seed=3)
+    d = ch.query(s, t)
+    od, _ = o.query_batch(s[:20_000], t[:20_000])
+    assert np.array_equal(d[:20_000], od)
+    for src in np.unique(s)[:2]:
+        ref = oracle.dijkstra(off, dst, w, int(src))
+        sel = s == src
+        assert np.array_equal(d[sel], ref[t[sel]])
+
+
+@pytest.mark.timeout(900)
+def test_road24m_properties(gpu):
+    progress("generating road24m")
+    off, dst, w = synth.config_road24m(seed=0)
+    n, m = len(off) - 1, len(dst)
+    knobs = autotune.params_for(n, m)
+    progress(f"road24m n={n} m={m} knobs={knobs}")
+    ch = _device_build(gpu, off, dst, w, seed=0, **knobs)
+    progress(f"road24m built: {ch.summary}")
+    check_ch_properties(ch.export(), off, dst, w, ch.summary["rounds"], sample=2_000_000)
+    # sampled distances: Dijkstra stopped after 500k settled vertices gives
+    # exact distances to those; targets drawn among them
+    rng = np.random.Generator(np.random.PCG64(11))
+    for src in rng.integers(0, n, size=3):
+        ref, c = oracle.dijkstra_settle(off, dst, w, int(src), 500_000)
+        progress(f"Dijkstra from {src}: {c} settled")
+        fin = np.flatnonzero(ref != np.uint64(0xFFFFFFFFFFFFFFFF)).astype(np.uint32)
+        t = rng.choice(fin, size=min(3000, len(fin)), replace=False)
+        d = ch.query(np.full(len(t), src, np.uint32), t)
+        assert np.array_equal(d, ref[t])
+    # the benchmark's query batch; s == t gives 0
+    s, t = synth.queries(n, 1_000_000, seed=3)
+    d, vis = ch.query_stats(s, t)
+    progress(f"1M queries: mean visited {vis.mean():.0f}, max {vis.max()}")
+    assert np.all(d[s == t] == 0)
+    assert np.all(vis >= 2)

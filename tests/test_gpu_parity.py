@@ -187,20 +187,46 @@ def test_road_100k_bit_exact(gpu):
     assert np.array_equal(d[:20], ref)
 
 
-def test_query_fallbacks(gpu):
-    # closures past the LDS tables (unit-weight grids have very large upward
-    # search spaces) and distances past 32 bits both take the global path
+def test_query_tiers(gpu):
+    # Upward search spaces of every size: the hub of a fan graph reaches the
+    # whole path, so its queries need the 8192-slot LDS tier (k = 3000), the
+    # 16384-slot tier in global memory (k = 10000) and the last tier with
+    # tables of 2n slots (k = 60000); the path's own queries stay in the first
+    # tier.  Batches made only of hub queries move the CH's first tier up,
+    # which must not change any result.
+    for k in (3000, 10000, 60000):
+        off, dst, w = synth.fan(k)
+        n = len(off) - 1
+        print(f"[parity] fan k={k}", flush=True)
+        o, ch = _case(f"fan{k}", off, dst, w, synth.labels(n, 9), gpu)
+        rs, rt = synth.queries(n, 200, seed=k)
+        s = np.concatenate([np.full(40, k, np.uint32), rs, np.arange(0, k, k // 20, dtype=np.uint32)])
+        t = np.concatenate([rt[:40], rt, np.full(20, k, np.uint32)])
+        od, _ = o.query_batch(s, t)
+        cs = closure_sizes(o, s, t)
+        assert cs.max() > {3000: 1792, 10000: 7168, 60000: 14336}[k]
+        for nw in (1, 2, 4):
+            d, vis = ch.query_stats(s, t, waves=nw)
+            assert np.array_equal(d, od), nw
+            assert np.array_equal(vis.astype(np.int64), cs), nw
+        for _ in range(2):
+            d, vis = ch.query_stats(s[:40], t[:40])
+            assert np.array_equal(d, od[:40])
+            assert np.array_equal(vis.astype(np.int64), cs[:40])
+        d, vis = ch.query_stats(s, t)
+        assert np.array_equal(d, od)
+        assert np.array_equal(vis.astype(np.int64), cs)
+    # unit-weight grids have large upward search spaces too
     off, dst, w = synth.grid(100, 100, seed=1, wmin=1, wmax=1)
     n = len(off) - 1
     ch = gpu.build(off, dst, w, labels=synth.labels(n, 2))
     s, t = synth.queries(n, 300, seed=4)
     ref = reference_distances(off, dst, w, s, t)
     for nw in (1, 2, 4):
-        d, vis = ch.query_stats(s, t, waves=nw)
-        assert np.array_equal(d, ref), nw
         assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
-    # one direction holds more than 7/8 of a 2048-slot table
-    assert vis.max() > 2 * 1792
+
+
+def test_query_distances_past_32_bits(gpu):
     # a one-way path with increasing labels is contracted from its source
     # end without shortcuts, so one upward search passes 2^32 on its own
     k = 7

@@ -325,6 +325,22 @@ def test_dijkstra_against_closure(oracle_lib):
             assert np.array_equal(d, exp)
 
 
+def test_dijkstra_settle_is_a_prefix_of_dijkstra(oracle_lib):
+    # stopped after k settled vertices: exactly the k nearest (up to ties)
+    # carry their true distances, every other entry is UINT64_MAX
+    off, dst, w = synth.road_like(5000, seed=2)
+    full = oracle.dijkstra(off, dst, w, 17)
+    reach = int(np.count_nonzero(full != np.uint64(0xFFFFFFFFFFFFFFFF)))
+    for k in (1, 10, 777, reach, reach + 50):
+        d, c = oracle.dijkstra_settle(off, dst, w, 17, k)
+        fin = d != np.uint64(0xFFFFFFFFFFFFFFFF)
+        assert c == min(k, reach) == int(fin.sum())
+        assert np.array_equal(d[fin], full[fin])
+        assert d[17] == 0
+        if c < reach:
+            assert full[~fin].min() >= d[fin].max()
+
+
 def test_default_labels_are_fmix32(oracle_lib):
     # MurmurHash3 fmix32 reference values computed here from its definition
     def fmix32(h):
