@@ -160,25 +160,86 @@ __device__ __forceinline__ uint64_t memo_bucket(uint64_t k, uint32_t s, uint32_t
 
 // Returns the stored value or SP_INF32 when the pair is absent.  Slots are
 // read four at a time (independent loads inside one bucket), then checked
-// in probe order.
-__device__ __forceinline__ uint32_t memo_get(const MemoSlot *__restrict__ t, uint64_t bmask,
-                                             uint32_t s, uint32_t v, uint32_t *probes) {
+// in probe order.  The probe sequence starts at slot j0 of the first bucket
+// (the earlier slots known to hold neither the pair nor an empty slot).
+__device__ __forceinline__ uint32_t memo_get_from(const MemoSlot *__restrict__ t, uint64_t bmask,
+                                                  uint32_t s, uint32_t v, uint32_t j0,
+                                                  uint32_t *probes) {
   const uint64_t k = ((uint64_t)s << 32) | v;
   const uint32_t o = lowbias32(v ^ 0x9e3779b9u) & (kMemoBucket - 1);
   for (uint32_t i = 0;; i++) {
     const MemoSlot *b = t + memo_bucket(k, s, i, bmask) * kMemoBucket;
-    for (uint32_t j = 0; j < kMemoBucket; j += 4) {
+    for (uint32_t j = i == 0 ? j0 : 0; j < kMemoBucket; j += 4) {
       ulonglong2 e[4];
 #pragma unroll
       for (int q = 0; q < 4; q++)
         e[q] = *reinterpret_cast<const ulonglong2 *>(&b[(o + j + q) & (kMemoBucket - 1)]);
+      // first slot in probe order holding the pair or empty; selects keep
+      // e[] in registers (an indexed read would move it to scratch)
+      uint32_t r = SP_INF32;
+      bool done = false;
 #pragma unroll
       for (int q = 0; q < 4; q++) {
+        if (done) continue;
         (*probes)++;
-        if (e[q].x == k) return (uint32_t)e[q].y;
-        if (e[q].x == SP_EMPTY64) return SP_INF32;
+        if (e[q].x == k) {
+          r = (uint32_t)e[q].y;
+          done = true;
+        } else if (e[q].x == SP_EMPTY64) {
+          done = true;
+        }
+      }
+      if (done) return r;
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t memo_get(const MemoSlot *__restrict__ t, uint64_t bmask,
+                                             uint32_t s, uint32_t v, uint32_t *probes) {
+  return memo_get_from(t, bmask, s, v, 0, probes);
+}
+
+// Lookups per lane batched by the pair loops of score, contract and prune.
+constexpr int kPairBatch = 4;
+
+// K lookups at once: the first four slots of every lookup are loaded before
+// any is examined (4K independent loads in flight), the rare lookups that
+// need more slots continue one by one.  out[k] = SP_INF32 for inactive k.
+template <int K>
+__device__ __forceinline__ void memo_get_batch(const MemoSlot *__restrict__ t, uint64_t bmask,
+                                               const uint32_t (&s)[K], const uint32_t (&v)[K],
+                                               const bool (&act)[K], uint32_t (&out)[K],
+                                               uint32_t *probes) {
+  ulonglong2 e[K][4];
+  uint64_t key[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    key[k] = ((uint64_t)s[k] << 32) | v[k];
+    const uint32_t o = lowbias32(v[k] ^ 0x9e3779b9u) & (kMemoBucket - 1);
+    const MemoSlot *b = t + memo_bucket(key[k], s[k], 0, bmask) * kMemoBucket;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      e[k][q] = make_ulonglong2(SP_EMPTY64, 0ull);
+      if (act[k]) e[k][q] = *reinterpret_cast<const ulonglong2 *>(&b[(o + q) & (kMemoBucket - 1)]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    uint32_t r = SP_INF32;
+    bool done = !act[k];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (done) continue;
+      (*probes)++;
+      if (e[k][q].x == key[k]) {
+        r = (uint32_t)e[k][q].y;
+        done = true;
+      } else if (e[k][q].x == SP_EMPTY64) {
+        done = true;
       }
     }
+    if (!done) r = memo_get_from(t, bmask, s[k], v[k], 4, probes);
+    out[k] = r;
   }
 }
 

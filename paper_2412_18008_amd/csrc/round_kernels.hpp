@@ -279,11 +279,27 @@ __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__res
     const uint32_t s = vw[k];
     const uint32_t gs = ov.gid[s];
     const uint32_t e1 = ov.foff[s + 1];
-    for (uint32_t e = ov.foff[s] + gl; e < e1; e += G) {
-      const uint2 a = ov.farc[e];
-      const uint32_t d = memo_get(memo, bmask, gs, ov.gid[a.x], &probes);
-      if (d != SP_INF32 && a.y > d) {
-        ov.farc[e].y = SP_INF32;
+    for (uint32_t eb = ov.foff[s] + gl; eb < e1; eb += G * kPairBatch) {
+      uint2 arc[kPairBatch];
+      uint32_t ss[kPairBatch], gv[kPairBatch], dd[kPairBatch];
+      bool act[kPairBatch];
+#pragma unroll
+      for (int q = 0; q < kPairBatch; q++) {
+        const uint32_t e = eb + q * G;
+        act[q] = e < e1;
+        arc[q] = act[q] ? ov.farc[e] : make_uint2(0, SP_INF32);
+      }
+#pragma unroll
+      for (int q = 0; q < kPairBatch; q++) {
+        ss[q] = gs;
+        gv[q] = act[q] ? ov.gid[arc[q].x] : 0u;
+      }
+      memo_get_batch<kPairBatch>(memo, bmask, ss, gv, act, dd, &probes);
+#pragma unroll
+      for (int q = 0; q < kPairBatch; q++) {
+        const uint2 a = arc[q];
+        if (!act[q] || dd[q] == SP_INF32 || a.y <= dd[q]) continue;
+        ov.farc[eb + q * G].y = SP_INF32;
         const uint32_t end = ov.roff[a.x + 1];
         uint32_t lo = ov.roff[a.x], hi = end;
         while (lo < hi) {
@@ -307,6 +323,58 @@ __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__res
 // Number of pairs (v1, v2) in N_in(u) x N_out(u), v1 != v2, both arcs live,
 // whose path through u is no longer than the memoized distance or whose
 // distance is not memoized.  Every group lane must call it.
+// Pair p of N_in(u) x N_out(u) in row-major order: (in-arc index, out-arc
+// index); 32-bit division when the pair count allows it.
+__device__ __forceinline__ uint2 pair_index(uint64_t p, uint32_t dout, bool narrow) {
+  if (narrow) {
+    const uint32_t i = (uint32_t)p / dout;
+    return make_uint2(i, (uint32_t)p - i * dout);
+  }
+  const uint32_t i = (uint32_t)(p / dout);
+  return make_uint2(i, (uint32_t)(p - (uint64_t)i * dout));
+}
+
+// The pairs of u handled by one lane in one step: kPairBatch pairs p0 + k G,
+// their arcs, via lengths and memoized distances, with all loads of a kind
+// issued together.
+struct PairBatch {
+  uint2 a[kPairBatch], b[kPairBatch];
+  uint64_t via[kPairBatch];
+  uint32_t d[kPairBatch];
+  bool live[kPairBatch];
+};
+
+template <int G>
+__device__ __forceinline__ void load_pairs(const Overlay &ov, const MemoSlot *memo, uint64_t mmask,
+                                           uint32_t i0, uint32_t o0, uint32_t dout, uint64_t np,
+                                           bool narrow, uint64_t p0, PairBatch &B,
+                                           uint32_t *probes) {
+  uint32_t gs[kPairBatch], gv[kPairBatch];
+#pragma unroll
+  for (int k = 0; k < kPairBatch; k++) {
+    const uint64_t p = p0 + (uint64_t)k * G;
+    B.a[k] = make_uint2(0, SP_INF32);
+    B.b[k] = make_uint2(0, SP_INF32);
+    if (p < np) {
+      const uint2 ij = pair_index(p, dout, narrow);
+      B.a[k] = ov.rarc[i0 + ij.x];
+      B.b[k] = ov.farc[o0 + ij.y];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kPairBatch; k++) {
+    B.live[k] = B.a[k].y != SP_INF32 && B.b[k].y != SP_INF32 && B.a[k].x != B.b[k].x;
+    B.via[k] = (uint64_t)B.a[k].y + B.b[k].y;
+    gs[k] = 0;
+    gv[k] = 0;
+    if (B.live[k]) {
+      gs[k] = ov.gid[B.a[k].x];
+      gv[k] = ov.gid[B.b[k].x];
+    }
+  }
+  memo_get_batch<kPairBatch>(memo, mmask, gs, gv, B.live, B.d, probes);
+}
+
 template <int G>
 __device__ __forceinline__ uint32_t count_pairs(const Overlay &ov, const MemoSlot *memo,
                                                 uint64_t mmask, uint32_t u, uint32_t *probes) {
@@ -315,13 +383,13 @@ __device__ __forceinline__ uint32_t count_pairs(const Overlay &ov, const MemoSlo
   const uint32_t o0 = ov.foff[u], dout = ov.foff[u + 1] - o0;
   uint32_t cnt = 0;
   const uint64_t np = (uint64_t)din * dout;
-  for (uint64_t p = gl; p < np; p += G) {
-    const uint32_t i = (uint32_t)(p / dout), j = (uint32_t)(p - (uint64_t)i * dout);
-    const uint2 a = ov.rarc[i0 + i], b = ov.farc[o0 + j];
-    if (a.y == SP_INF32 || b.y == SP_INF32 || a.x == b.x) continue;
-    const uint64_t via = (uint64_t)a.y + b.y;
-    const uint32_t d = memo_get(memo, mmask, ov.gid[a.x], ov.gid[b.x], probes);
-    if (d == SP_INF32 || via <= d) cnt++;
+  const bool narrow = np <= 0xFFFFFFFFull;
+  for (uint64_t p0 = gl; p0 < np; p0 += (uint64_t)G * kPairBatch) {
+    PairBatch B;
+    load_pairs<G>(ov, memo, mmask, i0, o0, dout, np, narrow, p0, B, probes);
+#pragma unroll
+    for (int k = 0; k < kPairBatch; k++)
+      cnt += B.live[k] && (B.d[k] == SP_INF32 || B.via[k] <= B.d[k]);
   }
   return gsum<G>(cnt);
 }
@@ -562,36 +630,30 @@ __global__ void __launch_bounds__(256) k_contract(
     const uint64_t pend = pos + cpair[k];
     const uint32_t din = i1 - i0, dout = o1 - o0;
     const uint64_t np = (uint64_t)din * dout;
-    for (uint64_t p0 = 0; p0 < np; p0 += G) {
-      const uint64_t p = p0 + gl;
-      bool emit = false;
-      uint2 a = make_uint2(0, 0), b = make_uint2(0, 0);
-      uint64_t via = 0;
-      if (p < np) {
-        const uint32_t i = (uint32_t)(p / dout), j = (uint32_t)(p - (uint64_t)i * dout);
-        a = ov.rarc[i0 + i];
-        b = ov.farc[o0 + j];
-        if (a.y != SP_INF32 && b.y != SP_INF32 && a.x != b.x) {
-          via = (uint64_t)a.y + b.y;
-          const uint32_t d = memo_get(memo, mmask, ov.gid[a.x], ov.gid[b.x], &probes);
-          emit = d == SP_INF32 || via <= d;
+    const bool narrow = np <= 0xFFFFFFFFull;
+    for (uint64_t q0 = 0; q0 < np; q0 += (uint64_t)G * kPairBatch) {
+      PairBatch B;
+      load_pairs<G>(ov, memo, mmask, i0, o0, dout, np, narrow, q0 + gl, B, &probes);
+      // emit in pair order: chunk k holds pairs q0 + k G .. q0 + k G + G - 1
+#pragma unroll
+      for (int k = 0; k < kPairBatch; k++) {
+        const bool emit = B.live[k] && (B.d[k] == SP_INF32 || B.via[k] <= B.d[k]);
+        const uint64_t msk = gballot<G>(emit);
+        if (emit) {
+          if (B.via[k] > SP_MAXW) atomicOr(err, kErrOverflow);
+          const uint64_t at = pos + __popcll(msk & below);
+          if (at >= pend) {
+            atomicOr(err, kErrCapacity);
+          } else {
+            ekey[at] = ((uint64_t)B.a[k].x << kb) | B.b[k].x;
+            ew[at] = (uint32_t)B.via[k];
+            elab[at] = lab;
+            emid[at] = gu;
+            S[B.a[k].x] = 1;
+          }
         }
+        pos += __popcll(msk);
       }
-      const uint64_t msk = gballot<G>(emit);
-      if (emit) {
-        if (via > SP_MAXW) atomicOr(err, kErrOverflow);
-        const uint64_t at = pos + __popcll(msk & below);
-        if (at >= pend) {
-          atomicOr(err, kErrCapacity);
-          continue;
-        }
-        ekey[at] = ((uint64_t)a.x << kb) | b.x;
-        ew[at] = (uint32_t)via;
-        elab[at] = lab;
-        emid[at] = gu;
-        S[a.x] = 1;
-      }
-      pos += __popcll(msk);
     }
   }
 }

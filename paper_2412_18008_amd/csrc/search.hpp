@@ -173,16 +173,29 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
   uint32_t D = 0, nt = 0;
   {
     const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
-    for (uint32_t i = gl; i < used; i += G) {
-      const IdxT slot = T.ldi(&T.order[i]);
-      const uint32_t v = T.ld(&T.key[slot]);
-      const uint32_t got = memo_get(memo, mmask, gs, ov.gid[v], &ss.probes);
-      if (got == SP_INF32) {
-        T.st(&T.flag[slot], kFlagTarget);
-        D = max(D, 0xFFFFFFFFu - T.ld(&T.dist[slot]));
-        nt++;
+    for (uint32_t i0 = gl; i0 < used; i0 += G * kPairBatch) {
+      IdxT slot[kPairBatch];
+      uint32_t ks[kPairBatch], kv[kPairBatch], got[kPairBatch];
+      bool act[kPairBatch];
+#pragma unroll
+      for (int q = 0; q < kPairBatch; q++) {
+        const uint32_t i = i0 + q * G;
+        act[q] = i < used;
+        slot[q] = act[q] ? T.ldi(&T.order[i]) : (IdxT)0;
+        ks[q] = gs;
+        kv[q] = act[q] ? ov.gid[T.ld(&T.key[slot[q]])] : 0u;
       }
-      T.st(&T.dist[slot], SP_INF32);
+      memo_get_batch<kPairBatch>(memo, mmask, ks, kv, act, got, &ss.probes);
+#pragma unroll
+      for (int q = 0; q < kPairBatch; q++) {
+        if (!act[q]) continue;
+        if (got[q] == SP_INF32) {
+          T.st(&T.flag[slot[q]], kFlagTarget);
+          D = max(D, 0xFFFFFFFFu - T.ld(&T.dist[slot[q]]));
+          nt++;
+        }
+        T.st(&T.dist[slot[q]], SP_INF32);
+      }
     }
   }
   D = gmax<G>(D);
