@@ -156,6 +156,7 @@ typedef struct {
   uint32_t ls_tier1;        /* first-tier search kernel used (CH_LS_16x128 ...)   */
   float ms_local_search;    /* device time of the first-tier witness-search kernel */
   float ms_total;           /* device time of the whole round (host gaps included) */
+  uint32_t n_ls_global;     /* sources searched with tables in global memory   */
 } ch_round_stats_t;
 
 /* Whole-build summary. */

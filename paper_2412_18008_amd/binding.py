@@ -85,7 +85,7 @@ class RoundStats(C.Structure):
         ("rows_expanded", C.c_uint64), ("arcs_scanned", C.c_uint64),
         ("memo_probes", C.c_uint64), ("memo_inserts", C.c_uint64),
         ("n_ls_fallback", C.c_uint32), ("ls_tier1", C.c_uint32), ("ms_local_search", C.c_float),
-        ("ms_total", C.c_float),
+        ("ms_total", C.c_float), ("n_ls_global", C.c_uint32),
     ]
 
 

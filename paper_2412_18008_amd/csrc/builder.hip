@@ -239,7 +239,7 @@ struct Builder {
         O.farc.as<uint2>(), O.fmid.as<uint32_t>());
     HIP_TRY(hipGetLastError());
     if (mu) {
-      k_swap_key<<<grid(mu), 256, 0, st>>>(ukey.as<uint64_t>(), &dc()->c32[C_HEADS], kb,
+      k_swap_key<<<grid(mu), 256, 0, st>>>(ukey.as<uint64_t>(), &dc()->c32[C_HEADS], mu, kb,
                                            ekey.as<uint64_t>());
       HIP_TRY(hipGetLastError());
       HIP_TRY(hipMemcpyAsync(ew.p, uw.p, (size_t)mu * 4, hipMemcpyDeviceToDevice, st));
@@ -359,15 +359,17 @@ struct Builder {
   void launch_select(const Overlay &v) {
     k_select<G><<<ggrid<G>(v.n), 256, 0, st>>>(v, key.as<uint64_t>(), F.as<uint8_t>());
   }
+  // counts of the selected vertices (count on the device, at most v.n)
   template <int G>
-  void launch_ccount(const Overlay &v, uint32_t nf) {
-    k_contract_count<G><<<ggrid<G>(nf), 256, 0, st>>>(
-        v, vf.as<uint32_t>(), nf, aflag.as<uint8_t>(), paircnt.as<uint32_t>(),
+  void launch_ccount(const Overlay &v, uint32_t cap) {
+    k_contract_count<G><<<ggrid<G>(cap), 256, 0, st>>>(
+        v, vf.as<uint32_t>(), &dc()->c32[C_NF], cap, aflag.as<uint8_t>(), paircnt.as<uint32_t>(),
         memo.as<MemoSlot>(), mcap / kMemoBucket - 1, cup.as<uint32_t>(), cdn.as<uint32_t>(),
         cpair.as<uint32_t>());
   }
+  // scanned positions at offset cap of cup, cdn, cpair
   template <int G>
-  void launch_contract(const Overlay &v, uint32_t nf, uint32_t round, int kb) {
+  void launch_contract(const Overlay &v, uint32_t nf, uint32_t cap, uint32_t round, int kb) {
     ArcOut up{ch->up_t.as<uint32_t>(), ch->up_h.as<uint32_t>(), ch->up_w.as<uint32_t>(),
               ch->up_m.as<uint32_t>()};
     ArcOut dn{ch->dn_t.as<uint32_t>(), ch->dn_h.as<uint32_t>(), ch->dn_w.as<uint32_t>(),
@@ -375,8 +377,8 @@ struct Builder {
     k_contract<G><<<ggrid<G>(nf), 256, 0, st>>>(
         v, vf.as<uint32_t>(), nf, ov[cur].P.as<int32_t>(), ch->label.as<uint32_t>(),
         memo.as<MemoSlot>(), mcap / kMemoBucket - 1, round, ch->level.as<uint32_t>(), ch->score.as<int32_t>(),
-        alive_g.as<uint8_t>(), cup.as<uint32_t>() + nf, cdn.as<uint32_t>() + nf,
-        cpair.as<uint32_t>() + nf, up, dn, ch->nup, ch->ndown, cpair.as<uint32_t>(), kb,
+        alive_g.as<uint8_t>(), cup.as<uint32_t>() + cap, cdn.as<uint32_t>() + cap,
+        cpair.as<uint32_t>() + cap, up, dn, ch->nup, ch->ndown, cpair.as<uint32_t>(), kb,
         ekey.as<uint64_t>(), ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(),
         S.as<uint8_t>(), newA.as<uint8_t>(), fstate(), &dc()->err);
   }
@@ -447,7 +449,7 @@ struct Builder {
     HIP_TRY(key.ensure(nn * 8));
     HIP_TRY(paircnt.ensure(nn * 4));
     HIP_TRY(newid.ensure(nn * 4));
-    HIP_TRY(cnt.ensure(nn * 4));
+    HIP_TRY(cnt.ensure((nn + 1) * 4));
     HIP_TRY(vw.ensure(nn * 4));
     HIP_TRY(va.ensure(nn * 4));
     HIP_TRY(vf.ensure(nn * 4));
@@ -491,14 +493,14 @@ struct Builder {
       // previous round's final readback)
       TRY(ensure_memo(next_bound));
       HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
+      const double thr = prm.dense_deg10 ? prm.dense_deg10 / 10.0 : 5.0;
+      const bool sparse = avgdeg <= thr;
       if (nw) {
         // tier 1: LDS tables sized for the overlay's degree (16 lanes x 128
         // slots on sparse overlays, 64 lanes x 2048 slots on dense ones);
         // sources whose search outgrows them go to a 4096-slot LDS tier
-        // (launched with its count on the device, so no host round trip),
-        // then to tables in global memory
-        const double thr = prm.dense_deg10 ? prm.dense_deg10 / 10.0 : 5.0;
-        const bool sparse = avgdeg <= thr;
+        // (launched with its count on the device), then, after the next
+        // readback, to tables in global memory
         uint32_t kind = sparse ? prm.ls_sparse : prm.ls_dense;
         if (kind == CH_LS_AUTO) kind = sparse ? CH_LS_16x128 : CH_LS_64x2048;
         rs.ls_tier1 = kind;
@@ -513,88 +515,99 @@ struct Builder {
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
         launch_ls<64, 4096>(v, ovf1.as<uint32_t>(), 0, &dc()->novf1, 2, 2);
         HIP_TRY(hipGetLastError());
-        TRY(readback());
-        rs.rows_expanded = hctr->ls.rows;
-        rs.arcs_scanned = hctr->ls.arcs;
-        rs.memo_probes = hctr->ls.probes;
-        rs.memo_inserts = hctr->ls.inserts;
-        rs.n_ls_fallback = hctr->novf1;
-        const uint32_t novf = hctr->novf2;
-        if (novf) {
-          const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
-          const size_t per = ((size_t)cap * 6 + 4) * 4;
-          size_t ntab = std::max<size_t>(1, std::min<size_t>({(size_t)novf, (size_t)cus * 2,
-                                                              (size_t)(4ull << 30) / per}));
-          HIP_TRY(gtabs.ensure(ntab * per));
-          // key, dist = all ones; flag, order, fronts, counters = 0
-          for (size_t t = 0; t < ntab; t++) {
-            uint32_t *b = gtabs.as<uint32_t>() + t * (per / 4);
-            HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));
-            HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, ((size_t)cap * 4 + 4) * 4, st));
-          }
-          k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
-              v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
-              mcap / kMemoBucket - 1, &dc()->ls2, gtabs.as<uint32_t>(), cap, f_ws.as<uint32_t>(),
-              &dc()->err);
+      }
+      // Steps 1 (pruning) to 4 (contraction counts) run before the searches
+      // are known to be complete; when a source needed the global tier they
+      // run again after it (pruning skips arcs it already pruned, the rest
+      // overwrite their outputs).
+      const int Gp = prm.group ? (int)prm.group : pick_group(avgdeg);
+      const int Gs = prm.group ? (int)prm.group : pick_group(avgdeg * avgdeg / 4.0);
+      const int Gsel = prm.group ? (int)prm.group : pick_group(avgdeg);
+      const uint32_t ncap = O.n;  // bound on the selected count
+      HIP_TRY(cup.ensure(((size_t)ncap * 2 + 1) * 4));
+      HIP_TRY(cdn.ensure(((size_t)ncap * 2 + 1) * 4));
+      HIP_TRY(cpair.ensure(((size_t)ncap * 2 + 1) * 4));
+      auto after_search = [&]() -> int {
+        // pruning at the end of Alg. 3
+        if (nw) {
+          dispatch(Gp, [&] { launch_prune<4>(v, nw); }, [&] { launch_prune<8>(v, nw); },
+                   [&] { launch_prune<16>(v, nw); }, [&] { launch_prune<32>(v, nw); },
+                   [&] { launch_prune<64>(v, nw); });
           HIP_TRY(hipGetLastError());
         }
-        TRY(readback());
-        TRY(check_err());
-        mcount += hctr->ls.inserts + hctr->ls2.inserts;
-        rs.n_targets = hctr->ls.targets + hctr->ls2.targets;
-
-        // pruning at the end of Alg. 3
-        const int Gp = prm.group ? (int)prm.group : pick_group(avgdeg);
-        dispatch(Gp, [&] { launch_prune<4>(v, nw); }, [&] { launch_prune<8>(v, nw); },
-                 [&] { launch_prune<16>(v, nw); }, [&] { launch_prune<32>(v, nw); },
-                 [&] { launch_prune<64>(v, nw); });
+        // ---- Step 2: Score (Alg. 4) ------------------------------------
+        if (na) {
+          dispatch(Gs, [&] { launch_score<4>(v, na); }, [&] { launch_score<8>(v, na); },
+                   [&] { launch_score<16>(v, na); }, [&] { launch_score<32>(v, na); },
+                   [&] { launch_score<64>(v, na); });
+          HIP_TRY(hipGetLastError());
+          if (prm.priority == CH_PRIO_LEARNED)
+            HIP_TRY(launch_mlp_priority(va.as<uint32_t>(), na, O.gid.as<uint32_t>(),
+                                        f_feat.as<float>(), mlpw.as<float>(), O.P.as<int32_t>(),
+                                        cus, st));
+        }
+        // ---- Step 3: Select (Alg. 5) -----------------------------------
+        k_keys<<<grid(O.n), 256, 0, st>>>(O.n, O.P.as<int32_t>(), O.gid.as<uint32_t>(),
+                                          ch->label.as<uint32_t>(), key.as<uint64_t>());
         HIP_TRY(hipGetLastError());
-      }
-
-      // ---- Step 2: Score (Alg. 4) --------------------------------------
-      const int Gs = prm.group ? (int)prm.group : pick_group(avgdeg * avgdeg / 4.0);
-      if (na) {
-        dispatch(Gs, [&] { launch_score<4>(v, na); }, [&] { launch_score<8>(v, na); },
-                 [&] { launch_score<16>(v, na); }, [&] { launch_score<32>(v, na); },
-                 [&] { launch_score<64>(v, na); });
+        dispatch(Gsel, [&] { launch_select<4>(v); }, [&] { launch_select<8>(v); },
+                 [&] { launch_select<16>(v); }, [&] { launch_select<32>(v); },
+                 [&] { launch_select<64>(v); });
         HIP_TRY(hipGetLastError());
-        if (prm.priority == CH_PRIO_LEARNED)
-          HIP_TRY(launch_mlp_priority(va.as<uint32_t>(), na, O.gid.as<uint32_t>(),
-                                      f_feat.as<float>(), mlpw.as<float>(), O.P.as<int32_t>(),
-                                      cus, st));
-      }
-
-      // ---- Step 3: Select (Alg. 5) -------------------------------------
-      k_keys<<<grid(O.n), 256, 0, st>>>(O.n, O.P.as<int32_t>(), O.gid.as<uint32_t>(),
-                                        ch->label.as<uint32_t>(), key.as<uint64_t>());
-      HIP_TRY(hipGetLastError());
-      const int Gsel = prm.group ? (int)prm.group : pick_group(avgdeg);
-      dispatch(Gsel, [&] { launch_select<4>(v); }, [&] { launch_select<8>(v); },
-               [&] { launch_select<16>(v); }, [&] { launch_select<32>(v); },
-               [&] { launch_select<64>(v); });
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(select_flags(F.as<uint8_t>(), O.n, vf.as<uint32_t>(), &dc()->c32[C_NF], tmp, st));
+        HIP_TRY(select_flags(F.as<uint8_t>(), O.n, vf.as<uint32_t>(), &dc()->c32[C_NF], tmp, st));
+        // ---- Step 4 counts (Alg. 6): arcs and shortcut pairs per selected
+        // vertex, exclusive scans into the second halves
+        dispatch(Gs, [&] { launch_ccount<4>(v, ncap); }, [&] { launch_ccount<8>(v, ncap); },
+                 [&] { launch_ccount<16>(v, ncap); }, [&] { launch_ccount<32>(v, ncap); },
+                 [&] { launch_ccount<64>(v, ncap); });
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(scan_u32(cup.as<uint32_t>(), cup.as<uint32_t>() + ncap, ncap, &dc()->c32[C_UP],
+                         tmp, st));
+        HIP_TRY(scan_u32(cdn.as<uint32_t>(), cdn.as<uint32_t>() + ncap, ncap, &dc()->c32[C_DN],
+                         tmp, st));
+        HIP_TRY(scan_u32(cpair.as<uint32_t>(), cpair.as<uint32_t>() + ncap, ncap,
+                         &dc()->c32[C_PAIR], tmp, st));
+        return CH_OK;
+      };
+      TRY(after_search());
       TRY(readback());
       TRY(check_err());
+      rs.rows_expanded = hctr->ls.rows;
+      rs.arcs_scanned = hctr->ls.arcs;
+      rs.memo_probes = hctr->ls.probes;
+      rs.memo_inserts = hctr->ls.inserts;
+      rs.n_ls_fallback = hctr->novf1;
+      const uint32_t novf = hctr->novf2;
+      rs.n_ls_global = novf;
+      if (novf) {
+        const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
+        const size_t per = ((size_t)cap * 6 + 4) * 4;
+        size_t ntab = std::max<size_t>(1, std::min<size_t>({(size_t)novf, (size_t)cus * 2,
+                                                            (size_t)(4ull << 30) / per}));
+        HIP_TRY(gtabs.ensure(ntab * per));
+        // key, dist = all ones; flag, order, fronts, counters = 0
+        for (size_t t = 0; t < ntab; t++) {
+          uint32_t *b = gtabs.as<uint32_t>() + t * (per / 4);
+          HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));
+          HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, ((size_t)cap * 4 + 4) * 4, st));
+        }
+        k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
+            v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
+            mcap / kMemoBucket - 1, &dc()->ls2, gtabs.as<uint32_t>(), cap, f_ws.as<uint32_t>(),
+            &dc()->err);
+        HIP_TRY(hipGetLastError());
+        TRY(after_search());
+        TRY(readback());
+        TRY(check_err());
+      }
+      mcount += hctr->ls.inserts + hctr->ls2.inserts;
+      rs.n_targets = hctr->ls.targets + hctr->ls2.targets;
       const uint32_t nf = hctr->c32[C_NF];
       rs.n_selected = nf;
       rs.n_pruned = hctr->pruned;
       if (nf == 0) return set_error(CH_E_DEVICE, "no vertex selected in a round (internal error)");
 
       // ---- Step 4: Contract (Alg. 6) -----------------------------------
-      HIP_TRY(cup.ensure(((size_t)nf * 2 + 1) * 4));
-      HIP_TRY(cdn.ensure(((size_t)nf * 2 + 1) * 4));
-      HIP_TRY(cpair.ensure(((size_t)nf * 2 + 1) * 4));
-      dispatch(Gs, [&] { launch_ccount<4>(v, nf); }, [&] { launch_ccount<8>(v, nf); },
-               [&] { launch_ccount<16>(v, nf); }, [&] { launch_ccount<32>(v, nf); },
-               [&] { launch_ccount<64>(v, nf); });
-      HIP_TRY(hipGetLastError());
-      // exclusive scans into the second halves (counts stay in the first)
-      HIP_TRY(scan_u32(cup.as<uint32_t>(), cup.as<uint32_t>() + nf, nf, &dc()->c32[C_UP], tmp, st));
-      HIP_TRY(scan_u32(cdn.as<uint32_t>(), cdn.as<uint32_t>() + nf, nf, &dc()->c32[C_DN], tmp, st));
-      HIP_TRY(scan_u32(cpair.as<uint32_t>(), cpair.as<uint32_t>() + nf, nf, &dc()->c32[C_PAIR],
-                       tmp, st));
-      TRY(readback());
       const uint32_t tup = hctr->c32[C_UP], tdn = hctr->c32[C_DN], ne = hctr->c32[C_PAIR];
       if (ch->nup + tup > up_cap) {
         uint64_t nc = std::max<uint64_t>((ch->nup + tup) * 3 / 2, up_cap * 2);
@@ -626,17 +639,18 @@ struct Builder {
       HIP_TRY(hipMemsetAsync(S.p, 0, O.n, st));
       HIP_TRY(hipMemsetAsync(newA.p, 0, O.n, st));
       const int kb = bits_for(O.n);
-      dispatch(Gs, [&] { launch_contract<4>(v, nf, round, kb); },
-               [&] { launch_contract<8>(v, nf, round, kb); },
-               [&] { launch_contract<16>(v, nf, round, kb); },
-               [&] { launch_contract<32>(v, nf, round, kb); },
-               [&] { launch_contract<64>(v, nf, round, kb); });
+      dispatch(Gs, [&] { launch_contract<4>(v, nf, ncap, round, kb); },
+               [&] { launch_contract<8>(v, nf, ncap, round, kb); },
+               [&] { launch_contract<16>(v, nf, ncap, round, kb); },
+               [&] { launch_contract<32>(v, nf, ncap, round, kb); },
+               [&] { launch_contract<64>(v, nf, ncap, round, kb); });
       HIP_TRY(hipGetLastError());
       ch->nup += tup;
       ch->ndown += tdn;
 
-      // shortcut set E+: sort candidates by (v1, v2), keep the minimum
-      uint32_t U = 0;
+      // shortcut set E+: sort candidates by (v1, v2), keep the minimum; the
+      // number U of distinct pairs stays on the device (C_HEADS)
+      const uint32_t *dU = &dc()->c32[C_HEADS];
       if (ne) {
         HIP_TRY(iota_u32(eidx.as<uint32_t>(), ne, st));
         HIP_TRY(radix_sort_u64(ekey.as<uint64_t>(), eidx.as<uint32_t>(), ekey_alt.as<uint64_t>(),
@@ -646,84 +660,77 @@ struct Builder {
         HIP_TRY(select_flags(ehead.as<uint8_t>(), ne, eheads.as<uint32_t>(), &dc()->c32[C_HEADS],
                              tmp, st));
         k_eplus_reduce<<<grid(ne), 256, 0, st>>>(
-            ekey.as<uint64_t>(), eidx.as<uint32_t>(), ne, eheads.as<uint32_t>(),
-            &dc()->c32[C_HEADS], ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(),
-            ukey.as<uint64_t>(), uw.as<uint32_t>(), umid.as<uint32_t>());
+            ekey.as<uint64_t>(), eidx.as<uint32_t>(), ne, eheads.as<uint32_t>(), dU,
+            ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(), ukey.as<uint64_t>(),
+            uw.as<uint32_t>(), umid.as<uint32_t>());
         HIP_TRY(hipGetLastError());
-        TRY(readback());
-        TRY(check_err());
-        U = hctr->c32[C_HEADS];
-        if (batch && U) {
-          k_count_by_graph<<<grid(U), 256, 0, st>>>(ukey.as<uint64_t>(), U, kb,
-                                                    O.gid.as<uint32_t>(), batch->gof,
-                                                    batch->shortcuts);
+        if (batch) {
+          k_count_by_graph<<<grid(ne), 256, 0, st>>>(ukey.as<uint64_t>(), dU, kb,
+                                                     O.gid.as<uint32_t>(), batch->gof,
+                                                     batch->shortcuts);
           HIP_TRY(hipGetLastError());
         }
-        k_swap_key<<<grid(U), 256, 0, st>>>(ukey.as<uint64_t>(), &dc()->c32[C_HEADS], kb,
-                                            rkey.as<uint64_t>());
+        // reverse order (v2, v1) over all ne entries; the U real keys sort
+        // in front of the padding
+        k_swap_key<<<grid(ne), 256, 0, st>>>(ukey.as<uint64_t>(), dU, ne, kb,
+                                             rkey.as<uint64_t>());
         HIP_TRY(hipGetLastError());
-        HIP_TRY(iota_u32(ridx.as<uint32_t>(), U, st));
+        HIP_TRY(iota_u32(ridx.as<uint32_t>(), ne, st));
         HIP_TRY(radix_sort_u64(rkey.as<uint64_t>(), ridx.as<uint32_t>(), rkey_alt.as<uint64_t>(),
-                               ridx_alt.as<uint32_t>(), U, 2 * kb, tmp, st));
-      } else {
-        TRY(readback());
-        TRY(check_err());
+                               ridx_alt.as<uint32_t>(), ne, 2 * kb, tmp, st));
       }
-      rs.n_shortcuts = U;
 
       // ---- overlay rebuild: drop V_F, merge E+ ---------------------------
+      // sized by bounds known here: n2 < O.n vertices, m2 <= O.m + ne arcs;
+      // the exact counts come with the round's last readback
       k_keep<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), cnt.as<uint32_t>());
       HIP_TRY(hipGetLastError());
       HIP_TRY(scan_u32(cnt.as<uint32_t>(), newid.as<uint32_t>(), O.n, &dc()->c32[C_NNEW], tmp, st));
-      TRY(readback());
-      const uint32_t n2 = hctr->c32[C_NNEW];
       OvBuf &N = ov[cur ^ 1];
-      N.n = n2;
-      HIP_TRY(N.foff.ensure(((size_t)n2 + 1) * 4));
-      HIP_TRY(N.roff.ensure(((size_t)n2 + 1) * 4));
-      HIP_TRY(N.gid.ensure(std::max<size_t>(n2, 1) * 4));
-      HIP_TRY(N.P.ensure(std::max<size_t>(n2, 1) * 4));
+      const uint64_t mcap2 = std::max<uint64_t>((uint64_t)O.m + ne, 1);
+      HIP_TRY(N.foff.ensure(((size_t)O.n + 2) * 4));
+      HIP_TRY(N.roff.ensure(((size_t)O.n + 2) * 4));
+      HIP_TRY(N.gid.ensure(std::max<size_t>(O.n, 1) * 4));
+      HIP_TRY(N.P.ensure(std::max<size_t>(O.n, 1) * 4));
+      HIP_TRY(N.farc.ensure(mcap2 * 8));
+      HIP_TRY(N.rarc.ensure(mcap2 * 8));
+      HIP_TRY(N.fmid.ensure(mcap2 * 4));
+      HIP_TRY(N.rmid.ensure(mcap2 * 4));
+      HIP_TRY(cnt.ensure(((size_t)O.n + 1) * 4));
+      // row lengths of the new overlay (new ids < n2, zero up to O.n), then
+      // offsets over O.n + 1 entries: foff[n2 .. O.n] all equal m2
+      HIP_TRY(hipMemsetAsync(cnt.p, 0, ((size_t)O.n + 1) * 4, st));
       k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, U,
+          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, dU,
           uw.as<uint32_t>(), umid.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, nullptr);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.foff.as<uint32_t>(), n2, N.foff.as<uint32_t>() + n2,
+      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.foff.as<uint32_t>(), O.n + 1, &dc()->c32[C_MF],
                        tmp, st));
+      HIP_TRY(hipMemsetAsync(cnt.p, 0, ((size_t)O.n + 1) * 4, st));
       k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), U,
+          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), dU,
           uw.as<uint32_t>(), umid.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, nullptr);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.roff.as<uint32_t>(), n2, N.roff.as<uint32_t>() + n2,
+      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.roff.as<uint32_t>(), O.n + 1, &dc()->c32[C_MR],
                        tmp, st));
-      HIP_TRY(hipMemcpyAsync(&dc()->c32[C_MF], N.foff.as<uint32_t>() + n2, 4,
-                             hipMemcpyDeviceToDevice, st));
-      HIP_TRY(hipMemcpyAsync(&dc()->c32[C_MR], N.roff.as<uint32_t>() + n2, 4,
-                             hipMemcpyDeviceToDevice, st));
-      TRY(readback());
-      const uint32_t m2 = hctr->c32[C_MF];
-      if (hctr->c32[C_MR] != m2)
-        return set_error(CH_E_DEVICE, "forward and reverse overlay disagree (internal error)");
-      N.m = m2;
-      HIP_TRY(N.farc.ensure(std::max<size_t>(m2, 1) * 8));
-      HIP_TRY(N.rarc.ensure(std::max<size_t>(m2, 1) * 8));
-      HIP_TRY(N.fmid.ensure(std::max<size_t>(m2, 1) * 4));
-      HIP_TRY(N.rmid.ensure(std::max<size_t>(m2, 1) * 4));
       k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, U,
+          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, dU,
           uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.foff.as<uint32_t>(),
           N.farc.as<uint2>(), N.fmid.as<uint32_t>());
       HIP_TRY(hipGetLastError());
       k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), U,
+          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), dU,
           uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
           N.rarc.as<uint2>(), N.rmid.as<uint32_t>());
       HIP_TRY(hipGetLastError());
-      // carry state; V_W' = V_S + N_in(V_S); V_A' = N(V_F)
-      HIP_TRY(hipMemsetAsync(wflag.p, 0, std::max<uint32_t>(n2, 1), st));
+      // carry state; V_W' = V_S + N_in(V_S); V_A' = N(V_F); flags are zero
+      // beyond the new vertex count
+      HIP_TRY(hipMemsetAsync(wflag.p, 0, std::max<uint32_t>(O.n, 1), st));
+      HIP_TRY(hipMemsetAsync(aflag_next.p, 0, std::max<uint32_t>(O.n, 1), st));
       k_carry<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), newid.as<uint32_t>(),
                                          O.gid.as<uint32_t>(), O.P.as<int32_t>(), S.as<uint8_t>(),
                                          newA.as<uint8_t>(), N.gid.as<uint32_t>(),
@@ -734,16 +741,31 @@ struct Builder {
                                                       newid.as<uint32_t>(), N.roff.as<uint32_t>(),
                                                       N.rarc.as<uint2>(), wflag.as<uint8_t>());
       HIP_TRY(hipGetLastError());
-      HIP_TRY(select_flags(wflag.as<uint8_t>(), n2, vw.as<uint32_t>(), &dc()->c32[C_UP], tmp, st));
-      HIP_TRY(select_flags(aflag_next.as<uint8_t>(), n2, va.as<uint32_t>(), &dc()->c32[C_DN],
+      HIP_TRY(select_flags(wflag.as<uint8_t>(), O.n, vw.as<uint32_t>(), &dc()->c32[C_UP], tmp, st));
+      HIP_TRY(select_flags(aflag_next.as<uint8_t>(), O.n, va.as<uint32_t>(), &dc()->c32[C_DN],
                            tmp, st));
       // upper bound on the next round's memo inserts: over every source s
-      // and affected out-neighbour u, the out-degree of u
-      HIP_TRY(hipMemsetAsync(&dc()->bound, 0, 8, st));
-      k_ls_bound_flags<<<grid(n2), 256, 0, st>>>(view(N), wflag.as<uint8_t>(),
-                                                  aflag_next.as<uint8_t>(), &dc()->bound);
-      HIP_TRY(hipGetLastError());
+      // and affected out-neighbour u, the out-degree of u (rows past the new
+      // vertex count are empty)
+      {
+        Overlay vb = view(N);
+        vb.n = O.n;
+        HIP_TRY(hipMemsetAsync(&dc()->bound, 0, 8, st));
+        k_ls_bound_flags<<<grid(O.n), 256, 0, st>>>(vb, wflag.as<uint8_t>(),
+                                                     aflag_next.as<uint8_t>(), &dc()->bound);
+        HIP_TRY(hipGetLastError());
+      }
+      if (stats) HIP_TRY(hipEventRecord(ev[4], st));
       TRY(readback());
+      TRY(check_err());
+      const uint32_t n2 = hctr->c32[C_NNEW], m2 = hctr->c32[C_MF];
+      if (hctr->c32[C_MR] != m2)
+        return set_error(CH_E_DEVICE, "forward and reverse overlay disagree (internal error)");
+      if (n2 >= O.n || m2 > mcap2)
+        return set_error(CH_E_DEVICE, "overlay rebuild out of bounds (internal error)");
+      N.n = n2;
+      N.m = m2;
+      rs.n_shortcuts = hctr->c32[C_HEADS];
       nw = hctr->c32[C_UP];
       na = hctr->c32[C_DN];
       next_bound = hctr->bound;
@@ -751,8 +773,6 @@ struct Builder {
       cur ^= 1;
       rs.overlay_arcs = m2;
       if (stats) {
-        HIP_TRY(hipEventRecord(ev[4], st));
-        HIP_TRY(hipEventSynchronize(ev[4]));
         float ls = 0.f, tot = 0.f;
         if (rs.n_sources) HIP_TRY(hipEventElapsedTime(&ls, ev[2], ev[3]));
         HIP_TRY(hipEventElapsedTime(&tot, ev[1], ev[4]));

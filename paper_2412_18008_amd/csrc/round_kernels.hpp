@@ -84,14 +84,21 @@ __global__ void k_csr_from_sorted(const uint64_t *__restrict__ key, const uint32
 }
 
 // (a << kb) | b  ->  (b << kb) | a
-__global__ void k_swap_key(const uint64_t *__restrict__ in, const uint32_t *mcount, int kb,
-                           uint64_t *__restrict__ out) {
+// out[i] = in[i] with its two kb-bit halves swapped for i < *mcount; the
+// entries up to cap get UINT64_MAX, which no key reaches (its halves would
+// be equal), so a sort over cap entries leaves the *mcount keys in front.
+__global__ void k_swap_key(const uint64_t *__restrict__ in, const uint32_t *mcount, uint32_t cap,
+                           int kb, uint64_t *__restrict__ out) {
   const uint32_t m = *mcount;
   const uint64_t lowmask = (1ull << kb) - 1ull;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
-    const uint64_t k = in[i];
-    out[i] = ((k & lowmask) << kb) | (k >> kb);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += stride) {
+    if (i < m) {
+      const uint64_t k = in[i];
+      out[i] = ((k & lowmask) << kb) | (k >> kb);
+    } else {
+      out[i] = ~0ull;
+    }
   }
 }
 
@@ -298,7 +305,8 @@ __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__res
 #pragma unroll
       for (int q = 0; q < kPairBatch; q++) {
         const uint2 a = arc[q];
-        if (!act[q] || dd[q] == SP_INF32 || a.y <= dd[q]) continue;
+        // arcs pruned by an earlier pass of this round stay as they are
+        if (!act[q] || a.y == SP_INF32 || dd[q] == SP_INF32 || a.y <= dd[q]) continue;
         ov.farc[eb + q * G].y = SP_INF32;
         const uint32_t end = ov.roff[a.x + 1];
         uint32_t lo = ov.roff[a.x], hi = end;
@@ -509,14 +517,25 @@ __global__ void __launch_bounds__(256) k_select(Overlay ov, const uint64_t *__re
 // ===========================================================================
 // Per selected vertex: live out-arcs, live in-arcs, shortcut pairs (the
 // pair count of the score when the vertex was rescored this round).
+// The selected count *nfp is read on the device; entries nf .. cap - 1 of
+// the three count arrays are set to zero so that they can be scanned over
+// cap entries.
 template <int G>
 __global__ void __launch_bounds__(256) k_contract_count(
-    Overlay ov, const uint32_t *__restrict__ vf, uint32_t nf, const uint8_t *__restrict__ aflag,
-    const uint32_t *__restrict__ paircnt, const MemoSlot *__restrict__ memo, uint64_t mmask,
-    uint32_t *__restrict__ cup, uint32_t *__restrict__ cdn, uint32_t *__restrict__ cpair) {
+    Overlay ov, const uint32_t *__restrict__ vf, const uint32_t *nfp, uint32_t cap,
+    const uint8_t *__restrict__ aflag, const uint32_t *__restrict__ paircnt,
+    const MemoSlot *__restrict__ memo, uint64_t mmask, uint32_t *__restrict__ cup,
+    uint32_t *__restrict__ cdn, uint32_t *__restrict__ cpair) {
   const uint32_t ngroups = gridDim.x * (blockDim.x / G);
   const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
   const int gl = glane<G>();
+  const uint32_t nf = *nfp;
+  for (uint32_t k = nf + blockIdx.x * blockDim.x + threadIdx.x; k < cap;
+       k += gridDim.x * blockDim.x) {
+    cup[k] = 0;
+    cdn[k] = 0;
+    cpair[k] = 0;
+  }
   uint32_t probes = 0;
   for (uint32_t k = g0; k < nf; k += ngroups) {
     const uint32_t u = vf[k];
@@ -807,9 +826,10 @@ __global__ void k_sub_base(uint64_t m, const uint32_t *__restrict__ in, uint32_t
 }
 
 // Batch bookkeeping: one count per distinct shortcut pair, by graph of v1.
-__global__ void k_count_by_graph(const uint64_t *__restrict__ ukey, uint32_t U, int kb,
+__global__ void k_count_by_graph(const uint64_t *__restrict__ ukey, const uint32_t *nU, int kb,
                                  const uint32_t *__restrict__ gid, const uint32_t *__restrict__ gof,
                                  unsigned long long *__restrict__ cnt) {
+  const uint32_t U = *nU;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < U; i += stride)
     atomicAdd(&cnt[gof[gid[(uint32_t)(ukey[i] >> kb)]]], 1ull);
@@ -832,11 +852,12 @@ __global__ void k_merge_rows(uint32_t n, int kb, const uint8_t *__restrict__ F,
                              const uint32_t *__restrict__ newid, const uint32_t *__restrict__ off,
                              const uint2 *__restrict__ arc, const uint32_t *__restrict__ mid,
                              const uint64_t *__restrict__ ekey, const uint32_t *__restrict__ eidx,
-                             uint32_t ne, const uint32_t *__restrict__ uw,
+                             const uint32_t *nrec, const uint32_t *__restrict__ uw,
                              const uint32_t *__restrict__ umid, uint32_t *__restrict__ cnt,
                              const uint32_t *__restrict__ noff, uint2 *__restrict__ narc,
                              uint32_t *__restrict__ nmid) {
   const uint64_t lowmask = (1ull << kb) - 1ull;
+  const uint32_t ne = *nrec;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     if (F[u]) continue;

@@ -241,6 +241,19 @@ def test_query_distances_past_32_bits(gpu):
         assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
 
 
+def test_global_search_tier(gpu):
+    # every leaf's witness search covers the whole star (3201 vertices, past
+    # 3/4 of the 4096-slot LDS tier), so round 0 finishes its searches in
+    # global memory and prunes, scores and selects a second time
+    off, dst, w = synth.star(3200, seed=5)
+    n = len(off) - 1
+    o, ch = _case("star3200", off, dst, w, synth.labels(n, 3), gpu)
+    assert ch.round_stats()[0]["n_ls_global"] > 0
+    s, t = synth.queries(n, 500, seed=2)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(ch.query(s, t), od)
+
+
 def test_batch_equals_single_builds(gpu):
     graphs = [synth.random_geometric_small(800, seed=1), synth.grid(9, 11, seed=2),
               synth.random_digraph(60, 240, seed=3, wmax=9, zero_frac=0.1, loops=True),
