@@ -91,6 +91,48 @@ struct Tab {
   }
 };
 
+// Arcs of up to G rows spread over the group: row r of lane r holds rl arcs
+// from farc[rs]; entry idx (< total, the sum of rl) belongs to the first lane
+// whose inclusive prefix `incl` exceeds it.  arc_batch<G>() entries per lane are
+// loaded before any is used (one latency per batch instead of per entry);
+// f(arc, aux of the owning row) runs for each, then the group syncs.
+// Wide groups read long rows (dense overlays); narrow groups keep their
+// registers for occupancy.
+template <int G>
+constexpr int arc_batch() { return G >= 64 ? 8 : 4; }
+template <int G>
+constexpr int memo_batch() { return G >= 32 ? kPairBatch : 2; }
+
+template <int G, typename IdxT, bool GL, typename Fn>
+__device__ __forceinline__ void for_row_arcs(const Tab<IdxT, GL> &T, const uint2 *__restrict__ farc,
+                                             uint32_t incl, uint32_t rs, uint32_t rl,
+                                             uint32_t aux, uint32_t total, Fn f) {
+  constexpr int kArcBatch = arc_batch<G>();
+  const int gl = glane<G>();
+  for (uint32_t i0 = 0; i0 < total; i0 += G * kArcBatch) {
+    uint2 b[kArcBatch];
+    uint32_t sa[kArcBatch];
+#pragma unroll
+    for (int u = 0; u < kArcBatch; u++) {
+      const uint32_t idx = i0 + u * G + gl;
+      b[u] = make_uint2(SP_EMPTY32, 0u);
+      sa[u] = 0;
+      if (i0 + u * G < total) {  // uniform across the group
+        const int src = gfind<G>(incl, idx);
+        const uint32_t srs = gshfl<G>(rs, src), sinc = gshfl<G>(incl, src);
+        const uint32_t srl = gshfl<G>(rl, src);
+        sa[u] = gshfl<G>(aux, src);
+        if (idx < total) b[u] = farc[srs + (idx - (sinc - srl))];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kArcBatch; u++)
+      if (b[u].x != SP_EMPTY32) f(b[u], sa[u]);
+    T.sync();
+    if (T.ld(&T.ctr[kCtrOvf])) break;
+  }
+}
+
 struct SearchStats {
   uint32_t rows = 0, arcs = 0, probes = 0, inserts = 0, targets = 0, searched = 0;
 };
@@ -145,24 +187,15 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     }
     const uint32_t incl = gscan_incl<G>(rl);
     const uint32_t total = gshfl<G>(incl, G - 1);
-    for (uint32_t i0 = 0; i0 < total; i0 += G) {
-      const uint32_t idx = i0 + gl;
-      const int src = gfind<G>(incl, idx);
-      const uint32_t srs = gshfl<G>(rs, src), sinc = gshfl<G>(incl, src);
-      const uint32_t srl = gshfl<G>(rl, src), sw = gshfl<G>(wsu, src);
-      if (idx < total) {
-        const uint2 b = ov.farc[srs + (idx - (sinc - srl))];
-        ss.arcs++;
-        if (b.x != s) {
-          const uint64_t via = (uint64_t)sw + b.y;
-          const uint32_t viac = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
-          const int slot = T.insert(b.x);
-          if (slot >= 0) atomicMin(&T.dist[slot], 0xFFFFFFFFu - viac);
-        }
+    for_row_arcs<G>(T, ov.farc, incl, rs, rl, wsu, total, [&](uint2 b, uint32_t sw) {
+      ss.arcs++;
+      if (b.x != s) {
+        const uint64_t via = (uint64_t)sw + b.y;
+        const uint32_t viac = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
+        const int slot = T.insert(b.x);
+        if (slot >= 0) atomicMin(&T.dist[slot], 0xFFFFFFFFu - viac);
       }
-      T.sync();
-      if (T.ld(&T.ctr[kCtrOvf])) break;
-    }
+    });
     if (T.ld(&T.ctr[kCtrOvf])) break;
   }
   T.sync();
@@ -172,22 +205,23 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
   }
   uint32_t D = 0, nt = 0;
   {
+    constexpr int K = memo_batch<G>();
     const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
-    for (uint32_t i0 = gl; i0 < used; i0 += G * kPairBatch) {
-      IdxT slot[kPairBatch];
-      uint32_t ks[kPairBatch], kv[kPairBatch], got[kPairBatch];
-      bool act[kPairBatch];
+    for (uint32_t i0 = gl; i0 < used; i0 += G * K) {
+      IdxT slot[K];
+      uint32_t ks[K], kv[K], got[K];
+      bool act[K];
 #pragma unroll
-      for (int q = 0; q < kPairBatch; q++) {
+      for (int q = 0; q < K; q++) {
         const uint32_t i = i0 + q * G;
         act[q] = i < used;
         slot[q] = act[q] ? T.ldi(&T.order[i]) : (IdxT)0;
         ks[q] = gs;
         kv[q] = act[q] ? ov.gid[T.ld(&T.key[slot[q]])] : 0u;
       }
-      memo_get_batch<kPairBatch>(memo, mmask, ks, kv, act, got, &ss.probes);
+      memo_get_batch<K>(memo, mmask, ks, kv, act, got, &ss.probes);
 #pragma unroll
-      for (int q = 0; q < kPairBatch; q++) {
+      for (int q = 0; q < K; q++) {
         if (!act[q]) continue;
         if (got[q] == SP_INF32) {
           T.st(&T.flag[slot[q]], kFlagTarget);
@@ -248,32 +282,23 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       }
       const uint32_t incl = gscan_incl<G>(rl);
       const uint32_t total = gshfl<G>(incl, G - 1);
-      for (uint32_t i0 = 0; i0 < total; i0 += G) {
-        const uint32_t idx = i0 + gl;
-        const int src = gfind<G>(incl, idx);
-        const uint32_t srs = gshfl<G>(rs, src), sinc = gshfl<G>(incl, src);
-        const uint32_t srl = gshfl<G>(rl, src), sdx = gshfl<G>(dx, src);
-        if (idx < total) {
-          const uint2 b = ov.farc[srs + (idx - (sinc - srl))];
-          ss.arcs++;
-          const uint64_t nd = (uint64_t)sdx + b.y;
-          if (nd <= D) {
-            const int y = T.insert(b.x);
-            if (y >= 0) {
-              const uint32_t old = atomicMin(&T.dist[y], (uint32_t)nd);
-              if ((uint32_t)nd < old) {
-                const uint32_t f = atomicOr(&T.flag[y], kFlagFront);
-                if (!(f & kFlagFront)) {
-                  const uint32_t p = atomicAdd(nn, 1u);
-                  if (p < T.cap) T.sti(&fn[p], (IdxT)y);
-                }
+      for_row_arcs<G>(T, ov.farc, incl, rs, rl, dx, total, [&](uint2 b, uint32_t sdx) {
+        ss.arcs++;
+        const uint64_t nd = (uint64_t)sdx + b.y;
+        if (nd <= D) {
+          const int y = T.insert(b.x);
+          if (y >= 0) {
+            const uint32_t old = atomicMin(&T.dist[y], (uint32_t)nd);
+            if ((uint32_t)nd < old) {
+              const uint32_t f = atomicOr(&T.flag[y], kFlagFront);
+              if (!(f & kFlagFront)) {
+                const uint32_t p = atomicAdd(nn, 1u);
+                if (p < T.cap) T.sti(&fn[p], (IdxT)y);
               }
             }
           }
         }
-        T.sync();
-        if (T.ld(&T.ctr[kCtrOvf])) break;
-      }
+      });
       if (T.ld(&T.ctr[kCtrOvf])) break;
     }
     T.sync();
