@@ -80,7 +80,7 @@ struct Builder {
 
   OvBuf ov[2];
   int cur = 0;
-  DBuf aflag, aflag_next, wflag, F, S, newA, key, paircnt, newid, cnt, vw, va, vf;
+  DBuf aflag, aflag_next, wflag, F, S, newA, key, paircnt, newid, cnt, cnt2, cnt3, vw, va, vf;
   DBuf memo, alive_g;
   uint64_t mcap = 0, mcount = 0;
   DBuf f_cn, f_depth, f_ws, f_feat, mlpw;  // learned-priority feature state
@@ -107,7 +107,7 @@ struct Builder {
     o[0].release();
     o[1].release();
     DBuf *all[] = {&aflag, &aflag_next, &wflag, &F, &S, &newA, &key, &paircnt, &newid, &cnt,
-                   &vw, &va, &vf, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
+                   &vw, &va, &vf, &cnt2, &cnt3, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
                    &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
                    &f_cn, &f_depth, &f_ws, &f_feat, &mlpw};
@@ -548,7 +548,8 @@ struct Builder {
         }
         // ---- Step 3: Select (Alg. 5) -----------------------------------
         k_keys<<<grid(O.n), 256, 0, st>>>(O.n, O.P.as<int32_t>(), O.gid.as<uint32_t>(),
-                                          ch->label.as<uint32_t>(), key.as<uint64_t>());
+                                          ch->label.as<uint32_t>(), key.as<uint64_t>(),
+                                          S.as<uint8_t>(), newA.as<uint8_t>());
         HIP_TRY(hipGetLastError());
         dispatch(Gsel, [&] { launch_select<4>(v); }, [&] { launch_select<8>(v); },
                  [&] { launch_select<16>(v); }, [&] { launch_select<32>(v); },
@@ -561,12 +562,10 @@ struct Builder {
                  [&] { launch_ccount<16>(v, ncap); }, [&] { launch_ccount<32>(v, ncap); },
                  [&] { launch_ccount<64>(v, ncap); });
         HIP_TRY(hipGetLastError());
-        HIP_TRY(scan_u32(cup.as<uint32_t>(), cup.as<uint32_t>() + ncap, ncap, &dc()->c32[C_UP],
-                         tmp, st));
-        HIP_TRY(scan_u32(cdn.as<uint32_t>(), cdn.as<uint32_t>() + ncap, ncap, &dc()->c32[C_DN],
-                         tmp, st));
-        HIP_TRY(scan_u32(cpair.as<uint32_t>(), cpair.as<uint32_t>() + ncap, ncap,
-                         &dc()->c32[C_PAIR], tmp, st));
+        HIP_TRY(scan3_u32(cup.as<uint32_t>(), cup.as<uint32_t>() + ncap, &dc()->c32[C_UP],
+                          cdn.as<uint32_t>(), cdn.as<uint32_t>() + ncap, &dc()->c32[C_DN],
+                          cpair.as<uint32_t>(), cpair.as<uint32_t>() + ncap, &dc()->c32[C_PAIR],
+                          ncap, tmp, st));
         return CH_OK;
       };
       TRY(after_search());
@@ -636,8 +635,6 @@ struct Builder {
       HIP_TRY(rkey_alt.ensure(ne1 * 8));
       HIP_TRY(ridx.ensure(ne1 * 4));
       HIP_TRY(ridx_alt.ensure(ne1 * 4));
-      HIP_TRY(hipMemsetAsync(S.p, 0, O.n, st));
-      HIP_TRY(hipMemsetAsync(newA.p, 0, O.n, st));
       const int kb = bits_for(O.n);
       dispatch(Gs, [&] { launch_contract<4>(v, nf, ncap, round, kb); },
                [&] { launch_contract<8>(v, nf, ncap, round, kb); },
@@ -652,8 +649,7 @@ struct Builder {
       // number U of distinct pairs stays on the device (C_HEADS)
       const uint32_t *dU = &dc()->c32[C_HEADS];
       if (ne) {
-        HIP_TRY(iota_u32(eidx.as<uint32_t>(), ne, st));
-        HIP_TRY(radix_sort_u64(ekey.as<uint64_t>(), eidx.as<uint32_t>(), ekey_alt.as<uint64_t>(),
+        HIP_TRY(sort_u64_index(ekey.as<uint64_t>(), eidx.as<uint32_t>(), ekey_alt.as<uint64_t>(),
                                eidx_alt.as<uint32_t>(), ne, 2 * kb, tmp, st));
         k_run_heads<<<grid(ne), 256, 0, st>>>(ekey.as<uint64_t>(), ne, ehead.as<uint8_t>());
         HIP_TRY(hipGetLastError());
@@ -675,15 +671,19 @@ struct Builder {
         k_swap_key<<<grid(ne), 256, 0, st>>>(ukey.as<uint64_t>(), dU, ne, kb,
                                              rkey.as<uint64_t>());
         HIP_TRY(hipGetLastError());
-        HIP_TRY(iota_u32(ridx.as<uint32_t>(), ne, st));
-        HIP_TRY(radix_sort_u64(rkey.as<uint64_t>(), ridx.as<uint32_t>(), rkey_alt.as<uint64_t>(),
+        HIP_TRY(sort_u64_index(rkey.as<uint64_t>(), ridx.as<uint32_t>(), rkey_alt.as<uint64_t>(),
                                ridx_alt.as<uint32_t>(), ne, 2 * kb, tmp, st));
       }
 
       // ---- overlay rebuild: drop V_F, merge E+ ---------------------------
       // sized by bounds known here: n2 < O.n vertices, m2 <= O.m + ne arcs;
       // the exact counts come with the round's last readback
-      k_keep<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), cnt.as<uint32_t>());
+      HIP_TRY(cnt2.ensure(((size_t)O.n + 1) * 4));
+      HIP_TRY(cnt3.ensure(((size_t)O.n + 1) * 4));
+      // keep flags; zero the row counts and the next round's flags
+      k_keep<<<grid(O.n + 1), 256, 0, st>>>(O.n, F.as<uint8_t>(), cnt.as<uint32_t>(),
+                                            cnt2.as<uint32_t>(), cnt3.as<uint32_t>(),
+                                            wflag.as<uint8_t>(), aflag_next.as<uint8_t>());
       HIP_TRY(hipGetLastError());
       HIP_TRY(scan_u32(cnt.as<uint32_t>(), newid.as<uint32_t>(), O.n, &dc()->c32[C_NNEW], tmp, st));
       OvBuf &N = ov[cur ^ 1];
@@ -696,25 +696,21 @@ struct Builder {
       HIP_TRY(N.rarc.ensure(mcap2 * 8));
       HIP_TRY(N.fmid.ensure(mcap2 * 4));
       HIP_TRY(N.rmid.ensure(mcap2 * 4));
-      HIP_TRY(cnt.ensure(((size_t)O.n + 1) * 4));
       // row lengths of the new overlay (new ids < n2, zero up to O.n), then
       // offsets over O.n + 1 entries: foff[n2 .. O.n] all equal m2
-      HIP_TRY(hipMemsetAsync(cnt.p, 0, ((size_t)O.n + 1) * 4, st));
       k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
           O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, dU,
-          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, nullptr);
+          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt2.as<uint32_t>(), nullptr, nullptr, nullptr);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.foff.as<uint32_t>(), O.n + 1, &dc()->c32[C_MF],
-                       tmp, st));
-      HIP_TRY(hipMemsetAsync(cnt.p, 0, ((size_t)O.n + 1) * 4, st));
       k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
           O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), dU,
-          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt.as<uint32_t>(), nullptr, nullptr, nullptr);
+          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt3.as<uint32_t>(), nullptr, nullptr, nullptr);
       HIP_TRY(hipGetLastError());
-      HIP_TRY(scan_u32(cnt.as<uint32_t>(), N.roff.as<uint32_t>(), O.n + 1, &dc()->c32[C_MR],
-                       tmp, st));
+      HIP_TRY(scan3_u32(cnt2.as<uint32_t>(), N.foff.as<uint32_t>(), &dc()->c32[C_MF],
+                        cnt3.as<uint32_t>(), N.roff.as<uint32_t>(), &dc()->c32[C_MR], nullptr,
+                        nullptr, nullptr, O.n + 1, tmp, st));
       k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
           O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, dU,
@@ -727,10 +723,8 @@ struct Builder {
           uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
           N.rarc.as<uint2>(), N.rmid.as<uint32_t>());
       HIP_TRY(hipGetLastError());
-      // carry state; V_W' = V_S + N_in(V_S); V_A' = N(V_F); flags are zero
-      // beyond the new vertex count
-      HIP_TRY(hipMemsetAsync(wflag.p, 0, std::max<uint32_t>(O.n, 1), st));
-      HIP_TRY(hipMemsetAsync(aflag_next.p, 0, std::max<uint32_t>(O.n, 1), st));
+      // carry state; V_W' = V_S + N_in(V_S); V_A' = N(V_F) (flags zeroed by
+      // k_keep, so they are zero beyond the new vertex count)
       k_carry<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), newid.as<uint32_t>(),
                                          O.gid.as<uint32_t>(), O.P.as<int32_t>(), S.as<uint8_t>(),
                                          newA.as<uint8_t>(), N.gid.as<uint32_t>(),
@@ -750,7 +744,7 @@ struct Builder {
       {
         Overlay vb = view(N);
         vb.n = O.n;
-        HIP_TRY(hipMemsetAsync(&dc()->bound, 0, 8, st));
+        // the bound accumulates into the counter cleared at the round start
         k_ls_bound_flags<<<grid(O.n), 256, 0, st>>>(vb, wflag.as<uint8_t>(),
                                                      aflag_next.as<uint8_t>(), &dc()->bound);
         HIP_TRY(hipGetLastError());

@@ -141,18 +141,80 @@ __global__ void k_tile_scan(const T *__restrict__ in, T *__restrict__ out, uint6
   if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kScanBlock - 1) *total = pre;
 }
 
+// ---------------------------------------------------------------------------
+// single-block primitives for small inputs (one launch each): 1024 threads x
+// 8 consecutive items
+// ---------------------------------------------------------------------------
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallItems = 8;
+constexpr uint32_t kSmallN = kSmallBlock * kSmallItems;
+
+template <typename T>
+__device__ T small_block_excl_scan(T v, T *total) {
+  __shared__ T wt[kSmallBlock / kWave];
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  T incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    T x = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += x;
+  }
+  if (lane == kWave - 1) wt[w] = incl;
+  __syncthreads();
+  T pre = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kSmallBlock / kWave; i++) {
+    pre += i < w ? wt[i] : (T)0;
+    tot += wt[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + incl - v;
+}
+
+// Exclusive scans of up to three arrays of n <= kSmallN entries (in == out
+// allowed); null `in` skips that array.
+template <typename T>
+__global__ void __launch_bounds__(kSmallBlock) k_scan_small(const T *in0, T *out0, T *tot0,
+                                                            const T *in1, T *out1, T *tot1,
+                                                            const T *in2, T *out2, T *tot2,
+                                                            uint32_t n) {
+  const T *ins[3] = {in0, in1, in2};
+  T *outs[3] = {out0, out1, out2};
+  T *tots[3] = {tot0, tot1, tot2};
+  const uint32_t base = threadIdx.x * kSmallItems;
+  for (int a = 0; a < 3; a++) {
+    if (!ins[a]) {
+      if (tots[a] && threadIdx.x == 0) *tots[a] = 0;
+      continue;
+    }
+    T v[kSmallItems];
+    T c = 0;
+#pragma unroll
+    for (int k = 0; k < kSmallItems; k++) {
+      v[k] = base + k < n ? ins[a][base + k] : (T)0;
+      c += v[k];
+    }
+    T tot;
+    T pre = small_block_excl_scan<T>(c, &tot);
+#pragma unroll
+    for (int k = 0; k < kSmallItems; k++) {
+      if (base + k < n) outs[a][base + k] = pre;
+      pre += v[k];
+    }
+    if (tots[a] && threadIdx.x == 0) *tots[a] = tot;
+  }
+}
+
 template <typename T>
 static hipError_t scan_impl(const T *in, T *out, uint64_t n, T *total, DBuf &tmp, size_t tmp_off,
                             hipStream_t st) {
-  if (n == 0) {
-    if (total) return hipMemsetAsync(total, 0, sizeof(T), st);
-    return hipSuccess;
-  }
-  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-  if (tiles == 1) {
-    k_tile_scan<T><<<1, kScanBlock, 0, st>>>(in, out, n, nullptr, total);
+  if (n <= kSmallN) {  // one launch, also for n == 0 (total = 0)
+    k_scan_small<T><<<1, kSmallBlock, 0, st>>>(in, out, total, nullptr, nullptr, nullptr,
+                                               nullptr, nullptr, nullptr, (uint32_t)n);
     return hipGetLastError();
   }
+  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
   // layout of tmp from tmp_off: sums[tiles] (recursion uses the space after)
   size_t need = tmp_off + (tiles + 64) * sizeof(T);
   if (need > tmp.cap) return hipErrorInvalidValue;
@@ -178,13 +240,34 @@ static size_t scan_tmp_bytes(uint64_t n) {
 
 hipError_t scan_u32(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *total, DBuf &tmp,
                     hipStream_t st) {
+  if (n && (!in || !out)) return hipErrorInvalidValue;
   hipError_t e = tmp.ensure(scan_tmp_bytes<uint32_t>(n));
   if (e != hipSuccess) return e;
   return scan_impl<uint32_t>(in, out, n, total, tmp, 0, st);
 }
 
+hipError_t scan3_u32(const uint32_t *in0, uint32_t *out0, uint32_t *tot0, const uint32_t *in1,
+                     uint32_t *out1, uint32_t *tot1, const uint32_t *in2, uint32_t *out2,
+                     uint32_t *tot2, uint32_t n, DBuf &tmp, hipStream_t st) {
+  if (n <= kSmallN) {
+    k_scan_small<uint32_t><<<1, kSmallBlock, 0, st>>>(in0, out0, tot0, in1, out1, tot1, in2, out2,
+                                                      tot2, n);
+    return hipGetLastError();
+  }
+  // arrays with a null input are skipped, as in the single-block kernel
+  const uint32_t *ins[3] = {in0, in1, in2};
+  uint32_t *outs[3] = {out0, out1, out2}, *tots[3] = {tot0, tot1, tot2};
+  for (int a = 0; a < 3; a++) {
+    if (!ins[a]) continue;
+    hipError_t e = scan_u32(ins[a], outs[a], n, tots[a], tmp, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *total, DBuf &tmp,
                     hipStream_t st) {
+  if (n && (!in || !out)) return hipErrorInvalidValue;
   hipError_t e = tmp.ensure(scan_tmp_bytes<uint64_t>(n));
   if (e != hipSuccess) return e;
   return scan_impl<uint64_t>(in, out, n, total, tmp, 0, st);
@@ -224,9 +307,33 @@ __global__ void k_flag_scatter(const uint8_t *__restrict__ f, uint32_t n,
     if (v[k]) out[pre++] = (uint32_t)(base + k);
 }
 
+__global__ void __launch_bounds__(kSmallBlock) k_flag_select_small(const uint8_t *__restrict__ f,
+                                                                   uint32_t n,
+                                                                   uint32_t *__restrict__ out,
+                                                                   uint32_t *__restrict__ count) {
+  const uint32_t base = threadIdx.x * kSmallItems;
+  uint8_t v[kSmallItems];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kSmallItems; k++) {
+    v[k] = base + k < n ? f[base + k] : 0;
+    c += v[k] != 0;
+  }
+  uint32_t tot;
+  uint32_t pre = small_block_excl_scan<uint32_t>(c, &tot);
+#pragma unroll
+  for (int k = 0; k < kSmallItems; k++)
+    if (v[k]) out[pre++] = base + k;
+  if (threadIdx.x == 0) *count = tot;
+}
+
 hipError_t select_flags(const uint8_t *flags, uint32_t n, uint32_t *out, uint32_t *count,
                         DBuf &tmp, hipStream_t st) {
-  if (n == 0) return hipMemsetAsync(count, 0, sizeof(uint32_t), st);
+  if (!count || (n && (!flags || !out))) return hipErrorInvalidValue;
+  if (n <= kSmallN) {  // one launch, also for n == 0
+    k_flag_select_small<<<1, kSmallBlock, 0, st>>>(flags, n, out, count);
+    return hipGetLastError();
+  }
   const uint32_t tiles = (n + kScanTile - 1) / kScanTile;
   hipError_t e = tmp.ensure((tiles + 64) * sizeof(uint32_t) + scan_tmp_bytes<uint32_t>(tiles));
   if (e != hipSuccess) return e;
@@ -352,6 +459,64 @@ hipError_t radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, ui
     e = hipMemcpyAsync(vals, va, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
   }
   return e;
+}
+
+// (key, index) sort of n <= kSmallSort entries in one block: bitonic network
+// in LDS over the keys' low `bits` bits, ties by index (the order a stable
+// sort gives); vals receive the original indices.
+constexpr uint32_t kSmallSort = 4096;
+
+__global__ void __launch_bounds__(kSmallBlock) k_sort_small_iota(uint64_t *__restrict__ keys,
+                                                                 uint32_t *__restrict__ vals,
+                                                                 uint32_t n, uint64_t mask) {
+  __shared__ uint64_t sk[kSmallSort];
+  __shared__ uint32_t sv[kSmallSort];
+  uint32_t np = 1;
+  while (np < n) np <<= 1;
+  for (uint32_t i = threadIdx.x; i < np; i += kSmallBlock) {
+    sk[i] = i < n ? keys[i] : ~0ull;
+    sv[i] = i < n ? i : 0xFFFFFFFFu;
+  }
+  __syncthreads();
+  for (uint32_t k = 2; k <= np; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < np; i += kSmallBlock) {
+        const uint32_t l = i ^ j;
+        if (l > i) {
+          const uint64_t a = sk[i] & mask, b = sk[l] & mask;
+          const bool gt = a > b || (a == b && sv[i] > sv[l]);
+          const bool up = (i & k) == 0;
+          if (gt == up) {
+            const uint64_t tk = sk[i];
+            sk[i] = sk[l];
+            sk[l] = tk;
+            const uint32_t tv = sv[i];
+            sv[i] = sv[l];
+            sv[l] = tv;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += kSmallBlock) {
+    keys[i] = sk[i];
+    vals[i] = sv[i];
+  }
+}
+
+hipError_t sort_u64_index(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                          uint32_t n, int bits, DBuf &tmp, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (!keys || !vals || (n > kSmallSort && (!keys_alt || !vals_alt))) return hipErrorInvalidValue;
+  if (n <= kSmallSort) {
+    const uint64_t mask = bits >= 64 ? ~0ull : ((1ull << bits) - 1ull);
+    k_sort_small_iota<<<1, kSmallBlock, 0, st>>>(keys, vals, n, mask);
+    return hipGetLastError();
+  }
+  hipError_t e = iota_u32(vals, n, st);
+  if (e != hipSuccess) return e;
+  return radix_sort_u64(keys, vals, keys_alt, vals_alt, n, bits, tmp, st);
 }
 
 }  // namespace sp

@@ -37,6 +37,15 @@ hipError_t radix_sort_u64(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt,
                           uint32_t *vals_alt, uint32_t n, int bits, DBuf &tmp, hipStream_t st);
 
 // Fill helpers.
+// Up to three exclusive scans of n entries each (one launch when n is
+// small); an array with a null input is skipped.
+hipError_t scan3_u32(const uint32_t *in0, uint32_t *out0, uint32_t *tot0, const uint32_t *in1,
+                     uint32_t *out1, uint32_t *tot1, const uint32_t *in2, uint32_t *out2,
+                     uint32_t *tot2, uint32_t n, DBuf &tmp, hipStream_t st);
+// Sort keys by their low `bits` bits; vals receive each key's original
+// index (ties in index order, as a stable sort).
+hipError_t sort_u64_index(uint64_t *keys, uint32_t *vals, uint64_t *keys_alt, uint32_t *vals_alt,
+                          uint32_t n, int bits, DBuf &tmp, hipStream_t st);
 hipError_t fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);
 hipError_t fill_u64(uint64_t *p, uint64_t v, size_t n, hipStream_t st);
 hipError_t fill_u8(uint8_t *p, uint8_t v, size_t n, hipStream_t st);

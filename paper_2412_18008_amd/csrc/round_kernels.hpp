@@ -481,11 +481,17 @@ __global__ void __launch_bounds__(256) k_score(Overlay ov, const uint32_t *__res
 // ===========================================================================
 // Select (Alg. 5)
 // ===========================================================================
+// Selection keys (priority, label); also clears the per-vertex flags S and
+// newA that the contraction sets.
 __global__ void k_keys(uint32_t n, const int32_t *__restrict__ P, const uint32_t *__restrict__ gid,
-                       const uint32_t *__restrict__ label, uint64_t *__restrict__ key) {
+                       const uint32_t *__restrict__ label, uint64_t *__restrict__ key,
+                       uint8_t *__restrict__ S, uint8_t *__restrict__ newA) {
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     key[u] = ((uint64_t)((uint32_t)P[u] ^ 0x80000000u) << 32) | label[gid[u]];
+    S[u] = 0;
+    newA[u] = 0;
+  }
 }
 
 // u is selected iff key(u) < key(v) for every live neighbour v (keys are
@@ -838,9 +844,20 @@ __global__ void k_count_by_graph(const uint64_t *__restrict__ ukey, const uint32
 // ===========================================================================
 // overlay rebuild
 // ===========================================================================
-__global__ void k_keep(uint32_t n, const uint8_t *__restrict__ F, uint32_t *__restrict__ keep) {
+// keep[u] = !F[u]; zeroes the row-count arrays c2, c3 (n + 1 entries) and
+// the next round's flag arrays w, a (n entries).
+__global__ void k_keep(uint32_t n, const uint8_t *__restrict__ F, uint32_t *__restrict__ keep,
+                       uint32_t *__restrict__ c2, uint32_t *__restrict__ c3,
+                       uint8_t *__restrict__ w, uint8_t *__restrict__ a) {
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) keep[u] = !F[u];
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u <= n; u += stride) {
+    c2[u] = 0;
+    c3[u] = 0;
+    if (u == n) continue;
+    keep[u] = !F[u];
+    w[u] = 0;
+    a[u] = 0;
+  }
 }
 
 // Row of vertex u in direction dir merged with its shortcut row.  Old row:
