@@ -137,6 +137,52 @@ def plain_vs_learned(binding, args, t_off, t_dst, t_w, qs, qt, knobs, dev):
     return rep
 
 
+# Kernel sources whose change invalidates the committed HBM counter totals.
+TRAFFIC_SOURCES = ("paper_2412_18008_amd/csrc/search.hpp", "paper_2412_18008_amd/csrc/common.hpp",
+                   "paper_2412_18008_amd/csrc/round_kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_local_search_road1m.md")
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel):
+    """Measured HBM bytes per launch of `kernel` from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated against a plain copy), or
+    None when there is none for it or the kernel sources changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("traffic:"):
+                k, _, v = line[len("traffic:"):].strip().partition("=")
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def copy_calibration(dev, nbytes):
+    """One plain device copy of nbytes (reads nbytes, writes nbytes): the
+    reference for scaling the HBM counters of a profiled run."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)  # a streaming kernel: reads nbytes, writes nbytes
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: {nbytes} bytes", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +196,9 @@ def main():
                                                       "learned_weights.npy"),
                     help="weights (.npy, 4801 float32) of the learned priority; the plain vs "
                          "learned comparison runs after the timed steps when the file exists")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="after the steps, copy BYTES once on the device (a reference "
+                         "kernel for HBM counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the build is a single-GPU path "
@@ -260,7 +309,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": committed_traffic(dom),
             "launches": ls_launches,
             "avg_launch_ms": ls_ms / max(ls_launches, 1),
             "algorithmic_bytes_per_launch": ls_b / max(ls_launches, 1),
@@ -269,6 +318,8 @@ def main():
     if os.path.exists(args.learned):
         line["plain_vs_learned"] = plain_vs_learned(binding, args, t_off, t_dst, t_w, qs, qt,
                                                     knobs, dev)
+    if args.copy_calibration:
+        copy_calibration(dev, args.copy_calibration)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, f"the full {args.workload} build (same graph)")
