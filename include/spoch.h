@@ -49,11 +49,18 @@ extern "C" {
 
 /* ---- witness-path-search modes ---- */
 /* The paper bounds each search by a settled-vertex budget whose value it
- * does not give (Sec. "Step 1: Local Search with Memoization").  This
- * library searches from source s up to radius D_s = the largest two-arc
- * length w(s,u) + w(u,v) over its targets, which yields exact distances
- * for every target. */
+ * does not give (Sec. "Step 1: Local Search with Memoization").  Both modes
+ * search from source s up to radius D_s = the largest two-arc length
+ * w(s,u) + w(u,v) over its targets.
+ *   CH_WPS_EXACT: the exact overlay distance of every target.
+ *   CH_WPS_HOP:   hop- and distance-bounded: the minimum length over walks
+ *                 of at most hop_limit arcs within D_s, computed level by
+ *                 level (level k uses only level k-1 values); a target no
+ *                 such walk reaches gets no memo entry.  Distances of the
+ *                 finished CH stay exact (a missing witness only adds a
+ *                 shortcut). */
 #define CH_WPS_EXACT 0
+#define CH_WPS_HOP 1
 
 /* ---- flags ---- */
 #define CH_F_INPUT_ON_DEVICE 0x1u /* ch_graph_t arrays are device pointers */
@@ -83,7 +90,7 @@ typedef struct {
 } ch_graph_t;
 
 typedef struct {
-  uint32_t wps_mode;   /* CH_WPS_EXACT                                          */
+  uint32_t wps_mode;   /* CH_WPS_EXACT or CH_WPS_HOP                            */
   uint32_t max_rounds; /* 0: no limit; else CH_E_LIMIT after that many rounds    */
   uint64_t seed;       /* seed of the default labels                            */
   uint32_t flags;      /* CH_F_*                                                */
@@ -99,6 +106,7 @@ typedef struct {
   uint32_t dense_deg10;
   uint32_t priority;   /* CH_PRIO_PLAIN (edge difference, Alg. 4) or CH_PRIO_LEARNED */
   const float *mlp;    /* CH_PRIO_LEARNED: CH_MLP_PARAMS weights, host memory      */
+  uint32_t hop_limit;  /* CH_WPS_HOP: arcs per witness walk, >= 1 (else ignored)  */
 } ch_params_t;
 
 /* ---- learned priority ----

@@ -25,6 +25,7 @@ CH_E_LIMIT = -5
 CH_E_UNSUPPORTED = -6
 
 CH_WPS_EXACT = 0
+CH_WPS_HOP = 1
 CH_F_INPUT_ON_DEVICE = 0x1
 CH_F_STATS = 0x2
 CH_F_NO_QUERY_INDEX = 0x4
@@ -50,7 +51,8 @@ class Params(C.Structure):
     _fields_ = [("wps_mode", C.c_uint32), ("max_rounds", C.c_uint32), ("seed", C.c_uint64),
                 ("flags", C.c_uint32), ("group", C.c_uint32), ("stream", C.c_void_p),
                 ("ls_sparse", C.c_uint32), ("ls_dense", C.c_uint32),
-                ("dense_deg10", C.c_uint32), ("priority", C.c_uint32), ("mlp", C.c_void_p)]
+                ("dense_deg10", C.c_uint32), ("priority", C.c_uint32), ("mlp", C.c_void_p),
+                ("hop_limit", C.c_uint32)]
 
 
 CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
@@ -240,8 +242,9 @@ class CH:
 
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
-          record=False):
-    """ch_build on a CSR graph; numpy arrays or torch CUDA tensors."""
+          record=False, hop=0):
+    """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
+    selects the hop-bounded witness search with walks of at most `hop` arcs."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
     pd, kd = _ptr(dst, np.uint32)
@@ -259,16 +262,17 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     wts = None if mlp is None else np.ascontiguousarray(mlp, np.float32)
     if wts is not None and wts.size != CH_MLP_PARAMS:
         raise ValueError("mlp must hold 4801 weights")
-    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream, ls_sparse, ls_dense,
-               dense_deg10, CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
-               None if wts is None else wts.ctypes.data)
+    p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
+               ls_sparse, ls_dense, dense_deg10,
+               CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
+               None if wts is None else wts.ctypes.data, hop)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
 
 
 def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=True,
-                stream=None):
+                stream=None, hop=0):
     """ch_build_batch on a list of (off, dst, w) CSR graphs (numpy arrays or
     torch CUDA tensors); returns one CH per graph."""
     k = len(graphs)
@@ -285,8 +289,8 @@ def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=
         m = dst.numel() if dev else len(kd)
         arr[i] = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX)
-    p = Params(CH_WPS_EXACT, max_rounds, seed, flags, group, stream, 0, 0, 0, CH_PRIO_PLAIN,
-               None)
+    p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
+               0, 0, 0, CH_PRIO_PLAIN, None, hop)
     outs = (C.c_void_p * max(k, 1))()
     _check(lib().ch_build_batch(arr, k, C.byref(p), outs), "ch_build_batch")
     return [CH(C.c_void_p(outs[i])) for i in range(k)]

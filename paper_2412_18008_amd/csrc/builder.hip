@@ -332,17 +332,29 @@ struct Builder {
 
   // Persistent launch: blocks_per_cu one-wave blocks per CU; a group takes
   // 4 sources per scheduling step while sources are plentiful, else 1.
+  // Hop mode adds a second distance array to every table, so fewer blocks
+  // fit in a CU's 160 KB of LDS.
   template <int G, int CAP>
   void launch_ls(const Overlay &v, const uint32_t *list, uint32_t nl, const uint32_t *nl_dev,
                  int tier, int blocks_per_cu) {
+    const bool hop = prm.wps_mode == CH_WPS_HOP;
+    if (hop) {
+      const size_t lds = (size_t)(kLsBlock / G) * ((size_t)CAP * 22 + 16);
+      blocks_per_cu = std::max(1, std::min(blocks_per_cu, (int)((160u << 10) / lds)));
+    }
     const uint32_t groups = (uint32_t)cus * blocks_per_cu * (kLsBlock / G);
     const uint32_t chunk = (!nl_dev && nl >= 16u * groups) ? 4u : 1u;
     DevCtr *d = dc();
-    k_local_search<G, CAP><<<(unsigned)cus * blocks_per_cu, kLsBlock, 0, st>>>(
-        v, list, nl, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1,
-        tier == 1 ? &d->ls : &d->ls2, nl_dev, tier == 1 ? &d->work1 : &d->work2,
-        tier == 1 ? ovf1.as<uint32_t>() : ovf2.as<uint32_t>(), tier == 1 ? &d->novf1 : &d->novf2,
-        chunk, f_ws.as<uint32_t>(), &d->err);
+    auto go = [&](auto kern) {
+      kern<<<(unsigned)cus * blocks_per_cu, kLsBlock, 0, st>>>(
+          v, list, nl, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1,
+          tier == 1 ? &d->ls : &d->ls2, nl_dev, tier == 1 ? &d->work1 : &d->work2,
+          tier == 1 ? ovf1.as<uint32_t>() : ovf2.as<uint32_t>(),
+          tier == 1 ? &d->novf1 : &d->novf2, chunk, f_ws.as<uint32_t>(), &d->err,
+          prm.hop_limit);
+    };
+    if (hop) go(k_local_search<G, CAP, true>);
+    else go(k_local_search<G, CAP, false>);
   }
   template <int G>
   void launch_score(const Overlay &v, uint32_t na) {
@@ -580,20 +592,25 @@ struct Builder {
       rs.n_ls_global = novf;
       if (novf) {
         const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
-        const size_t per = ((size_t)cap * 6 + 4) * 4;
+        const bool hop = prm.wps_mode == CH_WPS_HOP;
+        const size_t per = ((size_t)cap * (hop ? 7 : 6) + 4) * 4;
         size_t ntab = std::max<size_t>(1, std::min<size_t>({(size_t)novf, (size_t)cus * 2,
                                                             (size_t)(4ull << 30) / per}));
         HIP_TRY(gtabs.ensure(ntab * per));
-        // key, dist = all ones; flag, order, fronts, counters = 0
+        // key, dist (and dist2) = all ones; flag, order, fronts, counters = 0
         for (size_t t = 0; t < ntab; t++) {
           uint32_t *b = gtabs.as<uint32_t>() + t * (per / 4);
-          HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));
-          HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, ((size_t)cap * 4 + 4) * 4, st));
+          const size_t arrays = hop ? 7 : 6;
+          HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));            // key, dist
+          HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, (size_t)cap * 4 * 4, st));  // flag .. fr1
+          if (hop) HIP_TRY(fill_u32(b + 6ull * cap, SP_EMPTY32, cap, st));     // dist2
+          HIP_TRY(hipMemsetAsync(b + arrays * cap, 0, 4 * 4, st));      // counters
         }
-        k_local_search_global<<<(unsigned)ntab, 64, 0, st>>>(
+        auto global = hop ? k_local_search_global<true> : k_local_search_global<false>;
+        global<<<(unsigned)ntab, 64, 0, st>>>(
             v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
             mcap / kMemoBucket - 1, &dc()->ls2, gtabs.as<uint32_t>(), cap, f_ws.as<uint32_t>(),
-            &dc()->err);
+            &dc()->err, prm.hop_limit);
         HIP_TRY(hipGetLastError());
         TRY(after_search());
         TRY(readback());
@@ -784,7 +801,10 @@ struct Builder {
 static int check_params(const ch_params_t *p, ch_params_t &prm) {
   prm = ch_params_t{};
   if (p) prm = *p;
-  if (prm.wps_mode != CH_WPS_EXACT) return set_error(CH_E_UNSUPPORTED, "unknown wps_mode");
+  if (prm.wps_mode != CH_WPS_EXACT && prm.wps_mode != CH_WPS_HOP)
+    return set_error(CH_E_UNSUPPORTED, "unknown wps_mode");
+  if (prm.wps_mode == CH_WPS_HOP && prm.hop_limit < 1)
+    return set_error(CH_E_INVALID, "hop mode needs hop_limit >= 1");
   if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&
       prm.group != 64)
     return set_error(CH_E_INVALID, "group must be 0, 4, 8, 16, 32 or 64");

@@ -183,18 +183,20 @@ constexpr int kLsBlock = 64;  // one wave per workgroup
 
 // LDS fast path: groups of G lanes, CAP-slot table per group.  Persistent:
 // every group takes `chunk` sources at a time from a global counter.
-template <int G, int CAP>
+template <int G, int CAP, bool HOP>
 __global__ void __launch_bounds__(kLsBlock) k_local_search(
     Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
     MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
     const uint32_t *__restrict__ nw_dev, uint32_t *__restrict__ work,
     uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count, uint32_t chunk,
-    uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
   constexpr int NG = kLsBlock / G;
+  constexpr int CAP2 = HOP ? CAP : 1;  // second distance array only in hop mode
   if (nw_dev) nw = *nw_dev;  // source count produced by an earlier kernel
   if (nw == 0) return;
   __shared__ uint32_t s_key[NG][CAP];
   __shared__ uint32_t s_dist[NG][CAP];
+  __shared__ uint32_t s_dist2[NG][CAP2];
   __shared__ uint32_t s_flag[NG][CAP];
   __shared__ uint16_t s_order[NG][CAP];
   __shared__ uint16_t s_fr[NG][2][CAP];
@@ -203,6 +205,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
   for (int i = gl; i < CAP; i += G) {
     s_key[g][i] = SP_EMPTY32;
     s_dist[g][i] = SP_INF32;
+    if constexpr (HOP) s_dist2[g][i] = SP_INF32;
     s_flag[g][i] = 0;
   }
   if (gl < 4) s_ctr[g][gl] = 0;
@@ -210,6 +213,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
   Tab<uint16_t, false> T;
   T.key = s_key[g];
   T.dist = s_dist[g];
+  T.dist2 = HOP ? s_dist2[g] : nullptr;
   T.flag = s_flag[g];
   T.order = s_order[g];
   T.fr0 = s_fr[g][0];
@@ -227,7 +231,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
     const uint32_t end = min(base + chunk, nw);
     for (uint32_t i = base; i < end; i++) {
       const uint32_t s = vw[i];
-      if (!search_source<G>(ov, aflag, memo, mmask, T, s, ss, ws, err)) {
+      if (!search_source<G, HOP>(ov, aflag, memo, mmask, T, s, ss, ws, err, hops)) {
         if (gl == 0) {
           const uint32_t k = atomicAdd(ovf_count, 1u);
           ovf_list[k] = s;
@@ -239,14 +243,17 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
 }
 
 // Global-memory fallback: one wave per source, table of `cap` slots per
-// wave at tabs + wave * stride_words (key, dist, flag, order, fr0, fr1 as
-// consecutive uint32 arrays of `cap`, then 4 counters).
+// wave at tabs + wave * stride_words (key, dist, flag, order, fr0, fr1 and,
+// in hop mode, dist2 as consecutive uint32 arrays of `cap`, then 4
+// counters).
+template <bool HOP>
 __global__ void __launch_bounds__(64) k_local_search_global(
     Overlay ov, const uint32_t *__restrict__ list, uint32_t nlist,
     const uint8_t *__restrict__ aflag, MemoSlot *__restrict__ memo, uint64_t mmask,
     LsCounters *__restrict__ cnt, uint32_t *__restrict__ tabs, uint32_t cap,
-    uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
-  uint32_t *base = tabs + (size_t)blockIdx.x * ((size_t)cap * 6 + 4);
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
+  constexpr size_t kArrays = HOP ? 7 : 6;
+  uint32_t *base = tabs + (size_t)blockIdx.x * ((size_t)cap * kArrays + 4);
   Tab<uint32_t, true> T;
   T.key = base;
   T.dist = base + cap;
@@ -254,13 +261,14 @@ __global__ void __launch_bounds__(64) k_local_search_global(
   T.order = base + 3 * (size_t)cap;
   T.fr0 = base + 4 * (size_t)cap;
   T.fr1 = base + 5 * (size_t)cap;
-  T.ctr = base + 6 * (size_t)cap;
+  T.dist2 = HOP ? base + 6 * (size_t)cap : nullptr;
+  T.ctr = base + kArrays * (size_t)cap;
   T.cap = cap;
   T.shift = 32 - __builtin_ctz(cap);
   T.limit = cap;  // cap >= 2 n_o: never overflows
   SearchStats ss;
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
-    if (!search_source<64>(ov, aflag, memo, mmask, T, list[i], ss, ws, err)) {
+    if (!search_source<64, HOP>(ov, aflag, memo, mmask, T, list[i], ss, ws, err, hops)) {
       if (lane_id() == 0) atomicOr(err, kErrCapacity);
     }
   }

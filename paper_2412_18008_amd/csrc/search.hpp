@@ -39,6 +39,7 @@ template <typename IdxT, bool GL>
 struct Tab {
   uint32_t *key;   // vertex (local id) or SP_EMPTY32
   uint32_t *dist;  // tentative distance; during target collection 0xFFFFFFFF - max via
+  uint32_t *dist2; // hop mode: the distances of the level being computed (else null)
   uint32_t *flag;  // kFlag*
   IdxT *order;     // slots in insertion order
   IdxT *fr0, *fr1; // frontier slot lists
@@ -148,6 +149,7 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
     IdxT s = T.ldi(&T.order[i]);
     T.st(&T.key[s], SP_EMPTY32);
     T.st(&T.dist[s], SP_INF32);
+    if (T.dist2) T.st(&T.dist2[s], SP_INF32);
     T.st(&T.flag[s], 0u);
   }
   T.sync();
@@ -155,6 +157,7 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
     for (uint32_t i = gl; i < T.cap; i += G) {
       T.st(&T.key[i], SP_EMPTY32);
       T.st(&T.dist[i], SP_INF32);
+      if (T.dist2) T.st(&T.dist2[i], SP_INF32);
       T.st(&T.flag[i], 0u);
     }
   }
@@ -163,11 +166,18 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
 }
 
 // One source.  Returns false when the table overflowed (nothing written).
-template <int G, typename IdxT, bool GL>
+// HOP: hop-synchronous search of at most `hops` levels -- level k expands
+// the vertices whose distance changed in level k-1 with their level-(k-1)
+// distance (dist) and writes dist2; at the end of the level the changed
+// entries are copied back.  The result is the minimum over walks of at most
+// `hops` arcs within the radius, independent of the order of relaxations.
+// Targets the walks do not reach get no memo entry.
+template <int G, bool HOP, typename IdxT, bool GL>
 __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ aflag,
                               MemoSlot *__restrict__ memo, uint64_t mmask,
                               const Tab<IdxT, GL> &T, uint32_t s, SearchStats &ss,
-                              uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
+                              uint32_t *__restrict__ ws, uint32_t *__restrict__ err,
+                              uint32_t hops) {
   const int gl = glane<G>();
   const uint32_t gs = ov.gid[s];
 
@@ -244,12 +254,14 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     return true;
   }
 
-  // ---- 2. bounded label-correcting search from s ----------------------
+  // ---- 2. bounded search from s: label-correcting (exact) or
+  //         hop-synchronous (HOP) ------------------------------------------
   T.sync();
   if (gl == 0) {
     const int slot = T.insert(s);
     if (slot >= 0) {
       T.st(&T.dist[slot], 0u);
+      if constexpr (HOP) T.st(&T.dist2[slot], 0u);
       T.st(&T.flag[slot], kFlagFront);
       T.sti(&T.fr0[0], (IdxT)slot);
       T.st(&T.ctr[kCtrF0], 1u);
@@ -257,6 +269,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
   }
   T.sync();
   int cur = 0;
+  uint32_t level = 0;
   while (!T.ld(&T.ctr[kCtrOvf])) {
     IdxT *fc = cur ? T.fr1 : T.fr0;
     IdxT *fn = cur ? T.fr0 : T.fr1;
@@ -264,6 +277,9 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     uint32_t *nn = &T.ctr[cur ? kCtrF0 : kCtrF1];
     const uint32_t ncur = T.ld(nc);
     if (ncur == 0) break;
+    if constexpr (HOP) {
+      if (level == hops) break;
+    }
     T.sync();
     if (gl == 0) T.st(nn, 0u);
     T.sync();
@@ -272,8 +288,10 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       uint32_t rs = 0, rl = 0, dx = 0;
       if (i < ncur) {
         const IdxT x = T.ldi(&fc[i]);
-        atomicAnd(&T.flag[x], ~kFlagFront);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if constexpr (!HOP) {
+          atomicAnd(&T.flag[x], ~kFlagFront);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
         dx = T.ld(&T.dist[x]);
         const uint32_t vx = T.ld(&T.key[x]);
         rs = ov.foff[vx];
@@ -288,7 +306,8 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
         if (nd <= D) {
           const int y = T.insert(b.x);
           if (y >= 0) {
-            const uint32_t old = atomicMin(&T.dist[y], (uint32_t)nd);
+            uint32_t *dw = HOP ? T.dist2 : T.dist;
+            const uint32_t old = atomicMin(&dw[y], (uint32_t)nd);
             if ((uint32_t)nd < old) {
               const uint32_t f = atomicOr(&T.flag[y], kFlagFront);
               if (!(f & kFlagFront)) {
@@ -302,6 +321,18 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       if (T.ld(&T.ctr[kCtrOvf])) break;
     }
     T.sync();
+    if constexpr (HOP) {
+      // end of the level: the changed entries take their new distance and
+      // may change again in the next level
+      const uint32_t nnext = min(T.ld(nn), T.cap);
+      for (uint32_t i = gl; i < nnext; i += G) {
+        const IdxT y = T.ldi(&fn[i]);
+        T.st(&T.dist[y], T.ld(&T.dist2[y]));
+        atomicAnd(&T.flag[y], ~kFlagFront);
+      }
+      T.sync();
+      level++;
+    }
     cur ^= 1;
   }
   T.sync();
@@ -324,7 +355,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
         if (d <= D) {
           memo_put(memo, mmask, gs, ov.gid[T.ld(&T.key[slot])], d);
           ss.inserts++;
-        } else {
+        } else if (!HOP) {
           atomicOr(err, kErrCapacity);  // cannot happen: every target is within D
         }
       }
