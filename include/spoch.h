@@ -107,7 +107,14 @@ typedef struct {
   uint32_t priority;   /* CH_PRIO_PLAIN (edge difference, Alg. 4) or CH_PRIO_LEARNED */
   const float *mlp;    /* CH_PRIO_LEARNED: CH_MLP_PARAMS weights, host memory      */
   uint32_t hop_limit;  /* CH_WPS_HOP: arcs per witness walk, >= 1 (else ignored)  */
+  /* Exact mode: once the overlay has at most dense_tail vertices, the
+   * distances of all its pairs are computed once (contraction keeps them
+   * unchanged for the rest of the build) and every later witness search is
+   * answered from that table.  0 = 2048; CH_DENSE_TAIL_OFF keeps the
+   * searches; at most 4096.  Changes speed only, never results. */
+  uint32_t dense_tail;
 } ch_params_t;
+#define CH_DENSE_TAIL_OFF 1u
 
 /* ---- learned priority ----
  * An MLP 8 -> 64 -> 64 -> 1 with GELU maps eight features of a rescored
@@ -142,6 +149,7 @@ typedef struct {
 #define CH_LS_32x512 2u
 #define CH_LS_64x512 3u
 #define CH_LS_64x2048 4u
+#define CH_LS_TABLE 5u  /* round stats only: searches answered from the all-pairs table */
 
 typedef struct ch_s ch_t;
 

@@ -52,7 +52,7 @@ class Params(C.Structure):
                 ("flags", C.c_uint32), ("group", C.c_uint32), ("stream", C.c_void_p),
                 ("ls_sparse", C.c_uint32), ("ls_dense", C.c_uint32),
                 ("dense_deg10", C.c_uint32), ("priority", C.c_uint32), ("mlp", C.c_void_p),
-                ("hop_limit", C.c_uint32)]
+                ("hop_limit", C.c_uint32), ("dense_tail", C.c_uint32)]
 
 
 CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
@@ -76,7 +76,9 @@ class MlpTrainParams(C.Structure):
 
 CH_LS_AUTO, CH_LS_16x128, CH_LS_32x512, CH_LS_64x512, CH_LS_64x2048 = 0, 1, 2, 3, 4
 LS_KERNELS = {1: "k_local_search<16, 128>", 2: "k_local_search<32, 512>",
-              3: "k_local_search<64, 512>", 4: "k_local_search<64, 2048>"}
+              3: "k_local_search<64, 512>", 4: "k_local_search<64, 2048>",
+              5: "k_ls_table"}
+CH_DENSE_TAIL_OFF = 1
 
 
 class RoundStats(C.Structure):
@@ -242,7 +244,7 @@ class CH:
 
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
-          record=False, hop=0):
+          record=False, hop=0, dense_tail=0):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
     selects the hop-bounded witness search with walks of at most `hop` arcs."""
     dev = _is_torch_cuda(off)
@@ -265,14 +267,14 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
                ls_sparse, ls_dense, dense_deg10,
                CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
-               None if wts is None else wts.ctypes.data, hop)
+               None if wts is None else wts.ctypes.data, hop, dense_tail)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
 
 
 def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=True,
-                stream=None, hop=0):
+                stream=None, hop=0, dense_tail=0):
     """ch_build_batch on a list of (off, dst, w) CSR graphs (numpy arrays or
     torch CUDA tensors); returns one CH per graph."""
     k = len(graphs)
@@ -290,7 +292,7 @@ def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=
         arr[i] = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX)
     p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
-               0, 0, 0, CH_PRIO_PLAIN, None, hop)
+               0, 0, 0, CH_PRIO_PLAIN, None, hop, dense_tail)
     outs = (C.c_void_p * max(k, 1))()
     _check(lib().ch_build_batch(arr, k, C.byref(p), outs), "ch_build_batch")
     return [CH(C.c_void_p(outs[i])) for i in range(k)]

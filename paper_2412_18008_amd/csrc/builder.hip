@@ -11,6 +11,7 @@
 #include "builder.hpp"
 #include "mlp.hpp"
 #include "round_kernels.hpp"
+#include "dense_tail.hpp"
 
 namespace sp {
 
@@ -88,6 +89,11 @@ struct Builder {
   DBuf ekey, ekey_alt, eidx, eidx_alt, ew, elab, emid, ehead, eheads, ukey, uw, umid, rkey,
       rkey_alt, ridx, ridx_alt;
   DBuf ovf1, ovf2, gtabs;
+  // all-pairs table of the small overlay (exact mode): matrix tab_N^2,
+  // table position of each original id, original id of each position
+  DBuf tab_D, tab_pos, tab_gid;
+  bool tab_on = false;
+  uint32_t tab_N = 0, tab_n0 = 0;
   DBuf dctr, tmp;
   DevCtr *hctr = nullptr;  // pinned
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -110,7 +116,7 @@ struct Builder {
                    &vw, &va, &vf, &cnt2, &cnt3, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
                    &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
-                   &f_cn, &f_depth, &f_ws, &f_feat, &mlpw};
+                   &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid};
     for (DBuf *b : all) b->release();
     if (hctr) (void)hipHostFree(hctr);
     for (auto &e : ev)
@@ -332,6 +338,33 @@ struct Builder {
 
   // Persistent launch: blocks_per_cu one-wave blocks per CU; a group takes
   // 4 sources per scheduling step while sources are plentiful, else 1.
+  // All-pairs distances of the current overlay (blocked Floyd-Warshall over
+  // 64 x 64 tiles; the matrix is padded to a multiple of 64).
+  int build_table(const Overlay &v) {
+    const uint32_t N = (v.n + kFwTile - 1) / kFwTile * kFwTile;
+    const uint32_t nb = N / kFwTile;
+    HIP_TRY(tab_D.ensure((size_t)N * N * 4));
+    HIP_TRY(tab_pos.ensure((size_t)std::max<uint32_t>(n, 1) * 4));
+    HIP_TRY(tab_gid.ensure((size_t)N * 4));
+    k_fw_init<<<grid((uint64_t)N * N), 256, 0, st>>>(tab_D.as<uint32_t>(), N);
+    HIP_TRY(hipGetLastError());
+    k_fw_arcs<<<grid(v.n), 256, 0, st>>>(v, N, tab_D.as<uint32_t>(), tab_pos.as<uint32_t>(),
+                                          tab_gid.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    for (uint32_t k = 0; k < nb; k++) {
+      k_fw_rowcol<<<2 * nb, kFwThreads, 0, st>>>(tab_D.as<uint32_t>(), N, k);
+      HIP_TRY(hipGetLastError());
+      if (nb > 1) {
+        k_fw_rest<<<nb * nb, kFwThreads, 0, st>>>(tab_D.as<uint32_t>(), N, k);
+        HIP_TRY(hipGetLastError());
+      }
+    }
+    tab_on = true;
+    tab_N = N;
+    tab_n0 = v.n;
+    return CH_OK;
+  }
+
   // Hop mode adds a second distance array to every table, so fewer blocks
   // fit in a CU's 160 KB of LDS.
   template <int G, int CAP>
@@ -507,7 +540,22 @@ struct Builder {
       HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
       const double thr = prm.dense_deg10 ? prm.dense_deg10 / 10.0 : 5.0;
       const bool sparse = avgdeg <= thr;
-      if (nw) {
+      // exact mode on a small overlay: all distances once, then lookups
+      const uint32_t tail = prm.dense_tail == 0 ? 2048u : prm.dense_tail;
+      if (!tab_on && prm.wps_mode == CH_WPS_EXACT && tail != CH_DENSE_TAIL_OFF && O.n &&
+          O.n <= tail)
+        TRY(build_table(v));
+      if (nw && tab_on) {
+        rs.ls_tier1 = CH_LS_TABLE;
+        if (stats) HIP_TRY(hipEventRecord(ev[2], st));
+        k_ls_table<<<(unsigned)std::min<uint64_t>(nw, (uint64_t)cus * 8), 64, 0, st>>>(
+            v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
+            mcap / kMemoBucket - 1, &dc()->ls, tab_D.as<uint32_t>(), tab_N, tab_n0,
+            tab_pos.as<uint32_t>(), tab_gid.as<uint32_t>(), alive_g.as<uint8_t>(),
+            f_ws.as<uint32_t>(), &dc()->err);
+        HIP_TRY(hipGetLastError());
+        if (stats) HIP_TRY(hipEventRecord(ev[3], st));
+      } else if (nw) {
         // tier 1: LDS tables sized for the overlay's degree (16 lanes x 128
         // slots on sparse overlays, 64 lanes x 2048 slots on dense ones);
         // sources whose search outgrows them go to a 4096-slot LDS tier
@@ -805,6 +853,8 @@ static int check_params(const ch_params_t *p, ch_params_t &prm) {
     return set_error(CH_E_UNSUPPORTED, "unknown wps_mode");
   if (prm.wps_mode == CH_WPS_HOP && prm.hop_limit < 1)
     return set_error(CH_E_INVALID, "hop mode needs hop_limit >= 1");
+  if (prm.dense_tail > kTabMaxN)
+    return set_error(CH_E_INVALID, "dense_tail must be at most 4096");
   if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&
       prm.group != 64)
     return set_error(CH_E_INVALID, "group must be 0, 4, 8, 16, 32 or 64");

@@ -1,0 +1,278 @@
+// dense_tail.hpp -- witness distances from an all-pairs table once the
+// overlay is small.
+//
+// Contraction preserves the distance between every two vertices that are
+// still in the overlay (a shortcut replaces exactly the path it removes,
+// pruning only deletes arcs longer than a known distance), so the exact
+// witness distance of a live pair (s, v) in any round is the overlay
+// distance at any earlier round.  When the overlay has n0 <= the threshold
+// vertices, the build computes all n0^2 distances once (blocked
+// Floyd-Warshall over 64 x 64 tiles in LDS); every later round in exact
+// mode answers its searches from the table: the same targets, radius D_s,
+// memo entries (target distances <= D_s) and reached-vertex count as the
+// search of Alg. 3 would give.
+#pragma once
+
+#include "common.hpp"
+#include "search.hpp"
+
+namespace sp {
+
+constexpr int kFwTile = 64;     // tile edge
+constexpr int kFwThreads = 256; // 16 entries of a tile per thread (4 x 4)
+
+// a + b clamped to 0xFFFFFFFF: a distance above 0xFFFFFFFE (or through an
+// absent entry) is stored as "none"; no witness radius reaches it.
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+  const uint64_t s = (uint64_t)a + b;
+  return s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
+}
+
+// Dense matrix N x N (N a multiple of kFwTile, row-major): none everywhere,
+// 0 on the diagonal (padding rows included).
+__global__ void k_fw_init(uint32_t *__restrict__ D, uint32_t N) {
+  const uint64_t total = (uint64_t)N * N;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+    D[i] = (i / N == i % N) ? 0u : SP_INF32;
+}
+
+// Arcs of the overlay (local ids = matrix rows), and the position <-> original
+// id maps of the table.
+__global__ void k_fw_arcs(Overlay ov, uint32_t N, uint32_t *__restrict__ D,
+                          uint32_t *__restrict__ pos_of_gid, uint32_t *__restrict__ gid_of_pos) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < ov.n; u += stride) {
+    pos_of_gid[ov.gid[u]] = u;
+    gid_of_pos[u] = ov.gid[u];
+    for (uint32_t e = ov.foff[u]; e < ov.foff[u + 1]; e++) {
+      const uint2 a = ov.farc[e];
+      if (a.y != SP_INF32) atomicMin(&D[(size_t)u * N + a.x], a.y);
+    }
+  }
+}
+
+// Closure of the tile in LDS over its own 64 intermediate vertices.
+__device__ __forceinline__ void fw_close_tile(uint32_t (*T)[kFwTile + 1]) {
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  for (int k = 0; k < kFwTile; k++) {
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+      const int i = ty * 4 + a;
+      const uint32_t dik = T[i][k];
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const int j = tx * 4 + b;
+        const uint32_t c = sat_add(dik, T[k][j]);
+        if (c < T[i][j]) T[i][j] = c;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void fw_load(uint32_t (*T)[kFwTile + 1], const uint32_t *D, uint32_t N,
+                                        uint32_t ti, uint32_t tj) {
+  for (int e = threadIdx.x; e < kFwTile * kFwTile; e += kFwThreads) {
+    const int i = e / kFwTile, j = e % kFwTile;
+    T[i][j] = D[(size_t)(ti * kFwTile + i) * N + tj * kFwTile + j];
+  }
+}
+
+__device__ __forceinline__ void fw_store(const uint32_t (*T)[kFwTile + 1], uint32_t *D, uint32_t N,
+                                         uint32_t ti, uint32_t tj) {
+  for (int e = threadIdx.x; e < kFwTile * kFwTile; e += kFwThreads) {
+    const int i = e / kFwTile, j = e % kFwTile;
+    D[(size_t)(ti * kFwTile + i) * N + tj * kFwTile + j] = T[i][j];
+  }
+}
+
+// C[i][j] = min(C[i][j], min_k A[i][k] + B[k][j]) over one tile.
+__device__ __forceinline__ void fw_minplus(uint32_t (*C)[kFwTile + 1],
+                                           const uint32_t (*A)[kFwTile + 1],
+                                           const uint32_t (*B)[kFwTile + 1]) {
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+  uint32_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) acc[a][b] = C[ty * 4 + a][tx * 4 + b];
+  for (int k = 0; k < kFwTile; k++) {
+    uint32_t av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; a++) av[a] = A[ty * 4 + a][k];
+#pragma unroll
+    for (int b = 0; b < 4; b++) bv[b] = B[k][tx * 4 + b];
+#pragma unroll
+    for (int a = 0; a < 4; a++)
+#pragma unroll
+      for (int b = 0; b < 4; b++) {
+        const uint32_t c = sat_add(av[a], bv[b]);
+        acc[a][b] = c < acc[a][b] ? c : acc[a][b];
+      }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++) C[ty * 4 + a][tx * 4 + b] = acc[a][b];
+  __syncthreads();
+}
+
+// Phase k, first part: every block closes the diagonal tile (k, k) itself
+// (re-closing a partly updated tile gives the same closure), then block b <
+// nb updates row tile (k, b) and block nb + b column tile (b, k); the
+// blocks of tile (k, k) write the closed diagonal.
+__global__ void __launch_bounds__(kFwThreads) k_fw_rowcol(uint32_t *__restrict__ D, uint32_t N,
+                                                          uint32_t k) {
+  __shared__ uint32_t Dk[kFwTile][kFwTile + 1];
+  __shared__ uint32_t T[kFwTile][kFwTile + 1];
+  const uint32_t nb = N / kFwTile;
+  const bool col = blockIdx.x >= nb;
+  const uint32_t b = col ? blockIdx.x - nb : blockIdx.x;
+  fw_load(Dk, D, N, k, k);
+  __syncthreads();
+  fw_close_tile(Dk);
+  if (b == k) {
+    if (!col) fw_store(Dk, D, N, k, k);
+    return;
+  }
+  if (col) {
+    fw_load(T, D, N, b, k);
+    __syncthreads();
+    fw_minplus(T, T, Dk);  // (b, k) <- (b, k) (x) closure(k, k)
+    fw_store(T, D, N, b, k);
+  } else {
+    fw_load(T, D, N, k, b);
+    __syncthreads();
+    fw_minplus(T, Dk, T);  // (k, b) <- closure(k, k) (x) (k, b)
+    fw_store(T, D, N, k, b);
+  }
+}
+
+// Phase k, second part: tile (i, j), i, j != k: min with (i, k) (x) (k, j).
+__global__ void __launch_bounds__(kFwThreads) k_fw_rest(uint32_t *__restrict__ D, uint32_t N,
+                                                        uint32_t k) {
+  __shared__ uint32_t A[kFwTile][kFwTile + 1];
+  __shared__ uint32_t B[kFwTile][kFwTile + 1];
+  __shared__ uint32_t C[kFwTile][kFwTile + 1];
+  const uint32_t nb = N / kFwTile;
+  const uint32_t i = blockIdx.x / nb, j = blockIdx.x % nb;
+  if (i == k || j == k) return;
+  fw_load(A, D, N, i, k);
+  fw_load(B, D, N, k, j);
+  fw_load(C, D, N, i, j);
+  __syncthreads();
+  fw_minplus(C, A, B);
+  fw_store(C, D, N, i, j);
+}
+
+// Witness search of Alg. 3 answered from the table (exact mode): one group
+// of 64 lanes per source.  Per group in LDS: a seen bit and the largest
+// two-arc length per table position.
+constexpr int kTabMaxN = 4096;  // largest table the lookup kernel serves
+
+__global__ void __launch_bounds__(64) k_ls_table(
+    Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
+    MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
+    const uint32_t *__restrict__ Dtab, uint32_t N, uint32_t n0,
+    const uint32_t *__restrict__ pos_of_gid, const uint32_t *__restrict__ gid_of_pos,
+    const uint8_t *__restrict__ alive_g, uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
+  __shared__ uint32_t s_seen[kTabMaxN / 32];
+  __shared__ uint32_t s_tgt[kTabMaxN / 32];
+  __shared__ uint32_t s_via[kTabMaxN];  // 0xFFFFFFFF - largest via (atomicMin)
+  const int l = lane_id();
+  const uint32_t words = (n0 + 31) / 32;
+  SearchStats ss;
+  for (uint32_t k = blockIdx.x; k < nw; k += gridDim.x) {
+    const uint32_t s = vw[k];
+    const uint32_t gs = ov.gid[s];
+    const uint32_t ps = pos_of_gid[gs];
+    wave_sync();  // the previous source's LDS reads come first
+    for (uint32_t i = l; i < words; i += kWave) {
+      s_seen[i] = 0;
+      s_tgt[i] = 0;
+    }
+    for (uint32_t i = l; i < n0; i += kWave) s_via[i] = 0xFFFFFFFFu;
+    wave_sync();
+    // ---- targets: out-neighbours v != s of affected out-neighbours u
+    const uint32_t a0 = ov.foff[s], a1 = ov.foff[s + 1];
+    for (uint32_t base = a0; base < a1; base += kWave) {
+      const uint32_t e = base + l;
+      uint32_t rs = 0, rl = 0, wsu = 0;
+      if (e < a1) {
+        const uint2 a = ov.farc[e];
+        if (aflag[a.x]) {
+          rs = ov.foff[a.x];
+          rl = ov.foff[a.x + 1] - rs;
+          wsu = a.y;
+          ss.rows++;
+        }
+      }
+      const uint32_t incl = gscan_incl<kWave>(rl);
+      const uint32_t total = __shfl(incl, kWave - 1, kWave);
+      for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+        const uint32_t idx = i0 + l;
+        const int src = gfind<kWave>(incl, idx);
+        const uint32_t srs = __shfl(rs, src, kWave), sinc = __shfl(incl, src, kWave);
+        const uint32_t srl = __shfl(rl, src, kWave), sw = __shfl(wsu, src, kWave);
+        if (idx < total) {
+          const uint2 b = ov.farc[srs + (idx - (sinc - srl))];
+          ss.arcs++;
+          if (b.x != s) {
+            const uint64_t via = (uint64_t)sw + b.y;
+            const uint32_t viac = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
+            const uint32_t p = pos_of_gid[ov.gid[b.x]];
+            atomicOr(&s_seen[p >> 5], 1u << (p & 31));
+            atomicMin(&s_via[p], 0xFFFFFFFFu - viac);
+          }
+        }
+      }
+    }
+    wave_sync();
+    // ---- targets are the candidates without a memo entry; radius D
+    uint32_t D = 0, nt = 0;
+    for (uint32_t w0 = 0; w0 < words; w0 += 2) {  // two bitmap words per step
+      const uint32_t w = w0 + ((uint32_t)l >> 5), bit = (uint32_t)l & 31u;
+      const uint32_t bits = w < words ? s_seen[w] : 0u;
+      const uint32_t p = w * 32 + bit;
+      bool tgt = false;
+      if (((bits >> bit) & 1u) &&
+          memo_get(memo, mmask, gs, gid_of_pos[p], &ss.probes) == SP_INF32) {
+        tgt = true;
+        D = max(D, 0xFFFFFFFFu - s_via[p]);
+        nt++;
+      }
+      const uint64_t tb = __ballot(tgt);
+      if (l == 0) s_tgt[w0] = (uint32_t)tb;
+      if (l == 0 && w0 + 1 < words) s_tgt[w0 + 1] = (uint32_t)(tb >> 32);
+    }
+    wave_sync();
+    D = gmax<kWave>(D);
+    nt = gsum<kWave>(nt);
+    if (nt == 0) continue;
+    if (D > SP_MAXW) {
+      if (l == 0) atomicOr(err, kErrOverflow);
+      continue;
+    }
+    ss.targets += l == 0 ? nt : 0;
+    ss.searched += l == 0 ? 1 : 0;
+    // ---- memo entries for targets within D; reached-vertex count
+    const uint32_t *row = Dtab + (size_t)ps * N;
+    uint32_t ball = 0;
+    for (uint32_t p = l; p < n0; p += kWave) {
+      const uint32_t d = row[p];
+      if (d > D) continue;
+      if (alive_g[gid_of_pos[p]]) ball++;
+      if ((s_tgt[p >> 5] >> (p & 31)) & 1u) {
+        memo_put(memo, mmask, gs, gid_of_pos[p], d);
+        ss.inserts++;
+      }
+    }
+    ball = gsum<kWave>(ball);
+    if (ws && l == 0) ws[gs] = ball;
+  }
+  flush_stats<64>(ss, cnt);
+}
+
+}  // namespace sp

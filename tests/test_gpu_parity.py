@@ -309,3 +309,42 @@ def test_autotuner_roundtrip(gpu, tmp_path, monkeypatch):
     n, m = len(off) - 1, len(dst)
     autotune.save({autotune.size_class(n, m): dict(params=best["params"], ms=best["ms"])})
     assert autotune.params_for(n, m) == best["params"]
+
+
+def test_dense_tail_table(gpu):
+    # exact-mode searches answered from the all-pairs table of the small
+    # overlay: from round 0 (threshold >= n), from a late round, or never --
+    # the CH and the round counts must equal the oracle's in every case
+    cases = small_cases()[:10] + [("grid64", *synth.config_grid64(seed=0)),
+                                  ("road30k", *synth.road_like(30_000, seed=9))]
+    for name, off, dst, w in cases:
+        n = len(off) - 1
+        lab = synth.labels(n, 23)
+        o = oracle.OracleCH(off, dst, w, labels=lab).run()
+        a = oracle_export(o)
+        for tail in (4096, 64, gpu.CH_DENSE_TAIL_OFF):
+            ch = gpu.build(off, dst, w, labels=lab, stats=True, dense_tail=tail)
+            assert_same_ch(a, gpu_export(ch), f"{name} tail={tail}")
+            assert gpu_round_counts(ch) == oracle_round_counts(o), f"{name} tail={tail}"
+            kinds = {r["ls_tier1"] for r in ch.round_stats() if r["n_sources"]}
+            if tail == gpu.CH_DENSE_TAIL_OFF:
+                assert 5 not in kinds
+            elif n <= tail:
+                assert kinds == {5}, (name, kinds)
+
+
+def test_dense_tail_learned_and_batch(gpu):
+    from paper_2412_18008_amd import learned
+
+    off, dst, w = synth.road_like(6000, seed=12)
+    n = len(off) - 1
+    lab = synth.labels(n, 4)
+    weights = learned.init_weights(5)
+    o = oracle.OracleCH(off, dst, w, labels=lab, mlp=weights).run()
+    ch = gpu.build(off, dst, w, labels=lab, mlp=weights, dense_tail=4096, record=True)
+    assert_same_ch(oracle_export(o), gpu_export(ch), "learned tail")
+    graphs = [synth.road_like(3000, seed=s) for s in (1, 2, 3)]
+    chs = gpu.build_batch(graphs, dense_tail=4096)
+    for (goff, gdst, gw), c in zip(graphs, chs):
+        single = gpu.build(goff, gdst, gw, dense_tail=gpu.CH_DENSE_TAIL_OFF)
+        assert_same_ch(gpu_export(single), gpu_export(c), "batch tail")
