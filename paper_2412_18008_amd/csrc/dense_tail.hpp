@@ -181,6 +181,7 @@ __global__ void __launch_bounds__(64) k_ls_table(
   __shared__ uint32_t s_seen[kTabMaxN / 32];
   __shared__ uint32_t s_tgt[kTabMaxN / 32];
   __shared__ uint32_t s_via[kTabMaxN];  // 0xFFFFFFFF - largest via (atomicMin)
+  __shared__ uint16_t s_cand[kTabMaxN];  // positions of the candidates
   const int l = lane_id();
   const uint32_t words = (n0 + 31) / 32;
   SearchStats ss;
@@ -230,22 +231,45 @@ __global__ void __launch_bounds__(64) k_ls_table(
       }
     }
     wave_sync();
-    // ---- targets are the candidates without a memo entry; radius D
+    // ---- candidates in position order (bitmap compaction), then the
+    // targets: candidates without a memo entry; radius D over them
+    uint32_t c = 0;
+    for (uint32_t w = l; w < words; w += kWave) c += __popc(s_seen[w]);
+    uint32_t nc;
+    {
+      const uint32_t incl = gscan_incl<kWave>(c);
+      nc = __shfl(incl, kWave - 1, kWave);
+      uint32_t p = incl - c;
+      for (uint32_t w = l; w < words; w += kWave) {
+        uint32_t bits = s_seen[w];
+        s_tgt[w] = 0;
+        while (bits) {
+          s_cand[p++] = (uint16_t)(w * 32 + __builtin_ctz(bits));
+          bits &= bits - 1;
+        }
+      }
+    }
+    wave_sync();
     uint32_t D = 0, nt = 0;
-    for (uint32_t w0 = 0; w0 < words; w0 += 2) {  // two bitmap words per step
-      const uint32_t w = w0 + ((uint32_t)l >> 5), bit = (uint32_t)l & 31u;
-      const uint32_t bits = w < words ? s_seen[w] : 0u;
-      const uint32_t p = w * 32 + bit;
-      bool tgt = false;
-      if (((bits >> bit) & 1u) &&
-          memo_get(memo, mmask, gs, gid_of_pos[p], &ss.probes) == SP_INF32) {
-        tgt = true;
-        D = max(D, 0xFFFFFFFFu - s_via[p]);
+    for (uint32_t i0 = l; i0 < nc; i0 += kWave * kPairBatch) {
+      uint32_t ks[kPairBatch], kv[kPairBatch], got[kPairBatch], pos[kPairBatch];
+      bool act[kPairBatch];
+#pragma unroll
+      for (int q = 0; q < kPairBatch; q++) {
+        const uint32_t i = i0 + q * kWave;
+        act[q] = i < nc;
+        pos[q] = act[q] ? s_cand[i] : 0u;
+        ks[q] = gs;
+        kv[q] = act[q] ? gid_of_pos[pos[q]] : 0u;
+      }
+      memo_get_batch<kPairBatch>(memo, mmask, ks, kv, act, got, &ss.probes);
+#pragma unroll
+      for (int q = 0; q < kPairBatch; q++) {
+        if (!act[q] || got[q] != SP_INF32) continue;
+        atomicOr(&s_tgt[pos[q] >> 5], 1u << (pos[q] & 31));
+        D = max(D, 0xFFFFFFFFu - s_via[pos[q]]);
         nt++;
       }
-      const uint64_t tb = __ballot(tgt);
-      if (l == 0) s_tgt[w0] = (uint32_t)tb;
-      if (l == 0 && w0 + 1 < words) s_tgt[w0 + 1] = (uint32_t)(tb >> 32);
     }
     wave_sync();
     D = gmax<kWave>(D);
@@ -260,13 +284,27 @@ __global__ void __launch_bounds__(64) k_ls_table(
     // ---- memo entries for targets within D; reached-vertex count
     const uint32_t *row = Dtab + (size_t)ps * N;
     uint32_t ball = 0;
-    for (uint32_t p = l; p < n0; p += kWave) {
-      const uint32_t d = row[p];
-      if (d > D) continue;
-      if (alive_g[gid_of_pos[p]]) ball++;
-      if ((s_tgt[p >> 5] >> (p & 31)) & 1u) {
-        memo_put(memo, mmask, gs, gid_of_pos[p], d);
-        ss.inserts++;
+    for (uint32_t p0 = l; p0 < n0; p0 += kWave * 4) {
+      uint32_t d[4], g[4];
+#pragma unroll
+      for (int q = 0; q < 4; q++) {  // four row loads in flight
+        const uint32_t p = p0 + q * kWave;
+        d[q] = p < n0 ? row[p] : SP_INF32;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t p = p0 + q * kWave;
+        g[q] = d[q] <= D ? gid_of_pos[p] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const uint32_t p = p0 + q * kWave;
+        if (d[q] > D) continue;
+        if (alive_g[g[q]]) ball++;
+        if ((s_tgt[p >> 5] >> (p & 31)) & 1u) {
+          memo_put(memo, mmask, gs, g[q], d[q]);
+          ss.inserts++;
+        }
       }
     }
     ball = gsum<kWave>(ball);
