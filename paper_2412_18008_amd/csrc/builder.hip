@@ -82,6 +82,7 @@ struct Builder {
   OvBuf ov[2];
   int cur = 0;
   DBuf aflag, aflag_next, wflag, F, S, newA, key, paircnt, newid, cnt, cnt2, cnt3, vw, va, vf;
+  DBuf rowb;  // shortcut-row bounds: 4 arrays of the overlay's vertex count
   DBuf memo, alive_g;
   uint64_t mcap = 0, mcount = 0;
   DBuf f_cn, f_depth, f_ws, f_feat, mlpw;  // learned-priority feature state
@@ -113,7 +114,7 @@ struct Builder {
     o[0].release();
     o[1].release();
     DBuf *all[] = {&aflag, &aflag_next, &wflag, &F, &S, &newA, &key, &paircnt, &newid, &cnt,
-                   &vw, &va, &vf, &cnt2, &cnt3, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
+                   &vw, &va, &vf, &cnt2, &cnt3, &rowb, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
                    &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
                    &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid};
@@ -495,6 +496,7 @@ struct Builder {
     HIP_TRY(paircnt.ensure(nn * 4));
     HIP_TRY(newid.ensure(nn * 4));
     HIP_TRY(cnt.ensure((nn + 1) * 4));
+    HIP_TRY(rowb.ensure(nn * 16));
     HIP_TRY(vw.ensure(nn * 4));
     HIP_TRY(va.ensure(nn * 4));
     HIP_TRY(vf.ensure(nn * 4));
@@ -609,7 +611,8 @@ struct Builder {
         // ---- Step 3: Select (Alg. 5) -----------------------------------
         k_keys<<<grid(O.n), 256, 0, st>>>(O.n, O.P.as<int32_t>(), O.gid.as<uint32_t>(),
                                           ch->label.as<uint32_t>(), key.as<uint64_t>(),
-                                          S.as<uint8_t>(), newA.as<uint8_t>());
+                                          S.as<uint8_t>(), newA.as<uint8_t>(),
+                                          rowb.as<uint32_t>());
         HIP_TRY(hipGetLastError());
         dispatch(Gsel, [&] { launch_select<4>(v); }, [&] { launch_select<8>(v); },
                  [&] { launch_select<16>(v); }, [&] { launch_select<32>(v); },
@@ -684,6 +687,8 @@ struct Builder {
         dn_cap = nc;
       }
       const size_t ne1 = std::max<uint32_t>(ne, 1);
+      uint32_t *fb0 = rowb.as<uint32_t>(), *fb1 = fb0 + O.n, *rb0 = fb0 + 2 * (size_t)O.n,
+               *rb1 = fb0 + 3 * (size_t)O.n;  // shortcut-row bounds, forward and reverse
       HIP_TRY(ekey.ensure(ne1 * 8));
       HIP_TRY(ekey_alt.ensure(ne1 * 8));
       HIP_TRY(eidx.ensure(ne1 * 4));
@@ -738,6 +743,10 @@ struct Builder {
         HIP_TRY(hipGetLastError());
         HIP_TRY(sort_u64_index(rkey.as<uint64_t>(), ridx.as<uint32_t>(), rkey_alt.as<uint64_t>(),
                                ridx_alt.as<uint32_t>(), ne, 2 * kb, tmp, st));
+        k_row_bounds<<<grid(ne), 256, 0, st>>>(ukey.as<uint64_t>(), dU, kb, fb0, fb1);
+        HIP_TRY(hipGetLastError());
+        k_row_bounds<<<grid(ne), 256, 0, st>>>(rkey.as<uint64_t>(), dU, kb, rb0, rb1);
+        HIP_TRY(hipGetLastError());
       }
 
       // ---- overlay rebuild: drop V_F, merge E+ ---------------------------
@@ -765,27 +774,28 @@ struct Builder {
       // offsets over O.n + 1 entries: foff[n2 .. O.n] all equal m2
       k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, dU,
+          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
           uw.as<uint32_t>(), umid.as<uint32_t>(), cnt2.as<uint32_t>(), nullptr, nullptr, nullptr);
       HIP_TRY(hipGetLastError());
       k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), dU,
-          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt3.as<uint32_t>(), nullptr, nullptr, nullptr);
+          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), rb0,
+          rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), cnt3.as<uint32_t>(), nullptr, nullptr,
+          nullptr);
       HIP_TRY(hipGetLastError());
       HIP_TRY(scan3_u32(cnt2.as<uint32_t>(), N.foff.as<uint32_t>(), &dc()->c32[C_MF],
                         cnt3.as<uint32_t>(), N.roff.as<uint32_t>(), &dc()->c32[C_MR], nullptr,
                         nullptr, nullptr, O.n + 1, tmp, st));
       k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, dU,
+          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
           uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.foff.as<uint32_t>(),
           N.farc.as<uint2>(), N.fmid.as<uint32_t>());
       HIP_TRY(hipGetLastError());
       k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
           O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), dU,
-          uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
+          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), rb0,
+          rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
           N.rarc.as<uint2>(), N.rmid.as<uint32_t>());
       HIP_TRY(hipGetLastError());
       // carry state; V_W' = V_S + N_in(V_S); V_A' = N(V_F) (flags zeroed by

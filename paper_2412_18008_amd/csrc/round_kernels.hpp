@@ -490,15 +490,35 @@ __global__ void __launch_bounds__(256) k_score(Overlay ov, const uint32_t *__res
 // Select (Alg. 5)
 // ===========================================================================
 // Selection keys (priority, label); also clears the per-vertex flags S and
-// newA that the contraction sets.
+// newA that the contraction sets and the shortcut-row bounds (4 arrays of n)
+// that k_row_bounds fills.
 __global__ void k_keys(uint32_t n, const int32_t *__restrict__ P, const uint32_t *__restrict__ gid,
                        const uint32_t *__restrict__ label, uint64_t *__restrict__ key,
-                       uint8_t *__restrict__ S, uint8_t *__restrict__ newA) {
+                       uint8_t *__restrict__ S, uint8_t *__restrict__ newA,
+                       uint32_t *__restrict__ bounds) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     key[u] = ((uint64_t)((uint32_t)P[u] ^ 0x80000000u) << 32) | label[gid[u]];
     S[u] = 0;
     newA[u] = 0;
+    bounds[u] = 0;
+    bounds[(size_t)n + u] = 0;
+    bounds[2 * (size_t)n + u] = 0;
+    bounds[3 * (size_t)n + u] = 0;
+  }
+}
+
+// Row bounds of sorted (row << kb | col) keys: for every row r with keys,
+// first[r] = index of its first key and stop[r] = one past its last (rows
+// without keys keep 0, 0 from k_keys).
+__global__ void k_row_bounds(const uint64_t *__restrict__ keys, const uint32_t *nkeys, int kb,
+                             uint32_t *__restrict__ first, uint32_t *__restrict__ stop) {
+  const uint32_t m = *nkeys;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint32_t r = (uint32_t)(keys[i] >> kb);
+    if (i == 0 || (uint32_t)(keys[i - 1] >> kb) != r) first[r] = i;
+    if (i + 1 == m || (uint32_t)(keys[i + 1] >> kb) != r) stop[r] = i + 1;
   }
 }
 
@@ -573,6 +593,23 @@ struct ArcOut {
   uint32_t *t, *h, *w, *m;
 };
 
+// Marks the entry of vertex x in row r (sorted by neighbour) as deleted: the
+// contracted vertex x leaves the overlay, and the rebuild then needs no
+// per-arc lookup of the contraction flag.  Rows of different contracted
+// vertices' neighbours never share an entry (the contracted set is
+// independent), so the write has no contention.
+__device__ __forceinline__ void kill_twin(const uint32_t *__restrict__ off, uint2 *__restrict__ arc,
+                                          uint32_t r, uint32_t x) {
+  uint32_t lo = off[r], hi = off[r + 1];
+  const uint32_t end = hi;
+  while (lo < hi) {
+    const uint32_t md = (lo + hi) >> 1;
+    if (arc[md].x < x) lo = md + 1;
+    else hi = md;
+  }
+  if (lo < end && arc[lo].x == x) arc[lo].y = SP_INF32;
+}
+
 // Moves the live arcs of each selected vertex into the CH (out-arcs to the
 // upward set, in-arcs to the downward set) at scanned positions, emits the
 // shortcut candidates (v1, v2, w1 + w2, label(u), u) and marks V_S and the
@@ -624,6 +661,7 @@ __global__ void __launch_bounds__(256) k_contract(
         const uint32_t gv = ov.gid[b.x];
         atomicAdd(&fs.cn[gv], 1u);
         atomicMax(&fs.depth[gv], dnext);
+        kill_twin(ov.roff, ov.rarc, b.x, u);  // (u -> b.x) in the reverse row of b.x
       }
       pos += __popcll(msk);
     }
@@ -655,6 +693,7 @@ __global__ void __launch_bounds__(256) k_contract(
         const uint32_t gv = ov.gid[a.x];
         if (!both) atomicAdd(&fs.cn[gv], 1u);
         atomicMax(&fs.depth[gv], dnext);
+        kill_twin(ov.foff, ov.farc, a.x, u);  // (a.x -> u) in the forward row of a.x
       }
       pos += __popcll(msk);
     }
@@ -877,39 +916,25 @@ __global__ void k_merge_rows(uint32_t n, int kb, const uint8_t *__restrict__ F,
                              const uint32_t *__restrict__ newid, const uint32_t *__restrict__ off,
                              const uint2 *__restrict__ arc, const uint32_t *__restrict__ mid,
                              const uint64_t *__restrict__ ekey, const uint32_t *__restrict__ eidx,
-                             const uint32_t *nrec, const uint32_t *__restrict__ uw,
+                             const uint32_t *__restrict__ rfirst, const uint32_t *__restrict__ rstop,
+                             const uint32_t *__restrict__ uw,
                              const uint32_t *__restrict__ umid, uint32_t *__restrict__ cnt,
                              const uint32_t *__restrict__ noff, uint2 *__restrict__ narc,
                              uint32_t *__restrict__ nmid) {
   const uint64_t lowmask = (1ull << kb) - 1ull;
-  const uint32_t ne = *nrec;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     if (F[u]) continue;
-    // shortcut row: keys in [u << kb, (u + 1) << kb)
-    const uint64_t lo_key = (uint64_t)u << kb, hi_key = lo_key | lowmask;
-    uint32_t lo = 0, hi = ne;
-    while (lo < hi) {
-      const uint32_t md = (lo + hi) >> 1;
-      if (ekey[md] < lo_key) lo = md + 1;
-      else hi = md;
-    }
-    uint32_t b = lo, b1;
-    {
-      uint32_t l2 = lo, h2 = ne;
-      while (l2 < h2) {
-        const uint32_t md = (l2 + h2) >> 1;
-        if (ekey[md] <= hi_key) l2 = md + 1;
-        else h2 = md;
-      }
-      b1 = l2;
-    }
+    // shortcut row: keys in [u << kb, (u + 1) << kb), bounds from k_row_bounds
+    uint32_t b = rfirst[u];
+    const uint32_t b1 = rstop[u];
     uint32_t a = off[u];
     const uint32_t a1 = off[u + 1];
     uint32_t c = 0;
     uint32_t outp = MODE ? noff[newid[u]] : 0;
     for (;;) {
-      while (a < a1 && (arc[a].y == SP_INF32 || F[arc[a].x])) a++;  // dead old arcs
+      // dead old arcs: pruned, or to a contracted vertex (marked by k_contract)
+      while (a < a1 && arc[a].y == SP_INF32) a++;
       const bool ha = a < a1, hb = b < b1;
       if (!ha && !hb) break;
       const uint32_t va = ha ? arc[a].x : 0xFFFFFFFFu;
