@@ -92,7 +92,7 @@ struct Builder {
   DBuf ovf1, ovf2, gtabs;
   // all-pairs table of the small overlay (exact mode): matrix tab_N^2,
   // table position of each original id, original id of each position
-  DBuf tab_D, tab_pos, tab_gid;
+  DBuf tab_D, tab_pos, tab_gid, tab_posl;
   bool tab_on = false;
   uint32_t tab_N = 0, tab_n0 = 0;
   DBuf dctr, tmp;
@@ -117,7 +117,7 @@ struct Builder {
                    &vw, &va, &vf, &cnt2, &cnt3, &rowb, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
                    &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
-                   &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid};
+                   &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid, &tab_posl};
     for (DBuf *b : all) b->release();
     if (hctr) (void)hipHostFree(hctr);
     for (auto &e : ev)
@@ -347,6 +347,7 @@ struct Builder {
     HIP_TRY(tab_D.ensure((size_t)N * N * 4));
     HIP_TRY(tab_pos.ensure((size_t)std::max<uint32_t>(n, 1) * 4));
     HIP_TRY(tab_gid.ensure((size_t)N * 4));
+    HIP_TRY(tab_posl.ensure((size_t)N * 4));
     k_fw_init<<<grid((uint64_t)N * N), 256, 0, st>>>(tab_D.as<uint32_t>(), N);
     HIP_TRY(hipGetLastError());
     k_fw_arcs<<<grid(v.n), 256, 0, st>>>(v, N, tab_D.as<uint32_t>(), tab_pos.as<uint32_t>(),
@@ -550,11 +551,14 @@ struct Builder {
       if (nw && tab_on) {
         rs.ls_tier1 = CH_LS_TABLE;
         if (stats) HIP_TRY(hipEventRecord(ev[2], st));
+        k_tab_posl<<<grid(O.n), 256, 0, st>>>(O.n, O.gid.as<uint32_t>(), tab_pos.as<uint32_t>(),
+                                               tab_posl.as<uint32_t>());
+        HIP_TRY(hipGetLastError());
         k_ls_table<<<(unsigned)std::min<uint64_t>(nw, (uint64_t)cus * 8), 64, 0, st>>>(
             v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
             mcap / kMemoBucket - 1, &dc()->ls, tab_D.as<uint32_t>(), tab_N, tab_n0,
-            tab_pos.as<uint32_t>(), tab_gid.as<uint32_t>(), alive_g.as<uint8_t>(),
-            f_ws.as<uint32_t>(), &dc()->err);
+            tab_pos.as<uint32_t>(), tab_gid.as<uint32_t>(), tab_posl.as<uint32_t>(),
+            alive_g.as<uint8_t>(), f_ws.as<uint32_t>(), &dc()->err);
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
       } else if (nw) {

@@ -167,6 +167,15 @@ __global__ void __launch_bounds__(kFwThreads) k_fw_rest(uint32_t *__restrict__ D
   fw_store(C, D, N, i, j);
 }
 
+// Table position of every vertex of the current overlay (local ids change
+// every round).
+__global__ void k_tab_posl(uint32_t n, const uint32_t *__restrict__ gid,
+                           const uint32_t *__restrict__ pos_of_gid, uint32_t *__restrict__ posl) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride)
+    posl[u] = pos_of_gid[gid[u]];
+}
+
 // Witness search of Alg. 3 answered from the table (exact mode): one group
 // of 64 lanes per source.  Per group in LDS: a seen bit and the largest
 // two-arc length per table position.
@@ -177,7 +186,8 @@ __global__ void __launch_bounds__(64) k_ls_table(
     MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
     const uint32_t *__restrict__ Dtab, uint32_t N, uint32_t n0,
     const uint32_t *__restrict__ pos_of_gid, const uint32_t *__restrict__ gid_of_pos,
-    const uint8_t *__restrict__ alive_g, uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
+    const uint32_t *__restrict__ posl, const uint8_t *__restrict__ alive_g,
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err) {
   __shared__ uint32_t s_seen[kTabMaxN / 32];
   __shared__ uint32_t s_tgt[kTabMaxN / 32];
   __shared__ uint32_t s_via[kTabMaxN];  // 0xFFFFFFFF - largest via (atomicMin)
@@ -188,7 +198,7 @@ __global__ void __launch_bounds__(64) k_ls_table(
   for (uint32_t k = blockIdx.x; k < nw; k += gridDim.x) {
     const uint32_t s = vw[k];
     const uint32_t gs = ov.gid[s];
-    const uint32_t ps = pos_of_gid[gs];
+    const uint32_t ps = posl[s];
     wave_sync();  // the previous source's LDS reads come first
     for (uint32_t i = l; i < words; i += kWave) {
       s_seen[i] = 0;
@@ -212,21 +222,35 @@ __global__ void __launch_bounds__(64) k_ls_table(
       }
       const uint32_t incl = gscan_incl<kWave>(rl);
       const uint32_t total = __shfl(incl, kWave - 1, kWave);
-      for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
-        const uint32_t idx = i0 + l;
-        const int src = gfind<kWave>(incl, idx);
-        const uint32_t srs = __shfl(rs, src, kWave), sinc = __shfl(incl, src, kWave);
-        const uint32_t srl = __shfl(rl, src, kWave), sw = __shfl(wsu, src, kWave);
-        if (idx < total) {
-          const uint2 b = ov.farc[srs + (idx - (sinc - srl))];
-          ss.arcs++;
-          if (b.x != s) {
-            const uint64_t via = (uint64_t)sw + b.y;
-            const uint32_t viac = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
-            const uint32_t p = pos_of_gid[ov.gid[b.x]];
-            atomicOr(&s_seen[p >> 5], 1u << (p & 31));
-            atomicMin(&s_via[p], 0xFFFFFFFFu - viac);
+      constexpr int U = 8;  // arcs per lane gathered before use
+      for (uint32_t i0 = 0; i0 < total; i0 += kWave * U) {
+        uint2 b[U];
+        uint32_t sw[U], p[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          const uint32_t idx = i0 + u * kWave + l;
+          b[u] = make_uint2(s, 0u);  // s itself is skipped below
+          sw[u] = 0;
+          if (i0 + u * kWave < total) {  // uniform across the wave
+            const int src = gfind<kWave>(incl, idx);
+            const uint32_t srs = __shfl(rs, src, kWave), sinc = __shfl(incl, src, kWave);
+            const uint32_t srl = __shfl(rl, src, kWave);
+            sw[u] = __shfl(wsu, src, kWave);
+            if (idx < total) {
+              b[u] = ov.farc[srs + (idx - (sinc - srl))];
+              ss.arcs++;
+            }
           }
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) p[u] = b[u].x != s ? posl[b[u].x] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+          if (b[u].x == s) continue;
+          const uint64_t via = (uint64_t)sw[u] + b[u].y;
+          const uint32_t viac = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
+          atomicOr(&s_seen[p[u] >> 5], 1u << (p[u] & 31));
+          atomicMin(&s_via[p[u]], 0xFFFFFFFFu - viac);
         }
       }
     }
