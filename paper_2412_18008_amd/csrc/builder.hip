@@ -83,8 +83,8 @@ struct Builder {
   int cur = 0;
   DBuf aflag, aflag_next, wflag, F, S, newA, key, paircnt, newid, cnt, cnt2, cnt3, vw, va, vf;
   DBuf rowb;  // shortcut-row bounds: 4 arrays of the overlay's vertex count
-  DBuf memo, alive_g;
-  uint64_t mcap = 0, mcount = 0;
+  DBuf memo, memo_spare, alive_g;
+  uint64_t mcap = 0, mcount = 0, mwmask = 0;  // slots, entries (upper bound), region width - 1
   DBuf f_cn, f_depth, f_ws, f_feat, mlpw;  // learned-priority feature state
   DBuf cup, cdn, cpair;
   DBuf ekey, ekey_alt, eidx, eidx_alt, ew, elab, emid, ehead, eheads, ukey, uw, umid, rkey,
@@ -114,7 +114,7 @@ struct Builder {
     o[0].release();
     o[1].release();
     DBuf *all[] = {&aflag, &aflag_next, &wflag, &F, &S, &newA, &key, &paircnt, &newid, &cnt,
-                   &vw, &va, &vf, &cnt2, &cnt3, &rowb, &memo, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
+                   &vw, &va, &vf, &cnt2, &cnt3, &rowb, &memo, &memo_spare, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
                    &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
                    &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid, &tab_posl};
@@ -313,26 +313,48 @@ struct Builder {
     return CH_OK;
   }
 
-  int ensure_memo(uint64_t extra) {
-    const uint64_t need = mcount + extra;
-    if (need * 2 <= mcap) return CH_OK;
-    uint64_t ncap = next_pow2(std::max<uint64_t>(need * 2, 1024));
-    DBuf nm;
-    HIP_TRY(nm.ensure(ncap * sizeof(MemoSlot)));
-    HIP_TRY(fill_u64(nm.as<uint64_t>(), SP_EMPTY64, ncap * 2, st));
+  MemoRef mref() { return MemoRef{memo.as<MemoSlot>(), mcap / kMemoBucket - 1, mwmask}; }
+
+  // Room for `extra` more memo entries with `alive` live vertices.  The table
+  // is rebuilt from its live entries when it would pass half full, or when
+  // the entries per live vertex outgrow the source regions (mcount bounds
+  // the live entries, so mcount <= 12 W alive keeps a source's first buckets
+  // from filling).  The rebuilt table has twice the room the live entries
+  // and `extra` need, and regions of W = 2 x (live entries per live vertex)
+  // / 8 buckets, so a region is a quarter full after the rebuild.
+  int ensure_memo(uint64_t extra, uint32_t alive) {
+    const uint64_t W = mwmask + 1, a = std::max<uint32_t>(alive, 1);
+    const bool grow = (mcount + extra) * 2 > mcap;
+    const bool spread = mcap && mcount > 12 * W * a && W * 4 < mcap / kMemoBucket;
+    if (!grow && !spread) return CH_OK;
+    uint64_t live = 0;
+    if (mcap) {
+      HIP_TRY(hipMemsetAsync(&dc()->kept, 0, 8, st));
+      k_memo_count_live<<<grid(mcap), 256, 0, st>>>(memo.as<MemoSlot>(), mcap,
+                                                     alive_g.as<uint8_t>(), &dc()->kept);
+      HIP_TRY(hipGetLastError());
+      TRY(readback());
+      live = hctr->kept;
+    }
+    const uint64_t ncap = next_pow2(std::max<uint64_t>((live + extra) * 2, 1024));
+    const uint64_t per = (2 * live + 8 * a - 1) / (8 * a);
+    const uint64_t nw = std::min<uint64_t>(next_pow2(std::max<uint64_t>(per, 1)),
+                                           ncap / kMemoBucket / 4);
+    HIP_TRY(memo_spare.ensure(ncap * sizeof(MemoSlot)));
+    HIP_TRY(fill_u64(memo_spare.as<uint64_t>(), SP_EMPTY64, ncap * 2, st));
+    const MemoRef nt{memo_spare.as<MemoSlot>(), ncap / kMemoBucket - 1, nw - 1};
     uint64_t kept = 0;
     if (mcap) {
       HIP_TRY(hipMemsetAsync(&dc()->kept, 0, 8, st));
       k_memo_rehash<<<grid(mcap), 256, 0, st>>>(memo.as<MemoSlot>(), mcap, alive_g.as<uint8_t>(),
-                                                 nm.as<MemoSlot>(), ncap / kMemoBucket - 1,
-                                                 &dc()->kept);
+                                                 nt, &dc()->kept);
       HIP_TRY(hipGetLastError());
       TRY(readback());
       kept = hctr->kept;
     }
-    memo.release();
-    memo = nm;
+    std::swap(memo, memo_spare);
     mcap = ncap;
+    mwmask = nw - 1;
     mcount = kept;
     return CH_OK;
   }
@@ -382,7 +404,7 @@ struct Builder {
     DevCtr *d = dc();
     auto go = [&](auto kern) {
       kern<<<(unsigned)cus * blocks_per_cu, kLsBlock, 0, st>>>(
-          v, list, nl, aflag.as<uint8_t>(), memo.as<MemoSlot>(), mcap / kMemoBucket - 1,
+          v, list, nl, aflag.as<uint8_t>(), mref(),
           tier == 1 ? &d->ls : &d->ls2, nl_dev, tier == 1 ? &d->work1 : &d->work2,
           tier == 1 ? ovf1.as<uint32_t>() : ovf2.as<uint32_t>(),
           tier == 1 ? &d->novf1 : &d->novf2, chunk, f_ws.as<uint32_t>(), &d->err,
@@ -393,14 +415,12 @@ struct Builder {
   }
   template <int G>
   void launch_score(const Overlay &v, uint32_t na) {
-    k_score<G><<<ggrid<G>(na), 256, 0, st>>>(v, va.as<uint32_t>(), na, memo.as<MemoSlot>(),
-                                              mcap / kMemoBucket - 1, ov[cur].P.as<int32_t>(),
+    k_score<G><<<ggrid<G>(na), 256, 0, st>>>(v, va.as<uint32_t>(), na, mref(), ov[cur].P.as<int32_t>(),
                                               paircnt.as<uint32_t>(), fstate());
   }
   template <int G>
   void launch_prune(const Overlay &v, uint32_t nw) {
-    k_prune<G><<<ggrid<G>(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, memo.as<MemoSlot>(),
-                                              mcap / kMemoBucket - 1, &dc()->pruned, &dc()->err);
+    k_prune<G><<<ggrid<G>(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, mref(), &dc()->pruned, &dc()->err);
   }
   template <int G>
   void launch_select(const Overlay &v) {
@@ -411,7 +431,7 @@ struct Builder {
   void launch_ccount(const Overlay &v, uint32_t cap) {
     k_contract_count<G><<<ggrid<G>(cap), 256, 0, st>>>(
         v, vf.as<uint32_t>(), &dc()->c32[C_NF], cap, aflag.as<uint8_t>(), paircnt.as<uint32_t>(),
-        memo.as<MemoSlot>(), mcap / kMemoBucket - 1, cup.as<uint32_t>(), cdn.as<uint32_t>(),
+        mref(), cup.as<uint32_t>(), cdn.as<uint32_t>(),
         cpair.as<uint32_t>());
   }
   // scanned positions at offset cap of cup, cdn, cpair
@@ -423,7 +443,7 @@ struct Builder {
               ch->dn_m.as<uint32_t>()};
     k_contract<G><<<ggrid<G>(nf), 256, 0, st>>>(
         v, vf.as<uint32_t>(), nf, ov[cur].P.as<int32_t>(), ch->label.as<uint32_t>(),
-        memo.as<MemoSlot>(), mcap / kMemoBucket - 1, round, ch->level.as<uint32_t>(), ch->score.as<int32_t>(),
+        mref(), round, ch->level.as<uint32_t>(), ch->score.as<int32_t>(),
         alive_g.as<uint8_t>(), cup.as<uint32_t>() + cap, cdn.as<uint32_t>() + cap,
         cpair.as<uint32_t>() + cap, up, dn, ch->nup, ch->ndown, cpair.as<uint32_t>(), kb,
         ekey.as<uint64_t>(), ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(),
@@ -539,7 +559,7 @@ struct Builder {
       // ---- Step 1: LocalSearch (Alg. 3) --------------------------------
       // memo capacity for this round's inserts (bound computed with the
       // previous round's final readback)
-      TRY(ensure_memo(next_bound));
+      TRY(ensure_memo(next_bound, O.n));
       HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
       const double thr = prm.dense_deg10 ? prm.dense_deg10 / 10.0 : 5.0;
       const bool sparse = avgdeg <= thr;
@@ -555,8 +575,7 @@ struct Builder {
                                                tab_posl.as<uint32_t>());
         HIP_TRY(hipGetLastError());
         k_ls_table<<<(unsigned)std::min<uint64_t>(nw, (uint64_t)cus * 8), 64, 0, st>>>(
-            v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
-            mcap / kMemoBucket - 1, &dc()->ls, tab_D.as<uint32_t>(), tab_N, tab_n0,
+            v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(), mref(), &dc()->ls, tab_D.as<uint32_t>(), tab_N, tab_n0,
             tab_pos.as<uint32_t>(), tab_gid.as<uint32_t>(), tab_posl.as<uint32_t>(),
             alive_g.as<uint8_t>(), f_ws.as<uint32_t>(), &dc()->err);
         HIP_TRY(hipGetLastError());
@@ -663,8 +682,7 @@ struct Builder {
         }
         auto global = hop ? k_local_search_global<true> : k_local_search_global<false>;
         global<<<(unsigned)ntab, 64, 0, st>>>(
-            v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), memo.as<MemoSlot>(),
-            mcap / kMemoBucket - 1, &dc()->ls2, gtabs.as<uint32_t>(), cap, f_ws.as<uint32_t>(),
+            v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), mref(), &dc()->ls2, gtabs.as<uint32_t>(), cap, f_ws.as<uint32_t>(),
             &dc()->err, prm.hop_limit);
         HIP_TRY(hipGetLastError());
         TRY(after_search());

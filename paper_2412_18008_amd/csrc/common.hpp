@@ -134,15 +134,26 @@ __host__ __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
 // ---------------------------------------------------------------------------
 // Memo: open addressing over 16-byte slots {key = (s << 32) | v, value},
 // grouped in buckets of 16 slots (256 bytes).  The probe sequence of a pair
-// visits bucket 0 = the bucket of its source s, then buckets chosen by the
-// pair; inside a bucket it starts at a pair-dependent slot and wraps.  So
-// the entries of one source share one bucket until it fills, and no probe
-// sequence walks a long cluster.  `bmask` = number of buckets - 1.
+// visits bucket 0 in the region of its source s (W adjacent buckets starting
+// at a bucket chosen by s, the one inside it chosen by v), then buckets
+// chosen by the pair; inside a bucket it starts at a pair-dependent slot and
+// wraps.  So the entries of one source share W buckets, and the builder
+// sizes W (a power of two, `wmask` = W - 1) from the entries per live source
+// whenever it rebuilds the table: W = 1 while sources hold a few entries
+// (all of a source's lookups touch one bucket), larger once they hold
+// hundreds (a lookup still resolves in its first bucket).  `bmask` = number
+// of buckets - 1.
 // ---------------------------------------------------------------------------
 struct MemoSlot {
   uint64_t key;
   uint32_t val;
   uint32_t pad;
+};
+
+struct MemoRef {
+  MemoSlot *t;
+  uint64_t bmask;
+  uint64_t wmask;
 };
 
 constexpr uint32_t kMemoBucket = 16;
@@ -154,21 +165,27 @@ __host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ uint64_t memo_bucket(uint64_t k, uint32_t s, uint32_t i, uint64_t bmask) {
-  return (i == 0 ? mix64(s) : mix64(k ^ (0x9E3779B97F4A7C15ull * i))) & bmask;
+// Hash of the pair's target: the low 4 bits pick the first slot inside a
+// bucket, the rest the bucket inside the source's region.
+__device__ __forceinline__ uint32_t memo_vhash(uint32_t v) { return lowbias32(v ^ 0x9e3779b9u); }
+
+__device__ __forceinline__ uint64_t memo_bucket(const MemoRef &m, uint64_t k, uint32_t s,
+                                                uint32_t hv, uint32_t i) {
+  return (i == 0 ? mix64(s) + ((hv >> 4) & m.wmask)
+                 : mix64(k ^ (0x9E3779B97F4A7C15ull * i))) & m.bmask;
 }
 
 // Returns the stored value or SP_INF32 when the pair is absent.  Slots are
 // read four at a time (independent loads inside one bucket), then checked
 // in probe order.  The probe sequence starts at slot j0 of the first bucket
 // (the earlier slots known to hold neither the pair nor an empty slot).
-__device__ __forceinline__ uint32_t memo_get_from(const MemoSlot *__restrict__ t, uint64_t bmask,
-                                                  uint32_t s, uint32_t v, uint32_t j0,
-                                                  uint32_t *probes) {
+__device__ __forceinline__ uint32_t memo_get_from(const MemoRef &m, uint32_t s, uint32_t v,
+                                                  uint32_t j0, uint32_t *probes) {
   const uint64_t k = ((uint64_t)s << 32) | v;
-  const uint32_t o = lowbias32(v ^ 0x9e3779b9u) & (kMemoBucket - 1);
+  const uint32_t hv = memo_vhash(v);
+  const uint32_t o = hv & (kMemoBucket - 1);
   for (uint32_t i = 0;; i++) {
-    const MemoSlot *b = t + memo_bucket(k, s, i, bmask) * kMemoBucket;
+    const MemoSlot *b = m.t + memo_bucket(m, k, s, hv, i) * kMemoBucket;
     for (uint32_t j = i == 0 ? j0 : 0; j < kMemoBucket; j += 4) {
       ulonglong2 e[4];
 #pragma unroll
@@ -194,9 +211,9 @@ __device__ __forceinline__ uint32_t memo_get_from(const MemoSlot *__restrict__ t
   }
 }
 
-__device__ __forceinline__ uint32_t memo_get(const MemoSlot *__restrict__ t, uint64_t bmask,
-                                             uint32_t s, uint32_t v, uint32_t *probes) {
-  return memo_get_from(t, bmask, s, v, 0, probes);
+__device__ __forceinline__ uint32_t memo_get(const MemoRef &m, uint32_t s, uint32_t v,
+                                             uint32_t *probes) {
+  return memo_get_from(m, s, v, 0, probes);
 }
 
 // Lookups per lane batched by the pair loops of score, contract and prune.
@@ -206,17 +223,17 @@ constexpr int kPairBatch = 4;
 // any is examined (4K independent loads in flight), the rare lookups that
 // need more slots continue one by one.  out[k] = SP_INF32 for inactive k.
 template <int K>
-__device__ __forceinline__ void memo_get_batch(const MemoSlot *__restrict__ t, uint64_t bmask,
-                                               const uint32_t (&s)[K], const uint32_t (&v)[K],
-                                               const bool (&act)[K], uint32_t (&out)[K],
-                                               uint32_t *probes) {
+__device__ __forceinline__ void memo_get_batch(const MemoRef &m, const uint32_t (&s)[K],
+                                               const uint32_t (&v)[K], const bool (&act)[K],
+                                               uint32_t (&out)[K], uint32_t *probes) {
   ulonglong2 e[K][4];
   uint64_t key[K];
 #pragma unroll
   for (int k = 0; k < K; k++) {
     key[k] = ((uint64_t)s[k] << 32) | v[k];
-    const uint32_t o = lowbias32(v[k] ^ 0x9e3779b9u) & (kMemoBucket - 1);
-    const MemoSlot *b = t + memo_bucket(key[k], s[k], 0, bmask) * kMemoBucket;
+    const uint32_t hv = memo_vhash(v[k]);
+    const uint32_t o = hv & (kMemoBucket - 1);
+    const MemoSlot *b = m.t + memo_bucket(m, key[k], s[k], hv, 0) * kMemoBucket;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
       e[k][q] = make_ulonglong2(SP_EMPTY64, 0ull);
@@ -238,19 +255,19 @@ __device__ __forceinline__ void memo_get_batch(const MemoSlot *__restrict__ t, u
         done = true;
       }
     }
-    if (!done) r = memo_get_from(t, bmask, s[k], v[k], 4, probes);
+    if (!done) r = memo_get_from(m, s[k], v[k], 4, probes);
     out[k] = r;
   }
 }
 
 // Insert (s, v) -> val if the pair is absent (first writer wins).  The
 // table is kept at most half full, so an empty slot is always reached.
-__device__ __forceinline__ void memo_put(MemoSlot *__restrict__ t, uint64_t bmask, uint32_t s,
-                                         uint32_t v, uint32_t val) {
+__device__ __forceinline__ void memo_put(const MemoRef &m, uint32_t s, uint32_t v, uint32_t val) {
   const uint64_t k = ((uint64_t)s << 32) | v;
-  const uint32_t o = lowbias32(v ^ 0x9e3779b9u) & (kMemoBucket - 1);
+  const uint32_t hv = memo_vhash(v);
+  const uint32_t o = hv & (kMemoBucket - 1);
   for (uint32_t i = 0;; i++) {
-    MemoSlot *b = t + memo_bucket(k, s, i, bmask) * kMemoBucket;
+    MemoSlot *b = m.t + memo_bucket(m, k, s, hv, i) * kMemoBucket;
     for (uint32_t j = 0; j < kMemoBucket; j++) {
       MemoSlot *slot = &b[(o + j) & (kMemoBucket - 1)];
       uint64_t cur = __hip_atomic_load(&slot->key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

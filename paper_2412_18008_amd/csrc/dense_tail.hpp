@@ -183,7 +183,7 @@ constexpr int kTabMaxN = 4096;  // largest table the lookup kernel serves
 
 __global__ void __launch_bounds__(64) k_ls_table(
     Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
-    MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
+    MemoRef memo, LsCounters *__restrict__ cnt,
     const uint32_t *__restrict__ Dtab, uint32_t N, uint32_t n0,
     const uint32_t *__restrict__ pos_of_gid, const uint32_t *__restrict__ gid_of_pos,
     const uint32_t *__restrict__ posl, const uint8_t *__restrict__ alive_g,
@@ -286,7 +286,7 @@ __global__ void __launch_bounds__(64) k_ls_table(
         ks[q] = gs;
         kv[q] = act[q] ? gid_of_pos[pos[q]] : 0u;
       }
-      memo_get_batch<kPairBatch>(memo, mmask, ks, kv, act, got, &ss.probes);
+      memo_get_batch<kPairBatch>(memo, ks, kv, act, got, &ss.probes);
 #pragma unroll
       for (int q = 0; q < kPairBatch; q++) {
         if (!act[q] || got[q] != SP_INF32) continue;
@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(64) k_ls_table(
         if (d[q] > D) continue;
         if (alive_g[g[q]]) ball++;
         if ((s_tgt[p >> 5] >> (p & 31)) & 1u) {
-          memo_put(memo, mmask, gs, g[q], d[q]);
+          memo_put(memo, gs, g[q], d[q]);
           ss.inserts++;
         }
       }

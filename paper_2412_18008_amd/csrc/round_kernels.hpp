@@ -186,7 +186,7 @@ constexpr int kLsBlock = 64;  // one wave per workgroup
 template <int G, int CAP, bool HOP>
 __global__ void __launch_bounds__(kLsBlock) k_local_search(
     Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
-    MemoSlot *__restrict__ memo, uint64_t mmask, LsCounters *__restrict__ cnt,
+    MemoRef memo, LsCounters *__restrict__ cnt,
     const uint32_t *__restrict__ nw_dev, uint32_t *__restrict__ work,
     uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count, uint32_t chunk,
     uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
     const uint32_t end = min(base + chunk, nw);
     for (uint32_t i = base; i < end; i++) {
       const uint32_t s = vw[i];
-      if (!search_source<G, HOP>(ov, aflag, memo, mmask, T, s, ss, ws, err, hops)) {
+      if (!search_source<G, HOP>(ov, aflag, memo, T, s, ss, ws, err, hops)) {
         if (gl == 0) {
           const uint32_t k = atomicAdd(ovf_count, 1u);
           ovf_list[k] = s;
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
 template <bool HOP>
 __global__ void __launch_bounds__(64) k_local_search_global(
     Overlay ov, const uint32_t *__restrict__ list, uint32_t nlist,
-    const uint8_t *__restrict__ aflag, MemoSlot *__restrict__ memo, uint64_t mmask,
+    const uint8_t *__restrict__ aflag, MemoRef memo,
     LsCounters *__restrict__ cnt, uint32_t *__restrict__ tabs, uint32_t cap,
     uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
   constexpr size_t kArrays = HOP ? 7 : 6;
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(64) k_local_search_global(
   T.limit = cap;  // cap >= 2 n_o: never overflows
   SearchStats ss;
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
-    if (!search_source<64, HOP>(ov, aflag, memo, mmask, T, list[i], ss, ws, err, hops)) {
+    if (!search_source<64, HOP>(ov, aflag, memo, T, list[i], ss, ws, err, hops)) {
       if (lane_id() == 0) atomicOr(err, kErrCapacity);
     }
   }
@@ -281,8 +281,7 @@ __global__ void __launch_bounds__(64) k_local_search_global(
 // source, lanes over its out-arcs.
 template <int G>
 __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__restrict__ vw,
-                                               uint32_t nw, const MemoSlot *__restrict__ memo,
-                                               uint64_t bmask,
+                                               uint32_t nw, MemoRef memo,
                                                unsigned long long *__restrict__ npruned,
                                                uint32_t *__restrict__ err) {
   const uint32_t ngroups = gridDim.x * (blockDim.x / G);
@@ -309,7 +308,7 @@ __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__res
         ss[q] = gs;
         gv[q] = act[q] ? ov.gid[arc[q].x] : 0u;
       }
-      memo_get_batch<kPairBatch>(memo, bmask, ss, gv, act, dd, &probes);
+      memo_get_batch<kPairBatch>(memo, ss, gv, act, dd, &probes);
 #pragma unroll
       for (int q = 0; q < kPairBatch; q++) {
         const uint2 a = arc[q];
@@ -361,7 +360,7 @@ struct PairBatch {
 };
 
 template <int G>
-__device__ __forceinline__ void load_pairs(const Overlay &ov, const MemoSlot *memo, uint64_t mmask,
+__device__ __forceinline__ void load_pairs(const Overlay &ov, const MemoRef &memo,
                                            uint32_t i0, uint32_t o0, uint32_t dout, uint64_t np,
                                            bool narrow, uint64_t p0, PairBatch &B,
                                            uint32_t *probes) {
@@ -388,12 +387,12 @@ __device__ __forceinline__ void load_pairs(const Overlay &ov, const MemoSlot *me
       gv[k] = ov.gid[B.b[k].x];
     }
   }
-  memo_get_batch<kPairBatch>(memo, mmask, gs, gv, B.live, B.d, probes);
+  memo_get_batch<kPairBatch>(memo, gs, gv, B.live, B.d, probes);
 }
 
 template <int G>
-__device__ __forceinline__ uint32_t count_pairs(const Overlay &ov, const MemoSlot *memo,
-                                                uint64_t mmask, uint32_t u, uint32_t *probes) {
+__device__ __forceinline__ uint32_t count_pairs(const Overlay &ov, const MemoRef &memo,
+                                                uint32_t u, uint32_t *probes) {
   const int gl = glane<G>();
   const uint32_t i0 = ov.roff[u], din = ov.roff[u + 1] - i0;
   const uint32_t o0 = ov.foff[u], dout = ov.foff[u + 1] - o0;
@@ -402,7 +401,7 @@ __device__ __forceinline__ uint32_t count_pairs(const Overlay &ov, const MemoSlo
   const bool narrow = np <= 0xFFFFFFFFull;
   for (uint64_t p0 = gl; p0 < np; p0 += (uint64_t)G * kPairBatch) {
     PairBatch B;
-    load_pairs<G>(ov, memo, mmask, i0, o0, dout, np, narrow, p0, B, probes);
+    load_pairs<G>(ov, memo, i0, o0, dout, np, narrow, p0, B, probes);
 #pragma unroll
     for (int k = 0; k < kPairBatch; k++)
       cnt += B.live[k] && (B.d[k] == SP_INF32 || B.via[k] <= B.d[k]);
@@ -455,15 +454,14 @@ __device__ __forceinline__ float squash(uint32_t x, float c) {
 // Edge difference (the plain priority) and the features of the learned one.
 template <int G>
 __global__ void __launch_bounds__(256) k_score(Overlay ov, const uint32_t *__restrict__ va,
-                                               uint32_t na, const MemoSlot *__restrict__ memo,
-                                               uint64_t mmask, int32_t *__restrict__ P,
+                                               uint32_t na, MemoRef memo, int32_t *__restrict__ P,
                                                uint32_t *__restrict__ paircnt, FeatState fs) {
   const uint32_t ngroups = gridDim.x * (blockDim.x / G);
   const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
   uint32_t probes = 0;
   for (uint32_t k = g0; k < na; k += ngroups) {
     const uint32_t u = va[k];
-    const uint32_t pairs = count_pairs<G>(ov, memo, mmask, u, &probes);
+    const uint32_t pairs = count_pairs<G>(ov, memo, u, &probes);
     const uint3 deg = count_neighbours<G>(ov, u);  // out, in, |N(u)|
     if (glane<G>() == 0) {
       int64_t p = (int64_t)pairs - (int64_t)deg.z;
@@ -558,7 +556,7 @@ template <int G>
 __global__ void __launch_bounds__(256) k_contract_count(
     Overlay ov, const uint32_t *__restrict__ vf, const uint32_t *nfp, uint32_t cap,
     const uint8_t *__restrict__ aflag, const uint32_t *__restrict__ paircnt,
-    const MemoSlot *__restrict__ memo, uint64_t mmask, uint32_t *__restrict__ cup,
+    MemoRef memo, uint32_t *__restrict__ cup,
     uint32_t *__restrict__ cdn, uint32_t *__restrict__ cpair) {
   const uint32_t ngroups = gridDim.x * (blockDim.x / G);
   const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
@@ -580,7 +578,7 @@ __global__ void __launch_bounds__(256) k_contract_count(
     ci = gsum<G>(ci);
     uint32_t pc;
     if (aflag[u]) pc = paircnt[u];
-    else pc = count_pairs<G>(ov, memo, mmask, u, &probes);
+    else pc = count_pairs<G>(ov, memo, u, &probes);
     if (gl == 0) {
       cup[k] = co;
       cdn[k] = ci;
@@ -617,7 +615,7 @@ __device__ __forceinline__ void kill_twin(const uint32_t *__restrict__ off, uint
 template <int G>
 __global__ void __launch_bounds__(256) k_contract(
     Overlay ov, const uint32_t *__restrict__ vf, uint32_t nf, const int32_t *__restrict__ P,
-    const uint32_t *__restrict__ label, const MemoSlot *__restrict__ memo, uint64_t mmask,
+    const uint32_t *__restrict__ label, MemoRef memo,
     uint32_t round, uint32_t *__restrict__ level, int32_t *__restrict__ score,
     uint8_t *__restrict__ alive_g, const uint32_t *__restrict__ pup,
     const uint32_t *__restrict__ pdn, const uint32_t *__restrict__ ppair, ArcOut up, ArcOut dn,
@@ -705,7 +703,7 @@ __global__ void __launch_bounds__(256) k_contract(
     const bool narrow = np <= 0xFFFFFFFFull;
     for (uint64_t q0 = 0; q0 < np; q0 += (uint64_t)G * kPairBatch) {
       PairBatch B;
-      load_pairs<G>(ov, memo, mmask, i0, o0, dout, np, narrow, q0 + gl, B, &probes);
+      load_pairs<G>(ov, memo, i0, o0, dout, np, narrow, q0 + gl, B, &probes);
       // emit in pair order: chunk k holds pairs q0 + k G .. q0 + k G + G - 1
 #pragma unroll
       for (int k = 0; k < kPairBatch; k++) {
@@ -1006,11 +1004,27 @@ __global__ void k_mark_in_neighbours(uint32_t n, const uint8_t *__restrict__ F,
   }
 }
 
-// Memo rehash into a larger table, dropping entries with a contracted
-// endpoint (they are never looked up again).
+// Entries of the memo whose endpoints are both live (the only ones looked up
+// again: lookups and inserts always pair two live vertices).
+__global__ void k_memo_count_live(const MemoSlot *__restrict__ old, uint64_t ocap,
+                                  const uint8_t *__restrict__ alive_g,
+                                  unsigned long long *__restrict__ live) {
+  uint64_t c = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ocap; i += stride) {
+    const uint64_t k = old[i].key;
+    if (k == SP_EMPTY64) continue;
+    c += alive_g[(uint32_t)(k >> 32)] && alive_g[(uint32_t)k];
+  }
+  c = gsum64<kWave>(c);
+  if (lane_id() == 0 && c) atomicAdd(live, (unsigned long long)c);
+}
+
+// Memo rebuild: the live entries of `old` inserted into the empty table nt
+// (its own size and source-region width), the others dropped.
 __global__ void k_memo_rehash(const MemoSlot *__restrict__ old, uint64_t ocap,
-                              const uint8_t *__restrict__ alive_g, MemoSlot *__restrict__ nt,
-                              uint64_t nmask, unsigned long long *__restrict__ kept) {
+                              const uint8_t *__restrict__ alive_g, MemoRef nt,
+                              unsigned long long *__restrict__ kept) {
   uint64_t c = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ocap; i += stride) {
@@ -1018,7 +1032,7 @@ __global__ void k_memo_rehash(const MemoSlot *__restrict__ old, uint64_t ocap,
     if (k == SP_EMPTY64) continue;
     const uint32_t s = (uint32_t)(k >> 32), v = (uint32_t)k;
     if (!alive_g[s] || !alive_g[v]) continue;
-    memo_put(nt, nmask, s, v, old[i].val);
+    memo_put(nt, s, v, old[i].val);
     c++;
   }
   c = gsum64<kWave>(c);

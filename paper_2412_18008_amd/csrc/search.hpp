@@ -174,8 +174,7 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
 // Targets the walks do not reach get no memo entry.
 template <int G, bool HOP, typename IdxT, bool GL>
 __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ aflag,
-                              MemoSlot *__restrict__ memo, uint64_t mmask,
-                              const Tab<IdxT, GL> &T, uint32_t s, SearchStats &ss,
+                              const MemoRef &memo, const Tab<IdxT, GL> &T, uint32_t s, SearchStats &ss,
                               uint32_t *__restrict__ ws, uint32_t *__restrict__ err,
                               uint32_t hops) {
   const int gl = glane<G>();
@@ -229,7 +228,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
         ks[q] = gs;
         kv[q] = act[q] ? ov.gid[T.ld(&T.key[slot[q]])] : 0u;
       }
-      memo_get_batch<K>(memo, mmask, ks, kv, act, got, &ss.probes);
+      memo_get_batch<K>(memo, ks, kv, act, got, &ss.probes);
 #pragma unroll
       for (int q = 0; q < K; q++) {
         if (!act[q]) continue;
@@ -353,7 +352,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       if (T.ld(&T.flag[slot]) & kFlagTarget) {
         const uint32_t d = T.ld(&T.dist[slot]);
         if (d <= D) {
-          memo_put(memo, mmask, gs, ov.gid[T.ld(&T.key[slot])], d);
+          memo_put(memo, gs, ov.gid[T.ld(&T.key[slot])], d);
           ss.inserts++;
         } else if (!HOP) {
           atomicOr(err, kErrCapacity);  // cannot happen: every target is within D
