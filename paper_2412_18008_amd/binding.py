@@ -62,10 +62,18 @@ CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
 
 
 def CH_Q_WAVES(nw):
-    """Query flag: waves that share one query (1, 2, 4; 0 = default)."""
-    if nw not in (0, 1, 2, 4):
-        raise ValueError("waves must be 0, 1, 2 or 4")
+    """Query flag: waves that share one query (1, 2, 4, 8; 0 = default)."""
+    if nw not in (0, 1, 2, 4, 8):
+        raise ValueError("waves must be 0, 1, 2, 4 or 8")
     return nw << 8
+
+
+def CH_Q_LEVEL_WINDOW(w):
+    """Query flag: level window of a search step (1 .. 254; 0 = default,
+    255 = none)."""
+    if not 0 <= w <= 255:
+        raise ValueError("window must be in 0 .. 255")
+    return w << 12
 
 
 class MlpTrainParams(C.Structure):
@@ -180,12 +188,13 @@ class CH:
             _lib.ch_free(self.h)
             self.h = None
 
-    def query(self, s, t, stream=None, waves=0):
+    def query(self, s, t, stream=None, waves=0, window=0):
         """dist[i] = shortest s[i] -> t[i] distance (uint64, max = unreachable).
         numpy inputs give a numpy result; torch CUDA inputs give a torch CUDA
         int64 tensor (holding the uint64 bit patterns).  waves: waves per
-        query in the kernel (1, 2, 4; 0 = default)."""
-        qf = CH_Q_WAVES(waves)
+        query in the kernel (1, 2, 4, 8; 0 = default); window: level window of
+        a search step (0 = default, 255 = none)."""
+        qf = CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window)
         if _is_torch_cuda(s):
             import torch
 
@@ -202,7 +211,7 @@ class CH:
                                     dist.ctypes.data, qf, stream), "ch_query_batch")
         return dist
 
-    def query_stats(self, s, t, waves=0):
+    def query_stats(self, s, t, waves=0, window=0):
         """(dist, visited): distances and vertices in the two upward search
         spaces of each query (numpy, host)."""
         s = np.ascontiguousarray(s, np.uint32)
@@ -211,7 +220,8 @@ class CH:
         vis = np.empty(len(s), np.uint32)
         _check(lib().ch_query_batch_stats(self.h, s.ctypes.data, t.ctypes.data, len(s),
                                           dist.ctypes.data, vis.ctypes.data,
-                                          CH_Q_WAVES(waves), None),
+                                          CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window),
+                                          None),
                "ch_query_batch_stats")
         return dist, vis
 

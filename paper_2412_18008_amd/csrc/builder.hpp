@@ -29,6 +29,10 @@ struct ch_s {
   // arcs stored at their head (walked head -> tail by the backward search)
   bool has_index = false;
   sp::DBuf q_upoff, q_uparc, q_dnoff, q_dnarc;  // offsets uint32[n+1], arcs uint2{other, w}
+  sp::DBuf q_lstart;  // first rank of each level (nlev + 1 entries)
+  uint32_t q_nlev = 0;
+  sp::DBuf q_wend;    // end of the query's level window at each rank
+  uint32_t q_wend_win = 0;  // its window (0: not computed)
 
   // query scratch
   sp::DBuf q_s, q_t, q_d, q_v, q_ovf, q_ovf2, q_tab, q_gtab, q_ctr;

@@ -75,6 +75,13 @@ __device__ __forceinline__ uint32_t gmax(uint32_t v) {
 }
 
 template <int G>
+__device__ __forceinline__ uint32_t gmin(uint32_t v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = min(v, (uint32_t)__shfl_xor(v, o, G));
+  return v;
+}
+
+template <int G>
 __device__ __forceinline__ uint64_t gmin64(uint64_t v) {
 #pragma unroll
   for (int o = G / 2; o > 0; o >>= 1) {

@@ -170,6 +170,64 @@ static int sort_arcs(ch_s *ch, bool up, DBuf &k1, DBuf &k2, DBuf &v1, DBuf &v2, 
   return CH_OK;
 }
 
+// Level of the vertex at each rank.
+__global__ void k_level_by_rank(uint32_t n, const uint32_t *__restrict__ rank,
+                                const uint32_t *__restrict__ level, uint32_t *__restrict__ lvr) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    lvr[rank[v]] = level[v];
+}
+
+// lstart[L] = the first rank whose level is >= L, for L <= nlev (levels do
+// not decrease along the ranks).
+__global__ void k_level_starts(uint32_t n, const uint32_t *__restrict__ lvr, uint32_t nlev,
+                               uint32_t *__restrict__ lstart) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t L = blockIdx.x * blockDim.x + threadIdx.x; L <= nlev; L += stride) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+      const uint32_t md = (lo + hi) >> 1;
+      if (lvr[md] < L) lo = md + 1;
+      else hi = md;
+    }
+    lstart[L] = lo;
+  }
+}
+
+// End of the level window of `win` levels that starts at each rank: the
+// first rank of level level(v) + win + 1 (n past the last level).  Always
+// above the rank itself.
+__global__ void k_window_ends(uint32_t n, const uint32_t *__restrict__ rank,
+                              const uint32_t *__restrict__ level,
+                              const uint32_t *__restrict__ lstart, uint32_t nlev, uint32_t win,
+                              uint32_t *__restrict__ wend) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint64_t e = (uint64_t)level[v] + win + 1;
+    wend[rank[v]] = lstart[e < nlev ? e : nlev];
+  }
+}
+
+// First rank of every level, for the query's level window.
+static int level_starts(ch_s *ch) {
+  hipStream_t st = ch->stream;
+  const uint32_t nlev = ch->rounds + 1;  // covers every level
+  DBuf lvr;
+  HIP_TRY(lvr.ensure((size_t)std::max<uint32_t>(ch->n, 1) * 4));
+  HIP_TRY(ch->q_lstart.ensure(((size_t)nlev + 1) * 4));
+  if (ch->n)
+    k_level_by_rank<<<gridn(ch->n), 256, 0, st>>>(ch->n, ch->rank.as<uint32_t>(),
+                                                  ch->level.as<uint32_t>(), lvr.as<uint32_t>());
+  k_level_starts<<<gridn((uint64_t)nlev + 1), 256, 0, st>>>(ch->n, lvr.as<uint32_t>(), nlev,
+                                                            ch->q_lstart.as<uint32_t>());
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(st));
+  lvr.release();
+  ch->q_nlev = nlev;
+  ch->q_wend_win = 0;
+  return CH_OK;
+}
+
 // Query index of a CH whose arc lists are already sorted by rank.
 int build_index(ch_s *ch) {
   hipStream_t st = ch->stream;
@@ -200,6 +258,8 @@ int build_index(ch_s *ch) {
   HIP_TRY(hipStreamSynchronize(st));
   k1.release();
   v1.release();
+  const int rc = level_starts(ch);
+  if (rc != CH_OK) return rc;
   ch->has_index = true;
   return CH_OK;
 }
@@ -253,6 +313,7 @@ int postprocess(ch_s *ch, bool make_index, const uint32_t *gof, uint32_t kgraphs
     }
     if ((rc = sort_arcs(ch, true, k1, k2, v1, v2, tmp, make_index)) != CH_OK) break;
     if ((rc = sort_arcs(ch, false, k1, k2, v1, v2, tmp, make_index)) != CH_OK) break;
+    if (make_index && (rc = level_starts(ch)) != CH_OK) break;
     ch->has_index = make_index;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) rc = hip_error(e, "postprocess");
   } while (0);
@@ -470,16 +531,25 @@ __device__ unsigned long long meet(const QTab<IdxT, DistT, GL> &Fw, const QTab<I
 // ---------------------------------------------------------------------------
 // Bitmap-frontier query: both upward closures of one query at once.  Each
 // direction has an open-addressing table of CAP slots (vertex, distance) and
-// one frontier bit per slot.  A level takes every flagged slot of both
+// one frontier bit per slot.  A step takes the flagged slots of both
 // directions (clearing the bits), expands them, and flags each slot whose
-// distance dropped; the closures are complete when no bit is set.  Arc loads
-// of a level are issued kQUnroll deep per lane before any of them is used.
+// distance dropped; the closures are complete when no bit is set.  With a
+// level window of W levels a step expands, per direction, only the flagged
+// vertices whose CH level is at most W above the lowest flagged level (ranks
+// are ordered by level, so this is a rank bound found from the first rank
+// of each level); the others stay flagged.  All in-arcs of a vertex come
+// from lower levels, so vertices are rarely expanded before their distance
+// is final, at the price of more steps.  Results do not depend on W: every
+// tentative distance is a path length, and the search ends only when no
+// distance can drop.  Arc loads of a step are issued kQUnroll deep per lane
+// before any of them is used.
 // A query moves to the next tier when a table passes 7/8 of CAP or a
 // distance passes 32 bits.  NW waves share one query's tables, which live in
 // LDS (GM = false: CAP 2048 fits four blocks in a CU, CAP 8192 one) or in
 // global memory (GM = true: one table set per block, reached through L2).
 // ---------------------------------------------------------------------------
 constexpr int kQUnroll = 8;
+constexpr uint32_t kQWindow = 24;  // default level window of the query
 
 template <uint32_t CAP>
 struct QLds {
@@ -581,8 +651,46 @@ __device__ __forceinline__ uint32_t qscan(QLds<CAP> &S, uint32_t c, uint32_t *to
       before += i < wv ? x : 0u;
       all += x;
     }
-    qsync<NW, GM>();
+    // wsum is written again only after the step's later barriers
     *total = all;
+    return before + incl - c;
+  }
+}
+
+// qscan that also returns the block minima of m0 and m1 (through wmin,
+// which is free until the end of a query).
+template <int NW, bool GM, uint32_t CAP>
+__device__ __forceinline__ uint32_t qscan_min(QLds<CAP> &S, uint32_t c, uint32_t m0, uint32_t m1,
+                                              uint32_t *total, uint32_t *M0, uint32_t *M1) {
+  const uint32_t incl = gscan_incl<kWave>(c);
+  m0 = gmin<kWave>(m0);
+  m1 = gmin<kWave>(m1);
+  if constexpr (NW == 1) {
+    *total = __shfl(incl, kWave - 1, kWave);
+    *M0 = m0;
+    *M1 = m1;
+    return incl - c;
+  } else {
+    const int wv = threadIdx.x / kWave;
+    uint32_t *wm = reinterpret_cast<uint32_t *>(S.wmin);
+    if (lane_id() == kWave - 1) {
+      qst<GM>(&S.wsum[wv], incl);
+      qst<GM>(&wm[2 * wv], m0);
+      qst<GM>(&wm[2 * wv + 1], m1);
+    }
+    qsync<NW, GM>();
+    uint32_t before = 0, all = 0, a0 = SP_EMPTY32, a1 = SP_EMPTY32;
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+      const uint32_t x = qld<GM>(&S.wsum[i]);
+      before += i < wv ? x : 0u;
+      all += x;
+      a0 = min(a0, qld<GM>(&wm[2 * i]));
+      a1 = min(a1, qld<GM>(&wm[2 * i + 1]));
+    }
+    *total = all;
+    *M0 = a0;
+    *M1 = a1;
     return before + incl - c;
   }
 }
@@ -613,7 +721,8 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     const uint2 *__restrict__ uparc, const uint32_t *__restrict__ dnoff,
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
-    uint32_t *__restrict__ ovf_count, QLds<CAP> *__restrict__ gtab) {
+    uint32_t *__restrict__ ovf_count, const uint32_t *__restrict__ wend,
+    QLds<CAP> *__restrict__ gtab) {
   using L = QLds<CAP>;
   using E = typename L::Entry;
   constexpr bool kLds = !GM;
@@ -646,13 +755,35 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     }
     qsync<NW, GM>();
     for (;;) {
-      // take the flags of both directions: words tid, tid + NT, ...
-      uint32_t c = 0;
-      for (uint32_t wi = tid; wi < kW2; wi += NT)
-        c += __popc(qld<GM>(&S.bits[wi / L::kWords][wi % L::kWords]));
-      uint32_t F;
-      uint32_t p = qscan<NW, GM>(S, c, &F);
+      // flagged slots of both directions (words tid, tid + NT, ...): their
+      // count and, with a window, the lowest flagged rank of each direction
+      uint32_t c = 0, mk0 = SP_EMPTY32, mk1 = SP_EMPTY32;
+      for (uint32_t wi = tid; wi < kW2; wi += NT) {
+        const uint32_t d = wi / L::kWords, wd = wi % L::kWords;
+        uint32_t x = qld<GM>(&S.bits[d][wd]);
+        c += __popc(x);
+        if (wend) {
+          while (x) {
+            const uint32_t b = __builtin_ctz(x);
+            x &= x - 1;
+            const uint32_t r = qld<GM>(&S.key[d][wd * 32 + b]);
+            if (d) mk1 = min(mk1, r);
+            else mk0 = min(mk0, r);
+          }
+        }
+      }
+      uint32_t F, M0 = SP_EMPTY32, M1 = SP_EMPTY32;
+      uint32_t p = wend ? qscan_min<NW, GM>(S, c, mk0, mk1, &F, &M0, &M1) : qscan<NW, GM>(S, c, &F);
       if (F == 0) break;
+      // ranks >= T[d] stay flagged for a later step (the minima are the same
+      // in every lane, so these are scalar loads)
+      uint32_t T0 = SP_EMPTY32, T1 = SP_EMPTY32;
+      if (wend) {
+        M0 = __builtin_amdgcn_readfirstlane(M0);
+        M1 = __builtin_amdgcn_readfirstlane(M1);
+        if (M0 != SP_EMPTY32) T0 = wend[M0];
+        if (M1 != SP_EMPTY32) T1 = wend[M1];
+      }
       for (uint32_t wi = tid; wi < kW2; wi += NT) {
         const uint32_t d = wi / L::kWords, wd = wi % L::kWords;
         uint32_t x = qld<GM>(&S.bits[d][wd]);
@@ -667,8 +798,9 @@ __global__ void __launch_bounds__(64 * NW) k_query(
       if (F > 2 * L::kLimit) F = 2 * L::kLimit;  // only after an overflow (then discarded)
       qsync<NW, GM>();
       uint32_t fresh0 = 0, fresh1 = 0;
-      for (uint32_t cb = wv * kWave; cb < F; cb += NT) {
-        const uint32_t i = cb + l;
+      // entries dealt to the waves in turn, so a small step still uses all
+      for (uint32_t cb = 0; cb < F; cb += NT) {
+        const uint32_t i = cb + (uint32_t)l * NW + wv;
         uint32_t rs = 0, rl = 0, dx = 0, dr = 0;
         if (i < F) {
           const uint32_t e = qlde<GM>(&S.list[i]);
@@ -676,9 +808,13 @@ __global__ void __launch_bounds__(64 * NW) k_query(
           const uint32_t slot = e & (CAP - 1);
           const uint32_t vx = qld<GM>(&S.key[dr][slot]);
           dx = qld<GM>(&S.dist[dr][slot]);
-          const uint32_t *o = dr ? dnoff : upoff;
-          rs = o[vx];
-          rl = o[vx + 1] - rs;
+          if (vx >= (dr ? T1 : T0)) {
+            atomicOr(&S.bits[dr][slot >> 5], 1u << (slot & 31));
+          } else {
+            const uint32_t *o = dr ? dnoff : upoff;
+            rs = o[vx];
+            rl = o[vx + 1] - rs;
+          }
         }
         const uint32_t incl = gscan_incl<kWave>(rl);
         const uint32_t T = __shfl(incl, kWave - 1, kWave);
@@ -866,15 +1002,28 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   const uint2 *uparc = ch->q_uparc.as<uint2>(), *dnarc = ch->q_dnarc.as<uint2>();
   uint32_t *ovf1 = ch->q_ovf.as<uint32_t>(), *ovf2 = ch->q_ovf2.as<uint32_t>();
   const int first = ch->q_first_tier;
+  const uint32_t wf = (flags >> 12) & 0xFFu;  // 0: default window, 255: none
+  const uint32_t win = wf == 0 ? kQWindow : (wf == 255 ? 0u : wf);
+  if (win && win != ch->q_wend_win) {
+    HIP_TRY(ch->q_wend.ensure((size_t)std::max<uint32_t>(ch->n, 1) * 4));
+    if (ch->n)
+      k_window_ends<<<gridn(ch->n), 256, 0, st>>>(ch->n, rank, ch->level.as<uint32_t>(),
+                                                  ch->q_lstart.as<uint32_t>(), ch->q_nlev, win,
+                                                  ch->q_wend.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    ch->q_wend_win = win;
+  }
+  const uint32_t *wend = win ? ch->q_wend.as<uint32_t>() : nullptr;
   if (first <= 1) {
     const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 4);
     const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
 #define SP_QUERY_LAUNCH(NW)                                                                    \
   k_query<NW, 2048, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
       q, ch->n, nullptr, nullptr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,   \
-      ovf1, ctr, nullptr)
+      ovf1, ctr, wend, nullptr)
     if (nw == 1) SP_QUERY_LAUNCH(1);
     else if (nw == 2) SP_QUERY_LAUNCH(2);
+    else if (nw == 8) SP_QUERY_LAUNCH(8);
     else SP_QUERY_LAUNCH(4);
 #undef SP_QUERY_LAUNCH
     HIP_TRY(hipGetLastError());
@@ -882,7 +1031,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   if (first <= 2) {
     k_query<16, 8192, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
-        dnarc, dd, dv, ovf2, ctr + 2, nullptr);
+        dnarc, dd, dv, ovf2, ctr + 2, wend, nullptr);
     HIP_TRY(hipGetLastError());
   }
   uint32_t hc[4] = {0, 0, 0, 0};
@@ -900,7 +1049,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     // overflows into ctr[4]; the input count is tier 2's, on the device
     k_query<8, 16384, true><<<(unsigned)nb, 512, 0, st>>>(
         q, ch->n, list3, ctr + 2, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,
-        ovf1, ctr + 4, reinterpret_cast<T3 *>(ch->q_tab.p));
+        ovf1, ctr + 4, wend, reinterpret_cast<T3 *>(ch->q_tab.p));
     HIP_TRY(hipGetLastError());
     uint32_t h2[4] = {0, 0, 0, 0};  // ctr[1..4]
     HIP_TRY(hipMemcpyAsync(h2, ctr + 1, 16, hipMemcpyDeviceToHost, st));

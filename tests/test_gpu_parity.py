@@ -75,11 +75,18 @@ def test_grid64_bit_exact_and_queries(gpu):
     assert np.array_equal(d, od)
     # query cost: the sizes of the two upward search spaces
     cs = closure_sizes(o, s[:300], t[:300])
-    for nw in (1, 2, 4):
+    for nw in (1, 2, 4, 8):
         assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
         d2, vis = ch.query_stats(s[:300], t[:300], waves=nw)
         assert np.array_equal(d2, d[:300])
         assert np.array_equal(vis.astype(np.int64), cs), nw
+    # the level window orders the expansions; distances and the reached
+    # sets do not depend on it (255 = none)
+    for win in (1, 2, 7, 64, 255):
+        assert np.array_equal(ch.query(s, t, window=win), ref), win
+        d2, vis = ch.query_stats(s[:300], t[:300], waves=1, window=win)
+        assert np.array_equal(d2, d[:300]), win
+        assert np.array_equal(vis.astype(np.int64), cs), win
 
 
 def test_group_split_invariance(gpu):
@@ -205,10 +212,14 @@ def test_query_tiers(gpu):
         od, _ = o.query_batch(s, t)
         cs = closure_sizes(o, s, t)
         assert cs.max() > {3000: 1792, 10000: 7168, 60000: 14336}[k]
-        for nw in (1, 2, 4):
+        for nw in (1, 2, 4, 8):
             d, vis = ch.query_stats(s, t, waves=nw)
             assert np.array_equal(d, od), nw
             assert np.array_equal(vis.astype(np.int64), cs), nw
+        for win in (1, 255):
+            d, vis = ch.query_stats(s, t, window=win)
+            assert np.array_equal(d, od), win
+            assert np.array_equal(vis.astype(np.int64), cs), win
         for _ in range(2):
             d, vis = ch.query_stats(s[:40], t[:40])
             assert np.array_equal(d, od[:40])
@@ -222,8 +233,10 @@ def test_query_tiers(gpu):
     ch = gpu.build(off, dst, w, labels=synth.labels(n, 2))
     s, t = synth.queries(n, 300, seed=4)
     ref = reference_distances(off, dst, w, s, t)
-    for nw in (1, 2, 4):
+    for nw in (1, 2, 4, 8):
         assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
+    for win in (1, 5, 255):
+        assert np.array_equal(ch.query(s, t, window=win), ref), win
 
 
 def test_query_distances_past_32_bits(gpu):
@@ -237,8 +250,10 @@ def test_query_distances_past_32_bits(gpu):
     s, t = (a.ravel().astype(np.uint32) for a in np.meshgrid(np.arange(k), np.arange(k)))
     ref = reference_distances(off, dst, w, s, t)
     assert ref.max(initial=0, where=ref != np.uint64(2**64 - 1)) == 6 * 0x7FFFFFFF
-    for nw in (1, 2, 4):
+    for nw in (1, 2, 4, 8):
         assert np.array_equal(ch.query(s, t, waves=nw), ref), nw
+    for win in (1, 255):
+        assert np.array_equal(ch.query(s, t, window=win), ref), win
 
 
 def test_global_search_tier(gpu):
