@@ -450,6 +450,45 @@ struct Builder {
         S.as<uint8_t>(), newA.as<uint8_t>(), fstate(), &dc()->err);
   }
 
+  // Row lengths of the new overlay (new ids < n2, zero up to O.n), their
+  // offsets over O.n + 1 entries (foff[n2 .. O.n] all equal m2), then the
+  // merged rows, both directions.  fb0/fb1 and rb0/rb1: shortcut-row bounds.
+  int merge_err = CH_OK;
+  template <int G>
+  void merge_rows(OvBuf &O, OvBuf &N, int kb, const uint32_t *fb0, const uint32_t *fb1,
+                  const uint32_t *rb0, const uint32_t *rb1) {
+    merge_err = CH_OK;
+    const unsigned gr = ggrid<G>(O.n);
+    k_merge_rows<G, 0><<<gr, 256, 0, st>>>(
+        O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
+        O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
+        uw.as<uint32_t>(), umid.as<uint32_t>(), cnt2.as<uint32_t>(), nullptr, nullptr, nullptr);
+    k_merge_rows<G, 0><<<gr, 256, 0, st>>>(
+        O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
+        O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), rb0,
+        rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), cnt3.as<uint32_t>(), nullptr, nullptr,
+        nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+      e = scan3_u32(cnt2.as<uint32_t>(), N.foff.as<uint32_t>(), &dc()->c32[C_MF],
+                    cnt3.as<uint32_t>(), N.roff.as<uint32_t>(), &dc()->c32[C_MR], nullptr,
+                    nullptr, nullptr, O.n + 1, tmp, st);
+    if (e == hipSuccess) {
+      k_merge_rows<G, 1><<<gr, 256, 0, st>>>(
+          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
+          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
+          uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.foff.as<uint32_t>(),
+          N.farc.as<uint2>(), N.fmid.as<uint32_t>());
+      k_merge_rows<G, 1><<<gr, 256, 0, st>>>(
+          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
+          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(),
+          rb0, rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
+          N.rarc.as<uint2>(), N.rmid.as<uint32_t>());
+      e = hipGetLastError();
+    }
+    if (e != hipSuccess) merge_err = hip_error(e, "overlay merge");
+  }
+
   static int pick_group(double work) {
     if (work <= 4) return 4;
     if (work <= 8) return 8;
@@ -794,32 +833,13 @@ struct Builder {
       HIP_TRY(N.rmid.ensure(mcap2 * 4));
       // row lengths of the new overlay (new ids < n2, zero up to O.n), then
       // offsets over O.n + 1 entries: foff[n2 .. O.n] all equal m2
-      k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
-          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
-          uw.as<uint32_t>(), umid.as<uint32_t>(), cnt2.as<uint32_t>(), nullptr, nullptr, nullptr);
-      HIP_TRY(hipGetLastError());
-      k_merge_rows<0><<<grid(O.n), 256, 0, st>>>(
-          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), rb0,
-          rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), cnt3.as<uint32_t>(), nullptr, nullptr,
-          nullptr);
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(scan3_u32(cnt2.as<uint32_t>(), N.foff.as<uint32_t>(), &dc()->c32[C_MF],
-                        cnt3.as<uint32_t>(), N.roff.as<uint32_t>(), &dc()->c32[C_MR], nullptr,
-                        nullptr, nullptr, O.n + 1, tmp, st));
-      k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
-          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
-          uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.foff.as<uint32_t>(),
-          N.farc.as<uint2>(), N.fmid.as<uint32_t>());
-      HIP_TRY(hipGetLastError());
-      k_merge_rows<1><<<grid(O.n), 256, 0, st>>>(
-          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), rb0,
-          rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
-          N.rarc.as<uint2>(), N.rmid.as<uint32_t>());
-      HIP_TRY(hipGetLastError());
+      const int gm = pick_group(avgdeg);
+      dispatch(gm, [&] { merge_rows<4>(O, N, kb, fb0, fb1, rb0, rb1); },
+               [&] { merge_rows<8>(O, N, kb, fb0, fb1, rb0, rb1); },
+               [&] { merge_rows<16>(O, N, kb, fb0, fb1, rb0, rb1); },
+               [&] { merge_rows<32>(O, N, kb, fb0, fb1, rb0, rb1); },
+               [&] { merge_rows<64>(O, N, kb, fb0, fb1, rb0, rb1); });
+      TRY(merge_err);
       // carry state; V_W' = V_S + N_in(V_S); V_A' = N(V_F) (flags zeroed by
       // k_keep, so they are zero beyond the new vertex count)
       k_carry<<<grid(O.n), 256, 0, st>>>(O.n, F.as<uint8_t>(), newid.as<uint32_t>(),

@@ -905,71 +905,188 @@ __global__ void k_keep(uint32_t n, const uint8_t *__restrict__ F, uint32_t *__re
   }
 }
 
-// Row of vertex u in direction dir merged with its shortcut row.  Old row:
-// live arcs to kept vertices.  Shortcut row: records with first key half u
-// (sorted by the second half).  On a common neighbour the shortcut wins only
-// if strictly lighter.  Mode 0 counts, mode 1 writes.
+// Sequential merge of one row (the fallback for rows longer than a group's
+// LDS share): old arcs (dead ones skipped) and the shortcut row, both sorted
+// by neighbour; on a common neighbour the shortcut replaces the arc only if
+// lighter.  Returns the merged length; MODE 1 also writes the merged row.
 template <int MODE>
-__global__ void k_merge_rows(uint32_t n, int kb, const uint8_t *__restrict__ F,
-                             const uint32_t *__restrict__ newid, const uint32_t *__restrict__ off,
-                             const uint2 *__restrict__ arc, const uint32_t *__restrict__ mid,
-                             const uint64_t *__restrict__ ekey, const uint32_t *__restrict__ eidx,
-                             const uint32_t *__restrict__ rfirst, const uint32_t *__restrict__ rstop,
-                             const uint32_t *__restrict__ uw,
-                             const uint32_t *__restrict__ umid, uint32_t *__restrict__ cnt,
-                             const uint32_t *__restrict__ noff, uint2 *__restrict__ narc,
-                             uint32_t *__restrict__ nmid) {
-  const uint64_t lowmask = (1ull << kb) - 1ull;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-    if (F[u]) continue;
-    // shortcut row: keys in [u << kb, (u + 1) << kb), bounds from k_row_bounds
-    uint32_t b = rfirst[u];
-    const uint32_t b1 = rstop[u];
-    uint32_t a = off[u];
-    const uint32_t a1 = off[u + 1];
-    uint32_t c = 0;
-    uint32_t outp = MODE ? noff[newid[u]] : 0;
-    for (;;) {
-      // dead old arcs: pruned, or to a contracted vertex (marked by k_contract)
-      while (a < a1 && arc[a].y == SP_INF32) a++;
-      const bool ha = a < a1, hb = b < b1;
-      if (!ha && !hb) break;
-      const uint32_t va = ha ? arc[a].x : 0xFFFFFFFFu;
-      const uint32_t vb = hb ? (uint32_t)(ekey[b] & lowmask) : 0xFFFFFFFFu;
-      uint32_t v, ww, mm;
-      if (ha && (!hb || va < vb)) {
-        v = va;
-        ww = arc[a].y;
-        mm = mid[a];
-        a++;
-      } else if (!ha || vb < va) {
-        const uint32_t r = eidx ? eidx[b] : b;
-        v = vb;
+__device__ uint32_t merge_row_serial(uint32_t a, uint32_t a1, uint32_t b, uint32_t b1,
+                                     uint64_t lowmask, const uint32_t *__restrict__ newid,
+                                     const uint2 *__restrict__ arc, const uint32_t *__restrict__ mid,
+                                     const uint64_t *__restrict__ ekey,
+                                     const uint32_t *__restrict__ eidx,
+                                     const uint32_t *__restrict__ uw,
+                                     const uint32_t *__restrict__ umid, uint32_t outp,
+                                     uint2 *__restrict__ narc, uint32_t *__restrict__ nmid) {
+  uint32_t c = 0;
+  for (;;) {
+    while (a < a1 && arc[a].y == SP_INF32) a++;
+    const bool ha = a < a1, hb = b < b1;
+    if (!ha && !hb) break;
+    const uint32_t va = ha ? arc[a].x : 0xFFFFFFFFu;
+    const uint32_t vb = hb ? (uint32_t)(ekey[b] & lowmask) : 0xFFFFFFFFu;
+    uint32_t v, ww, mm;
+    if (ha && (!hb || va < vb)) {
+      v = va;
+      ww = arc[a].y;
+      mm = mid[a];
+      a++;
+    } else if (!ha || vb < va) {
+      const uint32_t r = eidx ? eidx[b] : b;
+      v = vb;
+      ww = uw[r];
+      mm = umid[r];
+      b++;
+    } else {
+      const uint32_t r = eidx ? eidx[b] : b;
+      if (uw[r] < arc[a].y) {
         ww = uw[r];
         mm = umid[r];
-        b++;
-      } else {  // same neighbour: the shortcut replaces the arc only if lighter
-        const uint32_t r = eidx ? eidx[b] : b;
-        if (uw[r] < arc[a].y) {
-          ww = uw[r];
-          mm = umid[r];
-        } else {
-          ww = arc[a].y;
-          mm = mid[a];
-        }
-        v = va;
-        a++;
-        b++;
+      } else {
+        ww = arc[a].y;
+        mm = mid[a];
       }
-      if (MODE) {
-        narc[outp] = make_uint2(newid[v], ww);
-        nmid[outp] = mm;
-        outp++;
-      }
-      c++;
+      v = va;
+      a++;
+      b++;
     }
-    if (!MODE) cnt[newid[u]] = c;
+    if (MODE) {
+      narc[outp] = make_uint2(newid[v], ww);
+      nmid[outp] = mm;
+      outp++;
+    }
+    c++;
+  }
+  return c;
+}
+
+// New overlay rows: per kept vertex u, its old row (arcs off[u] ..
+// off[u+1], sorted by neighbour; dead ones -- pruned, or to a contracted
+// vertex, marked by k_contract -- dropped) merged with its shortcut row
+// (sorted keys (u << kb | v), bounds rfirst/rstop; eidx maps a key to its
+// weight and middle vertex, or null for the identity); on a common neighbour
+// the shortcut replaces the arc only if lighter (a tie keeps the arc).
+// MODE 0 counts each merged row into cnt[newid[u]]; MODE 1 writes it at
+// noff[newid[u]] with new neighbour ids.
+//
+// G lanes per row, each element placed independently: a live old arc to v
+// lands after the live old arcs before it and the shortcuts to neighbours
+// below v, less the shortcuts among those that share a neighbour with a live
+// old arc; a shortcut to v without a live old arc to v lands after the live
+// old arcs to neighbours below v and the shortcuts before it, less those
+// that share a neighbour.  The live-arc prefix of the old row is kept in
+// LDS; rows longer than the group's share take the sequential merge.
+template <int G, int MODE>
+__global__ void __launch_bounds__(256) k_merge_rows(
+    uint32_t n, int kb, const uint8_t *__restrict__ F, const uint32_t *__restrict__ newid,
+    const uint32_t *__restrict__ off, const uint2 *__restrict__ arc,
+    const uint32_t *__restrict__ mid, const uint64_t *__restrict__ ekey,
+    const uint32_t *__restrict__ eidx, const uint32_t *__restrict__ rfirst,
+    const uint32_t *__restrict__ rstop, const uint32_t *__restrict__ uw,
+    const uint32_t *__restrict__ umid, uint32_t *__restrict__ cnt,
+    const uint32_t *__restrict__ noff, uint2 *__restrict__ narc, uint32_t *__restrict__ nmid) {
+  constexpr uint32_t kGroups = 256 / G;
+  constexpr uint32_t kCap = 4096 / kGroups;  // live-arc prefix entries per group
+  __shared__ uint16_t s_live[4096];
+  uint16_t *lr = s_live + (threadIdx.x / G) * kCap;
+  const uint64_t lowmask = (1ull << kb) - 1ull;
+  const uint32_t ngroups = gridDim.x * kGroups;
+  const uint32_t g0 = blockIdx.x * kGroups + threadIdx.x / G;
+  const uint32_t gl = (uint32_t)glane<G>();
+  const uint64_t below = gl == 0 ? 0ull : ((1ull << gl) - 1ull);
+  for (uint32_t u = g0; u < n; u += ngroups) {
+    if (F[u]) continue;
+    const uint32_t a0 = off[u], na = off[u + 1] - a0;
+    const uint32_t b0 = rfirst[u], nb = rstop[u] - b0;
+    const uint32_t outp = MODE ? noff[newid[u]] : 0;
+    if (na > kCap) {
+      if (gl == 0) {
+        const uint32_t c = merge_row_serial<MODE>(a0, a0 + na, b0, b0 + nb, lowmask, newid, arc,
+                                                  mid, ekey, eidx, uw, umid, outp, narc, nmid);
+        if (!MODE) cnt[newid[u]] = c;
+      }
+      continue;
+    }
+    // old arcs
+    uint32_t live_n = 0, dup_n = 0;
+    for (uint32_t x0 = 0; x0 < na; x0 += G) {
+      const uint32_t i = x0 + gl;
+      uint2 e = make_uint2(0u, SP_INF32);
+      if (i < na) e = arc[a0 + i];
+      const bool live = i < na && e.y != SP_INF32;
+      uint32_t lb = 0;
+      bool dup = false;
+      if (live && nb) {  // first shortcut with neighbour >= e.x
+        uint32_t lo = 0, hi = nb;
+        while (lo < hi) {
+          const uint32_t md = (lo + hi) >> 1;
+          if ((uint32_t)(ekey[b0 + md] & lowmask) < e.x) lo = md + 1;
+          else hi = md;
+        }
+        lb = lo;
+        dup = lb < nb && (uint32_t)(ekey[b0 + lb] & lowmask) == e.x;
+      }
+      const uint64_t lm = gballot<G>(live), dm = gballot<G>(dup);
+      const uint32_t lrank = live_n + (uint32_t)__popcll(lm & below);
+      if (MODE && i < na) lr[i] = (uint16_t)lrank;
+      if (MODE && live) {
+        const uint32_t pos = lrank + lb - (dup_n + (uint32_t)__popcll(dm & below));
+        uint32_t ww = e.y, mm;
+        if (dup) {
+          const uint32_t r = eidx ? eidx[b0 + lb] : b0 + lb;
+          const uint32_t sw = uw[r];
+          if (sw < e.y) {
+            ww = sw;
+            mm = umid[r];
+          } else {
+            mm = mid[a0 + i];
+          }
+        } else {
+          mm = mid[a0 + i];
+        }
+        narc[outp + pos] = make_uint2(newid[e.x], ww);
+        nmid[outp + pos] = mm;
+      }
+      live_n += (uint32_t)__popcll(lm);
+      dup_n += (uint32_t)__popcll(dm);
+    }
+    wave_sync();  // the group's prefix entries are visible to all its lanes
+    // shortcuts without a live old arc to the same neighbour
+    if (MODE) {
+      uint32_t in_n = 0;
+      for (uint32_t y0 = 0; y0 < nb; y0 += G) {
+        const uint32_t j = y0 + gl;
+        const bool valid = j < nb;
+        const uint32_t v = valid ? (uint32_t)(ekey[b0 + j] & lowmask) : 0u;
+        uint32_t la = 0;
+        bool in_a = false;
+        if (valid) {  // first old arc with neighbour >= v
+          uint32_t lo = 0, hi = na;
+          while (lo < hi) {
+            const uint32_t md = (lo + hi) >> 1;
+            if (arc[a0 + md].x < v) lo = md + 1;
+            else hi = md;
+          }
+          la = lo;
+          if (la < na) {
+            const uint2 e = arc[a0 + la];
+            in_a = e.x == v && e.y != SP_INF32;
+          }
+        }
+        const uint64_t im = gballot<G>(in_a);
+        if (valid && !in_a) {
+          const uint32_t live_below = la < na ? (uint32_t)lr[la] : live_n;
+          const uint32_t pos = live_below + j - (in_n + (uint32_t)__popcll(im & below));
+          const uint32_t r = eidx ? eidx[b0 + j] : b0 + j;
+          narc[outp + pos] = make_uint2(newid[v], uw[r]);
+          nmid[outp + pos] = umid[r];
+        }
+        in_n += (uint32_t)__popcll(im);
+      }
+    } else if (gl == 0) {
+      cnt[newid[u]] = live_n + nb - dup_n;
+    }
+    wave_sync();  // before the next row overwrites the prefix entries
   }
 }
 
