@@ -139,7 +139,8 @@ def plain_vs_learned(binding, args, t_off, t_dst, t_w, qs, qt, knobs, dev):
 
 # Kernel sources whose change invalidates the committed HBM counter totals.
 TRAFFIC_SOURCES = ("paper_2412_18008_amd/csrc/search.hpp", "paper_2412_18008_amd/csrc/common.hpp",
-                   "paper_2412_18008_amd/csrc/round_kernels.hpp")
+                   "paper_2412_18008_amd/csrc/round_kernels.hpp",
+                   "paper_2412_18008_amd/csrc/dense_tail.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_local_search_road1m.md")
 
 
@@ -163,11 +164,11 @@ def committed_traffic(kernel):
     with open(TRAFFIC_FILE) as f:
         for line in f:
             if line.startswith("traffic:"):
-                k, _, v = line[len("traffic:"):].strip().partition("=")
+                k, _, v = line[len("traffic:"):].strip().rpartition("=")
                 rec[k.strip()] = v.strip()
-    if rec.get("kernel") != kernel or rec.get("source_hash") != kernel_source_hash():
+    if rec.get("source_hash") != kernel_source_hash() or kernel not in rec:
         return None
-    return float(rec["bytes_per_launch"])
+    return float(rec[kernel])
 
 
 def copy_calibration(dev, nbytes):
