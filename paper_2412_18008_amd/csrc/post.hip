@@ -530,44 +530,54 @@ __device__ unsigned long long meet(const QTab<IdxT, DistT, GL> &Fw, const QTab<I
 
 // ---------------------------------------------------------------------------
 // Bitmap-frontier query: both upward closures of one query at once.  Each
-// direction has an open-addressing table of CAP slots (vertex, distance) and
-// one frontier bit per slot.  A step takes the flagged slots of both
-// directions (clearing the bits), expands them, and flags each slot whose
-// distance dropped; the closures are complete when no bit is set.  With a
-// level window of W levels a step expands, per direction, only the flagged
-// vertices whose CH level is at most W above the lowest flagged level (ranks
-// are ordered by level, so this is a rank bound found from the first rank
-// of each level); the others stay flagged.  All in-arcs of a vertex come
-// from lower levels, so vertices are rarely expanded before their distance
-// is final, at the price of more steps.  Results do not depend on W: every
-// tentative distance is a path length, and the search ends only when no
-// distance can drop.  Arc loads of a step are issued kQUnroll deep per lane
-// before any of them is used.
+// direction has TOP + CAP distance slots and one frontier bit per slot: the
+// TOP highest ranks (the top of the hierarchy, which most upward searches
+// reach) have a slot each, indexed by rank - (n - TOP); every other vertex
+// goes to an open-addressing table of CAP (vertex, distance) slots.  A step
+// takes up to LIST flagged slots of both directions (clearing their bits),
+// expands them, and flags each slot whose distance dropped; the closures are
+// complete when no bit is set.  With a level window of W levels a step
+// expands, per direction, only the flagged vertices whose CH level is at most
+// W above the lowest flagged level (ranks are ordered by level, so this is a
+// rank bound: the window end of the lowest flagged rank); the others stay
+// flagged.  All in-arcs of a vertex come from lower levels, so vertices are
+// rarely expanded before their distance is final, at the price of more
+// steps.  Results do not depend on W or LIST: every tentative distance is a
+// path length, and the search ends only when no distance can drop.  Arc
+// loads of a step are issued kQUnroll deep per lane before any is used.
 // A query moves to the next tier when a table passes 7/8 of CAP or a
 // distance passes 32 bits.  NW waves share one query's tables, which live in
-// LDS (GM = false: CAP 2048 fits four blocks in a CU, CAP 8192 one) or in
-// global memory (GM = true: one table set per block, reached through L2).
+// LDS (GM = false) or in global memory (GM = true: one table set per block,
+// reached through L2).
 // ---------------------------------------------------------------------------
 constexpr int kQUnroll = 8;
 constexpr uint32_t kQWindow = 24;  // default level window of the query
 
-template <uint32_t CAP>
+template <uint32_t CAP, uint32_t TOP = 0, uint32_t LIST = 2 * (CAP * 7 / 8)>
 struct QLds {
-  using Entry = typename std::conditional<(2 * CAP <= 65536), uint16_t, uint32_t>::type;
+  static constexpr uint32_t kSlots = TOP + CAP;
+  using Entry = typename std::conditional<(2 * kSlots <= 65536), uint16_t, uint32_t>::type;
   static constexpr uint32_t kLimit = CAP * 7 / 8;
-  static constexpr uint32_t kWords = CAP / 32;
+  static constexpr uint32_t kWords = kSlots / 32;
   static constexpr uint32_t kShift = 32 - __builtin_ctz(CAP);
-  uint32_t key[2][CAP];
-  uint32_t dist[2][CAP];
+  static constexpr uint32_t kTop = TOP;
+  static constexpr uint32_t kList = LIST;
+  uint32_t key[2][CAP];      // hashed part
+  uint32_t dist[2][kSlots];  // dense top part, then hashed part
   uint32_t bits[2][kWords];
-  Entry list[2 * kLimit];  // flagged slots of one level: dir * CAP + slot
-  uint32_t used[2];
+  Entry list[LIST];          // flagged slots of one step: dir * kSlots + slot
+  uint32_t used[2];          // hashed entries
+  uint32_t usedt[2];         // dense entries
   uint32_t ovf;
   uint32_t wsum[16];
+  uint32_t wsum2[16];  // a second scan within one step
   unsigned long long wmin[16];
 };
-static_assert(sizeof(QLds<2048>) * 4 <= 163840, "four 2048-slot query blocks per CU");
-static_assert(sizeof(QLds<8192>) <= 163840, "one 8192-slot query block per CU");
+using QTier1 = QLds<2048>;
+using QTier2 = QLds<4096, 8192, 4096>;
+using QTier3 = QLds<16384>;
+static_assert(sizeof(QTier1) * 4 <= 163840, "four tier-1 query blocks per CU");
+static_assert(sizeof(QTier2) <= 163840, "one tier-2 query block per CU");
 
 // Table accessors: plain LDS accesses, or device-coherent ones for tables in
 // global memory (written by other waves' atomics, which bypass the CU's
@@ -602,9 +612,10 @@ __device__ __forceinline__ void qsync() {
 
 // Slot of v in direction d (inserted if absent); *fresh = 1 when inserted
 // here; -1 when the table is full.
-template <bool GM, uint32_t CAP>
-__device__ __forceinline__ int qins(QLds<CAP> &S, uint32_t d, uint32_t v, uint32_t *fresh) {
-  uint32_t h = (v * 0x9E3779B1u) >> QLds<CAP>::kShift;
+template <bool GM, typename L>
+__device__ __forceinline__ int qins(L &S, uint32_t d, uint32_t v, uint32_t *fresh) {
+  constexpr uint32_t CAP = sizeof(S.key[0]) / 4;
+  uint32_t h = (v * 0x9E3779B1u) >> L::kShift;
   for (uint32_t probes = 0; probes < CAP; probes++) {
     const uint32_t k = qld<GM>(&S.key[d][h]);
     if (k == v) return (int)h;
@@ -621,9 +632,10 @@ __device__ __forceinline__ int qins(QLds<CAP> &S, uint32_t d, uint32_t v, uint32
   return -1;
 }
 
-template <bool GM, uint32_t CAP>
-__device__ __forceinline__ int qfind(const QLds<CAP> &S, uint32_t d, uint32_t v) {
-  uint32_t h = (v * 0x9E3779B1u) >> QLds<CAP>::kShift;
+template <bool GM, typename L>
+__device__ __forceinline__ int qfind(const L &S, uint32_t d, uint32_t v) {
+  constexpr uint32_t CAP = sizeof(S.key[0]) / 4;
+  uint32_t h = (v * 0x9E3779B1u) >> L::kShift;
   for (uint32_t probes = 0; probes < CAP; probes++) {
     const uint32_t k = qld<GM>(&S.key[d][h]);
     if (k == v) return (int)h;
@@ -634,20 +646,20 @@ __device__ __forceinline__ int qfind(const QLds<CAP> &S, uint32_t d, uint32_t v)
 }
 
 // Block-wide exclusive prefix of c over NW waves; *total = the block sum.
-template <int NW, bool GM, uint32_t CAP>
-__device__ __forceinline__ uint32_t qscan(QLds<CAP> &S, uint32_t c, uint32_t *total) {
+template <int NW, bool GM, typename L>
+__device__ __forceinline__ uint32_t qscan(L &S, uint32_t c, uint32_t *total, uint32_t *ws) {
   const uint32_t incl = gscan_incl<kWave>(c);
   if constexpr (NW == 1) {
     *total = __shfl(incl, kWave - 1, kWave);
     return incl - c;
   } else {
     const int wv = threadIdx.x / kWave;
-    if (lane_id() == kWave - 1) qst<GM>(&S.wsum[wv], incl);
+    if (lane_id() == kWave - 1) qst<GM>(&ws[wv], incl);
     qsync<NW, GM>();
     uint32_t before = 0, all = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
-      const uint32_t x = qld<GM>(&S.wsum[i]);
+      const uint32_t x = qld<GM>(&ws[i]);
       before += i < wv ? x : 0u;
       all += x;
     }
@@ -659,8 +671,8 @@ __device__ __forceinline__ uint32_t qscan(QLds<CAP> &S, uint32_t c, uint32_t *to
 
 // qscan that also returns the block minima of m0 and m1 (through wmin,
 // which is free until the end of a query).
-template <int NW, bool GM, uint32_t CAP>
-__device__ __forceinline__ uint32_t qscan_min(QLds<CAP> &S, uint32_t c, uint32_t m0, uint32_t m1,
+template <int NW, bool GM, typename L>
+__device__ __forceinline__ uint32_t qscan_min(L &S, uint32_t c, uint32_t m0, uint32_t m1,
                                               uint32_t *total, uint32_t *M0, uint32_t *M1) {
   const uint32_t incl = gscan_incl<kWave>(c);
   m0 = gmin<kWave>(m0);
@@ -695,24 +707,30 @@ __device__ __forceinline__ uint32_t qscan_min(QLds<CAP> &S, uint32_t c, uint32_t
   }
 }
 
-template <bool GM, uint32_t CAP>
-__device__ __forceinline__ void qclear(QLds<CAP> &S, uint32_t tid, uint32_t nt) {
+template <bool GM, typename L>
+__device__ __forceinline__ void qclear(L &S, uint32_t tid, uint32_t nt) {
+  constexpr uint32_t CAP = sizeof(S.key[0]) / 4;
   for (uint32_t i = tid; i < CAP; i += nt) {
     qst<GM>(&S.key[0][i], SP_EMPTY32);
     qst<GM>(&S.key[1][i], SP_EMPTY32);
+  }
+  for (uint32_t i = tid; i < L::kSlots; i += nt) {
     qst<GM>(&S.dist[0][i], SP_INF32);
     qst<GM>(&S.dist[1][i], SP_INF32);
   }
-  for (uint32_t i = tid; i < 2 * QLds<CAP>::kWords; i += nt)
-    qst<GM>(&S.bits[i / QLds<CAP>::kWords][i % QLds<CAP>::kWords], 0u);
-  if (tid < 2) qst<GM>(&S.used[tid], 0u);
+  for (uint32_t i = tid; i < 2 * L::kWords; i += nt)
+    qst<GM>(&S.bits[i / L::kWords][i % L::kWords], 0u);
+  if (tid < 2) {
+    qst<GM>(&S.used[tid], 0u);
+    qst<GM>(&S.usedt[tid], 0u);
+  }
   if (tid == 0) qst<GM>(&S.ovf, 0u);
 }
 
 // Queries: list ? list[i] for i < *nlist : i for i < q.  Queries that do
-// not fit go to ovf_list (count in *ovf_count).  GM: gtab holds one
-// QLds<CAP> per block.
-template <int NW, uint32_t CAP, bool GM>
+// not fit go to ovf_list (count in *ovf_count).  GM: gtab holds one L per
+// block.
+template <int NW, typename L, bool GM>
 __global__ void __launch_bounds__(64 * NW) k_query(
     uint64_t q, uint32_t n, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ nlist, uint32_t *__restrict__ bad,
@@ -722,9 +740,10 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
     uint32_t *__restrict__ ovf_count, const uint32_t *__restrict__ wend,
-    QLds<CAP> *__restrict__ gtab) {
-  using L = QLds<CAP>;
+    L *__restrict__ gtab) {
   using E = typename L::Entry;
+  constexpr uint32_t CAP = sizeof(((L *)nullptr)->key[0]) / 4;
+  constexpr uint32_t TOP = L::kTop, NS = L::kSlots;
   constexpr bool kLds = !GM;
   __shared__ typename std::conditional<kLds, L, char>::type sh;
   L &S = *(GM ? gtab + blockIdx.x : reinterpret_cast<L *>(&sh));
@@ -734,6 +753,18 @@ __global__ void __launch_bounds__(64 * NW) k_query(
   const int l = lane_id();
   const uint32_t wv = tid / kWave;
   const uint64_t nq = list ? (uint64_t)*nlist : q;
+  // ranks >= tbase have a dense slot (rank - tbase)
+  const uint32_t tbase = TOP ? (n > TOP ? n - TOP : 0u) : 0xFFFFFFFFu;
+  // slot of v in direction d, inserted into the hashed part if absent
+  // (*fresh = 1 then); -1 when the hashed part is full
+  auto slot_of = [&](uint32_t d, uint32_t v, uint32_t *fresh) -> int {
+    if (TOP && v >= tbase) return (int)(v - tbase);
+    const int h = qins<GM>(S, d, v, fresh);
+    return h < 0 ? -1 : (int)TOP + h;
+  };
+  auto rank_of = [&](uint32_t d, uint32_t slot) -> uint32_t {
+    return (TOP && slot < TOP) ? tbase + slot : qld<GM>(&S.key[d][slot - TOP]);
+  };
   qclear<GM>(S, tid, NT);
   qsync<NW, GM>();
   for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
@@ -748,10 +779,11 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     if (tid < 2) {
       const uint32_t v = rank[tid ? qt[k] : qs[k]];
       uint32_t fresh = 0;
-      const int a = qins<GM>(S, tid, v, &fresh);  // an empty table has room
+      const int a = slot_of(tid, v, &fresh);  // an empty table has room
       qst<GM>(&S.dist[tid][a], 0u);
       qst<GM>(&S.bits[tid][a >> 5], 1u << (a & 31));
-      qst<GM>(&S.used[tid], 1u);
+      if (TOP && (uint32_t)a < TOP) qst<GM>(&S.usedt[tid], 1u);
+      else qst<GM>(&S.used[tid], 1u);
     }
     qsync<NW, GM>();
     for (;;) {
@@ -766,14 +798,15 @@ __global__ void __launch_bounds__(64 * NW) k_query(
           while (x) {
             const uint32_t b = __builtin_ctz(x);
             x &= x - 1;
-            const uint32_t r = qld<GM>(&S.key[d][wd * 32 + b]);
+            const uint32_t r = rank_of(d, wd * 32 + b);
             if (d) mk1 = min(mk1, r);
             else mk0 = min(mk0, r);
           }
         }
       }
       uint32_t F, M0 = SP_EMPTY32, M1 = SP_EMPTY32;
-      uint32_t p = wend ? qscan_min<NW, GM>(S, c, mk0, mk1, &F, &M0, &M1) : qscan<NW, GM>(S, c, &F);
+      uint32_t p = wend ? qscan_min<NW, GM>(S, c, mk0, mk1, &F, &M0, &M1)
+                        : qscan<NW, GM>(S, c, &F, S.wsum);
       if (F == 0) break;
       // ranks >= T[d] stay flagged for a later step (the minima are the same
       // in every lane, so these are scalar loads)
@@ -784,29 +817,57 @@ __global__ void __launch_bounds__(64 * NW) k_query(
         if (M0 != SP_EMPTY32) T0 = wend[M0];
         if (M1 != SP_EMPTY32) T1 = wend[M1];
       }
+      // the flagged slots go to the list (in word order) and leave the
+      // bitmap; when there are more than LIST, only slots inside the window
+      // are taken (counted and placed by a second scan), so a step always
+      // expands the lowest flagged rank of each direction, and the first
+      // LIST of them are taken, the rest stay flagged
+      const bool part = F > L::kList;
+      if (part) {
+        uint32_t c2 = 0;
+        for (uint32_t wi = tid; wi < kW2; wi += NT) {
+          const uint32_t d = wi / L::kWords, wd = wi % L::kWords;
+          uint32_t x = qld<GM>(&S.bits[d][wd]);
+          const uint32_t Td = d ? T1 : T0;
+          while (x) {
+            const uint32_t b = __builtin_ctz(x);
+            x &= x - 1;
+            c2 += rank_of(d, wd * 32 + b) < Td;
+          }
+        }
+        p = qscan<NW, GM>(S, c2, &F, S.wsum2);
+      }
       for (uint32_t wi = tid; wi < kW2; wi += NT) {
         const uint32_t d = wi / L::kWords, wd = wi % L::kWords;
         uint32_t x = qld<GM>(&S.bits[d][wd]);
-        qst<GM>(&S.bits[d][wd], 0u);
+        if (!x) continue;
+        const uint32_t Td = d ? T1 : T0;
+        uint32_t keep = 0;
         while (x) {
           const uint32_t b = __builtin_ctz(x);
           x &= x - 1;
-          if (p < 2 * L::kLimit) qste<GM>(&S.list[p], (E)(d * CAP + wd * 32 + b));
+          if (part && rank_of(d, wd * 32 + b) >= Td) {
+            keep |= 1u << b;
+            continue;
+          }
+          if (p < L::kList) qste<GM>(&S.list[p], (E)(d * NS + wd * 32 + b));
+          else keep |= 1u << b;
           p++;
         }
+        qst<GM>(&S.bits[d][wd], keep);
       }
-      if (F > 2 * L::kLimit) F = 2 * L::kLimit;  // only after an overflow (then discarded)
+      if (F > L::kList) F = L::kList;
       qsync<NW, GM>();
-      uint32_t fresh0 = 0, fresh1 = 0;
+      uint32_t fresh0 = 0, fresh1 = 0, ft0 = 0, ft1 = 0;
       // entries dealt to the waves in turn, so a small step still uses all
       for (uint32_t cb = 0; cb < F; cb += NT) {
         const uint32_t i = cb + (uint32_t)l * NW + wv;
         uint32_t rs = 0, rl = 0, dx = 0, dr = 0;
         if (i < F) {
           const uint32_t e = qlde<GM>(&S.list[i]);
-          dr = e / CAP;
-          const uint32_t slot = e & (CAP - 1);
-          const uint32_t vx = qld<GM>(&S.key[dr][slot]);
+          dr = e / NS;
+          const uint32_t slot = e - dr * NS;
+          const uint32_t vx = rank_of(dr, slot);
           dx = qld<GM>(&S.dist[dr][slot]);
           if (vx >= (dr ? T1 : T0)) {
             atomicOr(&S.bits[dr][slot >> 5], 1u << (slot & 31));
@@ -845,7 +906,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
               continue;
             }
             uint32_t fr = 0;
-            const int y = qins<GM>(S, sdr[u], a[u].x, &fr);
+            const int y = slot_of(sdr[u], a[u].x, &fr);
             if (y < 0) {
               atomicOr(&S.ovf, 1u);
               continue;
@@ -853,16 +914,30 @@ __global__ void __launch_bounds__(64 * NW) k_query(
             if (sdr[u]) fresh1 += fr;
             else fresh0 += fr;
             const uint32_t old = atomicMin(&S.dist[sdr[u]][y], (uint32_t)nd);
-            if ((uint32_t)nd < old) atomicOr(&S.bits[sdr[u]][y >> 5], 1u << (y & 31));
+            if ((uint32_t)nd < old) {
+              atomicOr(&S.bits[sdr[u]][y >> 5], 1u << (y & 31));
+              if (TOP && (uint32_t)y < TOP && old == SP_INF32) {  // first reach of a dense slot
+                if (sdr[u]) ft1++;
+                else ft0++;
+              }
+            }
           }
         }
       }
       fresh0 = gsum<kWave>(fresh0);
       fresh1 = gsum<kWave>(fresh1);
+      if (TOP) {
+        ft0 = gsum<kWave>(ft0);
+        ft1 = gsum<kWave>(ft1);
+      }
       if (l == 0) {
         const uint32_t u0 = atomicAdd(&S.used[0], fresh0) + fresh0;
         const uint32_t u1 = atomicAdd(&S.used[1], fresh1) + fresh1;
         if (u0 > L::kLimit || u1 > L::kLimit) atomicOr(&S.ovf, 1u);
+        if (TOP) {
+          atomicAdd(&S.usedt[0], ft0);
+          atomicAdd(&S.usedt[1], ft1);
+        }
       }
       qsync<NW, GM>();
       if (qld<GM>(&S.ovf)) break;
@@ -871,13 +946,20 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     const bool ok = qld<GM>(&S.ovf) == 0;
     if (ok) {
       unsigned long long best = SP_INF64;
+      for (uint32_t i = tid; i < TOP; i += NT) {  // dense part: the same slot
+        const uint32_t a = qld<GM>(&S.dist[0][i]), b = qld<GM>(&S.dist[1][i]);
+        if (a != SP_INF32 && b != SP_INF32) {
+          const unsigned long long c2 = (unsigned long long)a + b;
+          best = c2 < best ? c2 : best;
+        }
+      }
       for (uint32_t i = tid; i < CAP; i += NT) {
         const uint32_t v = qld<GM>(&S.key[0][i]);
         if (v == SP_EMPTY32) continue;
         const int b = qfind<GM>(S, 1, v);
         if (b >= 0) {
-          const unsigned long long c2 = (unsigned long long)qld<GM>(&S.dist[0][i]) +
-                                        (unsigned long long)qld<GM>(&S.dist[1][b]);
+          const unsigned long long c2 = (unsigned long long)qld<GM>(&S.dist[0][TOP + i]) +
+                                        (unsigned long long)qld<GM>(&S.dist[1][TOP + b]);
           best = c2 < best ? c2 : best;
         }
       }
@@ -897,7 +979,9 @@ __global__ void __launch_bounds__(64 * NW) k_query(
       }
       if (tid == 0) {
         dist[k] = best;
-        if (visited) visited[k] = qld<GM>(&S.used[0]) + qld<GM>(&S.used[1]);
+        if (visited)
+          visited[k] = qld<GM>(&S.used[0]) + qld<GM>(&S.used[1]) + qld<GM>(&S.usedt[0]) +
+                       qld<GM>(&S.usedt[1]);
       }
     } else if (tid == 0) {
       const uint32_t p2 = atomicAdd(ovf_count, 1u);
@@ -985,11 +1069,13 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     dv = ch->q_v.as<uint32_t>();
   }
   HIP_TRY(ch->q_ovf.ensure(q * 4));
-  // Tiers: 1 = 2048-slot LDS tables (four blocks per CU), 2 = 8192-slot LDS
-  // tables (one block of 16 waves per CU), 3 = 16384-slot tables in global
-  // memory, 4 = tables of at least 2n slots with 64-bit distances (never
-  // overflow).  Each tier takes the previous one's overflow list; the first
-  // tier is the one where most queries of the previous batch ended.
+  // Tiers: 1 = 2048-slot LDS tables per direction (four blocks per CU),
+  // 2 = a slot per rank for the 8192 highest ranks plus 4096-slot tables per
+  // direction for the others (one block of 16 waves per CU), 3 = 16384-slot
+  // tables in global memory, 4 = tables of at least 2n slots with 64-bit
+  // distances (never overflow).  Each tier takes the previous one's overflow
+  // list; the first tier is the one where most queries of the previous batch
+  // ended.
   // counters: [0] tier-1 overflows, [1] bad ids, [2] tier-2 overflows,
   // [3] tier-3 overflows
   uint32_t *ctr = ch->q_ctr.as<uint32_t>();
@@ -1018,7 +1104,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 4);
     const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
 #define SP_QUERY_LAUNCH(NW)                                                                    \
-  k_query<NW, 2048, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
+  k_query<NW, QTier1, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
       q, ch->n, nullptr, nullptr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,   \
       ovf1, ctr, wend, nullptr)
     if (nw == 1) SP_QUERY_LAUNCH(1);
@@ -1029,7 +1115,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     HIP_TRY(hipGetLastError());
   }
   if (first <= 2) {
-    k_query<16, 8192, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
+    k_query<16, QTier2, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
         dnarc, dd, dv, ovf2, ctr + 2, wend, nullptr);
     HIP_TRY(hipGetLastError());
@@ -1043,11 +1129,11 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   uint32_t *list3 = first <= 2 ? ovf2 : nullptr;
   uint32_t n4 = 0;
   if (n3) {
-    using T3 = QLds<16384>;
+    using T3 = QTier3;
     const uint64_t nb = std::min<uint64_t>(n3, (uint64_t)cus * 4);
     HIP_TRY(ch->q_tab.ensure(nb * sizeof(T3)));
     // overflows into ctr[4]; the input count is tier 2's, on the device
-    k_query<8, 16384, true><<<(unsigned)nb, 512, 0, st>>>(
+    k_query<8, QTier3, true><<<(unsigned)nb, 512, 0, st>>>(
         q, ch->n, list3, ctr + 2, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,
         ovf1, ctr + 4, wend, reinterpret_cast<T3 *>(ch->q_tab.p));
     HIP_TRY(hipGetLastError());
