@@ -68,7 +68,7 @@ extern "C" {
 #define CH_F_NO_QUERY_INDEX 0x4u  /* skip the rank-space CSR (ch_query_batch then fails) */
 
 #define CH_Q_ON_DEVICE 0x1u       /* s, t, dist of ch_query_batch are device pointers */
-/* Waves that share one query in the first (2048-slot) query tier (1, 2, 4
+/* Waves that share one query in the first query tier (1, 2, 4
  * or 8; 0 = the default, 4).  Results do not depend on it. */
 #define CH_Q_WAVES(nw) ((uint32_t)(nw) << 8)
 /* Level window of the query's search steps (1 .. 254 levels; 0 = the

@@ -573,10 +573,14 @@ struct QLds {
   uint32_t wsum2[16];  // a second scan within one step
   unsigned long long wmin[16];
 };
-using QTier1 = QLds<2048>;
+// Tier 1: a slot per rank for the 2048 highest ranks, 512-slot tables for
+// the rest (on a road-like 1M CH at most about 250 vertices of a search
+// space lie below the top 2048 ranks); five blocks per CU.
+using QTier1 = QLds<512, 2048, 2048>;
 using QTier2 = QLds<4096, 8192, 4096>;
 using QTier3 = QLds<16384>;
-static_assert(sizeof(QTier1) * 4 <= 163840, "four tier-1 query blocks per CU");
+constexpr int kQTier1PerCU = 5;
+static_assert(sizeof(QTier1) * kQTier1PerCU <= 163840, "five tier-1 query blocks per CU");
 static_assert(sizeof(QTier2) <= 163840, "one tier-2 query block per CU");
 
 // Table accessors: plain LDS accesses, or device-coherent ones for tables in
@@ -1069,7 +1073,8 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     dv = ch->q_v.as<uint32_t>();
   }
   HIP_TRY(ch->q_ovf.ensure(q * 4));
-  // Tiers: 1 = 2048-slot LDS tables per direction (four blocks per CU),
+  // Tiers: 1 = a slot per rank for the 2048 highest ranks plus 512-slot
+  // tables per direction for the others (five blocks per CU),
   // 2 = a slot per rank for the 8192 highest ranks plus 4096-slot tables per
   // direction for the others (one block of 16 waves per CU), 3 = 16384-slot
   // tables in global memory, 4 = tables of at least 2n slots with 64-bit
@@ -1101,7 +1106,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   }
   const uint32_t *wend = win ? ch->q_wend.as<uint32_t>() : nullptr;
   if (first <= 1) {
-    const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * 4);
+    const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * kQTier1PerCU);
     const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
 #define SP_QUERY_LAUNCH(NW)                                                                    \
   k_query<NW, QTier1, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \

@@ -196,12 +196,14 @@ def test_road_100k_bit_exact(gpu):
 
 def test_query_tiers(gpu):
     # Upward search spaces of every size: the hub of a fan graph reaches the
-    # whole path, so its queries need the 8192-slot LDS tier (k = 3000), the
-    # 16384-slot tier in global memory (k = 10000) and the last tier with
-    # tables of 2n slots (k = 60000); the path's own queries stay in the first
-    # tier.  Batches made only of hub queries move the CH's first tier up,
-    # which must not change any result.
-    for k in (3000, 10000, 60000):
+    # whole path (the k highest ranks), so its queries need the second LDS
+    # tier (k = 3000: more than the first tier's 2048 rank slots + 448 table
+    # entries), the 16384-slot tier in global memory (k = 13000: more than
+    # the second tier's 8192 rank slots + 3584 table entries) and the last
+    # tier with tables of 2n slots (k = 60000); the path's own queries stay in
+    # the first tier.  Batches made only of hub queries move the CH's first
+    # tier up, which must not change any result.
+    for k in (3000, 13000, 60000):
         off, dst, w = synth.fan(k)
         n = len(off) - 1
         print(f"[parity] fan k={k}", flush=True)
@@ -211,7 +213,7 @@ def test_query_tiers(gpu):
         t = np.concatenate([rt[:40], rt, np.full(20, k, np.uint32)])
         od, _ = o.query_batch(s, t)
         cs = closure_sizes(o, s, t)
-        assert cs.max() > {3000: 1792, 10000: 7168, 60000: 14336}[k]
+        assert cs.max() > {3000: 2048 + 448, 13000: 8192 + 3584, 60000: 14336}[k]
         for nw in (1, 2, 4, 8):
             d, vis = ch.query_stats(s, t, waves=nw)
             assert np.array_equal(d, od), nw
