@@ -389,16 +389,15 @@ struct Builder {
     return CH_OK;
   }
 
-  // Hop mode adds a second distance array to every table, so fewer blocks
-  // fit in a CU's 160 KB of LDS.
+  // At most max_per_cu one-wave blocks per CU, and no more than the CU's
+  // 160 KB of LDS holds (hop mode adds a second distance array to every
+  // table).
   template <int G, int CAP>
   void launch_ls(const Overlay &v, const uint32_t *list, uint32_t nl, const uint32_t *nl_dev,
-                 int tier, int blocks_per_cu) {
+                 int tier, int max_per_cu) {
     const bool hop = prm.wps_mode == CH_WPS_HOP;
-    if (hop) {
-      const size_t lds = (size_t)(kLsBlock / G) * ((size_t)CAP * 22 + 16);
-      blocks_per_cu = std::max(1, std::min(blocks_per_cu, (int)((160u << 10) / lds)));
-    }
+    const size_t lds = ls_lds_bytes(G, CAP, hop);
+    const int blocks_per_cu = std::max(1, std::min(max_per_cu, (int)((160u << 10) / lds)));
     const uint32_t groups = (uint32_t)cus * blocks_per_cu * (kLsBlock / G);
     const uint32_t chunk = (!nl_dev && nl >= 16u * groups) ? 4u : 1u;
     DevCtr *d = dc();
@@ -633,11 +632,11 @@ struct Builder {
           case CH_LS_16x128: launch_ls<16, 128>(v, vw.as<uint32_t>(), nw, nullptr, 1, 16); break;
           case CH_LS_32x512: launch_ls<32, 512>(v, vw.as<uint32_t>(), nw, nullptr, 1, 8); break;
           case CH_LS_64x512: launch_ls<64, 512>(v, vw.as<uint32_t>(), nw, nullptr, 1, 16); break;
-          default: launch_ls<64, 2048>(v, vw.as<uint32_t>(), nw, nullptr, 1, 4); break;
+          default: launch_ls<64, 2048>(v, vw.as<uint32_t>(), nw, nullptr, 1, 8); break;
         }
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
-        launch_ls<64, 4096>(v, ovf1.as<uint32_t>(), 0, &dc()->novf1, 2, 2);
+        launch_ls<64, 4096>(v, ovf1.as<uint32_t>(), 0, &dc()->novf1, 2, 4);
         HIP_TRY(hipGetLastError());
       }
       // Steps 1 (pruning) to 4 (contraction counts) run before the searches

@@ -181,6 +181,18 @@ __device__ __forceinline__ void flush_stats(const SearchStats &ss, LsCounters *c
 
 constexpr int kLsBlock = 64;  // one wave per workgroup
 
+// LDS search tables: a search overflows past 3/4 of its slots, so the
+// insertion-order and frontier lists hold that many entries.
+constexpr int ls_limit(int cap) { return cap * 3 / 4; }
+// LDS bytes of one k_local_search block (kLsBlock / G tables): keys,
+// distances, hop-mode second distances, target and frontier bitmaps, four
+// counters, insertion order and two frontier lists.
+constexpr size_t ls_lds_bytes(int g, int cap, bool hop) {
+  return (size_t)(kLsBlock / g) *
+         (4 * (size_t)cap * (hop ? 3 : 2) + (hop ? 0 : 4) + 8 * (size_t)(cap / 32) + 16 +
+          6 * (size_t)ls_limit(cap));
+}
+
 // LDS fast path: groups of G lanes, CAP-slot table per group.  Persistent:
 // every group takes `chunk` sources at a time from a global counter.
 template <int G, int CAP, bool HOP>
@@ -192,21 +204,30 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
     uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
   constexpr int NG = kLsBlock / G;
   constexpr int CAP2 = HOP ? CAP : 1;  // second distance array only in hop mode
+  constexpr int LIM = ls_limit(CAP);
+  static_assert(ls_lds_bytes(G, CAP, HOP) ==
+                    sizeof(uint32_t) * (3 * NG * CAP + NG * (CAP2 - CAP) + 2 * NG * (CAP / 32) +
+                                        4 * NG) +
+                        sizeof(uint16_t) * 3 * NG * LIM,
+                "host LDS size of the search tables");
   if (nw_dev) nw = *nw_dev;  // source count produced by an earlier kernel
   if (nw == 0) return;
   __shared__ uint32_t s_key[NG][CAP];
   __shared__ uint32_t s_dist[NG][CAP];
   __shared__ uint32_t s_dist2[NG][CAP2];
-  __shared__ uint32_t s_flag[NG][CAP];
-  __shared__ uint16_t s_order[NG][CAP];
-  __shared__ uint16_t s_fr[NG][2][CAP];
+  __shared__ uint32_t s_bits[NG][2][CAP / 32];  // target, frontier
+  __shared__ uint16_t s_order[NG][LIM];
+  __shared__ uint16_t s_fr[NG][2][LIM];
   __shared__ uint32_t s_ctr[NG][4];
   const int g = threadIdx.x / G, gl = glane<G>();
   for (int i = gl; i < CAP; i += G) {
     s_key[g][i] = SP_EMPTY32;
     s_dist[g][i] = SP_INF32;
     if constexpr (HOP) s_dist2[g][i] = SP_INF32;
-    s_flag[g][i] = 0;
+  }
+  for (int i = gl; i < CAP / 32; i += G) {
+    s_bits[g][0][i] = 0;
+    s_bits[g][1][i] = 0;
   }
   if (gl < 4) s_ctr[g][gl] = 0;
   wave_sync();
@@ -214,14 +235,16 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
   T.key = s_key[g];
   T.dist = s_dist[g];
   T.dist2 = HOP ? s_dist2[g] : nullptr;
-  T.flag = s_flag[g];
+  T.tgt = s_bits[g][0];
+  T.front = s_bits[g][1];
   T.order = s_order[g];
   T.fr0 = s_fr[g][0];
   T.fr1 = s_fr[g][1];
   T.ctr = s_ctr[g];
   T.cap = CAP;
   T.shift = 32 - __builtin_ctz(CAP);
-  T.limit = (CAP * 3) / 4;
+  T.limit = LIM;
+  T.fcap = LIM;
   SearchStats ss;
   for (;;) {
     uint32_t base = 0;
@@ -243,9 +266,9 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
 }
 
 // Global-memory fallback: one wave per source, table of `cap` slots per
-// wave at tabs + wave * stride_words (key, dist, flag, order, fr0, fr1 and,
-// in hop mode, dist2 as consecutive uint32 arrays of `cap`, then 4
-// counters).
+// wave at tabs + wave * stride_words (key, dist, a region holding the
+// target and frontier bitmaps, order, fr0, fr1 and, in hop mode, dist2 as
+// consecutive uint32 arrays of `cap`, then 4 counters).
 template <bool HOP>
 __global__ void __launch_bounds__(64) k_local_search_global(
     Overlay ov, const uint32_t *__restrict__ list, uint32_t nlist,
@@ -257,7 +280,8 @@ __global__ void __launch_bounds__(64) k_local_search_global(
   Tab<uint32_t, true> T;
   T.key = base;
   T.dist = base + cap;
-  T.flag = base + 2 * (size_t)cap;
+  T.tgt = base + 2 * (size_t)cap;  // the two bitmaps share a region of cap words
+  T.front = T.tgt + cap / 32;
   T.order = base + 3 * (size_t)cap;
   T.fr0 = base + 4 * (size_t)cap;
   T.fr1 = base + 5 * (size_t)cap;
@@ -266,6 +290,7 @@ __global__ void __launch_bounds__(64) k_local_search_global(
   T.cap = cap;
   T.shift = 32 - __builtin_ctz(cap);
   T.limit = cap;  // cap >= 2 n_o: never overflows
+  T.fcap = cap;
   SearchStats ss;
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
     if (!search_source<64, HOP>(ov, aflag, memo, T, list[i], ss, ws, err, hops)) {

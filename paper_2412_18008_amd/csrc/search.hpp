@@ -32,7 +32,6 @@ struct Overlay {
   const uint32_t *gid;   // n: original id of each local vertex
 };
 
-enum : uint32_t { kFlagTarget = 1u, kFlagFront = 2u };
 enum : int { kCtrUsed = 0, kCtrF0 = 1, kCtrF1 = 2, kCtrOvf = 3 };
 
 template <typename IdxT, bool GL>
@@ -40,13 +39,15 @@ struct Tab {
   uint32_t *key;   // vertex (local id) or SP_EMPTY32
   uint32_t *dist;  // tentative distance; during target collection 0xFFFFFFFF - max via
   uint32_t *dist2; // hop mode: the distances of the level being computed (else null)
-  uint32_t *flag;  // kFlag*
-  IdxT *order;     // slots in insertion order
-  IdxT *fr0, *fr1; // frontier slot lists
+  uint32_t *tgt;   // bitmap: slot holds a target
+  uint32_t *front; // bitmap: slot is in the next frontier list
+  IdxT *order;     // slots in insertion order (limit entries)
+  IdxT *fr0, *fr1; // frontier slot lists (fcap entries each)
   uint32_t *ctr;   // used, |fr0|, |fr1|, overflow
   uint32_t cap;    // power of two
   uint32_t shift;  // 32 - log2(cap)
   uint32_t limit;  // overflow when more slots than this are used
+  uint32_t fcap;   // frontier list capacity (>= limit)
 
   __device__ __forceinline__ uint32_t ld(const uint32_t *p) const {
     if constexpr (GL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -150,7 +151,10 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
     T.st(&T.key[s], SP_EMPTY32);
     T.st(&T.dist[s], SP_INF32);
     if (T.dist2) T.st(&T.dist2[s], SP_INF32);
-    T.st(&T.flag[s], 0u);
+  }
+  for (uint32_t i = gl; i < T.cap / 32; i += G) {
+    T.st(&T.tgt[i], 0u);
+    T.st(&T.front[i], 0u);
   }
   T.sync();
   if (used >= T.limit) {  // an overflowing insert may have left unlisted keys
@@ -158,7 +162,6 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
       T.st(&T.key[i], SP_EMPTY32);
       T.st(&T.dist[i], SP_INF32);
       if (T.dist2) T.st(&T.dist2[i], SP_INF32);
-      T.st(&T.flag[i], 0u);
     }
   }
   if (gl < 4) T.st(&T.ctr[gl], 0u);
@@ -233,7 +236,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       for (int q = 0; q < K; q++) {
         if (!act[q]) continue;
         if (got[q] == SP_INF32) {
-          T.st(&T.flag[slot[q]], kFlagTarget);
+          atomicOr(&T.tgt[slot[q] >> 5], 1u << (slot[q] & 31));
           D = max(D, 0xFFFFFFFFu - T.ld(&T.dist[slot[q]]));
           nt++;
         }
@@ -261,7 +264,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     if (slot >= 0) {
       T.st(&T.dist[slot], 0u);
       if constexpr (HOP) T.st(&T.dist2[slot], 0u);
-      T.st(&T.flag[slot], kFlagFront);
+      atomicOr(&T.front[slot >> 5], 1u << (slot & 31));
       T.sti(&T.fr0[0], (IdxT)slot);
       T.st(&T.ctr[kCtrF0], 1u);
     }
@@ -288,7 +291,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       if (i < ncur) {
         const IdxT x = T.ldi(&fc[i]);
         if constexpr (!HOP) {
-          atomicAnd(&T.flag[x], ~kFlagFront);
+          atomicAnd(&T.front[x >> 5], ~(1u << (x & 31)));
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
         dx = T.ld(&T.dist[x]);
@@ -308,10 +311,13 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
             uint32_t *dw = HOP ? T.dist2 : T.dist;
             const uint32_t old = atomicMin(&dw[y], (uint32_t)nd);
             if ((uint32_t)nd < old) {
-              const uint32_t f = atomicOr(&T.flag[y], kFlagFront);
-              if (!(f & kFlagFront)) {
+              const uint32_t bit = 1u << (y & 31);
+              const uint32_t f = atomicOr(&T.front[y >> 5], bit);
+              if (!(f & bit)) {
+                // more than fcap distinct slots means more than limit used:
+                // the overflow is flagged and the search discarded
                 const uint32_t p = atomicAdd(nn, 1u);
-                if (p < T.cap) T.sti(&fn[p], (IdxT)y);
+                if (p < T.fcap) T.sti(&fn[p], (IdxT)y);
               }
             }
           }
@@ -323,11 +329,11 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     if constexpr (HOP) {
       // end of the level: the changed entries take their new distance and
       // may change again in the next level
-      const uint32_t nnext = min(T.ld(nn), T.cap);
+      const uint32_t nnext = min(T.ld(nn), T.fcap);
       for (uint32_t i = gl; i < nnext; i += G) {
         const IdxT y = T.ldi(&fn[i]);
         T.st(&T.dist[y], T.ld(&T.dist2[y]));
-        atomicAnd(&T.flag[y], ~kFlagFront);
+        atomicAnd(&T.front[y >> 5], ~(1u << (y & 31)));
       }
       T.sync();
       level++;
@@ -349,7 +355,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     for (uint32_t i = gl; i < used; i += G) {
       const IdxT slot = T.ldi(&T.order[i]);
       ball += T.ld(&T.dist[slot]) <= D ? 1u : 0u;
-      if (T.ld(&T.flag[slot]) & kFlagTarget) {
+      if ((T.ld(&T.tgt[slot >> 5]) >> (slot & 31)) & 1u) {
         const uint32_t d = T.ld(&T.dist[slot]);
         if (d <= D) {
           memo_put(memo, gs, ov.gid[T.ld(&T.key[slot])], d);
