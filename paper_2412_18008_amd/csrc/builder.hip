@@ -575,8 +575,8 @@ struct Builder {
     uint64_t next_bound = 0;
     if (n) {
       HIP_TRY(hipMemsetAsync(&dc()->bound, 0, 8, st));
-      k_ls_bound_flags<<<grid(n), 256, 0, st>>>(view(ov[cur]), aflag.as<uint8_t>(),
-                                                 aflag.as<uint8_t>(), &dc()->bound);
+      k_ls_bound_flags<4><<<ggrid<4>(n), 256, 0, st>>>(view(ov[cur]), aflag.as<uint8_t>(),
+                                                       aflag.as<uint8_t>(), &dc()->bound);
       HIP_TRY(hipGetLastError());
       TRY(readback());
       next_bound = hctr->bound;
@@ -861,8 +861,15 @@ struct Builder {
         Overlay vb = view(N);
         vb.n = O.n;
         // the bound accumulates into the counter cleared at the round start
-        k_ls_bound_flags<<<grid(O.n), 256, 0, st>>>(vb, wflag.as<uint8_t>(),
-                                                     aflag_next.as<uint8_t>(), &dc()->bound);
+        auto bound = [&](auto kern, unsigned gr) {
+          kern<<<gr, 256, 0, st>>>(vb, wflag.as<uint8_t>(), aflag_next.as<uint8_t>(),
+                                   &dc()->bound);
+        };
+        dispatch(gm, [&] { bound(k_ls_bound_flags<4>, ggrid<4>(O.n)); },
+                 [&] { bound(k_ls_bound_flags<8>, ggrid<8>(O.n)); },
+                 [&] { bound(k_ls_bound_flags<16>, ggrid<16>(O.n)); },
+                 [&] { bound(k_ls_bound_flags<32>, ggrid<32>(O.n)); },
+                 [&] { bound(k_ls_bound_flags<64>, ggrid<64>(O.n)); });
         HIP_TRY(hipGetLastError());
       }
       if (stats) HIP_TRY(hipEventRecord(ev[4], st));

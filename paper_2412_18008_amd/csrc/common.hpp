@@ -43,8 +43,8 @@ __device__ __forceinline__ uint64_t group_mask_bits() {
 template <int G>
 __device__ __forceinline__ uint64_t gballot(bool p) {
   uint64_t b = __ballot(p);
-  if (G == 64) return b;
-  return (b >> (lane_id() & ~(G - 1))) & ((1ull << G) - 1ull);
+  if constexpr (G == 64) return b;
+  else return (b >> (lane_id() & ~(G - 1))) & ((1ull << G) - 1ull);
 }
 
 template <int G>

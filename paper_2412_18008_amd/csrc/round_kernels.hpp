@@ -142,15 +142,20 @@ __global__ void k_ls_bound(Overlay ov, const uint32_t *__restrict__ vw, uint32_t
   if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
 }
 
-// Same bound with the sources given as a flag array (thread per vertex).
-__global__ void k_ls_bound_flags(Overlay ov, const uint8_t *__restrict__ wflag,
-                                 const uint8_t *__restrict__ aflag,
-                                 unsigned long long *__restrict__ out) {
+// Same bound with the sources given as a flag array (G lanes per vertex).
+template <int G>
+__global__ void __launch_bounds__(256) k_ls_bound_flags(Overlay ov,
+                                                        const uint8_t *__restrict__ wflag,
+                                                        const uint8_t *__restrict__ aflag,
+                                                        unsigned long long *__restrict__ out) {
   uint64_t acc = 0;
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < ov.n; s += stride) {
+  const uint32_t ngroups = gridDim.x * (blockDim.x / G);
+  const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
+  const uint32_t gl = (uint32_t)glane<G>();
+  for (uint32_t s = g0; s < ov.n; s += ngroups) {
     if (!wflag[s]) continue;
-    for (uint32_t e = ov.foff[s]; e < ov.foff[s + 1]; e++) {
+    const uint32_t e1 = ov.foff[s + 1];
+    for (uint32_t e = ov.foff[s] + gl; e < e1; e += G) {
       const uint32_t u = ov.farc[e].x;
       if (aflag[u]) acc += ov.foff[u + 1] - ov.foff[u];
     }
@@ -1147,16 +1152,27 @@ __global__ void k_mark_in_neighbours(uint32_t n, const uint8_t *__restrict__ F,
 }
 
 // Entries of the memo whose endpoints are both live (the only ones looked up
-// again: lookups and inserts always pair two live vertices).
+// again: lookups and inserts always pair two live vertices).  Each thread
+// takes four slots a stride apart per step, so all their key loads and then
+// all their liveness loads are in flight together.
+constexpr int kRehashBatch = 4;
+
 __global__ void k_memo_count_live(const MemoSlot *__restrict__ old, uint64_t ocap,
                                   const uint8_t *__restrict__ alive_g,
                                   unsigned long long *__restrict__ live) {
   uint64_t c = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ocap; i += stride) {
-    const uint64_t k = old[i].key;
-    if (k == SP_EMPTY64) continue;
-    c += alive_g[(uint32_t)(k >> 32)] && alive_g[(uint32_t)k];
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < ocap;
+       i0 += kRehashBatch * stride) {
+    uint64_t k[kRehashBatch];
+#pragma unroll
+    for (int q = 0; q < kRehashBatch; q++) {
+      const uint64_t i = i0 + q * stride;
+      k[q] = i < ocap ? old[i].key : SP_EMPTY64;
+    }
+#pragma unroll
+    for (int q = 0; q < kRehashBatch; q++)
+      if (k[q] != SP_EMPTY64) c += alive_g[(uint32_t)(k[q] >> 32)] && alive_g[(uint32_t)k[q]];
   }
   c = gsum64<kWave>(c);
   if (lane_id() == 0 && c) atomicAdd(live, (unsigned long long)c);
@@ -1169,13 +1185,26 @@ __global__ void k_memo_rehash(const MemoSlot *__restrict__ old, uint64_t ocap,
                               unsigned long long *__restrict__ kept) {
   uint64_t c = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ocap; i += stride) {
-    const uint64_t k = old[i].key;
-    if (k == SP_EMPTY64) continue;
-    const uint32_t s = (uint32_t)(k >> 32), v = (uint32_t)k;
-    if (!alive_g[s] || !alive_g[v]) continue;
-    memo_put(nt, s, v, old[i].val);
-    c++;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < ocap;
+       i0 += kRehashBatch * stride) {
+    ulonglong2 e[kRehashBatch];
+#pragma unroll
+    for (int q = 0; q < kRehashBatch; q++) {
+      const uint64_t i = i0 + q * stride;
+      e[q] = make_ulonglong2(SP_EMPTY64, 0ull);
+      if (i < ocap) e[q] = *reinterpret_cast<const ulonglong2 *>(&old[i]);
+    }
+    bool keep[kRehashBatch];
+#pragma unroll
+    for (int q = 0; q < kRehashBatch; q++)
+      keep[q] = e[q].x != SP_EMPTY64 && alive_g[(uint32_t)(e[q].x >> 32)] &&
+                alive_g[(uint32_t)e[q].x];
+#pragma unroll
+    for (int q = 0; q < kRehashBatch; q++) {
+      if (!keep[q]) continue;
+      memo_put(nt, (uint32_t)(e[q].x >> 32), (uint32_t)e[q].x, (uint32_t)e[q].y);
+      c++;
+    }
   }
   c = gsum64<kWave>(c);
   if (lane_id() == 0 && c) atomicAdd(kept, (unsigned long long)c);
