@@ -2,32 +2,118 @@
 #include "common.hpp"
 #include "prim.hpp"
 
+#include <map>
+#include <mutex>
+
 namespace sp {
+
+namespace {
+
+constexpr size_t kCacheMaxBytes = 32ull << 30;  // per device
+
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<std::pair<int, size_t>, void *> blocks;  // (device, size) -> block
+  std::map<int, size_t> bytes;                            // cached bytes per device
+};
+
+BlockCache &block_cache() {
+  static BlockCache *c = new BlockCache;  // lives until the process ends
+  return *c;
+}
+
+// Allocation size class: whole MiB from 1 MiB up, else a power of two.
+size_t size_class(size_t b) {
+  if (b >= (1u << 20)) return (b + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+  size_t c = 256;
+  while (c < b) c <<= 1;
+  return c;
+}
+
+// A cached block of device dev with at least `bytes` and at most twice that.
+void *cache_take(int dev, size_t bytes, size_t *got) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  auto it = c.blocks.lower_bound({dev, bytes});
+  if (it == c.blocks.end() || it->first.first != dev || it->first.second > 2 * bytes)
+    return nullptr;
+  void *p = it->second;
+  *got = it->first.second;
+  c.bytes[dev] -= *got;
+  c.blocks.erase(it);
+  return p;
+}
+
+// Frees every cached block of device dev (before retrying an allocation).
+void cache_flush(int dev) {
+  BlockCache &c = block_cache();
+  std::lock_guard<std::mutex> g(c.mu);
+  for (auto it = c.blocks.begin(); it != c.blocks.end();) {
+    if (it->first.first == dev) {
+      (void)hipFree(it->second);
+      it = c.blocks.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  c.bytes[dev] = 0;
+}
+
+}  // namespace
 
 hipError_t DBuf::ensure(size_t bytes) {
   if (bytes <= cap) return hipSuccess;
   size_t nc = cap + cap / 2;
   if (nc < bytes) nc = bytes;
-  if (nc < 256) nc = 256;
-  if (p) {
-    hipError_t e = hipFree(p);
-    if (e != hipSuccess) return e;
-    p = nullptr;
-    cap = 0;
+  nc = size_class(nc);
+  release();
+  int d = 0;
+  hipError_t e = hipGetDevice(&d);
+  if (e != hipSuccess) return e;
+  size_t got = 0;
+  if (void *q = cache_take(d, nc, &got)) {
+    e = hipDeviceSynchronize();  // no kernel may still use the block
+    if (e != hipSuccess) {
+      (void)hipFree(q);
+      return e;
+    }
+    p = q;
+    cap = got;
+    dev = d;
+    return hipSuccess;
   }
-  hipError_t e = hipMalloc(&p, nc);
+  e = hipMalloc(&p, nc);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    cache_flush(d);
+    e = hipMalloc(&p, nc);
+  }
   if (e != hipSuccess) {
     p = nullptr;
     return e;
   }
   cap = nc;
+  dev = d;
   return hipSuccess;
 }
 
 void DBuf::release() {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  BlockCache &c = block_cache();
+  bool kept = false;
+  {
+    std::lock_guard<std::mutex> g(c.mu);
+    size_t &b = c.bytes[dev];
+    if (b + cap <= kCacheMaxBytes) {
+      c.blocks.emplace(std::make_pair(dev, cap), p);
+      b += cap;
+      kept = true;
+    }
+  }
+  if (!kept) (void)hipFree(p);
   p = nullptr;
   cap = 0;
+  dev = -1;
 }
 
 // ---------------------------------------------------------------------------

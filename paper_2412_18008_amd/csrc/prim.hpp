@@ -9,10 +9,16 @@
 
 namespace sp {
 
-// Growable device buffer (hipMalloc'ed; grows by 1.5x, never shrinks).
+// Growable device buffer (grows by 1.5x, never shrinks).  Blocks come from
+// and go back to a per-device cache of released blocks (at most 32 GB per
+// device), so repeated builds and queries do not pay hipMalloc / hipFree:
+// taking a cached block first synchronises the device, so a block released
+// while a kernel on another stream may still use it is never handed out
+// early.
 struct DBuf {
   void *p = nullptr;
   size_t cap = 0;
+  int dev = -1;  // device of the allocation
   hipError_t ensure(size_t bytes);
   void release();
   template <typename T>
