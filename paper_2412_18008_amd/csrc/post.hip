@@ -569,6 +569,7 @@ struct QLds {
   uint32_t used[2];          // hashed entries
   uint32_t usedt[2];         // dense entries
   uint32_t ovf;
+  uint32_t next[2];    // index of the block's current query (low, high word)
   uint32_t wsum[16];
   uint32_t wsum2[16];  // a second scan within one step
   unsigned long long wmin[16];
@@ -731,9 +732,10 @@ __device__ __forceinline__ void qclear(L &S, uint32_t tid, uint32_t nt) {
   if (tid == 0) qst<GM>(&S.ovf, 0u);
 }
 
-// Queries: list ? list[i] for i < *nlist : i for i < q.  Queries that do
-// not fit go to ovf_list (count in *ovf_count).  GM: gtab holds one L per
-// block.
+// Queries: list ? list[i] for i < *nlist : i for i < q, taken one at a time
+// by the blocks from the counter *work (so blocks that draw large queries
+// take fewer).  Queries that do not fit go to ovf_list (count in
+// *ovf_count).  GM: gtab holds one L per block.
 template <int NW, typename L, bool GM>
 __global__ void __launch_bounds__(64 * NW) k_query(
     uint64_t q, uint32_t n, const uint32_t *__restrict__ list,
@@ -744,7 +746,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
     uint32_t *__restrict__ ovf_count, const uint32_t *__restrict__ wend,
-    L *__restrict__ gtab) {
+    unsigned long long *__restrict__ work, L *__restrict__ gtab) {
   using E = typename L::Entry;
   constexpr uint32_t CAP = sizeof(((L *)nullptr)->key[0]) / 4;
   constexpr uint32_t TOP = L::kTop, NS = L::kSlots;
@@ -771,13 +773,23 @@ __global__ void __launch_bounds__(64 * NW) k_query(
   };
   qclear<GM>(S, tid, NT);
   qsync<NW, GM>();
-  for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+  for (;;) {
+    // every thread has read the previous index (it passed a barrier since)
+    if (tid == 0) {
+      const unsigned long long w = atomicAdd(work, 1ull);
+      qst<GM>(&S.next[0], (uint32_t)w);
+      qst<GM>(&S.next[1], (uint32_t)(w >> 32));
+    }
+    qsync<NW, GM>();
+    const uint64_t qi = (uint64_t)qld<GM>(&S.next[0]) | ((uint64_t)qld<GM>(&S.next[1]) << 32);
+    if (qi >= nq) break;
     const uint64_t k = list ? (uint64_t)list[qi] : qi;
     if (qs[k] >= n || qt[k] >= n) {  // the same k in every thread
       if (tid == 0) {
         atomicOr(bad, 1u);
         dist[k] = SP_INF64;
       }
+      qsync<NW, GM>();
       continue;
     }
     if (tid < 2) {
@@ -1082,7 +1094,8 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   // list; the first tier is the one where most queries of the previous batch
   // ended.
   // counters: [0] tier-1 overflows, [1] bad ids, [2] tier-2 overflows,
-  // [3] tier-3 overflows
+  // [4] tier-3 overflows, [6] tier-4 overflows, 64-bit work counters of
+  // tiers 1-3 at [8], [10], [12]
   uint32_t *ctr = ch->q_ctr.as<uint32_t>();
   HIP_TRY(ch->q_ovf2.ensure(q * 4));
   HIP_TRY(hipMemsetAsync(ctr, 0, 64, st));
@@ -1111,7 +1124,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
 #define SP_QUERY_LAUNCH(NW)                                                                    \
   k_query<NW, QTier1, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
       q, ch->n, nullptr, nullptr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,   \
-      ovf1, ctr, wend, nullptr)
+      ovf1, ctr, wend, reinterpret_cast<unsigned long long *>(ctr + 8), nullptr)
     if (nw == 1) SP_QUERY_LAUNCH(1);
     else if (nw == 2) SP_QUERY_LAUNCH(2);
     else if (nw == 8) SP_QUERY_LAUNCH(8);
@@ -1122,7 +1135,8 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   if (first <= 2) {
     k_query<16, QTier2, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
-        dnarc, dd, dv, ovf2, ctr + 2, wend, nullptr);
+        dnarc, dd, dv, ovf2, ctr + 2, wend, reinterpret_cast<unsigned long long *>(ctr + 10),
+        nullptr);
     HIP_TRY(hipGetLastError());
   }
   uint32_t hc[4] = {0, 0, 0, 0};
@@ -1140,7 +1154,8 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     // overflows into ctr[4]; the input count is tier 2's, on the device
     k_query<8, QTier3, true><<<(unsigned)nb, 512, 0, st>>>(
         q, ch->n, list3, ctr + 2, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,
-        ovf1, ctr + 4, wend, reinterpret_cast<T3 *>(ch->q_tab.p));
+        ovf1, ctr + 4, wend, reinterpret_cast<unsigned long long *>(ctr + 12),
+        reinterpret_cast<T3 *>(ch->q_tab.p));
     HIP_TRY(hipGetLastError());
     uint32_t h2[4] = {0, 0, 0, 0};  // ctr[1..4]
     HIP_TRY(hipMemcpyAsync(h2, ctr + 1, 16, hipMemcpyDeviceToHost, st));
