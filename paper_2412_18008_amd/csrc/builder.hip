@@ -98,6 +98,7 @@ struct Builder {
   DBuf dctr, tmp;
   DevCtr *hctr = nullptr;  // pinned
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_rb = nullptr;  // readback completion
   uint64_t up_cap = 0, dn_cap = 0;
   // disjoint-union batch: graph of each original vertex, per-graph
   // shortcut counters (device), vertex bases (device, k+1)
@@ -122,6 +123,7 @@ struct Builder {
     if (hctr) (void)hipHostFree(hctr);
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (ev_rb) (void)hipEventDestroy(ev_rb);
   }
 
   DevCtr *dc() { return dctr.as<DevCtr>(); }
@@ -148,9 +150,16 @@ struct Builder {
     return grid(items * G);
   }
 
+  // Counters to the host.  The wait polls an event instead of blocking in
+  // hipStreamSynchronize: the round loop waits here twice per round, and a
+  // blocked host thread takes longer to resume than the copy takes.
   int readback() {
     HIP_TRY(hipMemcpyAsync(hctr, dctr.p, sizeof(DevCtr), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipEventRecord(ev_rb, st));
+    hipError_t e;
+    while ((e = hipEventQuery(ev_rb)) == hipErrorNotReady) {
+    }
+    HIP_TRY(e);
     return CH_OK;
   }
 
@@ -512,6 +521,7 @@ struct Builder {
     HIP_TRY(dctr.ensure(sizeof(DevCtr)));
     HIP_TRY(hipHostMalloc((void **)&hctr, sizeof(DevCtr), hipHostMallocDefault));
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+    HIP_TRY(hipEventCreateWithFlags(&ev_rb, hipEventDisableTiming));
     const bool stats = prm.flags & CH_F_STATS;
 
     TRY(ingest(g));
