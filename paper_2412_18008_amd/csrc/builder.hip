@@ -385,9 +385,11 @@ struct Builder {
                                           tab_gid.as<uint32_t>());
     HIP_TRY(hipGetLastError());
     for (uint32_t k = 0; k < nb; k++) {
-      k_fw_rowcol<<<2 * nb, kFwThreads, 0, st>>>(tab_D.as<uint32_t>(), N, k);
+      k_fw_diag<<<1, kFwDiagThreads, 0, st>>>(tab_D.as<uint32_t>(), N, k);
       HIP_TRY(hipGetLastError());
       if (nb > 1) {
+        k_fw_panels<<<2 * nb, kFwThreads, 0, st>>>(tab_D.as<uint32_t>(), N, k);
+        HIP_TRY(hipGetLastError());
         k_fw_rest<<<nb * nb, kFwThreads, 0, st>>>(tab_D.as<uint32_t>(), N, k);
         HIP_TRY(hipGetLastError());
       }

@@ -24,8 +24,7 @@ constexpr int kFwThreads = 256; // 16 entries of a tile per thread (4 x 4)
 // a + b clamped to 0xFFFFFFFF: a distance above 0xFFFFFFFE (or through an
 // absent entry) is stored as "none"; no witness radius reaches it.
 __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
-  const uint64_t s = (uint64_t)a + b;
-  return s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
+  return __builtin_elementwise_add_sat(a, b);  // one clamped 32-bit add
 }
 
 // Dense matrix N x N (N a multiple of kFwTile, row-major): none everywhere,
@@ -52,25 +51,6 @@ __global__ void k_fw_arcs(Overlay ov, uint32_t N, uint32_t *__restrict__ D,
   }
 }
 
-// Closure of the tile in LDS over its own 64 intermediate vertices.
-__device__ __forceinline__ void fw_close_tile(uint32_t (*T)[kFwTile + 1]) {
-  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  for (int k = 0; k < kFwTile; k++) {
-#pragma unroll
-    for (int a = 0; a < 4; a++) {
-      const int i = ty * 4 + a;
-      const uint32_t dik = T[i][k];
-#pragma unroll
-      for (int b = 0; b < 4; b++) {
-        const int j = tx * 4 + b;
-        const uint32_t c = sat_add(dik, T[k][j]);
-        if (c < T[i][j]) T[i][j] = c;
-      }
-    }
-    __syncthreads();
-  }
-}
-
 __device__ __forceinline__ void fw_load(uint32_t (*T)[kFwTile + 1], const uint32_t *D, uint32_t N,
                                         uint32_t ti, uint32_t tj) {
   for (int e = threadIdx.x; e < kFwTile * kFwTile; e += kFwThreads) {
@@ -87,16 +67,12 @@ __device__ __forceinline__ void fw_store(const uint32_t (*T)[kFwTile + 1], uint3
   }
 }
 
-// C[i][j] = min(C[i][j], min_k A[i][k] + B[k][j]) over one tile.
-__device__ __forceinline__ void fw_minplus(uint32_t (*C)[kFwTile + 1],
-                                           const uint32_t (*A)[kFwTile + 1],
-                                           const uint32_t (*B)[kFwTile + 1]) {
+// acc[a][b] (entry (ty*4 + a, tx*4 + b) of a tile, ty = thread / 16, tx =
+// thread % 16) = min(acc, min over k of A[row][k] + B[k][col]).
+__device__ __forceinline__ void fw_minplus_acc(uint32_t (&acc)[4][4],
+                                               const uint32_t (*A)[kFwTile + 1],
+                                               const uint32_t (*B)[kFwTile + 1]) {
   const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
-  uint32_t acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; a++)
-#pragma unroll
-    for (int b = 0; b < 4; b++) acc[a][b] = C[ty * 4 + a][tx * 4 + b];
   for (int k = 0; k < kFwTile; k++) {
     uint32_t av[4], bv[4];
 #pragma unroll
@@ -111,60 +87,119 @@ __device__ __forceinline__ void fw_minplus(uint32_t (*C)[kFwTile + 1],
         acc[a][b] = c < acc[a][b] ? c : acc[a][b];
       }
   }
-  __syncthreads();
+}
+
+// The 16 entries of a tile that this thread owns, straight from / to D.
+__device__ __forceinline__ void fw_acc_load(uint32_t (&acc)[4][4], const uint32_t *D, uint32_t N,
+                                            uint32_t ti, uint32_t tj) {
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
 #pragma unroll
   for (int a = 0; a < 4; a++)
 #pragma unroll
-    for (int b = 0; b < 4; b++) C[ty * 4 + a][tx * 4 + b] = acc[a][b];
-  __syncthreads();
+    for (int b = 0; b < 4; b++)
+      acc[a][b] = D[(size_t)(ti * kFwTile + ty * 4 + a) * N + tj * kFwTile + tx * 4 + b];
 }
 
-// Phase k, first part: every block closes the diagonal tile (k, k) itself
-// (re-closing a partly updated tile gives the same closure), then block b <
-// nb updates row tile (k, b) and block nb + b column tile (b, k); the
-// blocks of tile (k, k) write the closed diagonal.
-__global__ void __launch_bounds__(kFwThreads) k_fw_rowcol(uint32_t *__restrict__ D, uint32_t N,
+__device__ __forceinline__ void fw_acc_store(const uint32_t (&acc)[4][4], uint32_t *D, uint32_t N,
+                                             uint32_t ti, uint32_t tj) {
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int b = 0; b < 4; b++)
+      D[(size_t)(ti * kFwTile + ty * 4 + a) * N + tj * kFwTile + tx * 4 + b] = acc[a][b];
+}
+
+// Phase k, step 1: closure of the diagonal tile (k, k) over its own 64
+// intermediate vertices by six min-plus squarings (T <- T (x) T): with a
+// zero diagonal the 2^s-th power holds the shortest paths of at most 2^s
+// arcs, and a shortest path inside the tile has at most 63.  The minimum is
+// over the same paths as the Floyd-Warshall loop, so the entries are the
+// same; each squaring is one parallel product instead of 64 dependent steps.
+// 1024 threads, 2 x 2 entries each.
+constexpr int kFwDiagThreads = 1024;
+
+__global__ void __launch_bounds__(kFwDiagThreads) k_fw_diag(uint32_t *__restrict__ D, uint32_t N,
+                                                            uint32_t k) {
+  __shared__ uint32_t T[kFwTile][kFwTile + 1];
+  for (int e = threadIdx.x; e < kFwTile * kFwTile; e += kFwDiagThreads) {
+    const int i = e / kFwTile, j = e % kFwTile;
+    T[i][j] = D[(size_t)(k * kFwTile + i) * N + (size_t)k * kFwTile + j];
+  }
+  __syncthreads();
+  const int ty = threadIdx.x / 32, tx = threadIdx.x % 32;
+  uint32_t acc[2][2];
+  for (int sq = 0; sq < 6; sq++) {
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++) acc[a][b] = T[ty * 2 + a][tx * 2 + b];
+    for (int t = 0; t < kFwTile; t++) {
+      const uint32_t a0 = T[ty * 2][t], a1 = T[ty * 2 + 1][t];
+      const uint32_t b0 = T[t][tx * 2], b1 = T[t][tx * 2 + 1];
+      acc[0][0] = min(acc[0][0], sat_add(a0, b0));
+      acc[0][1] = min(acc[0][1], sat_add(a0, b1));
+      acc[1][0] = min(acc[1][0], sat_add(a1, b0));
+      acc[1][1] = min(acc[1][1], sat_add(a1, b1));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+      for (int b = 0; b < 2; b++) T[ty * 2 + a][tx * 2 + b] = acc[a][b];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; a++)
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+      D[(size_t)(k * kFwTile + ty * 2 + a) * N + (size_t)k * kFwTile + tx * 2 + b] = acc[a][b];
+}
+
+// Phase k, step 2: block b < nb updates row tile (k, b) and block nb + b
+// column tile (b, k), b != k, with the closed diagonal tile: (k, b) <-
+// closure(k, k) (x) (k, b) and (b, k) <- (b, k) (x) closure(k, k) (min-plus
+// products; the closure's zero diagonal keeps the old entries).
+__global__ void __launch_bounds__(kFwThreads) k_fw_panels(uint32_t *__restrict__ D, uint32_t N,
                                                           uint32_t k) {
   __shared__ uint32_t Dk[kFwTile][kFwTile + 1];
   __shared__ uint32_t T[kFwTile][kFwTile + 1];
   const uint32_t nb = N / kFwTile;
   const bool col = blockIdx.x >= nb;
   const uint32_t b = col ? blockIdx.x - nb : blockIdx.x;
+  if (b == k) return;
   fw_load(Dk, D, N, k, k);
+  if (col) fw_load(T, D, N, b, k);
+  else fw_load(T, D, N, k, b);
   __syncthreads();
-  fw_close_tile(Dk);
-  if (b == k) {
-    if (!col) fw_store(Dk, D, N, k, k);
-    return;
-  }
-  if (col) {
-    fw_load(T, D, N, b, k);
-    __syncthreads();
-    fw_minplus(T, T, Dk);  // (b, k) <- (b, k) (x) closure(k, k)
-    fw_store(T, D, N, b, k);
-  } else {
-    fw_load(T, D, N, k, b);
-    __syncthreads();
-    fw_minplus(T, Dk, T);  // (k, b) <- closure(k, k) (x) (k, b)
-    fw_store(T, D, N, k, b);
-  }
+  uint32_t acc[4][4];
+  const int ty = threadIdx.x / 16, tx = threadIdx.x % 16;
+#pragma unroll
+  for (int a = 0; a < 4; a++)
+#pragma unroll
+    for (int c = 0; c < 4; c++) acc[a][c] = T[ty * 4 + a][tx * 4 + c];
+  if (col) fw_minplus_acc(acc, T, Dk);
+  else fw_minplus_acc(acc, Dk, T);
+  if (col) fw_acc_store(acc, D, N, b, k);
+  else fw_acc_store(acc, D, N, k, b);
 }
 
-// Phase k, second part: tile (i, j), i, j != k: min with (i, k) (x) (k, j).
+// Phase k, step 3: tile (i, j), i, j != k: min with (i, k) (x) (k, j).  The
+// tile's own entries stay in registers.
 __global__ void __launch_bounds__(kFwThreads) k_fw_rest(uint32_t *__restrict__ D, uint32_t N,
                                                         uint32_t k) {
   __shared__ uint32_t A[kFwTile][kFwTile + 1];
   __shared__ uint32_t B[kFwTile][kFwTile + 1];
-  __shared__ uint32_t C[kFwTile][kFwTile + 1];
   const uint32_t nb = N / kFwTile;
   const uint32_t i = blockIdx.x / nb, j = blockIdx.x % nb;
   if (i == k || j == k) return;
   fw_load(A, D, N, i, k);
   fw_load(B, D, N, k, j);
-  fw_load(C, D, N, i, j);
+  uint32_t acc[4][4];
+  fw_acc_load(acc, D, N, i, j);
   __syncthreads();
-  fw_minplus(C, A, B);
-  fw_store(C, D, N, i, j);
+  fw_minplus_acc(acc, A, B);
+  fw_acc_store(acc, D, N, i, j);
 }
 
 // Table position of every vertex of the current overlay (local ids change
