@@ -587,8 +587,8 @@ struct Builder {
     uint64_t next_bound = 0;
     if (n) {
       HIP_TRY(hipMemsetAsync(&dc()->bound, 0, 8, st));
-      k_ls_bound_flags<4><<<ggrid<4>(n), 256, 0, st>>>(view(ov[cur]), aflag.as<uint8_t>(),
-                                                       aflag.as<uint8_t>(), &dc()->bound);
+      k_ls_bound_affected<<<grid(n), 256, 0, st>>>(view(ov[cur]), aflag.as<uint8_t>(),
+                                                   &dc()->bound);
       HIP_TRY(hipGetLastError());
       TRY(readback());
       next_bound = hctr->bound;
@@ -866,22 +866,15 @@ struct Builder {
       HIP_TRY(select_flags(wflag.as<uint8_t>(), O.n, vw.as<uint32_t>(), &dc()->c32[C_UP], tmp, st));
       HIP_TRY(select_flags(aflag_next.as<uint8_t>(), O.n, va.as<uint32_t>(), &dc()->c32[C_DN],
                            tmp, st));
-      // upper bound on the next round's memo inserts: over every source s
-      // and affected out-neighbour u, the out-degree of u (rows past the new
-      // vertex count are empty)
+      // upper bound on the next round's memo inserts: in-degree x out-degree
+      // summed over the affected vertices (rows past the new vertex count
+      // are empty)
       {
         Overlay vb = view(N);
         vb.n = O.n;
         // the bound accumulates into the counter cleared at the round start
-        auto bound = [&](auto kern, unsigned gr) {
-          kern<<<gr, 256, 0, st>>>(vb, wflag.as<uint8_t>(), aflag_next.as<uint8_t>(),
-                                   &dc()->bound);
-        };
-        dispatch(gm, [&] { bound(k_ls_bound_flags<4>, ggrid<4>(O.n)); },
-                 [&] { bound(k_ls_bound_flags<8>, ggrid<8>(O.n)); },
-                 [&] { bound(k_ls_bound_flags<16>, ggrid<16>(O.n)); },
-                 [&] { bound(k_ls_bound_flags<32>, ggrid<32>(O.n)); },
-                 [&] { bound(k_ls_bound_flags<64>, ggrid<64>(O.n)); });
+        k_ls_bound_affected<<<grid(O.n), 256, 0, st>>>(vb, aflag_next.as<uint8_t>(),
+                                                       &dc()->bound);
         HIP_TRY(hipGetLastError());
       }
       if (stats) HIP_TRY(hipEventRecord(ev[4], st));

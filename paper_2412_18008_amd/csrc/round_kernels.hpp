@@ -125,41 +125,19 @@ __global__ void k_adjacent_equal(uint32_t n, const uint64_t *__restrict__ key,
 // LocalSearch
 // ===========================================================================
 
-// Upper bound on this round's memo inserts: sum over s in V_W and affected
-// out-neighbours u of s of outdeg(u).
-__global__ void k_ls_bound(Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw,
-                           const uint8_t *__restrict__ aflag, unsigned long long *__restrict__ out) {
+// Upper bound on the next round's memo inserts.  A search from s inserts
+// at most outdeg(u) targets through each affected out-neighbour u of s, so
+// the sum of outdeg(u) over arcs s -> u into affected vertices bounds every
+// round; summing it over all in-arcs of the affected vertices, indeg(u) x
+// outdeg(u), bounds it again and reads the offsets in order (the exact sum
+// would read every source's row at random).
+__global__ void k_ls_bound_affected(Overlay ov, const uint8_t *__restrict__ aflag,
+                                    unsigned long long *__restrict__ out) {
   uint64_t acc = 0;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) {
-    const uint32_t s = vw[i];
-    for (uint32_t e = ov.foff[s]; e < ov.foff[s + 1]; e++) {
-      const uint32_t u = ov.farc[e].x;
-      if (aflag[u]) acc += ov.foff[u + 1] - ov.foff[u];
-    }
-  }
-  acc = gsum64<kWave>(acc);
-  if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
-}
-
-// Same bound with the sources given as a flag array (G lanes per vertex).
-template <int G>
-__global__ void __launch_bounds__(256) k_ls_bound_flags(Overlay ov,
-                                                        const uint8_t *__restrict__ wflag,
-                                                        const uint8_t *__restrict__ aflag,
-                                                        unsigned long long *__restrict__ out) {
-  uint64_t acc = 0;
-  const uint32_t ngroups = gridDim.x * (blockDim.x / G);
-  const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
-  const uint32_t gl = (uint32_t)glane<G>();
-  for (uint32_t s = g0; s < ov.n; s += ngroups) {
-    if (!wflag[s]) continue;
-    const uint32_t e1 = ov.foff[s + 1];
-    for (uint32_t e = ov.foff[s] + gl; e < e1; e += G) {
-      const uint32_t u = ov.farc[e].x;
-      if (aflag[u]) acc += ov.foff[u + 1] - ov.foff[u];
-    }
-  }
+  for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < ov.n; u += stride)
+    if (aflag[u])
+      acc += (uint64_t)(ov.roff[u + 1] - ov.roff[u]) * (ov.foff[u + 1] - ov.foff[u]);
   acc = gsum64<kWave>(acc);
   if (lane_id() == 0 && acc) atomicAdd(out, (unsigned long long)acc);
 }
