@@ -468,32 +468,23 @@ struct Builder {
   void merge_rows(OvBuf &O, OvBuf &N, int kb, const uint32_t *fb0, const uint32_t *fb1,
                   const uint32_t *rb0, const uint32_t *rb1) {
     merge_err = CH_OK;
-    const unsigned gr = ggrid<G>(O.n);
-    k_merge_rows<G, 0><<<gr, 256, 0, st>>>(
-        O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-        O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
-        uw.as<uint32_t>(), umid.as<uint32_t>(), cnt2.as<uint32_t>(), nullptr, nullptr, nullptr);
-    k_merge_rows<G, 0><<<gr, 256, 0, st>>>(
-        O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-        O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(), rb0,
-        rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), cnt3.as<uint32_t>(), nullptr, nullptr,
-        nullptr);
+    const dim3 gr(ggrid<G>(O.n), 2);  // y: forward, reverse
+    MergeSide f{O.foff.as<uint32_t>(), O.farc.as<uint2>(), O.fmid.as<uint32_t>(),
+                ukey.as<uint64_t>(), nullptr, fb0, fb1, cnt2.as<uint32_t>(),
+                N.foff.as<uint32_t>(), N.farc.as<uint2>(), N.fmid.as<uint32_t>()};
+    MergeSide r{O.roff.as<uint32_t>(), O.rarc.as<uint2>(), O.rmid.as<uint32_t>(),
+                rkey.as<uint64_t>(), ridx.as<uint32_t>(), rb0, rb1, cnt3.as<uint32_t>(),
+                N.roff.as<uint32_t>(), N.rarc.as<uint2>(), N.rmid.as<uint32_t>()};
+    k_merge_rows<G, 0><<<gr, 256, 0, st>>>(O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(),
+                                           uw.as<uint32_t>(), umid.as<uint32_t>(), f, r);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
       e = scan3_u32(cnt2.as<uint32_t>(), N.foff.as<uint32_t>(), &dc()->c32[C_MF],
                     cnt3.as<uint32_t>(), N.roff.as<uint32_t>(), &dc()->c32[C_MR], nullptr,
                     nullptr, nullptr, O.n + 1, tmp, st);
     if (e == hipSuccess) {
-      k_merge_rows<G, 1><<<gr, 256, 0, st>>>(
-          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.foff.as<uint32_t>(),
-          O.farc.as<uint2>(), O.fmid.as<uint32_t>(), ukey.as<uint64_t>(), nullptr, fb0, fb1,
-          uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.foff.as<uint32_t>(),
-          N.farc.as<uint2>(), N.fmid.as<uint32_t>());
-      k_merge_rows<G, 1><<<gr, 256, 0, st>>>(
-          O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(), O.roff.as<uint32_t>(),
-          O.rarc.as<uint2>(), O.rmid.as<uint32_t>(), rkey.as<uint64_t>(), ridx.as<uint32_t>(),
-          rb0, rb1, uw.as<uint32_t>(), umid.as<uint32_t>(), nullptr, N.roff.as<uint32_t>(),
-          N.rarc.as<uint2>(), N.rmid.as<uint32_t>());
+      k_merge_rows<G, 1><<<gr, 256, 0, st>>>(O.n, kb, F.as<uint8_t>(), newid.as<uint32_t>(),
+                                             uw.as<uint32_t>(), umid.as<uint32_t>(), f, r);
       e = hipGetLastError();
     }
     if (e != hipSuccess) merge_err = hip_error(e, "overlay merge");
@@ -799,8 +790,8 @@ struct Builder {
                              tmp, st));
         k_eplus_reduce<<<grid(ne), 256, 0, st>>>(
             ekey.as<uint64_t>(), eidx.as<uint32_t>(), ne, eheads.as<uint32_t>(), dU,
-            ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(), ukey.as<uint64_t>(),
-            uw.as<uint32_t>(), umid.as<uint32_t>());
+            ew.as<uint32_t>(), elab.as<uint32_t>(), emid.as<uint32_t>(), kb, ukey.as<uint64_t>(),
+            uw.as<uint32_t>(), umid.as<uint32_t>(), rkey.as<uint64_t>());
         HIP_TRY(hipGetLastError());
         if (batch) {
           k_count_by_graph<<<grid(ne), 256, 0, st>>>(ukey.as<uint64_t>(), dU, kb,
@@ -808,16 +799,12 @@ struct Builder {
                                                      batch->shortcuts);
           HIP_TRY(hipGetLastError());
         }
-        // reverse order (v2, v1) over all ne entries; the U real keys sort
-        // in front of the padding
-        k_swap_key<<<grid(ne), 256, 0, st>>>(ukey.as<uint64_t>(), dU, ne, kb,
-                                             rkey.as<uint64_t>());
-        HIP_TRY(hipGetLastError());
+        // reverse order (v2, v1) over all ne entries (written by the
+        // reduction); the U real keys sort in front of the padding
         HIP_TRY(sort_u64_index(rkey.as<uint64_t>(), ridx.as<uint32_t>(), rkey_alt.as<uint64_t>(),
                                ridx_alt.as<uint32_t>(), ne, 2 * kb, tmp, st));
-        k_row_bounds<<<grid(ne), 256, 0, st>>>(ukey.as<uint64_t>(), dU, kb, fb0, fb1);
-        HIP_TRY(hipGetLastError());
-        k_row_bounds<<<grid(ne), 256, 0, st>>>(rkey.as<uint64_t>(), dU, kb, rb0, rb1);
+        k_row_bounds<<<dim3(grid(ne), 2), 256, 0, st>>>(ukey.as<uint64_t>(), rkey.as<uint64_t>(),
+                                                         dU, kb, fb0, fb1, rb0, rb1);
         HIP_TRY(hipGetLastError());
       }
 
@@ -863,9 +850,8 @@ struct Builder {
                                                       newid.as<uint32_t>(), N.roff.as<uint32_t>(),
                                                       N.rarc.as<uint2>(), wflag.as<uint8_t>());
       HIP_TRY(hipGetLastError());
-      HIP_TRY(select_flags(wflag.as<uint8_t>(), O.n, vw.as<uint32_t>(), &dc()->c32[C_UP], tmp, st));
-      HIP_TRY(select_flags(aflag_next.as<uint8_t>(), O.n, va.as<uint32_t>(), &dc()->c32[C_DN],
-                           tmp, st));
+      HIP_TRY(select_flags2(wflag.as<uint8_t>(), aflag_next.as<uint8_t>(), O.n, vw.as<uint32_t>(),
+                            va.as<uint32_t>(), &dc()->c32[C_UP], &dc()->c32[C_DN], tmp, st));
       // upper bound on the next round's memo inserts: in-degree x out-degree
       // summed over the affected vertices (rows past the new vertex count
       // are empty)

@@ -413,6 +413,43 @@ __global__ void __launch_bounds__(kSmallBlock) k_flag_select_small(const uint8_t
   if (threadIdx.x == 0) *count = tot;
 }
 
+// Two flag arrays at once: block 0 compacts (f0, out0, count0), block 1
+// (f1, out1, count1).
+__global__ void __launch_bounds__(kSmallBlock) k_flag_select_small2(
+    const uint8_t *__restrict__ f0, const uint8_t *__restrict__ f1, uint32_t n,
+    uint32_t *__restrict__ out0, uint32_t *__restrict__ out1, uint32_t *__restrict__ count0,
+    uint32_t *__restrict__ count1) {
+  const uint8_t *f = blockIdx.x ? f1 : f0;
+  uint32_t *out = blockIdx.x ? out1 : out0;
+  const uint32_t base = threadIdx.x * kSmallItems;
+  uint8_t v[kSmallItems];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kSmallItems; k++) {
+    v[k] = base + k < n ? f[base + k] : 0;
+    c += v[k] != 0;
+  }
+  uint32_t tot;
+  uint32_t pre = small_block_excl_scan<uint32_t>(c, &tot);
+#pragma unroll
+  for (int k = 0; k < kSmallItems; k++)
+    if (v[k]) out[pre++] = base + k;
+  if (threadIdx.x == 0) *(blockIdx.x ? count1 : count0) = tot;
+}
+
+hipError_t select_flags2(const uint8_t *f0, const uint8_t *f1, uint32_t n, uint32_t *out0,
+                         uint32_t *out1, uint32_t *count0, uint32_t *count1, DBuf &tmp,
+                         hipStream_t st) {
+  if (!count0 || !count1 || (n && (!f0 || !f1 || !out0 || !out1))) return hipErrorInvalidValue;
+  if (n <= kSmallN) {
+    k_flag_select_small2<<<2, kSmallBlock, 0, st>>>(f0, f1, n, out0, out1, count0, count1);
+    return hipGetLastError();
+  }
+  hipError_t e = select_flags(f0, n, out0, count0, tmp, st);
+  if (e != hipSuccess) return e;
+  return select_flags(f1, n, out1, count1, tmp, st);
+}
+
 hipError_t select_flags(const uint8_t *flags, uint32_t n, uint32_t *out, uint32_t *count,
                         DBuf &tmp, hipStream_t st) {
   if (!count || (n && (!flags || !out))) return hipErrorInvalidValue;

@@ -36,6 +36,10 @@ hipError_t scan_u64(const uint64_t *in, uint64_t *out, uint64_t n, uint64_t *tot
 // out[k] = i for the k-th i (ascending) with flags[i] != 0; *count_dev = k.
 hipError_t select_flags(const uint8_t *flags, uint32_t n, uint32_t *out, uint32_t *count_dev,
                         DBuf &tmp, hipStream_t st);
+// select_flags of two flag arrays of the same length (one launch when small).
+hipError_t select_flags2(const uint8_t *f0, const uint8_t *f1, uint32_t n, uint32_t *out0,
+                         uint32_t *out1, uint32_t *count0, uint32_t *count1, DBuf &tmp,
+                         hipStream_t st);
 
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 // Results end in keys/vals (the alt buffers are scratch of the same size).

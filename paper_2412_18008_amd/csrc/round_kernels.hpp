@@ -516,9 +516,15 @@ __global__ void k_keys(uint32_t n, const int32_t *__restrict__ P, const uint32_t
 
 // Row bounds of sorted (row << kb | col) keys: for every row r with keys,
 // first[r] = index of its first key and stop[r] = one past its last (rows
-// without keys keep 0, 0 from k_keys).
-__global__ void k_row_bounds(const uint64_t *__restrict__ keys, const uint32_t *nkeys, int kb,
-                             uint32_t *__restrict__ first, uint32_t *__restrict__ stop) {
+// without keys keep 0, 0 from k_keys).  blockIdx.y selects the key set:
+// (keys0, first0, stop0) or (keys1, first1, stop1).
+__global__ void k_row_bounds(const uint64_t *__restrict__ keys0,
+                             const uint64_t *__restrict__ keys1, const uint32_t *nkeys, int kb,
+                             uint32_t *__restrict__ first0, uint32_t *__restrict__ stop0,
+                             uint32_t *__restrict__ first1, uint32_t *__restrict__ stop1) {
+  const uint64_t *keys = blockIdx.y ? keys1 : keys0;
+  uint32_t *first = blockIdx.y ? first1 : first0;
+  uint32_t *stop = blockIdx.y ? stop1 : stop0;
   const uint32_t m = *nkeys;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
@@ -737,16 +743,24 @@ __global__ void __launch_bounds__(256) k_contract(
 }
 
 // After sorting the candidates by (v1, v2): one record per distinct pair
-// with the smallest (weight, label of the middle vertex).
+// with the smallest (weight, label of the middle vertex), and the pair's
+// key with its halves swapped, (v2 << kb) | v1, in rkey; rkey entries from
+// the pair count up to ne get UINT64_MAX (no key reaches it), so a sort of
+// all ne entries leaves the real keys in front.
 __global__ void k_eplus_reduce(const uint64_t *__restrict__ key, const uint32_t *__restrict__ idx,
                                uint32_t ne, const uint32_t *__restrict__ heads,
                                const uint32_t *nheads, const uint32_t *__restrict__ ew,
                                const uint32_t *__restrict__ elab, const uint32_t *__restrict__ emid,
-                               uint64_t *__restrict__ ukey, uint32_t *__restrict__ uw,
-                               uint32_t *__restrict__ umid) {
+                               int kb, uint64_t *__restrict__ ukey, uint32_t *__restrict__ uw,
+                               uint32_t *__restrict__ umid, uint64_t *__restrict__ rkey) {
   const uint32_t nh = *nheads;
+  const uint64_t lowmask = (1ull << kb) - 1ull;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nh; k += stride) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += stride) {
+    if (k >= nh) {
+      rkey[k] = ~0ull;
+      continue;
+    }
     const uint32_t i = heads[k];
     const uint64_t kk = key[i];
     uint32_t bi = idx[i];
@@ -762,6 +776,7 @@ __global__ void k_eplus_reduce(const uint64_t *__restrict__ key, const uint32_t 
     ukey[k] = kk;
     uw[k] = bw;
     umid[k] = emid[bi];
+    rkey[k] = ((kk & lowmask) << kb) | (kk >> kb);
   }
 }
 
@@ -984,15 +999,42 @@ __device__ uint32_t merge_row_serial(uint32_t a, uint32_t a1, uint32_t b, uint32
 // old arcs to neighbours below v and the shortcuts before it, less those
 // that share a neighbour.  The live-arc prefix of the old row is kept in
 // LDS; rows longer than the group's share take the sequential merge.
+// One direction of the rebuild: old CSR (off, arc, mid), its shortcut rows
+// (keys ekey, record map eidx or null, bounds rfirst/rstop), row counts cnt
+// (MODE 0) or the new CSR (noff, narc, nmid; MODE 1).
+struct MergeSide {
+  const uint32_t *off;
+  const uint2 *arc;
+  const uint32_t *mid;
+  const uint64_t *ekey;
+  const uint32_t *eidx;
+  const uint32_t *rfirst, *rstop;
+  uint32_t *cnt;
+  const uint32_t *noff;
+  uint2 *narc;
+  uint32_t *nmid;
+};
+
+// blockIdx.y selects the direction: 0 = fwd, 1 = rev.
 template <int G, int MODE>
-__global__ void __launch_bounds__(256) k_merge_rows(
-    uint32_t n, int kb, const uint8_t *__restrict__ F, const uint32_t *__restrict__ newid,
-    const uint32_t *__restrict__ off, const uint2 *__restrict__ arc,
-    const uint32_t *__restrict__ mid, const uint64_t *__restrict__ ekey,
-    const uint32_t *__restrict__ eidx, const uint32_t *__restrict__ rfirst,
-    const uint32_t *__restrict__ rstop, const uint32_t *__restrict__ uw,
-    const uint32_t *__restrict__ umid, uint32_t *__restrict__ cnt,
-    const uint32_t *__restrict__ noff, uint2 *__restrict__ narc, uint32_t *__restrict__ nmid) {
+__global__ void __launch_bounds__(256) k_merge_rows(uint32_t n, int kb,
+                                                    const uint8_t *__restrict__ F,
+                                                    const uint32_t *__restrict__ newid,
+                                                    const uint32_t *__restrict__ uw,
+                                                    const uint32_t *__restrict__ umid,
+                                                    MergeSide fwd, MergeSide rev) {
+  const MergeSide &side = blockIdx.y ? rev : fwd;
+  const uint32_t *__restrict__ off = side.off;
+  const uint2 *__restrict__ arc = side.arc;
+  const uint32_t *__restrict__ mid = side.mid;
+  const uint64_t *__restrict__ ekey = side.ekey;
+  const uint32_t *__restrict__ eidx = side.eidx;
+  const uint32_t *__restrict__ rfirst = side.rfirst;
+  const uint32_t *__restrict__ rstop = side.rstop;
+  uint32_t *__restrict__ cnt = side.cnt;
+  const uint32_t *__restrict__ noff = side.noff;
+  uint2 *__restrict__ narc = side.narc;
+  uint32_t *__restrict__ nmid = side.nmid;
   constexpr uint32_t kGroups = 256 / G;
   constexpr uint32_t kCap = 4096 / kGroups;  // live-arc prefix entries per group
   __shared__ uint16_t s_live[4096];
