@@ -117,7 +117,11 @@ typedef struct {
    * distances of all its pairs are computed once (contraction keeps them
    * unchanged for the rest of the build) and every later witness search is
    * answered from that table.  0 = 2048; CH_DENSE_TAIL_OFF keeps the
-   * searches; at most 4096.  Changes speed only, never results. */
+   * searches; at most 4096.  With the plain priority, one graph and no
+   * recorded features, those rounds run as a device-driven sequence of
+   * launches (CH_LS_TAIL; its scratch is about 24 bytes per vertex pair of
+   * the table, e.g. 100 MB at 2048 vertices).  Changes speed only, never
+   * results. */
   uint32_t dense_tail;
 } ch_params_t;
 #define CH_DENSE_TAIL_OFF 1u
@@ -139,6 +143,10 @@ typedef struct {
 #define CH_PRIO_LEARNED 1u
 #define CH_MLP_PARAMS 4801
 #define CH_F_RECORD_FEATURES 0x8u /* keep each vertex's features at contraction */
+#define CH_F_TAIL_STEPWISE 0x10u  /* table rounds: one launch per step and a host round
+                                    * trip per round, as in the earlier rounds (the
+                                    * default runs them as one device-driven sequence;
+                                    * same results) */
 
 #define CH_MLP_ON_DEVICE 0x1u     /* x, t, y, prio are device pointers */
 #define CH_MLP_BF16 0x2u          /* forward with bf16 weights and activations */
@@ -156,6 +164,7 @@ typedef struct {
 #define CH_LS_64x512 3u
 #define CH_LS_64x2048 4u
 #define CH_LS_TABLE 5u  /* round stats only: searches answered from the all-pairs table */
+#define CH_LS_TAIL 6u   /* round stats only: table rounds run as one device-driven sequence */
 
 typedef struct ch_s ch_t;
 

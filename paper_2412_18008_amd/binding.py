@@ -58,6 +58,7 @@ class Params(C.Structure):
 CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
 CH_MLP_PARAMS = 4801
 CH_F_RECORD_FEATURES = 0x8
+CH_F_TAIL_STEPWISE = 0x10
 CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
 
 
@@ -85,7 +86,7 @@ class MlpTrainParams(C.Structure):
 CH_LS_AUTO, CH_LS_16x128, CH_LS_32x512, CH_LS_64x512, CH_LS_64x2048 = 0, 1, 2, 3, 4
 LS_KERNELS = {1: "k_local_search<16, 128>", 2: "k_local_search<32, 512>",
               3: "k_local_search<64, 512>", 4: "k_local_search<64, 2048>",
-              5: "k_ls_table"}
+              5: "k_ls_table", 6: "k_tail_search"}
 CH_DENSE_TAIL_OFF = 1
 
 
@@ -254,9 +255,10 @@ class CH:
 
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
-          record=False, hop=0, dense_tail=0):
+          record=False, hop=0, dense_tail=0, tail_stepwise=False):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
-    selects the hop-bounded witness search with walks of at most `hop` arcs."""
+    selects the hop-bounded witness search with walks of at most `hop` arcs;
+    tail_stepwise runs the table rounds one launch per step."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
     pd, kd = _ptr(dst, np.uint32)
@@ -266,7 +268,8 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     m = dst.numel() if dev else len(kd)
     g = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (CH_F_STATS if stats else 0) | (
-        0 if query_index else CH_F_NO_QUERY_INDEX) | (CH_F_RECORD_FEATURES if record else 0)
+        0 if query_index else CH_F_NO_QUERY_INDEX) | (CH_F_RECORD_FEATURES if record else 0) | (
+        CH_F_TAIL_STEPWISE if tail_stepwise else 0)
     if stream is None and dev:
         import torch
 

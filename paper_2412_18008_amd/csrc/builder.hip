@@ -12,6 +12,7 @@
 #include "mlp.hpp"
 #include "round_kernels.hpp"
 #include "dense_tail.hpp"
+#include "tail.hpp"
 
 namespace sp {
 
@@ -95,6 +96,12 @@ struct Builder {
   DBuf tab_D, tab_pos, tab_gid, tab_posl;
   bool tab_on = false;
   uint32_t tab_N = 0, tab_n0 = 0;
+  // device-driven tail (tail.hpp): bitmaps, W / MID, lists, list lengths,
+  // SC, touched pairs, per-vertex arrays, flags, vertex lists, state, records
+  DBuf t_bits, t_W, t_MID, t_ol, t_il, t_len, t_SC, t_touch, t_vert, t_flags, t_lists, t_ctr,
+      t_rec;
+  TailCtr *h_tail = nullptr;  // pinned, two copies (one per batch parity)
+  hipEvent_t ev_tail[2] = {nullptr, nullptr};
   DBuf dctr, tmp;
   DevCtr *hctr = nullptr;  // pinned
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -118,9 +125,14 @@ struct Builder {
                    &vw, &va, &vf, &cnt2, &cnt3, &rowb, &memo, &memo_spare, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
                    &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
-                   &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid, &tab_posl};
+                   &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid, &tab_posl,
+                   &t_bits, &t_W, &t_MID, &t_ol, &t_il, &t_len, &t_SC, &t_touch, &t_vert,
+                   &t_flags, &t_lists, &t_ctr, &t_rec};
     for (DBuf *b : all) b->release();
     if (hctr) (void)hipHostFree(hctr);
+    if (h_tail) (void)hipHostFree(h_tail);
+    for (auto &e : ev_tail)
+      if (e) (void)hipEventDestroy(e);
     for (auto &e : ev)
       if (e) (void)hipEventDestroy(e);
     if (ev_rb) (void)hipEventDestroy(ev_rb);
@@ -400,6 +412,197 @@ struct Builder {
     return CH_OK;
   }
 
+  // The rest of the build on the table positions (tail.hpp): eight launches
+  // per round, rounds enqueued kTailBatch at a time, the state read back
+  // once per batch while the next batch runs.  Entered at the start of a
+  // round, right after the table is built (positions = current local ids);
+  // nw: this round's source count.
+  static constexpr uint32_t kTailBatch = 8;
+
+  int run_tail(uint32_t &round, uint32_t nw) {
+    OvBuf &O = ov[cur];
+    const uint32_t n0 = O.n;
+    if (n0 == 0 || n0 > kTailMaxN || n0 != tab_n0)
+      return set_error(CH_E_DEVICE, "tail entered without a matching table (internal error)");
+    const bool stats = prm.flags & CH_F_STATS;
+    const uint32_t rw = (n0 + 31) / 32;
+    const size_t nn = (size_t)n0 * n0;
+    // every vertex pair gives at most one upward and one downward CH arc
+    const uint64_t pairs = (uint64_t)n0 * (n0 - 1) / 2 + 1;
+    DBuf *ub[] = {&ch->up_t, &ch->up_h, &ch->up_w, &ch->up_m, &ch->dn_t, &ch->dn_h, &ch->dn_w,
+                  &ch->dn_m};
+    if (ch->nup + pairs > up_cap) {
+      const uint64_t nc = ch->nup + pairs;
+      for (int i = 0; i < 4; i++) TRY(grow_copy(*ub[i], ch->nup * 4, nc * 4));
+      up_cap = nc;
+    }
+    if (ch->ndown + pairs > dn_cap) {
+      const uint64_t nc = ch->ndown + pairs;
+      for (int i = 4; i < 8; i++) TRY(grow_copy(*ub[i], ch->ndown * 4, nc * 4));
+      dn_cap = nc;
+    }
+    HIP_TRY(t_bits.ensure(3 * (size_t)n0 * rw * 4));
+    HIP_TRY(t_W.ensure(nn * 4));
+    HIP_TRY(t_MID.ensure(nn * 4));
+    HIP_TRY(t_ol.ensure(nn * 2));
+    HIP_TRY(t_il.ensure(nn * 2));
+    HIP_TRY(t_SC.ensure(nn * 8));
+    HIP_TRY(t_touch.ensure(nn * 4));
+    HIP_TRY(t_len.ensure(2 * (size_t)n0 * 4));
+    HIP_TRY(t_vert.ensure(5 * (size_t)n0 * 4));
+    HIP_TRY(t_flags.ensure(4 * (size_t)n0 * 4));
+    HIP_TRY(t_lists.ensure(5 * (size_t)n0 * 2));
+    HIP_TRY(t_ctr.ensure(sizeof(TailCtr)));
+    HIP_TRY(t_rec.ensure((size_t)n0 * sizeof(TailRound)));
+    if (!h_tail) HIP_TRY(hipHostMalloc((void **)&h_tail, 2 * sizeof(TailCtr), hipHostMallocDefault));
+    for (auto &e : ev_tail)
+      if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    TailArgs A;
+    A.n0 = n0;
+    A.rw = rw;
+    A.D = tab_D.as<uint32_t>();
+    A.N = tab_N;
+    A.gidp = tab_gid.as<uint32_t>();
+    uint32_t *vtx = t_vert.as<uint32_t>();
+    A.lab = vtx;
+    A.lrank = vtx + n0;
+    A.plr = vtx + 2 * (size_t)n0;
+    A.P = (int32_t *)(vtx + 3 * (size_t)n0);
+    A.alive = vtx + 4 * (size_t)n0;
+    A.ob = t_bits.as<uint32_t>();
+    A.ib = A.ob + (size_t)n0 * rw;
+    A.eb = A.ib + (size_t)n0 * rw;
+    A.W = t_W.as<uint32_t>();
+    A.MID = t_MID.as<uint32_t>();
+    A.ol = t_ol.as<uint16_t>();
+    A.il = t_il.as<uint16_t>();
+    A.olen = t_len.as<uint32_t>();
+    A.ilen = A.olen + n0;
+    A.SC = t_SC.as<unsigned long long>();
+    A.touched = t_touch.as<uint32_t>();
+    uint32_t *fl = t_flags.as<uint32_t>();
+    A.af0 = fl;
+    A.af1 = fl + n0;
+    A.wf0 = fl + 2 * (size_t)n0;
+    A.wf1 = fl + 3 * (size_t)n0;
+    uint16_t *ls = t_lists.as<uint16_t>();
+    A.la0 = ls;
+    A.la1 = ls + n0;
+    A.lw0 = ls + 2 * (size_t)n0;
+    A.lw1 = ls + 3 * (size_t)n0;
+    A.lf = ls + 4 * (size_t)n0;
+    A.C = t_ctr.as<TailCtr>();
+    A.err = &dc()->err;
+    HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
+    HIP_TRY(hipMemsetAsync(t_ctr.p, 0, sizeof(TailCtr), st));
+    k_tail_clear<<<grid(nn), 256, 0, st>>>(A);
+    HIP_TRY(hipGetLastError());
+    k_tail_load<<<grid(n0), 256, 0, st>>>(A, view(O), O.P.as<int32_t>(), aflag.as<uint8_t>(),
+                                          vw.as<uint32_t>(), nw, ch->label.as<uint32_t>());
+    HIP_TRY(hipGetLastError());
+    if (mcap) {
+      k_tail_memo<<<grid(mcap), 256, 0, st>>>(A, memo.as<MemoSlot>(), mcap,
+                                               alive_g.as<uint8_t>(), tab_pos.as<uint32_t>());
+      HIP_TRY(hipGetLastError());
+    }
+    k_tail_lrank<<<grid(n0), 256, 0, st>>>(A);
+    HIP_TRY(hipGetLastError());
+
+    ArcOut up{ch->up_t.as<uint32_t>(), ch->up_h.as<uint32_t>(), ch->up_w.as<uint32_t>(),
+              ch->up_m.as<uint32_t>()};
+    ArcOut dn{ch->dn_t.as<uint32_t>(), ch->dn_h.as<uint32_t>(), ch->dn_w.as<uint32_t>(),
+              ch->dn_m.as<uint32_t>()};
+    const uint32_t max_r = prm.max_rounds ? prm.max_rounds - round : 0xFFFFFFFFu;
+    TailRound *rec = t_rec.as<TailRound>();
+    uint32_t live = n0;  // last known live count (sizes the grids)
+    uint32_t r = 0, batches = 0;
+    bool stop = false;
+    while (!stop) {
+      // one wave per item; items never exceed the live count at the batch start
+      const unsigned wg = grid((uint64_t)std::max<uint32_t>(live, 1) * kWave, kTailBlock);
+      for (uint32_t b = 0; b < kTailBatch; b++, r++) {
+        const uint32_t c = r & 1u;
+        k_tail_search<<<wg, kTailBlock, 0, st>>>(A, c);
+        k_tail_score<<<wg, kTailBlock, 0, st>>>(A, c);
+        k_tail_select<<<wg, kTailBlock, 0, st>>>(A);
+        k_tail_contract<<<wg, kTailBlock, 0, st>>>(A, c, round + r, up, dn, ch->nup, ch->ndown,
+                                                   up_cap, dn_cap, ch->level.as<uint32_t>(),
+                                                   ch->score.as<int32_t>(), alive_g.as<uint8_t>());
+        k_tail_compact<<<wg, kTailBlock, 0, st>>>(A, c);
+        k_tail_merge<<<wg, kTailBlock, 0, st>>>(A);
+        k_tail_next<<<wg, kTailBlock, 0, st>>>(A, c);
+        k_tail_end<<<1, 1024, 0, st>>>(A, c, max_r, rec);
+      }
+      HIP_TRY(hipGetLastError());
+      const int slot = batches & 1;
+      HIP_TRY(hipMemcpyAsync(&h_tail[slot], t_ctr.p, sizeof(TailCtr), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipEventRecord(ev_tail[slot], st));
+      batches++;
+      // the previous batch's state (this batch runs meanwhile); after the
+      // first batch, wait for it directly
+      const int prev = batches >= 2 ? (slot ^ 1) : slot;
+      hipError_t e;
+      while ((e = hipEventQuery(ev_tail[prev])) == hipErrorNotReady) {
+      }
+      HIP_TRY(e);
+      live = h_tail[prev].live;
+      stop = h_tail[prev].done != 0;
+      if (!stop && r > n0 + 4 * kTailBatch)
+        return set_error(CH_E_DEVICE, "tail did not finish (internal error)");
+    }
+    // the newest copy holds the final state (later launches return at once)
+    const int last = (batches - 1) & 1;
+    {
+      hipError_t e;
+      while ((e = hipEventQuery(ev_tail[last])) == hipErrorNotReady) {
+      }
+      HIP_TRY(e);
+    }
+    const TailCtr T = h_tail[last];
+    TRY(readback());
+    TRY(check_err());
+    std::vector<TailRound> recs(T.rounds);
+    if (T.rounds)
+      HIP_TRY(hipMemcpy(recs.data(), rec, (size_t)T.rounds * sizeof(TailRound),
+                        hipMemcpyDeviceToHost));
+    int khz = 0;
+    if (stats) {
+      HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ch->device));
+    }
+    for (uint32_t i = 0; i < T.rounds; i++) {
+      const TailRound &x = recs[i];
+      ch_round_stats_t rs{};
+      rs.alive_before = x.alive_before;
+      rs.n_sources = x.n_sources;
+      rs.n_affected = x.n_affected;
+      rs.n_selected = x.n_selected;
+      rs.n_targets = x.n_targets;
+      rs.n_pruned = x.n_pruned;
+      rs.n_shortcuts = x.n_shortcuts;
+      rs.overlay_arcs = x.overlay_arcs;
+      rs.rows_expanded = x.rows;
+      rs.arcs_scanned = x.arcs;
+      rs.memo_probes = x.probes;
+      rs.memo_inserts = x.n_targets;
+      rs.ls_tier1 = CH_LS_TAIL;
+      const unsigned long long c0 = i ? recs[i - 1].clk : T.clk0;
+      if (stats && khz > 0) rs.ms_total = (float)((double)(x.clk - c0) / khz);
+      mcount += x.n_targets;
+      ch->stats.push_back(rs);
+    }
+    ch->nup += T.up_n;
+    ch->ndown += T.dn_n;
+    round += T.rounds;
+    if (T.live) {
+      if (prm.max_rounds && round >= prm.max_rounds)
+        return set_error(CH_E_LIMIT, "max_rounds reached before every vertex was contracted");
+      return set_error(CH_E_DEVICE, "tail stopped with live vertices (internal error)");
+    }
+    O.n = 0;
+    O.m = 0;
+    return CH_OK;
+  }
+
   // At most max_per_cu one-wave blocks per CU, and no more than the CU's
   // 160 KB of LDS holds (hop mode adds a second distance array to every
   // table).
@@ -597,6 +800,19 @@ struct Builder {
       if (stats) HIP_TRY(hipEventRecord(ev[1], st));
       const double avgdeg = O.n ? (double)O.m / O.n : 0.0;
 
+      // exact mode, plain priority, one graph: once the overlay fits the
+      // all-pairs table, the remaining rounds run on the device (tail.hpp)
+      {
+        const uint32_t lim = prm.dense_tail == 0 ? 2048u : prm.dense_tail;
+        const bool fused = prm.wps_mode == CH_WPS_EXACT && prm.dense_tail != CH_DENSE_TAIL_OFF &&
+                           prm.priority == CH_PRIO_PLAIN && !batch &&
+                           !(prm.flags & (CH_F_RECORD_FEATURES | CH_F_TAIL_STEPWISE));
+        if (fused && !tab_on && O.n && O.n <= lim && O.n <= kTailMaxN) {
+          TRY(build_table(v));
+          TRY(run_tail(round, nw));
+          break;
+        }
+      }
       // ---- Step 1: LocalSearch (Alg. 3) --------------------------------
       // memo capacity for this round's inserts (bound computed with the
       // previous round's final readback)

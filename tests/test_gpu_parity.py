@@ -339,15 +339,20 @@ def test_dense_tail_table(gpu):
         lab = synth.labels(n, 23)
         o = oracle.OracleCH(off, dst, w, labels=lab).run()
         a = oracle_export(o)
-        for tail in (4096, 64, gpu.CH_DENSE_TAIL_OFF):
-            ch = gpu.build(off, dst, w, labels=lab, stats=True, dense_tail=tail)
-            assert_same_ch(a, gpu_export(ch), f"{name} tail={tail}")
-            assert gpu_round_counts(ch) == oracle_round_counts(o), f"{name} tail={tail}"
+        for tail, stepwise in ((4096, False), (4096, True), (64, False), (64, True),
+                               (gpu.CH_DENSE_TAIL_OFF, False)):
+            ctx = f"{name} tail={tail} stepwise={stepwise}"
+            print(f"[parity] {ctx}", flush=True)
+            ch = gpu.build(off, dst, w, labels=lab, stats=True, dense_tail=tail,
+                           tail_stepwise=stepwise)
+            assert_same_ch(a, gpu_export(ch), ctx)
+            assert gpu_round_counts(ch) == oracle_round_counts(o), ctx
             kinds = {r["ls_tier1"] for r in ch.round_stats() if r["n_sources"]}
+            table_kind = 5 if stepwise else 6
             if tail == gpu.CH_DENSE_TAIL_OFF:
-                assert 5 not in kinds
+                assert not kinds & {5, 6}, ctx
             elif n <= tail:
-                assert kinds == {5}, (name, kinds)
+                assert kinds <= {table_kind}, (ctx, kinds)
 
 
 def test_dense_tail_learned_and_batch(gpu):
