@@ -147,6 +147,10 @@ typedef struct {
                                     * trip per round, as in the earlier rounds (the
                                     * default runs them as one device-driven sequence;
                                     * same results) */
+#define CH_F_KEEP_ORDER 0x20u  /* build on the input's vertex numbering (the default
+                                * renumbers graphs of 4096 or more vertices into
+                                * clusters of nearby vertices first and maps the
+                                * result back; same results) */
 
 #define CH_MLP_ON_DEVICE 0x1u     /* x, t, y, prio are device pointers */
 #define CH_MLP_BF16 0x2u          /* forward with bf16 weights and activations */

@@ -59,6 +59,7 @@ CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
 CH_MLP_PARAMS = 4801
 CH_F_RECORD_FEATURES = 0x8
 CH_F_TAIL_STEPWISE = 0x10
+CH_F_KEEP_ORDER = 0x20
 CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
 
 
@@ -255,10 +256,11 @@ class CH:
 
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
-          record=False, hop=0, dense_tail=0, tail_stepwise=False):
+          record=False, hop=0, dense_tail=0, tail_stepwise=False, keep_order=False):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
     selects the hop-bounded witness search with walks of at most `hop` arcs;
-    tail_stepwise runs the table rounds one launch per step."""
+    tail_stepwise runs the table rounds one launch per step; keep_order
+    builds on the input's numbering (no locality renumbering)."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
     pd, kd = _ptr(dst, np.uint32)
@@ -269,7 +271,7 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     g = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (CH_F_STATS if stats else 0) | (
         0 if query_index else CH_F_NO_QUERY_INDEX) | (CH_F_RECORD_FEATURES if record else 0) | (
-        CH_F_TAIL_STEPWISE if tail_stepwise else 0)
+        CH_F_TAIL_STEPWISE if tail_stepwise else 0) | (CH_F_KEEP_ORDER if keep_order else 0)
     if stream is None and dev:
         import torch
 

@@ -101,6 +101,10 @@ struct Builder {
   DBuf t_bits, t_W, t_MID, t_ol, t_il, t_len, t_SC, t_touch, t_vert, t_flags, t_lists, t_ctr,
       t_rec;
   TailCtr *h_tail = nullptr;  // pinned, two copies (one per batch parity)
+  // locality order: r_order[new] = input id, r_inv[input id] = new; the
+  // input-order labels wait in r_lab until the build is mapped back
+  bool renum = false;
+  DBuf r_order, r_inv, r_a, r_b, r_c, r_key, r_key_alt, r_val_alt, r_lab;
   hipEvent_t ev_tail[2] = {nullptr, nullptr};
   DBuf dctr, tmp;
   DevCtr *hctr = nullptr;  // pinned
@@ -127,7 +131,8 @@ struct Builder {
                    &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
                    &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid, &tab_posl,
                    &t_bits, &t_W, &t_MID, &t_ol, &t_il, &t_len, &t_SC, &t_touch, &t_vert,
-                   &t_flags, &t_lists, &t_ctr, &t_rec};
+                   &t_flags, &t_lists, &t_ctr, &t_rec, &r_order, &r_inv, &r_a, &r_b, &r_c,
+                   &r_key, &r_key_alt, &r_val_alt, &r_lab};
     for (DBuf *b : all) b->release();
     if (hctr) (void)hipHostFree(hctr);
     if (h_tail) (void)hipHostFree(h_tail);
@@ -229,9 +234,15 @@ struct Builder {
     }
     if (first != 0 || last != m)
       return set_error(CH_E_INVALID, "offsets[0] must be 0 and offsets[n] must equal m");
+    // locality order: the build runs on a renumbering that keeps clusters of
+    // nearby vertices together (one graph; not with recorded features)
+    renum = !batch && n >= kRenumberMin && m &&
+            !(prm.flags & (CH_F_RECORD_FEATURES | CH_F_KEEP_ORDER));
+    if (renum) TRY(locality_order(off, dst, m));
     if (m) {
       k_ingest_keys<<<grid(n), 256, 0, st>>>(n, m, kb, off, dst, w, ekey.as<uint64_t>(),
-                                             ew.as<uint32_t>(), &dc()->bad);
+                                             ew.as<uint32_t>(), &dc()->bad,
+                                             renum ? r_inv.as<uint32_t>() : nullptr);
       HIP_TRY(hipGetLastError());
       HIP_TRY(radix_sort_u64(ekey.as<uint64_t>(), ew.as<uint32_t>(), ekey_alt.as<uint64_t>(),
                              elab.as<uint32_t>(), m32, 2 * kb, tmp, st));
@@ -305,6 +316,81 @@ struct Builder {
       k_default_labels<<<grid(n), 256, 0, st>>>(n, mix, ch->label.as<uint32_t>());
       HIP_TRY(hipGetLastError());
     }
+    if (renum) {  // labels in the build's order; the input-order ones wait in r_lab
+      HIP_TRY(r_lab.ensure((size_t)n * 4));
+      k_permute_u32<<<grid(n), 256, 0, st>>>(n, r_order.as<uint32_t>(), ch->label.as<uint32_t>(),
+                                             r_lab.as<uint32_t>(), 0);
+      HIP_TRY(hipGetLastError());
+      std::swap(ch->label, r_lab);
+    }
+    return CH_OK;
+  }
+
+  // Locality order of the input graph (device arrays off, dst): sixteen
+  // steps of min-label propagation along the arcs, starting from the vertex
+  // ids; the labels after four steps (fine clusters) and after sixteen
+  // (coarse) give each vertex the key (coarse, fine), and the stable sort of
+  // the keys is the new order.  Changes speed only: every decision of the
+  // build depends on labels and distances, never on the numbering, and the
+  // results are mapped back to the input's ids.
+  static constexpr uint32_t kRenumberMin = 4096;
+  static constexpr int kFineSteps = 4, kCoarseSteps = 16;
+
+  int locality_order(const uint64_t *off, const uint32_t *dst, uint64_t m) {
+    const size_t nb = (size_t)n * 4;
+    HIP_TRY(r_order.ensure(nb));
+    HIP_TRY(r_inv.ensure(nb));
+    HIP_TRY(r_a.ensure(nb));
+    HIP_TRY(r_b.ensure(nb));
+    HIP_TRY(r_c.ensure(nb));
+    HIP_TRY(r_key.ensure((size_t)n * 8));
+    HIP_TRY(r_key_alt.ensure((size_t)n * 8));
+    HIP_TRY(r_val_alt.ensure(nb));
+    uint32_t *A = r_a.as<uint32_t>(), *B = r_b.as<uint32_t>();
+    HIP_TRY(iota_u32(A, n, st));
+    for (int k = 1; k <= kCoarseSteps; k++) {
+      // after the fine steps the labels go to r_c and stay there
+      uint32_t *out = k == kFineSteps ? r_c.as<uint32_t>() : B;
+      k_minlabel_step<<<grid(n), 256, 0, st>>>(n, m, off, dst, A, out);
+      HIP_TRY(hipGetLastError());
+      if (k == kFineSteps) {
+        HIP_TRY(hipMemcpyAsync(A, out, nb, hipMemcpyDeviceToDevice, st));
+      } else {
+        std::swap(A, B);
+      }
+    }
+    const int kb = bits_for(n);
+    k_order_keys<<<grid(n), 256, 0, st>>>(n, kb, A, r_c.as<uint32_t>(), r_key.as<uint64_t>());
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(sort_u64_index(r_key.as<uint64_t>(), r_order.as<uint32_t>(),
+                           r_key_alt.as<uint64_t>(), r_val_alt.as<uint32_t>(), n, 2 * kb, tmp,
+                           st));
+    HIP_TRY(iota_u32(r_a.as<uint32_t>(), n, st));
+    k_permute_u32<<<grid(n), 256, 0, st>>>(n, r_order.as<uint32_t>(), r_a.as<uint32_t>(),
+                                           r_inv.as<uint32_t>(), 1);
+    HIP_TRY(hipGetLastError());
+    return CH_OK;
+  }
+
+  // The finished build back in the input's ids: level and score per vertex,
+  // the labels, and the ends and middle vertices of the CH arcs.
+  int restore_order() {
+    const uint32_t *ord = r_order.as<uint32_t>();
+    for (DBuf *b : {&ch->level, &ch->score}) {
+      HIP_TRY(r_a.ensure((size_t)n * 4));
+      k_permute_u32<<<grid(n), 256, 0, st>>>(n, ord, b->as<uint32_t>(), r_a.as<uint32_t>(), 1);
+      HIP_TRY(hipGetLastError());
+      std::swap(*b, r_a);
+    }
+    std::swap(ch->label, r_lab);
+    DBuf *arcs[] = {&ch->up_t, &ch->up_h, &ch->up_m, &ch->dn_t, &ch->dn_h, &ch->dn_m};
+    for (int i = 0; i < 6; i++) {
+      const uint64_t cnt = i < 3 ? ch->nup : ch->ndown;
+      if (!cnt) continue;
+      k_map_ids<<<grid(cnt), 256, 0, st>>>(cnt, arcs[i]->as<uint32_t>(), ord);
+      HIP_TRY(hipGetLastError());
+    }
+    renum = false;
     return CH_OK;
   }
 
@@ -412,7 +498,7 @@ struct Builder {
     return CH_OK;
   }
 
-  // The rest of the build on the table positions (tail.hpp): eight launches
+  // The rest of the build on the table positions (tail.hpp): five launches
   // per round, rounds enqueued kTailBatch at a time, the state read back
   // once per batch while the next batch runs.  Entered at the start of a
   // round, right after the table is built (positions = current local ids);
@@ -450,8 +536,8 @@ struct Builder {
     HIP_TRY(t_touch.ensure(nn * 4));
     HIP_TRY(t_len.ensure(2 * (size_t)n0 * 4));
     HIP_TRY(t_vert.ensure(5 * (size_t)n0 * 4));
-    HIP_TRY(t_flags.ensure(4 * (size_t)n0 * 4));
-    HIP_TRY(t_lists.ensure(5 * (size_t)n0 * 2));
+    HIP_TRY(t_flags.ensure(5 * (size_t)n0 * 4));
+    HIP_TRY(t_lists.ensure(4 * (size_t)n0 * 2));
     HIP_TRY(t_ctr.ensure(sizeof(TailCtr)));
     HIP_TRY(t_rec.ensure((size_t)n0 * sizeof(TailRound)));
     if (!h_tail) HIP_TRY(hipHostMalloc((void **)&h_tail, 2 * sizeof(TailCtr), hipHostMallocDefault));
@@ -485,12 +571,12 @@ struct Builder {
     A.af1 = fl + n0;
     A.wf0 = fl + 2 * (size_t)n0;
     A.wf1 = fl + 3 * (size_t)n0;
+    A.sflag = fl + 4 * (size_t)n0;
     uint16_t *ls = t_lists.as<uint16_t>();
     A.la0 = ls;
     A.la1 = ls + n0;
     A.lw0 = ls + 2 * (size_t)n0;
     A.lw1 = ls + 3 * (size_t)n0;
-    A.lf = ls + 4 * (size_t)n0;
     A.C = t_ctr.as<TailCtr>();
     A.err = &dc()->err;
     HIP_TRY(hipMemsetAsync(dctr.p, 0, sizeof(DevCtr), st));
@@ -524,14 +610,11 @@ struct Builder {
         const uint32_t c = r & 1u;
         k_tail_search<<<wg, kTailBlock, 0, st>>>(A, c);
         k_tail_score<<<wg, kTailBlock, 0, st>>>(A, c);
-        k_tail_select<<<wg, kTailBlock, 0, st>>>(A);
-        k_tail_contract<<<wg, kTailBlock, 0, st>>>(A, c, round + r, up, dn, ch->nup, ch->ndown,
-                                                   up_cap, dn_cap, ch->level.as<uint32_t>(),
-                                                   ch->score.as<int32_t>(), alive_g.as<uint8_t>());
+        k_tail_selcon<<<wg, kTailBlock, 0, st>>>(A, c, round + r, up, dn, ch->nup, ch->ndown,
+                                                 up_cap, dn_cap, ch->level.as<uint32_t>(),
+                                                 ch->score.as<int32_t>(), alive_g.as<uint8_t>());
         k_tail_compact<<<wg, kTailBlock, 0, st>>>(A, c);
-        k_tail_merge<<<wg, kTailBlock, 0, st>>>(A);
-        k_tail_next<<<wg, kTailBlock, 0, st>>>(A, c);
-        k_tail_end<<<1, 1024, 0, st>>>(A, c, max_r, rec);
+        k_tail_merge_end<<<wg, kTailBlock, 0, st>>>(A, c, max_r, rec, n0);
       }
       HIP_TRY(hipGetLastError());
       const int slot = batches & 1;
@@ -1107,6 +1190,7 @@ struct Builder {
       round++;
     }
     ch->rounds = round;
+    if (renum) TRY(restore_order());
     return CH_OK;
   }
 };

@@ -16,10 +16,11 @@ namespace sp {
 
 // key = (tail << kb) | head for every input arc; self-loops get the
 // sentinel SP_EMPTY64 (sorted last, dropped).  Also validates the input.
+// With `inv` (new id of each input vertex), the keys are in the new ids.
 __global__ void k_ingest_keys(uint32_t n, uint64_t m, int kb, const uint64_t *__restrict__ off,
                               const uint32_t *__restrict__ dst, const uint32_t *__restrict__ w,
                               uint64_t *__restrict__ key, uint32_t *__restrict__ val,
-                              uint32_t *__restrict__ bad) {
+                              uint32_t *__restrict__ bad, const uint32_t *__restrict__ inv) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
     const uint64_t a = off[u], b = off[u + 1];
@@ -30,9 +31,63 @@ __global__ void k_ingest_keys(uint32_t n, uint64_t m, int kb, const uint64_t *__
     for (uint64_t e = a; e < b; e++) {
       const uint32_t v = dst[e], ww = w[e];
       if (v >= n || ww == SP_INF32) atomicOr(bad, 2u);
-      key[e] = (v == u || v >= n) ? SP_EMPTY64 : (((uint64_t)u << kb) | v);
+      key[e] = (v == u || v >= n) ? SP_EMPTY64
+               : inv ? (((uint64_t)inv[u] << kb) | inv[v])
+                     : (((uint64_t)u << kb) | v);
       val[e] = ww;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// locality order of the input (the build runs on it; results are mapped
+// back to the input's ids before postprocessing)
+// ---------------------------------------------------------------------------
+// One step of min-label propagation along the input arcs: L2[v] = the
+// smallest of L[v] and L over v's out-neighbours.  Bad rows and heads are
+// skipped here (the key pass reports them).
+__global__ void k_minlabel_step(uint32_t n, uint64_t m, const uint64_t *__restrict__ off,
+                                const uint32_t *__restrict__ dst, const uint32_t *__restrict__ L,
+                                uint32_t *__restrict__ L2) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint64_t a = off[v], b = off[v + 1];
+    uint32_t x = L[v];
+    if (a <= b && b <= m)
+      for (uint64_t e = a; e < b; e++) {
+        const uint32_t u = dst[e];
+        if (u < n) x = min(x, L[u]);
+      }
+    L2[v] = x;
+  }
+}
+
+// key = (coarse label << kb) | fine label: vertices of one coarse cluster
+// end up together, and inside it those of one fine cluster.
+__global__ void k_order_keys(uint32_t n, int kb, const uint32_t *__restrict__ coarse,
+                             const uint32_t *__restrict__ fine, uint64_t *__restrict__ key) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    key[v] = ((uint64_t)coarse[v] << kb) | fine[v];
+}
+
+// out[idx[i]] = in[i] (scatter) or out[i] = in[idx[i]] (gather).
+__global__ void k_permute_u32(uint32_t n, const uint32_t *__restrict__ idx,
+                              const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                              int scatter) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (scatter) out[idx[i]] = in[i];
+    else out[i] = in[idx[i]];
+  }
+}
+
+// Vertex ids x -> map[x] in place (SP_NOMID stays).
+__global__ void k_map_ids(uint64_t m, uint32_t *__restrict__ x, const uint32_t *__restrict__ map) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    const uint32_t v = x[i];
+    if (v != SP_NOMID) x[i] = map[v];
   }
 }
 

@@ -2,7 +2,7 @@
 // with no host round trip per round.
 //
 // Once the overlay fits the all-pairs table (at most 4096 vertices), the
-// remaining rounds of Alg. 2 run as a fixed sequence of eight launches per
+// remaining rounds of Alg. 2 run as a fixed sequence of five launches per
 // round whose sizes live on the device: the host enqueues rounds in batches
 // and reads the state back once per batch; launches after the last round
 // return at once.  Vertices are table positions (0 .. n0 - 1) for the whole
@@ -36,7 +36,8 @@ struct TailCtr {
   uint32_t done;    // set once no vertex is left, the round limit is hit or an error is set
   uint32_t live;    // live vertices
   uint32_t rounds;  // rounds completed
-  uint32_t nf, nS, ntouched;
+  uint32_t nf, ntouched;
+  uint32_t blocks;  // blocks of the merge launch that have finished
   uint32_t cntW[2], cntA[2];
   unsigned long long m;  // live overlay arcs
   unsigned long long targets, pruned, rows, arcs, probes, added;
@@ -70,7 +71,7 @@ struct TailArgs {
   uint32_t *alive;
   uint32_t *af0, *af1, *wf0, *wf1;  // V_A and V_W flags by parity
   uint16_t *la0, *la1, *lw0, *lw1;  // their lists
-  uint16_t *lf;                     // V_F of this round
+  uint32_t *sflag;                  // V_S of this round
   TailCtr *C;
   uint32_t *err;
 };
@@ -104,6 +105,7 @@ __global__ void k_tail_clear(TailArgs A) {
   for (uint64_t i = t0; i < nn; i += stride) A.SC[i] = SP_EMPTY64;
   for (uint64_t i = t0; i < A.n0; i += stride) {
     A.af0[i] = A.af1[i] = A.wf0[i] = A.wf1[i] = 0;
+    A.sflag[i] = 0;
   }
 }
 
@@ -187,28 +189,30 @@ __global__ void k_tail_lrank(TailArgs A) {
 // path; every target gets its entry.  Then pruning: an out-arc (s, v)
 // heavier than the memoized dist(s, v) is deleted.  The searches read only
 // the lists and weights, which pruning does not change, so they see the
-// overlay as it was at the start of the round.
+// overlay as it was at the start of the round.  One block per source; its
+// waves take every fourth out-neighbour and walk their rows together.
 __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t cur) {
   TailCtr *C = A.C;
   if (C->done) return;
   const uint32_t nw = C->cntW[cur];
   const uint16_t *lw = cur ? A.lw1 : A.lw0;
   const uint32_t *af = cur ? A.af1 : A.af0;
-  __shared__ uint32_t s_new[kTailWaves][kTailMaxN / 32];
-  uint32_t *nb = s_new[threadIdx.x / kWave];
+  __shared__ uint32_t nb[kTailMaxN / 32];  // new targets of the current source
+  __shared__ uint32_t s_red[kTailWaves][2];
   const int l = lane_id();
+  const uint32_t wv = threadIdx.x / kWave;
   const uint32_t n0 = A.n0, rw = A.rw;
-  for (uint32_t i = l; i < rw; i += kWave) nb[i] = 0;
-  wave_sync();
+  for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) nb[i] = 0;
+  __syncthreads();
   uint64_t rows = 0, arcs = 0, probes = 0, targets = 0, pruned = 0;
-  TAIL_WAVE_LOOP(k, nw) {
+  for (uint32_t k = blockIdx.x; k < nw; k += gridDim.x) {
     const uint32_t s = lw[k];
     const uint16_t *os = A.ol + (size_t)s * n0;
     const uint32_t ds = A.olen[s];
     const uint32_t *es = A.eb + (size_t)s * rw;
     uint32_t dmax = 0;
-    for (uint32_t b0 = 0; b0 < ds; b0 += kWave) {
-      const uint32_t e = b0 + l;
+    for (uint32_t b0 = 0; b0 < ds; b0 += kTailBlock) {
+      const uint32_t e = b0 + wv + kTailWaves * (uint32_t)l;
       uint32_t u = 0, rl = 0, wsu = 0;
       if (e < ds) {
         u = os[e];
@@ -238,15 +242,27 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t
         }
       }
     }
-    wave_sync();
+    __syncthreads();  // the new-target bitmap is complete
     uint32_t nt = 0;
-    for (uint32_t i = l; i < rw; i += kWave) nt += __popc(nb[i]);
+    for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) nt += __popc(nb[i]);
     nt = gsum<kWave>(nt);
     dmax = gmax<kWave>(dmax);
-    if (nt && dmax > SP_MAXW && l == 0) atomicOr(A.err, kErrOverflow);
-    targets += l == 0 ? nt : 0;
+    if (l == 0) {
+      s_red[wv][0] = nt;
+      s_red[wv][1] = dmax;
+    }
+    __syncthreads();
+    nt = 0;
+    dmax = 0;
+#pragma unroll
+    for (int x = 0; x < kTailWaves; x++) {
+      nt += s_red[x][0];
+      dmax = max(dmax, s_red[x][1]);
+    }
+    if (nt && dmax > SP_MAXW && threadIdx.x == 0) atomicOr(A.err, kErrOverflow);
+    targets += threadIdx.x == 0 ? nt : 0;
     // pruning against the entries, the new ones included
-    for (uint32_t e = l; e < ds; e += kWave) {
+    for (uint32_t e = threadIdx.x; e < ds; e += kTailBlock) {
       const uint32_t v = os[e];
       const bool has = ((es[v >> 5] | nb[v >> 5]) >> (v & 31)) & 1u;
       if (!has) continue;
@@ -256,16 +272,16 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t
       tclear(A.ib, rw, v, s);
       pruned++;
     }
-    wave_sync();
-    if (nt) {
+    if (nt) {  // a word of E's row s is written by one thread
       uint32_t *esw = A.eb + (size_t)s * rw;
-      for (uint32_t i = l; i < rw; i += kWave) {
+      for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) {
         const uint32_t x = nb[i];
         if (x) esw[i] |= x;
       }
     }
-    for (uint32_t i = l; i < rw; i += kWave) nb[i] = 0;
-    wave_sync();
+    __syncthreads();  // every read of nb and s_red is done
+    for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) nb[i] = 0;
+    __syncthreads();
   }
   rows = gsum64<kWave>(rows);
   arcs = gsum64<kWave>(arcs);
@@ -283,49 +299,86 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t
 
 // Pair (i, j) of N_in(u) x N_out(u) is a shortcut candidate when both arcs
 // are live, the ends differ and the path through u is no longer than the
-// memoized distance (or there is no entry).
-struct TailPair {
-  uint32_t a, b, via;
-  bool cand;
+// memoized distance (or there is no entry).  kTailPairs pairs per thread,
+// p0 + q * stride, with the loads of each kind issued together.
+constexpr int kTailPairs = 4;
+struct TailPairs {
+  uint32_t a[kTailPairs], b[kTailPairs], via[kTailPairs];
+  bool cand[kTailPairs];
 };
-__device__ __forceinline__ TailPair tail_pair(const TailArgs &A, uint32_t u, uint32_t p,
-                                              uint32_t dout) {
-  TailPair r;
-  const uint32_t i = p / dout, j = p - i * dout;
+__device__ __forceinline__ void tail_pairs(const TailArgs &A, uint32_t u, uint32_t p0,
+                                           uint32_t stride, uint32_t np, uint32_t dout,
+                                           TailPairs &r) {
   const size_t rowu = (size_t)u * A.n0;
-  r.a = A.il[rowu + i];
-  r.b = A.ol[rowu + j];
-  r.via = 0;
-  r.cand = false;
-  if (r.a == r.b || !tbit(A.ib, A.rw, u, r.a) || !tbit(A.ob, A.rw, u, r.b)) return r;
-  const uint64_t via = (uint64_t)A.W[(size_t)r.a * A.n0 + u] + A.W[rowu + r.b];
-  r.via = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
-  if (!tbit(A.eb, A.rw, r.a, r.b)) {
-    r.cand = true;
-  } else {
-    const uint32_t d = A.D[(size_t)r.a * A.N + r.b];
-    r.cand = d == SP_INF32 || via <= d;
+  const uint32_t *ibu = A.ib + (size_t)u * A.rw, *obu = A.ob + (size_t)u * A.rw;
+  bool act[kTailPairs];
+#pragma unroll
+  for (int q = 0; q < kTailPairs; q++) {
+    const uint32_t p = p0 + q * stride;
+    act[q] = p < np;
+    r.a[q] = r.b[q] = 0;
+    if (act[q]) {
+      const uint32_t i = p / dout, j = p - i * dout;
+      r.a[q] = A.il[rowu + i];
+      r.b[q] = A.ol[rowu + j];
+    }
   }
-  return r;
+  uint32_t wa[kTailPairs], wb[kTailPairs], ew[kTailPairs];
+  bool live[kTailPairs];
+#pragma unroll
+  for (int q = 0; q < kTailPairs; q++) {
+    const uint32_t a = r.a[q], b = r.b[q];
+    live[q] = act[q] && a != b && ((ibu[a >> 5] >> (a & 31)) & 1u) && ((obu[b >> 5] >> (b & 31)) & 1u);
+  }
+#pragma unroll
+  for (int q = 0; q < kTailPairs; q++) {
+    wa[q] = wb[q] = ew[q] = 0;
+    if (live[q]) {
+      wa[q] = A.W[(size_t)r.a[q] * A.n0 + u];
+      wb[q] = A.W[rowu + r.b[q]];
+      ew[q] = A.eb[(size_t)r.a[q] * A.rw + (r.b[q] >> 5)];
+    }
+  }
+  uint32_t d[kTailPairs];
+#pragma unroll
+  for (int q = 0; q < kTailPairs; q++) {
+    d[q] = SP_INF32;
+    if (live[q] && ((ew[q] >> (r.b[q] & 31)) & 1u)) d[q] = A.D[(size_t)r.a[q] * A.N + r.b[q]];
+  }
+#pragma unroll
+  for (int q = 0; q < kTailPairs; q++) {
+    const uint64_t via = (uint64_t)wa[q] + wb[q];
+    r.via[q] = via > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)via;
+    // no entry (d stays SP_INF32) or a path through u no longer than it
+    r.cand[q] = live[q] && (d[q] == SP_INF32 || via <= d[q]);
+  }
 }
 
-// Step 2 (Alg. 4): edge difference of every affected vertex.
+// Step 2 (Alg. 4): edge difference of every affected vertex, one block each.
 __global__ void __launch_bounds__(kTailBlock) k_tail_score(TailArgs A, uint32_t cur) {
   TailCtr *C = A.C;
   if (C->done) return;
   const uint32_t na = C->cntA[cur];
   const uint16_t *la = cur ? A.la1 : A.la0;
+  __shared__ uint32_t s_red[kTailWaves][3];
   const int l = lane_id();
-  TAIL_WAVE_LOOP(k, na) {
+  const uint32_t wv = threadIdx.x / kWave;
+  for (uint32_t k = blockIdx.x; k < na; k += gridDim.x) {
     const uint32_t u = la[k];
     const uint32_t din = A.ilen[u], dout = A.olen[u];
     const uint32_t np = din * dout;
     uint32_t pairs = 0;
-    for (uint32_t p = l; p < np; p += kWave) pairs += tail_pair(A, u, p, dout).cand;
+    for (uint32_t p0 = threadIdx.x; p0 < np; p0 += kTailBlock * kTailPairs) {
+      TailPairs r;
+      tail_pairs(A, u, p0, kTailBlock, np, dout, r);
+#pragma unroll
+      for (int q = 0; q < kTailPairs; q++) pairs += r.cand[q];
+    }
     uint32_t cout = 0, only_in = 0;
     const size_t rowu = (size_t)u * A.n0;
-    for (uint32_t e = l; e < dout; e += kWave) cout += tbit(A.ob, A.rw, u, A.ol[rowu + e]);
-    for (uint32_t e = l; e < din; e += kWave) {
+    for (uint32_t e = threadIdx.x; e < dout; e += kTailBlock)
+      cout += tbit(A.ob, A.rw, u, A.ol[rowu + e]);
+    for (uint32_t e = threadIdx.x; e < din; e += kTailBlock) {
       const uint32_t a = A.il[rowu + e];
       if (tbit(A.ib, A.rw, u, a)) only_in += !tbit(A.ob, A.rw, u, a);
     }
@@ -333,53 +386,40 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_score(TailArgs A, uint32_t 
     cout = gsum<kWave>(cout);
     only_in = gsum<kWave>(only_in);
     if (l == 0) {
-      int64_t p = (int64_t)pairs - (int64_t)(cout + only_in);
+      s_red[wv][0] = pairs;
+      s_red[wv][1] = cout;
+      s_red[wv][2] = only_in;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t p = 0;
+#pragma unroll
+      for (int x = 0; x < kTailWaves; x++)
+        p += (int64_t)s_red[x][0] - (int64_t)s_red[x][1] - (int64_t)s_red[x][2];
       p = p > INT32_MAX ? INT32_MAX : (p < INT32_MIN ? INT32_MIN : p);
       A.P[u] = (int32_t)p;
     }
+    __syncthreads();
   }
 }
 
-// Step 3 (Alg. 5): u is selected iff its key (priority, label) is below
-// every live neighbour's.
-__global__ void __launch_bounds__(kTailBlock) k_tail_select(TailArgs A) {
-  TailCtr *C = A.C;
-  if (C->done) return;
-  const int l = lane_id();
-  TAIL_WAVE_LOOP(u, A.n0) {
-    if (!A.alive[u]) continue;
-    auto key = [&](uint32_t x) {
-      return ((uint64_t)((uint32_t)A.P[x] ^ 0x80000000u) << 32) | A.lab[x];
-    };
-    const uint64_t ku = key(u);
-    const size_t rowu = (size_t)u * A.n0;
-    bool beaten = false;
-    for (uint32_t e = l; e < A.olen[u]; e += kWave) {
-      const uint32_t v = A.ol[rowu + e];
-      beaten |= tbit(A.ob, A.rw, u, v) && key(v) < ku;
-    }
-    for (uint32_t e = l; e < A.ilen[u]; e += kWave) {
-      const uint32_t a = A.il[rowu + e];
-      beaten |= tbit(A.ib, A.rw, u, a) && key(a) < ku;
-    }
-    beaten = gany<kWave>(beaten);
-    if (!beaten && l == 0) A.lf[atomicAdd(&C->nf, 1u)] = (uint16_t)u;
-  }
-}
-
-// Step 4 (Alg. 6): live out-arcs of each selected vertex go to the upward
-// set, live in-arcs to the downward set (their twins in the neighbours'
-// rows are cleared), the neighbours join the next V_A, and every candidate
-// pair lowers SC[a][b]; its first candidate lists the pair, and a joins
-// V_S (the next V_W).  The selected set is independent, so no selected
-// vertex's rows change while it is contracted.
-__global__ void __launch_bounds__(kTailBlock) k_tail_contract(TailArgs A, uint32_t cur,
-                                                              uint32_t round, ArcOut up, ArcOut dn,
-                                                              uint64_t up_base, uint64_t dn_base,
-                                                              uint64_t up_cap, uint64_t dn_cap,
-                                                              uint32_t *__restrict__ level,
-                                                              int32_t *__restrict__ score,
-                                                              uint8_t *__restrict__ alive_g) {
+// Steps 3 and 4 (Alg. 5 and 6) in one launch.  Select: u is selected iff
+// its key (priority, label) is below every live neighbour's; a wave decides
+// for one vertex.  Contract, by the whole block for each vertex its waves
+// selected: live out-arcs go to the upward set and live in-arcs to the
+// downward set, the neighbours join the next V_A, and every candidate pair
+// lowers SC[a][b]; its first candidate lists the pair, and a joins V_S (so
+// the next V_W; sflag marks V_S).  Contraction clears no bit: the twins of
+// the moved arcs stay set until the compaction drops every entry to a dead
+// vertex, so the selections in this launch all see the same overlay, and
+// the rows a contraction reads (its own) change in no way meanwhile.
+__global__ void __launch_bounds__(kTailBlock) k_tail_selcon(TailArgs A, uint32_t cur,
+                                                            uint32_t round, ArcOut up, ArcOut dn,
+                                                            uint64_t up_base, uint64_t dn_base,
+                                                            uint64_t up_cap, uint64_t dn_cap,
+                                                            uint32_t *__restrict__ level,
+                                                            int32_t *__restrict__ score,
+                                                            uint8_t *__restrict__ alive_g) {
   TailCtr *C = A.C;
   if (C->done) return;
   const uint32_t nxt = cur ^ 1u;
@@ -387,101 +427,135 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_contract(TailArgs A, uint32
   uint32_t *wfn = nxt ? A.wf1 : A.wf0;
   uint16_t *lan = nxt ? A.la1 : A.la0;
   uint16_t *lwn = nxt ? A.lw1 : A.lw0;
-  const uint32_t nf = C->nf;
+  __shared__ uint32_t s_sel[kTailWaves];
   const int l = lane_id();
+  const uint32_t wv = threadIdx.x / kWave;
   const uint64_t below = l == 0 ? 0ull : ((1ull << l) - 1ull);
   const uint32_t n0 = A.n0, rw = A.rw;
-  TAIL_WAVE_LOOP(k, nf) {
-    const uint32_t u = A.lf[k];
-    const uint32_t gu = A.gidp[u];
-    const size_t rowu = (size_t)u * n0;
-    if (l == 0) {
-      level[gu] = round;
-      score[gu] = A.P[u];
-      alive_g[gu] = 0;
-      A.alive[u] = 0;
-    }
-    const uint32_t dout = A.olen[u], din = A.ilen[u];
-    for (uint32_t b0 = 0; b0 < dout; b0 += kWave) {
-      const uint32_t e = b0 + l;
-      uint32_t v = 0;
-      bool live = false;
-      if (e < dout) {
-        v = A.ol[rowu + e];
-        live = tbit(A.ob, rw, u, v);
+  auto key = [&](uint32_t x) {
+    return ((uint64_t)((uint32_t)A.P[x] ^ 0x80000000u) << 32) | A.lab[x];
+  };
+  for (uint32_t base = blockIdx.x * kTailWaves; base < n0; base += gridDim.x * kTailWaves) {
+    const uint32_t u = base + wv;
+    bool sel = false;
+    if (u < n0 && A.alive[u]) {
+      const uint64_t ku = key(u);
+      const size_t rowu = (size_t)u * n0;
+      bool beaten = false;
+      for (uint32_t e = l; e < A.olen[u]; e += kWave) {
+        const uint32_t v = A.ol[rowu + e];
+        beaten |= tbit(A.ob, rw, u, v) && key(v) < ku;
       }
-      const uint64_t msk = __ballot(live);
-      unsigned long long base = 0;
-      if (l == 0 && msk) base = atomicAdd(&C->up_n, (unsigned long long)__popcll(msk));
-      base = __shfl(base, 0, kWave);
-      if (live) {
-        const uint64_t at = up_base + base + __popcll(msk & below);
-        if (at < up_cap) {
-          up.t[at] = gu;
-          up.h[at] = A.gidp[v];
-          up.w[at] = A.W[rowu + v];
-          up.m[at] = A.MID[rowu + v];
-        } else {
-          atomicOr(A.err, kErrCapacity);
+      for (uint32_t e = l; e < A.ilen[u]; e += kWave) {
+        const uint32_t a = A.il[rowu + e];
+        beaten |= tbit(A.ib, rw, u, a) && key(a) < ku;
+      }
+      sel = !gany<kWave>(beaten);
+    }
+    if (l == 0) s_sel[wv] = sel ? u : 0xFFFFFFFFu;
+    __syncthreads();
+    for (int x = 0; x < kTailWaves; x++) {
+      const uint32_t cu = s_sel[x];
+      if (cu == 0xFFFFFFFFu) continue;  // uniform over the block
+      const uint32_t gu = A.gidp[cu];
+      const size_t rowu = (size_t)cu * n0;
+      if (threadIdx.x == 0) {
+        level[gu] = round;
+        score[gu] = A.P[cu];
+        alive_g[gu] = 0;
+        A.alive[cu] = 0;
+        atomicAdd(&C->nf, 1u);
+      }
+      const uint32_t dout = A.olen[cu], din = A.ilen[cu];
+      for (uint32_t b0 = wv * kWave; b0 < dout; b0 += kTailBlock) {
+        const uint32_t e = b0 + l;
+        uint32_t v = 0;
+        bool live = false;
+        if (e < dout) {
+          v = A.ol[rowu + e];
+          live = tbit(A.ob, rw, cu, v);
         }
-        tmark(afn, lan, &C->cntA[nxt], v);
-        tclear(A.ib, rw, v, u);
-      }
-    }
-    for (uint32_t b0 = 0; b0 < din; b0 += kWave) {
-      const uint32_t e = b0 + l;
-      uint32_t a = 0;
-      bool live = false;
-      if (e < din) {
-        a = A.il[rowu + e];
-        live = tbit(A.ib, rw, u, a);
-      }
-      const uint64_t msk = __ballot(live);
-      unsigned long long base = 0;
-      if (l == 0 && msk) base = atomicAdd(&C->dn_n, (unsigned long long)__popcll(msk));
-      base = __shfl(base, 0, kWave);
-      if (live) {
-        const uint64_t at = dn_base + base + __popcll(msk & below);
-        if (at < dn_cap) {
-          dn.t[at] = A.gidp[a];
-          dn.h[at] = gu;
-          dn.w[at] = A.W[(size_t)a * n0 + u];
-          dn.m[at] = A.MID[(size_t)a * n0 + u];
-        } else {
-          atomicOr(A.err, kErrCapacity);
+        const uint64_t msk = __ballot(live);
+        unsigned long long at0 = 0;
+        if (l == 0 && msk) at0 = atomicAdd(&C->up_n, (unsigned long long)__popcll(msk));
+        at0 = __shfl(at0, 0, kWave);
+        if (live) {
+          const uint64_t at = up_base + at0 + __popcll(msk & below);
+          if (at < up_cap) {
+            up.t[at] = gu;
+            up.h[at] = A.gidp[v];
+            up.w[at] = A.W[rowu + v];
+            up.m[at] = A.MID[rowu + v];
+          } else {
+            atomicOr(A.err, kErrCapacity);
+          }
+          tmark(afn, lan, &C->cntA[nxt], v);
         }
-        tmark(afn, lan, &C->cntA[nxt], a);
-        tclear(A.ob, rw, a, u);
+      }
+      for (uint32_t b0 = wv * kWave; b0 < din; b0 += kTailBlock) {
+        const uint32_t e = b0 + l;
+        uint32_t a = 0;
+        bool live = false;
+        if (e < din) {
+          a = A.il[rowu + e];
+          live = tbit(A.ib, rw, cu, a);
+        }
+        const uint64_t msk = __ballot(live);
+        unsigned long long at0 = 0;
+        if (l == 0 && msk) at0 = atomicAdd(&C->dn_n, (unsigned long long)__popcll(msk));
+        at0 = __shfl(at0, 0, kWave);
+        if (live) {
+          const uint64_t at = dn_base + at0 + __popcll(msk & below);
+          if (at < dn_cap) {
+            dn.t[at] = A.gidp[a];
+            dn.h[at] = gu;
+            dn.w[at] = A.W[(size_t)a * n0 + cu];
+            dn.m[at] = A.MID[(size_t)a * n0 + cu];
+          } else {
+            atomicOr(A.err, kErrCapacity);
+          }
+          tmark(afn, lan, &C->cntA[nxt], a);
+        }
+      }
+      const uint32_t np = din * dout;
+      const uint32_t lr = A.lrank[cu];
+      for (uint32_t p0 = threadIdx.x; p0 < np; p0 += kTailBlock * kTailPairs) {
+        TailPairs r;
+        tail_pairs(A, cu, p0, kTailBlock, np, dout, r);
+#pragma unroll
+        for (int q = 0; q < kTailPairs; q++) {
+          if (!r.cand[q]) continue;
+          if (r.via[q] > SP_MAXW) {
+            atomicOr(A.err, kErrOverflow);
+            continue;
+          }
+          const unsigned long long val = ((unsigned long long)r.via[q] << 12) | lr;
+          if (atomicMin(&A.SC[(size_t)r.a[q] * n0 + r.b[q]], val) == SP_EMPTY64)
+            A.touched[atomicAdd(&C->ntouched, 1u)] = (r.a[q] << 12) | r.b[q];
+          A.sflag[r.a[q]] = 1;
+          tmark(wfn, lwn, &C->cntW[nxt], r.a[q]);
+        }
       }
     }
-    const uint32_t np = din * dout;
-    const uint32_t lr = A.lrank[u];
-    for (uint32_t p = l; p < np; p += kWave) {
-      const TailPair q = tail_pair(A, u, p, dout);
-      if (!q.cand) continue;
-      if (q.via > SP_MAXW) {
-        atomicOr(A.err, kErrOverflow);
-        continue;
-      }
-      const unsigned long long val = ((unsigned long long)q.via << 12) | lr;
-      if (atomicMin(&A.SC[(size_t)q.a * n0 + q.b], val) == SP_EMPTY64)
-        A.touched[atomicAdd(&C->ntouched, 1u)] = (q.a << 12) | q.b;
-      tmark(wfn, lwn, &C->cntW[nxt], q.a);
-    }
+    __syncthreads();  // s_sel is rewritten next
   }
 }
 
 // Drops the dead entries (pruned arcs, arcs to contracted vertices) from
-// the lists of the live vertices; records |V_S| for the next step.
+// the lists of the live vertices; the live in-neighbours of a V_S vertex
+// join the next V_W.
 __global__ void __launch_bounds__(kTailBlock) k_tail_compact(TailArgs A, uint32_t cur) {
   TailCtr *C = A.C;
   if (C->done) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) C->nS = C->cntW[cur ^ 1u];
+  const uint32_t nxt = cur ^ 1u;
+  uint32_t *wfn = nxt ? A.wf1 : A.wf0;
+  uint16_t *lwn = nxt ? A.lw1 : A.lw0;
   const int l = lane_id();
   const uint64_t below = l == 0 ? 0ull : ((1ull << l) - 1ull);
   TAIL_WAVE_LOOP(u, A.n0) {
     if (!A.alive[u]) continue;
     const size_t rowu = (size_t)u * A.n0;
+    const bool in_s = A.sflag[u] != 0;
     for (int side = 0; side < 2; side++) {
       uint16_t *lst = (side ? A.il : A.ol) + rowu;
       const uint32_t *bm = side ? A.ib : A.ob;
@@ -494,10 +568,13 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_compact(TailArgs A, uint32_
         bool keep = false;
         if (e < n) {
           x = lst[e];
-          keep = tbit(bm, A.rw, u, x);
+          keep = tbit(bm, A.rw, u, x) && A.alive[x];
         }
         const uint64_t msk = __ballot(keep);
-        if (keep) lst[kept + __popcll(msk & below)] = (uint16_t)x;
+        if (keep) {
+          lst[kept + __popcll(msk & below)] = (uint16_t)x;
+          if (side && in_s) tmark(wfn, lwn, &C->cntW[nxt], x);
+        }
         kept += (uint32_t)__popcll(msk);
         wave_sync();
       }
@@ -509,10 +586,20 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_compact(TailArgs A, uint32_
 // Overlay rebuild: each E+ pair (a, b) with its minimal (weight, label) --
 // a live arc (a, b) takes the shortcut's weight and middle vertex only if
 // the shortcut is lighter (a tie keeps the arc); otherwise the pair becomes
-// a new arc.  SC is emptied for the next round.
-__global__ void __launch_bounds__(kTailBlock) k_tail_merge(TailArgs A) {
+// a new arc, and a joins the next V_W when b is in V_S.  SC is emptied for
+// the next round.  The last block to finish ends the round: its record,
+// this round's flags cleared (they serve the round after next), the
+// counters of the next round, and the stop condition.  A round with an
+// error is not recorded.
+__global__ void __launch_bounds__(kTailBlock) k_tail_merge_end(TailArgs A, uint32_t cur,
+                                                               uint32_t max_rounds,
+                                                               TailRound *__restrict__ rec,
+                                                               uint32_t rec_cap) {
   TailCtr *C = A.C;
   if (C->done) return;
+  const uint32_t nxt = cur ^ 1u;
+  uint32_t *wfn = nxt ? A.wf1 : A.wf0;
+  uint16_t *lwn = nxt ? A.lw1 : A.lw0;
   const uint32_t nt = C->ntouched;
   const uint32_t stride = gridDim.x * blockDim.x;
   uint64_t added = 0;
@@ -537,35 +624,22 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_merge(TailArgs A) {
     tset(A.ib, A.rw, b, a);
     A.ol[(size_t)a * A.n0 + atomicAdd(&A.olen[a], 1u)] = (uint16_t)b;
     A.il[(size_t)b * A.n0 + atomicAdd(&A.ilen[b], 1u)] = (uint16_t)a;
+    if (A.sflag[b]) tmark(wfn, lwn, &C->cntW[nxt], a);
     added++;
   }
   added = gsum64<kWave>(added);
   if (lane_id() == 0 && added) atomicAdd(&C->added, (unsigned long long)added);
-}
 
-// V_W' = V_S plus the in-neighbours of V_S in the rebuilt overlay.
-__global__ void __launch_bounds__(kTailBlock) k_tail_next(TailArgs A, uint32_t cur) {
-  TailCtr *C = A.C;
-  if (C->done) return;
-  const uint32_t nxt = cur ^ 1u;
-  uint32_t *wfn = nxt ? A.wf1 : A.wf0;
-  uint16_t *lwn = nxt ? A.lw1 : A.lw0;
-  const uint32_t ns = C->nS;
-  const int l = lane_id();
-  TAIL_WAVE_LOOP(k, ns) {
-    const uint32_t u = lwn[k];
-    const size_t rowu = (size_t)u * A.n0;
-    for (uint32_t e = l; e < A.ilen[u]; e += kWave) tmark(wfn, lwn, &C->cntW[nxt], A.il[rowu + e]);
+  // ---- end of the round, by the last block
+  __shared__ uint32_t s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    s_last = atomicAdd(&C->blocks, 1u) == gridDim.x - 1;
   }
-}
-
-// End of a round (one block): its record, the counters of the next round,
-// this round's flags cleared (they serve the round after next), and the
-// stop condition.  A round with an error is not recorded.
-__global__ void __launch_bounds__(1024) k_tail_end(TailArgs A, uint32_t cur, uint32_t max_rounds,
-                                                   TailRound *__restrict__ rec) {
-  TailCtr *C = A.C;
-  if (C->done) return;
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
   uint32_t *af = cur ? A.af1 : A.af0;
   uint32_t *wf = cur ? A.wf1 : A.wf0;
   const uint16_t *la = cur ? A.la1 : A.la0;
@@ -573,10 +647,12 @@ __global__ void __launch_bounds__(1024) k_tail_end(TailArgs A, uint32_t cur, uin
   const uint32_t na = C->cntA[cur], nw = C->cntW[cur];
   for (uint32_t i = threadIdx.x; i < na; i += blockDim.x) af[la[i]] = 0;
   for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) wf[lw[i]] = 0;
+  for (uint32_t i = threadIdx.x; i < A.n0; i += blockDim.x) A.sflag[i] = 0;
   __syncthreads();
   if (threadIdx.x != 0) return;
-  if (*A.err || C->nf == 0) {
-    if (C->nf == 0) atomicOr(A.err, kErrCapacity);  // a round always selects a vertex
+  C->blocks = 0;
+  if (*A.err || C->nf == 0 || C->rounds >= rec_cap) {
+    if (C->nf == 0 || C->rounds >= rec_cap) atomicOr(A.err, kErrCapacity);
     C->done = 1;
     return;
   }
@@ -599,7 +675,7 @@ __global__ void __launch_bounds__(1024) k_tail_end(TailArgs A, uint32_t cur, uin
   C->live -= C->nf;
   C->m = m2;
   C->rounds++;
-  C->nf = C->nS = C->ntouched = 0;
+  C->nf = C->ntouched = 0;
   C->targets = C->pruned = C->rows = C->arcs = C->probes = C->added = 0;
   C->up_prev = C->up_n;
   C->dn_prev = C->dn_n;

@@ -192,6 +192,15 @@ def test_road_100k_bit_exact(gpu):
     assert np.array_equal(d, od)
     ref = reference_distances(off, dst, w, s[:20], t[:20])
     assert np.array_equal(d[:20], ref)
+    # the same build on the input's own numbering (no locality renumbering)
+    # and on the per-step table rounds gives the same CH and round counts
+    a = oracle_export(o)
+    for kw in (dict(keep_order=True), dict(tail_stepwise=True)):
+        print(f"[parity] road100k {kw}", flush=True)
+        ch2 = gpu.build(off, dst, w, labels=lab, stats=True, **kw)
+        assert_same_ch(a, gpu_export(ch2), f"road100k {kw}")
+        assert gpu_round_counts(ch2) == oracle_round_counts(o), kw
+        assert np.array_equal(ch2.query(s, t), od), kw
 
 
 def test_query_tiers(gpu):
