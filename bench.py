@@ -268,7 +268,9 @@ def main():
     per = {}
     for r in recs:
         for x in r["rounds"]:
-            if x["n_sources"] == 0:
+            # rounds of the device-driven tail have no separately timed
+            # search launch (their searches are part of a five-launch round)
+            if x["n_sources"] == 0 or x["ls_tier1"] == binding.CH_LS_TAIL:
                 continue
             k = binding.LS_KERNELS[x["ls_tier1"]]
             a = per.setdefault(k, [0, 0.0, 0])

@@ -85,6 +85,7 @@ class MlpTrainParams(C.Structure):
 
 
 CH_LS_AUTO, CH_LS_16x128, CH_LS_32x512, CH_LS_64x512, CH_LS_64x2048 = 0, 1, 2, 3, 4
+CH_LS_TABLE, CH_LS_TAIL = 5, 6
 LS_KERNELS = {1: "k_local_search<16, 128>", 2: "k_local_search<32, 512>",
               3: "k_local_search<64, 512>", 4: "k_local_search<64, 2048>",
               5: "k_ls_table", 6: "k_tail_search"}

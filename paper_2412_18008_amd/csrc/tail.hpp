@@ -189,30 +189,28 @@ __global__ void k_tail_lrank(TailArgs A) {
 // path; every target gets its entry.  Then pruning: an out-arc (s, v)
 // heavier than the memoized dist(s, v) is deleted.  The searches read only
 // the lists and weights, which pruning does not change, so they see the
-// overlay as it was at the start of the round.  One block per source; its
-// waves take every fourth out-neighbour and walk their rows together.
+// overlay as it was at the start of the round.
 __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t cur) {
   TailCtr *C = A.C;
   if (C->done) return;
   const uint32_t nw = C->cntW[cur];
   const uint16_t *lw = cur ? A.lw1 : A.lw0;
   const uint32_t *af = cur ? A.af1 : A.af0;
-  __shared__ uint32_t nb[kTailMaxN / 32];  // new targets of the current source
-  __shared__ uint32_t s_red[kTailWaves][2];
+  __shared__ uint32_t s_new[kTailWaves][kTailMaxN / 32];
+  uint32_t *nb = s_new[threadIdx.x / kWave];
   const int l = lane_id();
-  const uint32_t wv = threadIdx.x / kWave;
   const uint32_t n0 = A.n0, rw = A.rw;
-  for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) nb[i] = 0;
-  __syncthreads();
+  for (uint32_t i = l; i < rw; i += kWave) nb[i] = 0;
+  wave_sync();
   uint64_t rows = 0, arcs = 0, probes = 0, targets = 0, pruned = 0;
-  for (uint32_t k = blockIdx.x; k < nw; k += gridDim.x) {
+  TAIL_WAVE_LOOP(k, nw) {
     const uint32_t s = lw[k];
     const uint16_t *os = A.ol + (size_t)s * n0;
     const uint32_t ds = A.olen[s];
     const uint32_t *es = A.eb + (size_t)s * rw;
     uint32_t dmax = 0;
-    for (uint32_t b0 = 0; b0 < ds; b0 += kTailBlock) {
-      const uint32_t e = b0 + wv + kTailWaves * (uint32_t)l;
+    for (uint32_t b0 = 0; b0 < ds; b0 += kWave) {
+      const uint32_t e = b0 + l;
       uint32_t u = 0, rl = 0, wsu = 0;
       if (e < ds) {
         u = os[e];
@@ -242,27 +240,15 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t
         }
       }
     }
-    __syncthreads();  // the new-target bitmap is complete
+    wave_sync();
     uint32_t nt = 0;
-    for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) nt += __popc(nb[i]);
+    for (uint32_t i = l; i < rw; i += kWave) nt += __popc(nb[i]);
     nt = gsum<kWave>(nt);
     dmax = gmax<kWave>(dmax);
-    if (l == 0) {
-      s_red[wv][0] = nt;
-      s_red[wv][1] = dmax;
-    }
-    __syncthreads();
-    nt = 0;
-    dmax = 0;
-#pragma unroll
-    for (int x = 0; x < kTailWaves; x++) {
-      nt += s_red[x][0];
-      dmax = max(dmax, s_red[x][1]);
-    }
-    if (nt && dmax > SP_MAXW && threadIdx.x == 0) atomicOr(A.err, kErrOverflow);
-    targets += threadIdx.x == 0 ? nt : 0;
+    if (nt && dmax > SP_MAXW && l == 0) atomicOr(A.err, kErrOverflow);
+    targets += l == 0 ? nt : 0;
     // pruning against the entries, the new ones included
-    for (uint32_t e = threadIdx.x; e < ds; e += kTailBlock) {
+    for (uint32_t e = l; e < ds; e += kWave) {
       const uint32_t v = os[e];
       const bool has = ((es[v >> 5] | nb[v >> 5]) >> (v & 31)) & 1u;
       if (!has) continue;
@@ -272,16 +258,16 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t
       tclear(A.ib, rw, v, s);
       pruned++;
     }
-    if (nt) {  // a word of E's row s is written by one thread
+    wave_sync();
+    if (nt) {
       uint32_t *esw = A.eb + (size_t)s * rw;
-      for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) {
+      for (uint32_t i = l; i < rw; i += kWave) {
         const uint32_t x = nb[i];
         if (x) esw[i] |= x;
       }
     }
-    __syncthreads();  // every read of nb and s_red is done
-    for (uint32_t i = threadIdx.x; i < rw; i += kTailBlock) nb[i] = 0;
-    __syncthreads();
+    for (uint32_t i = l; i < rw; i += kWave) nb[i] = 0;
+    wave_sync();
   }
   rows = gsum64<kWave>(rows);
   arcs = gsum64<kWave>(arcs);

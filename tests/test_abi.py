@@ -87,3 +87,20 @@ def test_struct_layouts_match_header(binding, tmp_path):
         assert int(out[cname]) == C.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(out[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_header_constants_match_binding(binding):
+    """Every plain numeric #define of the header that the binding mirrors
+    has the same value there."""
+    import re
+
+    text = open(os.path.join(ROOT, "include", "spoch.h")).read()
+    found = 0
+    for name, val in re.findall(r"^#define\s+(CH_\w+)\s+(0x[0-9A-Fa-f]+|\d+)u?\b", text, re.M):
+        if hasattr(binding, name):
+            assert getattr(binding, name) == int(val, 0), name
+            found += 1
+    for name in ("CH_F_TAIL_STEPWISE", "CH_F_KEEP_ORDER", "CH_LS_TABLE", "CH_LS_TAIL",
+                 "CH_F_STATS", "CH_DENSE_TAIL_OFF"):
+        assert hasattr(binding, name), name
+    assert found >= 10
