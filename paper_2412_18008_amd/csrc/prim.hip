@@ -601,22 +601,23 @@ __global__ void __launch_bounds__(kSmallBlock) k_sort_small_iota(uint64_t *__res
     sv[i] = i < n ? i : 0xFFFFFFFFu;
   }
   __syncthreads();
+  // each step compares np / 2 pairs (i, i + j): pair p has i = p with a
+  // zero bit inserted at bit log2(j), so no thread idles on the upper halves
   for (uint32_t k = 2; k <= np; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      for (uint32_t i = threadIdx.x; i < np; i += kSmallBlock) {
-        const uint32_t l = i ^ j;
-        if (l > i) {
-          const uint64_t a = sk[i] & mask, b = sk[l] & mask;
-          const bool gt = a > b || (a == b && sv[i] > sv[l]);
-          const bool up = (i & k) == 0;
-          if (gt == up) {
-            const uint64_t tk = sk[i];
-            sk[i] = sk[l];
-            sk[l] = tk;
-            const uint32_t tv = sv[i];
-            sv[i] = sv[l];
-            sv[l] = tv;
-          }
+      for (uint32_t p = threadIdx.x; p < (np >> 1); p += kSmallBlock) {
+        const uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+        const uint32_t l = i | j;
+        const uint64_t a = sk[i] & mask, b = sk[l] & mask;
+        const bool gt = a > b || (a == b && sv[i] > sv[l]);
+        const bool up = (i & k) == 0;
+        if (gt == up) {
+          const uint64_t tk = sk[i];
+          sk[i] = sk[l];
+          sk[l] = tk;
+          const uint32_t tv = sv[i];
+          sv[i] = sv[l];
+          sv[l] = tv;
         }
       }
       __syncthreads();
