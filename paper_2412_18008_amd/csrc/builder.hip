@@ -504,6 +504,10 @@ struct Builder {
   // round, right after the table is built (positions = current local ids);
   // nw: this round's source count.
   static constexpr uint32_t kTailBatch = 8;
+  // default table threshold: road1m builds fastest between 2560 and 3584
+  // (a larger table costs more Floyd-Warshall, a smaller one more rounds on
+  // the general path)
+  static constexpr uint32_t kDenseTailDefault = 3072;
 
   int run_tail(uint32_t &round, uint32_t nw) {
     OvBuf &O = ov[cur];
@@ -886,7 +890,7 @@ struct Builder {
       // exact mode, plain priority, one graph: once the overlay fits the
       // all-pairs table, the remaining rounds run on the device (tail.hpp)
       {
-        const uint32_t lim = prm.dense_tail == 0 ? 2048u : prm.dense_tail;
+        const uint32_t lim = prm.dense_tail == 0 ? kDenseTailDefault : prm.dense_tail;
         const bool fused = prm.wps_mode == CH_WPS_EXACT && prm.dense_tail != CH_DENSE_TAIL_OFF &&
                            prm.priority == CH_PRIO_PLAIN && !batch &&
                            !(prm.flags & (CH_F_RECORD_FEATURES | CH_F_TAIL_STEPWISE));
@@ -904,7 +908,7 @@ struct Builder {
       const double thr = prm.dense_deg10 ? prm.dense_deg10 / 10.0 : 5.0;
       const bool sparse = avgdeg <= thr;
       // exact mode on a small overlay: all distances once, then lookups
-      const uint32_t tail = prm.dense_tail == 0 ? 2048u : prm.dense_tail;
+      const uint32_t tail = prm.dense_tail == 0 ? kDenseTailDefault : prm.dense_tail;
       if (!tab_on && prm.wps_mode == CH_WPS_EXACT && tail != CH_DENSE_TAIL_OFF && O.n &&
           O.n <= tail)
         TRY(build_table(v));
