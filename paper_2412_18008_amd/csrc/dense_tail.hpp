@@ -111,49 +111,36 @@ __device__ __forceinline__ void fw_acc_store(const uint32_t (&acc)[4][4], uint32
 }
 
 // Phase k, step 1: closure of the diagonal tile (k, k) over its own 64
-// intermediate vertices by six min-plus squarings (T <- T (x) T): with a
-// zero diagonal the 2^s-th power holds the shortest paths of at most 2^s
-// arcs, and a shortest path inside the tile has at most 63.  The minimum is
-// over the same paths as the Floyd-Warshall loop, so the entries are the
-// same; each squaring is one parallel product instead of 64 dependent steps.
-// 1024 threads, 2 x 2 entries each.
+// intermediate vertices: the Floyd-Warshall loop in LDS, one barrier per
+// pivot t.  Row t and column t keep their values while pivot t is applied
+// (the diagonal stays 0 with non-negative weights), so every thread can
+// update its own entries in place.  1024 threads, four entries of one row
+// each.
 constexpr int kFwDiagThreads = 1024;
 
 __global__ void __launch_bounds__(kFwDiagThreads) k_fw_diag(uint32_t *__restrict__ D, uint32_t N,
                                                             uint32_t k) {
   __shared__ uint32_t T[kFwTile][kFwTile + 1];
-  for (int e = threadIdx.x; e < kFwTile * kFwTile; e += kFwDiagThreads) {
-    const int i = e / kFwTile, j = e % kFwTile;
-    T[i][j] = D[(size_t)(k * kFwTile + i) * N + (size_t)k * kFwTile + j];
+  constexpr int kPer = kFwTile * kFwTile / kFwDiagThreads;  // 4
+  const int i = threadIdx.x / (kFwTile / kPer), j0 = (threadIdx.x % (kFwTile / kPer)) * kPer;
+  const size_t base = (size_t)(k * kFwTile + i) * N + (size_t)k * kFwTile + j0;
+  uint32_t r[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; q++) {
+    r[q] = D[base + q];
+    T[i][j0 + q] = r[q];
   }
   __syncthreads();
-  const int ty = threadIdx.x / 32, tx = threadIdx.x % 32;
-  uint32_t acc[2][2];
-  for (int sq = 0; sq < 6; sq++) {
+  for (int t = 0; t < kFwTile; t++) {
+    const uint32_t a = T[i][t];
 #pragma unroll
-    for (int a = 0; a < 2; a++)
+    for (int q = 0; q < kPer; q++) r[q] = min(r[q], sat_add(a, T[t][j0 + q]));
 #pragma unroll
-      for (int b = 0; b < 2; b++) acc[a][b] = T[ty * 2 + a][tx * 2 + b];
-    for (int t = 0; t < kFwTile; t++) {
-      const uint32_t a0 = T[ty * 2][t], a1 = T[ty * 2 + 1][t];
-      const uint32_t b0 = T[t][tx * 2], b1 = T[t][tx * 2 + 1];
-      acc[0][0] = min(acc[0][0], sat_add(a0, b0));
-      acc[0][1] = min(acc[0][1], sat_add(a0, b1));
-      acc[1][0] = min(acc[1][0], sat_add(a1, b0));
-      acc[1][1] = min(acc[1][1], sat_add(a1, b1));
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < 2; a++)
-#pragma unroll
-      for (int b = 0; b < 2; b++) T[ty * 2 + a][tx * 2 + b] = acc[a][b];
+    for (int q = 0; q < kPer; q++) T[i][j0 + q] = r[q];
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 2; a++)
-#pragma unroll
-    for (int b = 0; b < 2; b++)
-      D[(size_t)(k * kFwTile + ty * 2 + a) * N + (size_t)k * kFwTile + tx * 2 + b] = acc[a][b];
+  for (int q = 0; q < kPer; q++) D[base + q] = r[q];
 }
 
 // Phase k, step 2: block b < nb updates row tile (k, b) and block nb + b
