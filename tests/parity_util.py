@@ -12,11 +12,15 @@ _T0 = time.time()
 
 
 def progress(msg):
-    """A progress line on stdout and, for runs whose output pytest captures,
-    appended to gpurun_out/test_progress.log under the repository."""
+    """A progress line on stdout and, when SPOCH_TEST_LOG_DIR names a folder
+    (relative to the repository root), appended to test_progress.log there,
+    for runs whose output pytest captures."""
     line = f"[{time.time() - _T0:8.1f}s] {msg}"
     print(line, flush=True)
-    d = os.path.join(_ROOT, "gpurun_out")
+    sub = os.environ.get("SPOCH_TEST_LOG_DIR")
+    if not sub:
+        return
+    d = os.path.join(_ROOT, sub)
     try:
         os.makedirs(d, exist_ok=True)
         with open(os.path.join(d, "test_progress.log"), "a") as f:
