@@ -29,6 +29,7 @@ namespace sp {
 constexpr int kTailBlock = 256;
 constexpr int kTailWaves = kTailBlock / kWave;
 constexpr uint32_t kTailMaxN = 4096;  // positions fit 12 bits
+constexpr int kTailPaths = 4;        // two-arc paths per lane in flight (search)
 
 // Device state of the tail; list counts and flags are indexed by the
 // parity of the round (cur = this round's, nxt = the next round's).
@@ -222,21 +223,46 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t
       }
       const uint32_t incl = gscan_incl<kWave>(rl);
       const uint32_t total = __shfl(incl, kWave - 1, kWave);
-      for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
-        const uint32_t idx = i0 + l;
-        const int src = gfind<kWave>(incl, idx);
-        const uint32_t su = __shfl(u, src, kWave), sinc = __shfl(incl, src, kWave);
-        const uint32_t srl = __shfl(rl, src, kWave), sw = __shfl(wsu, src, kWave);
-        if (idx < total) {
-          const uint32_t v = A.ol[(size_t)su * n0 + (idx - (sinc - srl))];
-          arcs++;
-          if (v != s) {
-            probes++;
-            if (!((es[v >> 5] >> (v & 31)) & 1u)) {
-              dmax = max(dmax, tvia(sw, A.W[(size_t)su * n0 + v]));
-              atomicOr(&nb[v >> 5], 1u << (v & 31));
+      // kTailPaths paths per lane: their list entries, then their memo
+      // words and weights, are loaded together before any is used
+      for (uint32_t i0 = 0; i0 < total; i0 += kWave * kTailPaths) {
+        uint32_t v[kTailPaths], su[kTailPaths], sw[kTailPaths];
+        bool ok[kTailPaths];
+#pragma unroll
+        for (int q = 0; q < kTailPaths; q++) {
+          const uint32_t idx = i0 + q * kWave + l;
+          ok[q] = false;
+          v[q] = su[q] = sw[q] = 0;
+          if (i0 + q * kWave < total) {  // uniform across the wave
+            const int src = gfind<kWave>(incl, idx);
+            su[q] = __shfl(u, src, kWave);
+            sw[q] = __shfl(wsu, src, kWave);
+            const uint32_t sinc = __shfl(incl, src, kWave), srl = __shfl(rl, src, kWave);
+            if (idx < total) {
+              v[q] = A.ol[(size_t)su[q] * n0 + (idx - (sinc - srl))];
+              ok[q] = true;
             }
           }
+        }
+        uint32_t ew[kTailPaths], wv2[kTailPaths];
+#pragma unroll
+        for (int q = 0; q < kTailPaths; q++) {
+          ew[q] = wv2[q] = 0;
+          if (!ok[q]) continue;
+          arcs++;
+          if (v[q] == s) {
+            ok[q] = false;
+            continue;
+          }
+          probes++;
+          ew[q] = es[v[q] >> 5];
+          wv2[q] = A.W[(size_t)su[q] * n0 + v[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < kTailPaths; q++) {
+          if (!ok[q] || ((ew[q] >> (v[q] & 31)) & 1u)) continue;
+          dmax = max(dmax, tvia(sw[q], wv2[q]));
+          atomicOr(&nb[v[q] >> 5], 1u << (v[q] & 31));
         }
       }
     }
