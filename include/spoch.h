@@ -71,11 +71,12 @@ extern "C" {
 /* Waves that share one query in the first query tier (1, 2, 4
  * or 8; 0 = the default, 4).  Results do not depend on it. */
 #define CH_Q_WAVES(nw) ((uint32_t)(nw) << 8)
-/* Level window of the query's search steps (1 .. 254 levels; 0 = the
- * default, 24; 255 = none, every flagged vertex is expanded at once).  A
- * step expands the reached vertices whose CH level is within the window
- * above the lowest level still to be expanded, so fewer vertices are
- * expanded twice.  Results do not depend on it. */
+/* Level window of the query's search steps (1 .. 254 levels; 255 = none,
+ * every flagged vertex is expanded at once; 0 = the default: none on a
+ * hierarchy of at most 256 levels, else 48).  A step expands the reached
+ * vertices whose CH level is within the window above the lowest level
+ * still to be expanded, so fewer vertices are expanded twice; a window
+ * covering every level is the same as none.  Results do not depend on it. */
 #define CH_Q_LEVEL_WINDOW(w) ((uint32_t)(w) << 12)
 
 /* Input graph in CSR form, arcs grouped by tail vertex.
