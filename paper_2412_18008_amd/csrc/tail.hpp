@@ -190,7 +190,7 @@ __global__ void k_tail_lrank(TailArgs A) {
 // path; every target gets its entry.  Then pruning: an out-arc (s, v)
 // heavier than the memoized dist(s, v) is deleted.  The searches read only
 // the lists and weights, which pruning does not change, so they see the
-// overlay as it was at the start of the round.
+// overlay as it was at the start of the round.  One wave per source.
 __global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t cur) {
   TailCtr *C = A.C;
   if (C->done) return;
