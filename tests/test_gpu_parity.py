@@ -179,6 +179,19 @@ def test_errors(gpu):
     with pytest.raises(gpu.ChError) as e:
         ch.query(np.array([0], np.uint32), np.array([3], np.uint32))
     assert e.value.code == gpu.CH_E_INVALID
+    # inputs large enough for the locality renumbering are validated the same
+    # way (the renumbering reads them first and must skip bad rows and heads)
+    offb, dstb, wb = synth.grid(64, 64, seed=1)
+    bad_dst = dstb.copy()
+    bad_dst[len(bad_dst) // 2] = len(offb) + 5
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(offb, bad_dst, wb)
+    assert e.value.code == gpu.CH_E_INVALID
+    bad_off = offb.copy()
+    bad_off[100] = bad_off[101] + 1  # not non-decreasing
+    with pytest.raises(gpu.ChError) as e:
+        gpu.build(bad_off, dstb, wb)
+    assert e.value.code == gpu.CH_E_INVALID
 
 
 def test_road_100k_bit_exact(gpu):
