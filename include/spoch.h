@@ -117,11 +117,11 @@ typedef struct {
   /* Exact mode: once the overlay has at most dense_tail vertices, the
    * distances of all its pairs are computed once (contraction keeps them
    * unchanged for the rest of the build) and every later witness search is
-   * answered from that table.  0 = 3072; CH_DENSE_TAIL_OFF keeps the
+   * answered from that table.  0 = 3584; CH_DENSE_TAIL_OFF keeps the
    * searches; at most 4096.  With the plain priority, one graph and no
    * recorded features, those rounds run as a device-driven sequence of
    * launches (CH_LS_TAIL; its scratch is about 24 bytes per vertex pair of
-   * the table, e.g. 226 MB at 3072 vertices).  Changes speed only, never
+   * the table, e.g. 308 MB at 3584 vertices).  Changes speed only, never
    * results. */
   uint32_t dense_tail;
 } ch_params_t;

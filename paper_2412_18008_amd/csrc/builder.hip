@@ -504,10 +504,10 @@ struct Builder {
   // round, right after the table is built (positions = current local ids);
   // nw: this round's source count.
   static constexpr uint32_t kTailBatch = 8;
-  // default table threshold: road1m builds fastest between 2560 and 3584
+  // default table threshold: road1m builds fastest at about 3584 vertices
   // (a larger table costs more Floyd-Warshall, a smaller one more rounds on
   // the general path)
-  static constexpr uint32_t kDenseTailDefault = 3072;
+  static constexpr uint32_t kDenseTailDefault = 3584;
 
   int run_tail(uint32_t &round, uint32_t nw) {
     OvBuf &O = ov[cur];
