@@ -62,8 +62,13 @@ def build(force: bool = False) -> str:
 class _Params(C.Structure):
     _fields_ = [("wps_mode", C.c_uint32), ("hop_limit", C.c_uint32),
                 ("settle_limit", C.c_uint32), ("max_rounds", C.c_uint32),
-                ("priority", C.c_uint32), ("record", C.c_uint32), ("mlp", C.c_void_p)]
+                ("priority", C.c_uint32), ("record", C.c_uint32), ("mlp", C.c_void_p),
+                ("k_ed", C.c_int32), ("k_cn", C.c_int32), ("k_depth", C.c_int32),
+                ("tiebreak", C.c_uint32)]
 
+
+TIE_HASHED_ID = 0
+TIE_RAW_ID = 1
 
 PRIO_PLAIN = 0
 PRIO_LEARNED = 1
@@ -151,7 +156,8 @@ class OracleCH:
     or ``run()`` once; inspection methods copy state into numpy arrays."""
 
     def __init__(self, off, dst, w, labels=None, seed=0, wps_mode=WPS_EXACT,
-                 hop_limit=2, settle_limit=64, max_rounds=0, mlp=None, record=False):
+                 hop_limit=2, settle_limit=64, max_rounds=0, mlp=None, record=False,
+                 k_ed=1, k_cn=0, k_depth=0, tiebreak=TIE_HASHED_ID):
         L = lib()
         off, dst, w = _csr(off, dst, w)
         n = len(off) - 1
@@ -161,7 +167,8 @@ class OracleCH:
         if wts is not None and wts.size != MLP_PARAMS:
             raise ValueError("mlp must hold 4801 weights")
         p = _Params(wps_mode, hop_limit, settle_limit, max_rounds,
-                    PRIO_LEARNED if wts is not None else PRIO_PLAIN, int(record), _p(wts))
+                    PRIO_LEARNED if wts is not None else PRIO_PLAIN, int(record), _p(wts),
+                    k_ed, k_cn, k_depth, tiebreak)
         h = C.c_void_p()
         rc = L.orc_create(n, len(dst), _p(off), _p(dst), _p(w), _p(lab), seed,
                           C.byref(p), C.byref(h))

@@ -381,6 +381,8 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
   if (p->wps_mode == ORC_WPS_SETTLED && p->settle_limit < 1) return ORC_E_INVALID;
   if (p->priority > ORC_PRIO_LEARNED || (p->priority == ORC_PRIO_LEARNED && !p->mlp))
     return ORC_E_INVALID;
+  if (p->tiebreak > ORC_TIE_RAW_ID || (p->tiebreak == ORC_TIE_RAW_ID && labels))
+    return ORC_E_INVALID;
   if (n > 0 && (off[0] != 0 || off[n] != m)) return ORC_E_INVALID;
   for (uint32_t v = 0; v < n; v++)
     if (off[v] > off[v + 1]) return ORC_E_INVALID;
@@ -426,7 +428,8 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
     return ORC_E_OOM;
   }
   for (uint32_t v = 0; v < n; v++) {
-    st->label[v] = labels ? labels[v] : orc_default_label(v, seed);
+    st->label[v] = labels ? labels[v]
+                   : (p->tiebreak == ORC_TIE_RAW_ID ? v : orc_default_label(v, seed));
     st->dist[v] = INF64;
     st->dist2[v] = INF64;
     st->level[v] = INF32;
@@ -815,13 +818,21 @@ static void score(orc_state *st, orc_round_stats *rs) {
         }
       }
     }
+    /* READING: the score combines edge difference, contracted neighbours
+     * and hierarchy depth (the paper names the terms, not their weights)
+     * with integer weights k_ed, k_cn, k_depth; 1, 0, 0 is Alg. 5's edge
+     * difference. */
+    int64_t comb = (int64_t)st->p.k_ed * p + (int64_t)st->p.k_cn * st->cn[u] +
+                   (int64_t)st->p.k_depth * st->depth[u];
     /* READING: the score is an int32; a count outside that range (degrees
      * above ~46k) saturates. */
     if (p > INT32_MAX) p = INT32_MAX;
     if (p < INT32_MIN) p = INT32_MIN;
+    if (comb > INT32_MAX) comb = INT32_MAX;
+    if (comb < INT32_MIN) comb = INT32_MIN;
     float *f = &st->feat[(size_t)u * 8];
     vertex_features(st, u, (int32_t)p, li->n, lo->n, nb, pairs, f);
-    st->P[u] = st->mlp ? orc_mlp_priority(st->mlp, f, NULL) : (int32_t)p;
+    st->P[u] = st->mlp ? orc_mlp_priority(st->mlp, f, NULL) : (int32_t)comb;
   }
 }
 

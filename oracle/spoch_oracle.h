@@ -39,6 +39,12 @@ enum {
   ORC_WPS_SETTLED = 2  /* Dijkstra stopped after settle_limit pops         */
 };
 
+/* Tie-break labels when none are given. */
+enum {
+  ORC_TIE_HASHED_ID = 0, /* label[v] = fmix32(v ^ lo32(seed) ^ hi32(seed)) */
+  ORC_TIE_RAW_ID = 1     /* label[v] = v                                   */
+};
+
 /* Priority functions. */
 enum {
   ORC_PRIO_PLAIN = 0,   /* edge difference (Alg. 4)                       */
@@ -59,6 +65,12 @@ typedef struct {
   uint32_t priority;     /* ORC_PRIO_PLAIN or ORC_PRIO_LEARNED            */
   uint32_t record;       /* keep each vertex's features at contraction   */
   const float *mlp;      /* ORC_MLP_PARAMS weights (learned priority)    */
+  /* plain priority = k_ed * ED + k_cn * CN + k_depth * depth, evaluated in
+   * 64-bit integers and saturated to int32; ED = edge difference (Alg. 5),
+   * CN = contracted neighbours, depth = hierarchy depth (1 + the largest
+   * depth of a contracted neighbour).  1, 0, 0 is the pure edge difference. */
+  int32_t k_ed, k_cn, k_depth;
+  uint32_t tiebreak;     /* ORC_TIE_*; ORC_TIE_RAW_ID needs labels == NULL */
 } orc_params;
 
 typedef struct orc_state orc_state;
