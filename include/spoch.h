@@ -124,8 +124,25 @@ typedef struct {
    * the table, e.g. 308 MB at 3584 vertices).  Changes speed only, never
    * results. */
   uint32_t dense_tail;
+  /* Integer score weights, used with CH_F_SCORE_WEIGHTS (Sec. "Step 2:
+   * Score": the score used in practice combines edge difference, vertex
+   * degree, hop distance and hierarchy depth, with weights the paper does
+   * not give).  P = k_ed * ED + k_cn * CN + k_depth * depth in 64-bit
+   * integers, saturated to int32; ED = the edge difference of Alg. 5, CN =
+   * the vertex's contracted neighbours, depth = 1 + the largest depth of a
+   * contracted neighbour (0 before any).  Without the flag, and with the
+   * learned priority, the weights are 1, 0, 0 (the pure edge difference).
+   * Weights change the contraction order, never the distances. */
+  int32_t k_ed, k_cn, k_depth;
+  /* Tie-break labels when ch_graph_t.labels is NULL (Sec. "Step 3:
+   * Select" breaks ties by vertex label): CH_TIE_HASHED_ID (0, the default:
+   * fmix32 of the id and seed) or CH_TIE_RAW_ID (label = vertex id; the
+   * graph must then carry no labels, else CH_E_INVALID). */
+  uint32_t tiebreak;
 } ch_params_t;
 #define CH_DENSE_TAIL_OFF 1u
+#define CH_TIE_HASHED_ID 0u
+#define CH_TIE_RAW_ID 1u
 
 /* ---- learned priority ----
  * An MLP 8 -> 64 -> 64 -> 1 with GELU maps eight features of a rescored
@@ -148,6 +165,7 @@ typedef struct {
                                     * trip per round, as in the earlier rounds (the
                                     * default runs them as one device-driven sequence;
                                     * same results) */
+#define CH_F_SCORE_WEIGHTS 0x40u /* score = k_ed ED + k_cn CN + k_depth depth (ch_params_t) */
 #define CH_F_KEEP_ORDER 0x20u  /* build on the input's vertex numbering (the default
                                 * renumbers graphs of 4096 or more vertices into
                                 * clusters of nearby vertices first and maps the

@@ -52,7 +52,9 @@ class Params(C.Structure):
                 ("flags", C.c_uint32), ("group", C.c_uint32), ("stream", C.c_void_p),
                 ("ls_sparse", C.c_uint32), ("ls_dense", C.c_uint32),
                 ("dense_deg10", C.c_uint32), ("priority", C.c_uint32), ("mlp", C.c_void_p),
-                ("hop_limit", C.c_uint32), ("dense_tail", C.c_uint32)]
+                ("hop_limit", C.c_uint32), ("dense_tail", C.c_uint32),
+                ("k_ed", C.c_int32), ("k_cn", C.c_int32), ("k_depth", C.c_int32),
+                ("tiebreak", C.c_uint32)]
 
 
 CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
@@ -60,6 +62,8 @@ CH_MLP_PARAMS = 4801
 CH_F_RECORD_FEATURES = 0x8
 CH_F_TAIL_STEPWISE = 0x10
 CH_F_KEEP_ORDER = 0x20
+CH_F_SCORE_WEIGHTS = 0x40
+CH_TIE_HASHED_ID, CH_TIE_RAW_ID = 0, 1
 CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
 
 
@@ -257,11 +261,14 @@ class CH:
 
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
-          record=False, hop=0, dense_tail=0, tail_stepwise=False, keep_order=False):
+          record=False, hop=0, dense_tail=0, tail_stepwise=False, keep_order=False,
+          score_weights=None, raw_id=False):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
     selects the hop-bounded witness search with walks of at most `hop` arcs;
     tail_stepwise runs the table rounds one launch per step; keep_order
-    builds on the input's numbering (no locality renumbering)."""
+    builds on the input's numbering (no locality renumbering); score_weights
+    = (k_ed, k_cn, k_depth) sets the integer score weights; raw_id labels
+    every vertex by its id."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
     pd, kd = _ptr(dst, np.uint32)
@@ -272,7 +279,9 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     g = Graph(n, m, po, pd, pw, pl)
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (CH_F_STATS if stats else 0) | (
         0 if query_index else CH_F_NO_QUERY_INDEX) | (CH_F_RECORD_FEATURES if record else 0) | (
-        CH_F_TAIL_STEPWISE if tail_stepwise else 0) | (CH_F_KEEP_ORDER if keep_order else 0)
+        CH_F_TAIL_STEPWISE if tail_stepwise else 0) | (CH_F_KEEP_ORDER if keep_order else 0) | (
+        CH_F_SCORE_WEIGHTS if score_weights is not None else 0)
+    k_ed, k_cn, k_depth = score_weights if score_weights is not None else (1, 0, 0)
     if stream is None and dev:
         import torch
 
@@ -283,14 +292,15 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
                ls_sparse, ls_dense, dense_deg10,
                CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
-               None if wts is None else wts.ctypes.data, hop, dense_tail)
+               None if wts is None else wts.ctypes.data, hop, dense_tail, k_ed, k_cn, k_depth,
+               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
 
 
 def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=True,
-                stream=None, hop=0, dense_tail=0):
+                stream=None, hop=0, dense_tail=0, score_weights=None, raw_id=False):
     """ch_build_batch on a list of (off, dst, w) CSR graphs (numpy arrays or
     torch CUDA tensors); returns one CH per graph."""
     k = len(graphs)
@@ -306,9 +316,12 @@ def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=
         n = (off.numel() if dev else len(ko)) - 1
         m = dst.numel() if dev else len(kd)
         arr[i] = Graph(n, m, po, pd, pw, pl)
-    flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX)
+    flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX) | (
+        CH_F_SCORE_WEIGHTS if score_weights is not None else 0)
+    k_ed, k_cn, k_depth = score_weights if score_weights is not None else (1, 0, 0)
     p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
-               0, 0, 0, CH_PRIO_PLAIN, None, hop, dense_tail)
+               0, 0, 0, CH_PRIO_PLAIN, None, hop, dense_tail, k_ed, k_cn, k_depth,
+               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID)
     outs = (C.c_void_p * max(k, 1))()
     _check(lib().ch_build_batch(arr, k, C.byref(p), outs), "ch_build_batch")
     return [CH(C.c_void_p(outs[i])) for i in range(k)]

@@ -91,6 +91,7 @@ struct Builder {
   DBuf ekey, ekey_alt, eidx, eidx_alt, ew, elab, emid, ehead, eheads, ukey, uw, umid, rkey,
       rkey_alt, ridx, ridx_alt;
   DBuf ovf1, ovf2, gtabs;
+  DBuf prw;  // weights of the arcs pruned in the current round (overlay arc index)
   // all-pairs table of the small overlay (exact mode): matrix tab_N^2,
   // table position of each original id, original id of each position
   DBuf tab_D, tab_pos, tab_gid, tab_posl;
@@ -128,7 +129,7 @@ struct Builder {
     DBuf *all[] = {&aflag, &aflag_next, &wflag, &F, &S, &newA, &key, &paircnt, &newid, &cnt,
                    &vw, &va, &vf, &cnt2, &cnt3, &rowb, &memo, &memo_spare, &alive_g, &cup, &cdn, &cpair, &ekey, &ekey_alt,
                    &eidx, &eidx_alt, &ew, &elab, &emid, &ehead, &eheads, &ukey, &uw, &umid,
-                   &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &dctr, &tmp,
+                   &rkey, &rkey_alt, &ridx, &ridx_alt, &ovf1, &ovf2, &gtabs, &prw, &dctr, &tmp,
                    &f_cn, &f_depth, &f_ws, &f_feat, &mlpw, &tab_D, &tab_pos, &tab_gid, &tab_posl,
                    &t_bits, &t_W, &t_MID, &t_ol, &t_il, &t_len, &t_SC, &t_touch, &t_vert,
                    &t_flags, &t_lists, &t_ctr, &t_rec, &r_order, &r_inv, &r_a, &r_b, &r_c,
@@ -145,13 +146,24 @@ struct Builder {
 
   DevCtr *dc() { return dctr.as<DevCtr>(); }
 
+  // the learned priority and recorded features need every feature; nonzero
+  // k_cn or k_depth need the contracted-neighbour count and depth
+  bool need_feat() const {
+    return prm.priority == CH_PRIO_LEARNED || (prm.flags & CH_F_RECORD_FEATURES);
+  }
+  bool need_cn_depth() const { return need_feat() || prm.k_cn != 0 || prm.k_depth != 0; }
+
   FeatState fstate() {
     FeatState f;
-    f.cn = f_cn.as<uint32_t>();
-    f.depth = f_depth.as<uint32_t>();
-    f.ws = f_ws.as<uint32_t>();
-    f.feat = f_feat.as<float>();
+    const bool cd = need_cn_depth(), ft = need_feat();
+    f.cn = cd ? f_cn.as<uint32_t>() : nullptr;
+    f.depth = cd ? f_depth.as<uint32_t>() : nullptr;
+    f.ws = ft ? f_ws.as<uint32_t>() : nullptr;
+    f.feat = ft ? f_feat.as<float>() : nullptr;
     f.rec = (prm.flags & CH_F_RECORD_FEATURES) ? ch->rec.as<float>() : nullptr;
+    f.k_ed = prm.k_ed;
+    f.k_cn = prm.k_cn;
+    f.k_depth = prm.k_depth;
     return f;
   }
 
@@ -313,7 +325,8 @@ struct Builder {
       if (hctr->bad & 4) return set_error(CH_E_INVALID, "labels are not distinct");
     } else {
       const uint32_t mix = (uint32_t)prm.seed ^ (uint32_t)(prm.seed >> 32);
-      k_default_labels<<<grid(n), 256, 0, st>>>(n, mix, ch->label.as<uint32_t>());
+      k_default_labels<<<grid(n), 256, 0, st>>>(n, mix, prm.tiebreak == CH_TIE_RAW_ID,
+                                                ch->label.as<uint32_t>());
       HIP_TRY(hipGetLastError());
     }
     if (renum) {  // labels in the build's order; the input-order ones wait in r_lab
@@ -707,7 +720,7 @@ struct Builder {
           v, list, nl, aflag.as<uint8_t>(), mref(),
           tier == 1 ? &d->ls : &d->ls2, nl_dev, tier == 1 ? &d->work1 : &d->work2,
           tier == 1 ? ovf1.as<uint32_t>() : ovf2.as<uint32_t>(),
-          tier == 1 ? &d->novf1 : &d->novf2, chunk, f_ws.as<uint32_t>(), &d->err,
+          tier == 1 ? &d->novf1 : &d->novf2, chunk, fstate().ws, &d->err,
           prm.hop_limit);
     };
     if (hop) go(k_local_search<G, CAP, true>);
@@ -720,7 +733,8 @@ struct Builder {
   }
   template <int G>
   void launch_prune(const Overlay &v, uint32_t nw) {
-    k_prune<G><<<ggrid<G>(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, mref(), &dc()->pruned, &dc()->err);
+    k_prune<G><<<ggrid<G>(nw), 256, 0, st>>>(v, vw.as<uint32_t>(), nw, mref(), &dc()->pruned,
+                                              prw.as<uint32_t>(), &dc()->err);
   }
   template <int G>
   void launch_select(const Overlay &v) {
@@ -820,14 +834,18 @@ struct Builder {
     HIP_TRY(fill_u32(ch->level.as<uint32_t>(), SP_INF32, n, st));
     HIP_TRY(hipMemsetAsync(ch->score.p, 0, (size_t)n * 4, st));
     HIP_TRY(fill_u8(alive_g.as<uint8_t>(), 1, n, st));
-    HIP_TRY(f_cn.ensure(std::max<uint64_t>(n, 1) * 4));
-    HIP_TRY(f_depth.ensure(std::max<uint64_t>(n, 1) * 4));
-    HIP_TRY(f_ws.ensure(std::max<uint64_t>(n, 1) * 4));
-    HIP_TRY(f_feat.ensure(std::max<uint64_t>(n, 1) * 32));
-    HIP_TRY(hipMemsetAsync(f_cn.p, 0, (size_t)n * 4, st));
-    HIP_TRY(hipMemsetAsync(f_depth.p, 0, (size_t)n * 4, st));
-    HIP_TRY(hipMemsetAsync(f_ws.p, 0, (size_t)n * 4, st));
-    HIP_TRY(hipMemsetAsync(f_feat.p, 0, (size_t)n * 32, st));
+    if (need_cn_depth()) {
+      HIP_TRY(f_cn.ensure(std::max<uint64_t>(n, 1) * 4));
+      HIP_TRY(f_depth.ensure(std::max<uint64_t>(n, 1) * 4));
+      HIP_TRY(hipMemsetAsync(f_cn.p, 0, (size_t)n * 4, st));
+      HIP_TRY(hipMemsetAsync(f_depth.p, 0, (size_t)n * 4, st));
+    }
+    if (need_feat()) {
+      HIP_TRY(f_ws.ensure(std::max<uint64_t>(n, 1) * 4));
+      HIP_TRY(f_feat.ensure(std::max<uint64_t>(n, 1) * 32));
+      HIP_TRY(hipMemsetAsync(f_ws.p, 0, (size_t)n * 4, st));
+      HIP_TRY(hipMemsetAsync(f_feat.p, 0, (size_t)n * 32, st));
+    }
     if (prm.flags & CH_F_RECORD_FEATURES) {
       HIP_TRY(ch->rec.ensure(std::max<uint64_t>(n, 1) * 32));
       HIP_TRY(hipMemsetAsync(ch->rec.p, 0, (size_t)n * 32, st));
@@ -892,7 +910,8 @@ struct Builder {
       {
         const uint32_t lim = prm.dense_tail == 0 ? kDenseTailDefault : prm.dense_tail;
         const bool fused = prm.wps_mode == CH_WPS_EXACT && prm.dense_tail != CH_DENSE_TAIL_OFF &&
-                           prm.priority == CH_PRIO_PLAIN && !batch &&
+                           prm.priority == CH_PRIO_PLAIN && !batch && prm.k_ed == 1 &&
+                           prm.k_cn == 0 && prm.k_depth == 0 &&
                            !(prm.flags & (CH_F_RECORD_FEATURES | CH_F_TAIL_STEPWISE));
         if (fused && !tab_on && O.n && O.n <= lim && O.n <= kTailMaxN) {
           TRY(build_table(v));
@@ -921,7 +940,7 @@ struct Builder {
         k_ls_table<<<(unsigned)std::min<uint64_t>(nw, (uint64_t)cus * 8), 64, 0, st>>>(
             v, vw.as<uint32_t>(), nw, aflag.as<uint8_t>(), mref(), &dc()->ls, tab_D.as<uint32_t>(), tab_N, tab_n0,
             tab_pos.as<uint32_t>(), tab_gid.as<uint32_t>(), tab_posl.as<uint32_t>(),
-            alive_g.as<uint8_t>(), f_ws.as<uint32_t>(), &dc()->err);
+            alive_g.as<uint8_t>(), fstate().ws, &dc()->err);
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
       } else if (nw) {
@@ -946,13 +965,14 @@ struct Builder {
         HIP_TRY(hipGetLastError());
       }
       // Steps 1 (pruning) to 4 (contraction counts) run before the searches
-      // are known to be complete; when a source needed the global tier they
-      // run again after it (pruning skips arcs it already pruned, the rest
-      // overwrite their outputs).
+      // are known to be complete; when a source needed the global tier, the
+      // pruning is undone (k_unprune) before that search and all of them run
+      // again after it (the rest overwrite their outputs).
       const int Gp = prm.group ? (int)prm.group : pick_group(avgdeg);
       const int Gs = prm.group ? (int)prm.group : pick_group(avgdeg * avgdeg / 4.0);
       const int Gsel = prm.group ? (int)prm.group : pick_group(avgdeg);
       const uint32_t ncap = O.n;  // bound on the selected count
+      HIP_TRY(prw.ensure(std::max<size_t>(O.m, 1) * 4));
       HIP_TRY(cup.ensure(((size_t)ncap * 2 + 1) * 4));
       HIP_TRY(cdn.ensure(((size_t)ncap * 2 + 1) * 4));
       HIP_TRY(cpair.ensure(((size_t)ncap * 2 + 1) * 4));
@@ -1024,9 +1044,18 @@ struct Builder {
           if (hop) HIP_TRY(fill_u32(b + 6ull * cap, SP_EMPTY32, cap, st));     // dist2
           HIP_TRY(hipMemsetAsync(b + arrays * cap, 0, 4 * 4, st));      // counters
         }
+        // the global tier searches the overlay as the other searches saw it:
+        // this round's optimistic pruning is undone first and redone (and
+        // recounted) by the second pass below
+        if (nw) {
+          HIP_TRY(hipMemsetAsync(&dc()->pruned, 0, sizeof(unsigned long long), st));
+          k_unprune<<<grid((uint64_t)nw * kWave), 256, 0, st>>>(v, vw.as<uint32_t>(), nw,
+                                                               prw.as<uint32_t>(), &dc()->err);
+          HIP_TRY(hipGetLastError());
+        }
         auto global = hop ? k_local_search_global<true> : k_local_search_global<false>;
         global<<<(unsigned)ntab, 64, 0, st>>>(
-            v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), mref(), &dc()->ls2, gtabs.as<uint32_t>(), cap, f_ws.as<uint32_t>(),
+            v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), mref(), &dc()->ls2, gtabs.as<uint32_t>(), cap, fstate().ws,
             &dc()->err, prm.hop_limit);
         HIP_TRY(hipGetLastError());
         TRY(after_search());
@@ -1216,6 +1245,14 @@ static int check_params(const ch_params_t *p, ch_params_t &prm) {
   if (prm.priority > CH_PRIO_LEARNED) return set_error(CH_E_INVALID, "unknown priority");
   if (prm.priority == CH_PRIO_LEARNED && !prm.mlp)
     return set_error(CH_E_INVALID, "the learned priority needs mlp weights");
+  if (prm.tiebreak > CH_TIE_RAW_ID) return set_error(CH_E_INVALID, "unknown tiebreak");
+  // without CH_F_SCORE_WEIGHTS the score is the plain edge difference; the
+  // learned priority replaces the score, so it takes no weights
+  if (!(prm.flags & CH_F_SCORE_WEIGHTS) || prm.priority == CH_PRIO_LEARNED) {
+    prm.k_ed = 1;
+    prm.k_cn = 0;
+    prm.k_depth = 0;
+  }
   return CH_OK;
 }
 
@@ -1298,6 +1335,8 @@ int build_ch(const ch_graph_t *g, const ch_params_t *p, ch_t **out) {
   if (g->n == 0xFFFFFFFFu) return set_error(CH_E_INVALID, "n must be at most 0xFFFFFFFE");
   if (!g->offsets || (g->m && (!g->dst || !g->w)))
     return set_error(CH_E_INVALID, "offsets, dst and w must not be NULL");
+  if (g->labels && prm.tiebreak == CH_TIE_RAW_ID)
+    return set_error(CH_E_INVALID, "CH_TIE_RAW_ID takes no labels");
   ch_s *ch = nullptr;
   TRY(new_ch((hipStream_t)prm.stream, true, &ch));
   ch->n = g->n;
@@ -1342,6 +1381,8 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
   }
   if (any_labels && !all_labels)
     return set_error(CH_E_INVALID, "either every graph of a batch has labels or none has");
+  if (any_labels && prm.tiebreak == CH_TIE_RAW_ID)
+    return set_error(CH_E_INVALID, "CH_TIE_RAW_ID takes no labels");
   const uint32_t n = vb[k];
   const uint64_t m = ab[k];
   if (m >= 0xFFFFFFFFull)
@@ -1414,6 +1455,7 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
   if (!any_labels && n) {
     const uint32_t mix = (uint32_t)prm.seed ^ (uint32_t)(prm.seed >> 32);
     k_batch_default_labels<<<gr, 256, 0, st>>>(n, k, d_vb.as<uint32_t>(), mix,
+                                               prm.tiebreak == CH_TIE_RAW_ID,
                                                U->label.as<uint32_t>());
     BTRY(hipGetLastError());
   }

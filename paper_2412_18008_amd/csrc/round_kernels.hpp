@@ -157,10 +157,12 @@ __global__ void k_swap_key(const uint64_t *__restrict__ in, const uint32_t *mcou
   }
 }
 
-__global__ void k_default_labels(uint32_t n, uint32_t mixseed, uint32_t *__restrict__ lab) {
+// Default labels: fmix32(v ^ mixseed), or the id itself (raw).
+__global__ void k_default_labels(uint32_t n, uint32_t mixseed, bool raw,
+                                 uint32_t *__restrict__ lab) {
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    lab[v] = fmix32(v ^ mixseed);
+    lab[v] = raw ? v : fmix32(v ^ mixseed);
 }
 
 __global__ void k_labels_to_keys(uint32_t n, const uint32_t *__restrict__ lab,
@@ -346,6 +348,7 @@ template <int G>
 __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__restrict__ vw,
                                                uint32_t nw, MemoRef memo,
                                                unsigned long long *__restrict__ npruned,
+                                               uint32_t *__restrict__ pw,
                                                uint32_t *__restrict__ err) {
   const uint32_t ngroups = gridDim.x * (blockDim.x / G);
   const uint32_t g0 = blockIdx.x * (blockDim.x / G) + threadIdx.x / G;
@@ -377,6 +380,7 @@ __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__res
         const uint2 a = arc[q];
         // arcs pruned by an earlier pass of this round stay as they are
         if (!act[q] || a.y == SP_INF32 || dd[q] == SP_INF32 || a.y <= dd[q]) continue;
+        pw[eb + q * G] = a.y;  // kept until the round's searches are known complete
         ov.farc[eb + q * G].y = SP_INF32;
         const uint32_t end = ov.roff[a.x + 1];
         uint32_t lo = ov.roff[a.x], hi = end;
@@ -393,6 +397,37 @@ __global__ void __launch_bounds__(256) k_prune(Overlay ov, const uint32_t *__res
   }
   c = gsum64<kWave>(c);
   if (lane_id() == 0 && c) atomicAdd(npruned, (unsigned long long)c);
+}
+
+// Undoes this round's pruning (the weights k_prune saved in pw) before a
+// search that has to see the same overlay as the round's other searches:
+// Alg. 4 prunes only once every source has been searched.  Every arc with
+// weight SP_INF32 in the overlay was pruned in this round (the rebuild drops
+// pruned arcs).  A wave per source, lanes over its out-arcs.
+__global__ void __launch_bounds__(256) k_unprune(Overlay ov, const uint32_t *__restrict__ vw,
+                                                 uint32_t nw, const uint32_t *__restrict__ pw,
+                                                 uint32_t *__restrict__ err) {
+  const uint32_t nwaves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t k = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; k < nw;
+       k += nwaves) {
+    const uint32_t s = vw[k];
+    const uint32_t e1 = ov.foff[s + 1];
+    for (uint32_t e = ov.foff[s] + lane_id(); e < e1; e += kWave) {
+      const uint2 a = ov.farc[e];
+      if (a.y != SP_INF32) continue;
+      const uint32_t wt = pw[e];
+      ov.farc[e].y = wt;
+      const uint32_t end = ov.roff[a.x + 1];
+      uint32_t lo = ov.roff[a.x], hi = end;
+      while (lo < hi) {
+        const uint32_t md = (lo + hi) >> 1;
+        if (ov.rarc[md].x < s) lo = md + 1;
+        else hi = md;
+      }
+      if (lo < end && ov.rarc[lo].x == s) ov.rarc[lo].y = wt;
+      else atomicOr(err, kErrCapacity);  // reverse twin missing: internal error
+    }
+  }
 }
 
 // ===========================================================================
@@ -500,13 +535,17 @@ __device__ __forceinline__ uint3 count_neighbours(const Overlay &ov, uint32_t u)
   return make_uint3(cout, cin, cout + only_in);
 }
 
-// Per-vertex feature state of the learned priority (original ids).
+// Per-vertex state of the score terms beyond the edge difference (original
+// ids).  cn and depth are kept when the learned priority, recorded features
+// or a nonzero k_cn / k_depth need them; ws and feat only for the learned
+// priority and recorded features; null pointers skip that state.
 struct FeatState {
-  uint32_t *cn;     // contracted neighbours
-  uint32_t *depth;  // hierarchy depth
-  uint32_t *ws;     // vertices reached by the latest witness search
-  float *feat;      // current features, 8 per vertex
+  uint32_t *cn;     // contracted neighbours (or null)
+  uint32_t *depth;  // hierarchy depth (or null)
+  uint32_t *ws;     // vertices reached by the latest witness search (or null)
+  float *feat;      // current features, 8 per vertex (or null)
   float *rec;       // features at contraction (or null)
+  int32_t k_ed, k_cn, k_depth;  // integer score weights (1, 0, 0: edge difference)
 };
 
 // x / (x + c) in single precision (the learned priority's squash).
@@ -527,12 +566,15 @@ __global__ void __launch_bounds__(256) k_score(Overlay ov, const uint32_t *__res
     const uint32_t pairs = count_pairs<G>(ov, memo, u, &probes);
     const uint3 deg = count_neighbours<G>(ov, u);  // out, in, |N(u)|
     if (glane<G>() == 0) {
-      int64_t p = (int64_t)pairs - (int64_t)deg.z;
-      p = p > INT32_MAX ? INT32_MAX : (p < INT32_MIN ? INT32_MIN : p);
-      const int32_t ed = (int32_t)p;
-      P[u] = ed;
-      paircnt[u] = pairs;
+      const int64_t e64 = (int64_t)pairs - (int64_t)deg.z;
       const uint32_t g = ov.gid[u];
+      // k_ed ED + k_cn CN + k_depth depth in 64 bits, saturated to int32
+      int64_t p = (int64_t)fs.k_ed * e64;
+      if (fs.cn) p += (int64_t)fs.k_cn * fs.cn[g] + (int64_t)fs.k_depth * fs.depth[g];
+      P[u] = (int32_t)(p > INT32_MAX ? INT32_MAX : (p < INT32_MIN ? INT32_MIN : p));
+      paircnt[u] = pairs;
+      if (!fs.feat) continue;
+      const int32_t ed = (int32_t)(e64 > INT32_MAX ? INT32_MAX : (e64 < INT32_MIN ? INT32_MIN : e64));
       float *f = fs.feat + (size_t)g * 8;
       const uint32_t mag = ed < 0 ? (uint32_t)(-(int64_t)ed) : (uint32_t)ed;
       f[0] = __fdiv_rn((float)ed, __fadd_rn((float)mag, 8.0f));
@@ -708,7 +750,7 @@ __global__ void __launch_bounds__(256) k_contract(
     }
     if (fs.rec)
       for (int i = gl; i < 8; i += G) fs.rec[(size_t)gu * 8 + i] = fs.feat[(size_t)gu * 8 + i];
-    const uint32_t dnext = fs.depth[gu] + 1;
+    const uint32_t dnext = fs.depth ? fs.depth[gu] + 1 : 0u;
     // out-arcs -> upward set
     uint64_t pos = up_base + pup[k];
     const uint32_t o0 = ov.foff[u], o1 = ov.foff[u + 1];
@@ -725,9 +767,11 @@ __global__ void __launch_bounds__(256) k_contract(
         up.w[at] = b.y;
         up.m[at] = ov.fmid[e];
         newA[b.x] = 1;
-        const uint32_t gv = ov.gid[b.x];
-        atomicAdd(&fs.cn[gv], 1u);
-        atomicMax(&fs.depth[gv], dnext);
+        if (fs.cn) {
+          const uint32_t gv = ov.gid[b.x];
+          atomicAdd(&fs.cn[gv], 1u);
+          atomicMax(&fs.depth[gv], dnext);
+        }
         kill_twin(ov.roff, ov.rarc, b.x, u);  // (u -> b.x) in the reverse row of b.x
       }
       pos += __popcll(msk);
@@ -748,18 +792,20 @@ __global__ void __launch_bounds__(256) k_contract(
         dn.w[at] = a.y;
         dn.m[at] = ov.rmid[e];
         newA[a.x] = 1;
-        // one more contracted neighbour, unless a.x is also a live
-        // out-neighbour (counted above)
-        uint32_t lo = o0, hi = o1;
-        while (lo < hi) {
-          const uint32_t md = (lo + hi) >> 1;
-          if (ov.farc[md].x < a.x) lo = md + 1;
-          else hi = md;
+        if (fs.cn) {
+          // one more contracted neighbour, unless a.x is also a live
+          // out-neighbour (counted above)
+          uint32_t lo = o0, hi = o1;
+          while (lo < hi) {
+            const uint32_t md = (lo + hi) >> 1;
+            if (ov.farc[md].x < a.x) lo = md + 1;
+            else hi = md;
+          }
+          const bool both = lo < o1 && ov.farc[lo].x == a.x && ov.farc[lo].y != SP_INF32;
+          const uint32_t gv = ov.gid[a.x];
+          if (!both) atomicAdd(&fs.cn[gv], 1u);
+          atomicMax(&fs.depth[gv], dnext);
         }
-        const bool both = lo < o1 && ov.farc[lo].x == a.x && ov.farc[lo].y != SP_INF32;
-        const uint32_t gv = ov.gid[a.x];
-        if (!both) atomicAdd(&fs.cn[gv], 1u);
-        atomicMax(&fs.depth[gv], dnext);
         kill_twin(ov.foff, ov.farc, a.x, u);  // (a.x -> u) in the forward row of a.x
       }
       pos += __popcll(msk);
@@ -899,12 +945,14 @@ __global__ void k_batch_arcs(uint64_t m, uint32_t k, const uint32_t *__restrict_
   }
 }
 
-// Default labels per graph: fmix32(local id ^ mix).
+// Default labels per graph: fmix32(local id ^ mix), or the local id (raw).
 __global__ void k_batch_default_labels(uint32_t n, uint32_t k, const uint32_t *__restrict__ vbase,
-                                       uint32_t mix, uint32_t *__restrict__ lab) {
+                                       uint32_t mix, bool raw, uint32_t *__restrict__ lab) {
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
-    lab[v] = fmix32((v - vbase[graph_of(vbase, k, v)]) ^ mix);
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint32_t l = v - vbase[graph_of(vbase, k, v)];
+    lab[v] = raw ? l : fmix32(l ^ mix);
+  }
 }
 
 // key = (graph << 32) | label, for the per-graph distinctness check.

@@ -57,6 +57,14 @@ def test_null_and_invalid_arguments(binding):
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
     p = binding.Params(7, 0, 0, 0, 0, None, 0, 0, 0, 0, None)
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_UNSUPPORTED
+    p = binding.Params(tiebreak=2)  # unknown tie-break
+    assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
+    lab = np.zeros(1, np.uint32)
+    gl = binding.Graph(1, 0, off.ctypes.data, None, None, lab.ctypes.data)
+    p = binding.Params(tiebreak=binding.CH_TIE_RAW_ID)  # raw ids and labels together
+    assert L.ch_build(C.byref(gl), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
+    assert "RAW_ID" in L.ch_last_error().decode()
+    assert L.ch_build_batch(C.byref(gl), 1, C.byref(p), C.byref(h)) == binding.CH_E_INVALID
     g = binding.Graph(0xFFFFFFFF, 0, off.ctypes.data, None, None, None)
     assert L.ch_build(C.byref(g), None, C.byref(h)) == binding.CH_E_INVALID
     assert L.ch_query_batch(None, None, None, 0, None, 0, None) == binding.CH_E_INVALID

@@ -95,3 +95,19 @@ def test_hop_global_search_tier(gpu):
     s, t = synth.queries(n, 300, seed=2)
     od, _ = o.query_batch(s, t)
     assert np.array_equal(ch.query(s, t), od)
+
+
+def test_hop_global_search_tier_after_pruning(gpu):
+    # as the exact-mode test: the arc pruned in round 0 is still there for
+    # the global-tier searches, which in hop mode may need it (a shorter
+    # witness with more arcs does not replace it within H arcs)
+    from test_gpu_parity import star_with_prunable_arc
+
+    off, dst, w = star_with_prunable_arc(3200, seed=5)
+    n = len(off) - 1
+    o, ch = _hop_case("star3200+arc", off, dst, w, synth.labels(n, 3), gpu, 2)
+    rs = ch.round_stats()[0]
+    assert rs["n_ls_global"] > 0 and rs["n_pruned"] > 0, rs
+    s, t = synth.queries(n, 300, seed=2)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(ch.query(s, t), od)

@@ -295,6 +295,94 @@ def test_global_search_tier(gpu):
     assert np.array_equal(ch.query(s, t), od)
 
 
+def _wcase(name, off, dst, w, labels, gpu, okw, gkw):
+    """Oracle and GPU builds with their own keyword sets, compared whole."""
+    print(f"[parity] {name} n={len(off) - 1} m={len(dst)} {okw}", flush=True)
+    o = oracle.OracleCH(off, dst, w, labels=labels, **okw).run()
+    ch = gpu.build(off, dst, w, labels=labels, stats=True, **gkw)
+    a, b = oracle_export(o), gpu_export(ch)
+    assert_same_ch(a, b, name)
+    assert_export_order(b)
+    assert ch.summary["rounds"] == o.rounds
+    assert gpu_round_counts(ch) == oracle_round_counts(o), name
+    return o, ch
+
+
+WEIGHTS = [(1, 2, 5), (3, -1, 0), (0, 1, 0), (-1, 0, 4), (2, 0, -3)]
+
+
+def test_score_weights_bit_exact(gpu):
+    # integer score k_ed ED + k_cn CN + k_depth depth (the paper's combined
+    # score, weights ours): same order, scores and arcs as the oracle
+    for i, (name, off, dst, w) in enumerate(small_cases()):
+        kw = WEIGHTS[i % len(WEIGHTS)]
+        okw = dict(k_ed=kw[0], k_cn=kw[1], k_depth=kw[2])
+        _wcase(f"{name} {kw}", off, dst, w, synth.labels(len(off) - 1, 17), gpu, okw,
+               dict(score_weights=kw))
+    # a larger graph through the general rounds, the table rounds (step by
+    # step: the device-driven tail takes only the plain edge difference) and
+    # with the table off; default labels; hop mode too
+    off, dst, w = synth.road_like(30_000, seed=8)
+    for kw in WEIGHTS[:2]:
+        okw = dict(k_ed=kw[0], k_cn=kw[1], k_depth=kw[2])
+        _, ch = _wcase(f"road30k {kw}", off, dst, w, None, gpu, okw, dict(score_weights=kw))
+        assert any(r["ls_tier1"] == gpu.CH_LS_TABLE for r in ch.round_stats())
+        _wcase(f"road30k {kw} no table", off, dst, w, None, gpu, okw,
+               dict(score_weights=kw, dense_tail=gpu.CH_DENSE_TAIL_OFF))
+    kw = WEIGHTS[0]
+    _wcase(f"road30k {kw} hop 2", off, dst, w, None, gpu,
+           dict(k_ed=kw[0], k_cn=kw[1], k_depth=kw[2], wps_mode=oracle.WPS_HOP, hop_limit=2),
+           dict(score_weights=kw, hop=2))
+    # weights 1, 0, 0 are the plain edge difference
+    o = oracle.OracleCH(off, dst, w).run()
+    assert_same_ch(oracle_export(o), gpu_export(gpu.build(off, dst, w, score_weights=(1, 0, 0))),
+                   "weights 1 0 0")
+
+
+def test_raw_id_tiebreak_bit_exact(gpu):
+    # CH_TIE_RAW_ID: label = vertex id (on the input numbering, also when the
+    # library renumbers inputs of 4096 or more vertices internally)
+    cases = small_cases()[:6] + [("grid64", *synth.config_grid64(seed=0)),
+                                 ("road6000", *synth.road_like(6000, seed=3))]
+    for name, off, dst, w in cases:
+        _wcase(f"{name} raw", off, dst, w, None, gpu, dict(tiebreak=oracle.TIE_RAW_ID),
+               dict(raw_id=True))
+    graphs = [c[1:] for c in cases[:4]]
+    outs = gpu.build_batch(graphs, raw_id=True, score_weights=WEIGHTS[0])
+    for (name, off, dst, w), ch in zip(cases[:4], outs):
+        o = oracle.OracleCH(off, dst, w, tiebreak=oracle.TIE_RAW_ID, k_ed=1, k_cn=2,
+                            k_depth=5).run()
+        assert_same_ch(oracle_export(o), gpu_export(ch), f"batch {name}")
+
+
+def star_with_prunable_arc(d, seed):
+    """The star of synth.star plus one leaf-to-leaf arc a -> b (weight 1) with
+    w(0, a) + 1 < w(0, b): the centre's round-0 search reaches b through a,
+    so the arc 0 -> b is pruned in round 0, while every leaf's search (which
+    spans the whole star) runs in the global tier."""
+    off, dst, w = synth.star(d, seed=seed)
+    src, dd, ww = synth.arcs_of(off, dst, w)
+    cw = ww[src == 0]
+    leaves = dd[src == 0]
+    a, b = int(leaves[np.argmin(cw)]), int(leaves[np.argmax(cw)])
+    assert cw.min() + 1 < cw.max()
+    return synth.to_csr(d + 1, np.append(src, a), np.append(dd, b), np.append(ww, 1))
+
+
+def test_global_search_tier_after_pruning(gpu):
+    # the global-tier searches of round 0 must see the arc the round prunes
+    # (pruning follows all searches of the round)
+    off, dst, w = star_with_prunable_arc(3200, seed=5)
+    n = len(off) - 1
+    o, ch = _case("star3200+arc", off, dst, w, synth.labels(n, 3), gpu,
+                  dense_tail=gpu.CH_DENSE_TAIL_OFF)
+    rs = ch.round_stats()[0]
+    assert rs["n_ls_global"] > 0 and rs["n_pruned"] > 0, rs
+    s, t = synth.queries(n, 500, seed=2)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(ch.query(s, t), od)
+
+
 def test_batch_equals_single_builds(gpu):
     graphs = [synth.random_geometric_small(800, seed=1), synth.grid(9, 11, seed=2),
               synth.random_digraph(60, 240, seed=3, wmax=9, zero_frac=0.1, loops=True),
