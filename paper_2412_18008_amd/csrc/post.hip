@@ -944,7 +944,12 @@ __global__ void __launch_bounds__(64 * NW) k_query(
               }
             }
           }
+          // a full table fails every further insert only after probing all
+          // of it: leave the step once an overflow is flagged (the query
+          // goes to the next tier anyway)
+          if (__builtin_amdgcn_readfirstlane(qld<GM>(&S.ovf))) break;
         }
+        if (__builtin_amdgcn_readfirstlane(qld<GM>(&S.ovf))) break;
       }
       fresh0 = gsum<kWave>(fresh0);
       fresh1 = gsum<kWave>(fresh1);
