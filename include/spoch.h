@@ -275,6 +275,28 @@ int ch_query_batch(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_
 int ch_query_batch_stats(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                          uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ch_query_batch_stats
+ * without any allocation, with the same results.  s, t, dist and visited
+ * (visited may be NULL) must be device arrays: flags must include
+ * CH_Q_ON_DEVICE, else CH_E_INVALID.  Every scratch array (counters,
+ * overflow lists, the global-memory search tables) lives in one fixed device
+ * array of CH_NOALLOC_SCRATCH_BYTES per GPU, reserved where the library is
+ * loaded and held until the process ends.  All calls on one GPU share it and
+ * it keeps the last call's contents, so calls that overlap on one GPU (from
+ * other threads or on other streams) race; calls on one ch_t must not
+ * overlap either.  Queries run in passes of 2^20.  Its tables hold upward
+ * search spaces of up to 14,336 vertices per direction, then (one query at
+ * a time) of up to 917,504 -- every search space of a CH with at most
+ * 524,287 vertices; a query with a larger one makes the call return
+ * CH_E_LIMIT (ch_query_batch has no such limit).  Distances of other queries
+ * may have been written when the call fails.
+ * Errors: CH_E_INVALID (NULL, host arrays, id >= n, no query index),
+ * CH_E_LIMIT, CH_E_DEVICE. */
+#define CH_NOALLOC_SCRATCH_BYTES (96u << 20)
+int ch_query_batch_noalloc(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
+                           uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream);
+
 /* Copy the finished CH to host arrays, in original vertex ids.  Any pointer
  * may be NULL to skip that array.
  *   level[n]: round in which the vertex was contracted (0-based)

@@ -33,7 +33,8 @@ CH_Q_ON_DEVICE = 0x1
 
 EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
             "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version", "ch_export_features",
-            "ch_mlp_forward", "ch_mlp_grad", "ch_mlp_train", "ch_query_batch_stats")
+            "ch_mlp_forward", "ch_mlp_grad", "ch_mlp_train", "ch_query_batch_stats",
+            "ch_query_batch_noalloc")
 
 
 class ChError(RuntimeError):
@@ -145,6 +146,8 @@ def lib():
         L.ch_version.restype = C.c_char_p
         L.ch_query_batch_stats.argtypes = [vp, vp, vp, u64, vp, vp, u32, vp]
         L.ch_query_batch_stats.restype = i32
+        L.ch_query_batch_noalloc.argtypes = [vp, vp, vp, u64, vp, vp, u32, vp]
+        L.ch_query_batch_noalloc.restype = i32
         L.ch_export_features.argtypes = [vp, vp]
         L.ch_export_features.restype = i32
         L.ch_mlp_forward.argtypes = [vp, u64, vp, vp, vp, u32, vp]
@@ -230,6 +233,23 @@ class CH:
                                           CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window),
                                           None),
                "ch_query_batch_stats")
+        return dist, vis
+
+    def query_noalloc(self, s, t, visited=True, stream=None, waves=0, window=0):
+        """ch_query_batch_noalloc on torch CUDA uint32 tensors s, t: (dist,
+        visited or None) as CUDA int64 / int32 tensors, after the call has
+        finished."""
+        import torch
+
+        q = s.numel()
+        dist = torch.empty(q, dtype=torch.int64, device=s.device)
+        vis = torch.empty(q, dtype=torch.int32, device=s.device) if visited else None
+        st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _check(lib().ch_query_batch_noalloc(
+            self.h, s.data_ptr(), t.data_ptr(), q, dist.data_ptr(),
+            vis.data_ptr() if vis is not None else None,
+            CH_Q_ON_DEVICE | CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window), st),
+            "ch_query_batch_noalloc")
         return dist, vis
 
     def export(self):

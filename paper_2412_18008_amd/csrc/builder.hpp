@@ -66,5 +66,8 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
 // Query batch (post.hip).
 int query_batch(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                 uint64_t *dist, uint32_t *visited, uint32_t flags, hipStream_t st);
+// Query batch with every scratch array in a fixed per-GPU array (post.hip).
+int query_batch_noalloc(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
+                        uint64_t *dist, uint32_t *visited, uint32_t flags, hipStream_t st);
 
 }  // namespace sp

@@ -41,6 +41,14 @@ int ch_query_batch_stats(const ch_t *ch, const uint32_t *s, const uint32_t *t, u
   return sp::query_batch(ch, s, t, q, dist, visited, flags, (hipStream_t)stream);
 }
 
+int ch_query_batch_noalloc(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
+                           uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream) {
+  sp::clear_error();
+  if (!ch) return set_error(CH_E_INVALID, "ch must not be NULL");
+  if (q && (!s || !t || !dist)) return set_error(CH_E_INVALID, "s, t and dist must not be NULL");
+  return sp::query_batch_noalloc(ch, s, t, q, dist, visited, flags, (hipStream_t)stream);
+}
+
 static int copy_out(void *dst, const sp::DBuf &src, uint64_t count, hipStream_t st) {
   if (!dst || !count) return CH_OK;
   hipError_t e = hipMemcpyAsync(dst, src.p, count * 4, hipMemcpyDeviceToHost, st);

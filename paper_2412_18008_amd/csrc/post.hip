@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 #include <string>
 
@@ -15,6 +16,11 @@ namespace sp {
   do {                                                  \
     hipError_t e_ = (expr);                             \
     if (e_ != hipSuccess) return hip_error(e_, #expr);  \
+  } while (0)
+#define TRY(expr)               \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != CH_OK) return r_; \
   } while (0)
 
 static int bits_for(uint32_t n) {
@@ -215,6 +221,8 @@ static int level_starts(ch_s *ch) {
   DBuf lvr;
   HIP_TRY(lvr.ensure((size_t)std::max<uint32_t>(ch->n, 1) * 4));
   HIP_TRY(ch->q_lstart.ensure(((size_t)nlev + 1) * 4));
+  // level-window ends, filled by the first query batch that uses a window
+  HIP_TRY(ch->q_wend.ensure((size_t)std::max<uint32_t>(ch->n, 1) * 4));
   if (ch->n)
     k_level_by_rank<<<gridn(ch->n), 256, 0, st>>>(ch->n, ch->rank.as<uint32_t>(),
                                                   ch->level.as<uint32_t>(), lvr.as<uint32_t>());
@@ -1070,32 +1078,16 @@ __global__ void __launch_bounds__(64) k_query_global(
   }
 }
 
-int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t q, uint64_t *dist,
-                uint32_t *visited, uint32_t flags, hipStream_t st) {
-  ch_s *ch = const_cast<ch_s *>(chc);
-  if (!ch->has_index) return set_error(CH_E_INVALID, "the CH was built without a query index");
-  if (q == 0) return CH_OK;
-  if (!st) st = ch->stream;
-  const bool on_dev = flags & CH_Q_ON_DEVICE;
-  const uint32_t *ds = s, *dt = t;
-  unsigned long long *dd = reinterpret_cast<unsigned long long *>(dist);
-  HIP_TRY(ch->q_ctr.ensure(64));
-  if (!on_dev) {
-    HIP_TRY(ch->q_s.ensure(q * 4));
-    HIP_TRY(ch->q_t.ensure(q * 4));
-    HIP_TRY(ch->q_d.ensure(q * 8));
-    HIP_TRY(hipMemcpyAsync(ch->q_s.p, s, q * 4, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(ch->q_t.p, t, q * 4, hipMemcpyHostToDevice, st));
-    ds = ch->q_s.as<uint32_t>();
-    dt = ch->q_t.as<uint32_t>();
-    dd = ch->q_d.as<unsigned long long>();
-  }
-  uint32_t *dv = visited;
-  if (visited && !on_dev) {
-    HIP_TRY(ch->q_v.ensure(q * 4));
-    dv = ch->q_v.as<uint32_t>();
-  }
-  HIP_TRY(ch->q_ovf.ensure(q * 4));
+// The tiers of one batch on device arrays (ds, dt, dd, dv).  Scratch comes
+// from `sc`: sc.ctr (16 words), sc.ovf1 / sc.ovf2 (q entries each),
+// sc.tier3(n3, &tabs, &blocks) and sc.tier4(n4, &tabs, &cap, &limit, &ntab)
+// (tables for the global-memory tiers, requested only when a query needs
+// them); tier4 sets *limit < *cap when its tables can fill, and a query
+// that still overflows then makes the call fail with CH_E_LIMIT.
+template <typename Scratch>
+static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_t q,
+                       unsigned long long *dd, uint32_t *dv, uint32_t flags, hipStream_t st,
+                       Scratch &sc) {
   // Tiers: 1 = a slot per rank for the 2048 highest ranks plus 512-slot
   // tables per direction for the others (five blocks per CU),
   // 2 = a slot per rank for the 8192 highest ranks plus 4096-slot tables per
@@ -1107,21 +1099,24 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   // counters: [0] tier-1 overflows, [1] bad ids, [2] tier-2 overflows,
   // [4] tier-3 overflows, [6] tier-4 overflows, 64-bit work counters of
   // tiers 1-3 at [8], [10], [12]
-  uint32_t *ctr = ch->q_ctr.as<uint32_t>();
-  HIP_TRY(ch->q_ovf2.ensure(q * 4));
-  HIP_TRY(hipMemsetAsync(ctr, 0, 64, st));
+  uint32_t *ctr = sc.ctr;
+  // cleared by a fill kernel, not a memset (the scratch may be in use by a
+  // captured sequence of this stream)
+  HIP_TRY(fill_u32(ctr, 0u, 16, st));
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device);
   const uint32_t *rank = ch->rank.as<uint32_t>();
   const uint32_t *upoff = ch->q_upoff.as<uint32_t>(), *dnoff = ch->q_dnoff.as<uint32_t>();
   const uint2 *uparc = ch->q_uparc.as<uint2>(), *dnarc = ch->q_dnarc.as<uint2>();
-  uint32_t *ovf1 = ch->q_ovf.as<uint32_t>(), *ovf2 = ch->q_ovf2.as<uint32_t>();
+  uint32_t *ovf1 = sc.ovf1, *ovf2 = sc.ovf2;
   const int first = ch->q_first_tier;
   const uint32_t wf = (flags >> 12) & 0xFFu;  // 0: default window, 255: none
   uint32_t win = wf == 0 ? (ch->rounds <= kQShallow ? 0u : kQWindow) : (wf == 255 ? 0u : wf);
   if (win >= ch->rounds) win = 0;  // a window over every level: the plain path
   if (win && win != ch->q_wend_win) {
-    HIP_TRY(ch->q_wend.ensure((size_t)std::max<uint32_t>(ch->n, 1) * 4));
+    // q_wend is allocated with the query index
+    if (ch->q_wend.cap < (size_t)std::max<uint32_t>(ch->n, 1) * 4)
+      return set_error(CH_E_DEVICE, "query window array missing (internal error)");
     if (ch->n)
       k_window_ends<<<gridn(ch->n), 256, 0, st>>>(ch->n, rank, ch->level.as<uint32_t>(),
                                                   ch->q_lstart.as<uint32_t>(), ch->q_nlev, win,
@@ -1160,14 +1155,13 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   uint32_t *list3 = first <= 2 ? ovf2 : nullptr;
   uint32_t n4 = 0;
   if (n3) {
-    using T3 = QTier3;
-    const uint64_t nb = std::min<uint64_t>(n3, (uint64_t)cus * 4);
-    HIP_TRY(ch->q_tab.ensure(nb * sizeof(T3)));
+    QTier3 *tabs = nullptr;
+    uint64_t nb = std::min<uint64_t>(n3, (uint64_t)cus * 4);
+    TRY(sc.tier3(n3, &tabs, &nb));
     // overflows into ctr[4]; the input count is tier 2's, on the device
     k_query<8, QTier3, true><<<(unsigned)nb, 512, 0, st>>>(
         q, ch->n, list3, ctr + 2, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,
-        ovf1, ctr + 4, wend, reinterpret_cast<unsigned long long *>(ctr + 12),
-        reinterpret_cast<T3 *>(ch->q_tab.p));
+        ovf1, ctr + 4, wend, reinterpret_cast<unsigned long long *>(ctr + 12), tabs);
     HIP_TRY(hipGetLastError());
     uint32_t h2[4] = {0, 0, 0, 0};  // ctr[1..4]
     HIP_TRY(hipMemcpyAsync(h2, ctr + 1, 16, hipMemcpyDeviceToHost, st));
@@ -1176,29 +1170,175 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
     n4 = h2[3];
   }
   if (n4) {
-    uint64_t c = 1;
-    while (c < 2ull * ch->n + 2) c <<= 1;
-    const uint32_t cap = (uint32_t)std::min<uint64_t>(c, 1ull << 31);
-    const size_t per = ((size_t)cap * 8 + 4) * 4 * 2;
-    const size_t ntab = std::max<size_t>(
-        1, std::min<size_t>({(size_t)n4, (size_t)cus * 2, (size_t)(4ull << 30) / per}));
-    HIP_TRY(ch->q_gtab.ensure(ntab * per));
+    uint32_t *tabs = nullptr, cap = 0, limit = 0;
+    size_t ntab = 0;
+    TRY(sc.tier4(n4, cus, &tabs, &cap, &limit, &ntab));
     // keys and dists all ones; flag, order, fronts, counters zero
     for (size_t k = 0; k < 2 * ntab; k++) {
-      uint32_t *b = ch->q_gtab.as<uint32_t>() + k * ((size_t)cap * 8 + 4);
+      uint32_t *b = tabs + k * ((size_t)cap * 8 + 4);
       HIP_TRY(fill_u32(b, SP_EMPTY32, 3ull * cap, st));
-      HIP_TRY(hipMemsetAsync(b + 3ull * cap, 0, ((size_t)cap * 5 + 4) * 4, st));
+      HIP_TRY(fill_u32(b + 3ull * cap, 0u, (size_t)cap * 5 + 4, st));
     }
     k_query_global<<<(unsigned)ntab, 64, 0, st>>>(n4, ovf1, ds, dt, rank, upoff, uparc, dnoff,
-                                                 dnarc, dd, dv, ch->q_gtab.as<uint32_t>(), cap,
-                                                 cap, ovf2, ctr + 6);
+                                                 dnarc, dd, dv, tabs, cap, limit, ovf2, ctr + 6);
     HIP_TRY(hipGetLastError());
+    if (limit < cap) {
+      uint32_t n5 = 0;
+      HIP_TRY(hipMemcpyAsync(&n5, ctr + 6, 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (n5)
+        return set_error(CH_E_LIMIT, "a query's upward search space outgrew the largest table "
+                                     "of ch_query_batch_noalloc; use ch_query_batch");
+    }
   }
   // where the next batch starts
   if (first <= 1 && hc[0] * 2 > q) ch->q_first_tier = 2;
   if (first <= 2 && into2 && (uint64_t)hc[2] * 2 > into2) ch->q_first_tier = 3;
+  return CH_OK;
+}
+
+// Scratch of ch_query_batch: buffers of the CH, grown on demand.
+struct QScratchCH {
+  ch_s *ch;
+  uint32_t *ctr = nullptr, *ovf1 = nullptr, *ovf2 = nullptr;
+  int tier3(uint64_t, QTier3 **tabs, uint64_t *nb) {
+    HIP_TRY(ch->q_tab.ensure(*nb * sizeof(QTier3)));
+    *tabs = reinterpret_cast<QTier3 *>(ch->q_tab.p);
+    return CH_OK;
+  }
+  int tier4(uint32_t n4, int cus, uint32_t **tabs, uint32_t *cap, uint32_t *limit,
+            size_t *ntab) {
+    uint64_t c = 1;
+    while (c < 2ull * ch->n + 2) c <<= 1;
+    *cap = *limit = (uint32_t)std::min<uint64_t>(c, 1ull << 31);
+    const size_t per = ((size_t)*cap * 8 + 4) * 4 * 2;
+    *ntab = std::max<size_t>(
+        1, std::min<size_t>({(size_t)n4, (size_t)cus * 2, (size_t)(4ull << 30) / per}));
+    HIP_TRY(ch->q_gtab.ensure(*ntab * per));
+    *tabs = ch->q_gtab.as<uint32_t>();
+    return CH_OK;
+  }
+};
+
+int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t q, uint64_t *dist,
+                uint32_t *visited, uint32_t flags, hipStream_t st) {
+  ch_s *ch = const_cast<ch_s *>(chc);
+  if (!ch->has_index) return set_error(CH_E_INVALID, "the CH was built without a query index");
+  if (q == 0) return CH_OK;
+  if (!st) st = ch->stream;
+  const bool on_dev = flags & CH_Q_ON_DEVICE;
+  const uint32_t *ds = s, *dt = t;
+  unsigned long long *dd = reinterpret_cast<unsigned long long *>(dist);
+  HIP_TRY(ch->q_ctr.ensure(64));
+  if (!on_dev) {
+    HIP_TRY(ch->q_s.ensure(q * 4));
+    HIP_TRY(ch->q_t.ensure(q * 4));
+    HIP_TRY(ch->q_d.ensure(q * 8));
+    HIP_TRY(hipMemcpyAsync(ch->q_s.p, s, q * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(ch->q_t.p, t, q * 4, hipMemcpyHostToDevice, st));
+    ds = ch->q_s.as<uint32_t>();
+    dt = ch->q_t.as<uint32_t>();
+    dd = ch->q_d.as<unsigned long long>();
+  }
+  uint32_t *dv = visited;
+  if (visited && !on_dev) {
+    HIP_TRY(ch->q_v.ensure(q * 4));
+    dv = ch->q_v.as<uint32_t>();
+  }
+  HIP_TRY(ch->q_ovf.ensure(q * 4));
+  HIP_TRY(ch->q_ovf2.ensure(q * 4));
+  QScratchCH sc{ch, ch->q_ctr.as<uint32_t>(), ch->q_ovf.as<uint32_t>(), ch->q_ovf2.as<uint32_t>()};
+  TRY(query_tiers(ch, ds, dt, q, dd, dv, flags, st, sc));
   if (!on_dev) HIP_TRY(hipMemcpyAsync(dist, dd, q * 8, hipMemcpyDeviceToHost, st));
   if (visited && !on_dev) HIP_TRY(hipMemcpyAsync(visited, dv, q * 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return CH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Query batch without allocations (ch_query_batch_noalloc).  Every scratch
+// array of the tiers lives in `scratch`, one fixed array per GPU: counters,
+// two overflow lists of a pass of kNaChunk queries, kNaT3Blocks tier-3
+// tables and one tier-4 table set of kNaT4Cap slots per direction.  Host
+// code never uses the array's name as an address: the device address comes
+// from hipGetSymbolAddress, once per device.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kNaChunk = 1ull << 20;  // queries per pass
+constexpr uint32_t kNaT3Blocks = 64;
+constexpr uint32_t kNaT4Cap = 1u << 20;   // never fills on a CH of <= 524,287 vertices
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kNaOvf1 = 256;
+constexpr size_t kNaOvf2 = kNaOvf1 + kNaChunk * 4;
+constexpr size_t kNaT3 = na_align(kNaOvf2 + kNaChunk * 4);
+constexpr size_t kNaT4 = na_align(kNaT3 + (size_t)kNaT3Blocks * sizeof(QTier3));
+constexpr size_t kNaEnd = kNaT4 + 2 * ((size_t)kNaT4Cap * 8 + 4) * 4;
+static_assert(kNaEnd <= CH_NOALLOC_SCRATCH_BYTES, "no-allocation query scratch too small");
+static_assert(alignof(QTier3) <= 256, "tier-3 tables in the scratch array");
+
+static __device__ __align__(256) uint8_t scratch[CH_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kNaMaxDevices = 64;
+static std::mutex g_na_mu;
+static uint8_t *g_na_ptr[kNaMaxDevices] = {};
+
+// Device address of `scratch` on `dev`, looked up on the first call for that
+// device with it current.
+static int na_scratch(int dev, uint8_t **out) {
+  if (dev < 0 || dev >= kNaMaxDevices)
+    return set_error(CH_E_DEVICE, "device index out of range for the query scratch");
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != dev) HIP_TRY(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return set_error(CH_E_DEVICE, "no device address for the query scratch");
+    g_na_ptr[dev] = static_cast<uint8_t *>(p);
+  }
+  *out = g_na_ptr[dev];
+  return CH_OK;
+}
+
+struct QScratchFixed {
+  uint8_t *base;
+  uint32_t n;
+  uint32_t *ctr, *ovf1, *ovf2;
+  int tier3(uint64_t, QTier3 **tabs, uint64_t *nb) {
+    *nb = std::min<uint64_t>(*nb, kNaT3Blocks);
+    *tabs = reinterpret_cast<QTier3 *>(base + kNaT3);
+    return CH_OK;
+  }
+  int tier4(uint32_t, int, uint32_t **tabs, uint32_t *cap, uint32_t *limit, size_t *ntab) {
+    *tabs = reinterpret_cast<uint32_t *>(base + kNaT4);
+    *cap = kNaT4Cap;
+    // a table of >= 2n + 2 slots never fills; else a query stops at 7/8
+    *limit = 2ull * n + 2 <= kNaT4Cap ? kNaT4Cap : kNaT4Cap - kNaT4Cap / 8;
+    *ntab = 1;
+    return CH_OK;
+  }
+};
+
+int query_batch_noalloc(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t q,
+                        uint64_t *dist, uint32_t *visited, uint32_t flags, hipStream_t st) {
+  ch_s *ch = const_cast<ch_s *>(chc);
+  if (!ch->has_index) return set_error(CH_E_INVALID, "the CH was built without a query index");
+  if (!(flags & CH_Q_ON_DEVICE))
+    return set_error(CH_E_INVALID, "ch_query_batch_noalloc takes device arrays (CH_Q_ON_DEVICE)");
+  if (q == 0) return CH_OK;
+  if (!st) st = ch->stream;
+  uint8_t *base = nullptr;
+  TRY(na_scratch(ch->device, &base));
+  QScratchFixed sc{base, ch->n, reinterpret_cast<uint32_t *>(base),
+                   reinterpret_cast<uint32_t *>(base + kNaOvf1),
+                   reinterpret_cast<uint32_t *>(base + kNaOvf2)};
+  for (uint64_t c0 = 0; c0 < q; c0 += kNaChunk) {
+    const uint64_t qc = std::min<uint64_t>(kNaChunk, q - c0);
+    TRY(query_tiers(ch, s + c0, t + c0, qc, reinterpret_cast<unsigned long long *>(dist + c0),
+                    visited ? visited + c0 : nullptr, flags, st, sc));
+  }
   HIP_TRY(hipStreamSynchronize(st));
   return CH_OK;
 }
