@@ -726,6 +726,20 @@ struct Builder {
     if (hop) go(k_local_search<G, CAP, true>);
     else go(k_local_search<G, CAP, false>);
   }
+  // second tier: sources that outgrew the first tier's tables (list ovf1,
+  // count on the device), a block of kLsBlkWaves waves and one
+  // kLsBlkCap-slot LDS table per source, one block per CU; overflows go to
+  // ovf2 for the global tier
+  void launch_ls_blk(const Overlay &v) {
+    DevCtr *d = dc();
+    auto go = [&](auto kern) {
+      kern<<<(unsigned)cus, kWave * kLsBlkWaves, 0, st>>>(
+          v, ovf1.as<uint32_t>(), 0, aflag.as<uint8_t>(), mref(), &d->ls2, &d->novf1, &d->work2,
+          ovf2.as<uint32_t>(), &d->novf2, fstate().ws, &d->err, prm.hop_limit);
+    };
+    if (prm.wps_mode == CH_WPS_HOP) go(k_local_search_blk<kLsBlkCap, true, kLsBlkWaves>);
+    else go(k_local_search_blk<kLsBlkCap, false, kLsBlkWaves>);
+  }
   template <int G>
   void launch_score(const Overlay &v, uint32_t na) {
     k_score<G><<<ggrid<G>(na), 256, 0, st>>>(v, va.as<uint32_t>(), na, mref(), ov[cur].P.as<int32_t>(),
@@ -961,7 +975,7 @@ struct Builder {
         }
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
-        launch_ls<64, 4096>(v, ovf1.as<uint32_t>(), 0, &dc()->novf1, 2, 4);
+        launch_ls_blk(v);
         HIP_TRY(hipGetLastError());
       }
       // Steps 1 (pruning) to 4 (contraction counts) run before the searches
@@ -1035,15 +1049,10 @@ struct Builder {
         size_t ntab = std::max<size_t>(1, std::min<size_t>({(size_t)novf, (size_t)cus * 2,
                                                             (size_t)(4ull << 30) / per}));
         HIP_TRY(gtabs.ensure(ntab * per));
-        // key, dist (and dist2) = all ones; flag, order, fronts, counters = 0
-        for (size_t t = 0; t < ntab; t++) {
-          uint32_t *b = gtabs.as<uint32_t>() + t * (per / 4);
-          const size_t arrays = hop ? 7 : 6;
-          HIP_TRY(fill_u32(b, SP_EMPTY32, 2ull * cap, st));            // key, dist
-          HIP_TRY(hipMemsetAsync(b + 2ull * cap, 0, (size_t)cap * 4 * 4, st));  // flag .. fr1
-          if (hop) HIP_TRY(fill_u32(b + 6ull * cap, SP_EMPTY32, cap, st));     // dist2
-          HIP_TRY(hipMemsetAsync(b + arrays * cap, 0, 4 * 4, st));      // counters
-        }
+        // key, dist (and dist2) = all ones; bitmaps, lists, counters = 0
+        k_gtab_init<<<grid(ntab * (per / 4)), 256, 0, st>>>(gtabs.as<uint32_t>(), ntab * (per / 4),
+                                                            per / 4, cap, hop);
+        HIP_TRY(hipGetLastError());
         // the global tier searches the overlay as the other searches saw it:
         // this round's optimistic pruning is undone first and redone (and
         // recounted) by the second pass below
@@ -1053,8 +1062,9 @@ struct Builder {
                                                                prw.as<uint32_t>(), &dc()->err);
           HIP_TRY(hipGetLastError());
         }
-        auto global = hop ? k_local_search_global<true> : k_local_search_global<false>;
-        global<<<(unsigned)ntab, 64, 0, st>>>(
+        auto global = hop ? k_local_search_global<true, kLsBlkWaves>
+                          : k_local_search_global<false, kLsBlkWaves>;
+        global<<<(unsigned)ntab, kWave * kLsBlkWaves, 0, st>>>(
             v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), mref(), &dc()->ls2, gtabs.as<uint32_t>(), cap, fstate().ws,
             &dc()->err, prm.hop_limit);
         HIP_TRY(hipGetLastError());

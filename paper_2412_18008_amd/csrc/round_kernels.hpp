@@ -286,6 +286,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
   T.limit = LIM;
   T.fcap = LIM;
   SearchStats ss;
+  const Coop<G, 1> C{nullptr};
   for (;;) {
     uint32_t base = 0;
     if (gl == 0) base = atomicAdd(work, chunk);
@@ -294,7 +295,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
     const uint32_t end = min(base + chunk, nw);
     for (uint32_t i = base; i < end; i++) {
       const uint32_t s = vw[i];
-      if (!search_source<G, HOP>(ov, aflag, memo, T, s, ss, ws, err, hops)) {
+      if (!search_source<G, 1, HOP>(ov, aflag, memo, T, s, ss, ws, err, hops, C)) {
         if (gl == 0) {
           const uint32_t k = atomicAdd(ovf_count, 1u);
           ovf_list[k] = s;
@@ -305,17 +306,106 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
   flush_stats<G>(ss, cnt);
 }
 
-// Global-memory fallback: one wave per source, table of `cap` slots per
-// wave at tabs + wave * stride_words (key, dist, a region holding the
-// target and frontier bitmaps, order, fr0, fr1 and, in hop mode, dist2 as
-// consecutive uint32 arrays of `cap`, then 4 counters).
-template <bool HOP>
-__global__ void __launch_bounds__(64) k_local_search_global(
+// Searches that outgrow a wave's table: NW waves of one block share one
+// source and one CAP-slot LDS table (Coop in search.hpp), so a large search
+// gets NW times the lanes per frontier level.  Persistent: blocks take
+// sources one at a time from a global counter.
+constexpr int kLsBlkWaves = 16;
+constexpr int kLsBlkCap = 8192;
+constexpr size_t ls_blk_lds_bytes(int cap, bool hop, int nw) {
+  return 4 * (size_t)cap * (hop ? 3 : 2) + (hop ? 0 : 4) + 8 * (size_t)(cap / 32) + 16 +
+         6 * (size_t)ls_limit(cap) + 8 * (size_t)nw + 4;
+}
+template <int CAP, bool HOP, int NW>
+__global__ void __launch_bounds__(kWave * NW) k_local_search_blk(
+    Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
+    MemoRef memo, LsCounters *__restrict__ cnt, const uint32_t *__restrict__ nw_dev,
+    uint32_t *__restrict__ work, uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count,
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
+  constexpr int CAP2 = HOP ? CAP : 1;
+  constexpr int LIM = ls_limit(CAP);
+  static_assert(LIM <= 65536, "16-bit slot lists");
+  if (nw_dev) nw = *nw_dev;  // source count produced by an earlier kernel
+  if (nw == 0) return;
+  __shared__ uint32_t s_key[CAP];
+  __shared__ uint32_t s_dist[CAP];
+  __shared__ uint32_t s_dist2[CAP2];
+  __shared__ uint32_t s_bits[2][CAP / 32];  // target, frontier
+  __shared__ uint16_t s_order[LIM];
+  __shared__ uint16_t s_fr[2][LIM];
+  __shared__ uint32_t s_ctr[4];
+  __shared__ uint32_t s_red[2 * NW];
+  __shared__ uint32_t s_next;
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t i = tid; i < CAP; i += kWave * NW) {
+    s_key[i] = SP_EMPTY32;
+    s_dist[i] = SP_INF32;
+    if constexpr (HOP) s_dist2[i] = SP_INF32;
+  }
+  for (uint32_t i = tid; i < CAP / 32; i += kWave * NW) {
+    s_bits[0][i] = 0;
+    s_bits[1][i] = 0;
+  }
+  if (tid < 4) s_ctr[tid] = 0;
+  __syncthreads();
+  Tab<uint16_t, false> T;
+  T.key = s_key;
+  T.dist = s_dist;
+  T.dist2 = HOP ? s_dist2 : nullptr;
+  T.tgt = s_bits[0];
+  T.front = s_bits[1];
+  T.order = s_order;
+  T.fr0 = s_fr[0];
+  T.fr1 = s_fr[1];
+  T.ctr = s_ctr;
+  T.cap = CAP;
+  T.shift = 32 - __builtin_ctz(CAP);
+  T.limit = LIM;
+  T.fcap = LIM;
+  const Coop<kWave, NW> C{s_red};
+  SearchStats ss;
+  for (;;) {
+    if (tid == 0) s_next = atomicAdd(work, 1u);
+    __syncthreads();
+    const uint32_t i = s_next;
+    __syncthreads();
+    if (i >= nw) break;
+    const uint32_t s = vw[i];
+    if (!search_source<kWave, NW, HOP>(ov, aflag, memo, T, s, ss, ws, err, hops, C)) {
+      if (tid == 0) {
+        const uint32_t k = atomicAdd(ovf_count, 1u);
+        ovf_list[k] = s;
+      }
+    }
+  }
+  flush_stats<kWave>(ss, cnt);
+}
+
+// Tables of the global tier: per table `per` words (key, dist, bitmaps and
+// lists, hop-mode dist2, counters, each array `cap` words); key, dist and
+// dist2 start all ones, the rest zero.
+__global__ void k_gtab_init(uint32_t *__restrict__ tabs, uint64_t words, uint64_t per,
+                            uint32_t cap, bool hop) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) {
+    const uint64_t o = i % per;
+    const bool ones = o < 2ull * cap || (hop && o >= 6ull * cap && o < 7ull * cap);
+    tabs[i] = ones ? SP_EMPTY32 : 0u;
+  }
+}
+
+// Global-memory fallback: NW waves of one block per source, table of `cap`
+// slots per block at tabs + block * stride_words (key, dist, a region
+// holding the target and frontier bitmaps, order, fr0, fr1 and, in hop
+// mode, dist2 as consecutive uint32 arrays of `cap`, then 4 counters).
+template <bool HOP, int NW>
+__global__ void __launch_bounds__(kWave * NW) k_local_search_global(
     Overlay ov, const uint32_t *__restrict__ list, uint32_t nlist,
     const uint8_t *__restrict__ aflag, MemoRef memo,
     LsCounters *__restrict__ cnt, uint32_t *__restrict__ tabs, uint32_t cap,
     uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
   constexpr size_t kArrays = HOP ? 7 : 6;
+  __shared__ uint32_t s_red[2 * NW];
   uint32_t *base = tabs + (size_t)blockIdx.x * ((size_t)cap * kArrays + 4);
   Tab<uint32_t, true> T;
   T.key = base;
@@ -331,13 +421,14 @@ __global__ void __launch_bounds__(64) k_local_search_global(
   T.shift = 32 - __builtin_ctz(cap);
   T.limit = cap;  // cap >= 2 n_o: never overflows
   T.fcap = cap;
+  const Coop<kWave, NW> C{s_red};
   SearchStats ss;
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
-    if (!search_source<64, HOP>(ov, aflag, memo, T, list[i], ss, ws, err, hops)) {
-      if (lane_id() == 0) atomicOr(err, kErrCapacity);
+    if (!search_source<kWave, NW, HOP>(ov, aflag, memo, T, list[i], ss, ws, err, hops, C)) {
+      if (threadIdx.x == 0) atomicOr(err, kErrCapacity);
     }
   }
-  flush_stats<64>(ss, cnt);
+  flush_stats<kWave>(ss, cnt);
 }
 
 // Pruning (end of Alg. 3): an out-arc (s, v) of a source s whose weight

@@ -139,33 +139,90 @@ struct SearchStats {
   uint32_t rows = 0, arcs = 0, probes = 0, inserts = 0, targets = 0, searched = 0;
 };
 
+// A search is run by NW waves of one block together (NW > 1, G = 64: the
+// block-wide tiers for searches that outgrow a wave's table) or by one group
+// of G lanes (NW = 1).  Collective loops stride over all NT = G * NW lanes;
+// row expansion stays per wave (for_row_arcs), so waves never wait on each
+// other inside a level.  Coop holds this lane's place and a small LDS array
+// for reductions across the waves.
+template <int G, int NW>
+struct Coop {
+  static constexpr int NT = G * NW;
+  uint32_t *red;  // 2 * NW words of LDS (NW > 1)
+  __device__ __forceinline__ int tl() const {
+    if constexpr (NW == 1) return glane<G>();
+    else return (int)threadIdx.x;
+  }
+  __device__ __forceinline__ int wv() const {
+    if constexpr (NW == 1) return 0;
+    else return (int)(threadIdx.x / kWave);
+  }
+  // barrier of the lanes that share the search (and the table's fence)
+  template <typename TabT>
+  __device__ __forceinline__ void sync(const TabT &T) const {
+    if constexpr (NW == 1) {
+      T.sync();
+    } else {
+      T.sync();
+      __syncthreads();
+    }
+  }
+  template <typename TabT>
+  __device__ __forceinline__ uint32_t sum(uint32_t v, const TabT &T) const {
+    v = gsum<G>(v);
+    if constexpr (NW > 1) {
+      if (lane_id() == 0) red[wv()] = v;
+      __syncthreads();
+      v = 0;
+#pragma unroll
+      for (int i = 0; i < NW; i++) v += red[i];
+      __syncthreads();
+    }
+    return v;
+  }
+  template <typename TabT>
+  __device__ __forceinline__ uint32_t max(uint32_t v, const TabT &T) const {
+    v = gmax<G>(v);
+    if constexpr (NW > 1) {
+      if (lane_id() == 0) red[NW + wv()] = v;
+      __syncthreads();
+      v = 0;
+#pragma unroll
+      for (int i = 0; i < NW; i++) v = v > red[NW + i] ? v : red[NW + i];
+      __syncthreads();
+    }
+    return v;
+  }
+};
+
 // Clears the slots listed in `order` (and the counters) after a search.
-template <int G, typename IdxT, bool GL>
-__device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
-  const int gl = glane<G>();
-  T.sync();
+template <int G, int NW, typename IdxT, bool GL>
+__device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T, const Coop<G, NW> &C) {
+  constexpr int NT = Coop<G, NW>::NT;
+  const int tl = C.tl();
+  C.sync(T);
   uint32_t used = T.ld(&T.ctr[kCtrUsed]);
   if (used > T.limit) used = T.limit;
-  for (uint32_t i = gl; i < used; i += G) {
+  for (uint32_t i = tl; i < used; i += NT) {
     IdxT s = T.ldi(&T.order[i]);
     T.st(&T.key[s], SP_EMPTY32);
     T.st(&T.dist[s], SP_INF32);
     if (T.dist2) T.st(&T.dist2[s], SP_INF32);
   }
-  for (uint32_t i = gl; i < T.cap / 32; i += G) {
+  for (uint32_t i = tl; i < T.cap / 32; i += NT) {
     T.st(&T.tgt[i], 0u);
     T.st(&T.front[i], 0u);
   }
-  T.sync();
+  C.sync(T);
   if (used >= T.limit) {  // an overflowing insert may have left unlisted keys
-    for (uint32_t i = gl; i < T.cap; i += G) {
+    for (uint32_t i = tl; i < T.cap; i += NT) {
       T.st(&T.key[i], SP_EMPTY32);
       T.st(&T.dist[i], SP_INF32);
       if (T.dist2) T.st(&T.dist2[i], SP_INF32);
     }
   }
-  if (gl < 4) T.st(&T.ctr[gl], 0u);
-  T.sync();
+  if (tl < 4) T.st(&T.ctr[tl], 0u);
+  C.sync(T);
 }
 
 // One source.  Returns false when the table overflowed (nothing written).
@@ -175,17 +232,21 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T) {
 // entries are copied back.  The result is the minimum over walks of at most
 // `hops` arcs within the radius, independent of the order of relaxations.
 // Targets the walks do not reach get no memo entry.
-template <int G, bool HOP, typename IdxT, bool GL>
+template <int G, int NW, bool HOP, typename IdxT, bool GL>
 __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ aflag,
                               const MemoRef &memo, const Tab<IdxT, GL> &T, uint32_t s, SearchStats &ss,
                               uint32_t *__restrict__ ws, uint32_t *__restrict__ err,
-                              uint32_t hops) {
+                              uint32_t hops, const Coop<G, NW> &C) {
+  static_assert(NW == 1 || G == kWave, "cooperating waves use whole waves");
+  constexpr int NT = Coop<G, NW>::NT;
   const int gl = glane<G>();
+  const int tl = C.tl();
+  const uint32_t wbase = (uint32_t)C.wv() * G;  // this wave's first lane in the search
   const uint32_t gs = ov.gid[s];
 
   // ---- 1. targets and radius ------------------------------------------
   const uint32_t a0 = ov.foff[s], a1 = ov.foff[s + 1];
-  for (uint32_t base = a0; base < a1; base += G) {
+  for (uint32_t base = a0 + wbase; base < a1; base += NT) {
     const uint32_t e = base + gl;
     uint32_t rs = 0, rl = 0, wsu = 0;
     if (e < a1) {
@@ -210,22 +271,22 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     });
     if (T.ld(&T.ctr[kCtrOvf])) break;
   }
-  T.sync();
+  C.sync(T);
   if (T.ld(&T.ctr[kCtrOvf])) {
-    tab_reset<G>(T);
+    tab_reset(T, C);
     return false;
   }
   uint32_t D = 0, nt = 0;
   {
     constexpr int K = memo_batch<G>();
     const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
-    for (uint32_t i0 = gl; i0 < used; i0 += G * K) {
+    for (uint32_t i0 = tl; i0 < used; i0 += NT * K) {
       IdxT slot[K];
       uint32_t ks[K], kv[K], got[K];
       bool act[K];
 #pragma unroll
       for (int q = 0; q < K; q++) {
-        const uint32_t i = i0 + q * G;
+        const uint32_t i = i0 + q * NT;
         act[q] = i < used;
         slot[q] = act[q] ? T.ldi(&T.order[i]) : (IdxT)0;
         ks[q] = gs;
@@ -244,22 +305,22 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       }
     }
   }
-  D = gmax<G>(D);
-  nt = gsum<G>(nt);
+  D = C.max(D, T);
+  nt = C.sum(nt, T);
   if (nt == 0) {
-    tab_reset<G>(T);
+    tab_reset(T, C);
     return true;
   }
   if (D > SP_MAXW) {
-    if (gl == 0) atomicOr(err, kErrOverflow);
-    tab_reset<G>(T);
+    if (tl == 0) atomicOr(err, kErrOverflow);
+    tab_reset(T, C);
     return true;
   }
 
   // ---- 2. bounded search from s: label-correcting (exact) or
   //         hop-synchronous (HOP) ------------------------------------------
-  T.sync();
-  if (gl == 0) {
+  C.sync(T);
+  if (tl == 0) {
     const int slot = T.insert(s);
     if (slot >= 0) {
       T.st(&T.dist[slot], 0u);
@@ -269,7 +330,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       T.st(&T.ctr[kCtrF0], 1u);
     }
   }
-  T.sync();
+  C.sync(T);
   int cur = 0;
   uint32_t level = 0;
   while (!T.ld(&T.ctr[kCtrOvf])) {
@@ -282,17 +343,21 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     if constexpr (HOP) {
       if (level == hops) break;
     }
-    T.sync();
-    if (gl == 0) T.st(nn, 0u);
-    T.sync();
-    for (uint32_t fb = 0; fb < ncur; fb += G) {
+    C.sync(T);
+    if (tl == 0) T.st(nn, 0u);
+    C.sync(T);
+    for (uint32_t fb = wbase; fb < ncur; fb += NT) {
       const uint32_t i = fb + gl;
       uint32_t rs = 0, rl = 0, dx = 0;
       if (i < ncur) {
         const IdxT x = T.ldi(&fc[i]);
         if constexpr (!HOP) {
+          // the bit is cleared before the distance is read: an improvement
+          // made after the read re-flags x for the next level
           atomicAnd(&T.front[x >> 5], ~(1u << (x & 31)));
-          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          if constexpr (GL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+          else if constexpr (NW == 1) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         }
         dx = T.ld(&T.dist[x]);
         const uint32_t vx = T.ld(&T.key[x]);
@@ -325,36 +390,36 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       });
       if (T.ld(&T.ctr[kCtrOvf])) break;
     }
-    T.sync();
+    C.sync(T);
     if constexpr (HOP) {
       // end of the level: the changed entries take their new distance and
       // may change again in the next level
       const uint32_t nnext = min(T.ld(nn), T.fcap);
-      for (uint32_t i = gl; i < nnext; i += G) {
+      for (uint32_t i = tl; i < nnext; i += NT) {
         const IdxT y = T.ldi(&fn[i]);
         T.st(&T.dist[y], T.ld(&T.dist2[y]));
         atomicAnd(&T.front[y >> 5], ~(1u << (y & 31)));
       }
-      T.sync();
+      C.sync(T);
       level++;
     }
     cur ^= 1;
   }
-  T.sync();
+  C.sync(T);
   if (T.ld(&T.ctr[kCtrOvf])) {
-    tab_reset<G>(T);
+    tab_reset(T, C);
     return false;
   }
 
   // ---- 3. memoize the targets' distances ------------------------------
-  ss.targets += (gl == 0) ? nt : 0;  // counted once, by the attempt that completes
-  ss.searched += (gl == 0) ? 1 : 0;
+  ss.targets += (tl == 0) ? nt : 0;  // counted once, by the attempt that completes
+  ss.searched += (tl == 0) ? 1 : 0;
   {
     const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
     uint32_t ball = 0;  // vertices within radius D of s (s included)
-    for (uint32_t i = gl; i < used; i += G) {
+    for (uint32_t i = tl; i < used; i += NT) {
       const IdxT slot = T.ldi(&T.order[i]);
-      ball += T.ld(&T.dist[slot]) <= D ? 1u : 0u;
+      if (ws) ball += T.ld(&T.dist[slot]) <= D ? 1u : 0u;
       if ((T.ld(&T.tgt[slot >> 5]) >> (slot & 31)) & 1u) {
         const uint32_t d = T.ld(&T.dist[slot]);
         if (d <= D) {
@@ -365,10 +430,12 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
         }
       }
     }
-    ball = gsum<G>(ball);
-    if (ws && gl == 0) ws[gs] = ball;
+    if (ws) {
+      ball = C.sum(ball, T);
+      if (tl == 0) ws[gs] = ball;
+    }
   }
-  tab_reset<G>(T);
+  tab_reset(T, C);
   return true;
 }
 

@@ -5,18 +5,31 @@ configuration: device-resident input, tuned search-kernel knobs, statistics
 on): the whole CH is compared with the oracle's, element by element, and
 sampled query distances with the oracle's queries and Dijkstra's.
 
-clustered road-like 24M: too large for the oracle's full build, so the test
-checks what holds at any size -- every vertex contracted once, rank a
-permutation consistent with level, arcs oriented and sorted by rank, every
-shortcut's weight equal to the two CH arcs through its middle vertex, every
-input-arc entry equal to the lightest parallel input arc -- and sampled query
-distances against Dijkstra's on the input graph.
+clustered road-like 24M (the headline workload): the oracle's full build
+takes tens of minutes, so it ran once (tests/golden/make_road24m_digest.py)
+and left a digest -- one SHA-256 per canonical array (level, score, rank,
+upward and downward arcs with weights and middle vertices) and the
+per-round counts; the GPU build in the benchmark's launch configuration must
+give the same digest.  The test also checks what holds at any size -- every
+vertex contracted once, rank a permutation consistent with level, arcs
+oriented and sorted by rank, every shortcut's weight equal to the two CH
+arcs through its middle vertex, every input-arc entry equal to the lightest
+parallel input arc -- and sampled query distances against Dijkstra's on the
+input graph.
 """
+import json
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import oracle
 from paper_2412_18008_amd import autotune, synth
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+sys.path.insert(0, GOLDEN)
+from ch_digest import digest  # noqa: E402
 from parity_util import (assert_export_order, assert_same_ch, gpu_export, gpu_round_counts,
                          oracle_export, oracle_round_counts, progress)
 
@@ -146,15 +159,28 @@ def test_road1m_bench_config_bit_exact(gpu):
 
 
 @pytest.mark.timeout(900)
-def test_road24m_properties(gpu):
+def test_road24m_bit_exact(gpu):
+    with open(os.path.join(GOLDEN, "road24m_digest.json")) as f:
+        ref = json.load(f)
     progress("generating road24m")
     off, dst, w = synth.config_road24m(seed=0)
     n, m = len(off) - 1, len(dst)
+    assert (n, m) == (ref["n"], ref["m"])
     knobs = autotune.params_for(n, m)
     progress(f"road24m n={n} m={m} knobs={knobs}")
-    ch = _device_build(gpu, off, dst, w, seed=0, **knobs)
+    ch = _device_build(gpu, off, dst, w, seed=0, stats=True, **knobs)
     progress(f"road24m built: {ch.summary}")
-    check_ch_properties(ch.export(), off, dst, w, ch.summary["rounds"], sample=2_000_000)
+    e = ch.export()
+    got = digest(e["level"], e["score"], e["rank"],
+                 (e["up_tail"], e["up_head"], e["up_w"], e["up_mid"]),
+                 (e["down_tail"], e["down_head"], e["down_w"], e["down_mid"]),
+                 ch.round_stats())
+    progress("road24m digest computed")
+    for k in ("n", "up_arcs", "down_arcs", "rounds", "level", "score", "rank", "up", "down"):
+        assert got[k] == ref[k], k
+    assert got["round_counts"] == ref["round_counts"]
+    assert ch.summary["shortcuts"] == ref["shortcuts"]
+    check_ch_properties(e, off, dst, w, ch.summary["rounds"], sample=2_000_000)
     # sampled distances: Dijkstra stopped after 500k settled vertices gives
     # exact distances to those; targets drawn among them
     rng = np.random.Generator(np.random.PCG64(11))

@@ -86,15 +86,17 @@ def test_hop_mode_needs_a_limit(gpu):
 
 
 def test_hop_global_search_tier(gpu):
-    # the star's two-hop balls outgrow both LDS tiers (see the exact-mode
-    # star test), so hop mode runs in the global tables too
-    off, dst, w = synth.star(3200, seed=5)
-    n = len(off) - 1
-    o, ch = _hop_case("star3200", off, dst, w, synth.labels(n, 3), gpu, 2)
-    assert ch.round_stats()[0]["n_ls_global"] > 0
-    s, t = synth.queries(n, 300, seed=2)
-    od, _ = o.query_batch(s, t)
-    assert np.array_equal(ch.query(s, t), od)
+    # the stars' two-hop balls outgrow the first tier (3201 vertices: the
+    # block tier's LDS table) and the block tier too (6601 vertices: the
+    # global tables); see the exact-mode star test
+    for d, tier in ((3200, "n_ls_fallback"), (6600, "n_ls_global")):
+        off, dst, w = synth.star(d, seed=5)
+        n = len(off) - 1
+        o, ch = _hop_case(f"star{d}", off, dst, w, synth.labels(n, 3), gpu, 2)
+        assert ch.round_stats()[0][tier] > 0
+        s, t = synth.queries(n, 300, seed=2)
+        od, _ = o.query_batch(s, t)
+        assert np.array_equal(ch.query(s, t), od)
 
 
 def test_hop_global_search_tier_after_pruning(gpu):
@@ -103,9 +105,9 @@ def test_hop_global_search_tier_after_pruning(gpu):
     # witness with more arcs does not replace it within H arcs)
     from test_gpu_parity import star_with_prunable_arc
 
-    off, dst, w = star_with_prunable_arc(3200, seed=5)
+    off, dst, w = star_with_prunable_arc(6600, seed=5)
     n = len(off) - 1
-    o, ch = _hop_case("star3200+arc", off, dst, w, synth.labels(n, 3), gpu, 2)
+    o, ch = _hop_case("star6600+arc", off, dst, w, synth.labels(n, 3), gpu, 2)
     rs = ch.round_stats()[0]
     assert rs["n_ls_global"] > 0 and rs["n_pruned"] > 0, rs
     s, t = synth.queries(n, 300, seed=2)

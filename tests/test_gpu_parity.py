@@ -281,18 +281,23 @@ def test_query_distances_past_32_bits(gpu):
 
 
 def test_global_search_tier(gpu):
-    # every leaf's witness search covers the whole star (3201 vertices, past
-    # 3/4 of the 4096-slot LDS tier), so round 0 finishes its searches in
-    # global memory and prunes, scores and selects a second time (with the
-    # all-pairs table off: the star is small enough for the table)
-    off, dst, w = synth.star(3200, seed=5)
-    n = len(off) - 1
-    o, ch = _case("star3200", off, dst, w, synth.labels(n, 3), gpu,
-                  dense_tail=gpu.CH_DENSE_TAIL_OFF)
-    assert ch.round_stats()[0]["n_ls_global"] > 0
-    s, t = synth.queries(n, 500, seed=2)
-    od, _ = o.query_batch(s, t)
-    assert np.array_equal(ch.query(s, t), od)
+    # every leaf's witness search covers the whole star: 3201 vertices pass
+    # the first tier's table and fit the block tier's 8192-slot LDS table
+    # (3/4 of it); 6601 vertices pass that too, so round 0 finishes its
+    # searches in global memory and prunes, scores and selects a second time
+    # (with the all-pairs table off: the smaller star fits the table)
+    for d, tier in ((3200, "n_ls_fallback"), (6600, "n_ls_global")):
+        off, dst, w = synth.star(d, seed=5)
+        n = len(off) - 1
+        o, ch = _case(f"star{d}", off, dst, w, synth.labels(n, 3), gpu,
+                      dense_tail=gpu.CH_DENSE_TAIL_OFF)
+        r0 = ch.round_stats()[0]
+        assert r0[tier] > 0, r0
+        if tier == "n_ls_fallback":
+            assert r0["n_ls_global"] == 0, r0
+        s, t = synth.queries(n, 500, seed=2)
+        od, _ = o.query_batch(s, t)
+        assert np.array_equal(ch.query(s, t), od)
 
 
 def _wcase(name, off, dst, w, labels, gpu, okw, gkw):
@@ -372,9 +377,9 @@ def star_with_prunable_arc(d, seed):
 def test_global_search_tier_after_pruning(gpu):
     # the global-tier searches of round 0 must see the arc the round prunes
     # (pruning follows all searches of the round)
-    off, dst, w = star_with_prunable_arc(3200, seed=5)
+    off, dst, w = star_with_prunable_arc(6600, seed=5)
     n = len(off) - 1
-    o, ch = _case("star3200+arc", off, dst, w, synth.labels(n, 3), gpu,
+    o, ch = _case("star6600+arc", off, dst, w, synth.labels(n, 3), gpu,
                   dense_tail=gpu.CH_DENSE_TAIL_OFF)
     rs = ch.round_stats()[0]
     assert rs["n_ls_global"] > 0 and rs["n_pruned"] > 0, rs
