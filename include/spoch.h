@@ -111,7 +111,7 @@ typedef struct {
   uint32_t ls_sparse;
   uint32_t ls_dense;
   uint32_t dense_deg10;
-  uint32_t priority;   /* CH_PRIO_PLAIN (edge difference, Alg. 4) or CH_PRIO_LEARNED */
+  uint32_t priority;   /* CH_PRIO_PLAIN (edge difference, Alg. 5) or CH_PRIO_LEARNED */
   const float *mlp;    /* CH_PRIO_LEARNED: CH_MLP_PARAMS weights, host memory      */
   uint32_t hop_limit;  /* CH_WPS_HOP: arcs per witness walk, >= 1 (else ignored)  */
   /* Exact mode: once the overlay has at most dense_tail vertices, the
@@ -191,7 +191,10 @@ typedef struct {
 
 typedef struct ch_s ch_t;
 
-/* Per-round counters (CH_F_STATS). */
+/* Per-round counters (CH_F_STATS): the sets of one iteration of Alg. 3's
+ * loop (Sec. "Our Parallel CH Construction Algorithm") -- the search sources
+ * V_W, the rescored vertices V_A, the contracted set V_F and the shortcut set
+ * E+ -- and the work of the round's witness searches. */
 typedef struct {
   uint32_t alive_before;    /* |V_O| at the start of the round                */
   uint32_t n_sources;       /* |V_W|, witness-search sources                  */
@@ -211,9 +214,18 @@ typedef struct {
   float ms_local_search;    /* device time of the first-tier witness-search kernel */
   float ms_total;           /* device time of the whole round (host gaps included) */
   uint32_t n_ls_global;     /* sources searched with tables in global memory   */
+  /* the later search tiers: sources that outgrew the first tier's table run
+   * again with a block of waves per source, in LDS (n_ls_fallback sources),
+   * then with global-memory tables (n_ls_global sources) */
+  float ms_ls_blk;          /* device time of the LDS block tier               */
+  float ms_ls_global;       /* device time of the global-memory tier (0: none)  */
+  uint64_t rows2, arcs2, probes2, inserts2; /* block tier counters, as above    */
+  uint64_t rows3, arcs3, probes3, inserts3; /* global tier counters             */
 } ch_round_stats_t;
 
-/* Whole-build summary. */
+/* Whole-build summary: the size of the CH (Sec. "Contraction Hierarchies":
+ * G_CH holds the upward and downward arcs moved out of the overlay at
+ * contraction, Alg. 7) and of the build. */
 typedef struct {
   uint32_t n;
   uint32_t rounds;
@@ -226,8 +238,8 @@ typedef struct {
 } ch_summary_t;
 
 /* Build the CH of `g`.  Sec. "Our Parallel CH Construction Algorithm",
- * Alg. 2: rounds of LocalSearch (Alg. 3), Score (Alg. 4), Select (Alg. 5)
- * and Contract (Alg. 6) until the overlay is empty, then Postprocessing
+ * Alg. 3: rounds of LocalSearch (Alg. 4), Score (Alg. 5), Select (Alg. 6)
+ * and Contract (Alg. 7) until the overlay is empty, then Postprocessing
  * (rank by level, then score, then label).
  *   g:   input graph; host arrays, or device arrays with CH_F_INPUT_ON_DEVICE
  *   p:   parameters (NULL = defaults: exact mode, no round limit, seed 0)
@@ -297,7 +309,29 @@ int ch_query_batch_stats(const ch_t *ch, const uint32_t *s, const uint32_t *t, u
 int ch_query_batch_noalloc(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                            uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream);
 
-/* Copy the finished CH to host arrays, in original vertex ids.  Any pointer
+/* Counters of the last query batch on a CH (Sec. "Query on Contraction
+ * Hierarchies": one forward and one backward upward search per query).
+ * Queries start in the tier where most of the previous batch ended; a query
+ * whose search outgrows a tier's tables moves to the next tier. */
+typedef struct {
+  uint64_t queries;          /* queries of the last batch                        */
+  uint32_t first_tier;       /* tier (1-4) the batch started in                  */
+  uint32_t counted;          /* 1: rows and arcs were counted (a stats batch)    */
+  uint64_t tier_queries[4];  /* queries that entered each tier                   */
+  float tier_ms[4];          /* device time of each tier's launch (0: not run;   */
+                             /* not measured by ch_query_batch_noalloc)          */
+  uint64_t rows;             /* vertices expanded, every tier and re-expansion   */
+  uint64_t arcs;             /* arcs relaxed, every tier and re-expansion        */
+} ch_query_stats_t;
+
+/* Copies the counters of the CH's last query batch into *out (host).
+ * Errors: CH_E_INVALID (NULL). */
+int ch_get_query_stats(const ch_t *ch, ch_query_stats_t *out);
+
+/* The finished CH (Sec. "Contraction Hierarchies" and "Postprocessing":
+ * levels, the rank order by level then score, and the upward and downward
+ * arc sets E_up and E_down of Alg. 7, each arc with the middle vertex that
+ * unpacks a shortcut).  Copies to host arrays, in original vertex ids.  Any pointer
  * may be NULL to skip that array.
  *   level[n]: round in which the vertex was contracted (0-based)
  *   score[n]: its score when it was selected
@@ -313,9 +347,12 @@ int ch_export(const ch_t *ch, uint32_t *level, int32_t *score, uint32_t *rank,
               uint32_t *down_tail, uint32_t *down_head, uint32_t *down_w,
               uint32_t *down_mid);
 
+/* Copies the whole-build summary into *out (host).  Errors: CH_E_INVALID
+ * (NULL). */
 int ch_get_summary(const ch_t *ch, ch_summary_t *out);
 
-/* Copy min(cap, rounds) per-round records (filled only with CH_F_STATS). */
+/* Copy min(cap, rounds) per-round records (filled only with CH_F_STATS)
+ * into out (host, cap entries).  Errors: CH_E_INVALID (NULL). */
 int ch_get_round_stats(const ch_t *ch, ch_round_stats_t *out, uint32_t cap);
 
 /* Features (8 floats per vertex, original ids) each vertex had when it was

@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE.  This package wraps ``spoch_oracle.c``, a plain,
 sequential C implementation of the construction described by Wan et al.,
 "Parallel Contraction Hierarchies Can Be Efficient and Scalable" (ICS 2025):
-the main loop (Alg. 2), LocalSearch (Alg. 3), Score (Alg. 4), Select
-(Alg. 5), Contract (Alg. 6), Postprocessing, and the bidirectional CH query.
+the main loop (Alg. 3), LocalSearch (Alg. 4), Score (Alg. 5), Select
+(Alg. 6), Contract (Alg. 7), Postprocessing, and the bidirectional CH query.
 
 Only the tests, ``__graft_entry__.smoke()`` and the benchmark's
 ``cpu_baseline`` leg may import it.  It shares no code with the GPU library

@@ -9,12 +9,12 @@
  * benchmark's CPU baseline.  It shares no code with the GPU library.
  *
  * Map of the paper onto this file (published numbering):
- *   orc_round()      one iteration of the main loop of Alg. 2
- *     local_search() Alg. 3, "Step 1: Local Search with Memoization"
- *     prune()        the deletion at the end of Alg. 3
- *     score()        Alg. 4, "Step 2: Score" (edge difference)
- *     select_set()   Alg. 5, "Step 3: Select"
- *     contract()     Alg. 6, "Step 4: Contract", plus the combination of
+ *   orc_round()      one iteration of the main loop of Alg. 3
+ *     local_search() Alg. 4, "Step 1: Local Search with Memoization"
+ *     prune()        the deletion at the end of Alg. 4
+ *     score()        Alg. 5, "Step 2: Score" (edge difference)
+ *     select_set()   Alg. 6, "Step 3: Select"
+ *     contract()     Alg. 7, "Step 4: Contract", plus the combination of
  *                    the shortcut set with the overlay ("Maintaining the
  *                    Overlay Graph Dynamically", keep the smaller weight)
  *   orc_finish()     "Postprocessing": re-index by level, then score
@@ -474,7 +474,7 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
     }
   }
   st->n_alive = n;
-  /* Alg. 2 initialisation: V_A = V_W = V. */
+  /* Alg. 3 initialisation: V_A = V_W = V. */
   for (uint32_t v = 0; v < n; v++) {
     st->VW[v] = v;
     st->VA[v] = v;
@@ -490,7 +490,7 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
 }
 
 /* ------------------------------------------------------------------ */
-/* Step 1: LocalSearch (Alg. 3)                                        */
+/* Step 1: LocalSearch (Alg. 4)                                        */
 /* ------------------------------------------------------------------ */
 
 static void reset_touched(orc_state *st) {
@@ -610,7 +610,7 @@ static int wps_settled(orc_state *st, uint32_t s, uint64_t bound, uint32_t theta
   return ORC_OK;
 }
 
-/* Alg. 3.  For each source s in V_W, the target set V_n collects the
+/* Alg. 4.  For each source s in V_W, the target set V_n collects the
  * out-neighbours v of every affected out-neighbour u of s, except s itself
  * and pairs already in the memo.  One search from s then settles them all
  * and the distances go to the memo.  READING: the search radius is D_s, the
@@ -681,7 +681,7 @@ static int local_search(orc_state *st, orc_round_stats *rs) {
   return rc;
 }
 
-/* Pruning at the end of Alg. 3: delete overlay arc (s, v) of a source s in
+/* Pruning at the end of Alg. 4: delete overlay arc (s, v) of a source s in
  * V_W when its weight exceeds the memoized distance.  READING: applied after
  * all searches of the round, with any memo entry (of this or an earlier
  * round) as the justification. */
@@ -705,7 +705,7 @@ static void prune(orc_state *st, orc_round_stats *rs) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Step 2: Score (Alg. 4)                                              */
+/* Step 2: Score (Alg. 5)                                              */
 /* ------------------------------------------------------------------ */
 
 /* |N(u)| with N(u) = N_in(u) union N_out(u) as a set of vertices. */
@@ -791,7 +791,7 @@ static void vertex_features(const orc_state *st, uint32_t u, int32_t ed, uint32_
   f[7] = squash(pairs, 8.0f);
 }
 
-/* Alg. 4: P[u] = -|N(u)| + number of pairs (v1, v2) in N_in(u) x N_out(u)
+/* Alg. 5: P[u] = -|N(u)| + number of pairs (v1, v2) in N_in(u) x N_out(u)
  * whose path through u is no longer than the memoized distance, or whose
  * distance is not memoized.  READING: pairs with v1 == v2 are skipped (a
  * shortcut would be a self-loop); the test is "<=" (the text's "equal to or
@@ -837,7 +837,7 @@ static void score(orc_state *st, orc_round_stats *rs) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Step 3: Select (Alg. 5)                                             */
+/* Step 3: Select (Alg. 6)                                             */
 /* ------------------------------------------------------------------ */
 
 /* Strict order on (score, label); labels are distinct. */
@@ -846,7 +846,7 @@ static int key_less(const orc_state *st, uint32_t a, uint32_t b) {
   return st->label[a] < st->label[b];
 }
 
-/* Alg. 5: u is selected when its (score, label) is smaller than that of
+/* Alg. 6: u is selected when its (score, label) is smaller than that of
  * every neighbour in N_in(u) union N_out(u).  A vertex with no neighbour is
  * selected.  Returns the selected set in list1. */
 static uint32_t select_set(orc_state *st, uint32_t *sel) {
@@ -864,7 +864,7 @@ static uint32_t select_set(orc_state *st, uint32_t *sel) {
 }
 
 /* ------------------------------------------------------------------ */
-/* Step 4: Contract (Alg. 6) and combination of E+ with the overlay    */
+/* Step 4: Contract (Alg. 7) and combination of E+ with the overlay    */
 /* ------------------------------------------------------------------ */
 
 static int contract(orc_state *st, const uint32_t *VF, uint32_t nF, orc_round_stats *rs) {
@@ -1029,7 +1029,7 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
-/* main loop (Alg. 2)                                                  */
+/* main loop (Alg. 3)                                                  */
 /* ------------------------------------------------------------------ */
 
 static uint64_t overlay_arc_count(const orc_state *st) {

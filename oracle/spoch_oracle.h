@@ -47,7 +47,7 @@ enum {
 
 /* Priority functions. */
 enum {
-  ORC_PRIO_PLAIN = 0,   /* edge difference (Alg. 4)                       */
+  ORC_PRIO_PLAIN = 0,   /* edge difference (Alg. 5)                       */
   ORC_PRIO_LEARNED = 1  /* MLP over per-vertex features (see below)       */
 };
 

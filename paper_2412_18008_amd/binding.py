@@ -34,7 +34,7 @@ CH_Q_ON_DEVICE = 0x1
 EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
             "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version", "ch_export_features",
             "ch_mlp_forward", "ch_mlp_grad", "ch_mlp_train", "ch_query_batch_stats",
-            "ch_query_batch_noalloc")
+            "ch_query_batch_noalloc", "ch_get_query_stats")
 
 
 class ChError(RuntimeError):
@@ -106,7 +106,17 @@ class RoundStats(C.Structure):
         ("memo_probes", C.c_uint64), ("memo_inserts", C.c_uint64),
         ("n_ls_fallback", C.c_uint32), ("ls_tier1", C.c_uint32), ("ms_local_search", C.c_float),
         ("ms_total", C.c_float), ("n_ls_global", C.c_uint32),
+        ("ms_ls_blk", C.c_float), ("ms_ls_global", C.c_float),
+        ("rows2", C.c_uint64), ("arcs2", C.c_uint64), ("probes2", C.c_uint64),
+        ("inserts2", C.c_uint64), ("rows3", C.c_uint64), ("arcs3", C.c_uint64),
+        ("probes3", C.c_uint64), ("inserts3", C.c_uint64),
     ]
+
+
+class QueryStats(C.Structure):
+    _fields_ = [("queries", C.c_uint64), ("first_tier", C.c_uint32), ("counted", C.c_uint32),
+                ("tier_queries", C.c_uint64 * 4), ("tier_ms", C.c_float * 4),
+                ("rows", C.c_uint64), ("arcs", C.c_uint64)]
 
 
 class Summary(C.Structure):
@@ -148,6 +158,8 @@ def lib():
         L.ch_query_batch_stats.restype = i32
         L.ch_query_batch_noalloc.argtypes = [vp, vp, vp, u64, vp, vp, u32, vp]
         L.ch_query_batch_noalloc.restype = i32
+        L.ch_get_query_stats.argtypes = [vp, C.POINTER(QueryStats)]
+        L.ch_get_query_stats.restype = i32
         L.ch_export_features.argtypes = [vp, vp]
         L.ch_export_features.restype = i32
         L.ch_mlp_forward.argtypes = [vp, u64, vp, vp, vp, u32, vp]
@@ -234,6 +246,14 @@ class CH:
                                           None),
                "ch_query_batch_stats")
         return dist, vis
+
+    def last_query_stats(self):
+        """Counters and per-tier device times of the last query batch."""
+        qs = QueryStats()
+        _check(lib().ch_get_query_stats(self.h, C.byref(qs)), "ch_get_query_stats")
+        return {"queries": qs.queries, "first_tier": qs.first_tier, "counted": bool(qs.counted),
+                "tier_queries": list(qs.tier_queries), "tier_ms": list(qs.tier_ms),
+                "rows": qs.rows, "arcs": qs.arcs}
 
     def query_noalloc(self, s, t, visited=True, stream=None, waves=0, window=0):
         """ch_query_batch_noalloc on torch CUDA uint32 tensors s, t: (dist,

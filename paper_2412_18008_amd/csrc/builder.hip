@@ -1,5 +1,5 @@
 // builder.hip -- host driver of the round-synchronous CH construction
-// (Alg. 2 of Wan et al.): ingest, then rounds of LocalSearch, Score, Select
+// (Alg. 3 of Wan et al.): ingest, then rounds of LocalSearch, Score, Select
 // and Contract on a compacted overlay until no vertex is left, then the
 // postprocessing in post.hip.
 #include <hip/hip_runtime.h>
@@ -56,7 +56,7 @@ static uint64_t next_pow2(uint64_t x) {
 
 // Device-side counters read back by the host (one struct, one copy).
 struct DevCtr {
-  LsCounters ls, ls2;  // first search tier; later tiers
+  LsCounters ls, ls2, ls3;  // first search tier; block tier; global tier
   unsigned long long bound, pruned, kept;
   uint32_t work1, work2, novf1, novf2;  // persistent scheduling and overflow counts
   uint32_t err, bad;
@@ -109,7 +109,9 @@ struct Builder {
   hipEvent_t ev_tail[2] = {nullptr, nullptr};
   DBuf dctr, tmp;
   DevCtr *hctr = nullptr;  // pinned
-  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  // round timing: 1 start, 2/3 first search tier, 4 end, 5/6 block tier,
+  // 7/8 global tier
+  hipEvent_t ev[9] = {};
   hipEvent_t ev_rb = nullptr;  // readback completion
   uint64_t up_cap = 0, dn_cap = 0;
   // disjoint-union batch: graph of each original vertex, per-graph
@@ -933,7 +935,7 @@ struct Builder {
           break;
         }
       }
-      // ---- Step 1: LocalSearch (Alg. 3) --------------------------------
+      // ---- Step 1: LocalSearch (Alg. 4) --------------------------------
       // memo capacity for this round's inserts (bound computed with the
       // previous round's final readback)
       TRY(ensure_memo(next_bound, O.n));
@@ -945,6 +947,7 @@ struct Builder {
       if (!tab_on && prm.wps_mode == CH_WPS_EXACT && tail != CH_DENSE_TAIL_OFF && O.n &&
           O.n <= tail)
         TRY(build_table(v));
+      bool blk_ran = false;  // the block tier was launched (its events recorded)
       if (nw && tab_on) {
         rs.ls_tier1 = CH_LS_TABLE;
         if (stats) HIP_TRY(hipEventRecord(ev[2], st));
@@ -975,8 +978,11 @@ struct Builder {
         }
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[3], st));
+        if (stats) HIP_TRY(hipEventRecord(ev[5], st));
+        blk_ran = true;
         launch_ls_blk(v);
         HIP_TRY(hipGetLastError());
+        if (stats) HIP_TRY(hipEventRecord(ev[6], st));
       }
       // Steps 1 (pruning) to 4 (contraction counts) run before the searches
       // are known to be complete; when a source needed the global tier, the
@@ -991,14 +997,14 @@ struct Builder {
       HIP_TRY(cdn.ensure(((size_t)ncap * 2 + 1) * 4));
       HIP_TRY(cpair.ensure(((size_t)ncap * 2 + 1) * 4));
       auto after_search = [&]() -> int {
-        // pruning at the end of Alg. 3
+        // pruning at the end of Alg. 4
         if (nw) {
           dispatch(Gp, [&] { launch_prune<4>(v, nw); }, [&] { launch_prune<8>(v, nw); },
                    [&] { launch_prune<16>(v, nw); }, [&] { launch_prune<32>(v, nw); },
                    [&] { launch_prune<64>(v, nw); });
           HIP_TRY(hipGetLastError());
         }
-        // ---- Step 2: Score (Alg. 4) ------------------------------------
+        // ---- Step 2: Score (Alg. 5) ------------------------------------
         if (na) {
           dispatch(Gs, [&] { launch_score<4>(v, na); }, [&] { launch_score<8>(v, na); },
                    [&] { launch_score<16>(v, na); }, [&] { launch_score<32>(v, na); },
@@ -1009,7 +1015,7 @@ struct Builder {
                                         f_feat.as<float>(), mlpw.as<float>(), O.P.as<int32_t>(),
                                         cus, st));
         }
-        // ---- Step 3: Select (Alg. 5) -----------------------------------
+        // ---- Step 3: Select (Alg. 6) -----------------------------------
         k_keys<<<grid(O.n), 256, 0, st>>>(O.n, O.P.as<int32_t>(), O.gid.as<uint32_t>(),
                                           ch->label.as<uint32_t>(), key.as<uint64_t>(),
                                           S.as<uint8_t>(), newA.as<uint8_t>(),
@@ -1020,7 +1026,7 @@ struct Builder {
                  [&] { launch_select<64>(v); });
         HIP_TRY(hipGetLastError());
         HIP_TRY(select_flags(F.as<uint8_t>(), O.n, vf.as<uint32_t>(), &dc()->c32[C_NF], tmp, st));
-        // ---- Step 4 counts (Alg. 6): arcs and shortcut pairs per selected
+        // ---- Step 4 counts (Alg. 7): arcs and shortcut pairs per selected
         // vertex, exclusive scans into the second halves
         dispatch(Gs, [&] { launch_ccount<4>(v, ncap); }, [&] { launch_ccount<8>(v, ncap); },
                  [&] { launch_ccount<16>(v, ncap); }, [&] { launch_ccount<32>(v, ncap); },
@@ -1064,22 +1070,32 @@ struct Builder {
         }
         auto global = hop ? k_local_search_global<true, kLsBlkWaves>
                           : k_local_search_global<false, kLsBlkWaves>;
+        if (stats) HIP_TRY(hipEventRecord(ev[7], st));
         global<<<(unsigned)ntab, kWave * kLsBlkWaves, 0, st>>>(
-            v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), mref(), &dc()->ls2, gtabs.as<uint32_t>(), cap, fstate().ws,
+            v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), mref(), &dc()->ls3, gtabs.as<uint32_t>(), cap, fstate().ws,
             &dc()->err, prm.hop_limit);
         HIP_TRY(hipGetLastError());
+        if (stats) HIP_TRY(hipEventRecord(ev[8], st));
         TRY(after_search());
         TRY(readback());
         TRY(check_err());
       }
-      mcount += hctr->ls.inserts + hctr->ls2.inserts;
-      rs.n_targets = hctr->ls.targets + hctr->ls2.targets;
+      mcount += hctr->ls.inserts + hctr->ls2.inserts + hctr->ls3.inserts;
+      rs.rows2 = hctr->ls2.rows;  // block tier
+      rs.arcs2 = hctr->ls2.arcs;
+      rs.probes2 = hctr->ls2.probes;
+      rs.inserts2 = hctr->ls2.inserts;
+      rs.rows3 = hctr->ls3.rows;  // global tier
+      rs.arcs3 = hctr->ls3.arcs;
+      rs.probes3 = hctr->ls3.probes;
+      rs.inserts3 = hctr->ls3.inserts;
+      rs.n_targets = hctr->ls.targets + hctr->ls2.targets + hctr->ls3.targets;
       const uint32_t nf = hctr->c32[C_NF];
       rs.n_selected = nf;
       rs.n_pruned = hctr->pruned;
       if (nf == 0) return set_error(CH_E_DEVICE, "no vertex selected in a round (internal error)");
 
-      // ---- Step 4: Contract (Alg. 6) -----------------------------------
+      // ---- Step 4: Contract (Alg. 7) -----------------------------------
       const uint32_t tup = hctr->c32[C_UP], tdn = hctr->c32[C_DN], ne = hctr->c32[C_PAIR];
       if (ch->nup + tup > up_cap) {
         uint64_t nc = std::max<uint64_t>((ch->nup + tup) * 3 / 2, up_cap * 2);
@@ -1228,6 +1244,8 @@ struct Builder {
         HIP_TRY(hipEventElapsedTime(&tot, ev[1], ev[4]));
         rs.ms_local_search = ls;
         rs.ms_total = tot;
+        if (blk_ran) HIP_TRY(hipEventElapsedTime(&rs.ms_ls_blk, ev[5], ev[6]));
+        if (rs.n_ls_global) HIP_TRY(hipEventElapsedTime(&rs.ms_ls_global, ev[7], ev[8]));
       }
       ch->stats.push_back(rs);
       round++;
@@ -1621,5 +1639,7 @@ ch_s::~ch_s() {
                      &dn_w, &dn_m, &q_upoff, &q_uparc, &q_dnoff, &q_dnarc, &q_lstart, &q_wend, &q_s, &q_t, &q_d,
                      &q_ovf, &q_tab, &q_ctr, &rec, &q_v, &q_ovf2, &q_gtab};
   for (sp::DBuf *b : all) b->release();
+  for (auto &e : q_ev)
+    if (e) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

@@ -37,6 +37,8 @@ struct ch_s {
   // query scratch
   sp::DBuf q_s, q_t, q_d, q_v, q_ovf, q_ovf2, q_tab, q_gtab, q_ctr;
   int q_first_tier = 1;  // query tier where the previous batch mostly ended
+  ch_query_stats_t qstats{};              // counters of the last query batch
+  hipEvent_t q_ev[8] = {};                // tier timing (created on first use)
 
   // features at contraction (CH_F_RECORD_FEATURES), 8 floats per vertex
   bool has_rec = false;

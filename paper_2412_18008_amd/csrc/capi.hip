@@ -85,6 +85,13 @@ int ch_get_summary(const ch_t *ch, ch_summary_t *out) {
   return CH_OK;
 }
 
+int ch_get_query_stats(const ch_t *ch, ch_query_stats_t *out) {
+  sp::clear_error();
+  if (!ch || !out) return set_error(CH_E_INVALID, "ch and out must not be NULL");
+  *out = ch->qstats;
+  return CH_OK;
+}
+
 int ch_get_round_stats(const ch_t *ch, ch_round_stats_t *out, uint32_t cap) {
   sp::clear_error();
   if (!ch || (cap && !out)) return set_error(CH_E_INVALID, "ch and out must not be NULL");

@@ -10,7 +10,7 @@
 // Floyd-Warshall over 64 x 64 tiles in LDS); every later round in exact
 // mode answers its searches from the table: the same targets, radius D_s,
 // memo entries (target distances <= D_s) and reached-vertex count as the
-// search of Alg. 3 would give.
+// search of Alg. 4 would give.
 #pragma once
 
 #include "common.hpp"
@@ -198,7 +198,7 @@ __global__ void k_tab_posl(uint32_t n, const uint32_t *__restrict__ gid,
     posl[u] = pos_of_gid[gid[u]];
 }
 
-// Witness search of Alg. 3 answered from the table (exact mode): one group
+// Witness search of Alg. 4 answered from the table (exact mode): one group
 // of 64 lanes per source.  Per group in LDS: a seen bit and the largest
 // two-arc length per table position.
 constexpr int kTabMaxN = 4096;  // largest table the lookup kernel serves

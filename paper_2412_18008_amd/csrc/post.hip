@@ -23,6 +23,16 @@ namespace sp {
     if (r_ != CH_OK) return r_; \
   } while (0)
 
+// Default level window of the query: none on a hierarchy of at most
+// kQShallow levels (the per-step bookkeeping of a window costs more than it
+// saves there: road1m, 182 levels, 31.1 ms per 100k queries without one,
+// 34.6-35.9 ms with 24 to 128 levels), else kQWindow levels (road24m, 412
+// levels: 4.04 s per 1M queries with 48, 4.26 s with 24, 4.66 s with none).
+// A deeper hierarchy also starts its first query batch in the second tier:
+// on road24m 99.95% of the queries outgrow the first tier's tables.
+constexpr uint32_t kQWindow = 48;
+constexpr uint32_t kQShallow = 256;
+
 static int bits_for(uint32_t n) {
   int b = 1;
   while (b < 32 && (1ull << b) < (uint64_t)n) b++;
@@ -223,6 +233,7 @@ static int level_starts(ch_s *ch) {
   HIP_TRY(ch->q_lstart.ensure(((size_t)nlev + 1) * 4));
   // level-window ends, filled by the first query batch that uses a window
   HIP_TRY(ch->q_wend.ensure((size_t)std::max<uint32_t>(ch->n, 1) * 4));
+  ch->q_first_tier = ch->rounds > kQShallow ? 2 : 1;
   if (ch->n)
     k_level_by_rank<<<gridn(ch->n), 256, 0, st>>>(ch->n, ch->rank.as<uint32_t>(),
                                                   ch->level.as<uint32_t>(), lvr.as<uint32_t>());
@@ -442,7 +453,8 @@ __device__ void qtab_reset(const QTab<IdxT, DistT, GL> &T) {
 // the table or of the distance type.
 template <typename IdxT, typename DistT, bool GL>
 __device__ bool closure(const QTab<IdxT, DistT, GL> &T, const uint32_t *__restrict__ off,
-                        const uint2 *__restrict__ arc, uint32_t src) {
+                        const uint2 *__restrict__ arc, uint32_t src, uint32_t &nrows,
+                        uint32_t &narcs) {
   const int l = lane_id();
   constexpr unsigned long long kMax = sizeof(DistT) == 4 ? 0xFFFFFFFEull : 0xFFFFFFFFFFFFFFFEull;
   T.sync();
@@ -479,6 +491,8 @@ __device__ bool closure(const QTab<IdxT, DistT, GL> &T, const uint32_t *__restri
         const uint32_t vx = T.ld(&T.key[x]);
         rs = off[vx];
         rl = off[vx + 1] - rs;
+        nrows++;
+        narcs += rl;
       }
       const uint32_t incl = gscan_incl<kWave>(rl);
       const uint32_t total = __shfl(incl, kWave - 1, kWave);
@@ -559,13 +573,6 @@ __device__ unsigned long long meet(const QTab<IdxT, DistT, GL> &Fw, const QTab<I
 // reached through L2).
 // ---------------------------------------------------------------------------
 constexpr int kQUnroll = 8;
-// Default level window of the query: none on a hierarchy of at most
-// kQShallow levels (the per-step bookkeeping of a window costs more than it
-// saves there: road1m, 182 levels, 31.1 ms per 100k queries without one,
-// 34.6-35.9 ms with 24 to 128 levels), else kQWindow levels (road24m, 412
-// levels: 4.04 s per 1M queries with 48, 4.26 s with 24, 4.66 s with none).
-constexpr uint32_t kQWindow = 48;
-constexpr uint32_t kQShallow = 256;
 
 template <uint32_t CAP, uint32_t TOP = 0, uint32_t LIST = 2 * (CAP * 7 / 8)>
 struct QLds {
@@ -760,7 +767,8 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     const uint2 *__restrict__ dnarc, unsigned long long *__restrict__ dist,
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
     uint32_t *__restrict__ ovf_count, const uint32_t *__restrict__ wend,
-    unsigned long long *__restrict__ work, L *__restrict__ gtab) {
+    unsigned long long *__restrict__ work, L *__restrict__ gtab,
+    unsigned long long *__restrict__ qcount) {
   using E = typename L::Entry;
   constexpr uint32_t CAP = sizeof(((L *)nullptr)->key[0]) / 4;
   constexpr uint32_t TOP = L::kTop, NS = L::kSlots;
@@ -787,6 +795,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
   };
   qclear<GM>(S, tid, NT);
   qsync<NW, GM>();
+  uint32_t nrows = 0, narcs = 0;  // expansions and relaxations (stats batches)
   for (;;) {
     // every thread has read the previous index (it passed a barrier since)
     if (tid == 0) {
@@ -905,6 +914,8 @@ __global__ void __launch_bounds__(64 * NW) k_query(
             const uint32_t *o = dr ? dnoff : upoff;
             rs = o[vx];
             rl = o[vx + 1] - rs;
+            nrows++;
+            narcs += rl;
           }
         }
         const uint32_t incl = gscan_incl<kWave>(rl);
@@ -1026,6 +1037,13 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     qclear<GM>(S, tid, NT);
     qsync<NW, GM>();
   }
+  if (qcount) {
+    const uint64_t r = gsum64<kWave>(nrows), a = gsum64<kWave>(narcs);
+    if (l == 0) {
+      atomicAdd(&qcount[0], (unsigned long long)r);
+      atomicAdd(&qcount[1], (unsigned long long)a);
+    }
+  }
 }
 
 // Queries whose closures outgrow LDS or 32-bit distances: tables of cap
@@ -1039,7 +1057,7 @@ __global__ void __launch_bounds__(64) k_query_global(
     const uint32_t *__restrict__ dnoff, const uint2 *__restrict__ dnarc,
     unsigned long long *__restrict__ dist, uint32_t *__restrict__ visited,
     uint32_t *__restrict__ tabs, uint32_t cap, uint32_t limit, uint32_t *__restrict__ ovf_list,
-    uint32_t *__restrict__ ovf_count) {
+    uint32_t *__restrict__ ovf_count, unsigned long long *__restrict__ qcount) {
   // per direction: key[cap], dist[cap] (2 words each), flag[cap], order, fr0,
   // fr1 [cap] and 4 counters = 8 cap + 4 words
   const size_t per = (size_t)cap * 8 + 4;
@@ -1058,11 +1076,12 @@ __global__ void __launch_bounds__(64) k_query_global(
     T[d].shift = 32 - __builtin_ctz(cap);
     T[d].limit = limit;
   }
+  uint32_t nrows = 0, narcs = 0;  // expansions and relaxations (stats batches)
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
     const uint32_t k = list[i];
     const uint32_t rs = rank[qs[k]], rt = rank[qt[k]];
-    bool ok = closure(T[0], upoff, uparc, rs);
-    if (ok) ok = closure(T[1], dnoff, dnarc, rt);
+    bool ok = closure(T[0], upoff, uparc, rs, nrows, narcs);
+    if (ok) ok = closure(T[1], dnoff, dnarc, rt, nrows, narcs);
     if (ok) {
       const unsigned long long mu = meet(T[0], T[1]);
       if (lane_id() == 0) {
@@ -1076,7 +1095,17 @@ __global__ void __launch_bounds__(64) k_query_global(
     qtab_reset(T[0]);
     qtab_reset(T[1]);
   }
+  if (qcount) {
+    const uint64_t r = gsum64<kWave>(nrows), a = gsum64<kWave>(narcs);
+    if (lane_id() == 0) {
+      atomicAdd(&qcount[0], (unsigned long long)r);
+      atomicAdd(&qcount[1], (unsigned long long)a);
+    }
+  }
 }
+
+// Words of the per-batch query counters (see query_tiers).
+constexpr uint32_t kQCtrWords = 32;
 
 // The tiers of one batch on device arrays (ds, dt, dd, dv).  Scratch comes
 // from `sc`: sc.ctr (16 words), sc.ovf1 / sc.ovf2 (q entries each),
@@ -1101,8 +1130,19 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   // tiers 1-3 at [8], [10], [12]
   uint32_t *ctr = sc.ctr;
   // cleared by a fill kernel, not a memset (the scratch may be in use by a
-  // captured sequence of this stream)
-  HIP_TRY(fill_u32(ctr, 0u, 16, st));
+  // captured sequence of this stream); words 16-19: two 64-bit counters of
+  // expanded vertices and relaxed arcs (stats batches)
+  HIP_TRY(fill_u32(ctr, 0u, kQCtrWords, st));
+  unsigned long long *qcount = dv ? reinterpret_cast<unsigned long long *>(ctr + 16) : nullptr;
+  ch_query_stats_t qsn{};
+  qsn.queries = q;
+  qsn.first_tier = (uint32_t)ch->q_first_tier;
+  qsn.counted = dv ? 1u : 0u;
+  // tier timing: events 2t and 2t+1 around tier t (ch_query_batch only)
+  hipEvent_t *ev = sc.timed ? ch->q_ev : nullptr;
+  if (ev && !ev[0])
+    for (int i = 0; i < 8; i++) HIP_TRY(hipEventCreate(&ev[i]));
+  auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device);
   const uint32_t *rank = ch->rank.as<uint32_t>();
@@ -1126,31 +1166,37 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   }
   const uint32_t *wend = win ? ch->q_wend.as<uint32_t>() : nullptr;
   if (first <= 1) {
+    qsn.tier_queries[0] = q;
+    HIP_TRY(mark(0));
     const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * kQTier1PerCU);
     const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
 #define SP_QUERY_LAUNCH(NW)                                                                    \
   k_query<NW, QTier1, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
       q, ch->n, nullptr, nullptr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,   \
-      ovf1, ctr, wend, reinterpret_cast<unsigned long long *>(ctr + 8), nullptr)
+      ovf1, ctr, wend, reinterpret_cast<unsigned long long *>(ctr + 8), nullptr, qcount)
     if (nw == 1) SP_QUERY_LAUNCH(1);
     else if (nw == 2) SP_QUERY_LAUNCH(2);
     else if (nw == 8) SP_QUERY_LAUNCH(8);
     else SP_QUERY_LAUNCH(4);
 #undef SP_QUERY_LAUNCH
     HIP_TRY(hipGetLastError());
+    HIP_TRY(mark(1));
   }
   if (first <= 2) {
+    HIP_TRY(mark(2));
     k_query<16, QTier2, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
         dnarc, dd, dv, ovf2, ctr + 2, wend, reinterpret_cast<unsigned long long *>(ctr + 10),
-        nullptr);
+        nullptr, qcount);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(mark(3));
   }
   uint32_t hc[4] = {0, 0, 0, 0};
   HIP_TRY(hipMemcpyAsync(hc, ctr, 16, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (hc[1]) return set_error(CH_E_INVALID, "a query vertex id is >= n");
   const uint64_t into2 = first <= 1 ? hc[0] : q;
+  if (first <= 2) qsn.tier_queries[1] = into2;
   uint64_t n3 = first <= 2 ? hc[2] : q;
   uint32_t *list3 = first <= 2 ? ovf2 : nullptr;
   uint32_t n4 = 0;
@@ -1159,10 +1205,13 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
     uint64_t nb = std::min<uint64_t>(n3, (uint64_t)cus * 4);
     TRY(sc.tier3(n3, &tabs, &nb));
     // overflows into ctr[4]; the input count is tier 2's, on the device
+    qsn.tier_queries[2] = n3;
+    HIP_TRY(mark(4));
     k_query<8, QTier3, true><<<(unsigned)nb, 512, 0, st>>>(
         q, ch->n, list3, ctr + 2, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,
-        ovf1, ctr + 4, wend, reinterpret_cast<unsigned long long *>(ctr + 12), tabs);
+        ovf1, ctr + 4, wend, reinterpret_cast<unsigned long long *>(ctr + 12), tabs, qcount);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(mark(5));
     uint32_t h2[4] = {0, 0, 0, 0};  // ctr[1..4]
     HIP_TRY(hipMemcpyAsync(h2, ctr + 1, 16, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1179,9 +1228,13 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
       HIP_TRY(fill_u32(b, SP_EMPTY32, 3ull * cap, st));
       HIP_TRY(fill_u32(b + 3ull * cap, 0u, (size_t)cap * 5 + 4, st));
     }
+    qsn.tier_queries[3] = n4;
+    HIP_TRY(mark(6));
     k_query_global<<<(unsigned)ntab, 64, 0, st>>>(n4, ovf1, ds, dt, rank, upoff, uparc, dnoff,
-                                                 dnarc, dd, dv, tabs, cap, limit, ovf2, ctr + 6);
+                                                 dnarc, dd, dv, tabs, cap, limit, ovf2, ctr + 6,
+                                                 qcount);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(mark(7));
     if (limit < cap) {
       uint32_t n5 = 0;
       HIP_TRY(hipMemcpyAsync(&n5, ctr + 6, 4, hipMemcpyDeviceToHost, st));
@@ -1194,6 +1247,17 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   // where the next batch starts
   if (first <= 1 && hc[0] * 2 > q) ch->q_first_tier = 2;
   if (first <= 2 && into2 && (uint64_t)hc[2] * 2 > into2) ch->q_first_tier = 3;
+  // counters and tier times of this batch (one more wait, for the copies)
+  if (qcount || ev) {
+    unsigned long long qc[2] = {0, 0};
+    if (qcount) HIP_TRY(hipMemcpyAsync(qc, qcount, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    qsn.rows = qc[0];
+    qsn.arcs = qc[1];
+    for (int t = 0; ev && t < 4; t++)
+      if (qsn.tier_queries[t]) HIP_TRY(hipEventElapsedTime(&qsn.tier_ms[t], ev[2 * t], ev[2 * t + 1]));
+  }
+  ch->qstats = qsn;
   return CH_OK;
 }
 
@@ -1201,6 +1265,7 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
 struct QScratchCH {
   ch_s *ch;
   uint32_t *ctr = nullptr, *ovf1 = nullptr, *ovf2 = nullptr;
+  bool timed = true;
   int tier3(uint64_t, QTier3 **tabs, uint64_t *nb) {
     HIP_TRY(ch->q_tab.ensure(*nb * sizeof(QTier3)));
     *tabs = reinterpret_cast<QTier3 *>(ch->q_tab.p);
@@ -1229,7 +1294,7 @@ int query_batch(const ch_s *chc, const uint32_t *s, const uint32_t *t, uint64_t 
   const bool on_dev = flags & CH_Q_ON_DEVICE;
   const uint32_t *ds = s, *dt = t;
   unsigned long long *dd = reinterpret_cast<unsigned long long *>(dist);
-  HIP_TRY(ch->q_ctr.ensure(64));
+  HIP_TRY(ch->q_ctr.ensure(kQCtrWords * 4));
   if (!on_dev) {
     HIP_TRY(ch->q_s.ensure(q * 4));
     HIP_TRY(ch->q_t.ensure(q * 4));
@@ -1268,6 +1333,7 @@ constexpr uint32_t kNaT3Blocks = 64;
 constexpr uint32_t kNaT4Cap = 1u << 20;   // never fills on a CH of <= 524,287 vertices
 constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr size_t kNaOvf1 = 256;
+static_assert(kQCtrWords * 4 <= kNaOvf1, "query counters in the scratch array");
 constexpr size_t kNaOvf2 = kNaOvf1 + kNaChunk * 4;
 constexpr size_t kNaT3 = na_align(kNaOvf2 + kNaChunk * 4);
 constexpr size_t kNaT4 = na_align(kNaT3 + (size_t)kNaT3Blocks * sizeof(QTier3));
@@ -1306,6 +1372,7 @@ struct QScratchFixed {
   uint8_t *base;
   uint32_t n;
   uint32_t *ctr, *ovf1, *ovf2;
+  bool timed = false;  // creating events is left to ch_query_batch
   int tier3(uint64_t, QTier3 **tabs, uint64_t *nb) {
     *nb = std::min<uint64_t>(*nb, kNaT3Blocks);
     *tabs = reinterpret_cast<QTier3 *>(base + kNaT3);

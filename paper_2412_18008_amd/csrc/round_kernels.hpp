@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(kWave * NW) k_local_search_global(
   flush_stats<kWave>(ss, cnt);
 }
 
-// Pruning (end of Alg. 3): an out-arc (s, v) of a source s whose weight
+// Pruning (end of Alg. 4): an out-arc (s, v) of a source s whose weight
 // exceeds the memoized dist(s, v) is deleted (weight set to SP_INF32 in both
 // the forward row of s and the reverse row of v).  A group of G lanes per
 // source, lanes over its out-arcs.
@@ -522,7 +522,7 @@ __global__ void __launch_bounds__(256) k_unprune(Overlay ov, const uint32_t *__r
 }
 
 // ===========================================================================
-// Score (Alg. 4) -- group of G lanes per affected vertex
+// Score (Alg. 5) -- group of G lanes per affected vertex
 // ===========================================================================
 // Number of pairs (v1, v2) in N_in(u) x N_out(u), v1 != v2, both arcs live,
 // whose path through u is no longer than the memoized distance or whose
@@ -681,7 +681,7 @@ __global__ void __launch_bounds__(256) k_score(Overlay ov, const uint32_t *__res
 }
 
 // ===========================================================================
-// Select (Alg. 5)
+// Select (Alg. 6)
 // ===========================================================================
 // Selection keys (priority, label); also clears the per-vertex flags S and
 // newA that the contraction sets and the shortcut-row bounds (4 arrays of n)
@@ -747,7 +747,7 @@ __global__ void __launch_bounds__(256) k_select(Overlay ov, const uint64_t *__re
 }
 
 // ===========================================================================
-// Contract (Alg. 6)
+// Contract (Alg. 7)
 // ===========================================================================
 // Per selected vertex: live out-arcs, live in-arcs, shortcut pairs (the
 // pair count of the score when the vertex was rescored this round).

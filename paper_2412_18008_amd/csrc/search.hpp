@@ -1,5 +1,5 @@
 // search.hpp -- the witness-path search of one source by one group of G
-// lanes (Alg. 3, "Step 1: Local Search with Memoization").
+// lanes (Alg. 4, "Step 1: Local Search with Memoization").
 //
 // For a source s in V_W the group
 //   1. gathers the target set V_n: every out-neighbour v != s of every

@@ -2,7 +2,7 @@
 // with no host round trip per round.
 //
 // Once the overlay fits the all-pairs table (at most 4096 vertices), the
-// remaining rounds of Alg. 2 run as a fixed sequence of five launches per
+// remaining rounds of Alg. 3 run as a fixed sequence of five launches per
 // round whose sizes live on the device: the host enqueues rounds in batches
 // and reads the state back once per batch; launches after the last round
 // return at once.  Vertices are table positions (0 .. n0 - 1) for the whole
@@ -184,7 +184,7 @@ __global__ void k_tail_lrank(TailArgs A) {
   for (uint32_t k = blockIdx.x * kTailWaves + threadIdx.x / kWave; k < (count); \
        k += gridDim.x * kTailWaves)
 
-// Step 1 (Alg. 3), answered from the table: per source s, the targets are
+// Step 1 (Alg. 4), answered from the table: per source s, the targets are
 // the vertices v != s two arcs away through an affected out-neighbour with
 // no memo entry (s, v); the search radius D_s is the longest such two-arc
 // path; every target gets its entry.  Then pruning: an out-arc (s, v)
@@ -366,7 +366,7 @@ __device__ __forceinline__ void tail_pairs(const TailArgs &A, uint32_t u, uint32
   }
 }
 
-// Step 2 (Alg. 4): edge difference of every affected vertex, one block each.
+// Step 2 (Alg. 5): edge difference of every affected vertex, one block each.
 __global__ void __launch_bounds__(kTailBlock) k_tail_score(TailArgs A, uint32_t cur) {
   TailCtr *C = A.C;
   if (C->done) return;
@@ -415,7 +415,7 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_score(TailArgs A, uint32_t 
   }
 }
 
-// Steps 3 and 4 (Alg. 5 and 6) in one launch.  Select: u is selected iff
+// Steps 3 and 4 (Alg. 6 and 7) in one launch.  Select: u is selected iff
 // its key (priority, label) is below every live neighbour's; a wave decides
 // for one vertex.  Contract, by the whole block for each vertex its waves
 // selected: live out-arcs go to the upward set and live in-arcs to the

@@ -78,6 +78,7 @@ def test_struct_layouts_match_header(binding, tmp_path):
     import subprocess
 
     structs = {"ch_graph_t": binding.Graph, "ch_params_t": binding.Params,
+               "ch_query_stats_t": binding.QueryStats,
                "ch_summary_t": binding.Summary, "ch_round_stats_t": binding.RoundStats,
                "ch_mlp_train_params_t": binding.MlpTrainParams}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "spoch.h"', 'int main(void){']

@@ -6,12 +6,12 @@ mathematics, independent of the oracle's own code:
   Floyd-Warshall closures computed here in numpy;
 * after every round the overlay preserves distances among live vertices;
 * every shortcut equals the two-arc path it replaces, and in exact mode its
-  weight is the true distance (Alg. 6 adds a shortcut only when the path
+  weight is the true distance (Alg. 7 adds a shortcut only when the path
   through u is a shortest path);
-* the selected set is independent and locally minimal (Alg. 5);
-* closed forms of the edge difference (Alg. 4) on a unit 3x3 grid, a star
+* the selected set is independent and locally minimal (Alg. 6);
+* closed forms of the edge difference (Alg. 5) on a unit 3x3 grid, a star
   and a chain (the chain family adds exactly one shortcut per contraction);
-* pruning removes an arc longer than a two-arc detour (end of Alg. 3);
+* pruning removes an arc longer than a two-arc detour (end of Alg. 4);
 * memo values are exact distances (exact mode) or hop-bounded minima;
 * equivariance under vertex renumbering when labels travel with vertices;
 * termination: at least one contraction per round, logarithmic rounds on a
