@@ -15,7 +15,7 @@ Rooflines (HBM-bound integer work, 8 TB/s peak):
   stream).  Witness searches: 8 B per adjacency row (offset pair), 8 B per
   arc read, 16 B per memo slot read or written, counted on the device.
   Queries: 8 B per vertex expanded (offset pair) + 8 B per arc relaxed,
-  counted by the query kernels in one extra (untimed) stats batch.
+  counted by the query kernels in one extra (untimed) batch.
 * `roofline_wps`: every witness-search launch of the build together (the
   first tier, the block tier and the global tier), the same way.
 `traffic` (HBM bytes per launch from rocprofv3 counters) comes from the
@@ -370,10 +370,11 @@ def main():
 
     # query kernels: device time per tier from the timed batches; their
     # algorithmic units from one more batch with the stats counters
-    print("[bench] counting the query kernels' units in a stats batch", file=sys.stderr,
+    print("[bench] counting the query kernels' units in one more batch", file=sys.stderr,
           flush=True)
     ch = binding.build(t_off, t_dst, t_w, seed=0, **knobs)
-    ch.query_stats(qs, qt)  # a fresh CH starts in the first tier, as in the timed steps
+    ch.query(t_s, t_t, count=True)  # a fresh CH, as in the timed steps
+    torch.cuda.synchronize()
     qstat = ch.last_query_stats()
     first = qstat["first_tier"]
     ch.free()
@@ -400,7 +401,7 @@ def main():
         # bytes of the whole batch, all tiers; attributed to the dominant tier
         roof = roofline_obj(args.workload, dom, la, ms, q_bytes_batch * la,
                             "8 B per vertex expanded + 8 B per arc relaxed, the whole batch "
-                            "(counted in a stats batch)")
+                            "(counted in one more batch)")
     wl, wms, wb = (sum(v[i] for v in per.values()) for i in range(3))
     roof_wps = roofline_obj(args.workload, "all witness-search launches", wl, wms, wb,
                             "8 B per row + 8 B per arc + 16 B per memo slot read or written")

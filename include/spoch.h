@@ -78,6 +78,16 @@ extern "C" {
  * still to be expanded, so fewer vertices are expanded twice; a window
  * covering every level is the same as none.  Results do not depend on it. */
 #define CH_Q_LEVEL_WINDOW(w) ((uint32_t)(w) << 12)
+/* By default a query skips every vertex and arc whose distance from its end
+ * is not below the shortest s-t path met so far (no such vertex can be on a
+ * shorter path), which keeps distances exact.  CH_Q_FULL_CLOSURE expands
+ * both upward search spaces completely instead; ch_query_batch_stats always
+ * does, so its visited counts (the sizes of the two search spaces) do not
+ * depend on timing. */
+#define CH_Q_FULL_CLOSURE (1u << 20)
+/* Count the vertices expanded and arcs relaxed by the batch (read with
+ * ch_get_query_stats); ch_query_batch_stats always counts. */
+#define CH_Q_COUNT (1u << 21)
 
 /* Input graph in CSR form, arcs grouped by tail vertex.
  *   offsets[n+1]: offsets[0] = 0, non-decreasing, offsets[n] = m
@@ -282,8 +292,9 @@ int ch_query_batch(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_
                    uint64_t *dist, uint32_t flags, void *stream);
 
 /* As ch_query_batch, and visited[i] = the number of vertices in the two
- * upward search spaces of the i-th query (the query's cost; q uint32 entries,
- * host or device like dist). */
+ * upward search spaces of the i-th query (q uint32 entries, host or device
+ * like dist); both search spaces are expanded completely (CH_Q_FULL_CLOSURE
+ * is implied). */
 int ch_query_batch_stats(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                          uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream);
 

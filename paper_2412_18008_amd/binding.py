@@ -30,6 +30,8 @@ CH_F_INPUT_ON_DEVICE = 0x1
 CH_F_STATS = 0x2
 CH_F_NO_QUERY_INDEX = 0x4
 CH_Q_ON_DEVICE = 0x1
+CH_Q_FULL_CLOSURE = 1 << 20
+CH_Q_COUNT = 1 << 21
 
 EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
             "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version", "ch_export_features",
@@ -210,13 +212,16 @@ class CH:
             _lib.ch_free(self.h)
             self.h = None
 
-    def query(self, s, t, stream=None, waves=0, window=0):
+    def query(self, s, t, stream=None, waves=0, window=0, full=False, count=False):
         """dist[i] = shortest s[i] -> t[i] distance (uint64, max = unreachable).
         numpy inputs give a numpy result; torch CUDA inputs give a torch CUDA
         int64 tensor (holding the uint64 bit patterns).  waves: waves per
         query in the kernel (1, 2, 4, 8; 0 = default); window: level window of
-        a search step (0 = default, 255 = none)."""
-        qf = CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window)
+        a search step (0 = default, 255 = none); full: expand both upward
+        search spaces completely (no pruning by the best path met); count:
+        count expansions and relaxed arcs (last_query_stats)."""
+        qf = CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window) | (CH_Q_FULL_CLOSURE if full else 0) | (
+            CH_Q_COUNT if count else 0)
         if _is_torch_cuda(s):
             import torch
 

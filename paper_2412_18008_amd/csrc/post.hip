@@ -594,6 +594,7 @@ struct QLds {
   uint32_t wsum[16];
   uint32_t wsum2[16];  // a second scan within one step
   unsigned long long wmin[16];
+  unsigned long long mu;  // shortest s-t path length met so far (pruning bound)
 };
 // Tier 1: a slot per rank for the 2048 highest ranks, 512-slot tables for
 // the rest (on a road-like 1M CH at most about 250 vertices of a search
@@ -617,6 +618,16 @@ template <bool GM>
 __device__ __forceinline__ void qst(uint32_t *p, uint32_t v) {
   if constexpr (GM) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   else *p = v;
+}
+template <bool GM>
+__device__ __forceinline__ unsigned long long qld64(const unsigned long long *p) {
+  if constexpr (GM) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <bool GM>
+__device__ __forceinline__ void qst64(unsigned long long *p, unsigned long long v) {
+  if constexpr (GM) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 template <bool GM, typename E>
 __device__ __forceinline__ E qlde(const E *p) {
@@ -768,7 +779,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
     uint32_t *__restrict__ ovf_count, const uint32_t *__restrict__ wend,
     unsigned long long *__restrict__ work, L *__restrict__ gtab,
-    unsigned long long *__restrict__ qcount) {
+    unsigned long long *__restrict__ qcount, uint32_t prune) {
   using E = typename L::Entry;
   constexpr uint32_t CAP = sizeof(((L *)nullptr)->key[0]) / 4;
   constexpr uint32_t TOP = L::kTop, NS = L::kSlots;
@@ -823,6 +834,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
       qst<GM>(&S.bits[tid][a >> 5], 1u << (a & 31));
       if (TOP && (uint32_t)a < TOP) qst<GM>(&S.usedt[tid], 1u);
       else qst<GM>(&S.used[tid], 1u);
+      if (tid == 0) qst64<GM>(&S.mu, qs[k] == qt[k] ? 0ull : SP_INF64);
     }
     qsync<NW, GM>();
     for (;;) {
@@ -910,6 +922,8 @@ __global__ void __launch_bounds__(64 * NW) k_query(
           dx = qld<GM>(&S.dist[dr][slot]);
           if (vx >= (dr ? T1 : T0)) {
             atomicOr(&S.bits[dr][slot >> 5], 1u << (slot & 31));
+          } else if (prune && dx >= qld64<GM>(&S.mu)) {
+            // no path through x is shorter than one already met
           } else {
             const uint32_t *o = dr ? dnoff : upoff;
             rs = o[vx];
@@ -921,6 +935,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
         const uint32_t incl = gscan_incl<kWave>(rl);
         const uint32_t T = __shfl(incl, kWave - 1, kWave);
         for (uint32_t i0 = 0; i0 < T; i0 += kWave * kQUnroll) {
+          const unsigned long long mub = prune ? qld64<GM>(&S.mu) : SP_INF64;
           uint2 a[kQUnroll];
           uint32_t sd[kQUnroll], sdr[kQUnroll];
 #pragma unroll
@@ -942,6 +957,7 @@ __global__ void __launch_bounds__(64 * NW) k_query(
           for (int u = 0; u < kQUnroll; u++) {
             if (a[u].x == SP_EMPTY32) continue;
             const unsigned long long nd = (unsigned long long)sd[u] + a[u].y;
+            if (nd >= mub) continue;  // pruned: not shorter than a path already met
             if (nd > 0xFFFFFFFEull) {
               atomicOr(&S.ovf, 1u);
               continue;
@@ -960,6 +976,20 @@ __global__ void __launch_bounds__(64 * NW) k_query(
               if (TOP && (uint32_t)y < TOP && old == SP_INF32) {  // first reach of a dense slot
                 if (sdr[u]) ft1++;
                 else ft0++;
+              }
+              if (prune) {  // met by the other direction: a path s -> y -> t
+                const uint32_t od = sdr[u] ^ 1u;
+                int yo = -1;  // y's slot in the other direction's table
+                if (TOP && (uint32_t)y < TOP) {
+                  yo = y;
+                } else {
+                  const int h = qfind<GM>(S, od, a[u].x);
+                  if (h >= 0) yo = (int)TOP + h;
+                }
+                if (yo >= 0) {
+                  const uint32_t dv2 = qld<GM>(&S.dist[od][yo]);
+                  if (dv2 != SP_INF32) atomicMin(&S.mu, nd + dv2);
+                }
               }
             }
           }
@@ -1008,6 +1038,10 @@ __global__ void __launch_bounds__(64 * NW) k_query(
                                         (unsigned long long)qld<GM>(&S.dist[1][TOP + b]);
           best = c2 < best ? c2 : best;
         }
+      }
+      if (prune) {  // a met path that the scan no longer sees is still a path
+        const unsigned long long m = qld64<GM>(&S.mu);
+        best = m < best ? m : best;
       }
       best = gmin64<kWave>(best);
       if constexpr (NW > 1) {
@@ -1133,11 +1167,17 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   // captured sequence of this stream); words 16-19: two 64-bit counters of
   // expanded vertices and relaxed arcs (stats batches)
   HIP_TRY(fill_u32(ctr, 0u, kQCtrWords, st));
-  unsigned long long *qcount = dv ? reinterpret_cast<unsigned long long *>(ctr + 16) : nullptr;
+  // a stats batch (visited counts) expands both upward search spaces
+  // completely, so its counts do not depend on timing; other batches skip
+  // what cannot be shorter than a path already met
+  const uint32_t prune = (dv || (flags & CH_Q_FULL_CLOSURE)) ? 0u : 1u;
+  unsigned long long *qcount = (dv || (flags & CH_Q_COUNT))
+                                   ? reinterpret_cast<unsigned long long *>(ctr + 16)
+                                   : nullptr;
   ch_query_stats_t qsn{};
   qsn.queries = q;
   qsn.first_tier = (uint32_t)ch->q_first_tier;
-  qsn.counted = dv ? 1u : 0u;
+  qsn.counted = qcount ? 1u : 0u;
   // tier timing: events 2t and 2t+1 around tier t (ch_query_batch only)
   hipEvent_t *ev = sc.timed ? ch->q_ev : nullptr;
   if (ev && !ev[0])
@@ -1173,7 +1213,7 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
 #define SP_QUERY_LAUNCH(NW)                                                                    \
   k_query<NW, QTier1, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
       q, ch->n, nullptr, nullptr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,   \
-      ovf1, ctr, wend, reinterpret_cast<unsigned long long *>(ctr + 8), nullptr, qcount)
+      ovf1, ctr, wend, reinterpret_cast<unsigned long long *>(ctr + 8), nullptr, qcount, prune)
     if (nw == 1) SP_QUERY_LAUNCH(1);
     else if (nw == 2) SP_QUERY_LAUNCH(2);
     else if (nw == 8) SP_QUERY_LAUNCH(8);
@@ -1187,7 +1227,7 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
     k_query<16, QTier2, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
         dnarc, dd, dv, ovf2, ctr + 2, wend, reinterpret_cast<unsigned long long *>(ctr + 10),
-        nullptr, qcount);
+        nullptr, qcount, prune);
     HIP_TRY(hipGetLastError());
     HIP_TRY(mark(3));
   }
@@ -1209,7 +1249,8 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
     HIP_TRY(mark(4));
     k_query<8, QTier3, true><<<(unsigned)nb, 512, 0, st>>>(
         q, ch->n, list3, ctr + 2, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,
-        ovf1, ctr + 4, wend, reinterpret_cast<unsigned long long *>(ctr + 12), tabs, qcount);
+        ovf1, ctr + 4, wend, reinterpret_cast<unsigned long long *>(ctr + 12), tabs, qcount,
+        prune);
     HIP_TRY(hipGetLastError());
     HIP_TRY(mark(5));
     uint32_t h2[4] = {0, 0, 0, 0};  // ctr[1..4]

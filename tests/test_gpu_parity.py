@@ -82,8 +82,11 @@ def test_grid64_bit_exact_and_queries(gpu):
         assert np.array_equal(vis.astype(np.int64), cs), nw
     # the level window orders the expansions; distances and the reached
     # sets do not depend on it (255 = none)
+    # complete search spaces (no pruning by the best path met) give the same
+    assert np.array_equal(ch.query(s, t, full=True), ref)
     for win in (1, 2, 7, 64, 255):
         assert np.array_equal(ch.query(s, t, window=win), ref), win
+        assert np.array_equal(ch.query(s, t, window=win, full=True), ref), win
         d2, vis = ch.query_stats(s[:300], t[:300], waves=1, window=win)
         assert np.array_equal(d2, d[:300]), win
         assert np.array_equal(vis.astype(np.int64), cs), win
@@ -240,6 +243,8 @@ def test_query_tiers(gpu):
             d, vis = ch.query_stats(s, t, waves=nw)
             assert np.array_equal(d, od), nw
             assert np.array_equal(vis.astype(np.int64), cs), nw
+            assert np.array_equal(ch.query(s, t, waves=nw), od), nw
+            assert np.array_equal(ch.query(s, t, waves=nw, full=True), od), nw
         for win in (1, 255):
             d, vis = ch.query_stats(s, t, window=win)
             assert np.array_equal(d, od), win
