@@ -49,6 +49,12 @@ WORKLOADS = {
               "3 nearest neighbours symmetrised, weight round(1e4*length)+1, 10% of "
               "edges one-way, seed 0; 100,000 uniform s-t queries, seed 3"),
         queries=100_000),
+    "batch512": dict(
+        desc=("batched construction: 512 road-like graphs (the road-like 1M recipe), vertex "
+              "counts log-uniform in [1e4, 5e5] from PCG64(512) (68,749,675 vertices in all), "
+              "graph i from seed i, built by one ch_build_batch; 1,000 uniform s-t queries "
+              "per graph"),
+        queries=1_000),
     "grid64": dict(
         desc=("64x64 grid, 4-neighbour arcs both ways, uint32 weights uniform in "
               "[1,1000], seed 0; 1,000 uniform s-t queries, seed 1"),
@@ -287,6 +293,86 @@ def roofline_obj(workload, name, launches, ms, nbytes, bound_note):
             "algorithmic_bytes_per_launch": nbytes / max(launches, 1), "units": bound_note}
 
 
+def bench_batch512(args, binding, dev):
+    """ch_build_batch of the 512-graph workload plus a 1000-query batch per
+    graph as one step; aggregate shortcuts/s over the step and over the
+    batched build, and per-graph shortcuts/s of each graph built alone."""
+    import numpy as np
+    import torch
+
+    from paper_2412_18008_amd import synth
+
+    t_gen = time.perf_counter()
+    graphs = synth.config_batch512()
+    sizes = np.array([len(g[0]) - 1 for g in graphs])
+    print(f"[bench] batch512: {len(graphs)} graphs, {int(sizes.sum())} vertices "
+          f"(generated in {time.perf_counter() - t_gen:.0f} s)", file=sys.stderr, flush=True)
+    dgraphs = [(torch.from_numpy(o.astype(np.int64)).to(dev),
+                torch.from_numpy(d.astype(np.int32)).to(dev),
+                torch.from_numpy(w.astype(np.int32)).to(dev)) for o, d, w in graphs]
+    queries = []
+    for i, n in enumerate(sizes):
+        s, t = synth.queries(int(n), 1000, seed=i)
+        queries.append((torch.from_numpy(s.astype(np.int32)).to(dev),
+                        torch.from_numpy(t.astype(np.int32)).to(dev)))
+    torch.cuda.synchronize()
+
+    def step():
+        tb = time.perf_counter()
+        chs = binding.build_batch(dgraphs)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        for c, (s, t) in zip(chs, queries):
+            c.query(s, t)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        sc = [c.summary["shortcuts"] for c in chs]
+        for c in chs:
+            c.free()
+        return tq - tb, te - tq, sc
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    recs = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        recs.append(step())
+        print(f"[bench] step {i + 1}/{args.steps}: batch build {recs[-1][0]:.3f} s, "
+              f"queries {recs[-1][1] * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    sc = np.array(recs[-1][2], np.float64)
+    build_s = float(np.median([r[0] for r in recs]))
+    print("[bench] each graph alone (per-graph shortcuts/s)", file=sys.stderr, flush=True)
+    alone = []
+    for (o, d, w), n, k in zip(dgraphs, sizes, sc):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        c = binding.build(o, d, w)
+        torch.cuda.synchronize()
+        alone.append(k / (time.perf_counter() - ta))
+        c.free()
+    alone = np.array(alone)
+    line = {
+        "metric": "CH build time (s) + shortcuts/s + HBM roofline %, plain priority",
+        "value": float(sc.sum()) / (ms_per_step / 1e3), "unit": "shortcuts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["batch512"]["desc"], "graphs": len(graphs),
+                   "n": int(sizes.sum()), "m": int(sum(len(g[1]) for g in graphs)),
+                   "step": "ch_build_batch + 512 ch_query_batch calls of 1000 queries"},
+        "batch_build_s": build_s,
+        "shortcuts": int(sc.sum()),
+        "aggregate_shortcuts_per_build_s": float(sc.sum()) / build_s,
+        "per_graph_alone_shortcuts_per_s": {
+            "min": float(alone.min()), "median": float(np.median(alone)),
+            "max": float(alone.max()), "sum_of_alone_build_s": float((sc / alone).sum())},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,6 +405,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     binding.lib()
+    if args.workload == "batch512":
+        bench_batch512(args, binding, dev)
+        return
 
     t_gen = time.perf_counter()
     g, (qs, qt) = make_graph(args.workload)

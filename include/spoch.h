@@ -71,9 +71,8 @@ extern "C" {
 /* Waves that share one query in the first query tier (1, 2, 4
  * or 8; 0 = the default, 4).  Results do not depend on it. */
 #define CH_Q_WAVES(nw) ((uint32_t)(nw) << 8)
-/* Level window of the query's search steps (1 .. 254 levels; 255 = none,
- * every flagged vertex is expanded at once; 0 = the default: none on a
- * hierarchy of at most 256 levels, else 48).  A step expands the reached
+/* Level window of the query's search steps (1 .. 254 levels; 0 or 255 =
+ * none, every flagged vertex is expanded at once, the default).  A step expands the reached
  * vertices whose CH level is within the window above the lowest level
  * still to be expanded, so fewer vertices are expanded twice; a window
  * covering every level is the same as none.  Results do not depend on it. */

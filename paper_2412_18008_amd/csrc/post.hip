@@ -23,14 +23,13 @@ namespace sp {
     if (r_ != CH_OK) return r_; \
   } while (0)
 
-// Default level window of the query: none on a hierarchy of at most
-// kQShallow levels (the per-step bookkeeping of a window costs more than it
-// saves there: road1m, 182 levels, 31.1 ms per 100k queries without one,
-// 34.6-35.9 ms with 24 to 128 levels), else kQWindow levels (road24m, 412
-// levels: 4.04 s per 1M queries with 48, 4.26 s with 24, 4.66 s with none).
-// A deeper hierarchy also starts its first query batch in the second tier:
-// on road24m 99.95% of the queries outgrow the first tier's tables.
-constexpr uint32_t kQWindow = 48;
+// Default level window of the query: none.  With the searches pruned by the
+// shortest path met so far, expanding every flagged vertex at once is
+// fastest (road1m, 182 levels: 25.1 ms per 100k queries, 28.6-41.6 ms with
+// windows of 128 down to 8 levels; road24m, 412 levels: 3.14 s per 1M,
+// 3.34 s with 48 levels, 4.91 s with 8).  A hierarchy deeper than kQShallow
+// levels starts its first query batch in the second tier: on road24m 99.95%
+// of the queries outgrow the first tier's tables.
 constexpr uint32_t kQShallow = 256;
 
 static int bits_for(uint32_t n) {
@@ -1191,7 +1190,7 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   uint32_t *ovf1 = sc.ovf1, *ovf2 = sc.ovf2;
   const int first = ch->q_first_tier;
   const uint32_t wf = (flags >> 12) & 0xFFu;  // 0: default window, 255: none
-  uint32_t win = wf == 0 ? (ch->rounds <= kQShallow ? 0u : kQWindow) : (wf == 255 ? 0u : wf);
+  uint32_t win = (wf == 0 || wf == 255) ? 0u : wf;
   if (win >= ch->rounds) win = 0;  // a window over every level: the plain path
   if (win && win != ch->q_wend_win) {
     // q_wend is allocated with the query index

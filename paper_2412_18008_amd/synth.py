@@ -211,3 +211,16 @@ def config_road1m(seed=0):
 
 def config_road24m(seed=0):
     return clustered_road(24_000_000, seed=seed)
+
+
+def batch512_sizes(seed=512, k=512, lo=1e4, hi=5e5):
+    """Vertex counts of the batched-construction workload: k sizes
+    log-uniform in [lo, hi] (floor), from PCG64(seed)."""
+    rng = _rng(seed)
+    return np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi), size=k))).astype(np.int64)
+
+
+def config_batch512(k=512):
+    """k road-like graphs (the road-like 1M recipe) with batch512_sizes()
+    vertices, graph i from seed i."""
+    return [road_like(int(n), seed=i) for i, n in enumerate(batch512_sizes(k=512)[:k])]

@@ -197,3 +197,46 @@ def test_road24m_bit_exact(gpu):
     progress(f"1M queries: mean visited {vis.mean():.0f}, max {vis.max()}")
     assert np.all(d[s == t] == 0)
     assert np.all(vis >= 2)
+
+
+@pytest.mark.timeout(900)
+def test_batch512_full_size(gpu):
+    """The batched-construction workload at full size: 512 road-like graphs
+    with vertex counts log-uniform in [1e4, 5e5] (about 69M vertices), built
+    in one ch_build_batch.  The eight smallest members are compared with the
+    oracle's builds bit for bit (plus their round counts), every member with
+    the properties that hold at any size on a sample of its arcs, and 1000
+    queries per member of a sample of eight with Dijkstra on the input."""
+    from paper_2412_18008_amd import synth as sy
+
+    sizes = sy.batch512_sizes()
+    progress(f"batch512: generating {len(sizes)} graphs, {int(sizes.sum())} vertices")
+    graphs = sy.config_batch512()
+    progress("batch512 generated")
+    chs = gpu.build_batch(graphs)
+    progress("batch512 built")
+    order = np.argsort(sizes, kind="stable")
+    for i in order[:8]:
+        off, dst, w = graphs[i]
+        o = oracle.OracleCH(off, dst, w).run()
+        assert_same_ch(oracle_export(o), gpu_export(chs[i]), f"batch512[{i}] vs oracle")
+        assert chs[i].summary["rounds"] == o.rounds
+        assert chs[i].summary["shortcuts"] == sum(r["n_shortcuts"] for r in o.round_stats())
+    progress("batch512: eight smallest members equal the oracle")
+    for i, (g, c) in enumerate(zip(graphs, chs)):
+        check_ch_properties(c.export(), *g, c.summary["rounds"], sample=2000, seed=i)
+    progress("batch512: properties of every member checked")
+    rng = np.random.Generator(np.random.PCG64(5))
+    for i in rng.choice(len(graphs), size=8, replace=False):
+        off, dst, w = graphs[i]
+        n = len(off) - 1
+        s, t = sy.queries(n, 1000, seed=int(i))
+        d = chs[i].query(s, t)
+        for src in np.unique(s)[:3]:
+            ref = oracle.dijkstra(off, dst, w, int(src))
+            sel = s == src
+            assert np.array_equal(d[sel], ref[t[sel]])
+        od = oracle.OracleCH(off, dst, w).run() if n < 30000 else None
+        if od is not None:
+            assert np.array_equal(d, od.query_batch(s, t)[0])
+    progress("batch512: sampled queries checked")

@@ -403,6 +403,11 @@ def test_batch_equals_single_builds(gpu):
     print("[parity] batch of", len(graphs), flush=True)
     outs = gpu.build_batch(graphs, labels=labels)
     for i, (g, lab, ch) in enumerate(zip(graphs, labels, outs)):
+        # each member equals the oracle's build of that graph alone
+        o = oracle.OracleCH(*g, labels=lab).run()
+        assert_same_ch(oracle_export(o), gpu_export(ch), f"batch[{i}] vs oracle")
+        assert ch.summary["rounds"] == o.rounds
+        assert ch.summary["shortcuts"] == sum(r["n_shortcuts"] for r in o.round_stats())
         single = gpu.build(*g, labels=lab)
         a, b = gpu_export(single), gpu_export(ch)
         assert_same_ch(a, b, f"batch[{i}]")
@@ -415,7 +420,8 @@ def test_batch_equals_single_builds(gpu):
     # default labels: each graph labelled by its local ids
     outs = gpu.build_batch(graphs[:3], seed=77)
     for i, g in enumerate(graphs[:3]):
-        assert_same_ch(gpu_export(gpu.build(*g, seed=77)), gpu_export(outs[i]), f"default[{i}]")
+        assert_same_ch(oracle_export(oracle.OracleCH(*g, seed=77).run()), gpu_export(outs[i]),
+                       f"default[{i}] vs oracle")
     # labels need only be distinct within a graph
     same = [synth.labels(len(graphs[1][0]) - 1, 5)] * 2
     outs = gpu.build_batch([graphs[1], graphs[1]], labels=same)
@@ -490,5 +496,5 @@ def test_dense_tail_learned_and_batch(gpu):
     graphs = [synth.road_like(3000, seed=s) for s in (1, 2, 3)]
     chs = gpu.build_batch(graphs, dense_tail=4096)
     for (goff, gdst, gw), c in zip(graphs, chs):
-        single = gpu.build(goff, gdst, gw, dense_tail=gpu.CH_DENSE_TAIL_OFF)
-        assert_same_ch(gpu_export(single), gpu_export(c), "batch tail")
+        assert_same_ch(oracle_export(oracle.OracleCH(goff, gdst, gw).run()), gpu_export(c),
+                       "batch tail vs oracle")
