@@ -55,6 +55,11 @@ WORKLOADS = {
               "graph i from seed i, built by one ch_build_batch; 1,000 uniform s-t queries "
               "per graph"),
         queries=1_000),
+    **{f"knn{k}": dict(
+        desc=(f"k-NN k={k}: 1,000,000 uniform points in the unit square, arcs from every "
+              f"point to its {k} nearest neighbours (m = {k},000,000), weights uniform in "
+              f"[1,32], seed {k}; 100,000 uniform s-t queries, seed 3"),
+        queries=100_000) for k in (2, 5, 10)},
     "grid64": dict(
         desc=("64x64 grid, 4-neighbour arcs both ways, uint32 weights uniform in "
               "[1,1000], seed 0; 1,000 uniform s-t queries, seed 1"),
@@ -63,6 +68,8 @@ WORKLOADS = {
 
 # bounded CPU sample of each workload for the oracle (same generator)
 CPU_SAMPLES = {
+    **{f"knn{k}": (f"k-NN k={k} at 50,000 points (seed {k})",
+                   lambda synth, k=k: synth.knn_graph(50_000, k, seed=k)) for k in (2, 5, 10)},
     "road24m": ("clustered road-like 1M (the 24M recipe at 1,000,000 points, seed 0)",
                 lambda synth: synth.clustered_road(1_000_000, seed=0)),
     "road1m": ("the road-like 1M graph itself", lambda synth: synth.config_road1m(seed=0)),
@@ -79,6 +86,10 @@ def make_graph(name):
     elif name == "grid64":
         g = synth.config_grid64(seed=0)
         q = synth.queries(len(g[0]) - 1, WORKLOADS[name]["queries"], seed=1)
+    elif name.startswith("knn"):
+        k = int(name[3:])
+        g = synth.knn_graph(1_000_000, k, seed=k)
+        q = synth.queries(len(g[0]) - 1, WORKLOADS[name]["queries"], seed=3)
     else:
         g = synth.config_road24m(seed=0)
         q = synth.queries(len(g[0]) - 1, WORKLOADS[name]["queries"], seed=3)
@@ -100,7 +111,7 @@ def cpu_model():
     return platform.processor() or platform.machine()
 
 
-def cpu_baseline(workload):
+def cpu_baseline(workload, settle=0):
     """The oracle (plain sequential C, one thread) timed on this host on a
     bounded sample of the workload, plus the committed record of its full
     build of the 24M graph (run once, elsewhere) for context."""
@@ -111,7 +122,9 @@ def cpu_baseline(workload):
     off, dst, w = gen(synth)
     oracle.build()
     t0 = time.perf_counter()
-    o = oracle.OracleCH(off, dst, w, seed=0).run()
+    o = oracle.OracleCH(off, dst, w, seed=0,
+                        **(dict(wps_mode=oracle.WPS_SETTLED, settle_limit=settle)
+                           if settle else {})).run()
     el = time.perf_counter() - t0
     sc = sum(r["n_shortcuts"] for r in o.round_stats())
     rep = {"value": sc / el, "unit": "shortcuts/s", "cores": 1, "kind": "oracle",
@@ -120,7 +133,7 @@ def cpu_baseline(workload):
                       f"{cpu_model()}"),
            "build_s": el, "host_cpu": cpu_model(), "host_nproc": os.cpu_count()}
     dig = os.path.join(ROOT, "tests", "golden", "road24m_digest.json")
-    if workload == "road24m" and os.path.exists(dig):
+    if workload == "road24m" and not settle and os.path.exists(dig):
         with open(dig) as f:
             d = json.load(f)
         rep["full_workload_recorded"] = {
@@ -380,6 +393,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="road24m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--settle", type=int, default=0, metavar="THETA",
+                    help="witness searches in the paper's settled(theta) mode instead of "
+                         "exact")
     ap.add_argument("--untuned", action="store_true",
                     help="ignore the autotuner cache (default knobs)")
     ap.add_argument("--learned", default=os.path.join(ROOT, "paper_2412_18008_amd",
@@ -425,6 +441,8 @@ def main():
     from paper_2412_18008_amd import autotune
 
     knobs = {} if args.untuned else autotune.params_for(n, m)
+    if args.settle:
+        knobs = dict(knobs, settle=args.settle)
     print(f"[bench] knobs {knobs or 'default'}", file=sys.stderr, flush=True)
 
     def step():
@@ -514,7 +532,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload]["desc"], "n": n, "m": m,
                    "queries": int(len(qs)), "priority": "plain (edge difference)",
-                   "wps": "exact, radius D_s", "step": "ch_build + one ch_query_batch",
+                   "wps": (f"settled(theta={args.settle}), radius D_s" if args.settle
+                           else "exact, radius D_s"),
+                   "step": "ch_build + one ch_query_batch",
                    "knobs": knobs or "default"},
         "build_time_s": build_s,
         "query_batch_ms": query_s * 1e3,
@@ -537,7 +557,7 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample ...", file=sys.stderr,
               flush=True)
-        line["cpu_baseline"] = cpu_baseline(args.workload)
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.settle)
     print(json.dumps(line), flush=True)
 
 

@@ -61,6 +61,12 @@ extern "C" {
  *                 shortcut). */
 #define CH_WPS_EXACT 0
 #define CH_WPS_HOP 1
+/* The paper's literal bound (Sec. "Step 1: Local Search with Memoization",
+ * Alg. 4): a search settles vertices in (distance, label) order, s first,
+ * and stops after settle_limit settled vertices or once every target is
+ * settled; only settled targets get a memo entry (a target left unsettled
+ * gets a shortcut).  Radius D_s as above. */
+#define CH_WPS_SETTLED 2
 
 /* ---- flags ---- */
 #define CH_F_INPUT_ON_DEVICE 0x1u /* ch_graph_t arrays are device pointers */
@@ -106,7 +112,7 @@ typedef struct {
 } ch_graph_t;
 
 typedef struct {
-  uint32_t wps_mode;   /* CH_WPS_EXACT or CH_WPS_HOP                            */
+  uint32_t wps_mode;   /* CH_WPS_EXACT, CH_WPS_HOP or CH_WPS_SETTLED             */
   uint32_t max_rounds; /* 0: no limit; else CH_E_LIMIT after that many rounds    */
   uint64_t seed;       /* seed of the default labels                            */
   uint32_t flags;      /* CH_F_*                                                */
@@ -148,6 +154,7 @@ typedef struct {
    * fmix32 of the id and seed) or CH_TIE_RAW_ID (label = vertex id; the
    * graph must then carry no labels, else CH_E_INVALID). */
   uint32_t tiebreak;
+  uint32_t settle_limit; /* CH_WPS_SETTLED: vertices settled per search (theta), >= 1 */
 } ch_params_t;
 #define CH_DENSE_TAIL_OFF 1u
 #define CH_TIE_HASHED_ID 0u

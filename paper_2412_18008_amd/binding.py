@@ -26,6 +26,7 @@ CH_E_UNSUPPORTED = -6
 
 CH_WPS_EXACT = 0
 CH_WPS_HOP = 1
+CH_WPS_SETTLED = 2
 CH_F_INPUT_ON_DEVICE = 0x1
 CH_F_STATS = 0x2
 CH_F_NO_QUERY_INDEX = 0x4
@@ -57,7 +58,7 @@ class Params(C.Structure):
                 ("dense_deg10", C.c_uint32), ("priority", C.c_uint32), ("mlp", C.c_void_p),
                 ("hop_limit", C.c_uint32), ("dense_tail", C.c_uint32),
                 ("k_ed", C.c_int32), ("k_cn", C.c_int32), ("k_depth", C.c_int32),
-                ("tiebreak", C.c_uint32)]
+                ("tiebreak", C.c_uint32), ("settle_limit", C.c_uint32)]
 
 
 CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
@@ -307,13 +308,14 @@ class CH:
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
           record=False, hop=0, dense_tail=0, tail_stepwise=False, keep_order=False,
-          score_weights=None, raw_id=False):
+          score_weights=None, raw_id=False, settle=0):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
     selects the hop-bounded witness search with walks of at most `hop` arcs;
     tail_stepwise runs the table rounds one launch per step; keep_order
     builds on the input's numbering (no locality renumbering); score_weights
     = (k_ed, k_cn, k_depth) sets the integer score weights; raw_id labels
-    every vertex by its id."""
+    every vertex by its id; settle > 0 selects the settled(theta) witness
+    search with theta = settle."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
     pd, kd = _ptr(dst, np.uint32)
@@ -334,18 +336,19 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     wts = None if mlp is None else np.ascontiguousarray(mlp, np.float32)
     if wts is not None and wts.size != CH_MLP_PARAMS:
         raise ValueError("mlp must hold 4801 weights")
-    p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
+    mode = CH_WPS_SETTLED if settle else (CH_WPS_HOP if hop else CH_WPS_EXACT)
+    p = Params(mode, max_rounds, seed, flags, group, stream,
                ls_sparse, ls_dense, dense_deg10,
                CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
                None if wts is None else wts.ctypes.data, hop, dense_tail, k_ed, k_cn, k_depth,
-               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID)
+               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID, settle)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
 
 
 def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=True,
-                stream=None, hop=0, dense_tail=0, score_weights=None, raw_id=False):
+                stream=None, hop=0, dense_tail=0, score_weights=None, raw_id=False, settle=0):
     """ch_build_batch on a list of (off, dst, w) CSR graphs (numpy arrays or
     torch CUDA tensors); returns one CH per graph."""
     k = len(graphs)
@@ -364,9 +367,10 @@ def build_batch(graphs, labels=None, seed=0, group=0, max_rounds=0, query_index=
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (0 if query_index else CH_F_NO_QUERY_INDEX) | (
         CH_F_SCORE_WEIGHTS if score_weights is not None else 0)
     k_ed, k_cn, k_depth = score_weights if score_weights is not None else (1, 0, 0)
-    p = Params(CH_WPS_HOP if hop else CH_WPS_EXACT, max_rounds, seed, flags, group, stream,
+    mode = CH_WPS_SETTLED if settle else (CH_WPS_HOP if hop else CH_WPS_EXACT)
+    p = Params(mode, max_rounds, seed, flags, group, stream,
                0, 0, 0, CH_PRIO_PLAIN, None, hop, dense_tail, k_ed, k_cn, k_depth,
-               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID)
+               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID, settle)
     outs = (C.c_void_p * max(k, 1))()
     _check(lib().ch_build_batch(arr, k, C.byref(p), outs), "ch_build_batch")
     return [CH(C.c_void_p(outs[i])) for i in range(k)]

@@ -147,6 +147,10 @@ struct Builder {
   }
 
   DevCtr *dc() { return dctr.as<DevCtr>(); }
+  // the search bound of the mode: hop_limit (hop) or settle_limit (settled)
+  uint32_t mode_limit() const {
+    return prm.wps_mode == CH_WPS_SETTLED ? prm.settle_limit : prm.hop_limit;
+  }
 
   // the learned priority and recorded features need every feature; nonzero
   // k_cn or k_depth need the contracted-neighbour count and depth
@@ -711,7 +715,7 @@ struct Builder {
   template <int G, int CAP>
   void launch_ls(const Overlay &v, const uint32_t *list, uint32_t nl, const uint32_t *nl_dev,
                  int tier, int max_per_cu) {
-    const bool hop = prm.wps_mode == CH_WPS_HOP;
+    const bool hop = prm.wps_mode != CH_WPS_EXACT;  // a second per-slot array
     const size_t lds = ls_lds_bytes(G, CAP, hop);
     const int blocks_per_cu = std::max(1, std::min(max_per_cu, (int)((160u << 10) / lds)));
     const uint32_t groups = (uint32_t)cus * blocks_per_cu * (kLsBlock / G);
@@ -722,11 +726,12 @@ struct Builder {
           v, list, nl, aflag.as<uint8_t>(), mref(),
           tier == 1 ? &d->ls : &d->ls2, nl_dev, tier == 1 ? &d->work1 : &d->work2,
           tier == 1 ? ovf1.as<uint32_t>() : ovf2.as<uint32_t>(),
-          tier == 1 ? &d->novf1 : &d->novf2, chunk, fstate().ws, &d->err,
-          prm.hop_limit);
+          tier == 1 ? &d->novf1 : &d->novf2, chunk, fstate().ws, &d->err, mode_limit(),
+          ch->label.as<uint32_t>());
     };
-    if (hop) go(k_local_search<G, CAP, true>);
-    else go(k_local_search<G, CAP, false>);
+    if (prm.wps_mode == CH_WPS_HOP) go(k_local_search<G, CAP, kWpsHop>);
+    else if (prm.wps_mode == CH_WPS_SETTLED) go(k_local_search<G, CAP, kWpsSettled>);
+    else go(k_local_search<G, CAP, kWpsExact>);
   }
   // second tier: sources that outgrew the first tier's tables (list ovf1,
   // count on the device), a block of kLsBlkWaves waves and one
@@ -737,10 +742,13 @@ struct Builder {
     auto go = [&](auto kern) {
       kern<<<(unsigned)cus, kWave * kLsBlkWaves, 0, st>>>(
           v, ovf1.as<uint32_t>(), 0, aflag.as<uint8_t>(), mref(), &d->ls2, &d->novf1, &d->work2,
-          ovf2.as<uint32_t>(), &d->novf2, fstate().ws, &d->err, prm.hop_limit);
+          ovf2.as<uint32_t>(), &d->novf2, fstate().ws, &d->err, mode_limit(),
+          ch->label.as<uint32_t>());
     };
-    if (prm.wps_mode == CH_WPS_HOP) go(k_local_search_blk<kLsBlkCap, true, kLsBlkWaves>);
-    else go(k_local_search_blk<kLsBlkCap, false, kLsBlkWaves>);
+    if (prm.wps_mode == CH_WPS_HOP) go(k_local_search_blk<kLsBlkCap, kWpsHop, kLsBlkWaves>);
+    else if (prm.wps_mode == CH_WPS_SETTLED)
+      go(k_local_search_blk<kLsBlkCap, kWpsSettled, kLsBlkWaves>);
+    else go(k_local_search_blk<kLsBlkCap, kWpsExact, kLsBlkWaves>);
   }
   template <int G>
   void launch_score(const Overlay &v, uint32_t na) {
@@ -1050,7 +1058,7 @@ struct Builder {
       rs.n_ls_global = novf;
       if (novf) {
         const uint32_t cap = (uint32_t)std::min<uint64_t>(next_pow2(2ull * O.n + 2), 1ull << 31);
-        const bool hop = prm.wps_mode == CH_WPS_HOP;
+        const bool hop = prm.wps_mode != CH_WPS_EXACT;  // a seventh array
         const size_t per = ((size_t)cap * (hop ? 7 : 6) + 4) * 4;
         size_t ntab = std::max<size_t>(1, std::min<size_t>({(size_t)novf, (size_t)cus * 2,
                                                             (size_t)(4ull << 30) / per}));
@@ -1068,12 +1076,15 @@ struct Builder {
                                                                prw.as<uint32_t>(), &dc()->err);
           HIP_TRY(hipGetLastError());
         }
-        auto global = hop ? k_local_search_global<true, kLsBlkWaves>
-                          : k_local_search_global<false, kLsBlkWaves>;
+        auto global = prm.wps_mode == CH_WPS_HOP
+                          ? k_local_search_global<kWpsHop, kLsBlkWaves>
+                          : prm.wps_mode == CH_WPS_SETTLED
+                                ? k_local_search_global<kWpsSettled, kLsBlkWaves>
+                                : k_local_search_global<kWpsExact, kLsBlkWaves>;
         if (stats) HIP_TRY(hipEventRecord(ev[7], st));
         global<<<(unsigned)ntab, kWave * kLsBlkWaves, 0, st>>>(
             v, ovf2.as<uint32_t>(), novf, aflag.as<uint8_t>(), mref(), &dc()->ls3, gtabs.as<uint32_t>(), cap, fstate().ws,
-            &dc()->err, prm.hop_limit);
+            &dc()->err, mode_limit(), ch->label.as<uint32_t>());
         HIP_TRY(hipGetLastError());
         if (stats) HIP_TRY(hipEventRecord(ev[8], st));
         TRY(after_search());
@@ -1259,10 +1270,13 @@ struct Builder {
 static int check_params(const ch_params_t *p, ch_params_t &prm) {
   prm = ch_params_t{};
   if (p) prm = *p;
-  if (prm.wps_mode != CH_WPS_EXACT && prm.wps_mode != CH_WPS_HOP)
+  if (prm.wps_mode != CH_WPS_EXACT && prm.wps_mode != CH_WPS_HOP &&
+      prm.wps_mode != CH_WPS_SETTLED)
     return set_error(CH_E_UNSUPPORTED, "unknown wps_mode");
   if (prm.wps_mode == CH_WPS_HOP && prm.hop_limit < 1)
     return set_error(CH_E_INVALID, "hop mode needs hop_limit >= 1");
+  if (prm.wps_mode == CH_WPS_SETTLED && prm.settle_limit < 1)
+    return set_error(CH_E_INVALID, "settled mode needs settle_limit >= 1");
   if (prm.dense_tail > kTabMaxN)
     return set_error(CH_E_INVALID, "dense_tail must be at most 4096");
   if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&

@@ -235,15 +235,18 @@ constexpr size_t ls_lds_bytes(int g, int cap, bool hop) {
 
 // LDS fast path: groups of G lanes, CAP-slot table per group.  Persistent:
 // every group takes `chunk` sources at a time from a global counter.
-template <int G, int CAP, bool HOP>
+template <int G, int CAP, int M>
 __global__ void __launch_bounds__(kLsBlock) k_local_search(
     Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
     MemoRef memo, LsCounters *__restrict__ cnt,
     const uint32_t *__restrict__ nw_dev, uint32_t *__restrict__ work,
     uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count, uint32_t chunk,
-    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops,
+    const uint32_t *__restrict__ label) {
   constexpr int NG = kLsBlock / G;
-  constexpr int CAP2 = HOP ? CAP : 1;  // second distance array only in hop mode
+  // second array (hop-mode distances, settled-mode labels) only in those modes
+  constexpr bool HOP = M != kWpsExact;
+  constexpr int CAP2 = HOP ? CAP : 1;
   constexpr int LIM = ls_limit(CAP);
   static_assert(ls_lds_bytes(G, CAP, HOP) ==
                     sizeof(uint32_t) * (3 * NG * CAP + NG * (CAP2 - CAP) + 2 * NG * (CAP / 32) +
@@ -295,7 +298,7 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
     const uint32_t end = min(base + chunk, nw);
     for (uint32_t i = base; i < end; i++) {
       const uint32_t s = vw[i];
-      if (!search_source<G, 1, HOP>(ov, aflag, memo, T, s, ss, ws, err, hops, C)) {
+      if (!search_source<G, 1, M>(ov, aflag, memo, T, s, ss, ws, err, hops, C, label)) {
         if (gl == 0) {
           const uint32_t k = atomicAdd(ovf_count, 1u);
           ovf_list[k] = s;
@@ -316,12 +319,14 @@ constexpr size_t ls_blk_lds_bytes(int cap, bool hop, int nw) {
   return 4 * (size_t)cap * (hop ? 3 : 2) + (hop ? 0 : 4) + 8 * (size_t)(cap / 32) + 16 +
          6 * (size_t)ls_limit(cap) + 8 * (size_t)nw + 4;
 }
-template <int CAP, bool HOP, int NW>
+template <int CAP, int M, int NW>
 __global__ void __launch_bounds__(kWave * NW) k_local_search_blk(
     Overlay ov, const uint32_t *__restrict__ vw, uint32_t nw, const uint8_t *__restrict__ aflag,
     MemoRef memo, LsCounters *__restrict__ cnt, const uint32_t *__restrict__ nw_dev,
     uint32_t *__restrict__ work, uint32_t *__restrict__ ovf_list, uint32_t *__restrict__ ovf_count,
-    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops,
+    const uint32_t *__restrict__ label) {
+  constexpr bool HOP = M != kWpsExact;  // a second array (hop distances or settled labels)
   constexpr int CAP2 = HOP ? CAP : 1;
   constexpr int LIM = ls_limit(CAP);
   static_assert(LIM <= 65536, "16-bit slot lists");
@@ -334,7 +339,7 @@ __global__ void __launch_bounds__(kWave * NW) k_local_search_blk(
   __shared__ uint16_t s_order[LIM];
   __shared__ uint16_t s_fr[2][LIM];
   __shared__ uint32_t s_ctr[4];
-  __shared__ uint32_t s_red[2 * NW];
+  __shared__ __align__(8) uint32_t s_red[2 * NW];  // also read as NW 64-bit words
   __shared__ uint32_t s_next;
   const uint32_t tid = threadIdx.x;
   for (uint32_t i = tid; i < CAP; i += kWave * NW) {
@@ -371,7 +376,7 @@ __global__ void __launch_bounds__(kWave * NW) k_local_search_blk(
     __syncthreads();
     if (i >= nw) break;
     const uint32_t s = vw[i];
-    if (!search_source<kWave, NW, HOP>(ov, aflag, memo, T, s, ss, ws, err, hops, C)) {
+    if (!search_source<kWave, NW, M>(ov, aflag, memo, T, s, ss, ws, err, hops, C, label)) {
       if (tid == 0) {
         const uint32_t k = atomicAdd(ovf_count, 1u);
         ovf_list[k] = s;
@@ -398,14 +403,16 @@ __global__ void k_gtab_init(uint32_t *__restrict__ tabs, uint64_t words, uint64_
 // slots per block at tabs + block * stride_words (key, dist, a region
 // holding the target and frontier bitmaps, order, fr0, fr1 and, in hop
 // mode, dist2 as consecutive uint32 arrays of `cap`, then 4 counters).
-template <bool HOP, int NW>
+template <int M, int NW>
 __global__ void __launch_bounds__(kWave * NW) k_local_search_global(
     Overlay ov, const uint32_t *__restrict__ list, uint32_t nlist,
     const uint8_t *__restrict__ aflag, MemoRef memo,
     LsCounters *__restrict__ cnt, uint32_t *__restrict__ tabs, uint32_t cap,
-    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops) {
+    uint32_t *__restrict__ ws, uint32_t *__restrict__ err, uint32_t hops,
+    const uint32_t *__restrict__ label) {
+  constexpr bool HOP = M != kWpsExact;  // a seventh array (hop distances or settled labels)
   constexpr size_t kArrays = HOP ? 7 : 6;
-  __shared__ uint32_t s_red[2 * NW];
+  __shared__ __align__(8) uint32_t s_red[2 * NW];  // also read as NW 64-bit words
   uint32_t *base = tabs + (size_t)blockIdx.x * ((size_t)cap * kArrays + 4);
   Tab<uint32_t, true> T;
   T.key = base;
@@ -424,7 +431,8 @@ __global__ void __launch_bounds__(kWave * NW) k_local_search_global(
   const Coop<kWave, NW> C{s_red};
   SearchStats ss;
   for (uint32_t i = blockIdx.x; i < nlist; i += gridDim.x) {
-    if (!search_source<kWave, NW, HOP>(ov, aflag, memo, T, list[i], ss, ws, err, hops, C)) {
+    if (!search_source<kWave, NW, M>(ov, aflag, memo, T, list[i], ss, ws, err, hops, C,
+                                      label)) {
       if (threadIdx.x == 0) atomicOr(err, kErrCapacity);
     }
   }

@@ -33,6 +33,8 @@ struct Overlay {
 };
 
 enum : int { kCtrUsed = 0, kCtrF0 = 1, kCtrF1 = 2, kCtrOvf = 3 };
+// Witness-search modes (the values of CH_WPS_EXACT, CH_WPS_HOP, CH_WPS_SETTLED).
+enum : int { kWpsExact = 0, kWpsHop = 1, kWpsSettled = 2 };
 
 template <typename IdxT, bool GL>
 struct Tab {
@@ -180,6 +182,35 @@ struct Coop {
     }
     return v;
   }
+  // minimum of a 64-bit key over the lanes (uses red as NW 64-bit words)
+  template <typename TabT>
+  __device__ __forceinline__ uint64_t min64(uint64_t v, const TabT &T) const {
+    v = gmin64<G>(v);
+    if constexpr (NW > 1) {
+      uint64_t *r = reinterpret_cast<uint64_t *>(red);
+      if (lane_id() == 0) r[wv()] = v;
+      __syncthreads();
+      v = r[0];
+#pragma unroll
+      for (int i = 1; i < NW; i++) v = r[i] < v ? r[i] : v;
+      __syncthreads();
+    }
+    return v;
+  }
+  // x of the one lane with `mine` set (exactly one lane of the search has it)
+  template <typename TabT>
+  __device__ __forceinline__ uint32_t pick(uint32_t x, bool mine, const TabT &T) const {
+    if constexpr (NW == 1) {
+      const uint64_t b = gballot<G>(mine);
+      return gshfl<G>(x, b ? __builtin_ctzll(b) : 0);
+    } else {
+      if (mine) red[0] = x;
+      __syncthreads();
+      x = red[0];
+      __syncthreads();
+      return x;
+    }
+  }
   template <typename TabT>
   __device__ __forceinline__ uint32_t max(uint32_t v, const TabT &T) const {
     v = gmax<G>(v);
@@ -225,6 +256,97 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T, const Coop<G, 
   C.sync(T);
 }
 
+// Steps 2 and 3 of the settled(theta) mode (the paper's literal bound, Alg.
+// 4: a search stops once theta vertices are settled or once every target
+// is): Dijkstra from s that settles one vertex per step, the open vertex with
+// the smallest (distance, label) found by a min-reduction over the table;
+// s is the first settled vertex.  Only settled vertices are relaxed from and
+// only settled targets get a memo entry.  dist2 holds each slot's label, the
+// frontier bitmap marks settled slots; `hops` is theta.
+template <int G, int NW, typename IdxT, bool GL>
+__device__ bool settled_search(const Overlay &ov, const MemoRef &memo, const Tab<IdxT, GL> &T,
+                               uint32_t s, uint32_t gs, uint32_t D, uint32_t nt, SearchStats &ss,
+                               uint32_t *__restrict__ ws, uint32_t theta, const Coop<G, NW> &C,
+                               const uint32_t *__restrict__ label) {
+  constexpr int NT = Coop<G, NW>::NT;
+  const int tl = C.tl();
+  C.sync(T);
+  if (tl == 0) {
+    const int slot = T.insert(s);
+    if (slot >= 0) {
+      T.st(&T.dist[slot], 0u);
+      T.st(&T.dist2[slot], label[gs]);
+    }
+  }
+  C.sync(T);
+  uint32_t pops = 0, tdone = 0;
+  while (pops < theta && tdone < nt && !T.ld(&T.ctr[kCtrOvf])) {
+    const uint32_t used = min(T.ld(&T.ctr[kCtrUsed]), T.limit);
+    uint64_t mk = ~0ull;
+    uint32_t mslot = 0;
+    for (uint32_t i = tl; i < used; i += NT) {
+      const IdxT slot = T.ldi(&T.order[i]);
+      if ((T.ld(&T.front[slot >> 5]) >> (slot & 31)) & 1u) continue;  // settled
+      const uint32_t d = T.ld(&T.dist[slot]);
+      if (d == SP_INF32) continue;
+      const uint64_t k = ((uint64_t)d << 32) | T.ld(&T.dist2[slot]);
+      if (k < mk) {
+        mk = k;
+        mslot = slot;
+      }
+    }
+    const uint64_t best = C.min64(mk, T);
+    if (best == ~0ull) break;  // nothing left to settle
+    // labels are distinct, so exactly one lane holds the minimum
+    const uint32_t bs = C.pick(mslot, mk == best, T);
+    const uint32_t d = (uint32_t)(best >> 32);
+    const bool is_tgt = (T.ld(&T.tgt[bs >> 5]) >> (bs & 31)) & 1u;
+    const uint32_t x = T.ld(&T.key[bs]);
+    C.sync(T);
+    if (tl == 0) {
+      atomicOr(&T.front[bs >> 5], 1u << (bs & 31));
+      ss.rows++;
+    }
+    pops++;
+    tdone += is_tgt ? 1u : 0u;
+    const uint32_t a0 = ov.foff[x], a1 = ov.foff[x + 1];
+    for (uint32_t e = a0 + tl; e < a1; e += NT) {
+      const uint2 b = ov.farc[e];
+      ss.arcs++;
+      const uint64_t nd = (uint64_t)d + b.y;
+      if (nd > D) continue;
+      const int y = T.insert(b.x);
+      if (y < 0) continue;
+      if ((T.ld(&T.front[y >> 5]) >> (y & 31)) & 1u) continue;  // settled
+      const uint32_t old = atomicMin(&T.dist[y], (uint32_t)nd);
+      if ((uint32_t)nd < old) T.st(&T.dist2[y], label[ov.gid[b.x]]);
+    }
+    C.sync(T);
+  }
+  C.sync(T);
+  if (T.ld(&T.ctr[kCtrOvf])) {
+    tab_reset(T, C);
+    return false;
+  }
+  ss.targets += (tl == 0) ? nt : 0;
+  ss.searched += (tl == 0) ? 1 : 0;
+  {
+    const uint32_t used = T.ld(&T.ctr[kCtrUsed]);
+    for (uint32_t i = tl; i < used; i += NT) {
+      const IdxT slot = T.ldi(&T.order[i]);
+      const bool tg = (T.ld(&T.tgt[slot >> 5]) >> (slot & 31)) & 1u;
+      const bool st = (T.ld(&T.front[slot >> 5]) >> (slot & 31)) & 1u;
+      if (tg && st) {
+        memo_put(memo, gs, ov.gid[T.ld(&T.key[slot])], T.ld(&T.dist[slot]));
+        ss.inserts++;
+      }
+    }
+    if (ws && tl == 0) ws[gs] = pops;
+  }
+  tab_reset(T, C);
+  return true;
+}
+
 // One source.  Returns false when the table overflowed (nothing written).
 // HOP: hop-synchronous search of at most `hops` levels -- level k expands
 // the vertices whose distance changed in level k-1 with their level-(k-1)
@@ -232,12 +354,14 @@ __device__ __forceinline__ void tab_reset(const Tab<IdxT, GL> &T, const Coop<G, 
 // entries are copied back.  The result is the minimum over walks of at most
 // `hops` arcs within the radius, independent of the order of relaxations.
 // Targets the walks do not reach get no memo entry.
-template <int G, int NW, bool HOP, typename IdxT, bool GL>
+template <int G, int NW, int M, typename IdxT, bool GL>
 __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ aflag,
                               const MemoRef &memo, const Tab<IdxT, GL> &T, uint32_t s, SearchStats &ss,
                               uint32_t *__restrict__ ws, uint32_t *__restrict__ err,
-                              uint32_t hops, const Coop<G, NW> &C) {
+                              uint32_t hops, const Coop<G, NW> &C,
+                              const uint32_t *__restrict__ label) {
   static_assert(NW == 1 || G == kWave, "cooperating waves use whole waves");
+  constexpr bool HOP = M == kWpsHop, SET = M == kWpsSettled;
   constexpr int NT = Coop<G, NW>::NT;
   const int gl = glane<G>();
   const int tl = C.tl();
@@ -316,6 +440,8 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     tab_reset(T, C);
     return true;
   }
+
+  if constexpr (SET) return settled_search(ov, memo, T, s, gs, D, nt, ss, ws, hops, C, label);
 
   // ---- 2. bounded search from s: label-correcting (exact) or
   //         hop-synchronous (HOP) ------------------------------------------

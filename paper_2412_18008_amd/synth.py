@@ -12,6 +12,8 @@ experiments (its OpenStreetMap, DIMACS and k-NN data are not available):
 * ``clustered_road``  the same construction over Gaussian "city" clusters
                       with travel-time weights (length / speed class);
 * ``chain``           a path with weights 1..32 (the paper's chain family);
+* ``knn_graph``       arcs from every point to its k nearest neighbours with
+                      weights 1..32 (the paper's k-NN family);
 * ``fan``             a path plus a hub with arcs to all of it (a vertex
                       whose upward search space is the whole graph);
 * ``random_digraph``  small random digraphs with self-loops, parallel arcs
@@ -135,6 +137,22 @@ def clustered_road(n, seed=0, k=3, oneway_frac=0.1, centres=64, frac_city=0.7,
     sp = np.asarray(speeds, dtype=np.float64)[np.searchsorted(q, ln)]
     w = np.rint(scale * ln / sp).astype(np.int64) + 1
     return _orient(n, a, b, w, oneway_frac, _rng(seed + 2))
+
+
+def knn_graph(n, k, seed=0, wmin=1, wmax=32):
+    """k-NN graph over n uniform points in the unit square: each vertex has
+    arcs to its k nearest other points (m = k n), each with an independent
+    uniform integer weight in [wmin, wmax] (the paper's k-NN family: k
+    out-going edges per vertex, random weights 1..32)."""
+    from scipy.spatial import cKDTree
+
+    rng = _rng(seed)
+    pts = rng.random((n, 2))
+    _, nb = cKDTree(pts).query(pts, k=k + 1, workers=-1)
+    src = np.repeat(np.arange(n, dtype=np.int64), k)
+    dst = nb[:, 1:].reshape(-1).astype(np.int64)
+    w = _rng(seed + 1).integers(wmin, wmax + 1, size=len(src), dtype=np.int64)
+    return to_csr(n, src, dst, w)
 
 
 def chain(n, seed=0, directed=True, wmin=1, wmax=32):

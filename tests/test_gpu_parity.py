@@ -365,6 +365,19 @@ def test_raw_id_tiebreak_bit_exact(gpu):
         assert_same_ch(oracle_export(o), gpu_export(ch), f"batch {name}")
 
 
+def test_knn_graphs_bit_exact(gpu):
+    # the paper's k-NN family: k out-arcs per vertex to its nearest points,
+    # weights 1..32; scoring work grows with k (pairs in x out per vertex)
+    for n, k in ((3000, 2), (3000, 5), (3000, 10), (50_000, 5), (20_000, 10)):
+        off, dst, w = synth.knn_graph(n, k, seed=k)
+        lab = synth.labels(n, k)
+        o, ch = _case(f"knn n={n} k={k}", off, dst, w, lab, gpu)
+        s, t = synth.queries(n, 2000, seed=k)
+        od, _ = o.query_batch(s, t)
+        assert np.array_equal(ch.query(s, t), od)
+        assert np.array_equal(ch.query(s, t, full=True), od)
+
+
 def star_with_prunable_arc(d, seed):
     """The star of synth.star plus one leaf-to-leaf arc a -> b (weight 1) with
     w(0, a) + 1 < w(0, b): the centre's round-0 search reaches b through a,

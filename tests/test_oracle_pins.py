@@ -63,6 +63,8 @@ def small_graphs():
     out.append(("bichain", synth.chain(20, seed=2, directed=False)))
     out.append(("star", synth.star(6, seed=3)))
     out.append(("sparse", synth.random_digraph(30, 20, seed=9, wmax=5)))
+    for k in (2, 5):  # the paper's k-NN family (directed, weights 1..32)
+        out.append((f"knn{k}", synth.knn_graph(36, k, seed=k)))
     return out
 
 
