@@ -393,6 +393,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="road24m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--one-to-all", type=int, default=64, metavar="K",
+                    help="after the steps, time ch_one_to_all from K sources to every vertex "
+                         "(0 = skip)")
     ap.add_argument("--settle", type=int, default=0, metavar="THETA",
                     help="witness searches in the paper's settled(theta) mode instead of "
                          "exact")
@@ -550,6 +553,22 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in sorted(cands.items(),
                                                                   key=lambda x: -x[1])},
     }
+    if args.one_to_all:
+        print(f"[bench] one-to-all from {args.one_to_all} sources", file=sys.stderr, flush=True)
+        ch = binding.build(t_off, t_dst, t_w, seed=0, **knobs)
+        srcs = torch.from_numpy(qs[:args.one_to_all].astype(np.int32)).to(dev)
+        ch.one_to_all(srcs[:1])  # scratch sized once
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rows = ch.one_to_all(srcs)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        line["one_to_all"] = {"sources": args.one_to_all, "ms": el * 1e3,
+                              "ms_per_source": el * 1e3 / args.one_to_all,
+                              "levels": recs[-1]["summary"]["rounds"],
+                              "distances_per_s": args.one_to_all * n / el}
+        del rows
+        ch.free()
     if os.path.exists(args.learned):
         line["plain_vs_learned"] = plain_vs_learned(binding, args, dev)
     if args.copy_calibration:

@@ -304,6 +304,25 @@ int ch_query_batch(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_
 int ch_query_batch_stats(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                          uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream);
 
+/* One-to-all distances (and many-to-many) on the CH by its two sweeps (Sec.
+ * "Query on Contraction Hierarchies": vertices grouped by level as in
+ * PHAST; an upward search from each source, then a downward pass over the
+ * levels from the top, each vertex taking the minimum over its downward
+ * arcs).  Every CH arc joins two levels, so each level's distances are final
+ * before the next level reads them; the results are exact distances.
+ *   s:    ks source ids
+ *   t:    kt target ids, or NULL for every vertex (then kt is ignored and
+ *         each row has n entries)
+ *   dist: ks rows of (t ? kt : n) uint64 distances, row i for s[i], entry j
+ *         for t[j] (or vertex j in original ids); UINT64_MAX = unreachable.
+ *   s, t, dist on the host, or on the device with CH_Q_ON_DEVICE.
+ * Up to 64 sources share one pass over the levels; the CH keeps a scratch of
+ * n x 8 bytes per source of a pass (n x 512 bytes for 64).
+ * Errors: CH_E_INVALID (NULL, id >= n, no query index), CH_E_OOM,
+ * CH_E_DEVICE. */
+int ch_one_to_all(const ch_t *ch, const uint32_t *s, uint32_t ks, const uint32_t *t, uint32_t kt,
+                  uint64_t *dist, uint32_t flags, void *stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc): ch_query_batch_stats
  * without any allocation, with the same results.  s, t, dist and visited

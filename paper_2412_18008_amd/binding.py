@@ -37,7 +37,7 @@ CH_Q_COUNT = 1 << 21
 EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
             "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version", "ch_export_features",
             "ch_mlp_forward", "ch_mlp_grad", "ch_mlp_train", "ch_query_batch_stats",
-            "ch_query_batch_noalloc", "ch_get_query_stats")
+            "ch_query_batch_noalloc", "ch_get_query_stats", "ch_one_to_all")
 
 
 class ChError(RuntimeError):
@@ -163,6 +163,8 @@ def lib():
         L.ch_query_batch_noalloc.restype = i32
         L.ch_get_query_stats.argtypes = [vp, C.POINTER(QueryStats)]
         L.ch_get_query_stats.restype = i32
+        L.ch_one_to_all.argtypes = [vp, vp, u32, vp, u32, vp, u32, vp]
+        L.ch_one_to_all.restype = i32
         L.ch_export_features.argtypes = [vp, vp]
         L.ch_export_features.restype = i32
         L.ch_mlp_forward.argtypes = [vp, u64, vp, vp, vp, u32, vp]
@@ -252,6 +254,32 @@ class CH:
                                           None),
                "ch_query_batch_stats")
         return dist, vis
+
+    def one_to_all(self, s, t=None, stream=None):
+        """Distances from each source in s to every vertex (rows of n), or to
+        the targets t (rows of len(t)): numpy uint64 (host arrays), or a CUDA
+        int64 tensor of uint64 bit patterns for CUDA inputs."""
+        if _is_torch_cuda(s):
+            import torch
+
+            ks = s.numel()
+            kt = t.numel() if t is not None else 0
+            out = torch.empty(ks * (kt if t is not None else self.n), dtype=torch.int64,
+                              device=s.device)
+            st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+            _check(lib().ch_one_to_all(self.h, s.data_ptr(), ks,
+                                       t.data_ptr() if t is not None else None, kt,
+                                       out.data_ptr(), CH_Q_ON_DEVICE, st), "ch_one_to_all")
+            return out.view(ks, -1)
+        s = np.ascontiguousarray(s, np.uint32)
+        tt = None if t is None else np.ascontiguousarray(t, np.uint32)
+        nt = self.n if tt is None else len(tt)
+        out = np.empty((len(s), nt), np.uint64)
+        _check(lib().ch_one_to_all(self.h, s.ctypes.data, len(s),
+                                   None if tt is None else tt.ctypes.data,
+                                   0 if tt is None else len(tt), out.ctypes.data, 0, stream),
+               "ch_one_to_all")
+        return out
 
     def last_query_stats(self):
         """Counters and per-tier device times of the last query batch."""

@@ -1651,7 +1651,7 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
 ch_s::~ch_s() {
   sp::DBuf *all[] = {&level, &score, &label, &rank, &up_t, &up_h, &up_w, &up_m, &dn_t, &dn_h,
                      &dn_w, &dn_m, &q_upoff, &q_uparc, &q_dnoff, &q_dnarc, &q_lstart, &q_wend, &q_s, &q_t, &q_d,
-                     &q_ovf, &q_tab, &q_ctr, &rec, &q_v, &q_ovf2, &q_gtab};
+                     &q_ovf, &q_tab, &q_ctr, &rec, &q_v, &q_ovf2, &q_gtab, &q_phast};
   for (sp::DBuf *b : all) b->release();
   for (auto &e : q_ev)
     if (e) (void)hipEventDestroy(e);

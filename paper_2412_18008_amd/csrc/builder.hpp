@@ -37,6 +37,7 @@ struct ch_s {
   // query scratch
   sp::DBuf q_s, q_t, q_d, q_v, q_ovf, q_ovf2, q_tab, q_gtab, q_ctr;
   int q_first_tier = 1;  // query tier where the previous batch mostly ended
+  sp::DBuf q_phast;  // one-to-all sweeps: distances, rank-major, KC sources per vertex
   ch_query_stats_t qstats{};              // counters of the last query batch
   hipEvent_t q_ev[8] = {};                // tier timing (created on first use)
 
@@ -68,6 +69,9 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
 // Query batch (post.hip).
 int query_batch(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                 uint64_t *dist, uint32_t *visited, uint32_t flags, hipStream_t st);
+// One-to-all / many-to-many distances by the CH's two sweeps (phast.hip).
+int one_to_all(const ch_s *ch, const uint32_t *s, uint32_t ks, const uint32_t *t, uint32_t kt,
+               uint64_t *dist, uint32_t flags, hipStream_t st);
 // Query batch with every scratch array in a fixed per-GPU array (post.hip).
 int query_batch_noalloc(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                         uint64_t *dist, uint32_t *visited, uint32_t flags, hipStream_t st);

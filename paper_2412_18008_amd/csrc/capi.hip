@@ -41,6 +41,15 @@ int ch_query_batch_stats(const ch_t *ch, const uint32_t *s, const uint32_t *t, u
   return sp::query_batch(ch, s, t, q, dist, visited, flags, (hipStream_t)stream);
 }
 
+int ch_one_to_all(const ch_t *ch, const uint32_t *s, uint32_t ks, const uint32_t *t, uint32_t kt,
+                  uint64_t *dist, uint32_t flags, void *stream) {
+  sp::clear_error();
+  if (!ch) return set_error(CH_E_INVALID, "ch must not be NULL");
+  if (ks && (!s || !dist)) return set_error(CH_E_INVALID, "s and dist must not be NULL");
+  if (t && !kt) return set_error(CH_E_INVALID, "a target list needs kt > 0");
+  return sp::one_to_all(ch, s, ks, t, kt, dist, flags, (hipStream_t)stream);
+}
+
 int ch_query_batch_noalloc(const ch_t *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                            uint64_t *dist, uint32_t *visited, uint32_t flags, void *stream) {
   sp::clear_error();

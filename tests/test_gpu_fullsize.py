@@ -191,6 +191,15 @@ def test_road24m_bit_exact(gpu):
         t = rng.choice(fin, size=min(3000, len(fin)), replace=False)
         d = ch.query(np.full(len(t), src, np.uint32), t)
         assert np.array_equal(d, ref[t])
+    # one-to-all rows from the CH's two sweeps: exact on the settled part
+    srcs = rng.integers(0, n, size=2).astype(np.uint32)
+    rows = ch.one_to_all(srcs)
+    for src, row in zip(srcs, rows):
+        ref, c = oracle.dijkstra_settle(off, dst, w, int(src), 300_000)
+        fin = ref != np.uint64(0xFFFFFFFFFFFFFFFF)
+        assert np.array_equal(row[fin], ref[fin])
+        assert np.all(row[~fin] >= ref[fin].max())  # the rest lies beyond the settled ball
+    progress("one-to-all rows checked")
     # the benchmark's query batch; s == t gives 0
     s, t = synth.queries(n, 1_000_000, seed=3)
     d, vis = ch.query_stats(s, t)
