@@ -444,15 +444,17 @@ def main():
     from paper_2412_18008_amd import autotune
 
     knobs = {} if args.untuned else autotune.params_for(n, m)
+    qknobs = {} if args.untuned else autotune.query_params_for(n, m)
     if args.settle:
         knobs = dict(knobs, settle=args.settle)
-    print(f"[bench] knobs {knobs or 'default'}", file=sys.stderr, flush=True)
+    print(f"[bench] knobs {knobs or 'default'}, query {qknobs or 'default'}", file=sys.stderr,
+          flush=True)
 
     def step():
         tb = time.perf_counter()
         ch = binding.build(t_off, t_dst, t_w, seed=0, stats=True, **knobs)
         tq = time.perf_counter()
-        d = ch.query(t_s, t_t)
+        d = ch.query(t_s, t_t, **qknobs)
         te = time.perf_counter()
         rec = dict(build_s=tq - tb, query_s=te - tq, summary=dict(ch.summary),
                    rounds=ch.round_stats(), query=ch.last_query_stats())
@@ -483,7 +485,7 @@ def main():
     print("[bench] counting the query kernels' units in one more batch", file=sys.stderr,
           flush=True)
     ch = binding.build(t_off, t_dst, t_w, seed=0, **knobs)
-    ch.query(t_s, t_t, count=True)  # a fresh CH, as in the timed steps
+    ch.query(t_s, t_t, count=True, **qknobs)  # a fresh CH, as in the timed steps
     torch.cuda.synchronize()
     qstat = ch.last_query_stats()
     first = qstat["first_tier"]
@@ -538,7 +540,7 @@ def main():
                    "wps": (f"settled(theta={args.settle}), radius D_s" if args.settle
                            else "exact, radius D_s"),
                    "step": "ch_build + one ch_query_batch",
-                   "knobs": knobs or "default"},
+                   "knobs": knobs or "default", "query_knobs": qknobs or "default"},
         "build_time_s": build_s,
         "query_batch_ms": query_s * 1e3,
         "queries_per_s": len(qs) / query_s,

@@ -462,11 +462,24 @@ def test_autotuner_roundtrip(gpu, tmp_path, monkeypatch):
 
     monkeypatch.setenv("SPOCH_AUTOTUNE_CACHE", str(tmp_path / "tuned.json"))
     off, dst, w = synth.road_like(30_000, seed=2)
-    best, table = autotune.tune(off, dst, w, reps=1)
-    assert len(table) == len(autotune.candidates())
     n, m = len(off) - 1, len(dst)
-    autotune.save({autotune.size_class(n, m): dict(params=best["params"], ms=best["ms"])})
+    s, t = synth.queries(n, 4000, seed=3)
+    # every configuration is checked against the default one inside tune()
+    best, qbest, table = autotune.tune(off, dst, w, s, t, reps=1, log=lambda *_: None)
+    distinct = {tuple(sorted(r["params"].items())) for r in table}
+    assert len(distinct) == len(table) == 1 + sum(
+        len([v for v in autotune.CHOICES[k] if v != 0]) for k in autotune.KNOBS)
+    assert len(qbest["table"]) == len(autotune.QUERY_CHOICES["waves"]) * len(
+        autotune.QUERY_CHOICES["window"])
+    autotune.save({autotune.size_class(n, m): dict(params=best["params"], ms=best["ms"],
+                                                   query=qbest)})
     assert autotune.params_for(n, m) == best["params"]
+    assert autotune.query_params_for(n, m) == qbest["params"]
+    ch = gpu.build(off, dst, w, **autotune.params_for(n, m))
+    ref = oracle.OracleCH(off, dst, w, seed=0).run()
+    d = ch.query(s, t, **autotune.query_params_for(n, m))
+    od, _ = ref.query_batch(s[:500], t[:500])
+    assert np.array_equal(d[:500], od)
 
 
 def test_dense_tail_table(gpu):
