@@ -803,9 +803,77 @@ __global__ void __launch_bounds__(64 * NW) k_query(
   auto rank_of = [&](uint32_t d, uint32_t slot) -> uint32_t {
     return (TOP && slot < TOP) ? tbase + slot : qld<GM>(&S.key[d][slot - TOP]);
   };
+  // Stall-on-demand (pruned searches only).  Vertex x, reached in direction
+  // d at distance dx, is not expanded when some higher-ranked u with a CH arc
+  // between them that points along the search (u -> x for the search from s,
+  // x -> u for the one from t) gives d(u) + w < dx: d(u) is a real path
+  // length, so dx is not the distance of x, and every path that leaves x
+  // upward is beaten by the one through u.  The vertices of a shortest
+  // up-down path are never stalled at their exact distance (no real path is
+  // shorter), so they still expand and the result stays exact; x is checked
+  // again whenever its distance drops.  The arcs checked are x's arcs of the
+  // other direction, read by the whole wave as in an expansion; a lane that
+  // finds a stall sets its entry's bit in the wave's mask.  Called by every
+  // lane of a wave (wave-uniform loop bounds).
+  // rows and arcs read (expansions and stall checks; stats batches)
+  uint32_t nrows = 0, narcs = 0;
+  __shared__ unsigned long long s_stall[NW];
+  auto stall_check = [&](bool cand, uint32_t vx, uint32_t dx, uint32_t dr) -> bool {
+    uint32_t ss = 0, sl = 0;
+    if (cand) {
+      const uint32_t *o = dr ? upoff : dnoff;
+      ss = o[vx];
+      sl = o[vx + 1] - ss;
+      nrows++;
+      narcs += sl;
+    }
+    const uint32_t incl = gscan_incl<kWave>(sl);
+    const uint32_t T = __shfl(incl, kWave - 1, kWave);
+    if (T == 0) return false;
+    for (uint32_t i0 = 0; i0 < T; i0 += kWave * kQUnroll) {
+      uint2 a[kQUnroll];
+      uint32_t sd[kQUnroll], sdr[kQUnroll], src[kQUnroll];
+#pragma unroll
+      for (int u = 0; u < kQUnroll; u++) {
+        const uint32_t idx = i0 + u * kWave + l;
+        a[u] = make_uint2(SP_EMPTY32, 0u);
+        sd[u] = 0;
+        sdr[u] = 0;
+        src[u] = 0;
+        if (i0 + u * kWave < T) {  // uniform across the wave
+          const int sl2 = gfind<kWave>(incl, idx);
+          const uint32_t sss = __shfl(ss, sl2, kWave), sinc = __shfl(incl, sl2, kWave);
+          const uint32_t ssl = __shfl(sl, sl2, kWave);
+          sd[u] = __shfl(dx, sl2, kWave);
+          sdr[u] = __shfl(dr, sl2, kWave);
+          src[u] = (uint32_t)sl2;
+          if (idx < T) a[u] = (sdr[u] ? uparc : dnarc)[sss + (idx - (sinc - ssl))];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kQUnroll; u++) {
+        if (a[u].x == SP_EMPTY32 || a[u].y >= sd[u]) continue;
+        uint32_t du = SP_INF32;
+        if (TOP && a[u].x >= tbase) {
+          du = qld<GM>(&S.dist[sdr[u]][a[u].x - tbase]);
+        } else {
+          const int h = qfind<GM>(S, sdr[u], a[u].x);
+          if (h >= 0) du = qld<GM>(&S.dist[sdr[u]][TOP + h]);
+        }
+        if (du != SP_INF32 && (unsigned long long)du + a[u].y < sd[u])
+          atomicOr(&s_stall[wv], 1ull << src[u]);
+      }
+    }
+    wave_sync();
+    const bool st = (s_stall[wv] >> l) & 1ull;
+    wave_sync();
+    if (l == 0) s_stall[wv] = 0ull;
+    wave_sync();
+    return st;
+  };
+  if (tid < NW) s_stall[tid] = 0ull;
   qclear<GM>(S, tid, NT);
   qsync<NW, GM>();
-  uint32_t nrows = 0, narcs = 0;  // expansions and relaxations (stats batches)
   for (;;) {
     // every thread has read the previous index (it passed a barrier since)
     if (tid == 0) {
@@ -912,24 +980,29 @@ __global__ void __launch_bounds__(64 * NW) k_query(
       // entries dealt to the waves in turn, so a small step still uses all
       for (uint32_t cb = 0; cb < F; cb += NT) {
         const uint32_t i = cb + (uint32_t)l * NW + wv;
-        uint32_t rs = 0, rl = 0, dx = 0, dr = 0;
+        uint32_t rs = 0, rl = 0, dx = 0, dr = 0, vx = 0;
+        bool cand = false;
         if (i < F) {
           const uint32_t e = qlde<GM>(&S.list[i]);
           dr = e / NS;
           const uint32_t slot = e - dr * NS;
-          const uint32_t vx = rank_of(dr, slot);
+          vx = rank_of(dr, slot);
           dx = qld<GM>(&S.dist[dr][slot]);
           if (vx >= (dr ? T1 : T0)) {
             atomicOr(&S.bits[dr][slot >> 5], 1u << (slot & 31));
           } else if (prune && dx >= qld64<GM>(&S.mu)) {
             // no path through x is shorter than one already met
           } else {
-            const uint32_t *o = dr ? dnoff : upoff;
-            rs = o[vx];
-            rl = o[vx + 1] - rs;
-            nrows++;
-            narcs += rl;
+            cand = true;
           }
+        }
+        if (prune && stall_check(cand, vx, dx, dr)) cand = false;
+        if (cand) {
+          const uint32_t *o = dr ? dnoff : upoff;
+          rs = o[vx];
+          rl = o[vx + 1] - rs;
+          nrows++;
+          narcs += rl;
         }
         const uint32_t incl = gscan_incl<kWave>(rl);
         const uint32_t T = __shfl(incl, kWave - 1, kWave);
