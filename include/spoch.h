@@ -85,7 +85,10 @@ extern "C" {
 #define CH_Q_LEVEL_WINDOW(w) ((uint32_t)(w) << 12)
 /* By default a query skips every vertex and arc whose distance from its end
  * is not below the shortest s-t path met so far (no such vertex can be on a
- * shorter path), which keeps distances exact.  CH_Q_FULL_CLOSURE expands
+ * shorter path), and does not expand a vertex whose distance is beaten by a
+ * path through a higher-ranked neighbour (stall-on-demand: such a distance
+ * is not exact, so no shortest path leaves the vertex upward with it); both
+ * keep distances exact.  CH_Q_FULL_CLOSURE expands
  * both upward search spaces completely instead; ch_query_batch_stats always
  * does, so its visited counts (the sizes of the two search spaces) do not
  * depend on timing. */
@@ -93,6 +96,12 @@ extern "C" {
 /* Count the vertices expanded and arcs relaxed by the batch (read with
  * ch_get_query_stats); ch_query_batch_stats always counts. */
 #define CH_Q_COUNT (1u << 21)
+/* Tier a batch starts in: 1 = LDS tables for small search spaces, 2 = LDS
+ * tables for large ones, 3 = tables in global memory; 0 = chosen by the
+ * library (tier 2 for hierarchies deeper than 256 levels, else tier 1, and
+ * one tier up for later batches when more than half of a batch moved on).
+ * Queries that outgrow a tier still move on.  Results do not depend on it. */
+#define CH_Q_FIRST_TIER(t) ((uint32_t)(t) << 22)
 
 /* Input graph in CSR form, arcs grouped by tail vertex.
  *   offsets[n+1]: offsets[0] = 0, non-decreasing, offsets[n] = m

@@ -71,6 +71,11 @@ CH_TIE_HASHED_ID, CH_TIE_RAW_ID = 0, 1
 CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
 
 
+def CH_Q_FIRST_TIER(t):
+    """Query flag: the tier a batch starts in (1, 2, 3; 0 = chosen by the library)."""
+    return int(t) << 22
+
+
 def CH_Q_WAVES(nw):
     """Query flag: waves that share one query (1, 2, 4, 8; 0 = default)."""
     if nw not in (0, 1, 2, 4, 8):
@@ -215,16 +220,19 @@ class CH:
             _lib.ch_free(self.h)
             self.h = None
 
-    def query(self, s, t, stream=None, waves=0, window=0, full=False, count=False):
+    def query(self, s, t, stream=None, waves=0, window=0, full=False, count=False, tier=0):
         """dist[i] = shortest s[i] -> t[i] distance (uint64, max = unreachable).
         numpy inputs give a numpy result; torch CUDA inputs give a torch CUDA
         int64 tensor (holding the uint64 bit patterns).  waves: waves per
         query in the kernel (1, 2, 4, 8; 0 = default); window: level window of
         a search step (0 = default, 255 = none); full: expand both upward
         search spaces completely (no pruning by the best path met); count:
-        count expansions and relaxed arcs (last_query_stats)."""
+        count expansions and relaxed arcs (last_query_stats); tier: the tier
+        the batch starts in (1, 2, 3; 0 = chosen by the library)."""
+        if tier not in (0, 1, 2, 3):
+            raise ValueError("tier must be 0, 1, 2 or 3")
         qf = CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window) | (CH_Q_FULL_CLOSURE if full else 0) | (
-            CH_Q_COUNT if count else 0)
+            CH_Q_COUNT if count else 0) | CH_Q_FIRST_TIER(tier)
         if _is_torch_cuda(s):
             import torch
 

@@ -1248,7 +1248,8 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
                                    : nullptr;
   ch_query_stats_t qsn{};
   qsn.queries = q;
-  qsn.first_tier = (uint32_t)ch->q_first_tier;
+  const uint32_t forced = (flags >> 22) & 3u;  // CH_Q_FIRST_TIER; 0 = adaptive
+  qsn.first_tier = forced ? forced : (uint32_t)ch->q_first_tier;
   qsn.counted = qcount ? 1u : 0u;
   // tier timing: events 2t and 2t+1 around tier t (ch_query_batch only)
   hipEvent_t *ev = sc.timed ? ch->q_ev : nullptr;
@@ -1261,7 +1262,7 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   const uint32_t *upoff = ch->q_upoff.as<uint32_t>(), *dnoff = ch->q_dnoff.as<uint32_t>();
   const uint2 *uparc = ch->q_uparc.as<uint2>(), *dnarc = ch->q_dnarc.as<uint2>();
   uint32_t *ovf1 = sc.ovf1, *ovf2 = sc.ovf2;
-  const int first = ch->q_first_tier;
+  const int first = forced ? (int)forced : ch->q_first_tier;
   const uint32_t wf = (flags >> 12) & 0xFFu;  // 0: default window, 255: none
   uint32_t win = (wf == 0 || wf == 255) ? 0u : wf;
   if (win >= ch->rounds) win = 0;  // a window over every level: the plain path
@@ -1357,9 +1358,9 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
                                      "of ch_query_batch_noalloc; use ch_query_batch");
     }
   }
-  // where the next batch starts
-  if (first <= 1 && hc[0] * 2 > q) ch->q_first_tier = 2;
-  if (first <= 2 && into2 && (uint64_t)hc[2] * 2 > into2) ch->q_first_tier = 3;
+  // where the next batch starts (adaptive batches only)
+  if (!forced && first <= 1 && hc[0] * 2 > q) ch->q_first_tier = 2;
+  if (!forced && first <= 2 && into2 && (uint64_t)hc[2] * 2 > into2) ch->q_first_tier = 3;
   // counters and tier times of this batch (one more wait, for the copies)
   if (qcount || ev) {
     unsigned long long qc[2] = {0, 0};
