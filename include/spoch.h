@@ -164,7 +164,14 @@ typedef struct {
    * graph must then carry no labels, else CH_E_INVALID). */
   uint32_t tiebreak;
   uint32_t settle_limit; /* CH_WPS_SETTLED: vertices settled per search (theta), >= 1 */
+  /* Exact mode: a search step expands only the frontier vertices whose
+   * distance is below the smallest frontier distance plus D_s >> ls_step
+   * (distance buckets, so fewer vertices are expanded before their distance
+   * is final); 0 = the default, 2; CH_LS_STEP_ALL (32) expands the whole
+   * frontier every step.  At most 32.  Changes speed only, never results. */
+  uint32_t ls_step;
 } ch_params_t;
+#define CH_LS_STEP_ALL 32u
 #define CH_DENSE_TAIL_OFF 1u
 #define CH_TIE_HASHED_ID 0u
 #define CH_TIE_RAW_ID 1u

@@ -4,7 +4,8 @@ Build knobs (``ch_params_t``): the first-tier witness-search kernel (lanes
 per source x LDS table slots) for sparse and for dense rounds, the average
 out-degree that separates the two, the lanes per item of the other round
 kernels, and the overlay size below which exact-mode searches use the
-all-pairs table (``dense_tail``).  Query knobs (flags of ch_query_batch): the
+all-pairs table (``dense_tail``), and the distance-bucket width of an
+exact-mode search step (``ls_step``).  Query knobs (flags of ch_query_batch): the
 waves per query of the first query tier and the level window.  None of them
 may change the result: every build configuration tried must give a CH
 identical to the default one and every query configuration the same
@@ -31,12 +32,12 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuned.json")
-KNOBS = ("ls_sparse", "ls_dense", "dense_deg10", "group", "dense_tail")
+KNOBS = ("ls_sparse", "ls_dense", "dense_deg10", "group", "dense_tail", "ls_step")
 QUERY_KNOBS = ("waves", "window")
 # values tried per knob (0 = the library's default)
 # (dense_tail 1 = off: no all-pairs table)
 CHOICES = {"ls_sparse": (0, 2, 3), "ls_dense": (0, 1, 2, 3), "dense_deg10": (0, 40, 70),
-           "group": (0, 8, 16, 32), "dense_tail": (0, 1, 2048, 4096)}
+           "group": (0, 8, 16, 32), "dense_tail": (0, 1, 2048, 4096), "ls_step": (0, 1, 2, 5, 32)}
 QUERY_CHOICES = {"waves": (0, 1, 2, 8), "window": (0, 16, 48, 128)}
 
 

@@ -58,7 +58,8 @@ class Params(C.Structure):
                 ("dense_deg10", C.c_uint32), ("priority", C.c_uint32), ("mlp", C.c_void_p),
                 ("hop_limit", C.c_uint32), ("dense_tail", C.c_uint32),
                 ("k_ed", C.c_int32), ("k_cn", C.c_int32), ("k_depth", C.c_int32),
-                ("tiebreak", C.c_uint32), ("settle_limit", C.c_uint32)]
+                ("tiebreak", C.c_uint32), ("settle_limit", C.c_uint32),
+                ("ls_step", C.c_uint32)]
 
 
 CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
@@ -344,14 +345,15 @@ class CH:
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
           record=False, hop=0, dense_tail=0, tail_stepwise=False, keep_order=False,
-          score_weights=None, raw_id=False, settle=0):
+          score_weights=None, raw_id=False, settle=0, ls_step=0):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
     selects the hop-bounded witness search with walks of at most `hop` arcs;
     tail_stepwise runs the table rounds one launch per step; keep_order
     builds on the input's numbering (no locality renumbering); score_weights
     = (k_ed, k_cn, k_depth) sets the integer score weights; raw_id labels
     every vertex by its id; settle > 0 selects the settled(theta) witness
-    search with theta = settle."""
+    search with theta = settle; ls_step: distance-bucket width D_s >> ls_step
+    of exact-mode search steps (0 = default, 32 = whole frontier)."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
     pd, kd = _ptr(dst, np.uint32)
@@ -377,7 +379,7 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
                ls_sparse, ls_dense, dense_deg10,
                CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
                None if wts is None else wts.ctypes.data, hop, dense_tail, k_ed, k_cn, k_depth,
-               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID, settle)
+               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID, settle, ls_step)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)

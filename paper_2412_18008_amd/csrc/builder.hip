@@ -147,8 +147,10 @@ struct Builder {
   }
 
   DevCtr *dc() { return dctr.as<DevCtr>(); }
-  // the search bound of the mode: hop_limit (hop) or settle_limit (settled)
+  // the search bound of the mode: hop_limit (hop) or settle_limit
+  // (settled); in exact mode the distance-bucket shift of a search step
   uint32_t mode_limit() const {
+    if (prm.wps_mode == CH_WPS_EXACT) return prm.ls_step ? prm.ls_step : kLsStepDefault;
     return prm.wps_mode == CH_WPS_SETTLED ? prm.settle_limit : prm.hop_limit;
   }
 
@@ -1277,6 +1279,7 @@ static int check_params(const ch_params_t *p, ch_params_t &prm) {
     return set_error(CH_E_INVALID, "hop mode needs hop_limit >= 1");
   if (prm.wps_mode == CH_WPS_SETTLED && prm.settle_limit < 1)
     return set_error(CH_E_INVALID, "settled mode needs settle_limit >= 1");
+  if (prm.ls_step > CH_LS_STEP_ALL) return set_error(CH_E_INVALID, "ls_step must be at most 32");
   if (prm.dense_tail > kTabMaxN)
     return set_error(CH_E_INVALID, "dense_tail must be at most 4096");
   if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&

@@ -347,7 +347,17 @@ __device__ bool settled_search(const Overlay &ov, const MemoRef &memo, const Tab
   return true;
 }
 
+// Exact mode: distance-bucket shift of a search step (the default of
+// ch_params_t.ls_step); 32 expands the whole frontier every step.
+constexpr uint32_t kLsStepDefault = 2;
+
 // One source.  Returns false when the table overflowed (nothing written).
+// Exact mode: a step expands the frontier vertices whose distance is below
+// the smallest frontier distance plus D >> `hops` (the bucket shift; 32 =
+// the whole frontier); the others stay in the frontier for a later step.
+// Expanding near vertices first re-expands fewer vertices whose distance
+// drops later; the result is the same for every shift (every tentative value
+// is a path length and the search ends only when no distance can drop).
 // HOP: hop-synchronous search of at most `hops` levels -- level k expands
 // the vertices whose distance changed in level k-1 with their level-(k-1)
 // distance (dist) and writes dist2; at the end of the level the changed
@@ -469,6 +479,18 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     if constexpr (HOP) {
       if (level == hops) break;
     }
+    // exact mode: the step's distance bound (frontier entries at or above
+    // it wait for a later step)
+    uint32_t B = 0xFFFFFFFFu;
+    if constexpr (!HOP) {
+      if (hops < 32) {
+        uint32_t mn = SP_INF32;
+        for (uint32_t i = tl; i < ncur; i += NT) mn = min(mn, T.ld(&T.dist[T.ldi(&fc[i])]));
+        mn = (uint32_t)C.min64((uint64_t)mn, T);
+        const uint32_t width = max(D >> hops, 1u);
+        B = mn > 0xFFFFFFFFu - width ? 0xFFFFFFFFu : mn + width;
+      }
+    }
     C.sync(T);
     if (tl == 0) T.st(nn, 0u);
     C.sync(T);
@@ -477,19 +499,30 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
       uint32_t rs = 0, rl = 0, dx = 0;
       if (i < ncur) {
         const IdxT x = T.ldi(&fc[i]);
+        bool later = false;
         if constexpr (!HOP) {
-          // the bit is cleared before the distance is read: an improvement
-          // made after the read re-flags x for the next level
-          atomicAnd(&T.front[x >> 5], ~(1u << (x & 31)));
-          if constexpr (GL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
-          else if constexpr (NW == 1) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-          else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          if (T.ld(&T.dist[x]) >= B) {
+            // stays flagged and goes to the next list; an improvement made
+            // meanwhile finds the bit set and does not add x again
+            later = true;
+            const uint32_t p = atomicAdd(nn, 1u);
+            if (p < T.fcap) T.sti(&fn[p], x);
+          } else {
+            // the bit is cleared before the distance is read: an improvement
+            // made after the read re-flags x for the next level
+            atomicAnd(&T.front[x >> 5], ~(1u << (x & 31)));
+            if constexpr (GL) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+            else if constexpr (NW == 1) __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          }
         }
-        dx = T.ld(&T.dist[x]);
-        const uint32_t vx = T.ld(&T.key[x]);
-        rs = ov.foff[vx];
-        rl = ov.foff[vx + 1] - rs;
-        ss.rows++;
+        if (!later) {
+          dx = T.ld(&T.dist[x]);
+          const uint32_t vx = T.ld(&T.key[x]);
+          rs = ov.foff[vx];
+          rl = ov.foff[vx + 1] - rs;
+          ss.rows++;
+        }
       }
       const uint32_t incl = gscan_incl<G>(rl);
       const uint32_t total = gshfl<G>(incl, G - 1);

@@ -59,6 +59,9 @@ def test_null_and_invalid_arguments(binding):
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_UNSUPPORTED
     p = binding.Params(tiebreak=2)  # unknown tie-break
     assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
+    p = binding.Params(ls_step=33)  # bucket shift above 32
+    assert L.ch_build(C.byref(g), C.byref(p), C.byref(h)) == binding.CH_E_INVALID
+    assert "ls_step" in L.ch_last_error().decode()
     lab = np.zeros(1, np.uint32)
     gl = binding.Graph(1, 0, off.ctypes.data, None, None, lab.ctypes.data)
     p = binding.Params(tiebreak=binding.CH_TIE_RAW_ID)  # raw ids and labels together

@@ -444,6 +444,26 @@ def test_batch_equals_single_builds(gpu):
     assert e.value.code == gpu.CH_E_INVALID
 
 
+def test_search_step_buckets_bit_exact(gpu):
+    # exact-mode searches with distance buckets of every width (1 = D_s / 2
+    # ... 32 = the whole frontier per step), in the first, block and global
+    # tiers: the CH and the round counts equal the oracle's
+    cases = small_cases()[:6] + [("road20k", *synth.road_like(20_000, seed=8)),
+                                 ("grid64", *synth.config_grid64(seed=0)),
+                                 ("star6600", *synth.star(6600, seed=3))]
+    for name, off, dst, w in cases:
+        n = len(off) - 1
+        lab = synth.labels(n, 31)
+        ref = oracle.OracleCH(off, dst, w, labels=lab).run()
+        a = oracle_export(ref)
+        for step in (1, 2, 5, 32):
+            ch = gpu.build(off, dst, w, labels=lab, ls_step=step, stats=True, dense_tail=1)
+            assert_same_ch(a, gpu_export(ch), f"{name} ls_step={step}")
+            assert gpu_round_counts(ch) == oracle_round_counts(ref), (name, step)
+            if name == "star6600":
+                assert sum(r["n_ls_global"] for r in ch.round_stats()) > 0
+
+
 def test_search_kernel_knobs_invariance(gpu):
     off, dst, w = synth.road_like(20_000, seed=8)
     n = len(off) - 1
