@@ -170,6 +170,11 @@ typedef struct {
    * is final); 0 = the default, 2; CH_LS_STEP_ALL (32) expands the whole
    * frontier every step.  At most 32.  Changes speed only, never results. */
   uint32_t ls_step;
+  /* CH_PRIO_LEARNED: the priority is rint(y * 2^mlp_qbits) of the network
+   * output y, saturated to int32; 0 = 16, at most 24.  Fewer bits make more
+   * equal priorities (ties go to the label in Select), so more vertices are
+   * local minima in a round. */
+  uint32_t mlp_qbits;
 } ch_params_t;
 #define CH_LS_STEP_ALL 32u
 #define CH_DENSE_TAIL_OFF 1u
@@ -204,7 +209,9 @@ typedef struct {
                                 * result back; same results) */
 
 #define CH_MLP_ON_DEVICE 0x1u     /* x, t, y, prio are device pointers */
-#define CH_MLP_BF16 0x2u          /* forward with bf16 weights and activations */
+#define CH_MLP_BF16 0x2u          /* bf16 weights, inputs, activations and deltas on the
+                                   * matrix cores, fp32 accumulation (forward, gradient,
+                                   * training) */
 
 typedef struct {
   uint32_t batch;  /* samples per step (<= 2^20), drawn with replacement */
@@ -422,16 +429,19 @@ int ch_mlp_forward(const float *x, uint64_t n, const float *w, float *y, int32_t
 
 /* Gradient of the mean squared error (1/n) sum (f(x_i) - t_i)^2 over all n
  * samples with respect to the weights: grad (CH_MLP_PARAMS host floats),
- * loss (host float, may be NULL).  Sums run in sample order (deterministic).
+ * loss (host float, may be NULL).  fp32: sums run in sample order; with
+ * CH_MLP_BF16 each wave sums its 32-sample tiles on the matrix cores and the
+ * waves' sums are added in wave order; deterministic either way.
  * x (n*8), t (n): host, or device with CH_MLP_ON_DEVICE; w host. */
 int ch_mlp_grad(const float *x, const float *t, uint32_t n, const float *w, float *grad,
                 float *loss, uint32_t flags, void *stream);
 
 /* Adam on the mean squared error, minibatches drawn with replacement by a
  * counter-based generator (splitmix64 of seed and sample counter).  w (host,
- * CH_MLP_PARAMS) holds the initial weights and receives the trained ones;
- * losses (host, p->steps floats, may be NULL) receives each step's batch
- * loss.  Deterministic for given inputs. */
+ * CH_MLP_PARAMS) holds the initial weights and receives the trained ones
+ * (fp32 master weights and Adam state; CH_MLP_BF16 computes each step's
+ * gradient in bf16 as ch_mlp_grad does); losses (host, p->steps floats, may
+ * be NULL) receives each step's batch loss.  Deterministic for given inputs. */
 int ch_mlp_train(const float *x, const float *t, uint64_t n, float *w,
                  const ch_mlp_train_params_t *p, float *losses, uint32_t flags, void *stream);
 

@@ -64,7 +64,7 @@ class _Params(C.Structure):
                 ("settle_limit", C.c_uint32), ("max_rounds", C.c_uint32),
                 ("priority", C.c_uint32), ("record", C.c_uint32), ("mlp", C.c_void_p),
                 ("k_ed", C.c_int32), ("k_cn", C.c_int32), ("k_depth", C.c_int32),
-                ("tiebreak", C.c_uint32)]
+                ("tiebreak", C.c_uint32), ("mlp_qbits", C.c_uint32)]
 
 
 TIE_HASHED_ID = 0
@@ -136,6 +136,8 @@ def lib():
         L.orc_get_features.restype = i32
         L.orc_mlp_priority.argtypes = [vp, vp, C.POINTER(C.c_float)]
         L.orc_mlp_priority.restype = C.c_int32
+        L.orc_mlp_priority_q.argtypes = [vp, vp, C.c_uint32, C.POINTER(C.c_float)]
+        L.orc_mlp_priority_q.restype = C.c_int32
         L.orc_gelu.argtypes = [C.c_float]
         L.orc_gelu.restype = C.c_float
         L.orc_load.argtypes = [u32, vp, u64, vp, vp, vp, u64, vp, vp, vp, C.POINTER(vp)]
@@ -157,7 +159,7 @@ class OracleCH:
 
     def __init__(self, off, dst, w, labels=None, seed=0, wps_mode=WPS_EXACT,
                  hop_limit=2, settle_limit=64, max_rounds=0, mlp=None, record=False,
-                 k_ed=1, k_cn=0, k_depth=0, tiebreak=TIE_HASHED_ID):
+                 k_ed=1, k_cn=0, k_depth=0, tiebreak=TIE_HASHED_ID, mlp_qbits=0):
         L = lib()
         off, dst, w = _csr(off, dst, w)
         n = len(off) - 1
@@ -168,7 +170,7 @@ class OracleCH:
             raise ValueError("mlp must hold 4801 weights")
         p = _Params(wps_mode, hop_limit, settle_limit, max_rounds,
                     PRIO_LEARNED if wts is not None else PRIO_PLAIN, int(record), _p(wts),
-                    k_ed, k_cn, k_depth, tiebreak)
+                    k_ed, k_cn, k_depth, tiebreak, mlp_qbits)
         h = C.c_void_p()
         rc = L.orc_create(n, len(dst), _p(off), _p(dst), _p(w), _p(lab), seed,
                           C.byref(p), C.byref(h))
@@ -333,12 +335,13 @@ def dijkstra_settle(off, dst, w, s, max_settled):
     return d, c.value
 
 
-def mlp_priority(w, x):
-    """(priority, output y) of the learned priority for one feature vector."""
+def mlp_priority(w, x, qbits=16):
+    """(priority, output y) of the learned priority for one feature vector,
+    the output quantised to qbits fractional bits."""
     w = np.ascontiguousarray(w, np.float32)
     x = np.ascontiguousarray(x, np.float32)
     y = C.c_float()
-    p = lib().orc_mlp_priority(_p(w), _p(x), C.byref(y))
+    p = lib().orc_mlp_priority_q(_p(w), _p(x), int(qbits), C.byref(y))
     return p, y.value
 
 

@@ -383,6 +383,7 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
     return ORC_E_INVALID;
   if (p->tiebreak > ORC_TIE_RAW_ID || (p->tiebreak == ORC_TIE_RAW_ID && labels))
     return ORC_E_INVALID;
+  if (p->mlp_qbits > 24) return ORC_E_INVALID;
   if (n > 0 && (off[0] != 0 || off[n] != m)) return ORC_E_INVALID;
   for (uint32_t v = 0; v < n; v++)
     if (off[v] > off[v + 1]) return ORC_E_INVALID;
@@ -393,6 +394,7 @@ int orc_create(uint32_t n, uint64_t m, const uint64_t *off, const uint32_t *dst,
   if (!st) return ORC_E_OOM;
   st->n = n;
   st->p = *p;
+  if (!st->p.mlp_qbits) st->p.mlp_qbits = 16;
   size_t nn = n ? n : 1;
   st->label = (uint32_t *)malloc(nn * sizeof(uint32_t));
   st->out = (adj_t *)calloc(nn, sizeof(adj_t));
@@ -754,6 +756,10 @@ float orc_gelu(float x) {
 }
 
 int32_t orc_mlp_priority(const float *w, const float *x, float *y_out) {
+  return orc_mlp_priority_q(w, x, 16, y_out);
+}
+
+int32_t orc_mlp_priority_q(const float *w, const float *x, uint32_t qbits, float *y_out) {
   const float *W1 = w, *b1 = w + 512, *W2 = w + 576, *b2 = w + 4672, *W3 = w + 4736,
               *b3 = w + 4800;
   float a1[64], a2[64];
@@ -770,7 +776,7 @@ int32_t orc_mlp_priority(const float *w, const float *x, float *y_out) {
   float y = b3[0];
   for (int i = 0; i < 64; i++) y = y + W3[i] * a2[i];
   if (y_out) *y_out = y;
-  float z = y * 65536.0f;
+  float z = y * (float)(1u << qbits); /* a power of two: exact */
   if (!(z < 2147483648.0f)) return INT32_MAX; /* also NaN */
   if (z < -2147483648.0f) return INT32_MIN;
   return (int32_t)rintf(z);
@@ -832,7 +838,7 @@ static void score(orc_state *st, orc_round_stats *rs) {
     if (comb < INT32_MIN) comb = INT32_MIN;
     float *f = &st->feat[(size_t)u * 8];
     vertex_features(st, u, (int32_t)p, li->n, lo->n, nb, pairs, f);
-    st->P[u] = st->mlp ? orc_mlp_priority(st->mlp, f, NULL) : (int32_t)comb;
+    st->P[u] = st->mlp ? orc_mlp_priority_q(st->mlp, f, st->p.mlp_qbits, NULL) : (int32_t)comb;
   }
 }
 

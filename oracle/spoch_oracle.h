@@ -71,6 +71,10 @@ typedef struct {
    * depth of a contracted neighbour).  1, 0, 0 is the pure edge difference. */
   int32_t k_ed, k_cn, k_depth;
   uint32_t tiebreak;     /* ORC_TIE_*; ORC_TIE_RAW_ID needs labels == NULL */
+  /* learned priority: P = rint(y * 2^mlp_qbits) of the network output y,
+   * saturated to int32 (0 means 16; at most 24).  Fewer bits make more
+   * equal priorities, broken by label in Select. */
+  uint32_t mlp_qbits;
 } orc_params;
 
 typedef struct orc_state orc_state;
@@ -123,6 +127,8 @@ void orc_get_vertex_state(const orc_state *st, uint32_t *level, int32_t *pc,
 int orc_get_features(const orc_state *st, float *x);
 /* MLP helpers: the features -> priority map used by the learned priority. */
 int32_t orc_mlp_priority(const float *w, const float *x, float *y_out);
+/* The same with the output quantised to qbits fractional bits (1 .. 24). */
+int32_t orc_mlp_priority_q(const float *w, const float *x, uint32_t qbits, float *y_out);
 float orc_gelu(float x);
 /* rank[v] after orc_finish. */
 int orc_get_rank(const orc_state *st, uint32_t *rank);

@@ -59,7 +59,7 @@ class Params(C.Structure):
                 ("hop_limit", C.c_uint32), ("dense_tail", C.c_uint32),
                 ("k_ed", C.c_int32), ("k_cn", C.c_int32), ("k_depth", C.c_int32),
                 ("tiebreak", C.c_uint32), ("settle_limit", C.c_uint32),
-                ("ls_step", C.c_uint32)]
+                ("ls_step", C.c_uint32), ("mlp_qbits", C.c_uint32)]
 
 
 CH_PRIO_PLAIN, CH_PRIO_LEARNED = 0, 1
@@ -345,7 +345,7 @@ class CH:
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
           record=False, hop=0, dense_tail=0, tail_stepwise=False, keep_order=False,
-          score_weights=None, raw_id=False, settle=0, ls_step=0):
+          score_weights=None, raw_id=False, settle=0, ls_step=0, mlp_qbits=0):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
     selects the hop-bounded witness search with walks of at most `hop` arcs;
     tail_stepwise runs the table rounds one launch per step; keep_order
@@ -353,7 +353,8 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     = (k_ed, k_cn, k_depth) sets the integer score weights; raw_id labels
     every vertex by its id; settle > 0 selects the settled(theta) witness
     search with theta = settle; ls_step: distance-bucket width D_s >> ls_step
-    of exact-mode search steps (0 = default, 32 = whole frontier)."""
+    of exact-mode search steps (0 = default, 32 = whole frontier); mlp_qbits:
+    fractional bits of the learned priority (0 = 16)."""
     dev = _is_torch_cuda(off)
     po, ko = _ptr(off, np.uint64)
     pd, kd = _ptr(dst, np.uint32)
@@ -379,7 +380,7 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
                ls_sparse, ls_dense, dense_deg10,
                CH_PRIO_LEARNED if wts is not None else CH_PRIO_PLAIN,
                None if wts is None else wts.ctypes.data, hop, dense_tail, k_ed, k_cn, k_depth,
-               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID, settle, ls_step)
+               CH_TIE_RAW_ID if raw_id else CH_TIE_HASHED_ID, settle, ls_step, mlp_qbits)
     h = C.c_void_p()
     _check(lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     return CH(h)
@@ -439,27 +440,31 @@ def mlp_forward(x, w, bf16=False, stream=None):
     return y, p
 
 
-def mlp_grad(x, t, w):
-    """(gradient, loss) of the mean squared error over all samples."""
+def mlp_grad(x, t, w, bf16=False):
+    """(gradient, loss) of the mean squared error over all samples (bf16:
+    on the matrix cores with bf16 operands)."""
     x = np.ascontiguousarray(x, np.float32).reshape(-1, 8)
     t = np.ascontiguousarray(t, np.float32)
     w = np.ascontiguousarray(w, np.float32)
     g = np.empty(CH_MLP_PARAMS, np.float32)
     loss = C.c_float()
     _check(lib().ch_mlp_grad(x.ctypes.data, t.ctypes.data, len(x), w.ctypes.data, g.ctypes.data,
-                             C.byref(loss), 0, None), "ch_mlp_grad")
+                             C.byref(loss), CH_MLP_BF16 if bf16 else 0, None), "ch_mlp_grad")
     return g, loss.value
 
 
-def mlp_train(x, t, w, batch=1024, steps=500, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0):
-    """Adam on the GPU; returns (trained weights, per-step batch losses)."""
+def mlp_train(x, t, w, batch=1024, steps=500, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, seed=0,
+              bf16=False):
+    """Adam on the GPU; returns (trained weights, per-step batch losses);
+    bf16: gradients on the matrix cores with bf16 operands."""
     x = np.ascontiguousarray(x, np.float32).reshape(-1, 8)
     t = np.ascontiguousarray(t, np.float32)
     w = np.array(w, np.float32, copy=True)
     losses = np.empty(steps, np.float32)
     p = MlpTrainParams(batch, steps, lr, beta1, beta2, eps, seed)
     _check(lib().ch_mlp_train(x.ctypes.data, t.ctypes.data, len(x), w.ctypes.data, C.byref(p),
-                              losses.ctypes.data, 0, None), "ch_mlp_train")
+                              losses.ctypes.data, CH_MLP_BF16 if bf16 else 0, None),
+           "ch_mlp_train")
     return w, losses
 
 

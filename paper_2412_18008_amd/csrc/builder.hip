@@ -1023,7 +1023,7 @@ struct Builder {
           if (prm.priority == CH_PRIO_LEARNED)
             HIP_TRY(launch_mlp_priority(va.as<uint32_t>(), na, O.gid.as<uint32_t>(),
                                         f_feat.as<float>(), mlpw.as<float>(), O.P.as<int32_t>(),
-                                        cus, st));
+                                        prm.mlp_qbits, cus, st));
         }
         // ---- Step 3: Select (Alg. 6) -----------------------------------
         k_keys<<<grid(O.n), 256, 0, st>>>(O.n, O.P.as<int32_t>(), O.gid.as<uint32_t>(),
@@ -1280,6 +1280,8 @@ static int check_params(const ch_params_t *p, ch_params_t &prm) {
   if (prm.wps_mode == CH_WPS_SETTLED && prm.settle_limit < 1)
     return set_error(CH_E_INVALID, "settled mode needs settle_limit >= 1");
   if (prm.ls_step > CH_LS_STEP_ALL) return set_error(CH_E_INVALID, "ls_step must be at most 32");
+  if (prm.mlp_qbits > 24) return set_error(CH_E_INVALID, "mlp_qbits must be at most 24");
+  if (!prm.mlp_qbits) prm.mlp_qbits = 16;
   if (prm.dense_tail > kTabMaxN)
     return set_error(CH_E_INVALID, "dense_tail must be at most 4096");
   if (prm.group && prm.group != 4 && prm.group != 8 && prm.group != 16 && prm.group != 32 &&

@@ -1,7 +1,8 @@
 // mlp.hip -- the learned priority's network on gfx950: an MLP 8 -> 64 -> 64
 // -> 1 with GELU, its use inside the build (features -> int32 priority), a
-// standalone forward (fp32, or bf16 weights and activations with fp32
-// accumulation), and deterministic training kernels (MSE, Adam).
+// standalone forward (fp32, or bf16 on the matrix cores: mlp_mfma.hpp), and
+// deterministic training kernels (MSE, Adam; fp32 per sample, or bf16 on the
+// matrix cores).
 //
 // GELU(x) = x/2 * (1 + T(0.7978845608 * (x + 0.044715 x^3))) with T the [7/6]
 // Pade approximant of tanh (Lambert's continued fraction), +-1 for
@@ -92,12 +93,19 @@ __device__ __forceinline__ float mlp_forward(const float *__restrict__ w, const 
   return y;
 }
 
-__device__ __forceinline__ int32_t priority_of(float y) {
-  const float z = y * 65536.0f;
+// rint(y * scale), saturated; scale = 2^qbits (exact).
+__device__ __forceinline__ int32_t priority_of(float y, float scale = 65536.0f) {
+  const float z = y * scale;
   if (!(z < 2147483648.0f)) return INT32_MAX;  // also NaN
   if (z < -2147483648.0f) return INT32_MIN;
   return (int32_t)rintf(z);
 }
+
+}  // namespace sp
+
+#include "mlp_mfma.hpp"
+
+namespace sp {
 
 // Weights staged in LDS by every block (4801 floats).
 __device__ __forceinline__ void stage_weights(const float *__restrict__ w, float *s, bool bf16) {
@@ -110,7 +118,7 @@ __global__ void __launch_bounds__(256) k_mlp_priority(const uint32_t *__restrict
                                                       const uint32_t *__restrict__ gid,
                                                       const float *__restrict__ feat,
                                                       const float *__restrict__ w,
-                                                      int32_t *__restrict__ P) {
+                                                      int32_t *__restrict__ P, float scale) {
   __shared__ float sw[kMlpParams];
   stage_weights(w, sw, false);
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -119,7 +127,7 @@ __global__ void __launch_bounds__(256) k_mlp_priority(const uint32_t *__restrict
     const float *f = feat + (size_t)gid[u] * 8;
     float x[8];
     for (int i = 0; i < 8; i++) x[i] = f[i];
-    P[u] = priority_of(mlp_forward<false>(sw, x));
+    P[u] = priority_of(mlp_forward<false>(sw, x), scale);
   }
 }
 
@@ -259,11 +267,11 @@ __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float
   } while (0)
 
 hipError_t launch_mlp_priority(const uint32_t *va, uint32_t na, const uint32_t *gid,
-                               const float *feat, const float *w, int32_t *P, int cus,
-                               hipStream_t st) {
+                               const float *feat, const float *w, int32_t *P, uint32_t qbits,
+                               int cus, hipStream_t st) {
   if (!na) return hipSuccess;
   const unsigned g = (unsigned)std::min<uint64_t>((na + 255) / 256, (uint64_t)cus * 4);
-  k_mlp_priority<<<g, 256, 0, st>>>(va, na, gid, feat, w, P);
+  k_mlp_priority<<<g, 256, 0, st>>>(va, na, gid, feat, w, P, (float)(1u << qbits));
   return hipGetLastError();
 }
 
@@ -294,8 +302,14 @@ int mlp_forward(const float *x, uint64_t n, const float *w, float *y, int32_t *p
       pp = dp.as<int32_t>();
     }
   }
-  if (bf16) k_mlp_forward<true><<<blocks_for(n), 256, 0, st>>>(px, n, dw.as<float>(), py, pp);
-  else k_mlp_forward<false><<<blocks_for(n), 256, 0, st>>>(px, n, dw.as<float>(), py, pp);
+  if (bf16) {
+    const uint64_t steps = (n + kMfmaRows - 1) / kMfmaRows;
+    const unsigned g = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>((steps + kMfmaWaves - 1) / kMfmaWaves, 2048));
+    k_mlp_forward_mfma<<<g, 64 * kMfmaWaves, 0, st>>>(px, n, dw.as<float>(), py, pp);
+  } else {
+    k_mlp_forward<false><<<blocks_for(n), 256, 0, st>>>(px, n, dw.as<float>(), py, pp);
+  }
   HIP_TRY(hipGetLastError());
   if (!dev) {
     if (y) HIP_TRY(hipMemcpyAsync(y, py, n * 4, hipMemcpyDeviceToHost, st));
@@ -309,10 +323,13 @@ int mlp_forward(const float *x, uint64_t n, const float *w, float *y, int32_t *p
 
 // Shared by mlp_grad and mlp_train: device copies of the data and scratch.
 struct TrainCtx {
-  DBuf X, T, W, G, M, V, idx, loss, xb, h1, a1, h2, a2, d1, d2, dy, err;
+  DBuf X, T, W, G, M, V, idx, loss, xb, h1, a1, h2, a2, d1, d2, dy, err, part, lossp;
   TrainScratch s{};
+  bool bf16 = false;
+  uint32_t mblocks = 0;  // blocks of the bf16 gradient kernel
   ~TrainCtx() {
-    DBuf *all[] = {&X, &T, &W, &G, &M, &V, &idx, &loss, &xb, &h1, &a1, &h2, &a2, &d1, &d2, &dy, &err};
+    DBuf *all[] = {&X, &T, &W, &G, &M, &V, &idx, &loss, &xb, &h1, &a1, &h2, &a2, &d1, &d2, &dy,
+                   &err, &part, &lossp};
     for (DBuf *b : all) b->release();
   }
   int setup(const float *x, const float *t, uint64_t n, const float *w, uint32_t B, bool dev,
@@ -330,6 +347,13 @@ struct TrainCtx {
     HIP_TRY(hipMemsetAsync(V.p, 0, kMlpParams * 4, st));
     HIP_TRY(idx.ensure((size_t)B * 4));
     HIP_TRY(loss.ensure(4));
+    if (bf16) {  // per-wave gradient sums instead of per-sample scratch
+      const uint32_t steps = (B + kMfmaRows - 1) / kMfmaRows;
+      mblocks = std::max<uint32_t>(1, std::min<uint32_t>((steps + kMfmaWaves - 1) / kMfmaWaves, 256));
+      HIP_TRY(part.ensure((size_t)mblocks * kMfmaWaves * kMlpParams * 4));
+      HIP_TRY(lossp.ensure((size_t)mblocks * kMfmaWaves * 4));
+      return CH_OK;
+    }
     HIP_TRY(xb.ensure((size_t)B * 32));
     DBuf *q[] = {&h1, &a1, &h2, &a2, &d1, &d2};
     for (DBuf *b : q) HIP_TRY(b->ensure((size_t)B * 256));
@@ -343,6 +367,15 @@ struct TrainCtx {
   hipError_t batch_grad(uint64_t n, uint32_t B, uint64_t seed, uint64_t step, bool full,
                         hipStream_t st) {
     k_batch_index<<<blocks_for(B), 256, 0, st>>>(n, B, seed, step, idx.as<uint32_t>(), full);
+    if (bf16) {
+      k_mlp_grad_mfma<<<mblocks, 64 * kMfmaWaves, 0, st>>>(X.as<float>(), T.as<float>(),
+                                                            idx.as<uint32_t>(), B, W.as<float>(),
+                                                            part.as<float>(), lossp.as<float>());
+      k_mlp_grad_reduce<<<(kMlpParams + 256) / 256, 256, 0, st>>>(
+          mblocks * kMfmaWaves, B, part.as<float>(), lossp.as<float>(), G.as<float>(),
+          loss.as<float>());
+      return hipGetLastError();
+    }
     k_mlp_fwdbwd<<<blocks_for(B), 256, 0, st>>>(X.as<float>(), T.as<float>(), idx.as<uint32_t>(),
                                                   B, W.as<float>(), s);
     k_mlp_param_grad<<<(kMlpParams + 255) / 256, 256, 0, st>>>(B, s, G.as<float>());
@@ -355,6 +388,7 @@ int mlp_grad(const float *x, const float *t, uint32_t n, const float *w, float *
              uint32_t flags, hipStream_t st) {
   if (!n) return set_error(CH_E_INVALID, "n must be positive");
   TrainCtx c;
+  c.bf16 = flags & CH_MLP_BF16;
   int rc = c.setup(x, t, n, w, n, flags & CH_MLP_ON_DEVICE, st);
   if (rc) return rc;
   HIP_TRY(c.batch_grad(n, n, 0, 0, true, st));
@@ -369,6 +403,7 @@ int mlp_train(const float *x, const float *t, uint64_t n, float *w,
   if (!n || !p || !p->batch || p->batch > (1u << 20))
     return set_error(CH_E_INVALID, "need n > 0 and 0 < batch <= 2^20");
   TrainCtx c;
+  c.bf16 = flags & CH_MLP_BF16;
   int rc = c.setup(x, t, n, w, p->batch, flags & CH_MLP_ON_DEVICE, st);
   if (rc) return rc;
   double c1 = 1.0, c2 = 1.0;

@@ -12,8 +12,8 @@ constexpr int kMlpParams = CH_MLP_PARAMS;
 
 // P[u] for every u in va from feat[gid[u]] (8 floats) and weights w (device).
 hipError_t launch_mlp_priority(const uint32_t *va, uint32_t na, const uint32_t *gid,
-                               const float *feat, const float *w, int32_t *P, int cus,
-                               hipStream_t st);
+                               const float *feat, const float *w, int32_t *P, uint32_t qbits,
+                               int cus, hipStream_t st);
 
 int mlp_forward(const float *x, uint64_t n, const float *w, float *y, int32_t *prio,
                 uint32_t flags, hipStream_t st);

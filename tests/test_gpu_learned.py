@@ -6,9 +6,12 @@
 * the GPU gradient (deterministic sums) matches the fp64 reference;
 * a learned build equals the oracle's learned build bit for bit (same
   features, same priorities, same CH), and recorded features are identical;
-* training lowers the loss, and the trained network's CH answers every
-  sampled query exactly; its shortcut count and query cost are reported
-  beside the plain method's and an untrained network's."""
+* the bf16 gradient on the matrix cores is within 2e-2 of the fp64
+  reference, and bf16 training is deterministic and lowers the loss;
+* training (fp32 and bf16) lowers the loss, and the trained network's CH
+  answers every sampled query exactly; its shortcut count, rounds and
+  vertices settled per query are reported against the plain method's (the
+  judge of the learned priority), and it must beat an untrained network."""
 import numpy as np
 import pytest
 
@@ -75,10 +78,52 @@ def test_gradient_matches_reference(gpu):
     assert np.array_equal(g, g2)  # deterministic
 
 
-def _learned_case(gpu, name, off, dst, w, lab, weights):
+def test_bf16_gradient_matches_reference(gpu):
+    # bf16 operands on the matrix cores, fp32 sums: within 2e-2 of the fp64
+    # gradient (norm and largest entry), the loss likewise; deterministic;
+    # batches that are not a multiple of the 32-sample tile, and large ones
+    # spread over many waves
+    from paper_2412_18008_amd import learned
+
+    rng = np.random.default_rng(4)
+    for k, wseed in ((777, 3), (33, 4), (20_000, 5)):
+        w = learned.init_weights(wseed) + np.float32(0.05) * rng.standard_normal(4801).astype(
+            np.float32)
+        x = _features(rng, k)
+        t = rng.random(k).astype(np.float32)
+        g, loss = gpu.mlp_grad(x, t, w, bf16=True)
+        gr = ref.grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+        lr = ref.loss(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+        assert abs(loss - lr) <= 2e-2 * max(1.0, lr), k
+        assert np.linalg.norm(g - gr) <= 2e-2 * np.linalg.norm(gr), k
+        assert np.max(np.abs(g - gr)) <= 2e-2 * np.max(np.abs(gr)), k
+        # every block of the weight vector (W1, b1, W2, b2, W3, b3) is within
+        # the bound on its own, so a dropped or misplaced term shows
+        for a, b in ((0, 512), (512, 576), (576, 4672), (4672, 4736), (4736, 4800),
+                     (4800, 4801)):
+            assert np.linalg.norm(g[a:b] - gr[a:b]) <= 3e-2 * np.linalg.norm(gr[a:b]) + 1e-6, (k, a)
+        g2, _ = gpu.mlp_grad(x, t, w, bf16=True)
+        assert np.array_equal(g, g2), k
+
+
+def test_bf16_training_lowers_loss(gpu):
+    from paper_2412_18008_amd import learned
+
+    rng = np.random.default_rng(6)
+    x = _features(rng, 30_000)
+    t = (0.5 * x[:, 0] + 0.3 * x[:, 2] * x[:, 3]).astype(np.float32)
+    w, losses = gpu.mlp_train(x, t, learned.init_weights(1), batch=2048, steps=300, lr=3e-3,
+                              bf16=True)
+    assert np.mean(losses[-20:]) < 0.2 * np.mean(losses[:20])
+    w2, losses2 = gpu.mlp_train(x, t, learned.init_weights(1), batch=2048, steps=300, lr=3e-3,
+                                bf16=True)
+    assert np.array_equal(w, w2) and np.array_equal(losses, losses2)
+
+
+def _learned_case(gpu, name, off, dst, w, lab, weights, qbits=0):
     print(f"[learned] {name} n={len(off) - 1}", flush=True)
-    o = oracle.OracleCH(off, dst, w, labels=lab, mlp=weights).run()
-    ch = gpu.build(off, dst, w, labels=lab, mlp=weights, stats=True)
+    o = oracle.OracleCH(off, dst, w, labels=lab, mlp=weights, mlp_qbits=qbits).run()
+    ch = gpu.build(off, dst, w, labels=lab, mlp=weights, stats=True, mlp_qbits=qbits)
     assert_same_ch(oracle_export(o), gpu_export(ch), name)
     assert gpu_round_counts(ch) == oracle_round_counts(o), name
     return o, ch
@@ -90,11 +135,12 @@ def test_learned_build_bit_exact(gpu):
     cases = [("road3k", *synth.road_like(3000, seed=1)), ("grid", *synth.grid(12, 15, seed=2)),
              ("digraph", *synth.random_digraph(80, 320, seed=3, wmax=9, zero_frac=0.1)),
              ("road20k", *synth.road_like(20_000, seed=4))]
-    for wseed in (0, 5):
+    for wseed, qbits in ((0, 0), (5, 0), (5, 3)):
         weights = learned.init_weights(wseed)
         for name, off, dst, w in cases:
             n = len(off) - 1
-            _learned_case(gpu, f"{name}/w{wseed}", off, dst, w, synth.labels(n, 7), weights)
+            _learned_case(gpu, f"{name}/w{wseed}/q{qbits}", off, dst, w, synth.labels(n, 7),
+                          weights, qbits)
 
 
 def test_recorded_features_bit_exact(gpu):
@@ -107,15 +153,25 @@ def test_recorded_features_bit_exact(gpu):
 
 
 def test_training_and_gain(gpu):
+    # Train (fp32, and bf16 on the matrix cores) on plain builds, then build
+    # one unseen graph with the plain priority, an untrained network and the
+    # trained ones.  Every CH answers every sampled query exactly.  The
+    # comparison with the plain method, the judge of the learned priority, is
+    # reported in full (shortcuts, rounds, vertices settled per query by the
+    # oracle's CH query); the trained network must beat the untrained one.
     from paper_2412_18008_amd import learned
 
     graphs = list(learned.training_graphs(6, nmin=4000, nmax=20000))
     X, t = learned.record(graphs)
     assert X.shape[1] == 8 and len(X) == len(t) == sum(len(g[0]) - 1 for g in graphs)
-    w_trained, losses = learned.train(X, t, steps=400, batch=2048, lr=3e-3)
-    head, tail = float(np.mean(losses[:20])), float(np.mean(losses[-20:]))
-    print(f"[learned] loss {head:.4f} -> {tail:.4f}", flush=True)
-    assert tail < 0.5 * head
+    trained = {}
+    for bf16 in (False, True):
+        w_tr, losses = gpu.mlp_train(X, t, learned.init_weights(0), batch=2048, steps=400,
+                                     lr=3e-3, bf16=bf16)
+        head, tail = float(np.mean(losses[:20])), float(np.mean(losses[-20:]))
+        print(f"[learned] {'bf16' if bf16 else 'fp32'} loss {head:.4f} -> {tail:.4f}", flush=True)
+        assert tail < 0.5 * head
+        trained["trained_bf16" if bf16 else "trained"] = w_tr
 
     off, dst, w = synth.road_like(30_000, seed=4242)
     n = len(off) - 1
@@ -123,7 +179,7 @@ def test_training_and_gain(gpu):
     ref_d = reference_distances(off, dst, w, s[:40], tq[:40])
     report = {}
     for tag, weights in (("plain", None), ("untrained", learned.init_weights(77)),
-                         ("trained", w_trained)):
+                         *trained.items()):
         ch = gpu.build(off, dst, w, mlp=weights)
         d = ch.query(s, tq)
         assert np.array_equal(d[:40], ref_d), tag  # zero distance error
@@ -132,10 +188,13 @@ def test_training_and_gain(gpu):
                             e["down_head"], e["down_w"])
         od, settled = L.query_batch(s, tq)
         assert np.array_equal(od, d), tag
-        report[tag] = dict(shortcuts=ch.summary["shortcuts"],
-                           ch_arcs=ch.summary["up_arcs"] + ch.summary["down_arcs"],
+        report[tag] = dict(shortcuts=int(ch.summary["shortcuts"]), rounds=int(ch.summary["rounds"]),
                            settled=float(settled.mean()))
-    print(f"[learned] gain report: {report}", flush=True)
-    # the trained network must order contraction far better than an untrained one
-    assert report["trained"]["shortcuts"] < report["untrained"]["shortcuts"]
-    assert report["trained"]["settled"] < report["untrained"]["settled"]
+    for tag in ("untrained", "trained", "trained_bf16"):
+        p = report["plain"]
+        report[tag]["vs_plain"] = {k: report[tag][k] / p[k] for k in ("shortcuts", "rounds",
+                                                                       "settled")}
+    print(f"[learned] trained vs plain: {report}", flush=True)
+    for tag in ("trained", "trained_bf16"):
+        assert report[tag]["shortcuts"] < report["untrained"]["shortcuts"], tag
+        assert report[tag]["settled"] < report["untrained"]["settled"], tag

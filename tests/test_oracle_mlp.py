@@ -2,8 +2,11 @@
 * the numpy backward equals central finite differences (fp64);
 * GELU through the Pade tanh is within 1e-4 of the erf-form GELU (so it is
   a GELU), and the C oracle's single-precision GELU and MLP priority equal
-  the fp64 reference within float rounding;
-* the learned oracle build preserves every pairwise distance."""
+  the fp64 reference within float rounding, and the quantised priority is
+  rint(y * 2^q) of the same output;
+* the learned oracle build preserves every pairwise distance (several
+  quantisations), and with a constant network Select takes exactly the
+  label-local minima."""
 import math
 
 import numpy as np
@@ -51,14 +54,19 @@ def test_c_single_precision_matches_reference():
         p, y = oracle.mlp_priority(w, X[i])
         assert abs(y - y_ref[i]) <= 1e-4 * (1 + abs(y_ref[i]))
         assert p == int(np.clip(np.rint(np.float32(y) * np.float32(65536)), -2**31, 2**31 - 1))
+        for q in (1, 3, 8, 24):  # quantised output: rint(y * 2^q), the same y
+            pq, yq = oracle.mlp_priority(w, X[i], q)
+            assert yq == y
+            assert pq == int(np.clip(np.rint(np.float64(y) * 2.0 ** q), -2**31, 2**31 - 1))
 
 
 def test_learned_build_preserves_distances(oracle_lib):
     w = mlp.init(11).astype(np.float32)
-    for name, (off, dst, w_) in small_graphs()[:10]:
+    for (name, (off, dst, w_)), q in zip(small_graphs()[:10], (0, 2, 0, 4, 0, 1, 0, 8, 0, 2)):
         n = len(off) - 1
         D = graph_closure(off, dst, w_)
-        o = oracle.OracleCH(off, dst, w_, labels=synth.labels(n, 1), mlp=w, record=True).run()
+        o = oracle.OracleCH(off, dst, w_, labels=synth.labels(n, 1), mlp=w, record=True,
+                            mlp_qbits=q).run()
         s = np.repeat(np.arange(n, dtype=np.uint32), n)
         t = np.tile(np.arange(n, dtype=np.uint32), n)
         d, _ = o.query_batch(s, t)
@@ -66,3 +74,28 @@ def test_learned_build_preserves_distances(oracle_lib):
         assert np.array_equal(d, exp), name
         f = o.features()
         assert np.all(np.isfinite(f)) and np.all(np.abs(f) < 1.0)
+
+
+def test_quantised_priority_ties_follow_labels(oracle_lib):
+    # a network whose output is 0.3 for every input: with 1 fractional bit
+    # every priority is rint(0.6) = 1, so Select takes the local minima of the
+    # labels alone; with 16 bits too (all equal); the round-0 selection must
+    # then be exactly the vertices whose label is below every neighbour's
+    w = np.zeros(4801, np.float32)
+    w[4800] = np.float32(0.3)
+    off, dst, w_ = synth.grid(6, 7, seed=4)
+    n = len(off) - 1
+    lab = synth.labels(n, 2)
+    nb = [set() for _ in range(n)]
+    for u in range(n):
+        for e in range(off[u], off[u + 1]):
+            if dst[e] != u:
+                nb[u].add(int(dst[e]))
+                nb[int(dst[e])].add(u)
+    expect = sum(1 for u in range(n) if all(lab[u] < lab[v] for v in nb[u]))
+    for q in (1, 16):
+        o = oracle.OracleCH(off, dst, w_, labels=lab, mlp=w, mlp_qbits=q)
+        o.round()
+        assert o.round_stats()[0]["n_selected"] == expect, q
+    with pytest.raises(oracle.OracleError):
+        oracle.OracleCH(off, dst, w_, mlp=w, mlp_qbits=25)
