@@ -147,7 +147,7 @@ def cpu_baseline(workload, settle=0):
 MLP_FLOP_PER_ROW = 2 * (8 * 64 + 64 * 64 + 64)  # multiply-adds of the three layers
 
 
-def mlp_throughput(binding, w_host, dev, rows=1 << 20, reps=20):
+def mlp_throughput(binding, w_host, dev, rows=1 << 24, reps=5):
     """GFLOP/s of the learned priority's forward kernel (fp32 and bf16) on
     `rows` device-resident feature vectors, timed with HIP events."""
     import numpy as np
@@ -167,45 +167,66 @@ def mlp_throughput(binding, w_host, dev, rows=1 << 20, reps=20):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        out[tag] = {"ms_per_launch": ms, "rows": rows,
-                    "gflop_s": rows * MLP_FLOP_PER_ROW / (ms / 1e3) / 1e9}
+        gf = rows * MLP_FLOP_PER_ROW / (ms / 1e3) / 1e9
+        peak = 2.5e6 if bf16 else 157.3e3  # GFLOP/s: bf16 MFMA dense, fp32 vector
+        out[tag] = {"ms_per_launch": ms, "rows": rows, "gflop_s": gf,
+                    "peak_gflop_s": peak, "frac_of_peak": gf / peak}
+    # training: 100 Adam steps of 4096 samples (forward, backward, gradient
+    # sums, update), host-timed around the whole call
+    xt = np.random.default_rng(3).random((1 << 18, 8)).astype(np.float32)
+    tt = xt[:, 0].copy()
+    for tag, bf16 in (("fp32", False), ("bf16", True)):
+        binding.mlp_train(xt, tt, np.asarray(w_host, np.float32), batch=4096, steps=5, bf16=bf16)
+        t0 = time.perf_counter()
+        binding.mlp_train(xt, tt, np.asarray(w_host, np.float32), batch=4096, steps=100,
+                          bf16=bf16)
+        out[tag]["train_ms_per_step_4096"] = (time.perf_counter() - t0) * 1e3 / 100
     return out
 
 
-def plain_vs_learned(binding, args, dev):
-    """On the road-like 1M graph, priority plain vs learned: build time,
-    shortcuts, CH arcs, mean vertices visited per query (the two upward
-    search spaces, counted by the query kernel) and the number of distances
-    that differ."""
+def plain_vs_learned(binding, args, dev, workload, graph):
+    """On `workload` (device tensors off, dst, w and host queries in
+    `graph`), priority plain vs learned: build time, rounds, shortcuts, CH
+    arcs, mean vertices visited per query (the two upward search spaces,
+    counted by the query kernel), the time of a pruned 100k-query batch and
+    the number of distances that differ."""
     import numpy as np
     import torch
 
     from paper_2412_18008_amd import autotune
 
-    (off, dst, w), (qs, qt) = make_graph("road1m")
-    t_off = torch.from_numpy(off.astype(np.int64)).to(dev)
-    t_dst = torch.from_numpy(dst.astype(np.int32)).to(dev)
-    t_w = torch.from_numpy(w.astype(np.int32)).to(dev)
-    knobs = autotune.params_for(len(off) - 1, len(dst))
+    t_off, t_dst, t_w, qs, qt = graph
+    knobs = autotune.params_for(t_off.numel() - 1, t_dst.numel())
     wts = np.load(args.learned).astype(np.float32)
     nq = min(len(qs), 20_000)
-    rep = {"graph": "road-like 1M (the road1m workload)",
+    nb = min(len(qs), 100_000)
+    ts = torch.from_numpy(qs[:nb].astype(np.int32)).to(dev)
+    tt = torch.from_numpy(qt[:nb].astype(np.int32)).to(dev)
+    rep = {"graph": WORKLOADS[workload]["desc"], "workload": workload,
            "weights": os.path.basename(args.learned), "queries": nq}
     dist = {}
     for tag, mlp in (("plain", None), ("learned", wts)):
         print(f"[bench] {tag} build for the comparison", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ch = binding.build(t_off, t_dst, t_w, seed=0, mlp=mlp, **knobs)
+        ch = binding.build(t_off, t_dst, t_w, seed=0, mlp=mlp, progress=True, **knobs)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         d, vis = ch.query_stats(qs[:nq], qt[:nq])
         dist[tag] = d
+        ch.query(ts, tt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.query(ts, tt)
+        torch.cuda.synchronize()
+        qms = (time.perf_counter() - t0) * 1e3
         sm = ch.summary
         rep[tag] = {"build_s": el, "rounds": sm["rounds"], "shortcuts": sm["shortcuts"],
                     "ch_arcs": sm["up_arcs"] + sm["down_arcs"],
-                    "mean_visited_per_query": float(vis.mean())}
+                    "mean_visited_per_query": float(vis.mean()),
+                    f"query_batch_{nb}_ms": qms}
         ch.free()
+        print(f"[bench] {tag}: {rep[tag]}", file=sys.stderr, flush=True)
     rep["distance_errors"] = int(np.count_nonzero(dist["plain"] != dist["learned"]))
     rep["mlp_forward"] = mlp_throughput(binding, wts, dev)
     return rep
@@ -248,6 +269,74 @@ def committed_traffic(workload, kernel):
     if kernel not in rec:
         return None
     return float(rec[kernel])
+
+
+def query_sizes(ch, qs, qt, dev, sizes=(1, 1000, 10_000, 100_000, 1_000_000), qknobs=None):
+    """Latency and throughput of one ch_query_batch call per batch size
+    (device-resident s, t; the median of 5 calls after one warm-up call,
+    each timed from launch to completion on the host)."""
+    import numpy as np
+    import torch
+
+    out = {}
+    for k in sizes:
+        k = min(k, len(qs))
+        s = torch.from_numpy(qs[:k].astype(np.int32)).to(dev)
+        t = torch.from_numpy(qt[:k].astype(np.int32)).to(dev)
+        ch.query(s, t, **(qknobs or {}))
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            ch.query(s, t, **(qknobs or {}))
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = float(np.median(ts)) * 1e3
+        out[str(k)] = {"latency_ms": ms, "queries_per_s": k / (ms / 1e3)}
+    return out
+
+
+def hbm_probe(dev, nbytes=1 << 30, gathers=1 << 26):
+    """Practical HBM rates on this GPU: a streaming kernel (reads and writes
+    nbytes) and a scattered one (`gathers` random 8-byte reads from a 2 GiB
+    array, with their indices read and results written in order), each the
+    median of 5 runs timed with events.  The scattered kernel is also the
+    check of the counter calibration: its FETCH_SIZE per launch, scaled like
+    the search kernels', should be near its 64-byte lines touched plus the
+    index bytes."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    src = torch.arange((2 << 30) // 8, dtype=torch.int64, device=dev)
+    g = torch.Generator(device=dev).manual_seed(11)
+    idx = torch.randint(0, src.numel(), (gathers,), device=dev, generator=g)
+    out = torch.empty(gathers, dtype=torch.int64, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return sorted(ms)[2]
+
+    ms_s = timed(lambda: torch.neg(a, out=b))
+    ms_g = timed(lambda: torch.index_select(src, 0, idx, out=out))
+    stream_gbs = 2 * nbytes / (ms_s / 1e3) / 1e9
+    useful = gathers * (8 + 8 + 8)  # value, index, result
+    lines = gathers * (64 + 8 + 8)   # a 64-byte line per random read
+    return {"stream": {"bytes": 2 * nbytes, "ms": ms_s, "gbs": stream_gbs,
+                       "frac_of_peak": stream_gbs / HBM_PEAK_GBS},
+            "scattered_8B": {"gathers": gathers, "ms": ms_g,
+                             "useful_gbs": useful / (ms_g / 1e3) / 1e9,
+                             "line_gbs": lines / (ms_g / 1e3) / 1e9,
+                             "gathers_per_s": gathers / (ms_g / 1e3)}}
 
 
 def copy_calibration(dev, nbytes):
@@ -405,6 +494,10 @@ def main():
                                                       "learned_weights.npy"),
                     help="weights (.npy, 4801 float32) of the learned priority; the plain vs "
                          "learned comparison runs after the timed steps when the file exists")
+    ap.add_argument("--learned-on", default="road1m", choices=("road1m", "road24m", "none"),
+                    help="workload of the plain vs learned comparison (after the timed steps)")
+    ap.add_argument("--no-hbm-probe", action="store_true",
+                    help="skip the streaming / scattered HBM probe")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="after the steps, copy BYTES once on the device (a reference "
                          "kernel for HBM counter runs)")
@@ -555,6 +648,13 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in sorted(cands.items(),
                                                                   key=lambda x: -x[1])},
     }
+    print("[bench] query latency and throughput per batch size", file=sys.stderr, flush=True)
+    ch = binding.build(t_off, t_dst, t_w, seed=0, **knobs)
+    line["query_batch_sizes"] = query_sizes(ch, qs, qt, dev, qknobs=qknobs)
+    ch.free()
+    if not args.no_hbm_probe:
+        print("[bench] HBM probe (streaming and scattered)", file=sys.stderr, flush=True)
+        line["hbm_probe"] = hbm_probe(dev)
     if args.one_to_all:
         print(f"[bench] one-to-all from {args.one_to_all} sources", file=sys.stderr, flush=True)
         ch = binding.build(t_off, t_dst, t_w, seed=0, **knobs)
@@ -571,8 +671,15 @@ def main():
                               "distances_per_s": args.one_to_all * n / el}
         del rows
         ch.free()
-    if os.path.exists(args.learned):
-        line["plain_vs_learned"] = plain_vs_learned(binding, args, dev)
+    if os.path.exists(args.learned) and args.learned_on != "none":
+        if args.learned_on == args.workload:
+            lg = (t_off, t_dst, t_w, qs, qt)
+        else:
+            (lo, ld, lw), (lqs, lqt) = make_graph(args.learned_on)
+            lg = (torch.from_numpy(lo.astype(np.int64)).to(dev),
+                  torch.from_numpy(ld.astype(np.int32)).to(dev),
+                  torch.from_numpy(lw.astype(np.int32)).to(dev), lqs, lqt)
+        line["plain_vs_learned"] = plain_vs_learned(binding, args, dev, args.learned_on, lg)
     if args.copy_calibration:
         copy_calibration(dev, args.copy_calibration)
     if not args.no_cpu_baseline:

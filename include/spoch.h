@@ -203,6 +203,8 @@ typedef struct {
                                     * default runs them as one device-driven sequence;
                                     * same results) */
 #define CH_F_SCORE_WEIGHTS 0x40u /* score = k_ed ED + k_cn CN + k_depth depth (ch_params_t) */
+#define CH_F_PROGRESS 0x80u      /* ch_build prints a line to stderr at most every 5 s
+                                  * (round, vertices left, shortcuts so far) */
 #define CH_F_KEEP_ORDER 0x20u  /* build on the input's vertex numbering (the default
                                 * renumbers graphs of 4096 or more vertices into
                                 * clusters of nearby vertices first and maps the

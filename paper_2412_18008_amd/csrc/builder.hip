@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <string>
 
@@ -919,6 +921,8 @@ struct Builder {
       next_bound = hctr->bound;
     }
     uint32_t round = 0;
+    unsigned long long sc_total = 0;  // shortcuts so far (progress lines)
+    auto last_note = std::chrono::steady_clock::now();
     while (ov[cur].n > 0) {
       if (prm.max_rounds && round >= prm.max_rounds)
         return set_error(CH_E_LIMIT, "max_rounds reached before every vertex was contracted");
@@ -1262,6 +1266,16 @@ struct Builder {
       }
       ch->stats.push_back(rs);
       round++;
+      sc_total += rs.n_shortcuts;
+      if (prm.flags & CH_F_PROGRESS) {  // a line at most every 5 s
+        const auto now = std::chrono::steady_clock::now();
+        if (now - last_note > std::chrono::seconds(5)) {
+          last_note = now;
+          std::fprintf(stderr, "[ch_build] round %u: %u vertices left, %llu shortcuts\n", round,
+                       n2, sc_total);
+          std::fflush(stderr);
+        }
+      }
     }
     ch->rounds = round;
     if (renum) TRY(restore_order());
