@@ -205,6 +205,9 @@ typedef struct {
 #define CH_F_SCORE_WEIGHTS 0x40u /* score = k_ed ED + k_cn CN + k_depth depth (ch_params_t) */
 #define CH_F_PROGRESS 0x80u      /* ch_build prints a line to stderr at most every 5 s
                                   * (round, vertices left, shortcuts so far) */
+#define CH_F_NO_GRAPH 0x100u     /* table rounds: launch each batch of rounds directly
+                                  * instead of replaying it as a captured HIP graph
+                                  * (same results) */
 #define CH_F_KEEP_ORDER 0x20u  /* build on the input's vertex numbering (the default
                                 * renumbers graphs of 4096 or more vertices into
                                 * clusters of nearby vertices first and maps the

@@ -69,6 +69,7 @@ CH_F_TAIL_STEPWISE = 0x10
 CH_F_KEEP_ORDER = 0x20
 CH_F_SCORE_WEIGHTS = 0x40
 CH_F_PROGRESS = 0x80
+CH_F_NO_GRAPH = 0x100
 CH_TIE_HASHED_ID, CH_TIE_RAW_ID = 0, 1
 CH_MLP_ON_DEVICE, CH_MLP_BF16 = 0x1, 0x2
 
@@ -346,7 +347,8 @@ class CH:
 def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
           query_index=True, stream=None, ls_sparse=0, ls_dense=0, dense_deg10=0, mlp=None,
           record=False, hop=0, dense_tail=0, tail_stepwise=False, keep_order=False,
-          score_weights=None, raw_id=False, settle=0, ls_step=0, mlp_qbits=0, progress=False):
+          score_weights=None, raw_id=False, settle=0, ls_step=0, mlp_qbits=0, progress=False,
+          graph=True):
     """ch_build on a CSR graph; numpy arrays or torch CUDA tensors.  hop > 0
     selects the hop-bounded witness search with walks of at most `hop` arcs;
     tail_stepwise runs the table rounds one launch per step; keep_order
@@ -367,7 +369,8 @@ def build(off, dst, w, labels=None, seed=0, stats=False, group=0, max_rounds=0,
     flags = (CH_F_INPUT_ON_DEVICE if dev else 0) | (CH_F_STATS if stats else 0) | (
         0 if query_index else CH_F_NO_QUERY_INDEX) | (CH_F_RECORD_FEATURES if record else 0) | (
         CH_F_TAIL_STEPWISE if tail_stepwise else 0) | (CH_F_KEEP_ORDER if keep_order else 0) | (
-        CH_F_SCORE_WEIGHTS if score_weights is not None else 0) | (CH_F_PROGRESS if progress else 0)
+        CH_F_SCORE_WEIGHTS if score_weights is not None else 0) | (
+        CH_F_PROGRESS if progress else 0) | (0 if graph else CH_F_NO_GRAPH)
     k_ed, k_cn, k_depth = score_weights if score_weights is not None else (1, 0, 0)
     if stream is None and dev:
         import torch

@@ -454,6 +454,9 @@ struct Builder {
   // / 8 buckets, so a region is a quarter full after the rebuild.
   int ensure_memo(uint64_t extra, uint32_t alive) {
     const uint64_t W = mwmask + 1, a = std::max<uint32_t>(alive, 1);
+    // the round's bound counts paths s -> u -> v, but the memo holds at most
+    // one entry per ordered pair of alive vertices
+    extra = std::min<uint64_t>(extra, a * (a - 1));
     const bool grow = (mcount + extra) * 2 > mcap;
     const bool spread = mcap && mcount > 12 * W * a && W * 4 < mcap / kMemoBucket;
     if (!grow && !spread) return CH_OK;
@@ -630,19 +633,55 @@ struct Builder {
     uint32_t live = n0;  // last known live count (sizes the grids)
     uint32_t r = 0, batches = 0;
     bool stop = false;
+    // one batch of rounds: five launches per round with fixed arguments (the
+    // kernels read the round's parity and number from the device)
+    auto enqueue_batch = [&](unsigned wg) {
+      for (uint32_t b = 0; b < kTailBatch; b++) {
+        k_tail_search<<<wg, kTailBlock, 0, st>>>(A);
+        k_tail_score<<<wg, kTailBlock, 0, st>>>(A);
+        k_tail_selcon<<<wg, kTailBlock, 0, st>>>(A, round, up, dn, ch->nup, ch->ndown, up_cap,
+                                                 dn_cap, ch->level.as<uint32_t>(),
+                                                 ch->score.as<int32_t>(), alive_g.as<uint8_t>());
+        k_tail_compact<<<wg, kTailBlock, 0, st>>>(A);
+        k_tail_merge_end<<<wg, kTailBlock, 0, st>>>(A, max_r, rec, n0);
+      }
+    };
+    // batches replay a captured graph, one per grid size (the live count
+    // rounded up to a power of two); CH_F_NO_GRAPH launches them directly
+    const bool use_graph = !(prm.flags & CH_F_NO_GRAPH);
+    struct GraphSet {
+      std::vector<std::pair<unsigned, hipGraphExec_t>> ex;
+      ~GraphSet() {
+        for (auto &e : ex) (void)hipGraphExecDestroy(e.second);
+      }
+    } graphs;
     while (!stop) {
       // one wave per item; items never exceed the live count at the batch start
-      const unsigned wg = grid((uint64_t)std::max<uint32_t>(live, 1) * kWave, kTailBlock);
-      for (uint32_t b = 0; b < kTailBatch; b++, r++) {
-        const uint32_t c = r & 1u;
-        k_tail_search<<<wg, kTailBlock, 0, st>>>(A, c);
-        k_tail_score<<<wg, kTailBlock, 0, st>>>(A, c);
-        k_tail_selcon<<<wg, kTailBlock, 0, st>>>(A, c, round + r, up, dn, ch->nup, ch->ndown,
-                                                 up_cap, dn_cap, ch->level.as<uint32_t>(),
-                                                 ch->score.as<int32_t>(), alive_g.as<uint8_t>());
-        k_tail_compact<<<wg, kTailBlock, 0, st>>>(A, c);
-        k_tail_merge_end<<<wg, kTailBlock, 0, st>>>(A, c, max_r, rec, n0);
+      uint32_t lb = 64;
+      while (lb < live && lb < n0) lb <<= 1;
+      const unsigned wg = grid((uint64_t)lb * kWave, kTailBlock);
+      if (use_graph) {
+        hipGraphExec_t ex = nullptr;
+        for (auto &e : graphs.ex)
+          if (e.first == wg) ex = e.second;
+        if (!ex) {
+          hipGraph_t gr = nullptr;
+          HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          enqueue_batch(wg);
+          const hipError_t le = hipGetLastError();
+          const hipError_t ce = hipStreamEndCapture(st, &gr);
+          HIP_TRY(le);
+          HIP_TRY(ce);
+          const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(gr);
+          HIP_TRY(ie);
+          graphs.ex.emplace_back(wg, ex);
+        }
+        HIP_TRY(hipGraphLaunch(ex, st));
+      } else {
+        enqueue_batch(wg);
       }
+      r += kTailBatch;
       HIP_TRY(hipGetLastError());
       const int slot = batches & 1;
       HIP_TRY(hipMemcpyAsync(&h_tail[slot], t_ctr.p, sizeof(TailCtr), hipMemcpyDeviceToHost, st));

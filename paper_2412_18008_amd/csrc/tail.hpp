@@ -32,7 +32,10 @@ constexpr uint32_t kTailMaxN = 4096;  // positions fit 12 bits
 constexpr int kTailPaths = 4;        // two-arc paths per lane in flight (search)
 
 // Device state of the tail; list counts and flags are indexed by the
-// parity of the round (cur = this round's, nxt = the next round's).
+// parity of the round (cur = this round's, nxt = the next round's); every
+// kernel takes the parity and the round number from the device counter of
+// finished rounds, so a batch of rounds has fixed launch arguments (and is
+// replayed as one captured graph).
 struct TailCtr {
   uint32_t done;    // set once no vertex is left, the round limit is hit or an error is set
   uint32_t live;    // live vertices
@@ -191,9 +194,10 @@ __global__ void k_tail_lrank(TailArgs A) {
 // heavier than the memoized dist(s, v) is deleted.  The searches read only
 // the lists and weights, which pruning does not change, so they see the
 // overlay as it was at the start of the round.  One wave per source.
-__global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A, uint32_t cur) {
+__global__ void __launch_bounds__(kTailBlock) k_tail_search(TailArgs A) {
   TailCtr *C = A.C;
   if (C->done) return;
+  const uint32_t cur = C->rounds & 1u;
   const uint32_t nw = C->cntW[cur];
   const uint16_t *lw = cur ? A.lw1 : A.lw0;
   const uint32_t *af = cur ? A.af1 : A.af0;
@@ -367,9 +371,10 @@ __device__ __forceinline__ void tail_pairs(const TailArgs &A, uint32_t u, uint32
 }
 
 // Step 2 (Alg. 5): edge difference of every affected vertex, one block each.
-__global__ void __launch_bounds__(kTailBlock) k_tail_score(TailArgs A, uint32_t cur) {
+__global__ void __launch_bounds__(kTailBlock) k_tail_score(TailArgs A) {
   TailCtr *C = A.C;
   if (C->done) return;
+  const uint32_t cur = C->rounds & 1u;
   const uint32_t na = C->cntA[cur];
   const uint16_t *la = cur ? A.la1 : A.la0;
   __shared__ uint32_t s_red[kTailWaves][3];
@@ -425,8 +430,8 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_score(TailArgs A, uint32_t 
 // the moved arcs stay set until the compaction drops every entry to a dead
 // vertex, so the selections in this launch all see the same overlay, and
 // the rows a contraction reads (its own) change in no way meanwhile.
-__global__ void __launch_bounds__(kTailBlock) k_tail_selcon(TailArgs A, uint32_t cur,
-                                                            uint32_t round, ArcOut up, ArcOut dn,
+__global__ void __launch_bounds__(kTailBlock) k_tail_selcon(TailArgs A,
+                                                            uint32_t round0, ArcOut up, ArcOut dn,
                                                             uint64_t up_base, uint64_t dn_base,
                                                             uint64_t up_cap, uint64_t dn_cap,
                                                             uint32_t *__restrict__ level,
@@ -434,6 +439,7 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_selcon(TailArgs A, uint32_t
                                                             uint8_t *__restrict__ alive_g) {
   TailCtr *C = A.C;
   if (C->done) return;
+  const uint32_t cur = C->rounds & 1u, round = round0 + C->rounds;
   const uint32_t nxt = cur ^ 1u;
   uint32_t *afn = nxt ? A.af1 : A.af0;
   uint32_t *wfn = nxt ? A.wf1 : A.wf0;
@@ -556,9 +562,10 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_selcon(TailArgs A, uint32_t
 // Drops the dead entries (pruned arcs, arcs to contracted vertices) from
 // the lists of the live vertices; the live in-neighbours of a V_S vertex
 // join the next V_W.
-__global__ void __launch_bounds__(kTailBlock) k_tail_compact(TailArgs A, uint32_t cur) {
+__global__ void __launch_bounds__(kTailBlock) k_tail_compact(TailArgs A) {
   TailCtr *C = A.C;
   if (C->done) return;
+  const uint32_t cur = C->rounds & 1u;
   const uint32_t nxt = cur ^ 1u;
   uint32_t *wfn = nxt ? A.wf1 : A.wf0;
   uint16_t *lwn = nxt ? A.lw1 : A.lw0;
@@ -603,12 +610,13 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_compact(TailArgs A, uint32_
 // this round's flags cleared (they serve the round after next), the
 // counters of the next round, and the stop condition.  A round with an
 // error is not recorded.
-__global__ void __launch_bounds__(kTailBlock) k_tail_merge_end(TailArgs A, uint32_t cur,
-                                                               uint32_t max_rounds,
+__global__ void __launch_bounds__(kTailBlock) k_tail_merge_end(TailArgs A, uint32_t max_rounds,
                                                                TailRound *__restrict__ rec,
                                                                uint32_t rec_cap) {
   TailCtr *C = A.C;
   if (C->done) return;
+  // the last block increments C->rounds only after every block has finished
+  const uint32_t cur = C->rounds & 1u;
   const uint32_t nxt = cur ^ 1u;
   uint32_t *wfn = nxt ? A.wf1 : A.wf0;
   uint16_t *lwn = nxt ? A.lw1 : A.lw0;

@@ -529,6 +529,25 @@ def test_dense_tail_table(gpu):
                 assert kinds <= {table_kind}, (ctx, kinds)
 
 
+def test_tail_graph_replay_bit_exact(gpu):
+    # the device-driven table rounds replay one captured graph per grid size
+    # (batches of rounds with fixed arguments); launched directly instead
+    # (CH_F_NO_GRAPH) they must give the same CH, equal to the oracle's, on
+    # graphs whose tails run several batches and grid sizes, built twice in a
+    # row in one process
+    cases = [("grid64", *synth.config_grid64(seed=0)),
+             ("road30k", *synth.road_like(30_000, seed=9)),
+             ("digraph", *synth.random_digraph(3000, 12000, seed=4, wmax=30))]
+    for name, off, dst, w in cases:
+        n = len(off) - 1
+        lab = synth.labels(n, 29)
+        a = oracle_export(oracle.OracleCH(off, dst, w, labels=lab).run())
+        for graph in (True, False, True):
+            ch = gpu.build(off, dst, w, labels=lab, stats=True, graph=graph)
+            assert_same_ch(a, gpu_export(ch), f"{name} graph={graph}")
+            assert sum(1 for r in ch.round_stats() if r["ls_tier1"] == 6) > 8, name
+
+
 def test_dense_tail_learned_and_batch(gpu):
     from paper_2412_18008_amd import learned
 
