@@ -164,8 +164,9 @@ typedef struct {
    * graph must then carry no labels, else CH_E_INVALID). */
   uint32_t tiebreak;
   uint32_t settle_limit; /* CH_WPS_SETTLED: vertices settled per search (theta), >= 1 */
-  /* Exact mode: a search step expands only the frontier vertices whose
-   * distance is below the smallest frontier distance plus D_s >> ls_step
+  /* Exact mode, searches run by a whole wave or block (dense rounds and the
+   * larger-table tiers): a search step expands only the frontier vertices
+   * whose distance is below the smallest frontier distance plus D_s >> ls_step
    * (distance buckets, so fewer vertices are expanded before their distance
    * is final); 0 = the default, 2; CH_LS_STEP_ALL (32) expands the whole
    * frontier every step.  At most 32.  Changes speed only, never results. */

@@ -352,9 +352,13 @@ __device__ bool settled_search(const Overlay &ov, const MemoRef &memo, const Tab
 constexpr uint32_t kLsStepDefault = 2;
 
 // One source.  Returns false when the table overflowed (nothing written).
-// Exact mode: a step expands the frontier vertices whose distance is below
-// the smallest frontier distance plus D >> `hops` (the bucket shift; 32 =
-// the whole frontier); the others stay in the frontier for a later step.
+// Exact mode, wave-wide groups (G = 64): a step expands the frontier
+// vertices whose distance is below the smallest frontier distance plus
+// D >> `hops` (the bucket shift; 32 = the whole frontier); the others stay
+// in the frontier for a later step.  Narrow groups run the small searches of
+// sparse rounds, where the extra reduction per step costs more than it saves
+// (road-like 24M: 137 -> 152 ms per build in the 16-lane kernel), so they
+// expand the whole frontier.
 // Expanding near vertices first re-expands fewer vertices whose distance
 // drops later; the result is the same for every shift (every tentative value
 // is a path length and the search ends only when no distance can drop).
@@ -482,7 +486,7 @@ __device__ bool search_source(const Overlay &ov, const uint8_t *__restrict__ afl
     // exact mode: the step's distance bound (frontier entries at or above
     // it wait for a later step)
     uint32_t B = 0xFFFFFFFFu;
-    if constexpr (!HOP) {
+    if constexpr (!HOP && G == kWave) {  // wave and block searches (dense rounds)
       if (hops < 32) {
         uint32_t mn = SP_INF32;
         for (uint32_t i = tl; i < ncur; i += NT) mn = min(mn, T.ld(&T.dist[T.ldi(&fc[i])]));
