@@ -496,6 +496,8 @@ def main():
                          "learned comparison runs after the timed steps when the file exists")
     ap.add_argument("--learned-on", default="road1m", choices=("road1m", "road24m", "none"),
                     help="workload of the plain vs learned comparison (after the timed steps)")
+    ap.add_argument("--no-query-sweep", action="store_true",
+                    help="skip the query latency / throughput sweep over batch sizes")
     ap.add_argument("--no-hbm-probe", action="store_true",
                     help="skip the streaming / scattered HBM probe")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -648,10 +650,11 @@ def main():
         "kernel_ms_per_step": {k: v / args.steps for k, v in sorted(cands.items(),
                                                                   key=lambda x: -x[1])},
     }
-    print("[bench] query latency and throughput per batch size", file=sys.stderr, flush=True)
-    ch = binding.build(t_off, t_dst, t_w, seed=0, **knobs)
-    line["query_batch_sizes"] = query_sizes(ch, qs, qt, dev, qknobs=qknobs)
-    ch.free()
+    if not args.no_query_sweep:
+        print("[bench] query latency and throughput per batch size", file=sys.stderr, flush=True)
+        ch = binding.build(t_off, t_dst, t_w, seed=0, **knobs)
+        line["query_batch_sizes"] = query_sizes(ch, qs, qt, dev, qknobs=qknobs)
+        ch.free()
     if not args.no_hbm_probe:
         print("[bench] HBM probe (streaming and scattered)", file=sys.stderr, flush=True)
         line["hbm_probe"] = hbm_probe(dev)
