@@ -312,8 +312,11 @@ __global__ void __launch_bounds__(kLsBlock) k_local_search(
 // Searches that outgrow a wave's table: NW waves of one block share one
 // source and one CAP-slot LDS table (Coop in search.hpp), so a large search
 // gets NW times the lanes per frontier level.  Persistent: blocks take
-// sources one at a time from a global counter.
-constexpr int kLsBlkWaves = 16;
+// sources one at a time from a global counter.  Eight waves (also per
+// global-tier search): on road-like 24M the block and global tiers take 342
+// and 129 ms per build against 372 and 132 with sixteen waves (fewer idle
+// waves at a narrow frontier, cheaper barriers), 394 and 133 with four.
+constexpr int kLsBlkWaves = 8;
 constexpr int kLsBlkCap = 8192;
 constexpr size_t ls_blk_lds_bytes(int cap, bool hop, int nw) {
   return 4 * (size_t)cap * (hop ? 3 : 2) + (hop ? 0 : 4) + 8 * (size_t)(cap / 32) + 16 +
