@@ -1711,7 +1711,5 @@ ch_s::~ch_s() {
                      &dn_w, &dn_m, &q_upoff, &q_uparc, &q_dnoff, &q_dnarc, &q_lstart, &q_wend, &q_s, &q_t, &q_d,
                      &q_ovf, &q_tab, &q_ctr, &rec, &q_v, &q_ovf2, &q_gtab, &q_phast};
   for (sp::DBuf *b : all) b->release();
-  for (auto &e : q_ev)
-    if (e) (void)hipEventDestroy(e);
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

@@ -39,7 +39,6 @@ struct ch_s {
   int q_first_tier = 1;  // query tier where the previous batch mostly ended
   sp::DBuf q_phast;  // one-to-all sweeps: distances, rank-major, KC sources per vertex
   ch_query_stats_t qstats{};              // counters of the last query batch
-  hipEvent_t q_ev[8] = {};                // tier timing (created on first use)
 
   // features at contraction (CH_F_RECORD_FEATURES), 8 floats per vertex
   bool has_rec = false;

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <mutex>
 #include <type_traits>
 #include <string>
@@ -1252,9 +1254,17 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   qsn.first_tier = forced ? forced : (uint32_t)ch->q_first_tier;
   qsn.counted = qcount ? 1u : 0u;
   // tier timing: events 2t and 2t+1 around tier t (ch_query_batch only)
-  hipEvent_t *ev = sc.timed ? ch->q_ev : nullptr;
-  if (ev && !ev[0])
-    for (int i = 0; i < 8; i++) HIP_TRY(hipEventCreate(&ev[i]));
+  // the events come from a pool per host thread and device, made once and
+  // kept to the end of the process (creating and destroying eight events
+  // per CH cost about 2 ms per CH in a 512-graph batch)
+  hipEvent_t *ev = nullptr;
+  if (sc.timed) {
+    static thread_local std::map<int, std::array<hipEvent_t, 8>> pool;
+    auto &a = pool[ch->device];
+    if (!a[0])
+      for (int i = 0; i < 8; i++) HIP_TRY(hipEventCreate(&a[i]));
+    ev = a.data();
+  }
   auto mark = [&](int i) -> hipError_t { return ev ? hipEventRecord(ev[i], st) : hipSuccess; };
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ch->device);

@@ -9,13 +9,27 @@ namespace sp {
 
 namespace {
 
-constexpr size_t kCacheMaxBytes = 32ull << 30;  // per device
-
 struct BlockCache {
   std::mutex mu;
   std::multimap<std::pair<int, size_t>, void *> blocks;  // (device, size) -> block
   std::map<int, size_t> bytes;                            // cached bytes per device
+  std::map<int, size_t> limit;                            // cap per device
 };
+
+// Cache cap of a device: a quarter of its memory (72 GB of the 288 GB of an
+// MI355X), so that a batch of hundreds of CHs can be built, queried and
+// freed repeatedly without hipMalloc / hipFree (each CH holds about 30
+// buffers); an allocation that fails empties the cache and retries.
+size_t cache_limit(BlockCache &c, int dev) {
+  auto it = c.limit.find(dev);
+  if (it != c.limit.end()) return it->second;
+  hipDeviceProp_t prop;
+  size_t lim = 32ull << 30;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.totalGlobalMem)
+    lim = prop.totalGlobalMem / 4;
+  c.limit[dev] = lim;
+  return lim;
+}
 
 BlockCache &block_cache() {
   static BlockCache *c = new BlockCache;  // lives until the process ends
@@ -104,7 +118,7 @@ void DBuf::release() {
   {
     std::lock_guard<std::mutex> g(c.mu);
     size_t &b = c.bytes[dev];
-    if (b + cap <= kCacheMaxBytes) {
+    if (b + cap <= cache_limit(c, dev)) {
       c.blocks.emplace(std::make_pair(dev, cap), p);
       b += cap;
       kept = true;

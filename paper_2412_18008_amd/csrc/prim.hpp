@@ -10,8 +10,8 @@
 namespace sp {
 
 // Growable device buffer (grows by 1.5x, never shrinks).  Blocks come from
-// and go back to a per-device cache of released blocks (at most 32 GB per
-// device), so repeated builds and queries do not pay hipMalloc / hipFree:
+// and go back to a per-device cache of released blocks (at most a quarter
+// of the device's memory), so repeated builds and queries do not pay hipMalloc / hipFree:
 // taking a cached block first synchronises the device, so a block released
 // while a kernel on another stream may still use it is never handed out
 // early.
