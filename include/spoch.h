@@ -102,6 +102,13 @@ extern "C" {
  * one tier up for later batches when more than half of a batch moved on).
  * Queries that outgrow a tier still move on.  Results do not depend on it. */
 #define CH_Q_FIRST_TIER(t) ((uint32_t)(t) << 22)
+/* The second tier normally stops both searches at the 4096 highest ranks
+ * and finishes with a table of the exact distances among them (built once
+ * per CH, 64 MB, at its first pruned batch that reaches the tier; skipped
+ * when a distance in it could pass 32 bits; ch_query_batch_noalloc uses it
+ * only if it exists).  CH_Q_NO_CORE searches without it.  Results do not
+ * depend on it. */
+#define CH_Q_NO_CORE (1u << 26)
 
 /* Input graph in CSR form, arcs grouped by tail vertex.
  *   offsets[n+1]: offsets[0] = 0, non-decreasing, offsets[n] = m

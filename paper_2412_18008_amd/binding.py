@@ -33,6 +33,7 @@ CH_F_NO_QUERY_INDEX = 0x4
 CH_Q_ON_DEVICE = 0x1
 CH_Q_FULL_CLOSURE = 1 << 20
 CH_Q_COUNT = 1 << 21
+CH_Q_NO_CORE = 1 << 26
 
 EXPORTED = ("ch_build", "ch_build_batch", "ch_query_batch", "ch_export", "ch_get_summary",
             "ch_get_round_stats", "ch_free", "ch_last_error", "ch_version", "ch_export_features",
@@ -223,7 +224,8 @@ class CH:
             _lib.ch_free(self.h)
             self.h = None
 
-    def query(self, s, t, stream=None, waves=0, window=0, full=False, count=False, tier=0):
+    def query(self, s, t, stream=None, waves=0, window=0, full=False, count=False, tier=0,
+              core=True):
         """dist[i] = shortest s[i] -> t[i] distance (uint64, max = unreachable).
         numpy inputs give a numpy result; torch CUDA inputs give a torch CUDA
         int64 tensor (holding the uint64 bit patterns).  waves: waves per
@@ -231,11 +233,12 @@ class CH:
         a search step (0 = default, 255 = none); full: expand both upward
         search spaces completely (no pruning by the best path met); count:
         count expansions and relaxed arcs (last_query_stats); tier: the tier
-        the batch starts in (1, 2, 3; 0 = chosen by the library)."""
+        the batch starts in (1, 2, 3; 0 = chosen by the library); core: the
+        second tier finishes at the core table (the same distances)."""
         if tier not in (0, 1, 2, 3):
             raise ValueError("tier must be 0, 1, 2 or 3")
         qf = CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window) | (CH_Q_FULL_CLOSURE if full else 0) | (
-            CH_Q_COUNT if count else 0) | CH_Q_FIRST_TIER(tier)
+            CH_Q_COUNT if count else 0) | CH_Q_FIRST_TIER(tier) | (0 if core else CH_Q_NO_CORE)
         if _is_torch_cuda(s):
             import torch
 

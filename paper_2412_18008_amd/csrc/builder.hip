@@ -1322,6 +1322,25 @@ struct Builder {
   }
 };
 
+hipError_t fw_init(uint32_t *D, uint32_t N, hipStream_t st) {
+  const uint64_t nn = (uint64_t)N * N;
+  k_fw_init<<<(unsigned)std::max<uint64_t>(1, std::min<uint64_t>((nn + 255) / 256, 65535)), 256, 0,
+              st>>>(D, N);
+  return hipGetLastError();
+}
+
+hipError_t fw_close(uint32_t *D, uint32_t N, hipStream_t st) {
+  const uint32_t nb = N / kFwTile;
+  for (uint32_t k = 0; k < nb; k++) {
+    k_fw_diag<<<1, kFwDiagThreads, 0, st>>>(D, N, k);
+    if (nb > 1) {
+      k_fw_panels<<<2 * nb, kFwThreads, 0, st>>>(D, N, k);
+      k_fw_rest<<<nb * nb, kFwThreads, 0, st>>>(D, N, k);
+    }
+  }
+  return hipGetLastError();
+}
+
 static int check_params(const ch_params_t *p, ch_params_t &prm) {
   prm = ch_params_t{};
   if (p) prm = *p;
@@ -1709,7 +1728,8 @@ int build_batch(const ch_graph_t *gs, uint32_t k, const ch_params_t *p, ch_t **o
 ch_s::~ch_s() {
   sp::DBuf *all[] = {&level, &score, &label, &rank, &up_t, &up_h, &up_w, &up_m, &dn_t, &dn_h,
                      &dn_w, &dn_m, &q_upoff, &q_uparc, &q_dnoff, &q_dnarc, &q_lstart, &q_wend, &q_s, &q_t, &q_d,
-                     &q_ovf, &q_tab, &q_ctr, &rec, &q_v, &q_ovf2, &q_gtab, &q_phast};
+                     &q_ovf, &q_tab, &q_ctr, &rec, &q_v, &q_ovf2, &q_gtab, &q_phast,
+                     &q_core, &q_core_max};
   for (sp::DBuf *b : all) b->release();
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

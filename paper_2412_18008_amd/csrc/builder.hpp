@@ -38,6 +38,12 @@ struct ch_s {
   sp::DBuf q_s, q_t, q_d, q_v, q_ovf, q_ovf2, q_tab, q_gtab, q_ctr;
   int q_first_tier = 1;  // query tier where the previous batch mostly ended
   sp::DBuf q_phast;  // one-to-all sweeps: distances, rank-major, KC sources per vertex
+  // core table of the query: exact distances among the q_core_k highest
+  // ranks (row-major, q_core_n columns, 0xFFFFFFFF = none); 0 = not built,
+  // q_core_state: 0 not tried, 1 built, 2 not usable on this CH
+  sp::DBuf q_core, q_core_max;
+  uint32_t q_core_k = 0, q_core_n = 0;
+  int q_core_state = 0;
   ch_query_stats_t qstats{};              // counters of the last query batch
 
   // features at contraction (CH_F_RECORD_FEATURES), 8 floats per vertex
@@ -71,6 +77,12 @@ int query_batch(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q
 // One-to-all / many-to-many distances by the CH's two sweeps (phast.hip).
 int one_to_all(const ch_s *ch, const uint32_t *s, uint32_t ks, const uint32_t *t, uint32_t kt,
                uint64_t *dist, uint32_t flags, hipStream_t st);
+// All-pairs closure of an N x N distance matrix in place (N a multiple of
+// 64; 0xFFFFFFFF = none; sums clamped): blocked Floyd-Warshall (builder.hip,
+// the kernels of the all-pairs table).  fw_init sets none everywhere and 0
+// on the diagonal.
+hipError_t fw_init(uint32_t *D, uint32_t N, hipStream_t st);
+hipError_t fw_close(uint32_t *D, uint32_t N, hipStream_t st);
 // Query batch with every scratch array in a fixed per-GPU array (post.hip).
 int query_batch_noalloc(const ch_s *ch, const uint32_t *s, const uint32_t *t, uint64_t q,
                         uint64_t *dist, uint32_t *visited, uint32_t flags, hipStream_t st);

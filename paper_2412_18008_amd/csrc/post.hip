@@ -602,10 +602,12 @@ struct QLds {
 // space lie below the top 2048 ranks); five blocks per CU.
 using QTier1 = QLds<512, 2048, 2048>;
 using QTier2 = QLds<4096, 8192, 4096>;
+constexpr uint32_t kQCore = 4096;  // core ranks of tier 2 (within its 8192 rank slots)
 using QTier3 = QLds<16384>;
 constexpr int kQTier1PerCU = 5;
 static_assert(sizeof(QTier1) * kQTier1PerCU <= 163840, "five tier-1 query blocks per CU");
-static_assert(sizeof(QTier2) <= 163840, "one tier-2 query block per CU");
+static_assert(sizeof(QTier2) + 4 * kQCore + 8 * 16 <= 163840,
+              "one tier-2 query block per CU, with its core lists");
 
 // Table accessors: plain LDS accesses, or device-coherent ones for tables in
 // global memory (written by other waves' atomics, which bypass the CU's
@@ -769,7 +771,17 @@ __device__ __forceinline__ void qclear(L &S, uint32_t tid, uint32_t nt) {
 // by the blocks from the counter *work (so blocks that draw large queries
 // take fewer).  Queries that do not fit go to ovf_list (count in
 // *ovf_count).  GM: gtab holds one L per block.
-template <int NW, typename L, bool GM>
+// Core table (tier 2): a query does not expand the CORE highest ranks; it
+// takes min over pairs (a, b) of core vertices reached from s and from t of
+// d_s(a) + D[a][b] + d_t(b), with D the exact distances among them (the CH
+// arcs among the highest ranks keep those distances: a shortest up-down path
+// between two of them climbs from the lower one).  A shortest s-t path whose
+// highest vertex is in the core enters it at some a and leaves it at some b,
+// and its two ends are found exactly below the core; every other path is met
+// as before.  CORE = 0: no core (kQCore, the core size, is defined with the
+// tier tables).
+
+template <int NW, typename L, bool GM, int CORE = 0>
 __global__ void __launch_bounds__(64 * NW) k_query(
     uint64_t q, uint32_t n, const uint32_t *__restrict__ list,
     const uint32_t *__restrict__ nlist, uint32_t *__restrict__ bad,
@@ -780,7 +792,9 @@ __global__ void __launch_bounds__(64 * NW) k_query(
     uint32_t *__restrict__ visited, uint32_t *__restrict__ ovf_list,
     uint32_t *__restrict__ ovf_count, const uint32_t *__restrict__ wend,
     unsigned long long *__restrict__ work, L *__restrict__ gtab,
-    unsigned long long *__restrict__ qcount, uint32_t prune) {
+    unsigned long long *__restrict__ qcount, uint32_t prune,
+    const uint32_t *__restrict__ coreD = nullptr, uint32_t core0 = 0xFFFFFFFFu,
+    uint32_t coreN = 0, uint32_t coreK = 0) {
   using E = typename L::Entry;
   constexpr uint32_t CAP = sizeof(((L *)nullptr)->key[0]) / 4;
   constexpr uint32_t TOP = L::kTop, NS = L::kSlots;
@@ -820,6 +834,8 @@ __global__ void __launch_bounds__(64 * NW) k_query(
   // rows and arcs read (expansions and stall checks; stats batches)
   uint32_t nrows = 0, narcs = 0;
   __shared__ unsigned long long s_stall[NW];
+  // core entries of both directions at the end of a query (core index)
+  __shared__ uint16_t s_core[2][CORE > 0 ? CORE : 1];
   auto stall_check = [&](bool cand, uint32_t vx, uint32_t dx, uint32_t dr) -> bool {
     uint32_t ss = 0, sl = 0;
     if (cand) {
@@ -994,6 +1010,8 @@ __global__ void __launch_bounds__(64 * NW) k_query(
             atomicOr(&S.bits[dr][slot >> 5], 1u << (slot & 31));
           } else if (prune && dx >= qld64<GM>(&S.mu)) {
             // no path through x is shorter than one already met
+          } else if (CORE && coreD && vx >= core0) {
+            // a core vertex: its paths come from the core table at the end
           } else {
             cand = true;
           }
@@ -1117,6 +1135,34 @@ __global__ void __launch_bounds__(64 * NW) k_query(
         const unsigned long long m = qld64<GM>(&S.mu);
         best = m < best ? m : best;
       }
+      if constexpr (CORE > 0) {
+        if (coreD) {
+          // core entries of each direction (dense slots from cb on), listed
+          // by a block scan, then every pair through the core table
+          const uint32_t cb = core0 - tbase;
+          uint32_t cnt[2];
+#pragma unroll
+          for (int d = 0; d < 2; d++) {
+            uint32_t c = 0;
+            for (uint32_t i = tid; i < coreK; i += NT) c += qld<GM>(&S.dist[d][cb + i]) != SP_INF32;
+            uint32_t p = qscan<NW, GM>(S, c, &cnt[d], d ? S.wsum2 : S.wsum);
+            for (uint32_t i = tid; i < coreK; i += NT)
+              if (qld<GM>(&S.dist[d][cb + i]) != SP_INF32) s_core[d][p++] = (uint16_t)i;
+          }
+          qsync<NW, GM>();
+          const uint32_t n1 = cnt[1];
+          const uint64_t np = (uint64_t)cnt[0] * n1;
+          for (uint64_t pp = tid; pp < np; pp += NT) {
+            const uint32_t i = s_core[0][pp / n1], j = s_core[1][pp % n1];
+            const uint32_t w = coreD[(size_t)i * coreN + j];
+            narcs++;  // one table read (stats batches)
+            if (w == SP_INF32) continue;
+            const unsigned long long c2 = (unsigned long long)qld<GM>(&S.dist[0][cb + i]) + w +
+                                          qld<GM>(&S.dist[1][cb + j]);
+            best = c2 < best ? c2 : best;
+          }
+        }
+      }
       best = gmin64<kWave>(best);
       if constexpr (NW > 1) {
         if (l == 0) {
@@ -1221,6 +1267,65 @@ constexpr uint32_t kQCtrWords = 32;
 // (tables for the global-memory tiers, requested only when a query needs
 // them); tier4 sets *limit < *cap when its tables can fill, and a query
 // that still overflows then makes the call fail with CH_E_LIMIT.
+// Core matrix entries from the CH arcs of the core rows c0 .. n-1 (row
+// index = rank - c0): upward arcs of a row go to higher ranks, downward arcs
+// of a row come from higher ranks, so every such arc joins two core
+// vertices.  *maxw = the largest weight seen.
+__global__ void k_core_arcs(uint32_t c0, uint32_t n, uint32_t N, const uint32_t *__restrict__ upoff,
+                            const uint2 *__restrict__ uparc, const uint32_t *__restrict__ dnoff,
+                            const uint2 *__restrict__ dnarc, uint32_t *__restrict__ D,
+                            uint32_t *__restrict__ maxw) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  uint32_t mx = 0;
+  for (uint32_t r = c0 + blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const uint32_t i = r - c0;
+    for (uint32_t e = upoff[r]; e < upoff[r + 1]; e++) {
+      const uint2 a = uparc[e];
+      if (a.x < c0 || a.x >= n) continue;
+      atomicMin(&D[(size_t)i * N + (a.x - c0)], a.y);
+      mx = max(mx, a.y);
+    }
+    for (uint32_t e = dnoff[r]; e < dnoff[r + 1]; e++) {
+      const uint2 a = dnarc[e];
+      if (a.x < c0 || a.x >= n) continue;
+      atomicMin(&D[(size_t)(a.x - c0) * N + i], a.y);
+      mx = max(mx, a.y);
+    }
+  }
+  if (mx) atomicMax(maxw, mx);
+}
+
+// The core table of a CH (once per CH, at its first pruned tier-2 batch):
+// the kQCore highest ranks (all of them on smaller CHs), their arcs, then
+// the all-pairs closure.  Not used when a core distance could pass 32 bits
+// (largest core arc weight x core size above 0xFFFFFFFE).
+static int core_table(ch_s *ch, hipStream_t st) {
+  if (ch->q_core_state) return CH_OK;
+  ch->q_core_state = 2;
+  const uint32_t n = ch->n;
+  const uint32_t K = std::min<uint32_t>(kQCore, n);
+  if (K == 0) return CH_OK;
+  const uint32_t N = (K + 63) / 64 * 64, c0 = n - K;
+  HIP_TRY(ch->q_core.ensure((size_t)N * N * 4));
+  HIP_TRY(ch->q_core_max.ensure(4));
+  uint32_t *D = ch->q_core.as<uint32_t>(), *mx = ch->q_core_max.as<uint32_t>();
+  HIP_TRY(fw_init(D, N, st));
+  HIP_TRY(fill_u32(mx, 0u, 1, st));
+  k_core_arcs<<<(K + 255) / 256, 256, 0, st>>>(c0, n, N, ch->q_upoff.as<uint32_t>(),
+                                               ch->q_uparc.as<uint2>(), ch->q_dnoff.as<uint32_t>(),
+                                               ch->q_dnarc.as<uint2>(), D, mx);
+  HIP_TRY(hipGetLastError());
+  uint32_t hmx = 0;
+  HIP_TRY(hipMemcpyAsync(&hmx, mx, 4, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if ((uint64_t)hmx * K > 0xFFFFFFFEull) return CH_OK;
+  HIP_TRY(fw_close(D, N, st));
+  ch->q_core_k = K;
+  ch->q_core_n = N;
+  ch->q_core_state = 1;
+  return CH_OK;
+}
+
 template <typename Scratch>
 static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_t q,
                        unsigned long long *dd, uint32_t *dv, uint32_t flags, hipStream_t st,
@@ -1307,10 +1412,16 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   }
   if (first <= 2) {
     HIP_TRY(mark(2));
-    k_query<16, QTier2, false><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
+    // the core table: pruned batches only (full closures expand everything),
+    // made on the first such batch when the scratch may allocate
+    const bool use_core = prune && !(flags & CH_Q_NO_CORE);
+    if (use_core && ch->q_core_state == 0 && sc.can_alloc) TRY(core_table(ch, st));
+    const bool core = use_core && ch->q_core_state == 1;
+    k_query<16, QTier2, false, kQCore><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
         dnarc, dd, dv, ovf2, ctr + 2, wend, reinterpret_cast<unsigned long long *>(ctr + 10),
-        nullptr, qcount, prune);
+        nullptr, qcount, prune, core ? ch->q_core.as<uint32_t>() : nullptr,
+        core ? ch->n - ch->q_core_k : 0xFFFFFFFFu, ch->q_core_n, ch->q_core_k);
     HIP_TRY(hipGetLastError());
     HIP_TRY(mark(3));
   }
@@ -1390,6 +1501,7 @@ struct QScratchCH {
   ch_s *ch;
   uint32_t *ctr = nullptr, *ovf1 = nullptr, *ovf2 = nullptr;
   bool timed = true;
+  bool can_alloc = true;  // may build the CH's core table
   int tier3(uint64_t, QTier3 **tabs, uint64_t *nb) {
     HIP_TRY(ch->q_tab.ensure(*nb * sizeof(QTier3)));
     *tabs = reinterpret_cast<QTier3 *>(ch->q_tab.p);
@@ -1497,6 +1609,7 @@ struct QScratchFixed {
   uint32_t n;
   uint32_t *ctr, *ovf1, *ovf2;
   bool timed = false;  // creating events is left to ch_query_batch
+  bool can_alloc = false;  // uses a core table only if one was built before
   int tier3(uint64_t, QTier3 **tabs, uint64_t *nb) {
     *nb = std::min<uint64_t>(*nb, kNaT3Blocks);
     *tabs = reinterpret_cast<QTier3 *>(base + kNaT3);

@@ -268,6 +268,38 @@ def test_query_tiers(gpu):
         assert np.array_equal(ch.query(s, t, window=win), ref), win
 
 
+def test_query_core_table(gpu):
+    # The second query tier stops both searches at the 4096 highest ranks and
+    # finishes with the table of exact distances among them: every result
+    # equals the oracle's (and Dijkstra's) with and without the table, on a
+    # CH smaller than the core (every vertex in it), larger ones, random
+    # digraphs with unreachable pairs, self queries, and a fan whose hub
+    # queries overflow to the third tier; a second batch reuses the table.
+    cases = [("grid64", *synth.config_grid64(seed=0)),
+             ("road30k", *synth.road_like(30_000, seed=9)),
+             ("digraph", *synth.random_digraph(6000, 15000, seed=4, wmax=30)),
+             ("fan13000", *synth.fan(13000))]
+    for name, off, dst, w in cases:
+        n = len(off) - 1
+        lab = synth.labels(n, 41)
+        print(f"[parity] core {name}", flush=True)
+        o = oracle.OracleCH(off, dst, w, labels=lab).run()
+        ch = gpu.build(off, dst, w, labels=lab)
+        s, t = synth.queries(n, 3000, seed=7)
+        s[:50] = t[:50]  # self queries
+        if name == "fan13000":
+            s[50:90] = 13000  # the hub: overflows the second tier
+        od, _ = o.query_batch(s, t)
+        for rep in range(2):
+            d = ch.query(s, t, tier=2)
+            assert np.array_equal(d, od), (name, rep)
+        assert np.array_equal(ch.query(s, t, tier=2, core=False), od), name
+        assert np.array_equal(ch.query(s, t, tier=2, full=True), od), name
+        if name != "fan13000":
+            ref = reference_distances(off, dst, w, s[:200], t[:200])
+            assert np.array_equal(d[:200], ref), name
+
+
 def test_query_distances_past_32_bits(gpu):
     # a one-way path with increasing labels is contracted from its source
     # end without shortcuts, so one upward search passes 2^32 on its own
