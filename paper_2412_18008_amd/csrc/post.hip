@@ -606,8 +606,7 @@ constexpr uint32_t kQCore = 4096;  // core ranks of tier 2 (within its 8192 rank
 using QTier3 = QLds<16384>;
 constexpr int kQTier1PerCU = 5;
 static_assert(sizeof(QTier1) * kQTier1PerCU <= 163840, "five tier-1 query blocks per CU");
-static_assert(sizeof(QTier2) + 4 * kQCore + 8 * 16 <= 163840,
-              "one tier-2 query block per CU, with its core lists");
+static_assert(sizeof(QTier2) + 8 * 16 <= 163840, "one tier-2 query block per CU");
 
 // Table accessors: plain LDS accesses, or device-coherent ones for tables in
 // global memory (written by other waves' atomics, which bypass the CU's
@@ -834,8 +833,6 @@ __global__ void __launch_bounds__(64 * NW) k_query(
   // rows and arcs read (expansions and stall checks; stats batches)
   uint32_t nrows = 0, narcs = 0;
   __shared__ unsigned long long s_stall[NW];
-  // core entries of both directions at the end of a query (core index)
-  __shared__ uint16_t s_core[2][CORE > 0 ? CORE : 1];
   auto stall_check = [&](bool cand, uint32_t vx, uint32_t dx, uint32_t dr) -> bool {
     uint32_t ss = 0, sl = 0;
     if (cand) {
@@ -1138,7 +1135,11 @@ __global__ void __launch_bounds__(64 * NW) k_query(
       if constexpr (CORE > 0) {
         if (coreD) {
           // core entries of each direction (dense slots from cb on), listed
-          // by a block scan, then every pair through the core table
+          // by a block scan in the hashed keys' space (read for the last
+          // time above), then every pair through the core table
+          static_assert(2 * CORE * sizeof(uint16_t) <= sizeof(S.key), "core lists fit the keys");
+          qsync<NW, GM>();
+          uint16_t(*s_core)[CORE] = reinterpret_cast<uint16_t(*)[CORE]>(&S.key[0][0]);
           const uint32_t cb = core0 - tbase;
           uint32_t cnt[2];
 #pragma unroll
