@@ -93,8 +93,8 @@ extern "C" {
  * does, so its visited counts (the sizes of the two search spaces) do not
  * depend on timing. */
 #define CH_Q_FULL_CLOSURE (1u << 20)
-/* Count the vertices expanded and arcs relaxed by the batch (read with
- * ch_get_query_stats); ch_query_batch_stats always counts. */
+/* Count the adjacency rows and arcs the batch reads, and its core-table
+ * reads (ch_get_query_stats); ch_query_batch_stats always counts. */
 #define CH_Q_COUNT (1u << 21)
 /* Tier a batch starts in: 1 = LDS tables for small search spaces, 2 = LDS
  * tables for large ones, 3 = tables in global memory; 0 = chosen by the
@@ -392,8 +392,10 @@ typedef struct {
   uint64_t tier_queries[4];  /* queries that entered each tier                   */
   float tier_ms[4];          /* device time of each tier's launch (0: not run;   */
                              /* not measured by ch_query_batch_noalloc)          */
-  uint64_t rows;             /* vertices expanded, every tier and re-expansion   */
-  uint64_t arcs;             /* arcs relaxed, every tier and re-expansion        */
+  uint64_t rows;             /* adjacency rows read: vertices expanded and
+                              * stall-checked, every tier and re-expansion      */
+  uint64_t arcs;             /* arcs read (relaxed or stall-checked) plus
+                              * core-table entries read, every tier             */
 } ch_query_stats_t;
 
 /* Copies the counters of the CH's last query batch into *out (host).
