@@ -607,8 +607,9 @@ def main():
         la, ms = qper[dom]
         # bytes of the whole batch, all tiers; attributed to the dominant tier
         roof = roofline_obj(args.workload, dom, la, ms, q_bytes_batch * la,
-                            "8 B per vertex expanded + 8 B per arc relaxed, the whole batch "
-                            "(counted in one more batch)")
+                            "8 B per adjacency row read (expanded or stall-checked) + 8 B per "
+                            "arc or core-table entry read, the whole batch (counted in one more "
+                            "batch)")
     wl, wms, wb = (sum(v[i] for v in per.values()) for i in range(3))
     roof_wps = roofline_obj(args.workload, "all witness-search launches", wl, wms, wb,
                             "8 B per row + 8 B per arc + 16 B per memo slot read or written")
