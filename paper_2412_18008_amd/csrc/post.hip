@@ -26,12 +26,14 @@ namespace sp {
   } while (0)
 
 // Default level window of the query: none.  With the searches pruned by the
-// shortest path met so far, expanding every flagged vertex at once is
-// fastest (road1m, 182 levels: 25.1 ms per 100k queries, 28.6-41.6 ms with
-// windows of 128 down to 8 levels; road24m, 412 levels: 3.14 s per 1M,
-// 3.34 s with 48 levels, 4.91 s with 8).  A hierarchy deeper than kQShallow
-// levels starts its first query batch in the second tier: on road24m 99.95%
-// of the queries outgrow the first tier's tables.
+// shortest path met so far and by stall-on-demand, expanding every flagged
+// vertex at once is fastest (road1m, 182 levels: 17.2 ms per 100k queries,
+// 18.9-24.6 ms with windows of 128 down to 16 levels; road24m, 412 levels:
+// 1.00 s per 1M before the core table, 1.08-2.10 s with windows).  A
+// hierarchy deeper than kQShallow levels starts its first query batch in
+// the second tier, which also holds the core table: started in the first
+// tier, about 36% of the road24m queries outgrow its tables (1.11 s per 1M
+// then, against 1.00 s).
 constexpr uint32_t kQShallow = 256;
 
 static int bits_for(uint32_t n) {
