@@ -405,3 +405,63 @@ def test_loaded_ch_answers_like_built_ch(oracle_lib):
         a = o.query_batch(s, t)
         b = L.query_batch(s, t)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), name
+
+
+def test_top_ranks_keep_their_distances_in_the_ch(oracle_lib):
+    # The query's core table rests on this property of a CH: the CH arcs
+    # among the K highest ranks alone give the exact distance between any
+    # two of those vertices (a shortest up-down path between two of them
+    # climbs from the lower one, so it never drops below it).  Checked by
+    # Floyd-Warshall on those arcs against the input graph's closure, for
+    # several K, and the core-finished query (searches that stop at the
+    # core, then min over core pairs) against the closure for all pairs.
+    for name, (off, dst, w) in small_graphs():
+        n = len(off) - 1
+        full = graph_closure(off, dst, w)
+        o = oracle.OracleCH(off, dst, w, labels=synth.labels(n, 3)).run()
+        rank = o.rank()
+        up, dn = o.up(), o.down()
+        tails = np.concatenate([up["tail"], dn["tail"]]).astype(np.int64)
+        heads = np.concatenate([up["head"], dn["head"]]).astype(np.int64)
+        ws = np.concatenate([up["w"], dn["w"]]).astype(np.int64)
+        rt, rh = rank[tails], rank[heads]
+        by_rank = np.argsort(rank)
+        for K in sorted({1, 3, n // 2, n}):
+            if K == 0:
+                continue
+            c0 = n - K
+            sel = (rt >= c0) & (rh >= c0)
+            core = closure(K, rt[sel] - c0, rh[sel] - c0, ws[sel])
+            verts = by_rank[c0:]
+            assert np.array_equal(core, full[np.ix_(verts, verts)]), (name, K)
+            # upward closures from every vertex below the core, over arcs
+            # that leave non-core vertices only
+            upw = [[] for _ in range(n)]   # by rank: (higher rank, w) of upward arcs
+            dnw = [[] for _ in range(n)]   # by rank: (higher rank, w) of arcs into it
+            for a, b, x in zip(rt, rh, ws):
+                if a < b:
+                    upw[a].append((b, x))
+                else:
+                    dnw[b].append((a, x))
+
+            def climb(r0, adj):
+                d = {r0: 0}
+                for r in range(r0, n):  # ranks in increasing order: upward arcs only
+                    if r in d and r < c0:
+                        for b, x in adj[r]:
+                            d[b] = min(d.get(b, INF), d[r] + x)
+                return d
+            fw = [climb(rank[v], upw) for v in range(n)]
+            bw = [climb(rank[v], dnw) for v in range(n)]
+            for s in range(n):
+                for t in range(n):
+                    best = INF
+                    for r, x in fw[s].items():
+                        if r < c0 and r in bw[t]:
+                            best = min(best, x + bw[t][r])
+                    for a, x in fw[s].items():
+                        if a >= c0:
+                            for b, y in bw[t].items():
+                                if b >= c0 and core[a - c0, b - c0] < INF:
+                                    best = min(best, x + core[a - c0, b - c0] + y)
+                    assert best == full[s, t], (name, K, s, t)
