@@ -605,6 +605,7 @@ struct QLds {
 using QTier1 = QLds<512, 2048, 2048>;
 using QTier2 = QLds<4096, 8192, 4096>;
 constexpr uint32_t kQCore = 4096;  // core ranks of tier 2 (within its 8192 rank slots)
+constexpr uint64_t kQCoreBatch = 4096;  // smallest batch that builds the core table
 using QTier3 = QLds<16384>;
 constexpr int kQTier1PerCU = 5;
 static_assert(sizeof(QTier1) * kQTier1PerCU <= 163840, "five tier-1 query blocks per CU");
@@ -1416,9 +1417,12 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   if (first <= 2) {
     HIP_TRY(mark(2));
     // the core table: pruned batches only (full closures expand everything),
-    // made on the first such batch when the scratch may allocate
+    // made on the first such batch of at least kQCoreBatch queries when the
+    // scratch may allocate (its closure, about 6 ms at 4096 ranks, is
+    // amortised over the batch and the CH's later ones)
     const bool use_core = prune && !(flags & CH_Q_NO_CORE);
-    if (use_core && ch->q_core_state == 0 && sc.can_alloc) TRY(core_table(ch, st));
+    if (use_core && ch->q_core_state == 0 && sc.can_alloc && q >= kQCoreBatch)
+      TRY(core_table(ch, st));
     const bool core = use_core && ch->q_core_state == 1;
     k_query<16, QTier2, false, kQCore><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,

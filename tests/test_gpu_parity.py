@@ -285,14 +285,18 @@ def test_query_core_table(gpu):
         print(f"[parity] core {name}", flush=True)
         o = oracle.OracleCH(off, dst, w, labels=lab).run()
         ch = gpu.build(off, dst, w, labels=lab)
-        s, t = synth.queries(n, 3000, seed=7)
+        s, t = synth.queries(n, 5000, seed=7)  # a batch that builds the table
         s[:50] = t[:50]  # self queries
         if name == "fan13000":
             s[50:90] = 13000  # the hub: overflows the second tier
         od, _ = o.query_batch(s, t)
+        # a small batch first: no table yet, searched to the top
+        assert np.array_equal(ch.query(s[:100], t[:100], tier=2), od[:100]), name
         for rep in range(2):
             d = ch.query(s, t, tier=2)
             assert np.array_equal(d, od), (name, rep)
+        # a small batch now uses the table
+        assert np.array_equal(ch.query(s[:100], t[:100], tier=2), od[:100]), name
         assert np.array_equal(ch.query(s, t, tier=2, core=False), od), name
         assert np.array_equal(ch.query(s, t, tier=2, full=True), od), name
         if name != "fan13000":
