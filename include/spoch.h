@@ -102,10 +102,11 @@ extern "C" {
  * one tier up for later batches when more than half of a batch moved on).
  * Queries that outgrow a tier still move on.  Results do not depend on it. */
 #define CH_Q_FIRST_TIER(t) ((uint32_t)(t) << 22)
-/* The second tier normally stops both searches at the 4096 highest ranks
- * and finishes with a table of the exact distances among them (built once
- * per CH, 64 MB, at its first pruned batch of at least 4096 queries that
- * reaches the tier, and used by every later one; skipped
+/* The first and second tiers normally stop both searches at the 1024 and
+ * 4096 highest ranks and finish with a table of the exact distances among
+ * them (built once per CH, 4 MB and 64 MB, at its first pruned batch of at
+ * least 4096 queries that reaches the tier, and used by every later one;
+ * skipped
  * when a distance in it could pass 32 bits; ch_query_batch_noalloc uses it
  * only if it exists).  CH_Q_NO_CORE searches without it.  Results do not
  * depend on it. */

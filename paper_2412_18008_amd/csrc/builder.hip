@@ -1729,7 +1729,7 @@ ch_s::~ch_s() {
   sp::DBuf *all[] = {&level, &score, &label, &rank, &up_t, &up_h, &up_w, &up_m, &dn_t, &dn_h,
                      &dn_w, &dn_m, &q_upoff, &q_uparc, &q_dnoff, &q_dnarc, &q_lstart, &q_wend, &q_s, &q_t, &q_d,
                      &q_ovf, &q_tab, &q_ctr, &rec, &q_v, &q_ovf2, &q_gtab, &q_phast,
-                     &q_core, &q_core_max};
+                     &q_core, &q_core_max, &q_core1};
   for (sp::DBuf *b : all) b->release();
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }

@@ -44,6 +44,10 @@ struct ch_s {
   sp::DBuf q_core, q_core_max;
   uint32_t q_core_k = 0, q_core_n = 0;
   int q_core_state = 0;
+  // the first tier's smaller core table (the highest q_core1_k ranks)
+  sp::DBuf q_core1;
+  uint32_t q_core1_k = 0, q_core1_n = 0;
+  int q_core1_state = 0;
   ch_query_stats_t qstats{};              // counters of the last query batch
 
   // features at contraction (CH_F_RECORD_FEATURES), 8 floats per vertex

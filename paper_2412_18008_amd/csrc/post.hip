@@ -605,7 +605,8 @@ struct QLds {
 using QTier1 = QLds<512, 2048, 2048>;
 using QTier2 = QLds<4096, 8192, 4096>;
 constexpr uint32_t kQCore = 4096;  // core ranks of tier 2 (within its 8192 rank slots)
-constexpr uint64_t kQCoreBatch = 4096;  // smallest batch that builds the core table
+constexpr uint64_t kQCoreBatch = 4096;  // smallest batch that builds a core table
+constexpr uint32_t kQCore1 = 1024;  // core ranks of tier 1 (within its 2048 rank slots)
 using QTier3 = QLds<16384>;
 constexpr int kQTier1PerCU = 5;
 static_assert(sizeof(QTier1) * kQTier1PerCU <= 163840, "five tier-1 query blocks per CU");
@@ -1299,20 +1300,21 @@ __global__ void k_core_arcs(uint32_t c0, uint32_t n, uint32_t N, const uint32_t 
   if (mx) atomicMax(maxw, mx);
 }
 
-// The core table of a CH (once per CH, at its first pruned tier-2 batch):
-// the kQCore highest ranks (all of them on smaller CHs), their arcs, then
-// the all-pairs closure.  Not used when a core distance could pass 32 bits
+// A core table of a CH (once per CH and tier, at the tier's first pruned
+// batch of at least kQCoreBatch queries): the kmax highest ranks (all of
+// them on smaller CHs), their arcs, then the all-pairs closure.  Not used when a core distance could pass 32 bits
 // (largest core arc weight x core size above 0xFFFFFFFE).
-static int core_table(ch_s *ch, hipStream_t st) {
-  if (ch->q_core_state) return CH_OK;
-  ch->q_core_state = 2;
+static int core_table(ch_s *ch, uint32_t kmax, DBuf &tab, uint32_t &k_out, uint32_t &n_out,
+                      int &state, hipStream_t st) {
+  if (state) return CH_OK;
+  state = 2;
   const uint32_t n = ch->n;
-  const uint32_t K = std::min<uint32_t>(kQCore, n);
+  const uint32_t K = std::min<uint32_t>(kmax, n);
   if (K == 0) return CH_OK;
   const uint32_t N = (K + 63) / 64 * 64, c0 = n - K;
-  HIP_TRY(ch->q_core.ensure((size_t)N * N * 4));
+  HIP_TRY(tab.ensure((size_t)N * N * 4));
   HIP_TRY(ch->q_core_max.ensure(4));
-  uint32_t *D = ch->q_core.as<uint32_t>(), *mx = ch->q_core_max.as<uint32_t>();
+  uint32_t *D = tab.as<uint32_t>(), *mx = ch->q_core_max.as<uint32_t>();
   HIP_TRY(fw_init(D, N, st));
   HIP_TRY(fill_u32(mx, 0u, 1, st));
   k_core_arcs<<<(K + 255) / 256, 256, 0, st>>>(c0, n, N, ch->q_upoff.as<uint32_t>(),
@@ -1324,9 +1326,9 @@ static int core_table(ch_s *ch, hipStream_t st) {
   HIP_TRY(hipStreamSynchronize(st));
   if ((uint64_t)hmx * K > 0xFFFFFFFEull) return CH_OK;
   HIP_TRY(fw_close(D, N, st));
-  ch->q_core_k = K;
-  ch->q_core_n = N;
-  ch->q_core_state = 1;
+  k_out = K;
+  n_out = N;
+  state = 1;
   return CH_OK;
 }
 
@@ -1402,10 +1404,20 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
     HIP_TRY(mark(0));
     const uint64_t g = std::min<uint64_t>(q, (uint64_t)cus * kQTier1PerCU);
     const uint32_t nw = (flags >> 8) & 0xFu;  // 0: four waves per query
+    // the first tier's core table (the kQCore1 highest ranks, within its
+    // rank slots), made like the second tier's
+    const bool use_core1 = prune && !(flags & CH_Q_NO_CORE);
+    if (use_core1 && ch->q_core1_state == 0 && sc.can_alloc && q >= kQCoreBatch)
+      TRY(core_table(ch, kQCore1, ch->q_core1, ch->q_core1_k, ch->q_core1_n, ch->q_core1_state,
+                     st));
+    const bool core1 = use_core1 && ch->q_core1_state == 1;
+    const uint32_t *c1D = core1 ? ch->q_core1.as<uint32_t>() : nullptr;
+    const uint32_t c1lo = core1 ? ch->n - ch->q_core1_k : 0xFFFFFFFFu;
 #define SP_QUERY_LAUNCH(NW)                                                                    \
-  k_query<NW, QTier1, false><<<(unsigned)g, 64 * NW, 0, st>>>(                                  \
+  k_query<NW, QTier1, false, kQCore1><<<(unsigned)g, 64 * NW, 0, st>>>(                         \
       q, ch->n, nullptr, nullptr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff, dnarc, dd, dv,   \
-      ovf1, ctr, wend, reinterpret_cast<unsigned long long *>(ctr + 8), nullptr, qcount, prune)
+      ovf1, ctr, wend, reinterpret_cast<unsigned long long *>(ctr + 8), nullptr, qcount, prune, \
+      c1D, c1lo, ch->q_core1_n, ch->q_core1_k)
     if (nw == 1) SP_QUERY_LAUNCH(1);
     else if (nw == 2) SP_QUERY_LAUNCH(2);
     else if (nw == 8) SP_QUERY_LAUNCH(8);
@@ -1422,7 +1434,7 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
     // amortised over the batch and the CH's later ones)
     const bool use_core = prune && !(flags & CH_Q_NO_CORE);
     if (use_core && ch->q_core_state == 0 && sc.can_alloc && q >= kQCoreBatch)
-      TRY(core_table(ch, st));
+      TRY(core_table(ch, kQCore, ch->q_core, ch->q_core_k, ch->q_core_n, ch->q_core_state, st));
     const bool core = use_core && ch->q_core_state == 1;
     k_query<16, QTier2, false, kQCore><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,

@@ -269,8 +269,9 @@ def test_query_tiers(gpu):
 
 
 def test_query_core_table(gpu):
-    # The second query tier stops both searches at the 4096 highest ranks and
-    # finishes with the table of exact distances among them: every result
+    # The first and second query tiers stop both searches at the 1024 or
+    # 4096 highest ranks and finish with the table of exact distances among
+    # them: every result
     # equals the oracle's (and Dijkstra's) with and without the table, on a
     # CH smaller than the core (every vertex in it), larger ones, random
     # digraphs with unreachable pairs, self queries, and a fan whose hub
@@ -290,15 +291,16 @@ def test_query_core_table(gpu):
         if name == "fan13000":
             s[50:90] = 13000  # the hub: overflows the second tier
         od, _ = o.query_batch(s, t)
-        # a small batch first: no table yet, searched to the top
-        assert np.array_equal(ch.query(s[:100], t[:100], tier=2), od[:100]), name
-        for rep in range(2):
-            d = ch.query(s, t, tier=2)
-            assert np.array_equal(d, od), (name, rep)
-        # a small batch now uses the table
-        assert np.array_equal(ch.query(s[:100], t[:100], tier=2), od[:100]), name
-        assert np.array_equal(ch.query(s, t, tier=2, core=False), od), name
-        assert np.array_equal(ch.query(s, t, tier=2, full=True), od), name
+        for tier in (1, 2):  # cores of 1024 and 4096 ranks
+            # a small batch first: no table yet, searched to the top
+            assert np.array_equal(ch.query(s[:100], t[:100], tier=tier), od[:100]), name
+            for rep in range(2):
+                d = ch.query(s, t, tier=tier)
+                assert np.array_equal(d, od), (name, tier, rep)
+            # a small batch now uses the table
+            assert np.array_equal(ch.query(s[:100], t[:100], tier=tier), od[:100]), name
+            assert np.array_equal(ch.query(s, t, tier=tier, core=False), od), name
+            assert np.array_equal(ch.query(s, t, tier=tier, full=True), od), name
         if name != "fan13000":
             ref = reference_distances(off, dst, w, s[:200], t[:200])
             assert np.array_equal(d[:200], ref), name
