@@ -774,15 +774,15 @@ __device__ __forceinline__ void qclear(L &S, uint32_t tid, uint32_t nt) {
 // by the blocks from the counter *work (so blocks that draw large queries
 // take fewer).  Queries that do not fit go to ovf_list (count in
 // *ovf_count).  GM: gtab holds one L per block.
-// Core table (tier 2): a query does not expand the CORE highest ranks; it
+// Core table (tiers 1 and 2): a query does not expand the CORE highest ranks; it
 // takes min over pairs (a, b) of core vertices reached from s and from t of
 // d_s(a) + D[a][b] + d_t(b), with D the exact distances among them (the CH
 // arcs among the highest ranks keep those distances: a shortest up-down path
 // between two of them climbs from the lower one).  A shortest s-t path whose
 // highest vertex is in the core enters it at some a and leaves it at some b,
 // and its two ends are found exactly below the core; every other path is met
-// as before.  CORE = 0: no core (kQCore, the core size, is defined with the
-// tier tables).
+// as before.  CORE = 0: no core (kQCore1 and kQCore, the core sizes, are
+// defined with the tier tables).
 
 template <int NW, typename L, bool GM, int CORE = 0>
 __global__ void __launch_bounds__(64 * NW) k_query(
@@ -1302,8 +1302,9 @@ __global__ void k_core_arcs(uint32_t c0, uint32_t n, uint32_t N, const uint32_t 
 
 // A core table of a CH (once per CH and tier, at the tier's first pruned
 // batch of at least kQCoreBatch queries): the kmax highest ranks (all of
-// them on smaller CHs), their arcs, then the all-pairs closure.  Not used when a core distance could pass 32 bits
-// (largest core arc weight x core size above 0xFFFFFFFE).
+// them on smaller CHs), their arcs, then the all-pairs closure.  Not used
+// when a core distance could pass 32 bits (largest core arc weight x core
+// size above 0xFFFFFFFE).
 static int core_table(ch_s *ch, uint32_t kmax, DBuf &tab, uint32_t &k_out, uint32_t &n_out,
                       int &state, hipStream_t st) {
   if (state) return CH_OK;
