@@ -11,8 +11,14 @@ derivation):
   (contracted neighbours, in/out degree, depth, settled count, ...);
 * the settled(theta) witness search: settle order, the source counted
   first, the stop after theta settles (Alg. 4);
-* the pop count of a bidirectional CH query and its stopping rule (Sec.
-  "Query on Contraction Hierarchies").
+* the pop count of a bidirectional CH query, its stopping rule and its
+  alternation on equal queue minima (Sec. "Query on Contraction
+  Hierarchies");
+* per-round counts, scores and memo over whole rounds: which pairs become
+  targets (never the source, never a memoized pair), the radius D_s and
+  what a bounded search settles or reaches (exact and hop modes), the next
+  round's V_W and V_A, absent memo entries counted by the score, and the
+  contracted-neighbour term counting each neighbour once (Alg. 3-7).
 
 Each fixture was chosen so that a plausible slip in the rule it covers (a
 reversed comparison, a tie broken on the wrong key, a "<" for a "<=", a
@@ -121,8 +127,9 @@ def test_features_at_contraction(oracle_lib):
         assert np.array_equal(x[v], exp), (v, x[v], exp)
 
 
-def test_settled_theta_memo_and_count(oracle_lib):
-    rows = load("settled_theta_memo.txt")
+@pytest.mark.parametrize("fixture", ["settled_theta_memo.txt", "settled_theta_target_stop.txt"])
+def test_settled_theta_memo_and_count(oracle_lib, fixture):
+    rows = load(fixture)
     off, dst, w, lab = graph_of(rows)
     for theta, settled, *memo in (vals for k, vals in rows if k == "expect"):
         o = oracle.OracleCH(off, dst, w, labels=lab, wps_mode=oracle.WPS_SETTLED,
@@ -135,8 +142,9 @@ def test_settled_theta_memo_and_count(oracle_lib):
         assert o.round_stats()[0]["n_settled"] == settled, theta
 
 
-def test_query_pop_count_on_given_ch(oracle_lib):
-    rows = load("query_pop_count.txt")
+@pytest.mark.parametrize("fixture", ["query_pop_count.txt", "query_direction_tie.txt"])
+def test_query_pop_count_on_given_ch(oracle_lib, fixture):
+    rows = load(fixture)
     n = next(v[0] for k, v in rows if k == "n")
     rank = np.zeros(n, np.uint32)
     for k, v in rows:
@@ -196,3 +204,34 @@ def test_raw_id_tiebreak(oracle_lib):
     with pytest.raises(oracle.OracleError):
         oracle.OracleCH(off, dst, w, labels=np.arange(n, dtype=np.uint32),
                         tiebreak=oracle.TIE_RAW_ID)
+
+
+# per-round counters a round-counts fixture may name (orc_round_stats)
+ROUND_COUNTERS = ("alive_before", "n_sources", "n_affected", "n_searched", "n_targets",
+                  "n_pruned", "n_selected", "n_pairs_emitted", "n_shortcuts", "n_absent",
+                  "n_settled", "overlay_arcs")
+PARAMS = ("wps_mode", "hop_limit", "settle_limit", "k_ed", "k_cn", "k_depth")
+
+
+@pytest.mark.parametrize("fixture", ["round_counts_two_rounds.txt", "self_target.txt",
+                                     "hop_absent_score.txt", "affected_middles_hop.txt",
+                                     "contracted_neighbours_once.txt",
+                                     "memo_at_largest_distance.txt"])
+def test_round_counts_scores_and_memo(oracle_lib, fixture):
+    rows = load(fixture)
+    off, dst, w, lab = graph_of(rows)
+    kw = {k: v[0] for k, v in rows if k in PARAMS}
+    o = oracle.OracleCH(off, dst, w, labels=lab, **kw)
+    last = max(v[0] for k, v in rows if k in ROUND_COUNTERS or k == "p")
+    for r in range(last + 1):
+        assert o.round() == 1, (fixture, r)
+        p = o.vertex_state()["p"]
+        for v, val in (vals[1:] for k, vals in rows if k == "p" and vals[0] == r):
+            assert p[v] == val, (fixture, r, v, p[v], val)
+    stats = o.round_stats()
+    for k, (r, val) in ((k, v) for k, v in rows if k in ROUND_COUNTERS):
+        assert stats[r][k] == val, (fixture, r, k, stats[r][k], val)
+    exp = sorted(tuple(v) for k, v in rows if k == "memo")
+    if exp:
+        m = o.memo()
+        assert sorted(zip(m["s"].tolist(), m["t"].tolist(), m["d"].tolist())) == exp, fixture
