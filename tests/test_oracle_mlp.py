@@ -99,3 +99,31 @@ def test_quantised_priority_ties_follow_labels(oracle_lib):
         assert o.round_stats()[0]["n_selected"] == expect, q
     with pytest.raises(oracle.OracleError):
         oracle.OracleCH(off, dst, w_, mlp=w, mlp_qbits=25)
+
+
+def test_priority_rounding_and_saturation(oracle_lib):
+    # The priority is the output scaled by 2^qbits, rounded to nearest (ties
+    # to even) and saturated to int32; a NaN output saturates high.  With
+    # every weight zero but the output bias b3, the output is b3 exactly.
+    w = np.zeros(4801, np.float32)
+    x = np.zeros(8, np.float32)
+    cases = [
+        (0.5, 16, 32768),              # exact
+        (2.5 / 65536, 16, 2),          # 2.5 rounds to even 2
+        (3.5 / 65536, 16, 4),          # 3.5 rounds to even 4
+        (-2.5 / 65536, 16, -2),
+        (0.375, 3, 3),                 # 3 fractional bits: 0.375 * 8 = 3
+        (0.4375, 3, 4),                # 3.5 -> 4
+        (32767.0, 16, 2**31 - 2**16),  # in range: exact
+        (32768.0, 16, 2**31 - 1),      # 2^31 does not fit: saturates high
+        (1e6, 16, 2**31 - 1),
+        (-32768.0, 16, -2**31),        # -2^31 fits exactly
+        (-1e6, 16, -2**31),            # saturates low
+        (float("nan"), 16, 2**31 - 1),
+    ]
+    for b3, q, exp in cases:
+        w[4800] = b3
+        p, y = oracle.mlp_priority(w, x, qbits=q)
+        if b3 == b3:
+            assert y == np.float32(b3)
+        assert p == exp, (b3, q, p, exp)

@@ -375,6 +375,12 @@ def test_errors(oracle_lib):
     with pytest.raises(oracle.OracleError) as e:
         o.run()
     assert e.value.code == oracle.ORC_E_OVERFLOW
+    # a search radius D_s above 0xFFFFFFFE does not fit the 32-bit memo
+    # either, even where no shortcut would need it (1 is contracted last)
+    o = oracle.OracleCH(off, dst, w, labels=np.array([0, 5, 9], np.uint32))
+    with pytest.raises(oracle.OracleError) as e:
+        o.run()
+    assert e.value.code == oracle.ORC_E_OVERFLOW
     # max_rounds
     off, dst, w = synth.chain(50, seed=1, directed=False)
     o = oracle.OracleCH(off, dst, w, max_rounds=2)

@@ -142,7 +142,8 @@ def test_settled_theta_memo_and_count(oracle_lib, fixture):
         assert o.round_stats()[0]["n_settled"] == settled, theta
 
 
-@pytest.mark.parametrize("fixture", ["query_pop_count.txt", "query_direction_tie.txt"])
+@pytest.mark.parametrize("fixture", ["query_pop_count.txt", "query_direction_tie.txt",
+                                     "query_equal_paths.txt"])
 def test_query_pop_count_on_given_ch(oracle_lib, fixture):
     rows = load(fixture)
     n = next(v[0] for k, v in rows if k == "n")
@@ -216,7 +217,8 @@ PARAMS = ("wps_mode", "hop_limit", "settle_limit", "k_ed", "k_cn", "k_depth")
 @pytest.mark.parametrize("fixture", ["round_counts_two_rounds.txt", "self_target.txt",
                                      "hop_absent_score.txt", "affected_middles_hop.txt",
                                      "contracted_neighbours_once.txt",
-                                     "memo_at_largest_distance.txt"])
+                                     "memo_at_largest_distance.txt",
+                                     "stale_entry_and_prune.txt", "hop_radius.txt"])
 def test_round_counts_scores_and_memo(oracle_lib, fixture):
     rows = load(fixture)
     off, dst, w, lab = graph_of(rows)
