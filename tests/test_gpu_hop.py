@@ -113,3 +113,15 @@ def test_hop_global_search_tier_after_pruning(gpu):
     s, t = synth.queries(n, 300, seed=2)
     od, _ = o.query_batch(s, t)
     assert np.array_equal(ch.query(s, t), od)
+
+
+def test_hop_road1m_bit_exact(gpu):
+    # the hop-bounded build at the benchmark's 1M size: every tier of the
+    # search kernels and the table rounds, bit-exact with the oracle's
+    # (H = 4: the oracle's own build takes about 35 s on one core)
+    off, dst, w = synth.road_like(1_000_000, seed=6)
+    n = len(off) - 1
+    o, ch = _hop_case("road1m", off, dst, w, synth.labels(n, 2), gpu, 4)
+    s, t = synth.queries(n, 5000, seed=9)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(ch.query(s, t), od)
