@@ -198,3 +198,21 @@ def test_training_and_gain(gpu):
     for tag in ("trained", "trained_bf16"):
         assert report[tag]["shortcuts"] < report["untrained"]["shortcuts"], tag
         assert report[tag]["settled"] < report["untrained"]["settled"], tag
+
+
+def test_trained_weights_build_bit_exact_200k(gpu):
+    # the shipped trained weights (the ones bench.py compares with the plain
+    # method at 1M) on a 200k road-like graph: the whole CH and every round
+    # count equal the oracle's (its build takes about 16 s on one core)
+    import os
+
+    from paper_2412_18008_amd import learned
+
+    path = os.path.join(os.path.dirname(learned.__file__), "learned_weights.npy")
+    weights = np.load(path).astype(np.float32)
+    off, dst, w = synth.road_like(200_000, seed=4)
+    n = len(off) - 1
+    o, ch = _learned_case(gpu, "road200k/trained", off, dst, w, synth.labels(n, 7), weights, 0)
+    s, t = synth.queries(n, 5000, seed=11)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(ch.query(s, t), od)

@@ -99,3 +99,14 @@ def test_settled_needs_a_limit(gpu):
         h = C.c_void_p()
         gpu._check(gpu.lib().ch_build(C.byref(g), C.byref(p), C.byref(h)), "ch_build")
     assert e.value.code == gpu.CH_E_INVALID
+
+
+def test_settled_road1m_bit_exact(gpu):
+    # the paper's settled(theta) bound at the benchmark's 1M size (theta =
+    # 1000: the oracle's own build takes about 45 s on one core)
+    off, dst, w = synth.road_like(1_000_000, seed=6)
+    n = len(off) - 1
+    o, ch = _settled_case("road1m", off, dst, w, None, gpu, 1000)
+    s, t = synth.queries(n, 5000, seed=10)
+    od, _ = o.query_batch(s, t)
+    assert np.array_equal(ch.query(s, t), od)
