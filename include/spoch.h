@@ -104,12 +104,11 @@ extern "C" {
 #define CH_Q_FIRST_TIER(t) ((uint32_t)(t) << 22)
 /* The first and second tiers normally stop both searches at the 1024 and
  * 4096 highest ranks and finish with a table of the exact distances among
- * them (built once per CH, 4 MB and 64 MB, at its first pruned batch of at
- * least 4096 queries that reaches the tier, and used by every later one;
- * skipped
- * when a distance in it could pass 32 bits; ch_query_batch_noalloc uses it
- * only if it exists).  CH_Q_NO_CORE searches without it.  Results do not
- * depend on it. */
+ * them (built once per CH, 4 MB and 64 MB, at the first pruned batch in
+ * which at least 4096 queries enter the tier, and used by every later one;
+ * skipped when a distance in it could pass 32 bits; ch_query_batch_noalloc
+ * uses it only if it exists).  CH_Q_NO_CORE searches without it.  Results
+ * do not depend on it. */
 #define CH_Q_NO_CORE (1u << 26)
 
 /* Input graph in CSR form, arcs grouped by tail vertex.

@@ -1430,12 +1430,21 @@ static int query_tiers(ch_s *ch, const uint32_t *ds, const uint32_t *dt, uint64_
   if (first <= 2) {
     HIP_TRY(mark(2));
     // the core table: pruned batches only (full closures expand everything),
-    // made on the first such batch of at least kQCoreBatch queries when the
-    // scratch may allocate (its closure, about 6 ms at 4096 ranks, is
-    // amortised over the batch and the CH's later ones)
+    // made on the first such batch with at least kQCoreBatch queries in this
+    // tier when the scratch may allocate (its closure, about 7 ms at 4096
+    // ranks, is amortised over the batch and the CH's later ones).  After
+    // the first tier only its overflows come here: their count is read first
     const bool use_core = prune && !(flags & CH_Q_NO_CORE);
-    if (use_core && ch->q_core_state == 0 && sc.can_alloc && q >= kQCoreBatch)
-      TRY(core_table(ch, kQCore, ch->q_core, ch->q_core_k, ch->q_core_n, ch->q_core_state, st));
+    if (use_core && ch->q_core_state == 0 && sc.can_alloc && q >= kQCoreBatch) {
+      uint32_t in2 = 0xFFFFFFFFu;
+      if (first <= 1) {
+        HIP_TRY(hipMemcpyAsync(&in2, ctr, 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+      }
+      if (in2 >= kQCoreBatch)
+        TRY(core_table(ch, kQCore, ch->q_core, ch->q_core_k, ch->q_core_n, ch->q_core_state,
+                       st));
+    }
     const bool core = use_core && ch->q_core_state == 1;
     k_query<16, QTier2, false, kQCore><<<(unsigned)std::min<uint64_t>(q, cus), 1024, 0, st>>>(
         q, ch->n, first <= 1 ? ovf1 : nullptr, ctr, ctr + 1, ds, dt, rank, upoff, uparc, dnoff,
