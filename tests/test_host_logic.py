@@ -180,3 +180,38 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_roofline_arithmetic():
+    # algorithmic bytes of a witness search: 8 B per adjacency row, 8 B per
+    # arc, 16 B per memo slot read or written; the roofline object divides
+    # them by the summed launch time and by the 8 TB/s HBM peak
+    b = _bench()
+    assert b.ls_bytes(1, 0, 0, 0) == 8 and b.ls_bytes(0, 1, 0, 0) == 8
+    assert b.ls_bytes(0, 0, 1, 0) == 16 and b.ls_bytes(0, 0, 0, 1) == 16
+    assert b.ls_bytes(10, 20, 30, 40) == 80 + 160 + 480 + 640
+    r = b.roofline_obj("nowhere", "k_x", 4, 2.0, 8e9, "units")
+    assert r["achieved"] == 4000.0  # 8 GB in 2 ms
+    assert r["peak"] == 8000.0 and r["frac"] == 0.5 and r["unit"] == "GB/s"
+    assert r["avg_launch_ms"] == 0.5 and r["algorithmic_bytes_per_launch"] == 2e9
+    assert r["traffic"] is None  # no counter summary for that workload
+
+    # the per-kernel sums skip rounds without sources and the device-driven
+    # tail, and add the block and global tiers where they ran
+    class B:
+        CH_LS_TAIL = 99
+        LS_KERNELS = {0: "k_a", 1: "k_b"}
+
+    def rnd(tier, ms, rows, n_sources=1, blk=0.0, glob=0):
+        return dict(n_sources=n_sources, ls_tier1=tier, ms_local_search=ms,
+                    rows_expanded=rows, arcs_scanned=0, memo_probes=0, memo_inserts=0,
+                    ms_ls_blk=blk, rows2=1, arcs2=0, probes2=0, inserts2=0,
+                    n_ls_global=glob, ms_ls_global=0.5, rows3=2, arcs3=0, probes3=0,
+                    inserts3=0)
+    recs = [{"rounds": [rnd(0, 1.0, 5), rnd(0, 2.0, 7, blk=0.25), rnd(1, 3.0, 1, glob=3),
+                        rnd(0, 9.0, 100, n_sources=0), rnd(99, 9.0, 100)]}]
+    per = b.search_kernels(B, recs)
+    assert per["k_a"] == [2, 3.0, 8 * 12]
+    assert per["k_b"] == [1, 3.0, 8]
+    assert per[b.BLK_KERNEL] == [1, 0.25, 8]
+    assert per[b.GLOBAL_KERNEL] == [1, 0.5, 16]
