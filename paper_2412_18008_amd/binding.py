@@ -234,7 +234,8 @@ class CH:
         search spaces completely (no pruning by the best path met); count:
         count expansions and relaxed arcs (last_query_stats); tier: the tier
         the batch starts in (1, 2, 3; 0 = chosen by the library); core: the
-        second tier finishes at the core table (the same distances)."""
+        first and second tiers finish at their core tables (the same
+        distances)."""
         if tier not in (0, 1, 2, 3):
             raise ValueError("tier must be 0, 1, 2 or 3")
         qf = CH_Q_WAVES(waves) | CH_Q_LEVEL_WINDOW(window) | (CH_Q_FULL_CLOSURE if full else 0) | (
